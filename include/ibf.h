@@ -1,0 +1,177 @@
+/*
+ * ibf.h -- C-ABI of the MI355X interpolative butterfly factorization (IBF).
+ *
+ * The library factors the discrete Fourier integral operator
+ *     u(x) = sum_{xi in Omega} exp(2 pi i Phi(x, xi)) g(xi),   x in X
+ * (paper Sec. 1, eqn:DFIO with amplitude a == 1) into O(log N) block-sparse
+ * factors and applies them.  The construction is the preliminary IBF of
+ * Sec. 3 (explicit Chebyshev-interpolation factors, eqn:PIBF1, eqn:PIBF2,
+ * eqn:switchlocM, eqn:PIBF3, eqn:PIBFbf3) compressed by the sweep-out stage
+ * of Sec. 4.2 (eq:KeqUMV, eqn:GC, eqn:HR, eqn:V0) and, optionally, the
+ * sweep-in stage of Sec. 4.3 (eqn:IBFin).  Application multiplies the
+ * factors into a batch of vectors (Sec. 4, closing paragraph).
+ *
+ * Conventions shared by every entry point:
+ *   - Return value 0 on success or a negative IBF_ERR_* code.  Nothing is
+ *     thrown across the ABI; ibf_last_error() gives a thread-local message.
+ *   - Pointers named "host" are read during the call only; the library
+ *     copies what it keeps.  Pointers named "device" are HIP device memory
+ *     on the plan's device and are never retained.
+ *   - Complex numbers are interleaved (re, im): double2 for IBF_FP64 plans,
+ *     float2 for IBF_FP32 and IBF_BF16X2 plans.
+ *   - Streams are hipStream_t passed as void*; NULL means the legacy
+ *     default stream.  Calls are stream-ordered; ibf_build synchronises the
+ *     stream before it returns (it reads the per-level ranks back).
+ */
+#ifndef IBF_H
+#define IBF_H
+
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---- */
+#define IBF_OK                 0
+#define IBF_ERR_INVALID_ARG   -1   /* bad descriptor or argument */
+#define IBF_ERR_UNSUPPORTED   -2   /* valid but not implemented (e.g. r > 16) */
+#define IBF_ERR_OOM           -3   /* device allocation failed */
+#define IBF_ERR_DEVICE        -4   /* a HIP call failed */
+#define IBF_ERR_NOT_BUILT     -5   /* ibf_apply/ibf_query before ibf_build */
+
+/* ---- phase functions (paper Sec. 6) ----
+ * IBF_PHASE_DFT       Phi = s x xi,  s = params[0] (default +1)        Sec. 6.1
+ * IBF_PHASE_FIO1D     Phi = x xi + c(x)|xi|, c = (p0 + p1 sin 2 pi x)/p2 Sec. 6.2
+ *                     (defaults 2, 1, 8 as in eqn:1D-FIO-kernal)
+ * IBF_PHASE_SEPARABLE Phi = p0 x + p1 xi; the remainder R^{AB} of
+ *                     eqn:RAB vanishes, so the factorization is exact.
+ */
+#define IBF_PHASE_DFT        0
+#define IBF_PHASE_FIO1D      1
+#define IBF_PHASE_FIO2D      2
+#define IBF_PHASE_SEPARABLE  3
+
+/* ---- factor storage / apply precision ---- */
+#define IBF_FP64    0   /* complex double factors and vectors */
+#define IBF_FP32    1   /* complex float factors and vectors, FP32 accumulation */
+#define IBF_BF16X2  2   /* factors as bf16 hi + lo pairs, float vectors, FP32 accumulation */
+
+typedef struct ibf_plan_s* ibf_plan_t;
+
+/*
+ * Problem descriptor (1-D).  X lies in [0, 1) and Omega in
+ * [omega_lo, omega_lo + omega_width).  Tree depth L = ceil(log2 omega_width)
+ * keeps w_A * w_B <= 1 for every box pair (A at level l of T_X, B at level
+ * L - l of T_Omega, Sec. 2.1 and Sec. 3).  Leaves hold about `leaf` points;
+ * the butterfly runs from level l0 = log2(leaf) to L - l0.
+ */
+typedef struct {
+  int dim;                   /* 1 (2 reserved) */
+  int64_t n_x;               /* |X|  (rows)    */
+  int64_t n_xi;              /* |Omega| (cols) */
+  const double* x;           /* host, n_x values in [0, 1), any order */
+  const double* xi;          /* host, n_xi values in the Omega domain, any order */
+  double omega_lo;           /* Omega domain start; use -n_xi/2 for the paper's grid */
+  double omega_width;        /* Omega domain width; <= 0 selects n_xi */
+  int phase_id;              /* IBF_PHASE_* */
+  const double* phase_params;/* host, may be NULL for defaults */
+  int n_params;
+  int r;                     /* Chebyshev points per box, 2 <= r <= 16 (Sec. 2.1) */
+  double tol;                /* relative singular-value cut per block, 0 < tol < 1 */
+  int leaf;                  /* points per leaf, a power of two >= 2 */
+  int precision;             /* IBF_FP64 | IBF_FP32 | IBF_BF16X2 */
+  int sweep_in;              /* 0 off, 1 on (Sec. 4.3) */
+  int device;                /* HIP device ordinal the plan lives on */
+} ibf_desc;
+
+/* Per-plan sizes and timings (filled by ibf_query). */
+typedef struct {
+  int L, l0, h;              /* tree depth, first butterfly level, middle level */
+  int n_levels;              /* L - 2 l0 + 1 coefficient levels l0 .. L - l0 */
+  int rank[64];              /* per-level maximum rank K_l, index l - l0 */
+  int64_t n_pairs;           /* 2^L box pairs per level */
+  int64_t nnz_prelim;        /* complex entries of the preliminary IBF */
+  int64_t nnz_opt;           /* complex entries of the compressed IBF, each block at its own rank */
+  int64_t nnz_stored;        /* complex entries stored (blocks padded to the level rank) */
+  int64_t factor_bytes;      /* device bytes of the stored factors */
+  double build_ms;           /* wall time of the last ibf_build */
+  int smax_x, smax_xi;       /* largest leaf populations */
+} ibf_info;
+
+/*
+ * Validate the descriptor, build the dyadic trees on the host (sort points
+ * into leaves, Sec. 3 "Preliminaries") and size every buffer.  No device
+ * work.  Errors: INVALID_ARG if n < leaf^2, r < 2, tol outside (0,1), a
+ * point outside its domain, leaf not a power of two; UNSUPPORTED for dim != 1,
+ * r > 16 or an unknown phase.  On success *out owns the plan.
+ */
+int ibf_plan(const ibf_desc* desc, ibf_plan_t* out);
+
+/*
+ * Construct the compressed factorization on the plan's device: FP64 phase
+ * evaluation with exact mod-1 reduction, FP64 Lagrange weights, the middle
+ * SVDs (eq:KeqUMV), the sweep toward U (eqn:GC) and toward V (eqn:HR), the
+ * outer factors (Ubar = U C, Vbar = V R, eqn:V0), the optional sweep-in, and
+ * conversion to the storage precision.  `hip_stream` orders the work and is
+ * synchronised before return.  Rebuilding frees the previous factors.
+ * Errors: OOM, DEVICE.
+ */
+int ibf_build(ibf_plan_t plan, void* hip_stream);
+
+/*
+ * u = K_IBF g for nrhs right-hand sides.  g (device, read) and u (device,
+ * written) are column-major, n_xi x nrhs and n_x x nrhs, leading dimensions
+ * ldg >= n_xi and ldu >= n_x, in the caller's point order, complex
+ * interleaved in the plan's vector type.  g and u must not overlap.  The
+ * plan's apply workspace grows on demand (one hipMalloc when nrhs exceeds
+ * every previous call); only one apply per plan may be in flight.
+ * Errors: NOT_BUILT, INVALID_ARG (nrhs < 1, bad ld, NULL), OOM, DEVICE.
+ */
+int ibf_apply(ibf_plan_t plan, const void* g, int64_t ldg, void* u,
+              int64_t ldu, int64_t nrhs, void* hip_stream);
+
+/* Per-launch timings of one profiled application (see ibf_apply_profile). */
+#define IBF_PROFILE_MAX 64
+typedef struct {
+  int n_launches;
+  char name[IBF_PROFILE_MAX][24];   /* kernel class: "apply_v", "apply_stage", "apply_u", ... */
+  float ms[IBF_PROFILE_MAX];        /* device duration of each launch (hipEvent pairs) */
+  double flops[IBF_PROFILE_MAX];    /* algorithmic flops: 8 per complex MAC of unpadded blocks */
+  double bytes[IBF_PROFILE_MAX];    /* algorithmic HBM bytes: unpadded factors read once plus
+                                       the launch's own input and output vectors */
+} ibf_profile;
+
+/*
+ * Same result as ibf_apply, with a hipEvent recorded around every kernel
+ * launch on `hip_stream`; synchronises the stream and fills *prof.  For
+ * measurement only (the events serialise nothing but add launch gaps).
+ * Errors: as ibf_apply, plus INVALID_ARG for a NULL prof.
+ */
+int ibf_apply_profile(ibf_plan_t plan, const void* g, int64_t ldg, void* u,
+                      int64_t ldu, int64_t nrhs, void* hip_stream,
+                      ibf_profile* prof);
+
+/* Sizes, ranks and build time of a plan.  Errors: INVALID_ARG. */
+int ibf_query(ibf_plan_t plan, ibf_info* info);
+
+/* Free every host and device resource of the plan (NULL is a no-op). */
+int ibf_destroy(ibf_plan_t plan);
+
+/* Thread-local description of the last failure in this thread. */
+const char* ibf_last_error(void);
+
+/*
+ * Phase-evaluation probe: writes exp(2 pi i Phi(x[i], xi[i])) for n point
+ * pairs with the library's FP64 reduced phase (device pointers, double2
+ * output).  Used to check the kernel evaluation against the definition.
+ */
+int ibf_eval_kernel(int phase_id, const double* phase_params, int n_params,
+                    const double* x, const double* xi, int64_t n, void* out,
+                    void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IBF_H */

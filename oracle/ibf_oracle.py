@@ -113,11 +113,14 @@ def kernel(kind, params, x, xi):
 # Dense direct product (the definition u = K g, eqn:DFIO)
 # ----------------------------------------------------------------------------
 
-def dense_apply(kind, params, x, xi, g, rows=None, chunk=512):
+def dense_apply(kind, params, x, xi, g, rows=None, chunk=None):
     """u(x_i) = sum_j K(x_i, xi_j) g_j for the selected rows (all by default).
 
-    g has shape (n_xi,) or (n_xi, nrhs).  O(rows * n_xi) work, chunked.
+    g has shape (n_xi,) or (n_xi, nrhs).  O(rows * n_xi) work, chunked so that
+    one chunk of the kernel matrix holds about 2^22 entries.
     """
+    if chunk is None:
+        chunk = max(1, min(512, (1 << 22) // max(len(xi), 1)))
     g = np.asarray(g, dtype=np.complex128)
     squeeze = g.ndim == 1
     if squeeze:

@@ -1,0 +1,228 @@
+// Device helpers: complex arithmetic, FP64 reduced phase, tree geometry,
+// Chebyshev grids, Lagrange polynomials and the wave-group one-sided Jacobi
+// SVD used by every compression step.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include "ibf_internal.h"
+
+namespace ibf {
+
+// ---------------------------------------------------------------------------
+// complex helpers (double2 / float2 as re, im)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 conjd(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) {
+  return make_double2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ double2 cscale(double2 a, double s) {
+  return make_double2(a.x * s, a.y * s);
+}
+// acc += a * b
+__device__ __forceinline__ void cfma(double2& acc, double2 a, double2 b) {
+  acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
+  acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
+}
+__device__ __forceinline__ void cfma(float2& acc, float2 a, float2 b) {
+  acc.x = fmaf(a.x, b.x, fmaf(-a.y, b.y, acc.x));
+  acc.y = fmaf(a.x, b.y, fmaf(a.y, b.x, acc.y));
+}
+
+// ---------------------------------------------------------------------------
+// Phase Phi(x, xi) reduced mod 1 (paper eqn:FIO kernel exp(2 pi i Phi)).
+// Products of a coordinate and a frequency are reduced error-free with an
+// FMA-based two-product, so the fractional part survives |Phi| ~ N.
+// ---------------------------------------------------------------------------
+__device__ inline double frac_prod(double a, double b) {
+#pragma clang fp contract(off)
+  double p = a * b;
+  double e = fma(a, b, -p);
+  double t = (p - rint(p)) + e;
+  return t - rint(t);
+}
+
+__device__ inline double phase_frac(const PhaseDesc& P, double x, double xi) {
+#pragma clang fp contract(off)
+  double t;
+  if (P.kind == IBF_PHASE_DFT) {
+    t = P.p[0] * frac_prod(x, xi);
+  } else if (P.kind == IBF_PHASE_FIO1D) {
+    // c(x) = (p0 + p1 sin 2 pi x)/p2  (paper eqn:1D-FIO-kernal)
+    double c = (P.p[0] + P.p[1] * sinpi(2.0 * x)) / P.p[2];
+    t = frac_prod(x, xi) + frac_prod(c, fabs(xi));
+  } else {  // separable
+    t = frac_prod(P.p[0], x) + frac_prod(P.p[1], xi);
+  }
+  return t - rint(t);
+}
+
+// exp(2 pi i Phi(x, xi))
+__device__ inline double2 kval(const PhaseDesc& P, double x, double xi) {
+  double t = phase_frac(P, x, xi);
+  double s, c;
+  sincospi(2.0 * t, &s, &c);
+  return make_double2(c, s);
+}
+
+// ---------------------------------------------------------------------------
+// Geometry (half-open dyadic boxes with geometric centres).
+// ---------------------------------------------------------------------------
+__device__ inline double box_cx(int level, int64_t a) {
+#pragma clang fp contract(off)
+  return ((double)a + 0.5) * ldexp(1.0, -level);
+}
+__device__ inline double box_wx(int level) { return ldexp(1.0, -level); }
+__device__ inline double box_cxi(const Geo& g, int level, int64_t b) {
+#pragma clang fp contract(off)
+  double w = g.W / ldexp(1.0, level);
+  return g.lo + ((double)b + 0.5) * w;
+}
+__device__ inline double box_wxi(const Geo& g, int level) { return g.W / ldexp(1.0, level); }
+// grid point c + w z_t
+__device__ inline double grid_pt(double c, double w, double z) {
+#pragma clang fp contract(off)
+  return c + w * z;
+}
+// normalised coordinate (pt - c)/w
+__device__ inline double norm_pt(double pt, double c, double w) {
+#pragma clang fp contract(off)
+  return (pt - c) / w;
+}
+
+// Lagrange polynomial M_t(y) on nodes z[0..r) (paper Sec. 2.1, product form).
+__device__ inline double lagrange_t(const double* z, int r, int t, double y) {
+#pragma clang fp contract(off)
+  double m = 1.0;
+  for (int j = 0; j < r; ++j)
+    if (j != t) m *= (y - z[j]) / (z[t] - z[j]);
+  return m;
+}
+
+// ---------------------------------------------------------------------------
+// Group reductions over G lanes (G a power of two, groups aligned in the
+// wavefront).  The xor butterfly leaves bitwise-identical sums in every lane.
+// ---------------------------------------------------------------------------
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int m = G / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, G);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// One-sided (Hestenes) Jacobi SVD of an n x R complex matrix A, n <= G,
+// held one row per lane (lanes >= n hold zero rows).  On return a[] holds the
+// rows of Q = A J with mutually orthogonal columns, v[] holds row `lane` of
+// the unitary J (lanes < R), and sig[j] = ||Q_j||.  Then A = Q J^* and
+// A^* = J Sigma Uhat^* with Uhat_j = Q_j / sig_j.
+// ---------------------------------------------------------------------------
+constexpr int kJacobiMaxSweeps = 30;
+
+template <int R, int G>
+__device__ inline void jacobi_svd(double2 (&a)[R], double2 (&v)[R], int lane,
+                                  int n, double (&sig)[R]) {
+  const double thresh = 4.0 * (double)(n > 8 ? n : 8) * 1.1102230246251565e-16;
+#pragma unroll
+  for (int j = 0; j < R; ++j) v[j] = make_double2(lane == j ? 1.0 : 0.0, 0.0);
+  double nrm[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) nrm[j] = group_sum<G>(a[j].x * a[j].x + a[j].y * a[j].y);
+
+  for (int sweep = 0; sweep < kJacobiMaxSweeps; ++sweep) {
+    bool rotated = false;
+#pragma unroll
+    for (int p = 0; p < R - 1; ++p) {
+#pragma unroll
+      for (int q = p + 1; q < R; ++q) {
+        // gamma = a_p^H a_q
+        double gr = group_sum<G>(a[p].x * a[q].x + a[p].y * a[q].y);
+        double gi = group_sum<G>(a[p].x * a[q].y - a[p].y * a[q].x);
+        double ag = sqrt(gr * gr + gi * gi);
+        if (ag > thresh * sqrt(nrm[p] * nrm[q]) && ag > 0.0) {
+          double zeta = (nrm[q] - nrm[p]) / (2.0 * ag);
+          double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          double c = 1.0 / sqrt(1.0 + t * t);
+          double s = c * t;
+          double2 e = make_double2(gr / ag, -gi / ag);   // exp(-i arg gamma)
+          double2 eq = cmul(e, a[q]);
+          double2 ap = a[p];
+          a[p] = make_double2(c * ap.x - s * eq.x, c * ap.y - s * eq.y);
+          a[q] = make_double2(s * ap.x + c * eq.x, s * ap.y + c * eq.y);
+          double2 ev = cmul(e, v[q]);
+          double2 vp = v[p];
+          v[p] = make_double2(c * vp.x - s * ev.x, c * vp.y - s * ev.y);
+          v[q] = make_double2(s * vp.x + c * ev.x, s * vp.y + c * ev.y);
+          nrm[p] -= t * ag;
+          nrm[q] += t * ag;
+          rotated = true;
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) nrm[j] = group_sum<G>(a[j].x * a[j].x + a[j].y * a[j].y);
+    if (!__any(rotated)) break;
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) sig[j] = sqrt(nrm[j]);
+}
+
+// Position of column j in descending order of sig (ties by index), and the
+// number of sig_j > tol * max sig.
+template <int R>
+__device__ inline int rank_positions(const double (&sig)[R], double tol, int (&pos)[R]) {
+  double smax = 0.0;
+#pragma unroll
+  for (int j = 0; j < R; ++j) smax = fmax(smax, sig[j]);
+  int k = 0;
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    int pj = 0;
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+      pj += (sig[i] > sig[j] || (sig[i] == sig[j] && i < j)) ? 1 : 0;
+    pos[j] = pj;
+    k += (smax > 0.0 && sig[j] > tol * smax) ? 1 : 0;
+  }
+  return k;
+}
+
+// ---------------------------------------------------------------------------
+// Storage conversions
+// ---------------------------------------------------------------------------
+struct bf16x2c {   // one complex entry as bf16 hi + lo parts
+  unsigned short rh, ih, rl, il;
+};
+
+__device__ inline unsigned short f2bf_rn(float f) {
+  unsigned int u = __float_as_uint(f);
+  unsigned int lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (unsigned short)(u >> 16);
+}
+__device__ inline float bf2f(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
+
+__device__ inline void store_factor(double2* base, int64_t i, double2 v) { base[i] = v; }
+__device__ inline void store_factor(float2* base, int64_t i, double2 v) {
+  base[i] = make_float2((float)v.x, (float)v.y);
+}
+__device__ inline void store_factor(bf16x2c* base, int64_t i, double2 v) {
+  float re = (float)v.x, im = (float)v.y;
+  unsigned short rh = f2bf_rn(re), ih = f2bf_rn(im);
+  unsigned short rl = f2bf_rn((float)(v.x - (double)bf2f(rh)));
+  unsigned short il = f2bf_rn((float)(v.y - (double)bf2f(ih)));
+  base[i] = bf16x2c{rh, ih, rl, il};
+}
+
+__device__ __forceinline__ double2 load_factor(const double2* b, int64_t i) { return b[i]; }
+__device__ __forceinline__ float2 load_factor(const float2* b, int64_t i) { return b[i]; }
+__device__ __forceinline__ float2 load_factor(const bf16x2c* b, int64_t i) {
+  bf16x2c v = b[i];
+  return make_float2(bf2f(v.rh) + bf2f(v.rl), bf2f(v.ih) + bf2f(v.il));
+}
+
+}  // namespace ibf

@@ -1,0 +1,104 @@
+// Internal declarations shared by the planner, the build and the apply code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ibf.h"
+
+namespace ibf {
+
+constexpr int kMaxR = 16;          // Chebyshev points per box supported on device
+constexpr int kMaxParams = 6;
+
+struct PhaseDesc {
+  int kind;
+  double p[kMaxParams];
+};
+
+// Device-side geometry of one tree pair: T_X on [0,1), T_Omega on
+// [lo, lo + W).  Box centres and widths are closed-form per level.
+struct Geo {
+  int L, l0, h, r;
+  double lo, W;
+};
+
+void set_error(const std::string& msg);
+
+// Stored factors of one compressed level stage, in the plan's precision.
+struct Stage {
+  int level_out;     // output coefficient level (l0+1 .. L-l0)
+  int k_out, k_in;   // stored ranks
+  void* blk;         // [pair][k_out][2*k_in] complex
+  size_t bytes;
+  int64_t nnz;       // unpadded entries (each block at its own ranks)
+};
+
+}  // namespace ibf
+
+struct ibf_plan_s {
+  // descriptor
+  int dim = 1;
+  int64_t nx = 0, nxi = 0;
+  int device = 0;
+  ibf::PhaseDesc phase{};
+  int r = 0, leaf = 0, precision = 0, sweep_in = 0;
+  double tol = 0;
+  ibf::Geo geo{};
+  int64_t npairs = 0, nleaf = 0;
+
+  // host geometry (sorted order)
+  std::vector<double> xs, xis;
+  std::vector<int32_t> perm_x, perm_xi;   // sorted position -> caller index
+  std::vector<int32_t> xoff, xioff;       // leaf CSR offsets (nleaf + 1)
+  std::vector<int32_t> xleaf, xileaf;     // leaf of each sorted point
+  int smax_x = 0, smax_xi = 0;
+
+  // device copies of the geometry
+  double *d_xs = nullptr, *d_xis = nullptr;
+  int32_t *d_perm_x = nullptr, *d_perm_xi = nullptr;
+  int32_t *d_xoff = nullptr, *d_xioff = nullptr;
+  int32_t *d_xleaf = nullptr, *d_xileaf = nullptr;
+
+  // factors
+  bool built = false;
+  std::vector<int> rank;            // per coefficient level l0..L-l0 (index l - l0)
+  std::vector<int> rank_in_g, rank_in_h;  // sweep-in ranks (same indexing)
+  std::vector<ibf::Stage> stages;   // H stages then G stages, in apply order
+  void* d_vbar = nullptr;           // [xi point][2^l0][K_l0]
+  size_t vbar_bytes = 0;
+  void* d_ubar = nullptr;           // [x point][2^l0][K_{L-l0}]
+  size_t ubar_bytes = 0;
+  void* d_mdot = nullptr;           // sweep-in middle block [pair][KG][KH] or null
+  size_t mdot_bytes = 0;
+  int k_vbar = 0, k_ubar = 0, k_mid_g = 0, k_mid_h = 0;
+  int64_t nnz_vbar = 0, nnz_ubar = 0;   // unpadded outer-factor entries
+  int64_t nnz_prelim = 0, nnz_opt = 0, nnz_stored = 0;
+  double build_ms = 0;
+
+  // apply workspace (ping-pong coefficient buffers)
+  void* d_work[2] = {nullptr, nullptr};
+  size_t work_bytes = 0;
+};
+
+namespace ibf {
+int build_plan(ibf_plan_t p, hipStream_t s);
+int apply_plan(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu,
+               int64_t nrhs, hipStream_t s, ibf_profile* prof = nullptr);
+int eval_kernel(const PhaseDesc& ph, const double* x, const double* xi,
+                int64_t n, void* out, hipStream_t s);
+void free_factors(ibf_plan_t p);
+size_t complex_bytes(int precision);
+}  // namespace ibf
+
+#define IBF_HIP_CHECK(expr)                                                   \
+  do {                                                                        \
+    hipError_t _e = (expr);                                                   \
+    if (_e != hipSuccess) {                                                   \
+      ibf::set_error(std::string(#expr) + ": " + hipGetErrorString(_e));      \
+      return (_e == hipErrorOutOfMemory) ? IBF_ERR_OOM : IBF_ERR_DEVICE;      \
+    }                                                                         \
+  } while (0)

@@ -1,0 +1,264 @@
+// Host planner and C entry points.
+//
+// ibf_plan builds the dyadic trees of Sec. 3 ("Preliminaries"): T_X on
+// [0,1) and T_Omega on the frequency domain, with depth L chosen so that a
+// box pair (A at level l, B at level L-l) has w_A * w_B <= 1, and sorts both
+// point sets into leaves of about `leaf` points.  Everything here is host
+// integer / FP64 bookkeeping; all factor arithmetic runs on the device.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "ibf_internal.h"
+
+namespace {
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+// Stable counting sort of points into `nleaf` leaves given their leaf index.
+void sort_into_leaves(const std::vector<int64_t>& leaf_of, int64_t nleaf,
+                      std::vector<int32_t>& perm, std::vector<int32_t>& off,
+                      std::vector<int32_t>& leaf_sorted, int& smax) {
+  const int64_t n = (int64_t)leaf_of.size();
+  std::vector<int64_t> cnt(nleaf + 1, 0);
+  for (int64_t i = 0; i < n; ++i) cnt[leaf_of[i] + 1]++;
+  smax = 0;
+  for (int64_t b = 0; b < nleaf; ++b) smax = std::max<int64_t>(smax, cnt[b + 1]);
+  for (int64_t b = 0; b < nleaf; ++b) cnt[b + 1] += cnt[b];
+  off.assign(cnt.begin(), cnt.end());
+  perm.assign(n, 0);
+  leaf_sorted.assign(n, 0);
+  std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t b = leaf_of[i];
+    perm[pos[b]] = (int32_t)i;
+    leaf_sorted[pos[b]] = (int32_t)b;
+    pos[b]++;
+  }
+}
+}  // namespace
+
+namespace ibf {
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+size_t complex_bytes(int precision) { return precision == IBF_FP64 ? 16 : 8; }
+
+void free_factors(ibf_plan_t p) {
+  for (auto& st : p->stages)
+    if (st.blk) (void)hipFree(st.blk);
+  p->stages.clear();
+  void** bufs[] = {&p->d_vbar, &p->d_ubar, &p->d_mdot, &p->d_work[0], &p->d_work[1]};
+  for (void** b : bufs) {
+    if (*b) (void)hipFree(*b);
+    *b = nullptr;
+  }
+  p->work_bytes = 0;
+  p->built = false;
+}
+}  // namespace ibf
+
+extern "C" {
+
+const char* ibf_last_error(void) { return g_last_error.c_str(); }
+
+int ibf_plan(const ibf_desc* d, ibf_plan_t* out) {
+  if (!d || !out) return fail(IBF_ERR_INVALID_ARG, "ibf_plan: null argument");
+  *out = nullptr;
+  if (d->dim != 1) return fail(IBF_ERR_UNSUPPORTED, "ibf_plan: only dim == 1 is supported");
+  if (d->n_x < 1 || d->n_xi < 1) return fail(IBF_ERR_INVALID_ARG, "ibf_plan: empty point set");
+  if (d->n_x > (int64_t)1 << 30 || d->n_xi > (int64_t)1 << 30)
+    return fail(IBF_ERR_INVALID_ARG, "ibf_plan: more than 2^30 points");
+  if (!d->x || !d->xi) return fail(IBF_ERR_INVALID_ARG, "ibf_plan: null point array");
+  if (d->r < 2) return fail(IBF_ERR_INVALID_ARG, "ibf_plan: r must be >= 2");
+  if (d->r > ibf::kMaxR) return fail(IBF_ERR_UNSUPPORTED, "ibf_plan: r > 16 not supported");
+  if (!(d->tol > 0.0 && d->tol < 1.0))
+    return fail(IBF_ERR_INVALID_ARG, "ibf_plan: tol must lie in (0, 1)");
+  if (d->leaf < 2 || (d->leaf & (d->leaf - 1)))
+    return fail(IBF_ERR_INVALID_ARG, "ibf_plan: leaf must be a power of two >= 2");
+  if (d->precision < IBF_FP64 || d->precision > IBF_BF16X2)
+    return fail(IBF_ERR_INVALID_ARG, "ibf_plan: unknown precision");
+  if (d->sweep_in != 0 && d->sweep_in != 1)
+    return fail(IBF_ERR_INVALID_ARG, "ibf_plan: sweep_in must be 0 or 1");
+
+  ibf::PhaseDesc ph{};
+  ph.kind = d->phase_id;
+  const double* pp = d->phase_params;
+  int np = d->n_params;
+  if (np < 0 || np > ibf::kMaxParams || (np > 0 && !pp))
+    return fail(IBF_ERR_INVALID_ARG, "ibf_plan: bad phase parameters");
+  switch (d->phase_id) {
+    case IBF_PHASE_DFT:
+      ph.p[0] = np >= 1 ? pp[0] : 1.0;
+      if (ph.p[0] != 1.0 && ph.p[0] != -1.0)
+        return fail(IBF_ERR_INVALID_ARG, "ibf_plan: DFT sign must be +1 or -1");
+      break;
+    case IBF_PHASE_FIO1D:
+      ph.p[0] = np >= 1 ? pp[0] : 2.0;
+      ph.p[1] = np >= 2 ? pp[1] : 1.0;
+      ph.p[2] = np >= 3 ? pp[2] : 8.0;
+      if (ph.p[2] == 0.0) return fail(IBF_ERR_INVALID_ARG, "ibf_plan: p2 == 0");
+      break;
+    case IBF_PHASE_SEPARABLE:
+      ph.p[0] = np >= 1 ? pp[0] : 3.0;
+      ph.p[1] = np >= 2 ? pp[1] : 0.3125;
+      break;
+    default:
+      return fail(IBF_ERR_UNSUPPORTED, "ibf_plan: unsupported phase for dim 1");
+  }
+
+  const double W = d->omega_width > 0 ? d->omega_width : (double)d->n_xi;
+  const double lo = d->omega_lo;
+  int L = (int)std::ceil(std::log2(W) - 1e-12);
+  int l0 = 0;
+  while ((1 << l0) < d->leaf) ++l0;
+  if (L < 2 * l0)
+    return fail(IBF_ERR_INVALID_ARG, "ibf_plan: need omega_width >= leaf^2 (N >= leaf^2)");
+  if (L > 30) return fail(IBF_ERR_INVALID_ARG, "ibf_plan: tree too deep");
+
+  auto p = new ibf_plan_s();
+  p->dim = 1;
+  p->nx = d->n_x;
+  p->nxi = d->n_xi;
+  p->device = d->device;
+  p->phase = ph;
+  p->r = d->r;
+  p->leaf = d->leaf;
+  p->precision = d->precision;
+  p->sweep_in = d->sweep_in;
+  p->tol = d->tol;
+  p->geo = ibf::Geo{L, l0, L / 2, d->r, lo, W};
+  p->npairs = (int64_t)1 << L;
+  p->nleaf = (int64_t)1 << (L - l0);
+
+  // Leaf index of every point: floor(position * 2^(L-l0) / width).
+  const int64_t nl = p->nleaf;
+  std::vector<int64_t> lx(d->n_x), lxi(d->n_xi);
+  for (int64_t i = 0; i < d->n_x; ++i) {
+    double v = d->x[i];
+    if (!(v >= 0.0 && v < 1.0)) {
+      delete p;
+      return fail(IBF_ERR_INVALID_ARG, "ibf_plan: x outside [0, 1)");
+    }
+    int64_t b = (int64_t)std::floor(v * (double)nl);
+    lx[i] = std::min<int64_t>(std::max<int64_t>(b, 0), nl - 1);
+  }
+  for (int64_t j = 0; j < d->n_xi; ++j) {
+    double v = d->xi[j];
+    if (!(v >= lo && v < lo + W)) {
+      delete p;
+      return fail(IBF_ERR_INVALID_ARG, "ibf_plan: xi outside the Omega domain");
+    }
+    int64_t b = (int64_t)std::floor((v - lo) * (double)nl / W);
+    lxi[j] = std::min<int64_t>(std::max<int64_t>(b, 0), nl - 1);
+  }
+  sort_into_leaves(lx, nl, p->perm_x, p->xoff, p->xleaf, p->smax_x);
+  sort_into_leaves(lxi, nl, p->perm_xi, p->xioff, p->xileaf, p->smax_xi);
+  p->xs.resize(d->n_x);
+  p->xis.resize(d->n_xi);
+  for (int64_t i = 0; i < d->n_x; ++i) p->xs[i] = d->x[p->perm_x[i]];
+  for (int64_t j = 0; j < d->n_xi; ++j) p->xis[j] = d->xi[p->perm_xi[j]];
+
+  // Preliminary non-zeros (memory numerator of the compression ratio).
+  const int r = d->r;
+  const int nstages = L - 2 * l0;
+  p->nnz_prelim = (d->n_x + d->n_xi) * ((int64_t)1 << l0) * r +
+                  (int64_t)nstages * p->npairs * 2 * r * r + p->npairs * r * r;
+  *out = p;
+  return IBF_OK;
+}
+
+int ibf_build(ibf_plan_t p, void* stream) {
+  if (!p) return fail(IBF_ERR_INVALID_ARG, "ibf_build: null plan");
+  auto t0 = std::chrono::steady_clock::now();
+  int rc = ibf::build_plan(p, (hipStream_t)stream);
+  auto t1 = std::chrono::steady_clock::now();
+  p->build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  return rc;
+}
+
+int ibf_apply(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu,
+              int64_t nrhs, void* stream) {
+  if (!p) return fail(IBF_ERR_INVALID_ARG, "ibf_apply: null plan");
+  if (!p->built) return fail(IBF_ERR_NOT_BUILT, "ibf_apply: plan not built");
+  if (!g || !u) return fail(IBF_ERR_INVALID_ARG, "ibf_apply: null vector");
+  if (nrhs < 1) return fail(IBF_ERR_INVALID_ARG, "ibf_apply: nrhs < 1");
+  if (ldg < p->nxi || ldu < p->nx) return fail(IBF_ERR_INVALID_ARG, "ibf_apply: leading dimension too small");
+  return ibf::apply_plan(p, g, ldg, u, ldu, nrhs, (hipStream_t)stream);
+}
+
+int ibf_apply_profile(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu,
+                      int64_t nrhs, void* stream, ibf_profile* prof) {
+  if (!prof) return fail(IBF_ERR_INVALID_ARG, "ibf_apply_profile: null profile");
+  if (!p) return fail(IBF_ERR_INVALID_ARG, "ibf_apply_profile: null plan");
+  if (!p->built) return fail(IBF_ERR_NOT_BUILT, "ibf_apply_profile: plan not built");
+  if (!g || !u) return fail(IBF_ERR_INVALID_ARG, "ibf_apply_profile: null vector");
+  if (nrhs < 1) return fail(IBF_ERR_INVALID_ARG, "ibf_apply_profile: nrhs < 1");
+  if (ldg < p->nxi || ldu < p->nx)
+    return fail(IBF_ERR_INVALID_ARG, "ibf_apply_profile: leading dimension too small");
+  std::memset(prof, 0, sizeof(*prof));
+  return ibf::apply_plan(p, g, ldg, u, ldu, nrhs, (hipStream_t)stream, prof);
+}
+
+int ibf_query(ibf_plan_t p, ibf_info* info) {
+  if (!p || !info) return fail(IBF_ERR_INVALID_ARG, "ibf_query: null argument");
+  std::memset(info, 0, sizeof(*info));
+  info->L = p->geo.L;
+  info->l0 = p->geo.l0;
+  info->h = p->geo.h;
+  info->n_levels = p->geo.L - 2 * p->geo.l0 + 1;
+  for (size_t i = 0; i < p->rank.size() && i < 64; ++i) info->rank[i] = p->rank[i];
+  info->n_pairs = p->npairs;
+  info->nnz_prelim = p->nnz_prelim;
+  info->nnz_opt = p->nnz_opt;
+  info->nnz_stored = p->nnz_stored;
+  int64_t fb = (int64_t)(p->vbar_bytes + p->ubar_bytes + p->mdot_bytes);
+  for (auto& st : p->stages) fb += (int64_t)st.bytes;
+  info->factor_bytes = fb;
+  info->build_ms = p->build_ms;
+  info->smax_x = p->smax_x;
+  info->smax_xi = p->smax_xi;
+  return IBF_OK;
+}
+
+int ibf_destroy(ibf_plan_t p) {
+  if (!p) return IBF_OK;
+  if (!p->d_xs && !p->built) {   // never touched the device
+    delete p;
+    return IBF_OK;
+  }
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(p->device);
+  ibf::free_factors(p);
+  void* bufs[] = {p->d_xs, p->d_xis, p->d_perm_x, p->d_perm_xi,
+                  p->d_xoff, p->d_xioff, p->d_xleaf, p->d_xileaf};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  (void)hipSetDevice(cur);
+  delete p;
+  return IBF_OK;
+}
+
+int ibf_eval_kernel(int phase_id, const double* params, int n_params,
+                    const double* x, const double* xi, int64_t n, void* out,
+                    void* stream) {
+  if (!x || !xi || !out || n < 0 || n_params < 0 || n_params > ibf::kMaxParams ||
+      (n_params > 0 && !params))
+    return fail(IBF_ERR_INVALID_ARG, "ibf_eval_kernel: bad argument");
+  ibf::PhaseDesc ph{};
+  ph.kind = phase_id;
+  const double defaults[4][3] = {{1, 0, 0}, {2, 1, 8}, {2, 1, 16}, {3, 0.3125, 0}};
+  if (phase_id < 0 || phase_id > 3 || phase_id == IBF_PHASE_FIO2D)
+    return fail(IBF_ERR_UNSUPPORTED, "ibf_eval_kernel: unsupported phase");
+  for (int i = 0; i < 3; ++i) ph.p[i] = i < n_params ? params[i] : defaults[phase_id][i];
+  if (n == 0) return IBF_OK;
+  return ibf::eval_kernel(ph, x, xi, n, out, (hipStream_t)stream);
+}
+
+}  // extern "C"

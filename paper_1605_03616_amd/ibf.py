@@ -1,0 +1,251 @@
+"""Thin ctypes binding of libibf.so (the C-ABI in include/ibf.h).
+
+Argument marshalling only: every step of the factorization and of its
+application runs in the library's HIP kernels.  PyTorch supplies device
+memory and the current stream.  If the library is missing this module
+raises at import of the library, never falls back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from .inputs import PREC_BF16X2, PREC_FP32, PREC_FP64  # noqa: F401
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libibf.so")
+
+IBF_OK = 0
+ERRORS = {-1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "OOM", -4: "DEVICE", -5: "NOT_BUILT"}
+
+EXPORTED = ["ibf_plan", "ibf_build", "ibf_apply", "ibf_apply_profile", "ibf_query",
+            "ibf_destroy", "ibf_last_error", "ibf_eval_kernel"]
+PROFILE_MAX = 64
+
+
+class IBFDesc(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int),
+        ("n_x", C.c_int64),
+        ("n_xi", C.c_int64),
+        ("x", C.POINTER(C.c_double)),
+        ("xi", C.POINTER(C.c_double)),
+        ("omega_lo", C.c_double),
+        ("omega_width", C.c_double),
+        ("phase_id", C.c_int),
+        ("phase_params", C.POINTER(C.c_double)),
+        ("n_params", C.c_int),
+        ("r", C.c_int),
+        ("tol", C.c_double),
+        ("leaf", C.c_int),
+        ("precision", C.c_int),
+        ("sweep_in", C.c_int),
+        ("device", C.c_int),
+    ]
+
+
+class IBFInfo(C.Structure):
+    _fields_ = [
+        ("L", C.c_int), ("l0", C.c_int), ("h", C.c_int), ("n_levels", C.c_int),
+        ("rank", C.c_int * 64),
+        ("n_pairs", C.c_int64),
+        ("nnz_prelim", C.c_int64),
+        ("nnz_opt", C.c_int64),
+        ("nnz_stored", C.c_int64),
+        ("factor_bytes", C.c_int64),
+        ("build_ms", C.c_double),
+        ("smax_x", C.c_int), ("smax_xi", C.c_int),
+    ]
+
+
+class IBFProfile(C.Structure):
+    _fields_ = [
+        ("n_launches", C.c_int),
+        ("name", (C.c_char * 24) * PROFILE_MAX),
+        ("ms", C.c_float * PROFILE_MAX),
+        ("flops", C.c_double * PROFILE_MAX),
+        ("bytes", C.c_double * PROFILE_MAX),
+    ]
+
+
+class IBFError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libibf.so (raises OSError when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError(f"{path} not found: build it with paper_1605_03616_amd.build_lib")
+    lib = C.CDLL(path)
+    lib.ibf_plan.argtypes = [C.POINTER(IBFDesc), C.POINTER(C.c_void_p)]
+    lib.ibf_build.argtypes = [C.c_void_p, C.c_void_p]
+    lib.ibf_apply.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                              C.c_int64, C.c_void_p]
+    lib.ibf_apply_profile.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                      C.c_int64, C.c_int64, C.c_void_p, C.POINTER(IBFProfile)]
+    lib.ibf_query.argtypes = [C.c_void_p, C.POINTER(IBFInfo)]
+    lib.ibf_destroy.argtypes = [C.c_void_p]
+    lib.ibf_last_error.restype = C.c_char_p
+    lib.ibf_eval_kernel.argtypes = [C.c_int, C.POINTER(C.c_double), C.c_int, C.c_void_p,
+                                    C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+    for name in ("ibf_plan", "ibf_build", "ibf_apply", "ibf_apply_profile", "ibf_query",
+                 "ibf_destroy", "ibf_eval_kernel"):
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().ibf_last_error().decode()
+
+
+def _check(rc):
+    if rc != IBF_OK:
+        raise IBFError(rc, last_error())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def make_desc(x, xi, phase, params, r, tol, leaf, precision, sweep_in=0,
+              omega_lo=None, omega_width=0.0, device=0):
+    """Build an ibf_desc; returns (desc, keepalive) -- keep both alive."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    prm = np.ascontiguousarray(params if params is not None else [], dtype=np.float64)
+    d = IBFDesc()
+    d.dim = 1
+    d.n_x = x.shape[0]
+    d.n_xi = xi.shape[0]
+    d.x = x.ctypes.data_as(C.POINTER(C.c_double))
+    d.xi = xi.ctypes.data_as(C.POINTER(C.c_double))
+    d.omega_lo = float(-(xi.shape[0] // 2) if omega_lo is None else omega_lo)
+    d.omega_width = float(omega_width)
+    d.phase_id = int(phase)
+    d.phase_params = prm.ctypes.data_as(C.POINTER(C.c_double)) if prm.size else None
+    d.n_params = int(prm.size)
+    d.r = int(r)
+    d.tol = float(tol)
+    d.leaf = int(leaf)
+    d.precision = int(precision)
+    d.sweep_in = int(sweep_in)
+    d.device = int(device)
+    return d, (x, xi, prm)
+
+
+class Plan:
+    """Owns an ibf_plan_t.  Mirrors ibf_plan / ibf_build / ibf_apply /
+    ibf_query / ibf_destroy; device vectors are torch tensors."""
+
+    def __init__(self, x, xi, phase, params, r, tol, leaf=16, precision=PREC_FP64,
+                 sweep_in=0, omega_lo=None, omega_width=0.0, device=0):
+        lib = load()
+        self._lib = lib
+        d, keep = make_desc(x, xi, phase, params, r, tol, leaf, precision, sweep_in,
+                            omega_lo, omega_width, device)
+        h = C.c_void_p()
+        _check(lib.ibf_plan(C.byref(d), C.byref(h)))
+        self.handle = h
+        self.precision = precision
+        self.n_x = int(d.n_x)
+        self.n_xi = int(d.n_xi)
+        self.device = device
+
+    @classmethod
+    def from_problem(cls, P, precision=None, sweep_in=None):
+        return cls(P.x, P.xi, P.phase, P.params, P.r, P.tol, P.leaf,
+                   P.precision if precision is None else precision,
+                   P.sweep_in if sweep_in is None else sweep_in)
+
+    def build(self, stream=None):
+        _check(self._lib.ibf_build(self.handle, _stream_handle(stream)))
+        return self
+
+    def vector_dtype(self):
+        import torch
+        return torch.complex128 if self.precision == PREC_FP64 else torch.complex64
+
+    def apply(self, g, u=None, stream=None):
+        """g: device tensor (nrhs, n_xi) or (n_xi,), complex; returns u (nrhs, n_x)."""
+        import torch
+        squeeze = g.dim() == 1
+        if squeeze:
+            g = g.unsqueeze(0)
+        if g.dtype != self.vector_dtype() or not g.is_contiguous():
+            raise ValueError("g must be a contiguous tensor of the plan's complex dtype")
+        nrhs = g.shape[0]
+        if u is None:
+            u = torch.empty((nrhs, self.n_x), dtype=g.dtype, device=g.device)
+        _check(self._lib.ibf_apply(self.handle, C.c_void_p(g.data_ptr()), g.shape[1],
+                                   C.c_void_p(u.data_ptr()), u.shape[1], nrhs,
+                                   _stream_handle(stream)))
+        return u[0] if squeeze else u
+
+    def apply_raw(self, g_ptr, ldg, u_ptr, ldu, nrhs, stream=None):
+        _check(self._lib.ibf_apply(self.handle, C.c_void_p(g_ptr), ldg, C.c_void_p(u_ptr), ldu,
+                                   nrhs, _stream_handle(stream)))
+
+    def apply_profile(self, g, u, stream=None):
+        """ibf_apply_profile on (nrhs, n) tensors; returns a list of launches
+        (name, ms, flops, bytes)."""
+        prof = IBFProfile()
+        _check(self._lib.ibf_apply_profile(self.handle, C.c_void_p(g.data_ptr()), g.shape[1],
+                                           C.c_void_p(u.data_ptr()), u.shape[1], g.shape[0],
+                                           _stream_handle(stream), C.byref(prof)))
+        return [(bytes(prof.name[i]).split(b"\0")[0].decode(), float(prof.ms[i]),
+                 float(prof.flops[i]), float(prof.bytes[i])) for i in range(prof.n_launches)]
+
+    def query(self) -> dict:
+        info = IBFInfo()
+        _check(self._lib.ibf_query(self.handle, C.byref(info)))
+        n = info.n_levels
+        return {
+            "L": info.L, "l0": info.l0, "h": info.h, "n_levels": n,
+            "rank": [info.rank[i] for i in range(n)],
+            "n_pairs": info.n_pairs, "nnz_prelim": info.nnz_prelim,
+            "nnz_opt": info.nnz_opt, "nnz_stored": info.nnz_stored,
+            "factor_bytes": info.factor_bytes, "build_ms": info.build_ms,
+            "smax_x": info.smax_x, "smax_xi": info.smax_xi,
+            "R_comp": info.nnz_prelim / max(info.nnz_opt, 1),
+        }
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            self._lib.ibf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def eval_kernel(phase, params, x_dev, xi_dev, stream=None):
+    """exp(2 pi i Phi(x, xi)) on the device for paired float64 tensors."""
+    import torch
+    lib = load()
+    prm = np.ascontiguousarray(params if params is not None else [], dtype=np.float64)
+    out = torch.empty(x_dev.shape[0], dtype=torch.complex128, device=x_dev.device)
+    _check(lib.ibf_eval_kernel(int(phase),
+                               prm.ctypes.data_as(C.POINTER(C.c_double)) if prm.size else None,
+                               int(prm.size), C.c_void_p(x_dev.data_ptr()),
+                               C.c_void_p(xi_dev.data_ptr()), x_dev.shape[0],
+                               C.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out

@@ -1,0 +1,94 @@
+"""Host-side checks of the C-ABI: the library loads, exports every symbol
+that include/ibf.h declares, and validates descriptors without touching a
+device (ibf_plan is host-only)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1605_03616_amd import ibf
+from paper_1605_03616_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "ibf.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(ibf_\w+)\s*\(", src, re.M)))
+
+
+def test_header_and_binding_agree():
+    decl = _declared_symbols()
+    assert decl == sorted(ibf.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ibf.load()
+    for name in _declared_symbols():
+        assert hasattr(lib, name), name
+
+
+def _plan(**kw):
+    P = I.workload_fio1d_1k()
+    args = dict(x=P.x, xi=P.xi, phase=P.phase, params=P.params, r=P.r, tol=P.tol,
+                leaf=P.leaf, precision=P.precision)
+    args.update(kw)
+    return ibf.Plan(**args)
+
+
+def test_plan_and_query_geometry():
+    pl = _plan()
+    q = pl.query()
+    assert (q["L"], q["l0"], q["h"], q["n_levels"]) == (10, 4, 5, 3)
+    assert q["n_pairs"] == 1024
+    assert q["smax_x"] == 16 and q["smax_xi"] == 16
+    r = 8
+    assert q["nnz_prelim"] == 2 * 1024 * 16 * r + 2 * 1024 * 2 * r * r + 1024 * r * r
+    pl.destroy()
+
+
+def test_plan_geometry_ragged_and_odd_depth():
+    P = I.nudft_random(2048, 6, 1, 7)
+    pl = ibf.Plan(P.x, P.xi, P.phase, P.params, 6, 1e-6, 16, I.PREC_FP32)
+    q = pl.query()
+    assert (q["L"], q["l0"], q["h"]) == (11, 4, 5)
+    cnt = np.bincount(np.floor(P.x * 128).astype(int), minlength=128)
+    assert q["smax_x"] == cnt.max()
+    pl.destroy()
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(r=1), "INVALID_ARG"),
+    (dict(r=17), "UNSUPPORTED"),
+    (dict(tol=0.0), "INVALID_ARG"),
+    (dict(tol=1.5), "INVALID_ARG"),
+    (dict(leaf=12), "INVALID_ARG"),
+    (dict(leaf=64), "INVALID_ARG"),          # 1024 < 64^2
+    (dict(precision=7), "INVALID_ARG"),
+    (dict(phase=9), "UNSUPPORTED"),
+    (dict(x=np.full(1024, 1.0)), "INVALID_ARG"),   # outside [0,1)
+    (dict(xi=np.arange(1024.0) + 600), "INVALID_ARG"),
+])
+def test_plan_rejects_bad_descriptors(kw, code):
+    with pytest.raises(ibf.IBFError) as ei:
+        _plan(**kw)
+    assert code in str(ei.value)
+
+
+def test_apply_before_build_is_not_built():
+    pl = _plan()
+    lib = ibf.load()
+    rc = lib.ibf_apply(pl.handle, C.c_void_p(1), 1024, C.c_void_p(2), 1024, 1, None)
+    assert rc == -5
+    assert "not built" in ibf.last_error()
+    pl.destroy()
+
+
+def test_null_arguments():
+    lib = ibf.load()
+    assert lib.ibf_plan(None, None) == -1
+    assert lib.ibf_build(None, None) == -1
+    assert lib.ibf_query(None, None) == -1
+    assert lib.ibf_destroy(None) == 0

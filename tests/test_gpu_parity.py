@@ -1,0 +1,193 @@
+"""GPU parity: the HIP build + apply (through the C-ABI) against the FP64 oracle.
+
+Applied outputs and per-level ranks are compared (factor entries are not
+unique: SVD phases and rotations, zero padding).  Tolerances:
+  FP64   max(1e-12, 8 N 2^-53) relative  (the phase-evaluation floor, FP64
+         sin/cos of the two libraries differ by an ulp and |Phi| ~ N)
+  FP32   1e-5 relative
+  BF16X2 1e-4 relative
+"""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ibf_oracle as O
+from paper_1605_03616_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1605_03616_amd import ibf
+    ibf.load()
+    return torch
+
+
+def fp64_tol(n):
+    return max(1e-12, 8 * n * 2.0 ** -53)
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle(key):
+    P = _problems()[key]
+    prob, F, Op = O.build_optimal(P.phase, P.params, P.x, P.xi, P.r, P.tol, P.leaf,
+                                  sweep_in_on=False)
+    u = O.apply_optimal(Op, P.g)
+    return P, prob, Op, u
+
+
+@functools.lru_cache(maxsize=None)
+def _problems():
+    return {
+        "fio1k_r8": I.workload_fio1d_1k(),
+        "dft4k_r10": I.dft_uniform(4096, 10, 3, 21),
+        "nudft4k_r10": I.nudft_random(4096, 10, 2, 22, sweep_in=0, precision=I.PREC_FP64),
+        "fio3000_r9": I.Problem1D("fio3000", I.uniform_x(3000), I.uniform_xi(3000),
+                                  I.PHASE_FIO1D, (2.0, 1.0, 8.0), 9, 1e-6, 16, 2,
+                                  I.complex_normal(3000, 2, np.random.default_rng(23)),
+                                  I.PREC_FP64),
+        "fio256_r6": I.fio1d_uniform(256, 6, 1, 24),
+        "fio4k_r12": I.fio1d_uniform(4096, 12, 8, 25, precision=I.PREC_FP32),
+        "fio8k_r16": I.fio1d_uniform(8192, 16, 2, 26),
+        "fio2k_r2": I.fio1d_uniform(2048, 2, 1, 27, tol=1e-3),
+    }
+
+
+def _run_gpu(torch, P, precision, nrhs=None, ld_pad=0):
+    from paper_1605_03616_amd import ibf
+    pl = ibf.Plan(P.x, P.xi, P.phase, P.params, P.r, P.tol, P.leaf, precision, 0)
+    pl.build()
+    g = P.g if nrhs is None else P.g[:, :nrhs]
+    dt = torch.complex128 if precision == I.PREC_FP64 else torch.complex64
+    nr = g.shape[1]
+    gbuf = torch.zeros((nr, P.n + ld_pad), dtype=dt, device="cuda")
+    gbuf[:, :P.n] = torch.from_numpy(np.ascontiguousarray(g.T)).to(dt).cuda()
+    ubuf = torch.full((nr, P.n + ld_pad), 7.0 + 0j, dtype=dt, device="cuda")
+    pl.apply_raw(gbuf.data_ptr(), P.n + ld_pad, ubuf.data_ptr(), P.n + ld_pad, nr)
+    torch.cuda.synchronize()
+    u = ubuf[:, :P.n].cpu().numpy().T.astype(np.complex128)
+    if ld_pad:
+        assert torch.all(ubuf[:, P.n:] == 7.0).item()   # padding untouched
+    q = pl.query()
+    pl.destroy()
+    return u, q
+
+
+def test_kernel_evaluation_matches_definition(torch_dev):
+    torch = torch_dev
+    from paper_1605_03616_amd import ibf
+    rng = np.random.default_rng(40)
+    n = 1 << 20
+    x = rng.integers(0, n, 20000) / n
+    xi = rng.integers(-n // 2, n // 2, 20000).astype(np.float64)
+    for kind, prm, tol in [(I.PHASE_DFT, (1.0,), 2e-15), (I.PHASE_DFT, (-1.0,), 2e-15),
+                           (I.PHASE_FIO1D, (2.0, 1.0, 8.0), 2e-10),
+                           (I.PHASE_SEPARABLE, (3.0, 0.3125), 2e-15)]:
+        _say(f"eval_kernel kind={kind}")
+        out = ibf.eval_kernel(kind, prm, torch.from_numpy(x).cuda(),
+                              torch.from_numpy(xi).cuda()).cpu().numpy()
+        ref = O.kernel(kind, prm, x, xi)
+        assert np.max(np.abs(out - ref)) < tol, kind
+
+
+@pytest.mark.parametrize("key", ["fio1k_r8", "dft4k_r10", "nudft4k_r10", "fio3000_r9",
+                                 "fio256_r6", "fio8k_r16", "fio2k_r2"])
+def test_fp64_parity(torch_dev, key):
+    _say(f"fp64 parity {key}")
+    P, prob, Op, u_ref = _oracle(key)
+    u, q = _run_gpu(torch_dev, P, I.PREC_FP64)
+    err = O.rel_error(u, u_ref)
+    assert err < fp64_tol(P.n), (key, err)
+    assert q["rank"] == [v for _, v in sorted(O.level_ranks(Op).items())]
+    assert q["nnz_opt"] == O.nnz_optimal(Op)
+    assert q["nnz_prelim"] == O.nnz_prelim(prob)
+
+
+def test_fp64_leading_dimension(torch_dev):
+    _say("fp64 ld padding")
+    P, prob, Op, u_ref = _oracle("dft4k_r10")
+    u, _ = _run_gpu(torch_dev, P, I.PREC_FP64, ld_pad=5)
+    assert O.rel_error(u, u_ref) < fp64_tol(P.n)
+
+
+def test_fp32_parity(torch_dev):
+    _say("fp32 parity fio4k_r12")
+    P, prob, Op, u_ref = _oracle("fio4k_r12")
+    u, q = _run_gpu(torch_dev, P, I.PREC_FP32)
+    assert O.rel_error(u, u_ref) < 1e-5
+    assert q["rank"] == [v for _, v in sorted(O.level_ranks(Op).items())]
+
+
+def test_bf16x2_parity(torch_dev):
+    _say("bf16x2 parity fio4k_r12")
+    P, prob, Op, u_ref = _oracle("fio4k_r12")
+    u, q = _run_gpu(torch_dev, P, I.PREC_BF16X2)
+    assert O.rel_error(u, u_ref) < 1e-4
+
+
+def test_separable_phase_exact(torch_dev):
+    _say("separable exactness")
+    P = I.separable_uniform(2048, 4, 2, 30, tol=1e-10)
+    u, q = _run_gpu(torch_dev, P, I.PREC_FP64)
+    ud = O.dense_apply(P.phase, P.params, P.x, P.xi, P.g)
+    assert O.rel_error(u, ud) < 1e-12
+    assert all(k == 1 for k in q["rank"])
+
+
+def test_determinism(torch_dev):
+    _say("run-to-run determinism fio1k")
+    P = I.workload_fio1d_1k()
+    u1, q1 = _run_gpu(torch_dev, P, I.PREC_FP64)
+    u2, q2 = _run_gpu(torch_dev, P, I.PREC_FP64)
+    assert np.array_equal(u1, u2) and q1["rank"] == q2["rank"]
+
+
+def test_full_size_fio64k_fp32(torch_dev):
+    """N = 65536, r = 12, 64 RHS, FP32 apply (the benchmark workload): the
+    oracle's full IBF on 4 columns and the dense product on 256 rows."""
+    torch = torch_dev
+    from paper_1605_03616_amd import ibf
+    _say("full size fio1d n=65536 r=12 fp32 nrhs=64")
+    P = I.workload_fio1d_64k(nrhs=64)
+    pl = ibf.Plan.from_problem(P)
+    pl.build()
+    g = torch.from_numpy(np.ascontiguousarray(P.g.T)).to(torch.complex64).cuda()
+    u = pl.apply(g).cpu().numpy().T.astype(np.complex128)
+    q = pl.query()
+    pl.destroy()
+    rows = I.error_rows(P.n)
+    ud = O.dense_apply(P.phase, P.params, P.x, P.xi, P.g[:, :8], rows=rows)
+    assert O.rel_error(u[rows, :8], ud) < 3e-6
+    prob, F, Op = O.build_optimal(P.phase, P.params, P.x, P.xi, P.r, P.tol, P.leaf)
+    uo = O.apply_optimal(Op, P.g[:, :4])
+    assert O.rel_error(u[:, :4], uo) < 1e-5
+    assert q["rank"] == [v for _, v in sorted(O.level_ranks(Op).items())]
+
+
+def test_full_size_nudft_1m_sampled(torch_dev):
+    """N = 2^20 random x, r = 10, 16 RHS: BF16X2 and FP32 against the dense
+    product on 256 sampled rows (the oracle IBF does not fit this size)."""
+    torch = torch_dev
+    from paper_1605_03616_amd import ibf
+    P = I.workload_nudft_1m()
+    rows = I.error_rows(P.n)
+    ud = O.dense_apply(P.phase, P.params, P.x, P.xi, P.g[:, :4], rows=rows)
+    for prec, tol in [(I.PREC_FP32, 1e-5), (I.PREC_BF16X2, 1e-4)]:
+        _say(f"full size nudft n=2^20 r=10 precision={prec}")
+        pl = ibf.Plan(P.x, P.xi, P.phase, P.params, P.r, P.tol, P.leaf, prec, 0)
+        pl.build()
+        g = torch.from_numpy(np.ascontiguousarray(P.g.T)).to(torch.complex64).cuda()
+        u = pl.apply(g).cpu().numpy().T.astype(np.complex128)
+        pl.destroy()
+        assert O.rel_error(u[rows, :4], ud) < tol
