@@ -98,6 +98,9 @@ typedef struct {
   int64_t factor_bytes;      /* device bytes of the stored factors */
   double build_ms;           /* wall time of the last ibf_build */
   int smax_x, smax_xi;       /* largest leaf populations */
+  int sweep_in;              /* 1 when the sweep-in stage ran */
+  int rank_in_g[64];         /* sweep-in ranks, U/G side, index l - l0 (levels h .. L-l0) */
+  int rank_in_h[64];         /* sweep-in ranks, V/H side, index l - l0 (levels l0 .. h) */
 } ibf_info;
 
 /*

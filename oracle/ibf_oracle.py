@@ -842,6 +842,26 @@ def nnz_optimal(O: OptimalIBF):
     return tot
 
 
+def nnz_optimal_in(O: OptimalIBF):
+    """Non-zeros of the swept-in factors (eqn:IBFin), each block at its own rank."""
+    T = O.prob.tree
+    L, l0, h = T.L, T.l0, T.h
+    rg, rh = O.ranks_in["G"], O.ranks_in["H"]
+    xcnt = np.diff(T.xoff)
+    xicnt = np.diff(T.xioff)
+    tot = int(np.sum(rh[l0] * xicnt[None, :]))
+    tot += int(np.sum(rg[L - l0] * xcnt[:, None]))
+    tot += int(np.sum(rg[h] * rh[h]))
+    for l in range(l0 + 1, L - l0 + 1):
+        rk = rh if l <= h else rg
+        na, nb = 1 << l, 1 << (L - l)
+        kin = rk[l - 1]
+        kin_sum = kin[np.arange(na) // 2][:, 2 * np.arange(nb)] + \
+            kin[np.arange(na) // 2][:, 2 * np.arange(nb) + 1]
+        tot += int(np.sum(rk[l] * kin_sum))
+    return tot
+
+
 def rel_error(u, u_ref):
     """eq:relativeerr over the given rows (Frobenius over all columns)."""
     u = np.asarray(u)

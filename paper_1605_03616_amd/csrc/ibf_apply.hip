@@ -65,6 +65,23 @@ __global__ void k_apply_stage(const VT* __restrict__ in, VT* __restrict__ out,
   out[e] = acc;
 }
 
+// Middle block of the swept-in factorization: out[p][t][n] = sum_s Mdot[p][t][s] in[p][s][n]
+template <typename VT, typename FT>
+__global__ void k_apply_mid(const VT* __restrict__ in, VT* __restrict__ out,
+                            const FT* __restrict__ mdot, int kin, int kout, int nrhs,
+                            int64_t total) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int n = (int)(e % nrhs);
+  const int t = (int)((e / nrhs) % kout);
+  const int64_t p = e / ((int64_t)nrhs * kout);
+  const FT* row = mdot + (p * kout + t) * kin;
+  const VT* src = in + p * kin * nrhs + n;
+  VT acc = Zero<VT>::v();
+  for (int s = 0; s < kin; ++s) cfma(acc, load_factor(row, s), src[(int64_t)s * nrhs]);
+  out[e] = acc;
+}
+
 // u[perm(x)][n] = sum_b sum_k Ubar[x][b][k] mu[(a(x), b)][k][n]
 template <typename VT, typename FT>
 __global__ void k_apply_u(const VT* __restrict__ mu, VT* __restrict__ u, int64_t ldu,
@@ -135,6 +152,8 @@ int apply_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int6
   const int nrhs = (int)nrhs64;
   int kmax = 1;
   for (int k : p->rank) kmax = std::max(kmax, k);
+  for (int k : p->rank_in_g) kmax = std::max(kmax, k);
+  for (int k : p->rank_in_h) kmax = std::max(kmax, k);
   const size_t need = (size_t)p->npairs * kmax * nrhs * sizeof(VT);
   if (need > p->work_bytes) {
     for (int i = 0; i < 2; ++i) {
@@ -162,6 +181,20 @@ int apply_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int6
       return rc;
   }
   int cur = 0;
+  auto launch_mid = [&]() -> int {
+    const int64_t total = p->npairs * p->k_mid_g * nrhs;
+    int rc2;
+    if ((rc2 = T.begin())) return rc2;
+    hipLaunchKernelGGL((k_apply_mid<VT, FT>), dim3(nblocks(total)), dim3(kBlock), 0, s, w[cur],
+                       w[cur ^ 1], (const FT*)p->d_mdot, p->k_mid_h, p->k_mid_g, nrhs, total);
+    const double nnz = (double)p->npairs * p->k_mid_g * p->k_mid_h;
+    const double vec = (double)p->npairs * (p->k_mid_g + p->k_mid_h) * nrhs * vb;
+    if ((rc2 = T.end("apply_mid", 8.0 * nnz * nrhs, nnz * fb + vec))) return rc2;
+    cur ^= 1;
+    return IBF_OK;
+  };
+  if (p->d_mdot && geo.h == l0)
+    if ((rc = launch_mid())) return rc;
   for (const Stage& st : p->stages) {
     const int64_t total = p->npairs * st.k_out * nrhs;
     if ((rc = T.begin())) return rc;
@@ -172,6 +205,8 @@ int apply_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int6
     const double vec = (double)p->npairs * (st.k_in + st.k_out) * nrhs * vb;
     if ((rc = T.end("apply_stage", 8.0 * nnz * nrhs, nnz * fb + vec))) return rc;
     cur ^= 1;
+    if (p->d_mdot && st.level_out == geo.h)
+      if ((rc = launch_mid())) return rc;
   }
   {
     const int64_t total = p->nx * nrhs;

@@ -19,12 +19,14 @@
 #include <cstring>
 #include <vector>
 
-#include "ibf_device.h"
+#include "ibf_kern.h"
 
 namespace ibf {
 namespace {
 
-constexpr int kBlock = 256;
+using kern::kBlock;
+using kern::SweepArgs;
+using kern::block_accumulate;
 
 // ---------------------------------------------------------------------------
 // RAII device buffer for build temporaries.
@@ -64,266 +66,6 @@ __global__ void k_cheb(int r, double* cheb) {
     }
     cheb[r + e] = lagrange_t(z, r, t, y);
   }
-}
-
-template <int R>
-__device__ inline void load_cheb(const double* cheb, double* z, double* Lc) {
-  for (int e = threadIdx.x; e < R + 2 * R * R; e += blockDim.x) {
-    double v = cheb[e];
-    if (e < R) z[e] = v;
-    else Lc[e - R] = v;
-  }
-  __syncthreads();
-}
-
-__device__ __forceinline__ double2 shfl2(double2 v, int src, int width) {
-  return make_double2(__shfl(v.x, src, width), __shfl(v.y, src, width));
-}
-
-// Block-level reduction of the per-group rank (max) and a 64-bit counter.
-__device__ inline void block_accumulate(int k, unsigned long long add, bool leader,
-                                        int* rank_max_slot, unsigned long long* nnz) {
-  __shared__ int s_max;
-  __shared__ unsigned long long s_sum;
-  if (threadIdx.x == 0) { s_max = 0; s_sum = 0ull; }
-  __syncthreads();
-  if (leader) {
-    atomicMax(&s_max, k);
-    atomicAdd(&s_sum, add);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    atomicMax(rank_max_slot, s_max);
-    atomicAdd(nnz, s_sum);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Middle level: per pair (A at h, B at L-h), A = M~^* with rows s, then
-// C = U_k Sigma^(1/2), R = V_k Sigma^(1/2)  (M~ = C R^*).
-// ---------------------------------------------------------------------------
-template <int R, int G>
-__global__ __launch_bounds__(kBlock) void k_middle(PhaseDesc ph, Geo geo, const double* cheb,
-                                                   double tol, int64_t npairs, double2* Cout,
-                                                   double2* Rout, int* rk, int* rank_max,
-                                                   unsigned long long* nnz) {
-  __shared__ double z[R];
-  __shared__ double Lc[2 * R * R];
-  load_cheb<R>(cheb, z, Lc);
-  const int lane = threadIdx.x % G;
-  const int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
-  const bool valid = p < npairs;
-  const int L = geo.L, h = geo.h;
-  const int64_t a = p >> (L - h);
-  const int64_t b = p & (((int64_t)1 << (L - h)) - 1);
-
-  double2 arow[R];
-  double2 v[R];
-  const bool row_ok = valid && lane < R;
-  const double cA = box_cx(h, a), wA = box_wx(h);
-  const double cB = box_cxi(geo, L - h, b), wB = box_wxi(geo, L - h);
-  const double gBs = grid_pt(cB, wB, z[row_ok ? lane : 0]);
-#pragma unroll
-  for (int t = 0; t < R; ++t) {
-    double2 val = make_double2(0.0, 0.0);
-    if (row_ok) val = conjd(kval(ph, grid_pt(cA, wA, z[t]), gBs));
-    arow[t] = val;
-  }
-  double sig[R];
-  jacobi_svd<R, G>(arow, v, lane, R, sig);
-  int pos[R];
-  const int k = rank_positions<R>(sig, tol, pos);
-  if (valid && lane < R) {
-    double2* Cp = Cout + (p * R + lane) * R;
-    double2* Rp = Rout + (p * R + lane) * R;
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      const bool keep = pos[j] < k;
-      const double sq = keep ? sqrt(sig[j]) : 0.0;
-      Cp[pos[j]] = keep ? cscale(v[j], sq) : make_double2(0.0, 0.0);
-      Rp[pos[j]] = keep ? cscale(arow[j], 1.0 / sq) : make_double2(0.0, 0.0);
-    }
-  }
-  const bool leader = valid && lane == 0;
-  if (leader) rk[p] = k;
-  block_accumulate(k, (unsigned long long)k, leader, rank_max, nnz);
-}
-
-// ---------------------------------------------------------------------------
-// Sweep toward U, output level l (h < l <= L-l0).  Output pair (A, B):
-// A at level l (child alpha of P), B at level L-l with children C_c.
-//   G_c[t][s] = exp(2 pi i Phi(g^A_t, c_C)) M^P_s(g^A_t) exp(-2 pi i Phi(g^P_s, c_C))
-//   W = [G_0 C_{P C_0}, G_1 C_{P C_1}]   (r x 2r, zero-padded columns)
-// Rows of A = W^* are indexed by i = c r + j (input child c, input column j).
-// ---------------------------------------------------------------------------
-template <int R, int G>
-__global__ __launch_bounds__(kBlock) void k_sweep_g(PhaseDesc ph, Geo geo, const double* cheb,
-                                                    double tol, int l, int64_t npairs,
-                                                    const double2* Cin, double2* Cout,
-                                                    double2* stage, const int* rk_in, int* rk_out,
-                                                    int* rank_max, unsigned long long* nnz) {
-  __shared__ double z[R];
-  __shared__ double Lc[2 * R * R];
-  load_cheb<R>(cheb, z, Lc);
-  const int lane = threadIdx.x % G;
-  const int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
-  const bool valid = p < npairs;
-  const int L = geo.L;
-  const int sh = L - l;
-  const int64_t a = p >> sh;
-  const int64_t b = p & (((int64_t)1 << sh) - 1);
-  const int alpha = (int)(a & 1);
-  const int64_t ap = a >> 1;
-  const bool row_ok = valid && lane < 2 * R;
-  const int c = row_ok ? lane / R : 0;
-  const int jj = row_ok ? lane % R : 0;
-  const int64_t in_c = (ap << (sh + 1)) | (2 * b + c);
-
-  // phases: lane (c, jj) evaluates D1_c[jj] and D2_c[jj]
-  const double cC = box_cxi(geo, L - l + 1, 2 * b + c);
-  const double gA = grid_pt(box_cx(l, a), box_wx(l), z[jj]);
-  const double gP = grid_pt(box_cx(l - 1, ap), box_wx(l - 1), z[jj]);
-  const double2 d1 = valid ? kval(ph, gA, cC) : make_double2(0.0, 0.0);
-  const double2 d2 = valid ? conjd(kval(ph, gP, cC)) : make_double2(0.0, 0.0);
-
-  double2 y[R];
-#pragma unroll
-  for (int s = 0; s < R; ++s) {
-    double2 ds = shfl2(d2, c * R + s, G);
-    double2 cv = row_ok ? Cin[(in_c * R + s) * R + jj] : make_double2(0.0, 0.0);
-    y[s] = cmul(ds, cv);
-  }
-  double2 arow[R];
-#pragma unroll
-  for (int t = 0; t < R; ++t) {
-    double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-    for (int s = 0; s < R; ++s) {
-      const double lx = Lc[(alpha * R + s) * R + t];   // M^P_s(g^A_t)
-      acc.x = fma(lx, y[s].x, acc.x);
-      acc.y = fma(lx, y[s].y, acc.y);
-    }
-    double2 dt = shfl2(d1, c * R + t, G);
-    double2 w = cmul(dt, acc);
-    arow[t] = row_ok ? conjd(w) : make_double2(0.0, 0.0);
-  }
-  double2 v[R];
-  double sig[R];
-  jacobi_svd<R, G>(arow, v, lane, 2 * R, sig);
-  int pos[R];
-  const int k = rank_positions<R>(sig, tol, pos);
-  if (valid && lane < R) {
-    double2* Cp = Cout + (p * R + lane) * R;
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      const bool keep = pos[j] < k;
-      Cp[pos[j]] = keep ? cscale(v[j], sig[j]) : make_double2(0.0, 0.0);
-    }
-  }
-  if (row_ok) {
-    double2* Sp = stage + p * R * 2 * R;
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      const bool keep = pos[j] < k;
-      Sp[pos[j] * 2 * R + lane] =
-          keep ? cscale(conjd(arow[j]), 1.0 / sig[j]) : make_double2(0.0, 0.0);
-    }
-  }
-  const bool leader = valid && lane == 0;
-  unsigned long long add = 0;
-  if (leader) {
-    rk_out[p] = k;
-    const int64_t in0 = (ap << (sh + 1)) | (2 * b);
-    add = (unsigned long long)k * (unsigned long long)(rk_in[in0] + rk_in[in0 + 1]);
-  }
-  block_accumulate(k, add, leader, rank_max, nnz);
-}
-
-// ---------------------------------------------------------------------------
-// Sweep toward V for stage l (l0 < l <= h): per input pair (P, C) at level
-// l-1 with outputs (A_alpha, B) at level l, C = child c of B.
-//   H_alpha[t][s] = exp(-2 pi i Phi(c_A, g^B_t)) M^B_t(g^C_s) exp(2 pi i Phi(c_A, g^C_s))
-//   Z = [H_0^* R_{A0 B}, H_1^* R_{A1 B}],  A = Z^*,  A[i][s] with i = alpha r + j.
-// ---------------------------------------------------------------------------
-template <int R, int G>
-__global__ __launch_bounds__(kBlock) void k_sweep_h(PhaseDesc ph, Geo geo, const double* cheb,
-                                                    double tol, int l, int64_t npairs,
-                                                    const double2* Rin, double2* Rout,
-                                                    double2* stage, const int* rk_in, int* rk_out,
-                                                    int* rank_max, unsigned long long* nnz) {
-  __shared__ double z[R];
-  __shared__ double Lc[2 * R * R];
-  load_cheb<R>(cheb, z, Lc);
-  const int lane = threadIdx.x % G;
-  const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
-  const bool valid = q < npairs;
-  const int L = geo.L;
-  const int shin = L - l + 1;
-  const int64_t ap = q >> shin;
-  const int64_t j = q & (((int64_t)1 << shin) - 1);
-  const int64_t B = j >> 1;
-  const int c = (int)(j & 1);
-  const bool row_ok = valid && lane < 2 * R;
-  const int alpha = row_ok ? lane / R : 0;
-  const int jj = row_ok ? lane % R : 0;
-  const int64_t out_a = ((2 * ap + alpha) << (L - l)) | B;
-
-  const double cA = box_cx(l, 2 * ap + alpha);
-  const double gB = grid_pt(box_cxi(geo, L - l, B), box_wxi(geo, L - l), z[jj]);
-  const double gC = grid_pt(box_cxi(geo, L - l + 1, j), box_wxi(geo, L - l + 1), z[jj]);
-  const double2 e1 = valid ? conjd(kval(ph, cA, gB)) : make_double2(0.0, 0.0);
-  const double2 e2 = valid ? kval(ph, cA, gC) : make_double2(0.0, 0.0);
-
-  double2 y[R];
-#pragma unroll
-  for (int t = 0; t < R; ++t) {
-    double2 et = shfl2(e1, alpha * R + t, G);
-    double2 rv = row_ok ? Rin[(out_a * R + t) * R + jj] : make_double2(0.0, 0.0);
-    y[t] = cmul(et, conjd(rv));
-  }
-  double2 arow[R];
-#pragma unroll
-  for (int s = 0; s < R; ++s) {
-    double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-    for (int t = 0; t < R; ++t) {
-      const double lb = Lc[(c * R + t) * R + s];     // M^B_t(g^C_s)
-      acc.x = fma(lb, y[t].x, acc.x);
-      acc.y = fma(lb, y[t].y, acc.y);
-    }
-    double2 es = shfl2(e2, alpha * R + s, G);
-    arow[s] = row_ok ? cmul(es, acc) : make_double2(0.0, 0.0);
-  }
-  double2 v[R];
-  double sig[R];
-  jacobi_svd<R, G>(arow, v, lane, 2 * R, sig);
-  int pos[R];
-  const int k = rank_positions<R>(sig, tol, pos);
-  if (valid && lane < R) {
-    double2* Rp = Rout + (q * R + lane) * R;
-#pragma unroll
-    for (int jx = 0; jx < R; ++jx) {
-      const bool keep = pos[jx] < k;
-      Rp[pos[jx]] = keep ? cscale(v[jx], sig[jx]) : make_double2(0.0, 0.0);
-    }
-  }
-  if (row_ok) {
-    double2* Sp = stage + (out_a * R + jj) * 2 * R + c * R;
-#pragma unroll
-    for (int jx = 0; jx < R; ++jx) {
-      const bool keep = pos[jx] < k;
-      Sp[pos[jx]] = keep ? cscale(arow[jx], 1.0 / sig[jx]) : make_double2(0.0, 0.0);
-    }
-  }
-  const bool leader = valid && lane == 0;
-  unsigned long long add = 0;
-  if (leader) {
-    rk_out[q] = k;
-    const int64_t o0 = ((2 * ap) << (L - l)) | B;
-    const int64_t o1 = ((2 * ap + 1) << (L - l)) | B;
-    add = (unsigned long long)k * (unsigned long long)(rk_in[o0] + rk_in[o1]);
-  }
-  block_accumulate(k, add, leader, rank_max, nnz);
 }
 
 // ---------------------------------------------------------------------------
@@ -447,79 +189,68 @@ __global__ void k_vbar(PhaseDesc ph, Geo geo, const double* cheb, const double* 
   if (threadIdx.x == 0 && s_sum) atomicAdd(nnz, s_sum);
 }
 
+
+template <typename FT>
+__global__ void k_sweepin_mid(int R, int64_t npairs, const double2* cbar, const double2* rbar,
+                              const int* rkG, const int* rkH, int KG, int KH, FT* mdot,
+                              unsigned long long* nnz) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long add = 0;
+  if (e < npairs * KG * KH) {
+    const int64_t p = e / (KG * KH);
+    const int rem = (int)(e - p * KG * KH);
+    const int t = rem / KH, s = rem - t * KH;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int m = 0; m < R; ++m)
+      cfma(acc, cbar[(p * R + t) * R + m], rbar[(p * R + m) * R + s]);
+    store_factor(mdot, e, acc);
+    if (rem == 0) add = (unsigned long long)rkG[p] * (unsigned long long)rkH[p];
+  }
+  __shared__ unsigned long long s_sum;
+  if (threadIdx.x == 0) s_sum = 0;
+  __syncthreads();
+  if (add) atomicAdd(&s_sum, add);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_sum) atomicAdd(nnz, s_sum);
+}
+
+// Packs an outer factor [point][2^l0][r] FP64 into [point][2^l0][K] storage.
+template <typename FT>
+__global__ void k_pack_outer(const double2* src, FT* dst, int64_t rows, int R, int K) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < rows * K) {
+    const int64_t i = e / K;
+    const int k = (int)(e - i * K);
+    store_factor(dst, e, src[i * R + k]);
+  }
+}
+
+// Unpadded entries of an outer factor: sum over (point, box) of rank(pair).
+__global__ void k_count_outer(const int32_t* leaf_of, int64_t npts, int l0, int shift_leaf,
+                              const int* rk, unsigned long long* nnz) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long add = 0;
+  if (e < (npts << l0)) {
+    const int64_t i = e >> l0;
+    const int64_t o = e & ((1 << l0) - 1);
+    const int64_t leaf = leaf_of[i];
+    // U side: pair = leaf 2^l0 + o ; V side: pair = o 2^(L-l0) + leaf
+    const int64_t p = shift_leaf ? ((o << shift_leaf) | leaf) : ((leaf << l0) | o);
+    add = (unsigned long long)rk[p];
+  }
+  __shared__ unsigned long long s_sum;
+  if (threadIdx.x == 0) s_sum = 0;
+  __syncthreads();
+  if (add) atomicAdd(&s_sum, add);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_sum) atomicAdd(nnz, s_sum);
+}
+
 __global__ void k_eval(PhaseDesc ph, const double* x, const double* xi, int64_t n, double2* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = kval(ph, x[i], xi[i]);
 }
 
-// ---------------------------------------------------------------------------
-// Launch helpers templated on r.
-// ---------------------------------------------------------------------------
-struct SweepArgs {
-  PhaseDesc ph;
-  Geo geo;
-  const double* cheb;
-  double tol;
-  int64_t npairs;
-  int* rank_max;
-  unsigned long long* nnz;
-};
-
-template <int R>
-constexpr int group_for() { return R <= 8 ? 16 : 32; }
-
-template <int R>
-void launch_middle(const SweepArgs& A, double2* C, double2* Rm, int* rk, hipStream_t s) {
-  constexpr int G = group_for<R>();
-  const int64_t threads = A.npairs * G;
-  const unsigned blocks = (unsigned)((threads + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL((k_middle<R, G>), dim3(blocks), dim3(kBlock), 0, s, A.ph, A.geo, A.cheb,
-                     A.tol, A.npairs, C, Rm, rk, A.rank_max + (A.geo.h - A.geo.l0), A.nnz);
-}
-
-template <int R>
-void launch_sweep_g(const SweepArgs& A, int l, const double2* Cin, double2* Cout,
-                    double2* stage, const int* rk_in, int* rk_out, unsigned long long* nnz,
-                    hipStream_t s) {
-  constexpr int G = group_for<R>();
-  const int64_t threads = A.npairs * G;
-  const unsigned blocks = (unsigned)((threads + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL((k_sweep_g<R, G>), dim3(blocks), dim3(kBlock), 0, s, A.ph, A.geo, A.cheb,
-                     A.tol, l, A.npairs, Cin, Cout, stage, rk_in, rk_out,
-                     A.rank_max + (l - A.geo.l0), nnz);
-}
-
-template <int R>
-void launch_sweep_h(const SweepArgs& A, int l, const double2* Rin, double2* Rout,
-                    double2* stage, const int* rk_in, int* rk_out, unsigned long long* nnz,
-                    hipStream_t s) {
-  constexpr int G = group_for<R>();
-  const int64_t threads = A.npairs * G;
-  const unsigned blocks = (unsigned)((threads + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL((k_sweep_h<R, G>), dim3(blocks), dim3(kBlock), 0, s, A.ph, A.geo, A.cheb,
-                     A.tol, l, A.npairs, Rin, Rout, stage, rk_in, rk_out,
-                     A.rank_max + (l - 1 - A.geo.l0), nnz);
-}
-
-#define IBF_DISPATCH_R(r, FN, ...)                    \
-  switch (r) {                                        \
-    case 2: FN<2>(__VA_ARGS__); break;                \
-    case 3: FN<3>(__VA_ARGS__); break;                \
-    case 4: FN<4>(__VA_ARGS__); break;                \
-    case 5: FN<5>(__VA_ARGS__); break;                \
-    case 6: FN<6>(__VA_ARGS__); break;                \
-    case 7: FN<7>(__VA_ARGS__); break;                \
-    case 8: FN<8>(__VA_ARGS__); break;                \
-    case 9: FN<9>(__VA_ARGS__); break;                \
-    case 10: FN<10>(__VA_ARGS__); break;              \
-    case 11: FN<11>(__VA_ARGS__); break;              \
-    case 12: FN<12>(__VA_ARGS__); break;              \
-    case 13: FN<13>(__VA_ARGS__); break;              \
-    case 14: FN<14>(__VA_ARGS__); break;              \
-    case 15: FN<15>(__VA_ARGS__); break;              \
-    case 16: FN<16>(__VA_ARGS__); break;              \
-    default: break;                                   \
-  }
 
 template <typename FT>
 int pack_all(ibf_plan_t p, const std::vector<DevBuf<double2>>& stages, const double2* Cu,
@@ -565,6 +296,160 @@ int pack_all(ibf_plan_t p, const std::vector<DevBuf<double2>>& stages, const dou
     p->nnz_stored += n * p->k_vbar;
   }
   IBF_HIP_CHECK(hipGetLastError());
+  return IBF_OK;
+}
+
+// Sweep-in (Sec. 4.3) on the FP64 sweep-out results, then conversion of all
+// factors to the storage precision.  `stages` hold the sweep-out blocks in
+// the r x 2r staging layout and are rewritten in place.
+template <typename FT>
+int sweep_in_pack(ibf_plan_t p, std::vector<DevBuf<double2>>& stages, const double2* Cu,
+                  const double2* Rv, const int* rkU, const int* rkV, const double* cheb,
+                  hipStream_t s) {
+  const Geo& geo = p->geo;
+  const int L = geo.L, l0 = geo.l0, h = geo.h, R = p->r;
+  const int nlev = L - 2 * l0 + 1, nst = L - 2 * l0;
+  const int64_t np = p->npairs;
+  const size_t fb = sizeof(FT);
+  if (p->smax_x > 64 || p->smax_xi > 64) {
+    set_error("ibf_build: sweep-in needs leaves of at most 64 points");
+    return IBF_ERR_UNSUPPORTED;
+  }
+  DevBuf<double2> ub, vb, ud, vd, cb[2], rb[2];
+  IBF_HIP_CHECK(ub.alloc((size_t)(p->nx << l0) * R));
+  IBF_HIP_CHECK(ud.alloc((size_t)(p->nx << l0) * R));
+  IBF_HIP_CHECK(vb.alloc((size_t)(p->nxi << l0) * R));
+  IBF_HIP_CHECK(vd.alloc((size_t)(p->nxi << l0) * R));
+  DevBuf<int> rkg[2], rkh[2], rmax_g, rmax_h;
+  for (int i = 0; i < 2; ++i) {
+    IBF_HIP_CHECK(cb[i].alloc((size_t)np * R * R));
+    IBF_HIP_CHECK(rb[i].alloc((size_t)np * R * R));
+    IBF_HIP_CHECK(rkg[i].alloc(np));
+    IBF_HIP_CHECK(rkh[i].alloc(np));
+  }
+  IBF_HIP_CHECK(rmax_g.alloc(nlev));
+  IBF_HIP_CHECK(rmax_h.alloc(nlev));
+  DevBuf<unsigned long long> cnt, scratch;
+  IBF_HIP_CHECK(cnt.alloc(nst + 3));
+  IBF_HIP_CHECK(scratch.alloc(1));
+  IBF_HIP_CHECK(hipMemsetAsync(rmax_g.ptr, 0, nlev * sizeof(int), s));
+  IBF_HIP_CHECK(hipMemsetAsync(rmax_h.ptr, 0, nlev * sizeof(int), s));
+  IBF_HIP_CHECK(hipMemsetAsync(cnt.ptr, 0, (nst + 3) * sizeof(unsigned long long), s));
+
+  // outer factors in FP64 at width r
+  {
+    const int64_t n = p->nx << l0;
+    hipLaunchKernelGGL((k_ubar<double2>), dim3((unsigned)((n + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, s, p->phase, geo, cheb, p->d_xs, p->d_xleaf, p->nx, Cu,
+                       rkU, R, ub.ptr, scratch.ptr);
+  }
+  {
+    const int64_t n = p->nxi << l0;
+    hipLaunchKernelGGL((k_vbar<double2>), dim3((unsigned)((n + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, s, p->phase, geo, cheb, p->d_xis, p->d_xileaf, p->nxi, Rv,
+                       rkV, R, vb.ptr, scratch.ptr);
+  }
+  // U side inward
+  kern::sweepin_u(R, geo, p->tol, p->d_xoff, ub.ptr, ud.ptr, cb[0].ptr,
+                 rkg[0].ptr, rmax_g.ptr + (L - 2 * l0), s);
+  {
+    const int64_t n = p->nx << l0;
+    hipLaunchKernelGGL(k_count_outer, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
+                       0, s, p->d_xleaf, p->nx, l0, 0, rkg[0].ptr, cnt.ptr + nst + 1);
+  }
+  int cg = 0;
+  for (int l = L - l0; l > h; --l) {
+    kern::sweepin_g(R, geo, p->tol, l, cb[cg].ptr, cb[cg ^ 1].ptr,
+                   stages[l - l0 - 1].ptr, rkg[cg].ptr, rkg[cg ^ 1].ptr,
+                   rmax_g.ptr + (l - 1 - l0), cnt.ptr + (l - l0 - 1), s);
+    cg ^= 1;
+  }
+  // V side inward
+  kern::sweepin_v(R, geo, p->tol, p->d_xioff, vb.ptr, vd.ptr, rb[0].ptr,
+                 rkh[0].ptr, rmax_h.ptr, s);
+  {
+    const int64_t n = p->nxi << l0;
+    hipLaunchKernelGGL(k_count_outer, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
+                       0, s, p->d_xileaf, p->nxi, l0, L - l0, rkh[0].ptr, cnt.ptr + nst + 2);
+  }
+  int ch = 0;
+  for (int l = l0 + 1; l <= h; ++l) {
+    kern::sweepin_h(R, geo, p->tol, l, rb[ch].ptr, rb[ch ^ 1].ptr,
+                   stages[l - l0 - 1].ptr, rkh[ch].ptr, rkh[ch ^ 1].ptr, rmax_h.ptr + (l - l0),
+                   cnt.ptr + (l - l0 - 1), s);
+    ch ^= 1;
+  }
+  IBF_HIP_CHECK(hipGetLastError());
+  std::vector<int> rg(nlev), rh(nlev);
+  IBF_HIP_CHECK(hipMemcpyAsync(rg.data(), rmax_g.ptr, nlev * sizeof(int), hipMemcpyDeviceToHost, s));
+  IBF_HIP_CHECK(hipMemcpyAsync(rh.data(), rmax_h.ptr, nlev * sizeof(int), hipMemcpyDeviceToHost, s));
+  IBF_HIP_CHECK(hipStreamSynchronize(s));
+  for (auto& k : rg) k = std::max(k, 1);
+  for (auto& k : rh) k = std::max(k, 1);
+  p->rank_in_g = rg;
+  p->rank_in_h = rh;
+
+  p->nnz_stored = 0;
+  for (int l = l0 + 1; l <= L - l0; ++l) {
+    const std::vector<int>& rk = (l <= h) ? rh : rg;
+    Stage st;
+    st.level_out = l;
+    st.k_out = rk[l - l0];
+    st.k_in = rk[l - 1 - l0];
+    st.nnz = 0;
+    const int64_t count = np * st.k_out * 2 * st.k_in;
+    st.bytes = (size_t)count * fb;
+    IBF_HIP_CHECK(hipMalloc(&st.blk, std::max<size_t>(st.bytes, 1)));
+    p->stages.push_back(st);
+    const unsigned blocks = (unsigned)std::min<int64_t>((count + kBlock - 1) / kBlock, 1 << 20);
+    hipLaunchKernelGGL((k_pack_stage<FT>), dim3(std::max(blocks, 1u)), dim3(kBlock), 0, s,
+                       stages[l - l0 - 1].ptr, (FT*)st.blk, np, R, st.k_out, st.k_in);
+    p->nnz_stored += count;
+  }
+  p->k_mid_g = rg[h - l0];
+  p->k_mid_h = rh[h - l0];
+  {
+    const int64_t count = np * p->k_mid_g * p->k_mid_h;
+    p->mdot_bytes = (size_t)count * fb;
+    IBF_HIP_CHECK(hipMalloc(&p->d_mdot, std::max<size_t>(p->mdot_bytes, 1)));
+    hipLaunchKernelGGL((k_sweepin_mid<FT>), dim3((unsigned)((count + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, s, R, np, cb[cg].ptr, rb[ch].ptr, rkg[cg].ptr,
+                       rkh[ch].ptr, p->k_mid_g, p->k_mid_h, (FT*)p->d_mdot, cnt.ptr + nst);
+    p->nnz_stored += count;
+  }
+  p->k_ubar = rg[L - 2 * l0];
+  p->k_vbar = rh[0];
+  p->ubar_bytes = (size_t)(p->nx << l0) * p->k_ubar * fb;
+  p->vbar_bytes = (size_t)(p->nxi << l0) * p->k_vbar * fb;
+  IBF_HIP_CHECK(hipMalloc(&p->d_ubar, std::max<size_t>(p->ubar_bytes, 1)));
+  IBF_HIP_CHECK(hipMalloc(&p->d_vbar, std::max<size_t>(p->vbar_bytes, 1)));
+  {
+    const int64_t rows = p->nx << l0;
+    hipLaunchKernelGGL((k_pack_outer<FT>),
+                       dim3((unsigned)((rows * p->k_ubar + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       s, ud.ptr, (FT*)p->d_ubar, rows, R, p->k_ubar);
+    p->nnz_stored += rows * p->k_ubar;
+  }
+  {
+    const int64_t rows = p->nxi << l0;
+    hipLaunchKernelGGL((k_pack_outer<FT>),
+                       dim3((unsigned)((rows * p->k_vbar + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       s, vd.ptr, (FT*)p->d_vbar, rows, R, p->k_vbar);
+    p->nnz_stored += rows * p->k_vbar;
+  }
+  IBF_HIP_CHECK(hipGetLastError());
+  std::vector<unsigned long long> nn(nst + 3);
+  IBF_HIP_CHECK(hipMemcpyAsync(nn.data(), cnt.ptr, nn.size() * sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, s));
+  IBF_HIP_CHECK(hipStreamSynchronize(s));
+  p->nnz_opt = 0;
+  for (int i = 0; i < nst; ++i) {
+    p->stages[i].nnz = (int64_t)nn[i];
+    p->nnz_opt += (int64_t)nn[i];
+  }
+  p->nnz_ubar = (int64_t)nn[nst + 1];
+  p->nnz_vbar = (int64_t)nn[nst + 2];
+  p->nnz_opt += (int64_t)(nn[nst] + nn[nst + 1] + nn[nst + 2]);
   return IBF_OK;
 }
 
@@ -618,7 +503,7 @@ int build_plan(ibf_plan_t p, hipStream_t s) {
   for (int i = 0; i < nst; ++i) IBF_HIP_CHECK(stages[i].alloc((size_t)np * R * 2 * R));
 
   SweepArgs A{p->phase, geo, cheb.ptr, p->tol, np, rank_max.ptr, nnz.ptr + nst};
-  IBF_DISPATCH_R(R, launch_middle, A, Cb[0].ptr, Rb[0].ptr, rk_mid.ptr, s);
+  kern::middle(R, A, Cb[0].ptr, Rb[0].ptr, rk_mid.ptr, s);
 
   // sweep toward U
   const double2* Ccur = Cb[0].ptr;
@@ -629,7 +514,7 @@ int build_plan(ibf_plan_t p, hipStream_t s) {
   for (int l = h + 1; l <= L - l0; ++l) {
     double2* Cout = (Ccur == Cb[0].ptr) ? Cb[1].ptr : Cb[0].ptr;
     int* rkout = rkG[gi].ptr;
-    IBF_DISPATCH_R(R, launch_sweep_g, A, l, Ccur, Cout, stages[l - l0 - 1].ptr, rkcur, rkout,
+    kern::sweep_g(R, A, l, Ccur, Cout, stages[l - l0 - 1].ptr, rkcur, rkout,
                    nnz.ptr + (l - l0 - 1), s);
     Ccur = Cout;
     Cout_last = Cout;
@@ -646,7 +531,7 @@ int build_plan(ibf_plan_t p, hipStream_t s) {
   for (int l = h; l >= l0 + 1; --l) {
     double2* Rout = (Rcur == Rb[0].ptr) ? Rb[1].ptr : Rb[0].ptr;
     int* rkout = rkH[hi].ptr;
-    IBF_DISPATCH_R(R, launch_sweep_h, A, l, Rcur, Rout, stages[l - l0 - 1].ptr, rkcur, rkout,
+    kern::sweep_h(R, A, l, Rcur, Rout, stages[l - l0 - 1].ptr, rkcur, rkout,
                    nnz.ptr + (l - l0 - 1), s);
     Rcur = Rout;
     Rout_last = Rout;
@@ -662,6 +547,20 @@ int build_plan(ibf_plan_t p, hipStream_t s) {
   IBF_HIP_CHECK(hipStreamSynchronize(s));
   for (auto& k : rk_host) k = std::max(k, 1);
   p->rank = rk_host;
+  p->rank_in_g.clear();
+  p->rank_in_h.clear();
+
+  if (p->sweep_in) {
+    if (p->precision == IBF_FP64)
+      rc = sweep_in_pack<double2>(p, stages, Cout_last, Rout_last, rkU, rkV, cheb.ptr, s);
+    else if (p->precision == IBF_FP32)
+      rc = sweep_in_pack<float2>(p, stages, Cout_last, Rout_last, rkU, rkV, cheb.ptr, s);
+    else
+      rc = sweep_in_pack<bf16x2c>(p, stages, Cout_last, Rout_last, rkU, rkV, cheb.ptr, s);
+    if (rc) return rc;
+    p->built = true;
+    return IBF_OK;
+  }
 
   if (p->precision == IBF_FP64)
     rc = pack_all<double2>(p, stages, Cout_last, Rout_last, rkU, rkV, cheb.ptr,
@@ -698,3 +597,4 @@ int eval_kernel(const PhaseDesc& ph, const double* x, const double* xi, int64_t 
 }
 
 }  // namespace ibf
+

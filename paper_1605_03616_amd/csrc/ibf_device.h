@@ -123,8 +123,56 @@ __device__ __forceinline__ double group_sum(double v) {
 // ---------------------------------------------------------------------------
 constexpr int kJacobiMaxSweeps = 30;
 
+// One complex Jacobi rotation of columns (p, q): with gamma = a_p^H a_q =
+// |gamma| e^{i phi}, rotate [a_p, e^{-i phi} a_q] by the real Jacobi angle
+// that zeroes the off-diagonal of the 2 x 2 Gram matrix; J gets the same
+// column operation.  Column norms are updated in closed form.
+// Columns whose squared norm is below `small` (1e-30 of ||A||_F^2) are at
+// rounding level: rotating them only shrinks noise toward subnormals, where
+// exp(-i arg gamma) overflows, so they are left alone.
+template <int G>
+__device__ __forceinline__ void jacobi_rotate(double2& ap_, double2& aq_, double2& vp_,
+                                              double2& vq_, double& np_, double& nq_,
+                                              double thresh, double small, bool& rotated) {
+  const double gr = group_sum<G>(ap_.x * aq_.x + ap_.y * aq_.y);
+  const double gi = group_sum<G>(ap_.x * aq_.y - ap_.y * aq_.x);
+  const double ag = sqrt(gr * gr + gi * gi);
+  if (np_ > small && nq_ > small && ag > thresh * sqrt(np_ * nq_)) {
+    const double zeta = (nq_ - np_) / (2.0 * ag);
+    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    const double c = 1.0 / sqrt(1.0 + t * t);
+    const double s = c * t;
+    const double2 e = make_double2(gr / ag, -gi / ag);   // exp(-i arg gamma)
+    const double2 eq = cmul(e, aq_);
+    const double2 ap = ap_;
+    ap_ = make_double2(c * ap.x - s * eq.x, c * ap.y - s * eq.y);
+    aq_ = make_double2(s * ap.x + c * eq.x, s * ap.y + c * eq.y);
+    const double2 ev = cmul(e, vq_);
+    const double2 vp = vp_;
+    vp_ = make_double2(c * vp.x - s * ev.x, c * vp.y - s * ev.y);
+    vq_ = make_double2(s * vp.x + c * ev.x, s * vp.y + c * ev.y);
+    np_ -= t * ag;
+    nq_ += t * ag;
+    rotated = true;
+  }
+}
+
+// Cyclic-by-rows sweep (p, q), p < q, expanded at compile time so that every
+// register-array index is a constant.
+template <int R, int G, int P, int Q>
+__device__ __forceinline__ void jacobi_sweep(double2 (&a)[R], double2 (&v)[R], double (&nrm)[R],
+                                             double thresh, double small, bool& rotated) {
+  if constexpr (P < R - 1) {
+    jacobi_rotate<G>(a[P], a[Q], v[P], v[Q], nrm[P], nrm[Q], thresh, small, rotated);
+    if constexpr (Q + 1 < R)
+      jacobi_sweep<R, G, P, Q + 1>(a, v, nrm, thresh, small, rotated);
+    else
+      jacobi_sweep<R, G, P + 1, P + 2>(a, v, nrm, thresh, small, rotated);
+  }
+}
+
 template <int R, int G>
-__device__ inline void jacobi_svd(double2 (&a)[R], double2 (&v)[R], int lane,
+__device__ __forceinline__ void jacobi_svd(double2 (&a)[R], double2 (&v)[R], int lane,
                                   int n, double (&sig)[R]) {
   const double thresh = 4.0 * (double)(n > 8 ? n : 8) * 1.1102230246251565e-16;
 #pragma unroll
@@ -132,37 +180,14 @@ __device__ inline void jacobi_svd(double2 (&a)[R], double2 (&v)[R], int lane,
   double nrm[R];
 #pragma unroll
   for (int j = 0; j < R; ++j) nrm[j] = group_sum<G>(a[j].x * a[j].x + a[j].y * a[j].y);
+  double fro2 = 0.0;
+#pragma unroll
+  for (int j = 0; j < R; ++j) fro2 += nrm[j];
+  const double small = 1e-30 * fro2;
 
   for (int sweep = 0; sweep < kJacobiMaxSweeps; ++sweep) {
     bool rotated = false;
-#pragma unroll
-    for (int p = 0; p < R - 1; ++p) {
-#pragma unroll
-      for (int q = p + 1; q < R; ++q) {
-        // gamma = a_p^H a_q
-        double gr = group_sum<G>(a[p].x * a[q].x + a[p].y * a[q].y);
-        double gi = group_sum<G>(a[p].x * a[q].y - a[p].y * a[q].x);
-        double ag = sqrt(gr * gr + gi * gi);
-        if (ag > thresh * sqrt(nrm[p] * nrm[q]) && ag > 0.0) {
-          double zeta = (nrm[q] - nrm[p]) / (2.0 * ag);
-          double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          double c = 1.0 / sqrt(1.0 + t * t);
-          double s = c * t;
-          double2 e = make_double2(gr / ag, -gi / ag);   // exp(-i arg gamma)
-          double2 eq = cmul(e, a[q]);
-          double2 ap = a[p];
-          a[p] = make_double2(c * ap.x - s * eq.x, c * ap.y - s * eq.y);
-          a[q] = make_double2(s * ap.x + c * eq.x, s * ap.y + c * eq.y);
-          double2 ev = cmul(e, v[q]);
-          double2 vp = v[p];
-          v[p] = make_double2(c * vp.x - s * ev.x, c * vp.y - s * ev.y);
-          v[q] = make_double2(s * vp.x + c * ev.x, s * vp.y + c * ev.y);
-          nrm[p] -= t * ag;
-          nrm[q] += t * ag;
-          rotated = true;
-        }
-      }
-    }
+    jacobi_sweep<R, G, 0, 1>(a, v, nrm, thresh, small, rotated);
 #pragma unroll
     for (int j = 0; j < R; ++j) nrm[j] = group_sum<G>(a[j].x * a[j].x + a[j].y * a[j].y);
     if (!__any(rotated)) break;
@@ -174,7 +199,7 @@ __device__ inline void jacobi_svd(double2 (&a)[R], double2 (&v)[R], int lane,
 // Position of column j in descending order of sig (ties by index), and the
 // number of sig_j > tol * max sig.
 template <int R>
-__device__ inline int rank_positions(const double (&sig)[R], double tol, int (&pos)[R]) {
+__device__ __forceinline__ int rank_positions(const double (&sig)[R], double tol, int (&pos)[R]) {
   double smax = 0.0;
 #pragma unroll
   for (int j = 0; j < R; ++j) smax = fmax(smax, sig[j]);

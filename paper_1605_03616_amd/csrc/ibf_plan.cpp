@@ -223,6 +223,9 @@ int ibf_query(ibf_plan_t p, ibf_info* info) {
   info->build_ms = p->build_ms;
   info->smax_x = p->smax_x;
   info->smax_xi = p->smax_xi;
+  info->sweep_in = p->rank_in_g.empty() ? 0 : 1;
+  for (size_t i = 0; i < p->rank_in_g.size() && i < 64; ++i) info->rank_in_g[i] = p->rank_in_g[i];
+  for (size_t i = 0; i < p->rank_in_h.size() && i < 64; ++i) info->rank_in_h[i] = p->rank_in_h[i];
   return IBF_OK;
 }
 

@@ -57,6 +57,9 @@ class IBFInfo(C.Structure):
         ("factor_bytes", C.c_int64),
         ("build_ms", C.c_double),
         ("smax_x", C.c_int), ("smax_xi", C.c_int),
+        ("sweep_in", C.c_int),
+        ("rank_in_g", C.c_int * 64),
+        ("rank_in_h", C.c_int * 64),
     ]
 
 
@@ -223,6 +226,9 @@ class Plan:
             "factor_bytes": info.factor_bytes, "build_ms": info.build_ms,
             "smax_x": info.smax_x, "smax_xi": info.smax_xi,
             "R_comp": info.nnz_prelim / max(info.nnz_opt, 1),
+            "sweep_in": info.sweep_in,
+            "rank_in_g": [info.rank_in_g[i] for i in range(n)],
+            "rank_in_h": [info.rank_in_h[i] for i in range(n)],
         }
 
     def destroy(self):
