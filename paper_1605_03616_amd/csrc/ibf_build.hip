@@ -69,8 +69,9 @@ __global__ void k_cheb(int r, double* cheb) {
 }
 
 // ---------------------------------------------------------------------------
-// Conversion of one stage from the FP64 r x 2r staging layout to the stored
-// layout [pair][k_out][2 k_in] in the storage precision.
+// Conversion of one stage from the FP64 r x 2r staging layout [pair][t][c r + s]
+// to the stored layout [pair][c k_in + s][t] (input-major: the k_out entries
+// that multiply one input coefficient are contiguous) in the storage precision.
 // ---------------------------------------------------------------------------
 template <typename FT>
 __global__ void k_pack_stage(const double2* stage, FT* out, int64_t npairs, int R, int kout,
@@ -81,8 +82,8 @@ __global__ void k_pack_stage(const double2* stage, FT* out, int64_t npairs, int 
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = e / per;
     const int rem = (int)(e - p * per);
-    const int t = rem / (2 * kin);
-    const int cc = rem - t * 2 * kin;
+    const int cc = rem / kout;
+    const int t = rem - cc * kout;
     const int c = cc / kin, s = cc - c * kin;
     store_factor(out, e, stage[(p * R + t) * 2 * R + c * R + s]);
   }
