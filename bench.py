@@ -111,6 +111,8 @@ def main():
     ap.add_argument("--nrhs", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one plain 256 MiB elementwise copy first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); "
@@ -140,6 +142,12 @@ def main():
     u = torch.empty((P.nrhs, P.n), dtype=dt, device="cuda")
     stream = torch.cuda.current_stream()
 
+    if args.calib_copy:
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.mul(a, 1.0, out=b)          # reads 256 MiB, writes 256 MiB
+        torch.cuda.synchronize()
+        del a, b
     for _ in range(args.warmup):
         pl.apply(g, u)
     torch.cuda.synchronize()

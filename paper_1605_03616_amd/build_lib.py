@@ -21,11 +21,15 @@ SOURCES = ["ibf_plan.cpp", "ibf_build.hip", "ibf_sweep.hip", "ibf_sweepin.hip", 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include")]
+# Per-source extras.  The apply kernels keep MFMA accumulators in VGPRs: the
+# default AGPR form makes the register allocator copy every accumulator tile
+# once per loop iteration.
+EXTRA = {"ibf_apply.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, "-c", "-x", "hip", os.path.join(CSRC, src), "-o", obj] + FLAGS
+    cmd = [HIPCC, "-c", "-x", "hip", os.path.join(CSRC, src), "-o", obj] + FLAGS + EXTRA.get(src, [])
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{res.stderr}")

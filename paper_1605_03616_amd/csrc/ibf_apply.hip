@@ -8,13 +8,16 @@
 // through a k_out x 2 k_in block.  Fusing k consecutive stages closes over a
 // contiguous group of 2^k input pairs, whose 2^k outputs land at stride
 // 2^(L - l_end): one workgroup keeps such a group (for a chunk of the
-// right-hand sides) in LDS across the k stages.
+// right-hand sides) in LDS across the k stages, and stages each level's
+// factor blocks for the group through LDS with coalesced loads.
 //
 // Kernels:
-//   k_apply_v      Omega leaf -> 2^l0 pairs:  mu = Vbar^* g   (per-leaf GEMM, LDS-staged)
-//   k_apply_fused  k butterfly stages on one pair group in LDS
+//   k_apply_v      Omega leaf -> 2^l0 pairs:  mu = Vbar^* g   (per-leaf product, LDS-staged)
+//   k_apply_fused  k butterfly stages on one pair group in LDS; the FP32 variant
+//                  runs the complex block products on MFMA (v_mfma_f32_4x4x1f32,
+//                  16 blocks = 16 groups of 4 right-hand sides)
 //   k_apply_mid    swept-in middle block Mdot (per pair)
-//   k_apply_u      2^l0 pairs -> X leaf:  u = Ubar mu        (per-leaf GEMM, LDS-staged)
+//   k_apply_u      2^l0 pairs -> X leaf:  u = Ubar mu        (per-leaf product, LDS-staged)
 #include <algorithm>
 #include <cstdio>
 #include <vector>
@@ -25,12 +28,67 @@ namespace ibf {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kKmax = kMaxR;          // largest stored rank
-constexpr int kNumXcd = 8;            // MI355X: 8 XCDs, each with its own L2
+constexpr int kNumXcd = 8;             // MI355X: 8 XCDs, each with its own L2
+constexpr size_t kLdsBudget = 64 * 1024;
+constexpr size_t kLdsBudgetMfma = 80 * 1024;
+
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 template <typename VT> struct Zero;
 template <> struct Zero<double2> { __device__ static double2 v() { return make_double2(0, 0); } };
 template <> struct Zero<float2> { __device__ static float2 v() { return make_float2(0, 0); } };
+
+// Cooperative global -> LDS copy with UNR independent loads in flight per
+// thread (a plain loop would wait on every load before its LDS store).
+template <int UNR, typename T, typename LoadF, typename StoreF>
+__device__ __forceinline__ void staged_copy(int total, LoadF load, StoreF store) {
+  for (int e0 = threadIdx.x; e0 < total; e0 += UNR * kBlock) {
+    T tmp[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int e = e0 + u * kBlock;
+      if (e < total) tmp[u] = load(e);
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int e = e0 + u * kBlock;
+      if (e < total) store(e, tmp[u]);
+    }
+  }
+}
+
+// Batched copy into an LDS array: map(e, off) loads element e and sets its
+// destination offset; UNR loads are issued before any LDS store.
+template <int UNR, typename T, typename MapF>
+__device__ __forceinline__ void staged_copy_to(int total, T* base, MapF map) {
+  for (int e0 = threadIdx.x; e0 < total; e0 += UNR * kBlock) {
+    T tmp[UNR];
+    int off[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int e = e0 + u * kBlock;
+      off[u] = -1;
+      if (e < total) tmp[u] = map(e, off[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+      if (off[u] >= 0) base[off[u]] = tmp[u];
+  }
+}
+
+// q / d and q % d for 0 <= q < 2^22 and 1 <= d <= 2^10 through a float
+// reciprocal: (q + 1/2)/d sits at least 1/(2d) away from an integer, far
+// beyond float rounding, so the truncation is exact.
+struct FastDiv {
+  int d;
+  float inv;
+  __device__ __forceinline__ explicit FastDiv(int dd) : d(dd), inv(1.0f / (float)dd) {}
+  __device__ __forceinline__ int div(int q) const { return (int)(((float)q + 0.5f) * inv); }
+  __device__ __forceinline__ void divmod(int q, int& qq, int& rr) const {
+    qq = div(q);
+    rr = q - qq * d;
+  }
+};
 
 // Block index remapped so that consecutive logical blocks run on one XCD
 // (hardware dispatches block i to XCD i mod 8): RHS chunks of one pair group
@@ -43,57 +101,64 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t nblk) {
 
 // ---------------------------------------------------------------------------
 // V: per (Omega leaf b, RHS chunk): mu[(a,b)][k][n] = sum_{xi in b} Vbar^*[xi][a][k] g[xi][n]
-// LDS: g_leaf[cnt][NB], vbar_leaf[cnt][2^l0][K].
+// LDS: g_leaf[smax][NB], and when it fits vbar_leaf[smax][2^l0][KT] (zero-padded).
 // ---------------------------------------------------------------------------
-template <typename VT, typename FT>
+template <typename VT, typename FT, int KT>
 __global__ __launch_bounds__(kBlock) void k_apply_v(
     const VT* __restrict__ g, int64_t ldg, const int32_t* __restrict__ perm_xi,
     const int32_t* __restrict__ xioff, const FT* __restrict__ vbar, VT* __restrict__ mu, int L,
     int l0, int K, int nrhs, int NB, int nchunk, int smax, int stage_factor) {
   extern __shared__ __align__(16) unsigned char smem[];
   VT* gl = reinterpret_cast<VT*>(smem);                       // [smax][NB]
-  VT* vl = gl + (size_t)smax * NB;                            // [smax][2^l0][K] if staged
-  const int64_t nblk = (int64_t)gridDim.x;
-  const int64_t lb = xcd_logical_block(nblk);
+  VT* vl = gl + (size_t)smax * NB;                            // [smax][2^l0][KT]
+  const int64_t lb = xcd_logical_block((int64_t)gridDim.x);
   const int64_t b = lb / nchunk;
   const int chunk = (int)(lb % nchunk);
   const int nb0 = chunk * NB;
   const int nbw = min(NB, nrhs - nb0);
   const int32_t j0 = xioff[b], cnt = xioff[b + 1] - j0;
   const int na = 1 << l0;
-  // gather g for the leaf (points fastest: contiguous in a column)
-  for (int e = threadIdx.x; e < cnt * nbw; e += blockDim.x) {
-    const int j = e % cnt, n = e / cnt;
-    gl[j * NB + n] = g[(int64_t)(nb0 + n) * ldg + perm_xi[j0 + j]];
+  // gather g for the leaf (points fastest: contiguous within a column)
+  if (cnt > 0) {
+    // points fastest: contiguous within a column of g
+    const FastDiv divC(cnt);
+    staged_copy_to<8>(cnt * nbw, gl, [&](int e, int& off) {
+      int n, j;
+      divC.divmod(e, n, j);
+      off = j * NB + n;
+      return g[(int64_t)(nb0 + n) * ldg + perm_xi[j0 + j]];
+    });
   }
   const FT* vsrc = vbar + (int64_t)j0 * na * K;
   if (stage_factor)
-    for (int e = threadIdx.x; e < cnt * na * K; e += blockDim.x) vl[e] = load_factor(vsrc, e);
+    staged_copy_to<8>(cnt * na * KT, vl, [&](int e, int& off) {
+      const int ja = e / KT, k = e % KT;                      // KT is a compile-time constant
+      off = e;
+      return k < K ? load_factor(vsrc, (int64_t)ja * K + k) : Zero<VT>::v();
+    });
   __syncthreads();
   const int sh = L - l0;
   for (int item = threadIdx.x; item < na * nbw; item += blockDim.x) {
     const int n = item % nbw, a = item / nbw;
-    VT acc[kKmax];
+    VT acc[KT];
 #pragma unroll
-    for (int k = 0; k < kKmax; ++k) acc[k] = Zero<VT>::v();
+    for (int k = 0; k < KT; ++k) acc[k] = Zero<VT>::v();
     for (int j = 0; j < cnt; ++j) {
       const VT gv = gl[j * NB + n];
-      const int64_t off = ((int64_t)j * na + a) * K;
       if (stage_factor) {
-        const VT* vr = vl + off;
+        const VT* vr = vl + ((size_t)j * na + a) * KT;
 #pragma unroll
-        for (int k = 0; k < kKmax; ++k)
-          if (k < K) cfma(acc[k], vr[k], gv);
+        for (int k = 0; k < KT; ++k) cfma(acc[k], vr[k], gv);
       } else {
+        const int64_t off = ((int64_t)j * na + a) * K;
 #pragma unroll
-        for (int k = 0; k < kKmax; ++k)
-          if (k < K) cfma(acc[k], load_factor(vsrc, off + k), gv);
+        for (int k = 0; k < KT; ++k) cfma(acc[k], load_factor(vsrc, off + min(k, K - 1)), gv);
       }
     }
     const int64_t p = ((int64_t)a << sh) | b;
     VT* o = mu + p * K * nrhs + nb0 + n;
 #pragma unroll
-    for (int k = 0; k < kKmax; ++k)
+    for (int k = 0; k < KT; ++k)
       if (k < K) o[(int64_t)k * nrhs] = acc[k];
   }
 }
@@ -104,98 +169,191 @@ __global__ __launch_bounds__(kBlock) void k_apply_v(
 // group's pair at level l_start-1+j has local index (alpha bits << (nst-j)) |
 // (remaining child bits); a stage consumes the lowest child bit and appends
 // an alpha bit.  Outputs of a stage are held in registers across a barrier
-// and written back in place.  ranks[j] = K at level l_start-1+j.
+// and written back in place.  ranks[j] = stored K at level l_start-1+j.
 // ---------------------------------------------------------------------------
 struct FusedArgs {
-  int L, l_start, nst, nrhs, NB, nchunk, ipt;
+  int L, l_start, nst, nrhs, NB, nchunk, kmaxg;
   int ranks[kMaxR + 1];
   const void* blk[kMaxR];
 };
 
-template <typename VT, typename FT>
+// global output pair of local output slot `locp` after stage j (rem child bits left)
+__device__ __forceinline__ int64_t fused_pout(int locp, int j, int rem, int64_t ap, int64_t bpp,
+                                              int L, int l) {
+  const int anew = locp >> rem;
+  const int q = locp & ((1 << rem) - 1);
+  const int64_t a_l = (ap << (j + 1)) | anew;
+  const int64_t b_l = (bpp << rem) | q;
+  return (a_l << (L - l)) | b_l;
+}
+// local slot of the first of the two inputs of output slot `locp`
+__device__ __forceinline__ int fused_in0(int locp, int rem) {
+  const int anew = locp >> rem;
+  const int q = locp & ((1 << rem) - 1);
+  return ((anew >> 1) << (rem + 1)) | (2 * q);
+}
+
+template <typename VT, typename FT, int KT, bool MFMA>
 __global__ __launch_bounds__(kBlock) void k_apply_fused(const VT* __restrict__ in,
                                                         VT* __restrict__ out, FusedArgs A) {
+  static_assert(!MFMA || sizeof(VT) == 8, "MFMA variant computes in FP32");
+  constexpr int KG = KT / 2;                                  // row pairs (MFMA row groups)
   extern __shared__ __align__(16) unsigned char smem[];
-  VT* S = reinterpret_cast<VT*>(smem);                        // [2^nst][Kmax_g][NB]
-  const int k = A.nst, NB = A.NB, L = A.L;
-  int kmaxg = 1;
-  for (int j = 0; j <= k; ++j) kmaxg = max(kmaxg, A.ranks[j]);
-  const int64_t nblk = (int64_t)gridDim.x;
-  const int64_t lb = xcd_logical_block(nblk);
+  const int k = A.nst, NB = A.NB, L = A.L, kmaxg = A.kmaxg;
+  const int nslot = 1 << k;
+  VT* S = reinterpret_cast<VT*>(smem);                        // [nslot][kmaxg][NB]
+  VT* F = S + (size_t)nslot * kmaxg * NB;                     // [nslot][2 kmaxg][KT]
+  const int fstride = 2 * kmaxg * KT;
+  const int64_t lb = xcd_logical_block((int64_t)gridDim.x);
   const int64_t gid = lb / A.nchunk;
   const int chunk = (int)(lb % A.nchunk);
   const int nb0 = chunk * NB;
   const int nbw = min(NB, A.nrhs - nb0);
-  const int nslot = 1 << k;
   const int nrhs = A.nrhs;
   const int sh_end = L - (A.l_start + k - 1);
-
-  // load the group: slot c <- input pair (gid << k) | c
-  {
-    const int kin = A.ranks[0];
-    const int64_t base = (gid << k) * kin * nrhs;
-    for (int e = threadIdx.x; e < nslot * kin * nbw; e += blockDim.x) {
-      const int n = e % nbw;
-      const int rs = e / nbw;                                 // slot * kin + s
-      S[(size_t)rs / kin * kmaxg * NB + (rs % kin) * NB + n] =
-          in[base + (int64_t)rs * nrhs + nb0 + n];
-    }
-  }
-  __syncthreads();
   const int64_t ap = gid >> sh_end;
   const int64_t bpp = gid & (((int64_t)1 << sh_end) - 1);
+
+  const FastDiv divNB(NB);
+  // load the group: slot c <- input pair (gid << k) | c; columns >= nbw are zero
+  {
+    const int kin = A.ranks[0];
+    const FastDiv divK(kin);
+    const VT* src = in + (gid << k) * kin * nrhs + nb0;
+    staged_copy_to<8>(nslot * kin * NB, S, [&](int e, int& off) {
+      int rs, n, slot, s;
+      divNB.divmod(e, rs, n);                                 // rs = slot * kin + s
+      divK.divmod(rs, slot, s);
+      off = (slot * kmaxg + s) * NB + n;
+      return n < nbw ? src[(int64_t)rs * nrhs + n] : Zero<VT>::v();
+    });
+  }
   for (int j = 0; j < k; ++j) {
     const int l = A.l_start + j;
     const int kin = A.ranks[j], kout = A.ranks[j + 1];
+    const int rem = k - j - 1;
     const FT* blk = reinterpret_cast<const FT*>(A.blk[j]);
-    const int rem = k - j - 1;                                // child bits left after this stage
-    const int nitems = nslot * nbw;
-    VT hold[2][kKmax];
-    int hold_slot[2], hold_n[2];
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-      hold_slot[it] = -1;
-      hold_n[it] = 0;
-      const int item = threadIdx.x + it * blockDim.x;
-      if (it < A.ipt && item < nitems) {
-        const int n = item % nbw;
-        const int locp = item / nbw;                          // output local index
-        const int anew = locp >> rem;                         // alpha bits incl. the new one
-        const int q = locp & ((1 << rem) - 1);
-        const int abits = anew >> 1;
-        const int loc0 = (abits << (rem + 1)) | (2 * q);
-        const int64_t a_l = (ap << (j + 1)) | anew;
-        const int64_t b_l = (bpp << rem) | q;
-        const int64_t pout = (a_l << (L - l)) | b_l;
-        // stored block layout: [pair][c kin + s][t]
-        const FT* col0 = blk + pout * kout * 2 * kin;
-        VT acc[kKmax];
-#pragma unroll
-        for (int t = 0; t < kKmax; ++t) acc[t] = Zero<VT>::v();
-        for (int c = 0; c < 2; ++c) {
-          const VT* src = S + (size_t)(loc0 + c) * kmaxg * NB + n;
-          for (int s = 0; s < kin; ++s) {
-            const VT xv = src[s * NB];
-            const FT* col = col0 + (int64_t)(c * kin + s) * kout;
-#pragma unroll
-            for (int t = 0; t < kKmax; ++t)
-              if (t < kout) cfma(acc[t], load_factor(col, t), xv);
-          }
-        }
-#pragma unroll
-        for (int t = 0; t < kKmax; ++t) hold[it][t] = acc[t];
-        hold_slot[it] = locp;
-        hold_n[it] = n;
-      }
+    // stage this level's factor blocks of the group: F[slot][c kin + s][t]
+    {
+      const int per = kout * 2 * kin;
+      const int row = 2 * kin * KT;
+      const FastDiv divRow(row);
+      staged_copy_to<8>(nslot * row, F, [&](int e, int& off) {
+        int locp, r;
+        divRow.divmod(e, locp, r);
+        const int cs = r / KT, t = r % KT;                    // KT is a compile-time constant
+        off = locp * fstride + r;
+        const int64_t pout = fused_pout(locp, j, rem, ap, bpp, L, l);
+        return t < kout ? load_factor(blk, pout * per + cs * kout + t) : Zero<VT>::v();
+      });
     }
     __syncthreads();
+    if constexpr (MFMA) {
+      // Lane l carries RHS column l of the chunk.  Block b = l >> 2 is a group
+      // of 4 columns; A-operand row i = l & 3 is the raw float i of the pair of
+      // complex entries (t = 2g, 2g+1): (re t0, im t0, re t1, im t1).  With
+      // P = sum f_i x_re and Q = sum f_i x_im, the complex outputs are
+      //   out[2g]   = (P0 - Q1, P1 + Q0),  out[2g+1] = (P2 - Q3, P3 + Q2).
+      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+      const int fi = lane & 3;
+      v4f P[2][KG], Q[2][KG];
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
-      if (hold_slot[it] >= 0) {
-        VT* dst = S + (size_t)hold_slot[it] * kmaxg * NB + hold_n[it];
+      for (int m = 0; m < 2; ++m)
 #pragma unroll
-        for (int t = 0; t < kKmax; ++t)
-          if (t < kout) dst[t * NB] = hold[it][t];
+        for (int gq = 0; gq < KG; ++gq) {
+          P[m][gq] = v4f{0.f, 0.f, 0.f, 0.f};
+          Q[m][gq] = v4f{0.f, 0.f, 0.f, 0.f};
+        }
+      // slots of this wave; when the group has fewer than 8 slots the second
+      // one repeats the first (its results are discarded) so that the inner
+      // loop has no branches and all operand reads of an iteration batch
+      const int locp0 = wave, locp1 = wave + 4 < nslot ? wave + 4 : wave;
+      const bool act0 = locp0 < nslot, act1 = wave + 4 < nslot;
+      if (act0) {
+        const int in00 = fused_in0(locp0, rem), in10 = fused_in0(locp1, rem);
+        // one flat loop over the 2*kin inputs of both children: child c = 1
+        // starts kmaxg rows further in S, and its factor rows follow c = 0's
+        const VT* src0 = S + (size_t)in00 * kmaxg * NB + lane;
+        const VT* src1 = S + (size_t)in10 * kmaxg * NB + lane;
+        const float* f0 = reinterpret_cast<const float*>(F + (size_t)locp0 * fstride) + fi;
+        const float* f1 = reinterpret_cast<const float*>(F + (size_t)locp1 * fstride) + fi;
+        const int skip = (kmaxg - kin) * NB;
+#pragma unroll 1
+        for (int j = 0; j < 2 * kin; ++j) {
+          const int soff = j * NB + (j >= kin ? skip : 0);
+          const VT x0 = src0[soff];
+          const VT x1 = src1[soff];
+          float a0v[KG], a1v[KG];
+#pragma unroll
+          for (int gq = 0; gq < KG; ++gq) {
+            a0v[gq] = f0[(j * KT + 2 * gq) * 2];
+            a1v[gq] = f1[(j * KT + 2 * gq) * 2];
+          }
+#pragma unroll
+          for (int gq = 0; gq < KG; ++gq) {
+            P[0][gq] = __builtin_amdgcn_mfma_f32_4x4x1f32(a0v[gq], x0.x, P[0][gq], 0, 0, 0);
+            Q[0][gq] = __builtin_amdgcn_mfma_f32_4x4x1f32(a0v[gq], x0.y, Q[0][gq], 0, 0, 0);
+            P[1][gq] = __builtin_amdgcn_mfma_f32_4x4x1f32(a1v[gq], x1.x, P[1][gq], 0, 0, 0);
+            Q[1][gq] = __builtin_amdgcn_mfma_f32_4x4x1f32(a1v[gq], x1.y, Q[1][gq], 0, 0, 0);
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const int locp = m == 0 ? locp0 : locp1;
+        if (m == 0 ? act0 : act1) {
+          VT* dst = S + (size_t)locp * kmaxg * NB + lane;
+#pragma unroll
+          for (int gq = 0; gq < KG; ++gq) {
+            const v4f p = P[m][gq], q = Q[m][gq];
+            if (2 * gq < kout) dst[(2 * gq) * NB] = make_float2(p[0] - q[1], p[1] + q[0]);
+            if (2 * gq + 1 < kout)
+              dst[(2 * gq + 1) * NB] = make_float2(p[2] - q[3], p[3] + q[2]);
+          }
+        }
+      }
+    } else {
+      VT hold[2][KT];
+      int hslot[2], hn[2];
+      const int nitems = nslot * NB;
+#pragma unroll
+      for (int it = 0; it < 2; ++it) {
+        hslot[it] = -1;
+        hn[it] = 0;
+        const int item = threadIdx.x + it * kBlock;
+        if (item < nitems) {
+          const int n = item % NB;
+          const int locp = item / NB;
+          const int loc0 = fused_in0(locp, rem);
+          VT acc[KT];
+#pragma unroll
+          for (int t = 0; t < KT; ++t) acc[t] = Zero<VT>::v();
+          for (int c = 0; c < 2; ++c) {
+            const VT* src = S + (size_t)(loc0 + c) * kmaxg * NB + n;
+            const VT* fcol = F + (size_t)locp * fstride + (size_t)c * kin * KT;
+            for (int s = 0; s < kin; ++s) {
+              const VT xv = src[s * NB];
+              const VT* fr = fcol + s * KT;
+#pragma unroll
+              for (int t = 0; t < KT; ++t) cfma(acc[t], fr[t], xv);
+            }
+          }
+#pragma unroll
+          for (int t = 0; t < KT; ++t) hold[it][t] = acc[t];
+          hslot[it] = locp;
+          hn[it] = n;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int it = 0; it < 2; ++it) {
+        if (hslot[it] >= 0) {
+          VT* dst = S + (size_t)hslot[it] * kmaxg * NB + hn[it];
+#pragma unroll
+          for (int t = 0; t < KT; ++t)
+            if (t < kout) dst[t * NB] = hold[it][t];
+        }
       }
     }
     __syncthreads();
@@ -203,12 +361,14 @@ __global__ __launch_bounds__(kBlock) void k_apply_fused(const VT* __restrict__ i
   // store: final slot loc -> output pair (ap << (k + sh_end)) | (loc << sh_end) | bpp
   {
     const int kout = A.ranks[k];
-    for (int e = threadIdx.x; e < nslot * kout * nbw; e += blockDim.x) {
-      const int n = e % nbw;
-      const int rs = e / nbw;
-      const int loc = rs / kout, t = rs % kout;
+    const FastDiv divK(kout);
+    for (int e = threadIdx.x; e < nslot * kout * NB; e += kBlock) {
+      int rs, n, loc, t;
+      divNB.divmod(e, rs, n);
+      if (n >= nbw) continue;
+      divK.divmod(rs, loc, t);
       const int64_t pout = (ap << (k + sh_end)) | ((int64_t)loc << sh_end) | bpp;
-      out[(pout * kout + t) * nrhs + nb0 + n] = S[(size_t)loc * kmaxg * NB + t * NB + n];
+      out[(pout * kout + t) * nrhs + nb0 + n] = S[(size_t)(loc * kmaxg + t) * NB + n];
     }
   }
 }
@@ -232,7 +392,7 @@ __global__ void k_apply_mid(const VT* __restrict__ in, VT* __restrict__ out,
 
 // ---------------------------------------------------------------------------
 // U: per (X leaf a, RHS chunk): u[perm(x)][n] = sum_b sum_k Ubar[x][b][k] mu[(a,b)][k][n]
-// LDS: mu_leaf[2^l0][K][NB], ubar_leaf[cnt][2^l0 K + 1] (padded rows).
+// LDS: mu_leaf[2^l0][K][NB], and when it fits ubar_leaf[smax][2^l0 K + 1] (padded rows).
 // ---------------------------------------------------------------------------
 template <typename VT, typename FT>
 __global__ __launch_bounds__(kBlock) void k_apply_u(
@@ -244,24 +404,33 @@ __global__ __launch_bounds__(kBlock) void k_apply_u(
   const int urow = nb * K + 1;
   VT* ml = reinterpret_cast<VT*>(smem);                       // [nb][K][NB]
   VT* ul = ml + (size_t)nb * K * NB;                          // [smax][urow] if staged
-  const int64_t nblk = (int64_t)gridDim.x;
-  const int64_t lb = xcd_logical_block(nblk);
+  const int64_t lb = xcd_logical_block((int64_t)gridDim.x);
   const int64_t a = lb / nchunk;
   const int chunk = (int)(lb % nchunk);
   const int nb0 = chunk * NB;
   const int nbw = min(NB, nrhs - nb0);
   const int32_t x0 = xoff[a], cnt = xoff[a + 1] - x0;
   const int64_t p0 = a << l0;
-  for (int e = threadIdx.x; e < nb * K * nbw; e += blockDim.x) {
-    const int n = e % nbw, bk = e / nbw;
-    ml[(size_t)bk * NB + n] = mu[(p0 * K + bk) * nrhs + nb0 + n];
+  {
+    const FastDiv divW(nbw);
+    const VT* src = mu + p0 * K * nrhs + nb0;
+    staged_copy_to<8>(nb * K * nbw, ml, [&](int e, int& off) {
+      int bk, n;
+      divW.divmod(e, bk, n);
+      off = bk * NB + n;
+      return src[(int64_t)bk * nrhs + n];
+    });
   }
   const FT* usrc = ubar + (int64_t)x0 * nb * K;
-  if (stage_factor)
-    for (int e = threadIdx.x; e < cnt * nb * K; e += blockDim.x) {
-      const int x = e / (nb * K), r = e % (nb * K);
-      ul[(size_t)x * urow + r] = load_factor(usrc, e);
-    }
+  if (stage_factor) {
+    const FastDiv divR(nb * K);
+    staged_copy_to<8>(cnt * nb * K, ul, [&](int e, int& off) {
+      int x, r;
+      divR.divmod(e, x, r);
+      off = x * urow + r;
+      return load_factor(usrc, e);
+    });
+  }
   __syncthreads();
   for (int item = threadIdx.x; item < cnt * nbw; item += blockDim.x) {
     const int x = item % cnt, n = item / cnt;
@@ -289,8 +458,7 @@ struct LaunchTimer {
     for (auto e : ev) (void)hipEventDestroy(e);
   }
   int begin() {
-    if (!prof) return IBF_OK;
-    if (prof->n_launches >= IBF_PROFILE_MAX) return IBF_OK;
+    if (!prof || prof->n_launches >= IBF_PROFILE_MAX) return IBF_OK;
     hipEvent_t a;
     IBF_HIP_CHECK(hipEventCreate(&a));
     ev.push_back(a);
@@ -318,21 +486,21 @@ struct LaunchTimer {
   }
 };
 
-// RHS chunk width and fusion depth.  The group state 2^k x Kmax x NB of
-// vector entries stays within kLdsBudget bytes, and every thread holds at most
-// two output items (2^k * NB <= 2 * kBlock).
-constexpr size_t kLdsBudget = 64 * 1024;
+// Kernel templates are instantiated for even KT = 2..16 (the padded row
+// width of the staged factor blocks).
+#define IBF_DISPATCH_KT(kt, LAUNCH)                 \
+  switch (kt) {                                     \
+    case 2: LAUNCH(2); break;                       \
+    case 4: LAUNCH(4); break;                       \
+    case 6: LAUNCH(6); break;                       \
+    case 8: LAUNCH(8); break;                       \
+    case 10: LAUNCH(10); break;                     \
+    case 12: LAUNCH(12); break;                     \
+    case 14: LAUNCH(14); break;                     \
+    default: LAUNCH(16); break;                     \
+  }
 
-struct Schedule {
-  int NB, nchunk;
-};
-
-Schedule rhs_schedule(int nrhs) {
-  Schedule s;
-  s.NB = std::min(nrhs, 32);
-  s.nchunk = (nrhs + s.NB - 1) / s.NB;
-  return s;
-}
+inline int even_kt(int k) { return std::min(16, std::max(2, (k + 1) & ~1)); }
 
 template <typename VT, typename FT>
 int apply_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int64_t nrhs64,
@@ -366,17 +534,31 @@ int apply_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int6
   VT* w[2] = {(VT*)p->d_work[0], (VT*)p->d_work[1]};
   LaunchTimer T(prof, s);
   const double fb = (double)sizeof(FT), vb = (double)sizeof(VT);
-  const Schedule sc = rhs_schedule(nrhs);
-  const int NB = sc.NB, nchunk = sc.nchunk;
+  // Per-block LDS limit of the device (queried once per device).
+  static int lds_max[64] = {0};
+  int& lmax = lds_max[p->device & 63];
+  if (!lmax) {
+    int v = 0;
+    IBF_HIP_CHECK(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
+    lmax = v > 0 ? v : 65536;
+  }
+  const size_t budget_mfma = std::min<size_t>(kLdsBudgetMfma, (size_t)lmax);
+  // Multi-RHS FP32 stages run on MFMA with 64-column chunks; otherwise the
+  // vector kernels take chunks of up to 32 columns.
+  const bool mfma = sizeof(VT) == 8 && nrhs >= 32;
+  const int NB = mfma ? 64 : std::min(nrhs, 32);
+  const int nchunk = (nrhs + NB - 1) / NB;
+  const int NBo = std::min(nrhs, 32);                         // outer (V, U) kernels
   int rc;
   // V
   {
     const int K = p->k_vbar;
-    int NBv = NB;
+    const int KT = even_kt(K);
+    int NBv = NBo;
     while (NBv > 1 && (size_t)p->smax_xi * NBv * sizeof(VT) > kLdsBudget / 2) NBv /= 2;
     const int nchv = (nrhs + NBv - 1) / NBv;
     const size_t base = (size_t)p->smax_xi * NBv * sizeof(VT);
-    const size_t fac = (size_t)p->smax_xi * (1 << l0) * K * sizeof(VT);
+    const size_t fac = (size_t)p->smax_xi * (1 << l0) * KT * sizeof(VT);
     if (base > kLdsBudget) {
       set_error("ibf_apply: an Omega leaf holds too many points for the apply kernels");
       return IBF_ERR_UNSUPPORTED;
@@ -384,9 +566,12 @@ int apply_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int6
     const int stage_f = base + fac <= kLdsBudget ? 1 : 0;
     const size_t lds = base + (stage_f ? fac : 0);
     if ((rc = T.begin())) return rc;
-    hipLaunchKernelGGL((k_apply_v<VT, FT>), dim3((unsigned)(p->nleaf * nchv)), dim3(kBlock),
-                       lds, s, (const VT*)g, ldg, p->d_perm_xi, p->d_xioff, (const FT*)p->d_vbar,
-                       w[0], L, l0, K, nrhs, NBv, nchv, p->smax_xi, stage_f);
+#define IBF_LAUNCH_V(KTC)                                                                      \
+  hipLaunchKernelGGL((k_apply_v<VT, FT, KTC>), dim3((unsigned)(p->nleaf * nchv)), dim3(kBlock), \
+                     lds, s, (const VT*)g, ldg, p->d_perm_xi, p->d_xioff, (const FT*)p->d_vbar, \
+                     w[0], L, l0, K, nrhs, NBv, nchv, p->smax_xi, stage_f)
+    IBF_DISPATCH_KT(KT, IBF_LAUNCH_V);
+#undef IBF_LAUNCH_V
     const double nnz = (double)p->nnz_vbar;
     if ((rc = T.end("apply_v", 8.0 * nnz * nrhs,
                     nnz * fb + vb * nrhs * ((double)p->nxi + (double)p->npairs * K))))
@@ -405,7 +590,10 @@ int apply_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int6
     cur ^= 1;
     return IBF_OK;
   };
-  // fused butterfly stages, split at the middle when a middle block exists
+  // LDS bytes of a fused group of 2^k pairs: state [2^k][kmaxg][NB] + factors [2^k][2 kmaxg][KT]
+  auto fused_lds = [&](int kk, int kmg, int kt) -> size_t {
+    return ((size_t)1 << kk) * ((size_t)kmg * NB + (size_t)2 * kmg * kt) * sizeof(VT);
+  };
   auto run_stages = [&](int lo, int hi, bool gside) -> int {   // output levels lo..hi
     int l = lo;
     while (l <= hi) {
@@ -414,11 +602,11 @@ int apply_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int6
         const int next = kk + 1;
         if (l + next - 1 > hi) break;
         if (next > kMaxR - 1) break;
-        if (((int64_t)1 << next) * NB > 2 * kBlock) break;
         if (next > L - l + 1) break;                          // group must fit the b bits
+        if (mfma ? (next > 3) : (((int64_t)1 << next) * NB > 2 * kBlock)) break;
         int km = 1;
         for (int j = 0; j <= next; ++j) km = std::max(km, rank_at(l - 1 + j, gside));
-        if (((size_t)1 << next) * km * NB * sizeof(VT) > kLdsBudget) break;
+        if (fused_lds(next, km, even_kt(km)) > (mfma ? budget_mfma : kLdsBudget)) break;
         kk = next;
       }
       FusedArgs A{};
@@ -428,26 +616,42 @@ int apply_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int6
       A.nrhs = nrhs;
       A.NB = NB;
       A.nchunk = nchunk;
-      A.ipt = (int)(((((int64_t)1 << kk) * NB) + kBlock - 1) / kBlock);
-      int km = 1;
-      double nnz = 0, vec = 0;
+      int km = 1, kom = 1;
+      double nnz = 0;
       for (int j = 0; j <= kk; ++j) {
         A.ranks[j] = rank_at(l - 1 + j, gside);
         km = std::max(km, A.ranks[j]);
+        if (j > 0) kom = std::max(kom, A.ranks[j]);
       }
+      A.kmaxg = km;
       for (int j = 0; j < kk; ++j) {
         const Stage& st = p->stages[l + j - l0 - 1];
         A.blk[j] = st.blk;
         nnz += (double)st.nnz;
       }
-      vec = (double)p->npairs * (A.ranks[0] + A.ranks[kk]) * nrhs * vb;
-      const size_t lds = ((size_t)1 << kk) * km * NB * sizeof(VT);
+      const int KT = even_kt(kom);
+      const double vec = (double)p->npairs * (A.ranks[0] + A.ranks[kk]) * nrhs * vb;
+      const size_t lds = fused_lds(kk, km, KT);
       const int64_t ngroups = p->npairs >> kk;
+      const unsigned grid = (unsigned)(ngroups * nchunk);
       int rc2;
       if ((rc2 = T.begin())) return rc2;
-      hipLaunchKernelGGL((k_apply_fused<VT, FT>), dim3((unsigned)(ngroups * nchunk)),
-                         dim3(kBlock), lds, s, w[cur], w[cur ^ 1], A);
-      if ((rc2 = T.end("apply_fused", 8.0 * nnz * nrhs, nnz * fb + vec))) return rc2;
+      if (mfma) {
+        if constexpr (sizeof(VT) == 8) {
+#define IBF_LAUNCH_FM(KTC) \
+  hipLaunchKernelGGL((k_apply_fused<VT, FT, KTC, true>), dim3(grid), dim3(kBlock), lds, s, w[cur], w[cur ^ 1], A)
+          IBF_DISPATCH_KT(KT, IBF_LAUNCH_FM);
+#undef IBF_LAUNCH_FM
+        }
+      } else {
+#define IBF_LAUNCH_FV(KTC) \
+  hipLaunchKernelGGL((k_apply_fused<VT, FT, KTC, false>), dim3(grid), dim3(kBlock), lds, s, w[cur], w[cur ^ 1], A)
+        IBF_DISPATCH_KT(KT, IBF_LAUNCH_FV);
+#undef IBF_LAUNCH_FV
+      }
+      if ((rc2 = T.end(mfma ? "apply_fused_mfma" : "apply_fused", 8.0 * nnz * nrhs,
+                       nnz * fb + vec)))
+        return rc2;
       cur ^= 1;
       l += kk;
     }
@@ -463,7 +667,7 @@ int apply_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int6
   // U
   {
     const int K = p->k_ubar;
-    int NBu = NB;
+    int NBu = NBo;
     while (NBu > 1 && (size_t)(1 << l0) * K * NBu * sizeof(VT) > kLdsBudget / 2) NBu /= 2;
     const int nchu = (nrhs + NBu - 1) / NBu;
     const size_t base = (size_t)(1 << l0) * K * NBu * sizeof(VT);

@@ -131,6 +131,19 @@ def test_fp32_parity(torch_dev):
     assert q["rank"] == [v for _, v in sorted(O.level_ranks(Op).items())]
 
 
+def test_fp32_odd_nrhs_chunks(torch_dev):
+    """37 right-hand sides: two RHS chunks, the second partial."""
+    _say("fp32 nrhs=37 fio4k_r12")
+    P0 = _problems()["fio4k_r12"]
+    g = I.complex_normal(P0.n, 37, np.random.default_rng(31))
+    P = I.Problem1D("fio4k_r12_37", P0.x, P0.xi, P0.phase, P0.params, P0.r, P0.tol, P0.leaf,
+                    37, g, I.PREC_FP32)
+    _, prob, Op, _ = _oracle("fio4k_r12")
+    u_ref = O.apply_optimal(Op, g)
+    u, q = _run_gpu(torch_dev, P, I.PREC_FP32)
+    assert O.rel_error(u, u_ref) < 1e-5
+
+
 def test_bf16x2_parity(torch_dev):
     _say("bf16x2 parity fio4k_r12")
     P, prob, Op, u_ref = _oracle("fio4k_r12")
