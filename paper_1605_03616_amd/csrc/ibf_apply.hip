@@ -169,11 +169,15 @@ __global__ __launch_bounds__(kBlock) void k_apply_v(
 // group's pair at level l_start-1+j has local index (alpha bits << (nst-j)) |
 // (remaining child bits); a stage consumes the lowest child bit and appends
 // an alpha bit.  Outputs of a stage are held in registers across a barrier
-// and written back in place.  ranks[j] = stored K at level l_start-1+j.
+// and written back in place; those of the last stage go straight to HBM.
+// ranks[j] = stored K at level l_start-1+j; kld[j] = row length of stage j's
+// stored blocks (each pair's block is 2 ranks[j] rows of kld[j] entries,
+// contiguous in HBM and copied unchanged into LDS).
 // ---------------------------------------------------------------------------
 struct FusedArgs {
   int L, l_start, nst, nrhs, NB, nchunk, kmaxg;
   int ranks[kMaxR + 1];
+  int kld[kMaxR];
   const void* blk[kMaxR];
 };
 
@@ -193,17 +197,52 @@ __device__ __forceinline__ int fused_in0(int locp, int rem) {
   return ((anew >> 1) << (rem + 1)) | (2 * q);
 }
 
+// Factor blocks of one stage for slots s0 .. s0+NS-1 (fs <= 2 kBlock entries
+// per slot): loads into registers, stores into F[slot][fs].  The slot loop is
+// uniform, so the HBM address of a block is a scalar base plus the thread id.
+template <int NS, typename VT, typename FT>
+struct FactorBatch {
+  VT v[NS][2];
+  __device__ __forceinline__ void load(const FT* blk, int fs, int s0, int nslot, int j, int rem,
+                                       int64_t ap, int64_t bpp, int L, int l) {
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int slot = s0 + u;
+      if (slot < nslot) {
+        const FT* src = blk + fused_pout(slot, j, rem, ap, bpp, L, l) * fs;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int o = threadIdx.x + h * kBlock;
+          if (o < fs) v[u][h] = load_factor(src, o);
+        }
+      }
+    }
+  }
+  __device__ __forceinline__ void store(VT* F, int fs, int s0, int nslot) const {
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int slot = s0 + u;
+      if (slot < nslot) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int o = threadIdx.x + h * kBlock;
+          if (o < fs) F[slot * fs + o] = v[u][h];
+        }
+      }
+    }
+  }
+};
+
 template <typename VT, typename FT, int KT, bool MFMA>
 __global__ __launch_bounds__(kBlock) void k_apply_fused(const VT* __restrict__ in,
                                                         VT* __restrict__ out, FusedArgs A) {
   static_assert(!MFMA || sizeof(VT) == 8, "MFMA variant computes in FP32");
   constexpr int KG = KT / 2;                                  // row pairs (MFMA row groups)
   extern __shared__ __align__(16) unsigned char smem[];
-  const int k = A.nst, NB = A.NB, L = A.L, kmaxg = A.kmaxg;
+  const int k = A.nst, NB = MFMA ? 64 : A.NB, L = A.L, kmaxg = A.kmaxg;
   const int nslot = 1 << k;
   VT* S = reinterpret_cast<VT*>(smem);                        // [nslot][kmaxg][NB]
-  VT* F = S + (size_t)nslot * kmaxg * NB;                     // [nslot][2 kmaxg][KT]
-  const int fstride = 2 * kmaxg * KT;
+  VT* F = S + (size_t)nslot * kmaxg * NB;                     // [nslot][fs] (+ KT slack)
   const int64_t lb = xcd_logical_block((int64_t)gridDim.x);
   const int64_t gid = lb / A.nchunk;
   const int chunk = (int)(lb % A.nchunk);
@@ -213,49 +252,63 @@ __global__ __launch_bounds__(kBlock) void k_apply_fused(const VT* __restrict__ i
   const int sh_end = L - (A.l_start + k - 1);
   const int64_t ap = gid >> sh_end;
   const int64_t bpp = gid & (((int64_t)1 << sh_end) - 1);
+  // thread -> (column n, first row w) of the [row][NB] tiles it moves
+  const int rstep = kBlock / NB;
+  const int n = threadIdx.x % NB, w = threadIdx.x / NB;
 
-  const FastDiv divNB(NB);
   // load the group: slot c <- input pair (gid << k) | c; columns >= nbw are zero
   {
     const int kin = A.ranks[0];
-    const FastDiv divK(kin);
-    const VT* src = in + (gid << k) * kin * nrhs + nb0;
-    staged_copy_to<8>(nslot * kin * NB, S, [&](int e, int& off) {
-      int rs, n, slot, s;
-      divNB.divmod(e, rs, n);                                 // rs = slot * kin + s
-      divK.divmod(rs, slot, s);
-      off = (slot * kmaxg + s) * NB + n;
-      return n < nbw ? src[(int64_t)rs * nrhs + n] : Zero<VT>::v();
-    });
-  }
-  for (int j = 0; j < k; ++j) {
-    const int l = A.l_start + j;
-    const int kin = A.ranks[j], kout = A.ranks[j + 1];
-    const int rem = k - j - 1;
-    const FT* blk = reinterpret_cast<const FT*>(A.blk[j]);
-    // stage this level's factor blocks of the group: F[slot][c kin + s][t]
-    {
-      const int per = kout * 2 * kin;
-      const int row = 2 * kin * KT;
-      const FastDiv divRow(row);
-      staged_copy_to<8>(nslot * row, F, [&](int e, int& off) {
-        int locp, r;
-        divRow.divmod(e, locp, r);
-        const int cs = r / KT, t = r % KT;                    // KT is a compile-time constant
-        off = locp * fstride + r;
-        const int64_t pout = fused_pout(locp, j, rem, ap, bpp, L, l);
-        return t < kout ? load_factor(blk, pout * per + cs * kout + t) : Zero<VT>::v();
-      });
+    const VT* src = in + (gid << k) * kin * nrhs + nb0 + n;
+    const int rows = nslot * kin;
+    if (w < rstep) {
+      int slot = 0, s = w;
+      while (s >= kin) { s -= kin; ++slot; }
+      for (int r0 = w; r0 < rows; r0 += 4 * rstep) {
+        VT tmp[4];
+        int off[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int r = r0 + u * rstep;
+          off[u] = -1;
+          if (r < rows) {
+            tmp[u] = n < nbw ? src[(int64_t)r * nrhs] : Zero<VT>::v();
+            off[u] = (slot * kmaxg + s) * NB + n;
+          }
+          s += rstep;
+          while (s >= kin) { s -= kin; ++slot; }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (off[u] >= 0) S[off[u]] = tmp[u];
+      }
     }
+  }
+
+  if constexpr (MFMA) {
+    // Lane l carries RHS column l of the chunk.  Block b = l >> 2 is a group
+    // of 4 columns; A-operand row i = l & 3 is the raw float i of the pair of
+    // complex entries (t = 2g, 2g+1): (re t0, im t0, re t1, im t1).  With
+    // P = sum f_i x_re and Q = sum f_i x_im, the complex outputs are
+    //   out[2g]   = (P0 - Q1, P1 + Q0),  out[2g+1] = (P2 - Q3, P3 + Q2).
+    // Wave v owns output slots v and v + 4; when the group has fewer than 8
+    // slots the second repeats the first (results discarded) so that the
+    // inner loop has no branches and all operand reads of an iteration batch.
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int fi = lane & 3;
+    FactorBatch<8, VT, FT> fb;
+    fb.load(reinterpret_cast<const FT*>(A.blk[0]), 2 * A.ranks[0] * A.kld[0], 0, nslot, 0, k - 1,
+            ap, bpp, L, A.l_start);
+    fb.store(F, 2 * A.ranks[0] * A.kld[0], 0, nslot);
     __syncthreads();
-    if constexpr (MFMA) {
-      // Lane l carries RHS column l of the chunk.  Block b = l >> 2 is a group
-      // of 4 columns; A-operand row i = l & 3 is the raw float i of the pair of
-      // complex entries (t = 2g, 2g+1): (re t0, im t0, re t1, im t1).  With
-      // P = sum f_i x_re and Q = sum f_i x_im, the complex outputs are
-      //   out[2g]   = (P0 - Q1, P1 + Q0),  out[2g+1] = (P2 - Q3, P3 + Q2).
-      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-      const int fi = lane & 3;
+    for (int j = 0; j < k; ++j) {
+      const int l = A.l_start + j;
+      const int kin = A.ranks[j], kout = A.ranks[j + 1], ke = A.kld[j];
+      const int fs = 2 * kin * ke;
+      const int rem = k - j - 1;
+      if (j + 1 < k)   // next stage's factor blocks: in flight during this stage
+        fb.load(reinterpret_cast<const FT*>(A.blk[j + 1]), 2 * kout * A.kld[j + 1], 0, nslot,
+                j + 1, rem - 1, ap, bpp, L, l + 1);
       v4f P[2][KG], Q[2][KG];
 #pragma unroll
       for (int m = 0; m < 2; ++m)
@@ -264,30 +317,27 @@ __global__ __launch_bounds__(kBlock) void k_apply_fused(const VT* __restrict__ i
           P[m][gq] = v4f{0.f, 0.f, 0.f, 0.f};
           Q[m][gq] = v4f{0.f, 0.f, 0.f, 0.f};
         }
-      // slots of this wave; when the group has fewer than 8 slots the second
-      // one repeats the first (its results are discarded) so that the inner
-      // loop has no branches and all operand reads of an iteration batch
       const int locp0 = wave, locp1 = wave + 4 < nslot ? wave + 4 : wave;
       const bool act0 = locp0 < nslot, act1 = wave + 4 < nslot;
       if (act0) {
         const int in00 = fused_in0(locp0, rem), in10 = fused_in0(locp1, rem);
-        // one flat loop over the 2*kin inputs of both children: child c = 1
+        // one flat loop over the 2 kin inputs of both children: child c = 1
         // starts kmaxg rows further in S, and its factor rows follow c = 0's
         const VT* src0 = S + (size_t)in00 * kmaxg * NB + lane;
         const VT* src1 = S + (size_t)in10 * kmaxg * NB + lane;
-        const float* f0 = reinterpret_cast<const float*>(F + (size_t)locp0 * fstride) + fi;
-        const float* f1 = reinterpret_cast<const float*>(F + (size_t)locp1 * fstride) + fi;
+        const float* f0 = reinterpret_cast<const float*>(F + (size_t)locp0 * fs) + fi;
+        const float* f1 = reinterpret_cast<const float*>(F + (size_t)locp1 * fs) + fi;
         const int skip = (kmaxg - kin) * NB;
 #pragma unroll 1
-        for (int j = 0; j < 2 * kin; ++j) {
-          const int soff = j * NB + (j >= kin ? skip : 0);
+        for (int jj = 0; jj < 2 * kin; ++jj) {
+          const int soff = jj * NB + (jj >= kin ? skip : 0);
           const VT x0 = src0[soff];
           const VT x1 = src1[soff];
           float a0v[KG], a1v[KG];
 #pragma unroll
           for (int gq = 0; gq < KG; ++gq) {
-            a0v[gq] = f0[(j * KT + 2 * gq) * 2];
-            a1v[gq] = f1[(j * KT + 2 * gq) * 2];
+            a0v[gq] = f0[(jj * ke + 2 * gq) * 2];
+            a1v[gq] = f1[(jj * ke + 2 * gq) * 2];
           }
 #pragma unroll
           for (int gq = 0; gq < KG; ++gq) {
@@ -298,22 +348,56 @@ __global__ __launch_bounds__(kBlock) void k_apply_fused(const VT* __restrict__ i
           }
         }
       }
-      __syncthreads();
+      if (j + 1 < k) {
+        __syncthreads();                                      // S and F reads done
 #pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        const int locp = m == 0 ? locp0 : locp1;
-        if (m == 0 ? act0 : act1) {
-          VT* dst = S + (size_t)locp * kmaxg * NB + lane;
+        for (int m = 0; m < 2; ++m) {
+          const int locp = m == 0 ? locp0 : locp1;
+          if (m == 0 ? act0 : act1) {
+            VT* dst = S + (size_t)locp * kmaxg * NB + lane;
 #pragma unroll
-          for (int gq = 0; gq < KG; ++gq) {
-            const v4f p = P[m][gq], q = Q[m][gq];
-            if (2 * gq < kout) dst[(2 * gq) * NB] = make_float2(p[0] - q[1], p[1] + q[0]);
-            if (2 * gq + 1 < kout)
-              dst[(2 * gq + 1) * NB] = make_float2(p[2] - q[3], p[3] + q[2]);
+            for (int gq = 0; gq < KG; ++gq) {
+              const v4f p = P[m][gq], q = Q[m][gq];
+              if (2 * gq < kout) dst[(2 * gq) * NB] = make_float2(p[0] - q[1], p[1] + q[0]);
+              if (2 * gq + 1 < kout)
+                dst[(2 * gq + 1) * NB] = make_float2(p[2] - q[3], p[3] + q[2]);
+            }
+          }
+        }
+        fb.store(F, 2 * kout * A.kld[j + 1], 0, nslot);
+        __syncthreads();
+      } else if (lane < nbw) {
+        // last stage: coalesced rows of 64 columns straight to HBM
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          const int locp = m == 0 ? locp0 : locp1;
+          if (m == 0 ? act0 : act1) {
+            VT* dst = out + fused_pout(locp, j, 0, ap, bpp, L, l) * kout * nrhs + nb0 + lane;
+#pragma unroll
+            for (int gq = 0; gq < KG; ++gq) {
+              const v4f p = P[m][gq], q = Q[m][gq];
+              if (2 * gq < kout)
+                dst[(int64_t)(2 * gq) * nrhs] = make_float2(p[0] - q[1], p[1] + q[0]);
+              if (2 * gq + 1 < kout)
+                dst[(int64_t)(2 * gq + 1) * nrhs] = make_float2(p[2] - q[3], p[3] + q[2]);
+            }
           }
         }
       }
-    } else {
+    }
+  } else {
+    for (int j = 0; j < k; ++j) {
+      const int l = A.l_start + j;
+      const int kin = A.ranks[j], kout = A.ranks[j + 1], ke = A.kld[j];
+      const int fs = 2 * kin * ke;
+      const int rem = k - j - 1;
+      const FT* blk = reinterpret_cast<const FT*>(A.blk[j]);
+      for (int s0 = 0; s0 < nslot; s0 += 4) {
+        FactorBatch<4, VT, FT> fb;
+        fb.load(blk, fs, s0, nslot, j, rem, ap, bpp, L, l);
+        fb.store(F, fs, s0, nslot);
+      }
+      __syncthreads();
       VT hold[2][KT];
       int hslot[2], hn[2];
       const int nitems = nslot * NB;
@@ -323,18 +407,18 @@ __global__ __launch_bounds__(kBlock) void k_apply_fused(const VT* __restrict__ i
         hn[it] = 0;
         const int item = threadIdx.x + it * kBlock;
         if (item < nitems) {
-          const int n = item % NB;
+          const int nn = item % NB;
           const int locp = item / NB;
           const int loc0 = fused_in0(locp, rem);
           VT acc[KT];
 #pragma unroll
           for (int t = 0; t < KT; ++t) acc[t] = Zero<VT>::v();
           for (int c = 0; c < 2; ++c) {
-            const VT* src = S + (size_t)(loc0 + c) * kmaxg * NB + n;
-            const VT* fcol = F + (size_t)locp * fstride + (size_t)c * kin * KT;
+            const VT* src = S + (size_t)(loc0 + c) * kmaxg * NB + nn;
+            const VT* fcol = F + (size_t)locp * fs + (size_t)c * kin * ke;
             for (int s = 0; s < kin; ++s) {
               const VT xv = src[s * NB];
-              const VT* fr = fcol + s * KT;
+              const VT* fr = fcol + s * ke;
 #pragma unroll
               for (int t = 0; t < KT; ++t) cfma(acc[t], fr[t], xv);
             }
@@ -342,7 +426,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_fused(const VT* __restrict__ i
 #pragma unroll
           for (int t = 0; t < KT; ++t) hold[it][t] = acc[t];
           hslot[it] = locp;
-          hn[it] = n;
+          hn[it] = nn;
         }
       }
       __syncthreads();
@@ -355,20 +439,20 @@ __global__ __launch_bounds__(kBlock) void k_apply_fused(const VT* __restrict__ i
             if (t < kout) dst[t * NB] = hold[it][t];
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
-  }
-  // store: final slot loc -> output pair (ap << (k + sh_end)) | (loc << sh_end) | bpp
-  {
+    // store: final slot loc -> output pair (ap << (k + sh_end)) | (loc << sh_end) | bpp
     const int kout = A.ranks[k];
-    const FastDiv divK(kout);
-    for (int e = threadIdx.x; e < nslot * kout * NB; e += kBlock) {
-      int rs, n, loc, t;
-      divNB.divmod(e, rs, n);
-      if (n >= nbw) continue;
-      divK.divmod(rs, loc, t);
-      const int64_t pout = (ap << (k + sh_end)) | ((int64_t)loc << sh_end) | bpp;
-      out[(pout * kout + t) * nrhs + nb0 + n] = S[(size_t)(loc * kmaxg + t) * NB + n];
+    const int rows = nslot * kout;
+    if (w < rstep && n < nbw) {
+      int loc = 0, t = w;
+      while (t >= kout) { t -= kout; ++loc; }
+      for (int r = w; r < rows; r += rstep) {
+        const int64_t pout = (ap << (k + sh_end)) | ((int64_t)loc << sh_end) | bpp;
+        out[(pout * kout + t) * nrhs + nb0 + n] = S[(size_t)(loc * kmaxg + t) * NB + n];
+        t += rstep;
+        while (t >= kout) { t -= kout; ++loc; }
+      }
     }
   }
 }
@@ -590,9 +674,11 @@ int apply_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int6
     cur ^= 1;
     return IBF_OK;
   };
-  // LDS bytes of a fused group of 2^k pairs: state [2^k][kmaxg][NB] + factors [2^k][2 kmaxg][KT]
+  // LDS bytes of a fused group of 2^k pairs: state [2^k][kmaxg][NB] + factors
+  // [2^k][2 kmaxg kld] with kld <= kt, + kt entries of slack (the compute loops
+  // read whole kt-wide rows; entries past a row feed only discarded outputs)
   auto fused_lds = [&](int kk, int kmg, int kt) -> size_t {
-    return ((size_t)1 << kk) * ((size_t)kmg * NB + (size_t)2 * kmg * kt) * sizeof(VT);
+    return (((size_t)1 << kk) * ((size_t)kmg * NB + (size_t)2 * kmg * kt) + kt) * sizeof(VT);
   };
   auto run_stages = [&](int lo, int hi, bool gside) -> int {   // output levels lo..hi
     int l = lo;
@@ -627,6 +713,7 @@ int apply_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int6
       for (int j = 0; j < kk; ++j) {
         const Stage& st = p->stages[l + j - l0 - 1];
         A.blk[j] = st.blk;
+        A.kld[j] = st.k_ld;
         nnz += (double)st.nnz;
       }
       const int KT = even_kt(kom);

@@ -70,22 +70,24 @@ __global__ void k_cheb(int r, double* cheb) {
 
 // ---------------------------------------------------------------------------
 // Conversion of one stage from the FP64 r x 2r staging layout [pair][t][c r + s]
-// to the stored layout [pair][c k_in + s][t] (input-major: the k_out entries
-// that multiply one input coefficient are contiguous) in the storage precision.
+// to the stored layout [pair][c k_in + s][t < kld] (input-major: the k_out
+// entries that multiply one input coefficient are contiguous; rows padded with
+// zeros to the even length kld so that a pair's block copies in 16-byte units)
+// in the storage precision.
 // ---------------------------------------------------------------------------
 template <typename FT>
 __global__ void k_pack_stage(const double2* stage, FT* out, int64_t npairs, int R, int kout,
-                             int kin) {
-  const int64_t per = (int64_t)kout * 2 * kin;
+                             int kin, int kld) {
+  const int64_t per = (int64_t)kld * 2 * kin;
   const int64_t total = npairs * per;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = e / per;
     const int rem = (int)(e - p * per);
-    const int cc = rem / kout;
-    const int t = rem - cc * kout;
+    const int cc = rem / kld;
+    const int t = rem - cc * kld;
     const int c = cc / kin, s = cc - c * kin;
-    store_factor(out, e, stage[(p * R + t) * 2 * R + c * R + s]);
+    store_factor(out, e, t < kout ? stage[(p * R + t) * 2 * R + c * R + s] : make_double2(0, 0));
   }
 }
 
@@ -266,13 +268,15 @@ int pack_all(ibf_plan_t p, const std::vector<DevBuf<double2>>& stages, const dou
     st.level_out = l;
     st.k_out = p->rank[l - l0];
     st.k_in = p->rank[l - 1 - l0];
-    const int64_t count = p->npairs * st.k_out * 2 * st.k_in;
+    st.k_ld = (st.k_out + 1) & ~1;
+    const int64_t count = p->npairs * st.k_ld * 2 * st.k_in;
     st.bytes = (size_t)count * fb;
     IBF_HIP_CHECK(hipMalloc(&st.blk, std::max<size_t>(st.bytes, 1)));
     p->stages.push_back(st);
     const unsigned blocks = (unsigned)std::min<int64_t>((count + kBlock - 1) / kBlock, 1 << 20);
     hipLaunchKernelGGL((k_pack_stage<FT>), dim3(std::max(blocks, 1u)), dim3(kBlock), 0, s,
-                       stages[l - l0 - 1].ptr, (FT*)st.blk, p->npairs, R, st.k_out, st.k_in);
+                       stages[l - l0 - 1].ptr, (FT*)st.blk, p->npairs, R, st.k_out, st.k_in,
+                       st.k_ld);
     p->nnz_stored += count;
   }
   // Ubar at level L-l0, Vbar at level l0
@@ -398,13 +402,14 @@ int sweep_in_pack(ibf_plan_t p, std::vector<DevBuf<double2>>& stages, const doub
     st.k_out = rk[l - l0];
     st.k_in = rk[l - 1 - l0];
     st.nnz = 0;
-    const int64_t count = np * st.k_out * 2 * st.k_in;
+    st.k_ld = (st.k_out + 1) & ~1;
+    const int64_t count = np * st.k_ld * 2 * st.k_in;
     st.bytes = (size_t)count * fb;
     IBF_HIP_CHECK(hipMalloc(&st.blk, std::max<size_t>(st.bytes, 1)));
     p->stages.push_back(st);
     const unsigned blocks = (unsigned)std::min<int64_t>((count + kBlock - 1) / kBlock, 1 << 20);
     hipLaunchKernelGGL((k_pack_stage<FT>), dim3(std::max(blocks, 1u)), dim3(kBlock), 0, s,
-                       stages[l - l0 - 1].ptr, (FT*)st.blk, np, R, st.k_out, st.k_in);
+                       stages[l - l0 - 1].ptr, (FT*)st.blk, np, R, st.k_out, st.k_in, st.k_ld);
     p->nnz_stored += count;
   }
   p->k_mid_g = rg[h - l0];

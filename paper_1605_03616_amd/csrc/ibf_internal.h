@@ -32,7 +32,8 @@ void set_error(const std::string& msg);
 struct Stage {
   int level_out;     // output coefficient level (l0+1 .. L-l0)
   int k_out, k_in;   // stored ranks
-  void* blk;         // [pair][k_out][2*k_in] complex
+  int k_ld;          // row length: k_out rounded up to even, zero-padded
+  void* blk;         // [pair][c k_in + s][k_ld] complex (input-major rows)
   size_t bytes;
   int64_t nnz;       // unpadded entries (each block at its own ranks)
 };
