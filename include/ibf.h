@@ -174,6 +174,38 @@ int ibf_eval_kernel(int phase_id, const double* phase_params, int n_params,
                     const double* x, const double* xi, int64_t n, void* out,
                     void* hip_stream);
 
+/*
+ * Batched application of many independent plans with uneven sizes and RHS
+ * counts (the paper's applications are one plan at a time; the batch runs
+ * many small problems of Sec. 6 together so that each launch fills the GPU).
+ * A batch references `count` built plans of one precision on one device; it
+ * does not own them, and they must outlive it.  Errors: INVALID_ARG (NULL,
+ * count < 1, a plan not built, mixed precision or device), DEVICE.
+ */
+typedef struct ibf_batch_s* ibf_batch_t;
+int ibf_batch_create(const ibf_plan_t* plans, int count, ibf_batch_t* out);
+
+/*
+ * u_i = K_IBF,i g_i for every plan i of the batch: host arrays of `count`
+ * entries holding device pointers g[i], u[i] (layout as in ibf_apply),
+ * leading dimensions ldg[i], ldu[i] and RHS counts nrhs[i].  All plans'
+ * work runs in a few launches, one per phase of the apply (V, each fused
+ * butterfly stage group, U); a block finds its plan from a per-launch table
+ * of descriptors copied to the device before the launches.  With flags &
+ * IBF_BATCH_GRAPH the launches are captured once into a hipGraph and
+ * replayed while the RHS counts stay the same (new g/u pointers only
+ * rewrite the table).  Stream-ordered on `hip_stream`; the same plan must not
+ * be applied concurrently elsewhere.  Plans built with the sweep-in are not
+ * batched (UNSUPPORTED).  Errors: INVALID_ARG, UNSUPPORTED, OOM, DEVICE.
+ */
+#define IBF_BATCH_GRAPH 1
+int ibf_apply_batch(ibf_batch_t batch, const void* const* g, const int64_t* ldg,
+                    void* const* u, const int64_t* ldu, const int64_t* nrhs,
+                    int flags, void* hip_stream);
+
+/* Free the batch's table, graph and capture stream (NULL is a no-op). */
+int ibf_batch_destroy(ibf_batch_t batch);
+
 #ifdef __cplusplus
 }
 #endif

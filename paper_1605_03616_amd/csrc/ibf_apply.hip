@@ -103,15 +103,29 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t nblk) {
 // V: per (Omega leaf b, RHS chunk): mu[(a,b)][k][n] = sum_{xi in b} Vbar^*[xi][a][k] g[xi][n]
 // LDS: g_leaf[smax][NB], and when it fits vbar_leaf[smax][2^l0][KT] (zero-padded).
 // ---------------------------------------------------------------------------
+struct VDesc {
+  const void* g;
+  int64_t ldg;
+  const int32_t* perm_xi;
+  const int32_t* xioff;
+  const void* vbar;
+  void* mu;
+  int L, l0, K, nrhs, NB, nchunk, smax, stage_f;
+};
+
 template <typename VT, typename FT, int KT>
-__global__ __launch_bounds__(kBlock) void k_apply_v(
-    const VT* __restrict__ g, int64_t ldg, const int32_t* __restrict__ perm_xi,
-    const int32_t* __restrict__ xioff, const FT* __restrict__ vbar, VT* __restrict__ mu, int L,
-    int l0, int K, int nrhs, int NB, int nchunk, int smax, int stage_factor) {
+__device__ __forceinline__ void apply_v_body(const VDesc& d, int64_t lb) {
   extern __shared__ __align__(16) unsigned char smem[];
+  const VT* __restrict__ g = reinterpret_cast<const VT*>(d.g);
+  const FT* __restrict__ vbar = reinterpret_cast<const FT*>(d.vbar);
+  VT* __restrict__ mu = reinterpret_cast<VT*>(d.mu);
+  const int32_t* __restrict__ perm_xi = d.perm_xi;
+  const int32_t* __restrict__ xioff = d.xioff;
+  const int64_t ldg = d.ldg;
+  const int L = d.L, l0 = d.l0, K = d.K, nrhs = d.nrhs, NB = d.NB, nchunk = d.nchunk;
+  const int smax = d.smax, stage_factor = d.stage_f;
   VT* gl = reinterpret_cast<VT*>(smem);                       // [smax][NB]
   VT* vl = gl + (size_t)smax * NB;                            // [smax][2^l0][KT]
-  const int64_t lb = xcd_logical_block((int64_t)gridDim.x);
   const int64_t b = lb / nchunk;
   const int chunk = (int)(lb % nchunk);
   const int nb0 = chunk * NB;
@@ -161,6 +175,29 @@ __global__ __launch_bounds__(kBlock) void k_apply_v(
     for (int k = 0; k < KT; ++k)
       if (k < K) o[(int64_t)k * nrhs] = acc[k];
   }
+}
+
+// Batched launches: problem p owns logical blocks [boff[p], boff[p+1]).
+__device__ __forceinline__ int find_problem(const int64_t* __restrict__ boff, int count,
+                                            int64_t b) {
+  int lo = 0, hi = count - 1;                                 // largest p with boff[p] <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (boff[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename VT, typename FT, int KT>
+__global__ __launch_bounds__(kBlock) void k_apply_v(VDesc d) {
+  apply_v_body<VT, FT, KT>(d, xcd_logical_block((int64_t)gridDim.x));
+}
+template <typename VT, typename FT, int KT>
+__global__ __launch_bounds__(kBlock) void k_batch_v(const VDesc* __restrict__ ds,
+                                                    const int64_t* __restrict__ boff, int count) {
+  const int p = find_problem(boff, count, blockIdx.x);
+  apply_v_body<VT, FT, KT>(ds[p], (int64_t)blockIdx.x - boff[p]);
 }
 
 // ---------------------------------------------------------------------------
@@ -233,17 +270,24 @@ struct FactorBatch {
   }
 };
 
+struct FusedDesc {
+  const void* in;
+  void* out;
+  FusedArgs A;
+};
+
 template <typename VT, typename FT, int KT, bool MFMA>
-__global__ __launch_bounds__(kBlock) void k_apply_fused(const VT* __restrict__ in,
-                                                        VT* __restrict__ out, FusedArgs A) {
+__device__ __forceinline__ void apply_fused_body(const FusedDesc& D, int64_t lb) {
   static_assert(!MFMA || sizeof(VT) == 8, "MFMA variant computes in FP32");
   constexpr int KG = KT / 2;                                  // row pairs (MFMA row groups)
   extern __shared__ __align__(16) unsigned char smem[];
+  const VT* __restrict__ in = reinterpret_cast<const VT*>(D.in);
+  VT* __restrict__ out = reinterpret_cast<VT*>(D.out);
+  const FusedArgs& A = D.A;
   const int k = A.nst, NB = MFMA ? 64 : A.NB, L = A.L, kmaxg = A.kmaxg;
   const int nslot = 1 << k;
   VT* S = reinterpret_cast<VT*>(smem);                        // [nslot][kmaxg][NB]
   VT* F = S + (size_t)nslot * kmaxg * NB;                     // [nslot][fs] (+ KT slack)
-  const int64_t lb = xcd_logical_block((int64_t)gridDim.x);
   const int64_t gid = lb / A.nchunk;
   const int chunk = (int)(lb % A.nchunk);
   const int nb0 = chunk * NB;
@@ -457,11 +501,34 @@ __global__ __launch_bounds__(kBlock) void k_apply_fused(const VT* __restrict__ i
   }
 }
 
+template <typename VT, typename FT, int KT, bool MFMA>
+__global__ __launch_bounds__(kBlock) void k_apply_fused(FusedDesc D) {
+  apply_fused_body<VT, FT, KT, MFMA>(D, xcd_logical_block((int64_t)gridDim.x));
+}
+template <typename VT, typename FT, int KT, bool MFMA>
+__global__ __launch_bounds__(kBlock) void k_batch_fused(const FusedDesc* __restrict__ ds,
+                                                        const int64_t* __restrict__ boff,
+                                                        int count) {
+  const int p = find_problem(boff, count, blockIdx.x);
+  apply_fused_body<VT, FT, KT, MFMA>(ds[p], (int64_t)blockIdx.x - boff[p]);
+}
+
 // Middle block of the swept-in factorization: out[p][t][n] = sum_s Mdot[p][t][s] in[p][s][n]
+struct MidDesc {
+  const void* in;
+  void* out;
+  const void* mdot;
+  int kin, kout, nrhs;
+  int64_t total;
+};
+
 template <typename VT, typename FT>
-__global__ void k_apply_mid(const VT* __restrict__ in, VT* __restrict__ out,
-                            const FT* __restrict__ mdot, int kin, int kout, int nrhs,
-                            int64_t total) {
+__global__ __launch_bounds__(kBlock) void k_apply_mid(MidDesc d) {
+  const VT* __restrict__ in = reinterpret_cast<const VT*>(d.in);
+  VT* __restrict__ out = reinterpret_cast<VT*>(d.out);
+  const FT* __restrict__ mdot = reinterpret_cast<const FT*>(d.mdot);
+  const int kin = d.kin, kout = d.kout, nrhs = d.nrhs;
+  const int64_t total = d.total;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
   const int n = (int)(e % nrhs);
@@ -478,17 +545,31 @@ __global__ void k_apply_mid(const VT* __restrict__ in, VT* __restrict__ out,
 // U: per (X leaf a, RHS chunk): u[perm(x)][n] = sum_b sum_k Ubar[x][b][k] mu[(a,b)][k][n]
 // LDS: mu_leaf[2^l0][K][NB], and when it fits ubar_leaf[smax][2^l0 K + 1] (padded rows).
 // ---------------------------------------------------------------------------
+struct UDesc {
+  const void* mu;
+  void* u;
+  int64_t ldu;
+  const int32_t* perm_x;
+  const int32_t* xoff;
+  const void* ubar;
+  int l0, K, nrhs, NB, nchunk, smax, stage_f;
+};
+
 template <typename VT, typename FT>
-__global__ __launch_bounds__(kBlock) void k_apply_u(
-    const VT* __restrict__ mu, VT* __restrict__ u, int64_t ldu, const int32_t* __restrict__ perm_x,
-    const int32_t* __restrict__ xoff, const FT* __restrict__ ubar, int l0, int K, int nrhs,
-    int NB, int nchunk, int smax, int stage_factor) {
+__device__ __forceinline__ void apply_u_body(const UDesc& d, int64_t lb) {
   extern __shared__ __align__(16) unsigned char smem[];
+  const VT* __restrict__ mu = reinterpret_cast<const VT*>(d.mu);
+  VT* __restrict__ u = reinterpret_cast<VT*>(d.u);
+  const FT* __restrict__ ubar = reinterpret_cast<const FT*>(d.ubar);
+  const int32_t* __restrict__ perm_x = d.perm_x;
+  const int32_t* __restrict__ xoff = d.xoff;
+  const int64_t ldu = d.ldu;
+  const int l0 = d.l0, K = d.K, nrhs = d.nrhs, NB = d.NB, nchunk = d.nchunk;
+  const int stage_factor = d.stage_f;
   const int nb = 1 << l0;
   const int urow = nb * K + 1;
   VT* ml = reinterpret_cast<VT*>(smem);                       // [nb][K][NB]
   VT* ul = ml + (size_t)nb * K * NB;                          // [smax][urow] if staged
-  const int64_t lb = xcd_logical_block((int64_t)gridDim.x);
   const int64_t a = lb / nchunk;
   const int chunk = (int)(lb % nchunk);
   const int nb0 = chunk * NB;
@@ -528,6 +609,17 @@ __global__ __launch_bounds__(kBlock) void k_apply_u(
     }
     u[(int64_t)(nb0 + n) * ldu + perm_x[x0 + x]] = acc;
   }
+}
+
+template <typename VT, typename FT>
+__global__ __launch_bounds__(kBlock) void k_apply_u(UDesc d) {
+  apply_u_body<VT, FT>(d, xcd_logical_block((int64_t)gridDim.x));
+}
+template <typename VT, typename FT>
+__global__ __launch_bounds__(kBlock) void k_batch_u(const UDesc* __restrict__ ds,
+                                                    const int64_t* __restrict__ boff, int count) {
+  const int p = find_problem(boff, count, blockIdx.x);
+  apply_u_body<VT, FT>(ds[p], (int64_t)blockIdx.x - boff[p]);
 }
 
 inline unsigned nblocks(int64_t total) { return (unsigned)((total + kBlock - 1) / kBlock); }
@@ -586,12 +678,53 @@ struct LaunchTimer {
 
 inline int even_kt(int k) { return std::min(16, std::max(2, (k + 1) & ~1)); }
 
+// One kernel launch of an apply, with everything it needs.
+enum LaunchKind { kLaunchV = 0, kLaunchFused = 1, kLaunchMid = 2, kLaunchU = 3 };
+struct Launch {
+  LaunchKind kind;
+  int kt = 2;
+  bool mfma = false;
+  size_t lds = 0;
+  int64_t nblocks = 0;
+  double flops = 0, bytes = 0;
+  VDesc v{};
+  FusedDesc f{};
+  MidDesc m{};
+  UDesc u{};
+};
+
+inline const char* launch_name(const Launch& x) {
+  switch (x.kind) {
+    case kLaunchV: return "apply_v";
+    case kLaunchFused: return x.mfma ? "apply_fused_mfma" : "apply_fused";
+    case kLaunchMid: return "apply_mid";
+    default: return "apply_u";
+  }
+}
+
+// Per-block LDS limit of the device (queried once per device).
+inline int lds_limit(int device, int* out) {
+  static int lds_max[64] = {0};
+  int& lmax = lds_max[device & 63];
+  if (!lmax) {
+    int v = 0;
+    IBF_HIP_CHECK(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+    lmax = v > 0 ? v : 65536;
+  }
+  *out = lmax;
+  return IBF_OK;
+}
+
+// The launch sequence of one apply of plan p: V, the fused butterfly stage
+// groups (with the swept-in middle block between the two halves), U.
+// Allocates the plan's ping-pong coefficient buffers when they are too small
+// for nrhs, so it must run outside any graph capture.
 template <typename VT, typename FT>
-int apply_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int64_t nrhs64,
-            hipStream_t s, ibf_profile* prof) {
+int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int nrhs,
+                  std::vector<Launch>& seq) {
+  seq.clear();
   const Geo& geo = p->geo;
   const int L = geo.L, l0 = geo.l0, h = geo.h;
-  const int nrhs = (int)nrhs64;
   const bool swept = p->d_mdot != nullptr;
   // stored rank of level l on the V/H side (l <= h) or the G/U side (l >= h);
   // they differ only at l = h, and only after the sweep-in
@@ -615,17 +748,10 @@ int apply_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int6
     IBF_HIP_CHECK(hipMalloc(&p->d_work[1], need));
     p->work_bytes = need;
   }
-  VT* w[2] = {(VT*)p->d_work[0], (VT*)p->d_work[1]};
-  LaunchTimer T(prof, s);
+  void* w[2] = {p->d_work[0], p->d_work[1]};
   const double fb = (double)sizeof(FT), vb = (double)sizeof(VT);
-  // Per-block LDS limit of the device (queried once per device).
-  static int lds_max[64] = {0};
-  int& lmax = lds_max[p->device & 63];
-  if (!lmax) {
-    int v = 0;
-    IBF_HIP_CHECK(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
-    lmax = v > 0 ? v : 65536;
-  }
+  int lmax = 0, rc;
+  if ((rc = lds_limit(p->device, &lmax))) return rc;
   const size_t budget_mfma = std::min<size_t>(kLdsBudgetMfma, (size_t)lmax);
   // Multi-RHS FP32 stages run on MFMA with 64-column chunks; otherwise the
   // vector kernels take chunks of up to 32 columns.
@@ -633,46 +759,43 @@ int apply_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int6
   const int NB = mfma ? 64 : std::min(nrhs, 32);
   const int nchunk = (nrhs + NB - 1) / NB;
   const int NBo = std::min(nrhs, 32);                         // outer (V, U) kernels
-  int rc;
   // V
   {
+    Launch x;
+    x.kind = kLaunchV;
     const int K = p->k_vbar;
-    const int KT = even_kt(K);
+    x.kt = even_kt(K);
     int NBv = NBo;
     while (NBv > 1 && (size_t)p->smax_xi * NBv * sizeof(VT) > kLdsBudget / 2) NBv /= 2;
     const int nchv = (nrhs + NBv - 1) / NBv;
     const size_t base = (size_t)p->smax_xi * NBv * sizeof(VT);
-    const size_t fac = (size_t)p->smax_xi * (1 << l0) * KT * sizeof(VT);
+    const size_t fac = (size_t)p->smax_xi * (1 << l0) * x.kt * sizeof(VT);
     if (base > kLdsBudget) {
       set_error("ibf_apply: an Omega leaf holds too many points for the apply kernels");
       return IBF_ERR_UNSUPPORTED;
     }
     const int stage_f = base + fac <= kLdsBudget ? 1 : 0;
-    const size_t lds = base + (stage_f ? fac : 0);
-    if ((rc = T.begin())) return rc;
-#define IBF_LAUNCH_V(KTC)                                                                      \
-  hipLaunchKernelGGL((k_apply_v<VT, FT, KTC>), dim3((unsigned)(p->nleaf * nchv)), dim3(kBlock), \
-                     lds, s, (const VT*)g, ldg, p->d_perm_xi, p->d_xioff, (const FT*)p->d_vbar, \
-                     w[0], L, l0, K, nrhs, NBv, nchv, p->smax_xi, stage_f)
-    IBF_DISPATCH_KT(KT, IBF_LAUNCH_V);
-#undef IBF_LAUNCH_V
+    x.lds = base + (stage_f ? fac : 0);
+    x.nblocks = p->nleaf * nchv;
+    x.v = VDesc{g, ldg, p->d_perm_xi, p->d_xioff, p->d_vbar, w[0], L, l0, K, nrhs, NBv, nchv,
+                p->smax_xi, stage_f};
     const double nnz = (double)p->nnz_vbar;
-    if ((rc = T.end("apply_v", 8.0 * nnz * nrhs,
-                    nnz * fb + vb * nrhs * ((double)p->nxi + (double)p->npairs * K))))
-      return rc;
+    x.flops = 8.0 * nnz * nrhs;
+    x.bytes = nnz * fb + vb * nrhs * ((double)p->nxi + (double)p->npairs * K);
+    seq.push_back(x);
   }
   int cur = 0;
-  auto launch_mid = [&]() -> int {
+  auto add_mid = [&]() {
+    Launch x;
+    x.kind = kLaunchMid;
     const int64_t total = p->npairs * p->k_mid_g * nrhs;
-    int rc2;
-    if ((rc2 = T.begin())) return rc2;
-    hipLaunchKernelGGL((k_apply_mid<VT, FT>), dim3(nblocks(total)), dim3(kBlock), 0, s, w[cur],
-                       w[cur ^ 1], (const FT*)p->d_mdot, p->k_mid_h, p->k_mid_g, nrhs, total);
+    x.nblocks = (total + kBlock - 1) / kBlock;
+    x.m = MidDesc{w[cur], w[cur ^ 1], p->d_mdot, p->k_mid_h, p->k_mid_g, nrhs, total};
     const double nnz = (double)p->npairs * p->k_mid_g * p->k_mid_h;
-    const double vec = (double)p->npairs * (p->k_mid_g + p->k_mid_h) * nrhs * vb;
-    if ((rc2 = T.end("apply_mid", 8.0 * nnz * nrhs, nnz * fb + vec))) return rc2;
+    x.flops = 8.0 * nnz * nrhs;
+    x.bytes = nnz * fb + (double)p->npairs * (p->k_mid_g + p->k_mid_h) * nrhs * vb;
+    seq.push_back(x);
     cur ^= 1;
-    return IBF_OK;
   };
   // LDS bytes of a fused group of 2^k pairs: state [2^k][kmaxg][NB] + factors
   // [2^k][2 kmaxg kld] with kld <= kt, + kt entries of slack (the compute loops
@@ -680,7 +803,7 @@ int apply_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int6
   auto fused_lds = [&](int kk, int kmg, int kt) -> size_t {
     return (((size_t)1 << kk) * ((size_t)kmg * NB + (size_t)2 * kmg * kt) + kt) * sizeof(VT);
   };
-  auto run_stages = [&](int lo, int hi, bool gside) -> int {   // output levels lo..hi
+  auto add_stages = [&](int lo, int hi, bool gside) {   // output levels lo..hi
     int l = lo;
     while (l <= hi) {
       int kk = 1;
@@ -695,7 +818,10 @@ int apply_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int6
         if (fused_lds(next, km, even_kt(km)) > (mfma ? budget_mfma : kLdsBudget)) break;
         kk = next;
       }
-      FusedArgs A{};
+      Launch x;
+      x.kind = kLaunchFused;
+      x.mfma = mfma;
+      FusedArgs& A = x.f.A;
       A.L = L;
       A.l_start = l;
       A.nst = kk;
@@ -716,43 +842,29 @@ int apply_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int6
         A.kld[j] = st.k_ld;
         nnz += (double)st.nnz;
       }
-      const int KT = even_kt(kom);
-      const double vec = (double)p->npairs * (A.ranks[0] + A.ranks[kk]) * nrhs * vb;
-      const size_t lds = fused_lds(kk, km, KT);
-      const int64_t ngroups = p->npairs >> kk;
-      const unsigned grid = (unsigned)(ngroups * nchunk);
-      int rc2;
-      if ((rc2 = T.begin())) return rc2;
-      if (mfma) {
-        if constexpr (sizeof(VT) == 8) {
-#define IBF_LAUNCH_FM(KTC) \
-  hipLaunchKernelGGL((k_apply_fused<VT, FT, KTC, true>), dim3(grid), dim3(kBlock), lds, s, w[cur], w[cur ^ 1], A)
-          IBF_DISPATCH_KT(KT, IBF_LAUNCH_FM);
-#undef IBF_LAUNCH_FM
-        }
-      } else {
-#define IBF_LAUNCH_FV(KTC) \
-  hipLaunchKernelGGL((k_apply_fused<VT, FT, KTC, false>), dim3(grid), dim3(kBlock), lds, s, w[cur], w[cur ^ 1], A)
-        IBF_DISPATCH_KT(KT, IBF_LAUNCH_FV);
-#undef IBF_LAUNCH_FV
-      }
-      if ((rc2 = T.end(mfma ? "apply_fused_mfma" : "apply_fused", 8.0 * nnz * nrhs,
-                       nnz * fb + vec)))
-        return rc2;
+      x.kt = even_kt(kom);
+      x.lds = fused_lds(kk, km, x.kt);
+      x.nblocks = (p->npairs >> kk) * nchunk;
+      x.f.in = w[cur];
+      x.f.out = w[cur ^ 1];
+      x.flops = 8.0 * nnz * nrhs;
+      x.bytes = nnz * fb + (double)p->npairs * (A.ranks[0] + A.ranks[kk]) * nrhs * vb;
+      seq.push_back(x);
       cur ^= 1;
       l += kk;
     }
-    return IBF_OK;
   };
   if (swept) {
-    if ((rc = run_stages(l0 + 1, h, false))) return rc;
-    if ((rc = launch_mid())) return rc;
-    if ((rc = run_stages(h + 1, L - l0, true))) return rc;
+    add_stages(l0 + 1, h, false);
+    add_mid();
+    add_stages(h + 1, L - l0, true);
   } else {
-    if ((rc = run_stages(l0 + 1, L - l0, true))) return rc;
+    add_stages(l0 + 1, L - l0, true);
   }
   // U
   {
+    Launch x;
+    x.kind = kLaunchU;
     const int K = p->k_ubar;
     int NBu = NBo;
     while (NBu > 1 && (size_t)(1 << l0) * K * NBu * sizeof(VT) > kLdsBudget / 2) NBu /= 2;
@@ -764,18 +876,316 @@ int apply_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int6
       return IBF_ERR_UNSUPPORTED;
     }
     const int stage_f = base + fac <= kLdsBudget ? 1 : 0;
-    const size_t lds = base + (stage_f ? fac : 0);
-    if ((rc = T.begin())) return rc;
-    hipLaunchKernelGGL((k_apply_u<VT, FT>), dim3((unsigned)(p->nleaf * nchu)), dim3(kBlock),
-                       lds, s, w[cur], (VT*)u, ldu, p->d_perm_x, p->d_xoff, (const FT*)p->d_ubar,
-                       l0, K, nrhs, NBu, nchu, p->smax_x, stage_f);
+    x.lds = base + (stage_f ? fac : 0);
+    x.nblocks = p->nleaf * nchu;
+    x.u = UDesc{w[cur], u, ldu, p->d_perm_x, p->d_xoff, p->d_ubar, l0, K, nrhs, NBu, nchu,
+                p->smax_x, stage_f};
     const double nnz = (double)p->nnz_ubar;
-    if ((rc = T.end("apply_u", 8.0 * nnz * nrhs,
-                    nnz * fb + vb * nrhs * ((double)p->nx + (double)p->npairs * K))))
-      return rc;
+    x.flops = 8.0 * nnz * nrhs;
+    x.bytes = nnz * fb + vb * nrhs * ((double)p->nx + (double)p->npairs * K);
+    seq.push_back(x);
+  }
+  return IBF_OK;
+}
+
+template <typename VT, typename FT>
+int launch_one(const Launch& x, hipStream_t s) {
+  const dim3 grid((unsigned)x.nblocks), blk(kBlock);
+  switch (x.kind) {
+    case kLaunchV:
+#define IBF_LAUNCH_V(KTC) hipLaunchKernelGGL((k_apply_v<VT, FT, KTC>), grid, blk, x.lds, s, x.v)
+      IBF_DISPATCH_KT(x.kt, IBF_LAUNCH_V);
+#undef IBF_LAUNCH_V
+      break;
+    case kLaunchFused:
+      if (x.mfma) {
+        if constexpr (sizeof(VT) == 8) {
+#define IBF_LAUNCH_FM(KTC) \
+  hipLaunchKernelGGL((k_apply_fused<VT, FT, KTC, true>), grid, blk, x.lds, s, x.f)
+          IBF_DISPATCH_KT(x.kt, IBF_LAUNCH_FM);
+#undef IBF_LAUNCH_FM
+        }
+      } else {
+#define IBF_LAUNCH_FV(KTC) \
+  hipLaunchKernelGGL((k_apply_fused<VT, FT, KTC, false>), grid, blk, x.lds, s, x.f)
+        IBF_DISPATCH_KT(x.kt, IBF_LAUNCH_FV);
+#undef IBF_LAUNCH_FV
+      }
+      break;
+    case kLaunchMid:
+      hipLaunchKernelGGL((k_apply_mid<VT, FT>), grid, blk, 0, s, x.m);
+      break;
+    default:
+      hipLaunchKernelGGL((k_apply_u<VT, FT>), grid, blk, x.lds, s, x.u);
+      break;
   }
   IBF_HIP_CHECK(hipGetLastError());
+  return IBF_OK;
+}
+
+template <typename VT, typename FT>
+int apply_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int64_t nrhs,
+            hipStream_t s, ibf_profile* prof) {
+  std::vector<Launch> seq;
+  int rc;
+  if ((rc = make_schedule<VT, FT>(p, g, ldg, u, ldu, (int)nrhs, seq))) return rc;
+  LaunchTimer T(prof, s);
+  for (const Launch& x : seq) {
+    if ((rc = T.begin())) return rc;
+    if ((rc = launch_one<VT, FT>(x, s))) return rc;
+    if ((rc = T.end(launch_name(x), x.flops, x.bytes))) return rc;
+  }
   return T.finish();
+}
+
+// ---------------------------------------------------------------------------
+// Batched apply of many plans (uneven sizes and RHS counts).  Phase i of the
+// batch holds launch i of every plan's sequence that has one: V for all, then
+// the fused stage groups in order, then U for all (a plan with fewer groups
+// waits for the U phase).  Each phase is one launch over the concatenated
+// blocks of its plans; a block finds its plan by binary search over the
+// per-plan block offsets.  The descriptors live in a device table written
+// before each apply, so a captured graph of the phase launches replays for new
+// vectors of the same RHS counts without recapture.
+// ---------------------------------------------------------------------------
+struct BatchPhase {
+  LaunchKind kind;
+  bool mfma;
+  int kt, count;
+  size_t lds;
+  int64_t nblocks;
+  size_t desc_off, boff_off;                                 // byte offsets in the table
+};
+
+}  // namespace
+}  // namespace ibf
+
+struct ibf_batch_s {
+  std::vector<ibf_plan_t> plans;
+  int device = 0, precision = 0;
+  hipStream_t cap = nullptr;                                 // capture stream
+  void* d_table = nullptr;
+  void* h_table = nullptr;                                   // pinned staging
+  size_t table_cap = 0;
+  hipEvent_t table_ev = nullptr;
+  bool table_pending = false;
+  std::vector<ibf::BatchPhase> phases;
+  std::vector<int64_t> graph_key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace ibf {
+namespace {
+
+inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
+
+template <typename VT, typename FT>
+int launch_phase(const ibf_batch_s* b, const BatchPhase& ph, hipStream_t s) {
+  const char* base = static_cast<const char*>(b->d_table);
+  const int64_t* boff = reinterpret_cast<const int64_t*>(base + ph.boff_off);
+  const dim3 grid((unsigned)ph.nblocks), blk(kBlock);
+  switch (ph.kind) {
+    case kLaunchV: {
+      const VDesc* ds = reinterpret_cast<const VDesc*>(base + ph.desc_off);
+#define IBF_LAUNCH_BV(KTC) \
+  hipLaunchKernelGGL((k_batch_v<VT, FT, KTC>), grid, blk, ph.lds, s, ds, boff, ph.count)
+      IBF_DISPATCH_KT(ph.kt, IBF_LAUNCH_BV);
+#undef IBF_LAUNCH_BV
+      break;
+    }
+    case kLaunchFused: {
+      const FusedDesc* ds = reinterpret_cast<const FusedDesc*>(base + ph.desc_off);
+      if (ph.mfma) {
+        if constexpr (sizeof(VT) == 8) {
+#define IBF_LAUNCH_BFM(KTC) \
+  hipLaunchKernelGGL((k_batch_fused<VT, FT, KTC, true>), grid, blk, ph.lds, s, ds, boff, ph.count)
+          IBF_DISPATCH_KT(ph.kt, IBF_LAUNCH_BFM);
+#undef IBF_LAUNCH_BFM
+        }
+      } else {
+#define IBF_LAUNCH_BFV(KTC) \
+  hipLaunchKernelGGL((k_batch_fused<VT, FT, KTC, false>), grid, blk, ph.lds, s, ds, boff, ph.count)
+        IBF_DISPATCH_KT(ph.kt, IBF_LAUNCH_BFV);
+#undef IBF_LAUNCH_BFV
+      }
+      break;
+    }
+    case kLaunchU: {
+      const UDesc* ds = reinterpret_cast<const UDesc*>(base + ph.desc_off);
+      hipLaunchKernelGGL((k_batch_u<VT, FT>), grid, blk, ph.lds, s, ds, boff, ph.count);
+      break;
+    }
+    default:
+      set_error("ibf_apply_batch: internal error (unexpected launch kind)");
+      return IBF_ERR_DEVICE;
+  }
+  IBF_HIP_CHECK(hipGetLastError());
+  return IBF_OK;
+}
+
+template <typename VT, typename FT>
+int apply_batch_t(ibf_batch_s* b, const void* const* g, const int64_t* ldg, void* const* u,
+                  const int64_t* ldu, const int64_t* nrhs, int use_graph, hipStream_t s) {
+  const int count = (int)b->plans.size();
+  std::vector<std::vector<Launch>> seqs(count);
+  int rc;
+  size_t nmax = 0;
+  for (int i = 0; i < count; ++i) {
+    if ((rc = make_schedule<VT, FT>(b->plans[i], g[i], ldg[i], u[i], ldu[i], (int)nrhs[i],
+                                    seqs[i])))
+      return rc;
+    for (const Launch& x : seqs[i])
+      if (x.kind == kLaunchMid) {
+        set_error("ibf_apply_batch: plans built with the sweep-in are not batched");
+        return IBF_ERR_UNSUPPORTED;
+      }
+    nmax = std::max(nmax, seqs[i].size());
+  }
+  // phase membership: V (launch 0), fused launch j (1..), U (last launch)
+  std::vector<std::vector<const Launch*>> members;
+  auto add_phase_members = [&](auto pick) {
+    std::vector<const Launch*> mf, mv;
+    for (int i = 0; i < count; ++i) {
+      const Launch* x = pick(seqs[i]);
+      if (!x) continue;
+      (x->mfma ? mf : mv).push_back(x);
+    }
+    if (!mv.empty()) members.push_back(mv);
+    if (!mf.empty()) members.push_back(mf);
+  };
+  add_phase_members([](const std::vector<Launch>& q) { return &q.front(); });
+  for (size_t j = 1; j + 1 < nmax; ++j)
+    add_phase_members([j](const std::vector<Launch>& q) -> const Launch* {
+      return j + 1 < q.size() ? &q[j] : nullptr;
+    });
+  add_phase_members([](const std::vector<Launch>& q) { return &q.back(); });
+  // Table layout.  A phase runs every member at the phase's largest KT, so
+  // the members' LDS footprints are recomputed at that KT: the V body stages
+  // Vbar rows KT wide (when they fit), the fused body reads KT-wide rows.
+  int lmax = 0;
+  if ((rc = lds_limit(b->device, &lmax))) return rc;
+  std::vector<BatchPhase> phases;
+  std::vector<std::vector<Launch>> adj(members.size());
+  size_t bytes = 0;
+  for (size_t q = 0; q < members.size(); ++q) {
+    const auto& m = members[q];
+    BatchPhase ph{};
+    ph.kind = m[0]->kind;
+    ph.mfma = m[0]->mfma;
+    ph.count = (int)m.size();
+    const size_t dsz = ph.kind == kLaunchV ? sizeof(VDesc)
+                       : ph.kind == kLaunchU ? sizeof(UDesc) : sizeof(FusedDesc);
+    ph.desc_off = bytes;
+    bytes = align16(bytes + dsz * m.size());
+    ph.boff_off = bytes;
+    bytes = align16(bytes + sizeof(int64_t) * (m.size() + 1));
+    for (const Launch* x : m) {
+      ph.kt = std::max(ph.kt, x->kt);
+      ph.nblocks += x->nblocks;
+    }
+    for (const Launch* x : m) {
+      Launch y = *x;
+      if (y.kind == kLaunchV) {
+        const size_t base = (size_t)y.v.smax * y.v.NB * sizeof(VT);
+        const size_t fac = (size_t)y.v.smax * ((size_t)1 << y.v.l0) * ph.kt * sizeof(VT);
+        y.v.stage_f = base + fac <= kLdsBudget ? 1 : 0;
+        y.lds = base + (y.v.stage_f ? fac : 0);
+      } else if (y.kind == kLaunchFused) {
+        const FusedArgs& A = y.f.A;
+        const size_t nbv = y.mfma ? 64 : (size_t)A.NB;
+        y.lds = (((size_t)1 << A.nst) * ((size_t)A.kmaxg * nbv + (size_t)2 * A.kmaxg * ph.kt) +
+                 ph.kt) * sizeof(VT);
+      }
+      ph.lds = std::max(ph.lds, y.lds);
+      adj[q].push_back(y);
+    }
+    if (ph.nblocks > 0x7fffffff || ph.lds > (size_t)lmax) {
+      set_error("ibf_apply_batch: a phase exceeds the grid or LDS limits of one launch");
+      return IBF_ERR_UNSUPPORTED;
+    }
+    phases.push_back(ph);
+  }
+  if (bytes > b->table_cap) {
+    if (b->table_pending) IBF_HIP_CHECK(hipEventSynchronize(b->table_ev));
+    b->table_pending = false;
+    if (b->d_table) IBF_HIP_CHECK(hipFree(b->d_table));
+    if (b->h_table) IBF_HIP_CHECK(hipHostFree(b->h_table));
+    b->d_table = b->h_table = nullptr;
+    b->table_cap = 0;
+    IBF_HIP_CHECK(hipMalloc(&b->d_table, bytes));
+    IBF_HIP_CHECK(hipHostMalloc(&b->h_table, bytes, hipHostMallocDefault));
+    b->table_cap = bytes;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_key.clear();
+  }
+  // the previous apply's table copy must have left the staging buffer
+  if (b->table_pending) IBF_HIP_CHECK(hipEventSynchronize(b->table_ev));
+  char* h = static_cast<char*>(b->h_table);
+  for (size_t q = 0; q < phases.size(); ++q) {
+    const auto& m = adj[q];
+    int64_t* boff = reinterpret_cast<int64_t*>(h + phases[q].boff_off);
+    int64_t acc = 0;
+    for (size_t i = 0; i < m.size(); ++i) {
+      boff[i] = acc;
+      acc += m[i].nblocks;
+      char* dst = h + phases[q].desc_off;
+      switch (phases[q].kind) {
+        case kLaunchV: reinterpret_cast<VDesc*>(dst)[i] = m[i].v; break;
+        case kLaunchU: reinterpret_cast<UDesc*>(dst)[i] = m[i].u; break;
+        default: reinterpret_cast<FusedDesc*>(dst)[i] = m[i].f; break;
+      }
+    }
+    boff[m.size()] = acc;
+  }
+  IBF_HIP_CHECK(hipMemcpyAsync(b->d_table, b->h_table, bytes, hipMemcpyHostToDevice, s));
+  IBF_HIP_CHECK(hipEventRecord(b->table_ev, s));
+  b->table_pending = true;
+  b->phases = phases;
+  if (!use_graph) {
+    for (const BatchPhase& ph : phases)
+      if ((rc = launch_phase<VT, FT>(b, ph, s))) return rc;
+    return IBF_OK;
+  }
+  // graph of the phase launches, keyed by everything that shapes them
+  std::vector<int64_t> key;
+  key.push_back((int64_t)(uintptr_t)b->d_table);
+  for (const BatchPhase& ph : phases) {
+    key.push_back(ph.kind);
+    key.push_back(ph.mfma);
+    key.push_back(ph.kt);
+    key.push_back(ph.count);
+    key.push_back((int64_t)ph.lds);
+    key.push_back(ph.nblocks);
+    key.push_back((int64_t)ph.desc_off);
+    key.push_back((int64_t)ph.boff_off);
+  }
+  if (!b->exec || key != b->graph_key) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_key.clear();
+    IBF_HIP_CHECK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    int lrc = IBF_OK;
+    for (const BatchPhase& ph : phases)
+      if ((lrc = launch_phase<VT, FT>(b, ph, b->cap))) break;
+    hipGraph_t gr = nullptr;
+    const hipError_t ec = hipStreamEndCapture(b->cap, &gr);
+    if (lrc) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return lrc;
+    }
+    IBF_HIP_CHECK(ec);
+    b->graph = gr;
+    IBF_HIP_CHECK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->graph_key = key;
+  }
+  IBF_HIP_CHECK(hipGraphLaunch(b->exec, s));
+  return IBF_OK;
 }
 
 }  // namespace
@@ -795,3 +1205,87 @@ int apply_plan(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, i
 }
 
 }  // namespace ibf
+
+extern "C" {
+
+int ibf_batch_create(const ibf_plan_t* plans, int count, ibf_batch_t* out) {
+  if (!out) {
+    ibf::set_error("ibf_batch_create: NULL output");
+    return IBF_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  if (!plans || count < 1) {
+    ibf::set_error("ibf_batch_create: no plans");
+    return IBF_ERR_INVALID_ARG;
+  }
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i] || !plans[i]->built) {
+      ibf::set_error("ibf_batch_create: plan " + std::to_string(i) + " is NULL or not built");
+      return IBF_ERR_INVALID_ARG;
+    }
+    if (plans[i]->precision != plans[0]->precision || plans[i]->device != plans[0]->device) {
+      ibf::set_error("ibf_batch_create: plans differ in precision or device");
+      return IBF_ERR_INVALID_ARG;
+    }
+  }
+  ibf_batch_s* b = new ibf_batch_s;
+  b->plans.assign(plans, plans + count);
+  b->device = plans[0]->device;
+  b->precision = plans[0]->precision;
+  auto fail = [&](hipError_t e) {
+    ibf::set_error(std::string("ibf_batch_create: ") + hipGetErrorString(e));
+    ibf_batch_destroy(b);
+    return IBF_ERR_DEVICE;
+  };
+  hipError_t e = hipSetDevice(b->device);
+  if (e != hipSuccess) return fail(e);
+  if ((e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess) return fail(e);
+  if ((e = hipEventCreateWithFlags(&b->table_ev, hipEventDisableTiming)) != hipSuccess)
+    return fail(e);
+  *out = b;
+  return IBF_OK;
+}
+
+int ibf_apply_batch(ibf_batch_t b, const void* const* g, const int64_t* ldg, void* const* u,
+                    const int64_t* ldu, const int64_t* nrhs, int flags, void* hip_stream) {
+  if (!b || !g || !ldg || !u || !ldu || !nrhs) {
+    ibf::set_error("ibf_apply_batch: NULL argument");
+    return IBF_ERR_INVALID_ARG;
+  }
+  for (size_t i = 0; i < b->plans.size(); ++i) {
+    const ibf_plan_t p = b->plans[i];
+    if (!g[i] || !u[i] || nrhs[i] < 1 || nrhs[i] > (1 << 20) || ldg[i] < p->nxi ||
+        ldu[i] < p->nx) {
+      ibf::set_error("ibf_apply_batch: bad vector, leading dimension or nrhs for plan " +
+                     std::to_string(i));
+      return IBF_ERR_INVALID_ARG;
+    }
+  }
+  IBF_HIP_CHECK(hipSetDevice(b->device));
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int graph = (flags & IBF_BATCH_GRAPH) ? 1 : 0;
+  switch (b->precision) {
+    case IBF_FP64:
+      return ibf::apply_batch_t<double2, double2>(b, g, ldg, u, ldu, nrhs, graph, s);
+    case IBF_FP32:
+      return ibf::apply_batch_t<float2, float2>(b, g, ldg, u, ldu, nrhs, graph, s);
+    default:
+      return ibf::apply_batch_t<float2, ibf::bf16x2c>(b, g, ldg, u, ldu, nrhs, graph, s);
+  }
+}
+
+int ibf_batch_destroy(ibf_batch_t b) {
+  if (!b) return IBF_OK;
+  (void)hipSetDevice(b->device);
+  if (b->table_pending && b->table_ev) (void)hipEventSynchronize(b->table_ev);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->table_ev) (void)hipEventDestroy(b->table_ev);
+  if (b->d_table) (void)hipFree(b->d_table);
+  if (b->h_table) (void)hipHostFree(b->h_table);
+  delete b;
+  return IBF_OK;
+}
+
+}  // extern "C"

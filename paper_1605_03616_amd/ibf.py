@@ -21,7 +21,9 @@ IBF_OK = 0
 ERRORS = {-1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "OOM", -4: "DEVICE", -5: "NOT_BUILT"}
 
 EXPORTED = ["ibf_plan", "ibf_build", "ibf_apply", "ibf_apply_profile", "ibf_query",
-            "ibf_destroy", "ibf_last_error", "ibf_eval_kernel"]
+            "ibf_destroy", "ibf_last_error", "ibf_eval_kernel", "ibf_batch_create",
+            "ibf_apply_batch", "ibf_batch_destroy"]
+BATCH_GRAPH = 1
 PROFILE_MAX = 64
 
 
@@ -101,8 +103,14 @@ def load(path: str = LIB_PATH):
     lib.ibf_last_error.restype = C.c_char_p
     lib.ibf_eval_kernel.argtypes = [C.c_int, C.POINTER(C.c_double), C.c_int, C.c_void_p,
                                     C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+    lib.ibf_batch_create.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_void_p)]
+    lib.ibf_apply_batch.argtypes = [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_int64), C.c_int, C.c_void_p]
+    lib.ibf_batch_destroy.argtypes = [C.c_void_p]
     for name in ("ibf_plan", "ibf_build", "ibf_apply", "ibf_apply_profile", "ibf_query",
-                 "ibf_destroy", "ibf_eval_kernel"):
+                 "ibf_destroy", "ibf_eval_kernel", "ibf_batch_create", "ibf_apply_batch",
+                 "ibf_batch_destroy"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -234,6 +242,50 @@ class Plan:
     def destroy(self):
         if getattr(self, "handle", None):
             self._lib.ibf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Batch:
+    """ibf_batch_create / ibf_apply_batch over built plans (kept alive here)."""
+
+    def __init__(self, plans):
+        self._lib = load()
+        self.plans = list(plans)
+        arr = (C.c_void_p * len(self.plans))(*[p.handle for p in self.plans])
+        h = C.c_void_p()
+        _check(self._lib.ibf_batch_create(arr, len(self.plans), C.byref(h)))
+        self.handle = h
+
+    def apply(self, gs, us=None, graph=True, stream=None):
+        """gs: list of device tensors (nrhs_i, n_xi_i); returns the list of u_i (nrhs_i, n_x_i)."""
+        import torch
+        n = len(self.plans)
+        if len(gs) != n:
+            raise ValueError("one g per plan")
+        if us is None:
+            us = [torch.empty((g.shape[0], p.n_x), dtype=g.dtype, device=g.device)
+                  for g, p in zip(gs, self.plans)]
+        for g, u, p in zip(gs, us, self.plans):
+            if g.dtype != p.vector_dtype() or not g.is_contiguous() or not u.is_contiguous():
+                raise ValueError("g and u must be contiguous tensors of the plans' complex dtype")
+        gp = (C.c_void_p * n)(*[g.data_ptr() for g in gs])
+        up = (C.c_void_p * n)(*[u.data_ptr() for u in us])
+        ldg = (C.c_int64 * n)(*[g.shape[1] for g in gs])
+        ldu = (C.c_int64 * n)(*[u.shape[1] for u in us])
+        nr = (C.c_int64 * n)(*[g.shape[0] for g in gs])
+        _check(self._lib.ibf_apply_batch(self.handle, gp, ldg, up, ldu, nr,
+                                         BATCH_GRAPH if graph else 0, _stream_handle(stream)))
+        return us
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            self._lib.ibf_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

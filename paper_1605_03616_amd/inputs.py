@@ -146,13 +146,13 @@ def workload_nudft_1m(n: int = 1 << 20, nrhs: int = 16,
                         sweep_in=1, name=f"nudft_n{n}_r10")
 
 
-def batched_sizes(count: int = 256, seed: int = 3):
-    """Uneven batch: N = round(2^U), U ~ U(10,16), bumped to even; nrhs in 1..8.
+def batched_sizes(count: int = 256, seed: int = 3, lo: float = 10.0, hi: float = 16.0):
+    """Uneven batch: N = round(2^U), U ~ U(lo,hi), bumped to even; nrhs in 1..8.
 
-    Draw order: U = rng.uniform(10, 16, count), then nrhs = rng.integers(1, 9, count).
+    Draw order: U = rng.uniform(lo, hi, count), then nrhs = rng.integers(1, 9, count).
     """
     rng = np.random.default_rng(seed)
-    u = rng.uniform(10.0, 16.0, count)
+    u = rng.uniform(lo, hi, count)
     nrhs = rng.integers(1, 9, count)
     ns = np.round(2.0 ** u).astype(np.int64)
     ns = ns + (ns % 2)
@@ -165,3 +165,19 @@ def error_rows(n: int, count: int = 256, seed: int = 1234) -> np.ndarray:
         return np.arange(n)
     rng = np.random.default_rng(seed)
     return np.sort(rng.choice(n, size=count, replace=False))
+
+
+def workload_batched(count: int = 256, seed: int = 3, r: int = 12, lo: float = 10.0,
+                     hi: float = 16.0, precision: int = PREC_FP32) -> list:
+    """Uneven batch of independent 1-D FIO problems (uniform grids, phase as in
+    workload_fio1d_1k): sizes and RHS counts from batched_sizes(count, seed, lo,
+    hi); problem i draws its right-hand sides from default_rng(seed * 1000 + i)."""
+    ns, nrhs = batched_sizes(count, seed, lo, hi)
+    out = []
+    for i, (n, k) in enumerate(zip(ns.tolist(), nrhs.tolist())):
+        rng = np.random.default_rng(seed * 1000 + i)
+        g = complex_normal(n, k, rng)
+        out.append(Problem1D(f"batch{i}_fio1d_n{n}_r{r}", uniform_x(n), uniform_xi(n),
+                             PHASE_FIO1D, DEFAULT_PARAMS[PHASE_FIO1D], r, 1e-6, 16, k, g,
+                             precision))
+    return out
