@@ -10,7 +10,7 @@ the dense product on 256 sampled rows, the plain FP64 single-RHS apply rate,
 the roofline of the dominant kernel and the CPU oracle baseline.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-                       [--workload fio1d_64k|nudft_1m|fio1d_1k] [--no-cpu-baseline]
+                       [--workload fio1d_64k|nudft_1m|fio1d_1k|batched] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -77,12 +77,7 @@ def _cpu_baseline(P, nrhs_sample=4):
     """Time the FP64 oracle's IBF apply on the host: full oracle build (not
     timed), then the apply of `nrhs_sample` columns, scaled to the metric."""
     from oracle import ibf_oracle as O
-    try:
-        import threadpoolctl
-        info = threadpoolctl.threadpool_info()
-        cores = max([d.get("num_threads", 1) for d in info] or [1])
-    except Exception:
-        cores = os.cpu_count()
+    cores = _cores()
     t0 = time.perf_counter()
     prob, F, Op = O.build_optimal(P.phase, P.params, P.x, P.xi, P.r, P.tol, P.leaf)
     t_build = time.perf_counter() - t0
@@ -102,6 +97,99 @@ def _cpu_baseline(P, nrhs_sample=4):
     }
 
 
+def _bench_batched(args):
+    """Uneven batch of 256 1-D FIO problems, one graph-replayed batched apply per step."""
+    import torch
+    from oracle import ibf_oracle as O
+    from paper_1605_03616_amd import ibf
+    from paper_1605_03616_amd import inputs as I
+
+    ibf.load()
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    probs = I.workload_batched(count=args.batch_count, seed=3, r=args.batch_r)
+    print(f"[bench] batched workload: {len(probs)} problems, sum N = {sum(P.n for P in probs)}",
+          file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plans = [ibf.Plan.from_problem(P).build() for P in probs]
+    build_s = time.perf_counter() - t0
+    qs = [pl.query() for pl in plans]
+    gs = [torch.from_numpy(np.ascontiguousarray(P.g.T)).to(torch.complex64).cuda() for P in probs]
+    us = [torch.empty((P.nrhs, P.n), dtype=torch.complex64, device="cuda") for P in probs]
+    B = ibf.Batch(plans)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        B.apply(gs, us, graph=True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        B.apply(gs, us, graph=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    units = sum(P.n * P.nrhs for P in probs)
+    value = units / (ms * 1e-3) / 1e9
+    # algorithmic bytes: unpadded FP32 factors once + input and output samples
+    abytes = sum(8.0 * q["nnz_opt"] + 16.0 * P.n * P.nrhs for q, P in zip(qs, probs))
+    achieved = abytes / (ms * 1e-3) / 1e9
+    out = {
+        "metric": "IBF apply G(complex samples*RHS)/s at rel err 1e-5 vs plain FP64; build ms",
+        "value": round(value, 4),
+        "unit": "G(complex samples*RHS)/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched_fio1d_{len(probs)}_problems_r{args.batch_r}",
+                   "count": len(probs), "sum_N": sum(P.n for P in probs),
+                   "sum_N_x_nrhs": units, "tol": 1e-6, "parallelism": "single-gpu"},
+        "build_ms": round(sum(q["build_ms"] for q in qs), 3),
+        "build_wall_ms": round(build_s * 1e3, 3),
+        "nnz_opt": sum(q["nnz_opt"] for q in qs),
+        "roofline": {"kernel": "whole batched apply (graph of phase launches)", "bound": "hbm",
+                     "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_bytes_per_step": abytes},
+    }
+    if not args.no_accuracy:
+        worst = 0.0
+        for P, u in zip(probs, us):
+            rows = I.error_rows(P.n, count=64)
+            ud = O.dense_apply(P.phase, P.params, P.x, P.xi, P.g, rows=rows)
+            un = u.cpu().numpy().T[rows].astype(np.complex128)
+            worst = max(worst, O.rel_error(un, ud))
+        out["max_rel_err_vs_dense_sampled"] = worst
+    if not args.no_cpu_baseline:
+        small = [P for P in probs if P.n <= 2048][:8]
+        t_app = 0.0
+        for P in small:
+            _, _, Op = O.build_optimal(P.phase, P.params, P.x, P.xi, P.r, P.tol, P.leaf,
+                                       sweep_in_on=False)
+            t0 = time.perf_counter()
+            O.apply_optimal(Op, P.g)
+            t_app += time.perf_counter() - t0
+        su = sum(P.n * P.nrhs for P in small)
+        out["cpu_baseline"] = {"value": round(su / t_app / 1e9, 8),
+                               "unit": "G(complex samples*RHS)/s", "cores": _cores(),
+                               "kind": "oracle",
+                               "sample": f"numpy FP64 oracle IBF apply of the {len(small)} "
+                                         f"problems of the batch with N <= 2048 (build not timed)"}
+    B.destroy()
+    for pl in plans:
+        pl.destroy()
+    print(json.dumps(out), flush=True)
+
+
+def _cores():
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        return max([d.get("num_threads", 1) for d in info] or [1])
+    except Exception:
+        return os.cpu_count()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,11 +201,16 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 256 MiB elementwise copy first (HBM counter calibration)")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-r", type=int, default=12)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); "
               "the IBF path here is single-GPU", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        _bench_batched(args)
+        return
 
     import torch
 

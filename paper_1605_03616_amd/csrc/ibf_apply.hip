@@ -430,73 +430,44 @@ __device__ __forceinline__ void apply_fused_body(const FusedDesc& D, int64_t lb)
       }
     }
   } else {
+    // Few right-hand sides: the stage is a stream of factor blocks, each
+    // entry used by NB columns only.  One thread per output (slot, row t,
+    // column n), n fastest; it reads its factor row entries straight from HBM
+    // (the threads of one slot read whole rows together, and consecutive
+    // rows share cache lines) and the inputs from the LDS state, which
+    // ping-pongs between two buffers so that no output waits in registers.
+    VT* S1 = S + (size_t)nslot * kmaxg * NB;
+    const FastDiv divNB(NB);
+    __syncthreads();                                          // the gathered group is in S
     for (int j = 0; j < k; ++j) {
       const int l = A.l_start + j;
       const int kin = A.ranks[j], kout = A.ranks[j + 1], ke = A.kld[j];
       const int fs = 2 * kin * ke;
       const int rem = k - j - 1;
-      const FT* blk = reinterpret_cast<const FT*>(A.blk[j]);
-      for (int s0 = 0; s0 < nslot; s0 += 4) {
-        FactorBatch<4, VT, FT> fb;
-        fb.load(blk, fs, s0, nslot, j, rem, ap, bpp, L, l);
-        fb.store(F, fs, s0, nslot);
-      }
-      __syncthreads();
-      VT hold[2][KT];
-      int hslot[2], hn[2];
-      const int nitems = nslot * NB;
-#pragma unroll
-      for (int it = 0; it < 2; ++it) {
-        hslot[it] = -1;
-        hn[it] = 0;
-        const int item = threadIdx.x + it * kBlock;
-        if (item < nitems) {
-          const int nn = item % NB;
-          const int locp = item / NB;
-          const int loc0 = fused_in0(locp, rem);
-          VT acc[KT];
-#pragma unroll
-          for (int t = 0; t < KT; ++t) acc[t] = Zero<VT>::v();
-          for (int c = 0; c < 2; ++c) {
-            const VT* src = S + (size_t)(loc0 + c) * kmaxg * NB + nn;
-            const VT* fcol = F + (size_t)locp * fs + (size_t)c * kin * ke;
-            for (int s = 0; s < kin; ++s) {
-              const VT xv = src[s * NB];
-              const VT* fr = fcol + s * ke;
-#pragma unroll
-              for (int t = 0; t < KT; ++t) cfma(acc[t], fr[t], xv);
-            }
-          }
-#pragma unroll
-          for (int t = 0; t < KT; ++t) hold[it][t] = acc[t];
-          hslot[it] = locp;
-          hn[it] = nn;
+      const FT* __restrict__ blk = reinterpret_cast<const FT*>(A.blk[j]);
+      const VT* Sin = (j & 1) ? S1 : S;
+      VT* Sout = (j & 1) ? S : S1;
+      const bool last = j == k - 1;
+      const int items = nslot * kout * NB;
+      const FastDiv divK(kout);
+      for (int item = threadIdx.x; item < items; item += kBlock) {
+        int r, nn, locp, t;
+        divNB.divmod(item, r, nn);
+        divK.divmod(r, locp, t);
+        const int64_t pout = fused_pout(locp, j, rem, ap, bpp, L, l);
+        const FT* f = blk + pout * fs + t;
+        const VT* x = Sin + (size_t)fused_in0(locp, rem) * kmaxg * NB + nn;
+        VT acc = Zero<VT>::v();
+        for (int c = 0; c < 2; ++c) {
+          const FT* fc = f + c * kin * ke;
+          const VT* xc = x + (size_t)c * kmaxg * NB;
+#pragma unroll 4
+          for (int s2 = 0; s2 < kin; ++s2) cfma(acc, load_factor(fc, s2 * ke), xc[s2 * NB]);
         }
+        if (!last) Sout[(size_t)(locp * kmaxg + t) * NB + nn] = acc;
+        else if (nn < nbw) out[(pout * kout + t) * nrhs + nb0 + nn] = acc;
       }
-      __syncthreads();
-#pragma unroll
-      for (int it = 0; it < 2; ++it) {
-        if (hslot[it] >= 0) {
-          VT* dst = S + (size_t)hslot[it] * kmaxg * NB + hn[it];
-#pragma unroll
-          for (int t = 0; t < KT; ++t)
-            if (t < kout) dst[t * NB] = hold[it][t];
-        }
-      }
-      __syncthreads();
-    }
-    // store: final slot loc -> output pair (ap << (k + sh_end)) | (loc << sh_end) | bpp
-    const int kout = A.ranks[k];
-    const int rows = nslot * kout;
-    if (w < rstep && n < nbw) {
-      int loc = 0, t = w;
-      while (t >= kout) { t -= kout; ++loc; }
-      for (int r = w; r < rows; r += rstep) {
-        const int64_t pout = (ap << (k + sh_end)) | ((int64_t)loc << sh_end) | bpp;
-        out[(pout * kout + t) * nrhs + nb0 + n] = S[(size_t)(loc * kmaxg + t) * NB + n];
-        t += rstep;
-        while (t >= kout) { t -= kout; ++loc; }
-      }
+      if (!last) __syncthreads();
     }
   }
 }
@@ -800,7 +771,9 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
   // LDS bytes of a fused group of 2^k pairs: state [2^k][kmaxg][NB] + factors
   // [2^k][2 kmaxg kld] with kld <= kt, + kt entries of slack (the compute loops
   // read whole kt-wide rows; entries past a row feed only discarded outputs)
+  // (vector path: two state buffers [2^k][kmaxg][NB], no factors)
   auto fused_lds = [&](int kk, int kmg, int kt) -> size_t {
+    if (!mfma) return ((size_t)2 << kk) * kmg * NB * sizeof(VT);
     return (((size_t)1 << kk) * ((size_t)kmg * NB + (size_t)2 * kmg * kt) + kt) * sizeof(VT);
   };
   auto add_stages = [&](int lo, int hi, bool gside) {   // output levels lo..hi
@@ -812,9 +785,10 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
         if (l + next - 1 > hi) break;
         if (next > kMaxR - 1) break;
         if (next > L - l + 1) break;                          // group must fit the b bits
-        if (mfma ? (next > 3) : (((int64_t)1 << next) * NB > 2 * kBlock)) break;
         int km = 1;
         for (int j = 0; j <= next; ++j) km = std::max(km, rank_at(l - 1 + j, gside));
+        // MFMA: 8 slots for 4 waves; vector: at most 4 outputs per thread and stage
+        if (mfma ? (next > 3) : (((int64_t)1 << next) * km * NB > 4 * kBlock)) break;
         if (fused_lds(next, km, even_kt(km)) > (mfma ? budget_mfma : kLdsBudget)) break;
         kk = next;
       }
@@ -1091,7 +1065,7 @@ int apply_batch_t(ibf_batch_s* b, const void* const* g, const int64_t* ldg, void
         const size_t fac = (size_t)y.v.smax * ((size_t)1 << y.v.l0) * ph.kt * sizeof(VT);
         y.v.stage_f = base + fac <= kLdsBudget ? 1 : 0;
         y.lds = base + (y.v.stage_f ? fac : 0);
-      } else if (y.kind == kLaunchFused) {
+      } else if (y.kind == kLaunchFused && y.mfma) {
         const FusedArgs& A = y.f.A;
         const size_t nbv = y.mfma ? 64 : (size_t)A.NB;
         y.lds = (((size_t)1 << A.nst) * ((size_t)A.kmaxg * nbv + (size_t)2 * A.kmaxg * ph.kt) +
