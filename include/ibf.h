@@ -175,6 +175,83 @@ int ibf_eval_kernel(int phase_id, const double* phase_params, int n_params,
                     void* hip_stream);
 
 /*
+ * Direct FP64 product u(x_i) = sum_j exp(2 pi i Phi(x_i, xi_j)) g_j (the dense
+ * definition the factorization approximates, Sec. 1) on the device, with the
+ * library's reduced phase.  x (n_x), xi (n_xi), g (ldg x nrhs, double2) and u
+ * (ldu x nrhs, double2) are device pointers; O(n_x n_xi nrhs) work, meant for
+ * small problems (the predictor's training labels).  Errors: INVALID_ARG,
+ * UNSUPPORTED (phase), DEVICE.
+ */
+int ibf_dense_apply(int phase_id, const double* phase_params, int n_params,
+                    const double* x, int64_t n_x, const double* xi, int64_t n_xi,
+                    const void* g, int64_t ldg, void* u, int64_t ldu, int64_t nrhs,
+                    void* hip_stream);
+
+/*
+ * Learned Chebyshev-order predictor.  The paper fixes one order r and reports
+ * the achieved error (eq:relativeerr) as a function of r, independent of N
+ * (Sec. 6, Tables 1, 3, 4).  A multilayer perceptron
+ *   h1 = tanh(W1 x + b1), h2 = tanh(W2 h1 + b2), y = w3 . h2 + b3
+ * models y = log10(achieved error) from the IBF_MLP_FEATURES features of
+ * ibf_mlp_features; the order is the smallest r whose prediction plus a
+ * margin (decades) meets the tolerance.  Parameters are one flat FP32 vector
+ * [W1 (H x F row-major), b1 (H), W2 (H x H row-major), b2 (H), w3 (H), b3],
+ * H = n_hidden in {8, 16, 32}.  Training and inference run on the device.
+ */
+#define IBF_MLP_FEATURES 6
+
+/* Number of parameters for n_hidden (or -1 if unsupported).  Host only. */
+int ibf_mlp_n_params(int n_hidden);
+
+/*
+ * Host-only feature vector of one (problem, r, tol): [log2(n)/16, n / 2^L
+ * with L = ceil(log2 n), phase is FIO1D, phase is DFT, r/16, -log10(tol)/16]
+ * written to out[0..5] (host memory).  Errors: INVALID_ARG.
+ */
+int ibf_mlp_features(int64_t n, int phase_id, int r, double tol, float* out);
+
+/* y[s] = network(X[s]) for n samples (device pointers, X row-major n x F). */
+int ibf_mlp_forward(const float* params, int n_hidden, const float* X, int64_t n,
+                    float* y, void* hip_stream);
+
+/* Floats of device workspace ibf_mlp_loss_grad needs for n samples (-1 if invalid). */
+int64_t ibf_mlp_grad_work(int n_hidden, int64_t n);
+
+/*
+ * Mean squared error over n samples and its gradient with respect to the
+ * parameters (device pointers: params, X (n x F), targets (n), grad
+ * (n_params), loss (1 float, may be NULL), work (ibf_mlp_grad_work floats)).
+ * The sum over samples runs in a fixed order (deterministic).
+ */
+int ibf_mlp_loss_grad(const float* params, int n_hidden, const float* X,
+                      const float* targets, int64_t n, float* grad, float* loss,
+                      float* work, void* hip_stream);
+
+/*
+ * One Adam step t >= 1 in place on params, m, v (device, n_params each):
+ * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps).
+ */
+int ibf_mlp_adam(float* params, const float* grad, float* m, float* v, int n_params,
+                 int step, float lr, float beta1, float beta2, float eps,
+                 void* hip_stream);
+
+/*
+ * Order selection for one problem with accuracy target tol: evaluates the
+ * network on the device (synchronises the stream) for r = rmin..rmax and the
+ * truncation tolerances 3 tol, tol, tol/3, tol/10 (those below 1), and writes
+ * the first candidate whose prediction + margin <= log10(tol), trying the
+ * loosest truncation first (ranks, hence stored entries, follow it) and then
+ * the smallest r (the build's work grows with r): *r_out and *svd_tol_out
+ * (the ibf_desc r and tol to build with).  *r_out = 0 when none qualifies
+ * (the caller then falls back to a fixed order).  rmin >= 2, rmax <= 16.
+ * Errors: INVALID_ARG, OOM, DEVICE.
+ */
+int ibf_mlp_select(const float* params, int n_hidden, int64_t n, int phase_id,
+                   double tol, double margin, int rmin, int rmax, int* r_out,
+                   double* svd_tol_out, void* hip_stream);
+
+/*
  * Batched application of many independent plans with uneven sizes and RHS
  * counts (the paper's applications are one plan at a time; the batch runs
  * many small problems of Sec. 6 together so that each launch fills the GPU).

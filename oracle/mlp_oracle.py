@@ -9,9 +9,10 @@ factorization (Sec. 2.1, the interpolation of eqn:ab1 / eqn:ab2) and reports
 the achieved relative error (eq:relativeerr) as a function of r, with the
 error essentially independent of N (Sec. 6, Tables 1, 3 and 4).  The
 predictor is a small multilayer perceptron that models log10 of that
-achieved error from problem features and r; the plan then takes the smallest
-r whose predicted error, plus a safety margin in decades, meets the
-tolerance.  In the collapsed-level geometry every box pair has the same
+achieved error from problem features, r and the truncation tolerance; for an
+accuracy target the plan takes the loosest truncation tolerance, then the
+smallest r, whose predicted error, plus a safety margin in decades, meets
+the target.  In the collapsed-level geometry every box pair has the same
 width product w_A w_B = N / 2^L, so one r serves every level.  The network,
 its loss and the Adam optimiser (Kingma and Ba, 2015) are not from the paper.
 
@@ -117,12 +118,17 @@ def train(p, X, Y, nh: int, steps: int, lr: float = 1e-2):
     return p
 
 
-def select_r(p, nh: int, n: int, phase: int, tol: float, margin: float = 0.5,
-             rmin: int = 2, rmax: int = 16):
-    """Smallest r in [rmin, rmax] whose predicted log10 error + margin <= log10 tol
-    (None when no r qualifies: the caller falls back to a fixed r)."""
-    for r in range(rmin, rmax + 1):
-        y = forward(p, features(n, phase, r, tol)[None, :], nh)[0]
-        if y + margin <= math.log10(tol):
-            return r
+def select(p, nh: int, n: int, phase: int, tol: float, margin: float = 0.3,
+           rmin: int = 2, rmax: int = 16):
+    """First (r, svd_tol) whose predicted log10 error + margin <= log10 tol,
+    trying the truncation tolerances 3 tol, tol, tol/3, tol/10 (those below 1)
+    loosest first and, for each, r ascending; None when none qualifies (the
+    caller falls back to a fixed order)."""
+    for st in (3.0 * tol, tol, tol / 3.0, tol / 10.0):
+        if not st < 1.0:
+            continue
+        for r in range(rmin, rmax + 1):
+            y = forward(p, features(n, phase, r, st)[None, :], nh)[0]
+            if y + margin <= math.log10(tol):
+                return r, st
     return None

@@ -594,6 +594,35 @@ int build_plan(ibf_plan_t p, hipStream_t s) {
   return IBF_OK;
 }
 
+// Direct product u(x_i) = sum_j K(x_i, xi_j) g_j in FP64 (the plain definition
+// the factorization approximates): one thread per (row, right-hand side).
+__global__ __launch_bounds__(256) void k_dense(PhaseDesc ph, const double* __restrict__ x,
+                                               int64_t nx, const double* __restrict__ xi,
+                                               int64_t nxi, const double2* __restrict__ g,
+                                               int64_t ldg, double2* __restrict__ u, int64_t ldu) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (i >= nx) return;
+  const double xv = x[i];
+  const double2* gc = g + c * ldg;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int64_t j = 0; j < nxi; ++j) {
+    const double2 k = kval(ph, xv, xi[j]);
+    const double2 gv = gc[j];
+    acc.x = fma(k.x, gv.x, fma(-k.y, gv.y, acc.x));
+    acc.y = fma(k.x, gv.y, fma(k.y, gv.x, acc.y));
+  }
+  u[c * ldu + i] = acc;
+}
+
+int dense_apply(const PhaseDesc& ph, const double* x, int64_t nx, const double* xi, int64_t nxi,
+                const void* g, int64_t ldg, void* u, int64_t ldu, int64_t nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense, dim3((unsigned)((nx + 255) / 256), (unsigned)nrhs), dim3(256), 0, s,
+                     ph, x, nx, xi, nxi, (const double2*)g, ldg, (double2*)u, ldu);
+  IBF_HIP_CHECK(hipGetLastError());
+  return IBF_OK;
+}
+
 int eval_kernel(const PhaseDesc& ph, const double* x, const double* xi, int64_t n, void* out,
                 hipStream_t s) {
   hipLaunchKernelGGL(k_eval, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ph, x, xi, n,

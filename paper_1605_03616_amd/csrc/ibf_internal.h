@@ -89,6 +89,8 @@ namespace ibf {
 int build_plan(ibf_plan_t p, hipStream_t s);
 int apply_plan(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu,
                int64_t nrhs, hipStream_t s, ibf_profile* prof = nullptr);
+int dense_apply(const PhaseDesc& ph, const double* x, int64_t nx, const double* xi, int64_t nxi,
+                const void* g, int64_t ldg, void* u, int64_t ldu, int64_t nrhs, hipStream_t s);
 int eval_kernel(const PhaseDesc& ph, const double* x, const double* xi,
                 int64_t n, void* out, hipStream_t s);
 void free_factors(ibf_plan_t p);

@@ -248,20 +248,43 @@ int ibf_destroy(ibf_plan_t p) {
   return IBF_OK;
 }
 
+// Phase descriptor of the probe entry points (missing parameters take the defaults).
+static int probe_phase(const char* who, int phase_id, const double* params, int n_params,
+                       ibf::PhaseDesc* ph) {
+  if (n_params < 0 || n_params > ibf::kMaxParams || (n_params > 0 && !params))
+    return fail(IBF_ERR_INVALID_ARG, std::string(who) + ": bad phase parameters");
+  const double defaults[4][3] = {{1, 0, 0}, {2, 1, 8}, {2, 1, 16}, {3, 0.3125, 0}};
+  if (phase_id < 0 || phase_id > 3 || phase_id == IBF_PHASE_FIO2D)
+    return fail(IBF_ERR_UNSUPPORTED, std::string(who) + ": unsupported phase");
+  *ph = ibf::PhaseDesc{};
+  ph->kind = phase_id;
+  for (int i = 0; i < 3; ++i) ph->p[i] = i < n_params ? params[i] : defaults[phase_id][i];
+  return IBF_OK;
+}
+
 int ibf_eval_kernel(int phase_id, const double* params, int n_params,
                     const double* x, const double* xi, int64_t n, void* out,
                     void* stream) {
-  if (!x || !xi || !out || n < 0 || n_params < 0 || n_params > ibf::kMaxParams ||
-      (n_params > 0 && !params))
+  if (!x || !xi || !out || n < 0)
     return fail(IBF_ERR_INVALID_ARG, "ibf_eval_kernel: bad argument");
   ibf::PhaseDesc ph{};
-  ph.kind = phase_id;
-  const double defaults[4][3] = {{1, 0, 0}, {2, 1, 8}, {2, 1, 16}, {3, 0.3125, 0}};
-  if (phase_id < 0 || phase_id > 3 || phase_id == IBF_PHASE_FIO2D)
-    return fail(IBF_ERR_UNSUPPORTED, "ibf_eval_kernel: unsupported phase");
-  for (int i = 0; i < 3; ++i) ph.p[i] = i < n_params ? params[i] : defaults[phase_id][i];
+  const int rc = probe_phase("ibf_eval_kernel", phase_id, params, n_params, &ph);
+  if (rc) return rc;
   if (n == 0) return IBF_OK;
   return ibf::eval_kernel(ph, x, xi, n, out, (hipStream_t)stream);
+}
+
+int ibf_dense_apply(int phase_id, const double* params, int n_params, const double* x,
+                    int64_t n_x, const double* xi, int64_t n_xi, const void* g, int64_t ldg,
+                    void* u, int64_t ldu, int64_t nrhs, void* stream) {
+  if (!x || !xi || !g || !u || n_x < 0 || n_xi < 0 || nrhs < 1 || nrhs > 65535 || ldg < n_xi ||
+      ldu < n_x)
+    return fail(IBF_ERR_INVALID_ARG, "ibf_dense_apply: bad argument");
+  ibf::PhaseDesc ph{};
+  const int rc = probe_phase("ibf_dense_apply", phase_id, params, n_params, &ph);
+  if (rc) return rc;
+  if (n_x == 0) return IBF_OK;
+  return ibf::dense_apply(ph, x, n_x, xi, n_xi, g, ldg, u, ldu, nrhs, (hipStream_t)stream);
 }
 
 }  // extern "C"

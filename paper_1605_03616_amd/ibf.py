@@ -22,7 +22,10 @@ ERRORS = {-1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "OOM", -4: "DEVICE", -5: "NO
 
 EXPORTED = ["ibf_plan", "ibf_build", "ibf_apply", "ibf_apply_profile", "ibf_query",
             "ibf_destroy", "ibf_last_error", "ibf_eval_kernel", "ibf_batch_create",
-            "ibf_apply_batch", "ibf_batch_destroy"]
+            "ibf_apply_batch", "ibf_batch_destroy", "ibf_dense_apply", "ibf_mlp_n_params",
+            "ibf_mlp_features", "ibf_mlp_forward", "ibf_mlp_grad_work", "ibf_mlp_loss_grad",
+            "ibf_mlp_adam", "ibf_mlp_select"]
+MLP_FEATURES = 6
 BATCH_GRAPH = 1
 PROFILE_MAX = 64
 
@@ -108,9 +111,24 @@ def load(path: str = LIB_PATH):
                                     C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
                                     C.POINTER(C.c_int64), C.c_int, C.c_void_p]
     lib.ibf_batch_destroy.argtypes = [C.c_void_p]
+    vp, i64, f32 = C.c_void_p, C.c_int64, C.c_float
+    lib.ibf_dense_apply.argtypes = [C.c_int, C.POINTER(C.c_double), C.c_int, vp, i64, vp, i64,
+                                    vp, i64, vp, i64, i64, vp]
+    lib.ibf_mlp_n_params.argtypes = [C.c_int]
+    lib.ibf_mlp_features.argtypes = [i64, C.c_int, C.c_int, C.c_double, C.POINTER(C.c_float)]
+    lib.ibf_mlp_forward.argtypes = [vp, C.c_int, vp, i64, vp, vp]
+    lib.ibf_mlp_grad_work.argtypes = [C.c_int, i64]
+    lib.ibf_mlp_grad_work.restype = i64
+    lib.ibf_mlp_loss_grad.argtypes = [vp, C.c_int, vp, vp, i64, vp, vp, vp, vp]
+    lib.ibf_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_int, C.c_int, f32, f32, f32, f32, vp]
+    lib.ibf_mlp_select.argtypes = [vp, C.c_int, i64, C.c_int, C.c_double, C.c_double,
+                                   C.c_int, C.c_int, C.POINTER(C.c_int),
+                                   C.POINTER(C.c_double), vp]
     for name in ("ibf_plan", "ibf_build", "ibf_apply", "ibf_apply_profile", "ibf_query",
                  "ibf_destroy", "ibf_eval_kernel", "ibf_batch_create", "ibf_apply_batch",
-                 "ibf_batch_destroy"):
+                 "ibf_batch_destroy", "ibf_dense_apply", "ibf_mlp_n_params",
+                 "ibf_mlp_features", "ibf_mlp_forward", "ibf_mlp_loss_grad", "ibf_mlp_adam",
+                 "ibf_mlp_select"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -307,3 +325,73 @@ def eval_kernel(phase, params, x_dev, xi_dev, stream=None):
                                C.c_void_p(xi_dev.data_ptr()), x_dev.shape[0],
                                C.c_void_p(out.data_ptr()), _stream_handle(stream)))
     return out
+
+
+def dense_apply(phase, params, x_dev, xi_dev, g, stream=None):
+    """Device FP64 direct product: g (nrhs, n_xi) complex128 -> u (nrhs, n_x)."""
+    import torch
+    lib = load()
+    prm = np.ascontiguousarray(params if params is not None else [], dtype=np.float64)
+    nrhs = g.shape[0]
+    u = torch.empty((nrhs, x_dev.shape[0]), dtype=torch.complex128, device=g.device)
+    _check(lib.ibf_dense_apply(int(phase),
+                               prm.ctypes.data_as(C.POINTER(C.c_double)) if prm.size else None,
+                               int(prm.size), C.c_void_p(x_dev.data_ptr()), x_dev.shape[0],
+                               C.c_void_p(xi_dev.data_ptr()), xi_dev.shape[0],
+                               C.c_void_p(g.data_ptr()), g.shape[1], C.c_void_p(u.data_ptr()),
+                               u.shape[1], nrhs, _stream_handle(stream)))
+    return u
+
+
+def mlp_n_params(n_hidden):
+    n = load().ibf_mlp_n_params(n_hidden)
+    if n < 0:
+        raise ValueError(f"unsupported hidden width {n_hidden}")
+    return n
+
+
+def mlp_features(n, phase, r, tol):
+    out = (C.c_float * MLP_FEATURES)()
+    _check(load().ibf_mlp_features(int(n), int(phase), int(r), float(tol), out))
+    return np.array(out[:], dtype=np.float32)
+
+
+def mlp_forward(params, n_hidden, X, stream=None):
+    import torch
+    y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    _check(load().ibf_mlp_forward(C.c_void_p(params.data_ptr()), n_hidden,
+                                  C.c_void_p(X.data_ptr()), X.shape[0], C.c_void_p(y.data_ptr()),
+                                  _stream_handle(stream)))
+    return y
+
+
+def mlp_loss_grad(params, n_hidden, X, T, stream=None):
+    """(loss, grad) device tensors for the mean squared error over the samples."""
+    import torch
+    lib = load()
+    n = X.shape[0]
+    work = torch.empty(lib.ibf_mlp_grad_work(n_hidden, n), dtype=torch.float32, device=X.device)
+    grad = torch.empty_like(params)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    _check(lib.ibf_mlp_loss_grad(C.c_void_p(params.data_ptr()), n_hidden,
+                                 C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()), n,
+                                 C.c_void_p(grad.data_ptr()), C.c_void_p(loss.data_ptr()),
+                                 C.c_void_p(work.data_ptr()), _stream_handle(stream)))
+    return loss, grad
+
+
+def mlp_adam(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(load().ibf_mlp_adam(C.c_void_p(params.data_ptr()), C.c_void_p(grad.data_ptr()),
+                               C.c_void_p(m.data_ptr()), C.c_void_p(v.data_ptr()),
+                               params.numel(), int(step), lr, beta1, beta2, eps,
+                               _stream_handle(stream)))
+
+
+def mlp_select(params, n_hidden, n, phase, tol, margin=0.3, rmin=2, rmax=16, stream=None):
+    """(r, svd_tol) predicted to meet tol, or (0, tol) when none qualifies."""
+    r = C.c_int(0)
+    st = C.c_double(0.0)
+    _check(load().ibf_mlp_select(C.c_void_p(params.data_ptr()), n_hidden, int(n), int(phase),
+                                 float(tol), float(margin), rmin, rmax, C.byref(r), C.byref(st),
+                                 _stream_handle(stream)))
+    return r.value, st.value

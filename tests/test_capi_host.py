@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared_symbols():
     src = open(os.path.join(ROOT, "include", "ibf.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(ibf_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|const char\*)\s+(ibf_\w+)\s*\(", src, re.M)))
 
 
 def test_header_and_binding_agree():
@@ -92,3 +92,18 @@ def test_null_arguments():
     assert lib.ibf_build(None, None) == -1
     assert lib.ibf_query(None, None) == -1
     assert lib.ibf_destroy(None) == 0
+
+
+def test_mlp_feature_map_matches_oracle():
+    # host-only entry point: the predictor's features against the oracle's
+    from oracle import mlp_oracle as M
+    for n, ph, r, tol in [(256, 1, 8, 1e-6), (3000, 0, 11, 1e-4), (65482, 1, 12, 1e-6),
+                          (1025, 3, 5, 0.5)]:
+        assert np.allclose(ibf.mlp_features(n, ph, r, tol), M.features(n, ph, r, tol),
+                           rtol=1e-6, atol=1e-7)
+    for h in (8, 16, 32):
+        assert ibf.mlp_n_params(h) == M.n_params(M.N_FEATURES, h)
+    with pytest.raises(ValueError):
+        ibf.mlp_n_params(12)
+    with pytest.raises(ibf.IBFError):
+        ibf.mlp_features(1024, 1, 8, 0.0)
