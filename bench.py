@@ -106,9 +106,32 @@ def _bench_batched(args):
 
     ibf.load()
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
-    probs = I.workload_batched(count=args.batch_count, seed=3, r=args.batch_r)
+    learned = args.batch_r == "mlp"
+    probs = I.workload_batched(count=args.batch_count, seed=3,
+                               r=12 if learned else int(args.batch_r))
     print(f"[bench] batched workload: {len(probs)} problems, sum N = {sum(P.n for P in probs)}",
           file=sys.stderr, flush=True)
+    pred_info = None
+    if learned:
+        # orders (and truncation) from the learned predictor for the 1e-6 target,
+        # trained here on the device from the factorization's own error data
+        from paper_1605_03616_amd import predictor as PR
+        t0 = time.perf_counter()
+        data = PR.generate(PR.default_sizes())
+        t_data = time.perf_counter() - t0
+        pred = PR.Predictor(n_hidden=16, seed=5)
+        t0 = time.perf_counter()
+        loss = pred.fit(data)
+        t_fit = time.perf_counter() - t0
+        choice = [pred.select(P.n, P.phase, 1e-6) for P in probs]
+        for P, (r, st) in zip(probs, choice):
+            P.r, P.tol = r, st
+        rs = [c[0] for c in choice]
+        pred_info = {"samples": len(data.Y), "data_s": round(t_data, 2),
+                     "train_s": round(t_fit, 2), "train_loss": loss,
+                     "r_hist": {int(r): rs.count(r) for r in sorted(set(rs))},
+                     "truncations": sorted({f"{c[1]:.2g}" for c in choice})}
+        print(f"[bench] predictor: {pred_info}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plans = [ibf.Plan.from_problem(P).build() for P in probs]
@@ -142,8 +165,9 @@ def _bench_batched(args):
         "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"batched_fio1d_{len(probs)}_problems_r{args.batch_r}",
+                   "target_tol": 1e-6,
                    "count": len(probs), "sum_N": sum(P.n for P in probs),
-                   "sum_N_x_nrhs": units, "tol": 1e-6, "parallelism": "single-gpu"},
+                   "sum_N_x_nrhs": units, "parallelism": "single-gpu"},
         "build_ms": round(sum(q["build_ms"] for q in qs), 3),
         "build_wall_ms": round(build_s * 1e3, 3),
         "nnz_opt": sum(q["nnz_opt"] for q in qs),
@@ -152,6 +176,8 @@ def _bench_batched(args):
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "algorithmic_bytes_per_step": abytes},
     }
+    if pred_info:
+        out["predictor"] = pred_info
     if not args.no_accuracy:
         worst = 0.0
         for P, u in zip(probs, us):
@@ -202,7 +228,8 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 256 MiB elementwise copy first (HBM counter calibration)")
     ap.add_argument("--batch-count", type=int, default=256)
-    ap.add_argument("--batch-r", type=int, default=12)
+    ap.add_argument("--batch-r", default="12",
+                    help="order of every batched problem, or 'mlp' for the learned predictor")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); "

@@ -198,15 +198,17 @@ int ibf_dense_apply(int phase_id, const double* phase_params, int n_params,
  * [W1 (H x F row-major), b1 (H), W2 (H x H row-major), b2 (H), w3 (H), b3],
  * H = n_hidden in {8, 16, 32}.  Training and inference run on the device.
  */
-#define IBF_MLP_FEATURES 6
+#define IBF_MLP_FEATURES 5
 
 /* Number of parameters for n_hidden (or -1 if unsupported).  Host only. */
 int ibf_mlp_n_params(int n_hidden);
 
 /*
- * Host-only feature vector of one (problem, r, tol): [log2(n)/16, n / 2^L
- * with L = ceil(log2 n), phase is FIO1D, phase is DFT, r/16, -log10(tol)/16]
- * written to out[0..5] (host memory).  Errors: INVALID_ARG.
+ * Host-only feature vector of one (problem, r, tol): [n / 2^L with L =
+ * ceil(log2 n) (the width product of every box pair), phase is FIO1D, phase
+ * is DFT, r/16, -log10(tol)/16] written to out[0..4] (host memory).  N
+ * enters only through that width product: the achieved error does not
+ * depend on N otherwise (Sec. 6).  Errors: INVALID_ARG.
  */
 int ibf_mlp_features(int64_t n, int phase_id, int r, double tol, float* out);
 

@@ -27,17 +27,18 @@ import math
 
 import numpy as np
 
-N_FEATURES = 6
+N_FEATURES = 5
 PHASE_DFT, PHASE_FIO1D = 0, 1
 
 
 def features(n: int, phase: int, r: int, tol: float) -> np.ndarray:
-    """x = [log2(N)/16, kappa, [phase is FIO], [phase is DFT], r/16, -log10(tol)/16]
-    with kappa = N / 2^L, L = ceil(log2 N) the tree depth (the width product
-    of every box pair in the collapsed-level geometry)."""
+    """x = [kappa, [phase is FIO], [phase is DFT], r/16, -log10(tol)/16] with
+    kappa = N / 2^L, L = ceil(log2 N) the tree depth (the width product of
+    every box pair in the collapsed-level geometry).  N enters only through
+    kappa: the achieved error does not otherwise depend on N (Sec. 6)."""
     L = int(math.ceil(math.log2(n)))
     kappa = n / float(2 ** L)
-    return np.array([math.log2(n) / 16.0, kappa, 1.0 if phase == PHASE_FIO1D else 0.0,
+    return np.array([kappa, 1.0 if phase == PHASE_FIO1D else 0.0,
                      1.0 if phase == PHASE_DFT else 0.0, r / 16.0, -math.log10(tol) / 16.0])
 
 

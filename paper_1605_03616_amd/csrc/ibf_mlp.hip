@@ -213,12 +213,11 @@ int ibf_mlp_features(int64_t n, int phase_id, int r, double tol, float* out) {
     return ibf::fail_arg("ibf_mlp_features: bad argument");
   int L = 0;
   while (((int64_t)1 << L) < n) ++L;                          // tree depth ceil(log2 n)
-  out[0] = (float)(std::log2((double)n) / 16.0);
-  out[1] = (float)((double)n / (double)((int64_t)1 << L));    // width product of every pair
-  out[2] = phase_id == IBF_PHASE_FIO1D ? 1.0f : 0.0f;
-  out[3] = phase_id == IBF_PHASE_DFT ? 1.0f : 0.0f;
-  out[4] = (float)(r / 16.0);
-  out[5] = (float)(-std::log10(tol) / 16.0);
+  out[0] = (float)((double)n / (double)((int64_t)1 << L));    // width product of every pair
+  out[1] = phase_id == IBF_PHASE_FIO1D ? 1.0f : 0.0f;
+  out[2] = phase_id == IBF_PHASE_DFT ? 1.0f : 0.0f;
+  out[3] = (float)(r / 16.0);
+  out[4] = (float)(-std::log10(tol) / 16.0);
   return IBF_OK;
 }
 

@@ -25,7 +25,7 @@ EXPORTED = ["ibf_plan", "ibf_build", "ibf_apply", "ibf_apply_profile", "ibf_quer
             "ibf_apply_batch", "ibf_batch_destroy", "ibf_dense_apply", "ibf_mlp_n_params",
             "ibf_mlp_features", "ibf_mlp_forward", "ibf_mlp_grad_work", "ibf_mlp_loss_grad",
             "ibf_mlp_adam", "ibf_mlp_select"]
-MLP_FEATURES = 6
+MLP_FEATURES = 5
 BATCH_GRAPH = 1
 PROFILE_MAX = 64
 

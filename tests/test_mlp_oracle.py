@@ -90,7 +90,7 @@ def test_adam_converges_on_quadratic():
 def test_training_fits_smooth_function():
     rng = np.random.default_rng(6)
     X = rng.uniform(-1, 1, (200, NF))
-    Y = np.sin(2 * X[:, 0]) + 0.5 * X[:, 4] ** 2 - X[:, 5]
+    Y = np.sin(2 * X[:, 0]) + 0.5 * X[:, 3] ** 2 - X[:, 4]
     p0 = M.init_params(NF, 16, np.random.default_rng(7))
     l0 = M.loss(p0, X, Y, 16)
     p = M.train(p0, X, Y, 16, steps=1500, lr=1e-2)
@@ -99,7 +99,7 @@ def test_training_fits_smooth_function():
 
 def test_features_tree_quantities():
     f = M.features(4096, M.PHASE_FIO1D, 12, 1e-6)
-    assert np.allclose(f, [12 / 16, 1.0, 1.0, 0.0, 12 / 16, 6 / 16])
+    assert np.allclose(f, [1.0, 1.0, 0.0, 12 / 16, 6 / 16])
     f = M.features(3000, M.PHASE_DFT, 8, 1e-4)
-    assert math.isclose(f[1], 3000 / 4096) and f[2] == 0.0 and f[3] == 1.0
-    assert math.isclose(f[0], math.log2(3000) / 16)
+    assert math.isclose(f[0], 3000 / 4096) and f[1] == 0.0 and f[2] == 1.0
+    assert np.allclose(M.features(65536, M.PHASE_DFT, 8, 1e-4), M.features(256, M.PHASE_DFT, 8, 1e-4))
