@@ -32,6 +32,36 @@ FP64_PEAK_TFS = 78.6
 BF16_PEAK_TFS = 2500.0
 
 
+# HBM traffic of the dominant apply kernel measured with rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE passes (KiB per dispatch), each scaled by what the
+# counter reads for a plain 256 MiB elementwise copy (FETCH_SIZE reads half
+# the bytes read: x2.0; WRITE_SIZE reads the bytes written: x1.0).  Valid only
+# for the apply source it was measured on: any change to it voids the figure.
+APPLY_SRC = os.path.join(ROOT, "paper_1605_03616_amd", "csrc", "ibf_apply.hip")
+MEASURED_TRAFFIC = {
+    # workload -> (sha1 of the apply source, kernel class,
+    #              [(launches per step, FETCH_SIZE KiB, WRITE_SIZE KiB), ...])
+    "fio1d_n65536_r12_fp32": ("11610ed9aceabe796b706f8f9b76678cfe1b8349", "apply_fused_mfma",
+                              [(2, 324695, 344064), (1, 261203, 294912)]),
+}
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+
+
+def _measured_traffic(workload, kernel):
+    """Average HBM bytes per launch of `kernel`, or None if not measured for
+    this exact apply source."""
+    import hashlib
+    ent = MEASURED_TRAFFIC.get(workload)
+    if not ent or ent[1] != kernel:
+        return None
+    with open(APPLY_SRC, "rb") as f:
+        if hashlib.sha1(f.read()).hexdigest() != ent[0]:
+            return None
+    n = sum(c for c, _, _ in ent[2])
+    tot = sum(c * (fk * FETCH_SCALE + wk * WRITE_SCALE) * 1024.0 for c, fk, wk in ent[2])
+    return tot / n
+
+
 def _workload(name, nrhs=None):
     from paper_1605_03616_amd import inputs as I
     if name == "fio1d_64k":
@@ -294,6 +324,9 @@ def main():
         bound, peak = ("hbm", HBM_PEAK_GBS) if P.nrhs < 64 else ("mfma", BF16_PEAK_TFS)
     unit = "TFLOP/s" if bound == "mfma" else "GB/s"
     dom, roof, per_class = _roofline(launches, bound, peak, unit)
+    roof["traffic"] = _measured_traffic(P.name, dom)
+    if roof["traffic"] is not None:
+        roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)"
 
     out = {
         "metric": "IBF apply G(complex samples*RHS)/s at rel err 1e-5 vs plain FP64; build ms",
