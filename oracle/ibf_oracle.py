@@ -81,7 +81,7 @@ def phase_frac(kind, params, x, xi):
     kind 0: Phi = s x xi                         (Sec. 6.1, s = params[0])
     kind 1: Phi = x xi + c(x)|xi|, c = (p0 + p1 sin 2 pi x)/p2   (Sec. 6.2)
     kind 3: Phi = p0 x + p1 xi  (separable; R^{AB} == 0 in eqn:RAB)
-    For kind 2 (2-D) see phase_frac_2d.
+    For kind 2 (2-D) see ibf2d_oracle.phase_frac_2d.
     """
     x = np.asarray(x, dtype=np.float64)
     xi = np.asarray(xi, dtype=np.float64)

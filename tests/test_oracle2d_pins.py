@@ -1,0 +1,134 @@
+"""Pins of the 2-D / MIBF oracle (no GPU), each against something other than
+the oracle itself: the 2-D DFT closed form (numpy.fft), exactness for an
+x-independent phase, interpolation error decaying with r, compression
+within the truncation tolerance, the corona partition as a set identity,
+linearity of the multiscale sum over the parts, and the MIBF against the
+dense product at the magnitude expected for r = 5 (Sec. 6.3)."""
+import numpy as np
+import pytest
+
+from oracle import ibf2d_oracle as D
+from oracle import ibf_oracle as O
+
+
+def _grid_x(n):
+    i1, i2 = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    return np.stack([i1.ravel() / n, i2.ravel() / n], -1)
+
+
+def _grid_xi(lo, w):
+    j1, j2 = np.meshgrid(np.arange(w), np.arange(w), indexing="ij")
+    return np.stack([lo[0] + j1.ravel(), lo[1] + j2.ravel()], -1).astype(np.float64)
+
+
+def _cn(m, k, seed):
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal((m, k)) + 1j * rng.standard_normal((m, k))) / np.sqrt(2)
+
+
+def test_morton_codes():
+    i1, i2 = np.meshgrid(np.arange(16), np.arange(16), indexing="ij")
+    code = D.morton_encode(i1, i2, 4)
+    assert sorted(code.ravel().tolist()) == list(range(256))
+    d1, d2 = D.morton_decode(code, 4)
+    assert np.array_equal(d1, i1) and np.array_equal(d2, i2)
+    # parent and child relations of the quadtree
+    p1, p2 = D.morton_decode(code >> 2, 3)
+    assert np.array_equal(p1, i1 >> 1) and np.array_equal(p2, i2 >> 1)
+    assert np.array_equal(code & 3, 2 * (i1 & 1) + (i2 & 1))
+
+
+def test_dense_2d_dft_closed_form():
+    # sum_xi exp(2 pi i x.xi) g(xi), x = i/n, xi = j - n/2  ==  (-1)^(i1+i2) n^2 ifft2(g)
+    n = 16
+    x = _grid_x(n)
+    xi = _grid_xi((-n // 2, -n // 2), n)
+    g = _cn(n * n, 1, 3)
+    u = D.dense_apply_2d(0, (1.0,), x, xi, g)[:, 0].reshape(n, n)
+    i1, i2 = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    want = (-1.0) ** (i1 + i2) * n * n * np.fft.ifft2(g[:, 0].reshape(n, n))
+    assert np.max(np.abs(u - want)) <= 1e-11 * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("w,o", [(8, (8.0, -8.0)), (16, (16.0, 0.0))])
+def test_x_independent_phase_is_exact(w, o):
+    x = _grid_x(16)
+    xi = _grid_xi(o, w)
+    g = _cn(len(xi), 2, 4)
+    ud = D.dense_apply_2d(3, (3.0, 0.3125), x, xi, g)
+    P, F, Op = D.build_box(3, (3.0, 0.3125), x, xi, o, w, 3, 1e-8)
+    assert O.rel_error(D.apply_prelim_2d(F, g), ud) <= 1e-12
+    assert O.rel_error(D.apply_optimal_2d(Op, g), ud) <= 1e-12
+    assert max(D.level_ranks_2d(Op).values()) == 1
+
+
+@pytest.mark.parametrize("kind,params", [(0, (1.0,)), (2, (2.0, 1.0, 16.0))])
+def test_error_decays_with_r(kind, params):
+    x = _grid_x(16)
+    o = np.array([16.0, -16.0])
+    xi = _grid_xi(o, 16)
+    g = _cn(len(xi), 1, 5)
+    ud = D.dense_apply_2d(kind, params, x, xi, g)
+    errs = []
+    for r in (3, 5, 7):
+        P = D.make_box_problem(kind, params, x, xi, o, 16, r)
+        errs.append(O.rel_error(D.apply_prelim_2d(D.prelim_factors_2d(P), g), ud))
+    assert errs[0] > 10 * errs[1] > 100 * errs[2]
+    assert errs[2] < 1e-3
+
+
+def test_compression_within_tolerance():
+    x = _grid_x(16)
+    o = np.array([16.0, -16.0])
+    xi = _grid_xi(o, 16)
+    g = _cn(len(xi), 2, 6)
+    tol = 1e-4
+    P, F, Op = D.build_box(2, (2.0, 1.0, 16.0), x, xi, o, 16, 5, tol)
+    up = D.apply_prelim_2d(F, g)
+    uo = D.apply_optimal_2d(Op, g)
+    nlev = P.L - P.lV + 1
+    assert O.rel_error(uo, up) <= 10 * tol * np.sqrt(nlev)
+    assert D.nnz_prelim_2d(P) > D.nnz_optimal_2d(Op)
+
+
+def test_corona_partition():
+    n = 64
+    xi = _grid_xi((-n // 2, -n // 2), n)
+    part = D.mibf_partition(xi, n)
+    boxes, hc = D.mibf_boxes(n)
+    assert (part >= -1).all()                           # every point in some part
+    counts = np.bincount(part + 1)
+    assert counts[0] == 16 * 16                         # the centre [-8, 8)^2
+    assert [w for _, w in boxes] == [16] * 12 + [8] * 12
+    assert all(counts[1 + i] == w * w for i, (_, w) in enumerate(boxes))
+    # boxes are disjoint and avoid the centre: counts add up to the grid exactly
+    assert counts.sum() == n * n
+
+
+def test_multiscale_sum_of_parts():
+    n = 32
+    x = _grid_x(n)
+    xi = _grid_xi((-n // 2, -n // 2), n)
+    g = _cn(len(xi), 1, 7)
+    part = D.mibf_partition(xi, n)
+    total = sum(D.dense_apply_2d(2, (2.0, 1.0, 16.0), x, xi[part == p], g[part == p])
+                for p in np.unique(part))
+    ud = D.dense_apply_2d(2, (2.0, 1.0, 16.0), x, xi, g)
+    assert O.rel_error(total, ud) <= 1e-12
+
+
+def test_mibf_against_dense():
+    n = 64
+    x = _grid_x(n)
+    xi = _grid_xi((-n // 2, -n // 2), n)
+    g = _cn(len(xi), 1, 8)
+    rows = np.random.default_rng(9).choice(len(x), 256, replace=False)
+    ud = D.dense_apply_2d(2, (2.0, 1.0, 16.0), x, xi, g, rows=rows)
+    errs = []
+    for r in (4, 5):
+        part, built, cidx = D.mibf_build(2, (2.0, 1.0, 16.0), x, xi, n, r, 1e-4)
+        u = D.mibf_apply(2, (2.0, 1.0, 16.0), x, xi, g, built, cidx)
+        errs.append(O.rel_error(u[rows], ud))
+        pre, opt = D.nnz_mibf(built, cidx, len(x))
+        assert pre > opt
+    assert errs[1] < errs[0] and errs[1] < 3e-2
