@@ -1,0 +1,1364 @@
+// Two-dimensional IBF on the boxes of the multiscale IBF (MIBF) of paper
+// Sec. 5: Omega = [-W/2, W/2)^2 is split into coronas (eq:domaindecomp), each
+// the union of 12 dyadic boxes, plus a centre square summed directly; every
+// box carries its own IBF on quadtrees with tensor Chebyshev grids, and the
+// results add up (eq:mba, eq:f1).
+//
+// Geometry of a box of side w (a power of two), L = log2 w: the pair (T_X box
+// at level l, T_Omega box at level L - l) has width product 1 per coordinate.
+// V pairs the Omega leaves (side 2^lV, level L - lV) with the T_X boxes at
+// level lV; U pairs the T_X boxes at level L with the box itself; the middle
+// level is h = floor((lV + L) / 2).  Boxes are Morton codes (child digit
+// 2 c1 + c2), so the inputs of output pair (a, b) at level l are the four
+// contiguous pairs (a >> 2, 4b + c) at level l - 1, and a pair index is
+// p = a 4^(L-l) + b.  Tensor grid index t = t1 r + t2.
+//
+// Compression (Sec. 4.2): every block is reduced through its 25 x 25 (r^2 x
+// r^2) Gram matrix, eigen-decomposed by one-sided Jacobi in FP64 (the
+// normalised orthogonalised columns are the eigenvectors): singular values
+// sqrt(lambda) are resolved down to about 1e-8 of the largest, so this path
+// requires tol >= 1e-7.  One 32-lane group per pair, rows on lanes.
+//
+// Kernels: k2_tables (Chebyshev nodes, tensor child->parent Lagrange
+// matrices), k2_middle (eq:KeqUMV), k2_sweep_g (eqn:GC), k2_sweep_h (eqn:HR),
+// k2_pack_stage, k2_vbar (eqn:V0), k2_ubar, k2_centre; apply: k2_apply_v,
+// k2_apply_stage, k2_apply_u, k2_apply_centre.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ibf_device.h"
+
+namespace ibf {
+
+struct Stage2 {
+  int level, kin, kout, kld;
+  void* blk;                   // [pair][c kin + s][kld], c = 0..3
+  size_t bytes;
+};
+
+struct XTree2 {                // X points sorted into the level-L boxes (Morton)
+  int L = 0;
+  double* d_xs = nullptr;      // [sorted][2]
+  int32_t* d_perm = nullptr;   // sorted -> caller
+  int32_t* d_leaf = nullptr;   // leaf of each sorted point
+};
+
+struct Box2 {
+  double o1 = 0, o2 = 0, w = 0;
+  int L = 0, lV = 0, h = 0, xt = 0;
+  int64_t m = 0;               // Omega points in the box
+  double* d_xis = nullptr;     // [sorted][2]
+  int32_t* d_perm_xi = nullptr;
+  int32_t* d_xileaf = nullptr;
+  int32_t* d_xioff = nullptr;  // Omega leaf CSR offsets (4^(L-lV) + 1)
+  int smax_xi = 0;
+  std::vector<Stage2> stages;  // H stages then G stages, in apply order
+  void* d_vbar = nullptr;      // [Omega point][4^lV][K_V]
+  void* d_ubar = nullptr;      // [X point (sorted at level L)][K_U]
+  int K_V = 0, K_U = 0;
+  size_t vbar_bytes = 0, ubar_bytes = 0;
+  std::vector<int> rank;       // level maxima, index l - lV
+  int64_t nnz_prelim = 0, nnz_opt = 0;
+};
+
+struct Mibf2D {
+  PhaseDesc ph{};
+  int r = 0, R2 = 0, leaf_side = 0, precision = 0, device = 0;
+  double tol = 0, W = 0;
+  int64_t nx = 0, nxi = 0;
+  double* d_x = nullptr;       // caller order [n][2]
+  std::vector<XTree2> xtrees;
+  std::vector<Box2> boxes;
+  std::vector<double> xi_host; // caller order [n][2] (for the box point lists)
+  std::vector<std::vector<int32_t>> box_pts;   // caller indices per box
+  std::vector<int32_t> centre;                 // caller indices of the centre points
+  int32_t* d_cidx = nullptr;
+  void* d_kc = nullptr;        // [x][centre point] kernel values, storage precision
+  double* d_z = nullptr;       // Chebyshev nodes [r]
+  double* d_lc = nullptr;      // [4][R2][R2] child -> parent Lagrange matrices
+  void* d_work[2] = {nullptr, nullptr};
+  size_t work_bytes = 0;
+  bool built = false;
+  int64_t nnz_prelim = 0, nnz_opt = 0, nnz_stored = 0, factor_bytes = 0;
+  int maxL = 0;
+};
+
+namespace {
+
+constexpr int kB2 = 256;
+constexpr int kGroup = 32;                 // lanes per pair in the build kernels
+constexpr int kCentreSide = 16;            // centre square side (Sec. 6.3: down to 16 x 16)
+
+struct BoxDev {
+  PhaseDesc ph;
+  double o1, o2, w;
+  int L, lV, h, r;
+};
+
+// ---------------------------------------------------------------------------
+// 2-D phase (Sec. 6.3) with exact mod-1 reduction of the coordinate products
+// ---------------------------------------------------------------------------
+__device__ inline double phase_frac2(const PhaseDesc& P, double x1, double x2, double k1,
+                                     double k2) {
+#pragma clang fp contract(off)
+  double t;
+  if (P.kind == IBF_PHASE_DFT) {
+    t = P.p[0] * (frac_prod(x1, k1) + frac_prod(x2, k2));
+  } else if (P.kind == IBF_PHASE_FIO2D) {
+    const double s1 = sinpi(2.0 * x1), s2 = sinpi(2.0 * x2);
+    const double q1 = cospi(2.0 * x1), q2 = cospi(2.0 * x2);
+    const double c1 = (P.p[0] + P.p[1] * s1 * s2) / P.p[2];
+    const double c2 = (P.p[0] + P.p[1] * q1 * q2) / P.p[2];
+    const double a1 = c1 * k1, a2 = c2 * k2;
+    const double root = sqrt(a1 * a1 + a2 * a2);
+    t = frac_prod(x1, k1) + frac_prod(x2, k2) + (root - rint(root));
+  } else {  // separable: p0 xi1 + p1 xi2
+    t = frac_prod(P.p[0], k1) + frac_prod(P.p[1], k2);
+  }
+  return t - rint(t);
+}
+
+__device__ inline double2 kval2(const PhaseDesc& P, double x1, double x2, double k1, double k2) {
+  const double t = phase_frac2(P, x1, x2, k1, k2);
+  double s, c;
+  sincospi(2.0 * t, &s, &c);
+  return make_double2(c, s);
+}
+
+__device__ inline void morton_xy(int64_t code, int level, int64_t& i1, int64_t& i2) {
+  i1 = 0;
+  i2 = 0;
+  for (int j = 0; j < level; ++j) {
+    const int64_t d = (code >> (2 * j)) & 3;
+    i1 |= (d >> 1) << j;
+    i2 |= (d & 1) << j;
+  }
+}
+
+__device__ inline void cx2(int level, int64_t a, double& c1, double& c2) {
+#pragma clang fp contract(off)
+  int64_t i1, i2;
+  morton_xy(a, level, i1, i2);
+  const double s = ldexp(1.0, -level);
+  c1 = ((double)i1 + 0.5) * s;
+  c2 = ((double)i2 + 0.5) * s;
+}
+
+__device__ inline void cxi2(const BoxDev& B, int level, int64_t b, double& c1, double& c2) {
+#pragma clang fp contract(off)
+  int64_t j1, j2;
+  morton_xy(b, level, j1, j2);
+  const double s = B.w / ldexp(1.0, level);
+  c1 = B.o1 + ((double)j1 + 0.5) * s;
+  c2 = B.o2 + ((double)j2 + 0.5) * s;
+}
+
+__device__ inline double gpt(double c, double w, double z) {
+#pragma clang fp contract(off)
+  return c + w * z;
+}
+
+// M_t(y) = M_t1(y1) M_t2(y2) on the tensor grid (t = t1 r + t2)
+__device__ inline double lag2(const double* z, int r, int t, double y1, double y2) {
+  return lagrange_t(z, r, t / r, y1) * lagrange_t(z, r, t % r, y2);
+}
+
+__device__ __forceinline__ double2 shfl2(double2 v, int src) {
+  return make_double2(__shfl(v.x, src, kGroup), __shfl(v.y, src, kGroup));
+}
+__device__ __forceinline__ double2 csum(double2 v) {
+  return make_double2(group_sum<kGroup>(v.x), group_sum<kGroup>(v.y));
+}
+
+// One-sided Jacobi on a Hermitian positive semidefinite matrix held one row
+// per lane (columns in a[]): afterwards column j is lambda_j u_j with u_j an
+// eigenvector, and lam[j] = ||column j|| = lambda_j.
+template <int G>
+__device__ __forceinline__ void jrot(double2& ap_, double2& aq_, double& np_, double& nq_,
+                                     double thresh, double small, bool& rotated) {
+  const double gr = group_sum<G>(ap_.x * aq_.x + ap_.y * aq_.y);
+  const double gi = group_sum<G>(ap_.x * aq_.y - ap_.y * aq_.x);
+  const double ag = sqrt(gr * gr + gi * gi);
+  if (np_ > small && nq_ > small && ag > thresh * sqrt(np_ * nq_)) {
+    const double zeta = (nq_ - np_) / (2.0 * ag);
+    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    const double c = 1.0 / sqrt(1.0 + t * t);
+    const double s = c * t;
+    const double2 e = make_double2(gr / ag, -gi / ag);
+    const double2 eq = cmul(e, aq_);
+    const double2 ap = ap_;
+    ap_ = make_double2(c * ap.x - s * eq.x, c * ap.y - s * eq.y);
+    aq_ = make_double2(s * ap.x + c * eq.x, s * ap.y + c * eq.y);
+    np_ -= t * ag;
+    nq_ += t * ag;
+    rotated = true;
+  }
+}
+
+template <int R, int G, int P, int Q>
+__device__ __forceinline__ void jsweep(double2 (&a)[R], double (&nrm)[R], double thresh,
+                                       double small, bool& rotated) {
+  if constexpr (P < R - 1) {
+    jrot<G>(a[P], a[Q], nrm[P], nrm[Q], thresh, small, rotated);
+    if constexpr (Q + 1 < R)
+      jsweep<R, G, P, Q + 1>(a, nrm, thresh, small, rotated);
+    else
+      jsweep<R, G, P + 1, P + 2>(a, nrm, thresh, small, rotated);
+  }
+}
+
+template <int R, int G>
+__device__ __forceinline__ void jacobi_eig(double2 (&a)[R], double (&lam)[R]) {
+  const double thresh = 4.0 * (double)(R > 8 ? R : 8) * 1.1102230246251565e-16;
+  double nrm[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) nrm[j] = group_sum<G>(a[j].x * a[j].x + a[j].y * a[j].y);
+  double fro2 = 0.0;
+#pragma unroll
+  for (int j = 0; j < R; ++j) fro2 += nrm[j];
+  const double small = 1e-30 * fro2;
+  for (int sweep = 0; sweep < kJacobiMaxSweeps; ++sweep) {
+    bool rotated = false;
+    jsweep<R, G, 0, 1>(a, nrm, thresh, small, rotated);
+#pragma unroll
+    for (int j = 0; j < R; ++j) nrm[j] = group_sum<G>(a[j].x * a[j].x + a[j].y * a[j].y);
+    if (!__any(rotated)) break;
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) lam[j] = sqrt(nrm[j]);
+}
+
+// v[i] for a lane-dependent i without dynamic register indexing
+template <int R, typename T>
+__device__ __forceinline__ T sel(const T (&v)[R], int i) {
+  T out = v[0];
+#pragma unroll
+  for (int j = 1; j < R; ++j)
+    if (i == j) out = v[j];
+  return out;
+}
+
+// Ranks from eigenvalues: sigma_j = sqrt(lambda_j) > tol * sigma_max.
+template <int R>
+__device__ __forceinline__ int eig_rank(const double (&lam)[R], double tol, int (&pos)[R]) {
+  double sig[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) sig[j] = sqrt(lam[j]);
+  return rank_positions<R>(sig, tol, pos);
+}
+
+// ---------------------------------------------------------------------------
+// Tables: Chebyshev nodes and the tensor child -> parent Lagrange matrices
+//   lc[c][t][s] = M^B_t(g^{C_c}_s) = M_t1((2c1-1)/4 + z_s1/2) M_t2((2c2-1)/4 + z_s2/2)
+// ---------------------------------------------------------------------------
+__global__ void k2_tables(int r, double* z, double* lc) {
+  double zz[kMaxR];
+  for (int t = 0; t < r; ++t) zz[t] = 0.5 * cos((double)t * M_PI / (double)(r - 1));
+  const int R2 = r * r;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < r) z[e] = zz[e];
+  if (e >= 4 * R2 * R2) return;
+  const int c = e / (R2 * R2), t = (e / R2) % R2, s = e % R2;
+  const int c1 = c >> 1, c2 = c & 1;
+  double y1, y2;
+  {
+#pragma clang fp contract(off)
+    y1 = (double)(2 * c1 - 1) / 4.0 + zz[s / r] / 2.0;
+    y2 = (double)(2 * c2 - 1) / 4.0 + zz[s % r] / 2.0;
+  }
+  lc[e] = lagrange_t(zz, r, t / r, y1) * lagrange_t(zz, r, t % r, y2);
+}
+
+// Thread -> (pair, lane) of the 32-lane groups
+#define IBF2_GROUP_INDEX                                                        \
+  const int lane = threadIdx.x & (kGroup - 1);                                  \
+  const int64_t p = ((int64_t)blockIdx.x * kB2 + threadIdx.x) / kGroup;         \
+  if (p >= npairs) return;                                                      \
+  const bool row = lane < R2;
+
+// ---------------------------------------------------------------------------
+// Middle level (eq:KeqUMV, eq:lowrankSVD): M~ = K(g^A_t, g^B_s) per pair at h,
+// C = U_k S^(1/2), R = V_k S^(1/2) (both [pair][R2][R2], columns in
+// descending singular-value order, zero beyond the rank).
+// ---------------------------------------------------------------------------
+template <int R2>
+__global__ __launch_bounds__(kB2) void k2_middle(BoxDev B, const double* __restrict__ z,
+                                                 double2* __restrict__ Cb,
+                                                 double2* __restrict__ Rb,
+                                                 int* __restrict__ rank, int* __restrict__ kmax,
+                                                 unsigned long long* __restrict__ nnz,
+                                                 int64_t npairs, double tol) {
+  IBF2_GROUP_INDEX
+  const int r = B.r, L = B.L, h = B.h;
+  const int64_t a = p >> (2 * (L - h)), b = p & (((int64_t)1 << (2 * (L - h))) - 1);
+  double ca1, ca2, cb1, cb2;
+  cx2(h, a, ca1, ca2);
+  cxi2(B, L - h, b, cb1, cb2);
+  const double wa = ldexp(1.0, -h), wb = B.w / ldexp(1.0, L - h);
+  const int tl = row ? lane : 0;
+  const double ga1 = gpt(ca1, wa, z[tl / r]), ga2 = gpt(ca2, wa, z[tl % r]);
+  double2 gram[R2];
+#pragma unroll
+  for (int j = 0; j < R2; ++j) gram[j] = make_double2(0.0, 0.0);
+  for (int s = 0; s < R2; ++s) {
+    const double2 w = row ? kval2(B.ph, ga1, ga2, gpt(cb1, wb, z[s / r]), gpt(cb2, wb, z[s % r]))
+                          : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < R2; ++j) cfma(gram[j], w, conjd(shfl2(w, j)));
+  }
+  double lam[R2];
+  jacobi_eig<R2, kGroup>(gram, lam);
+  int pos[R2];
+  const int k = eig_rank<R2>(lam, tol, pos);
+  // C row t: Q[t][j] lambda_j^(-3/4)
+  double2* crow = Cb + (p * R2 + tl) * R2;
+#pragma unroll
+  for (int j = 0; j < R2; ++j) {
+    const bool keep = pos[j] < k && lam[j] > 0.0;
+    const double sc = keep ? pow(lam[j], -0.75) : 0.0;
+    if (row) crow[pos[j]] = cscale(gram[j], sc);
+  }
+  // R row s: (sum_t conj(M[t][s]) Q[t][j]) lambda_j^(-5/4); lane j keeps column j
+  const int my_pos = sel<R2>(pos, tl);
+  const double my_lam = sel<R2>(lam, tl);
+  const double my_sc = (my_pos < k && my_lam > 0.0) ? pow(my_lam, -1.25) : 0.0;
+  for (int s = 0; s < R2; ++s) {
+    const double2 mts = row ? kval2(B.ph, ga1, ga2, gpt(cb1, wb, z[s / r]), gpt(cb2, wb, z[s % r]))
+                            : make_double2(0.0, 0.0);
+    double2 mine = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < R2; ++j) {
+      const double2 v = csum(cmul(conjd(mts), gram[j]));
+      if (lane == j) mine = v;
+    }
+    if (row) Rb[(p * R2 + s) * R2 + my_pos] = cscale(mine, my_sc);
+  }
+  if (lane == 0) {
+    rank[p] = k;
+    atomicMax(kmax, k);
+    atomicAdd(nnz, (unsigned long long)k);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sweep toward U (eqn:GC) at output level l: per output pair (a, b),
+//   W = [G_c C^{l-1}_{(a>>2, 4b+c)}]_c,  G_c[t][s] = K(g^A_t, c_C) M^P_s(g^A_t) conj K(g^P_s, c_C),
+//   W ~= C^l [Gbar_0 .. Gbar_3],  C^l = U_k S_k,  Gbar = S_k^-1 U_k^* W.
+// Gbar goes to stage[p][c][t = output rank index][s = input rank index] (FP64).
+// ---------------------------------------------------------------------------
+template <int R2>
+__global__ __launch_bounds__(kB2) void k2_sweep_g(BoxDev B, int l, const double* __restrict__ z,
+                                                  const double* __restrict__ lc,
+                                                  const double2* __restrict__ Cprev,
+                                                  const int* __restrict__ rprev,
+                                                  double2* __restrict__ Cout,
+                                                  int* __restrict__ rout, int* __restrict__ kmax,
+                                                  double2* __restrict__ stage,
+                                                  unsigned long long* __restrict__ nnz,
+                                                  int64_t npairs, double tol) {
+  __shared__ double lcs[4 * R2 * R2];
+  for (int e = threadIdx.x; e < 4 * R2 * R2; e += kB2) lcs[e] = lc[e];
+  __syncthreads();
+  IBF2_GROUP_INDEX
+  const int r = B.r, L = B.L;
+  const int sh = 2 * (L - l);
+  const int64_t a = p >> sh, b = p & (((int64_t)1 << sh) - 1);
+  const int64_t par = a >> 2;
+  const int alpha = (int)(a & 3);
+  const int64_t pin0 = (par << (sh + 2)) + 4 * b;
+  double ca1, ca2, cp1, cp2;
+  cx2(l, a, ca1, ca2);
+  cx2(l - 1, par, cp1, cp2);
+  const double wa = ldexp(1.0, -l), wp = ldexp(1.0, -(l - 1));
+  const int tl = row ? lane : 0;
+  const double ga1 = gpt(ca1, wa, z[tl / r]), ga2 = gpt(ca2, wa, z[tl % r]);
+  const double gp1 = gpt(cp1, wp, z[tl / r]), gp2 = gpt(cp2, wp, z[tl % r]);
+  const double* la = lcs + alpha * R2 * R2;             // la[s * R2 + t] = M^P_s(g^A_t)
+  int kin[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) kin[c] = rprev[pin0 + c];
+  // W_c[t][m] for this lane's row t
+  auto wcol = [&](int c, int m, double2 at, double2 bs) -> double2 {
+    const double2* cs = Cprev + (pin0 + c) * R2 * R2 + m;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int s = 0; s < R2; ++s)
+      cfma(acc, cscale(shfl2(bs, s), la[s * R2 + tl]), cs[s * R2]);
+    return row ? cmul(at, acc) : make_double2(0.0, 0.0);
+  };
+  double2 gram[R2];
+#pragma unroll
+  for (int j = 0; j < R2; ++j) gram[j] = make_double2(0.0, 0.0);
+  double2 at[4], bs[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double cc1, cc2;
+    cxi2(B, L - l + 1, 4 * b + c, cc1, cc2);
+    at[c] = kval2(B.ph, ga1, ga2, cc1, cc2);
+    bs[c] = conjd(kval2(B.ph, gp1, gp2, cc1, cc2));    // lane s holds B_s
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    for (int m = 0; m < kin[c]; ++m) {
+      const double2 w = wcol(c, m, at[c], bs[c]);
+#pragma unroll
+      for (int j = 0; j < R2; ++j) cfma(gram[j], w, conjd(shfl2(w, j)));
+    }
+  double lam[R2];
+  jacobi_eig<R2, kGroup>(gram, lam);
+  int pos[R2];
+  const int k = eig_rank<R2>(lam, tol, pos);
+  double2* crow = Cout + (p * R2 + tl) * R2;
+#pragma unroll
+  for (int j = 0; j < R2; ++j) {
+    const bool keep = pos[j] < k && lam[j] > 0.0;
+    if (row) crow[pos[j]] = keep ? cscale(gram[j], 1.0 / sqrt(lam[j])) : make_double2(0.0, 0.0);
+  }
+  const int my_pos = sel<R2>(pos, tl);
+  const double my_lam = sel<R2>(lam, tl);
+  const double my_sc = (my_pos < k && my_lam > 0.0) ? pow(my_lam, -1.5) : 0.0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double2* st = stage + (p * 4 + c) * R2 * R2;
+    for (int m = 0; m < R2; ++m) {
+      if (m < kin[c]) {
+        const double2 w = wcol(c, m, at[c], bs[c]);
+        double2 mine = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < R2; ++j) {
+          const double2 v = csum(cmul(conjd(gram[j]), w));
+          if (lane == j) mine = v;
+        }
+        if (row) st[my_pos * R2 + m] = cscale(mine, my_sc);
+      } else if (row) {
+        st[tl * R2 + m] = make_double2(0.0, 0.0);
+      }
+    }
+  }
+  if (lane == 0) {
+    rout[p] = k;
+    atomicMax(kmax, k);
+    atomicAdd(nnz, (unsigned long long)k * (kin[0] + kin[1] + kin[2] + kin[3]));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sweep toward V (eqn:HR) producing R^{l-1}: per input pair q = (P, C) at
+// level l - 1 with C = 4B + c, the outputs are (A_alpha = 4P + alpha, B) at l:
+//   Z = [H_alpha^* R^l_{(A_alpha, B)}]_alpha,
+//   H_alpha^*[s][t] = conj K(c_A, g^C_s) M^B_t(g^C_s) K(c_A, g^B_t),
+//   Z ~= R^{l-1} [Hbar_alpha],  R^{l-1} = U_k S_k,  Hbar^* rows = (Z^* U_k S_k^-1).
+// The block of output (A_alpha, B), child c, row m (output rank index),
+// column j (input rank index) goes to stage[pout][c][m][j].
+// ---------------------------------------------------------------------------
+template <int R2>
+__global__ __launch_bounds__(kB2) void k2_sweep_h(BoxDev B, int l, const double* __restrict__ z,
+                                                  const double* __restrict__ lc,
+                                                  const double2* __restrict__ Rcur,
+                                                  const int* __restrict__ rcur,
+                                                  double2* __restrict__ Rnext,
+                                                  int* __restrict__ rnext, int* __restrict__ kmax,
+                                                  double2* __restrict__ stage,
+                                                  unsigned long long* __restrict__ nnz,
+                                                  int64_t npairs, double tol) {
+  __shared__ double lcs[4 * R2 * R2];
+  for (int e = threadIdx.x; e < 4 * R2 * R2; e += kB2) lcs[e] = lc[e];
+  __syncthreads();
+  IBF2_GROUP_INDEX
+  const int r = B.r, L = B.L;
+  const int shq = 2 * (L - l + 1);
+  const int64_t q = p;
+  const int64_t P = q >> shq, C = q & (((int64_t)1 << shq) - 1);
+  const int64_t Bb = C >> 2;
+  const int c = (int)(C & 3);
+  double cc1, cc2, cb1, cb2;
+  cxi2(B, L - l + 1, C, cc1, cc2);
+  cxi2(B, L - l, Bb, cb1, cb2);
+  const double wc = B.w / ldexp(1.0, L - l + 1), wb = B.w / ldexp(1.0, L - l);
+  const int sl = row ? lane : 0;
+  const double gc1 = gpt(cc1, wc, z[sl / r]), gc2 = gpt(cc2, wc, z[sl % r]);
+  const double gb1 = gpt(cb1, wb, z[sl / r]), gb2 = gpt(cb2, wb, z[sl % r]);
+  const double* lcc = lcs + c * R2 * R2;                 // lcc[t * R2 + s] = M^B_t(g^C_s)
+  int64_t pout[4];
+  int kout[4];
+  double2 ds[4], et[4];
+#pragma unroll
+  for (int al = 0; al < 4; ++al) {
+    const int64_t A = 4 * P + al;
+    pout[al] = (A << (2 * (L - l))) + Bb;
+    kout[al] = rcur[pout[al]];
+    double ca1, ca2;
+    cx2(l, A, ca1, ca2);
+    ds[al] = conjd(kval2(B.ph, ca1, ca2, gc1, gc2));      // this lane's row s
+    et[al] = kval2(B.ph, ca1, ca2, gb1, gb2);             // lane t holds E_t
+  }
+  auto zcol = [&](int al, int m) -> double2 {
+    const double2* rs = Rcur + pout[al] * R2 * R2 + m;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int t = 0; t < R2; ++t)
+      cfma(acc, cscale(shfl2(et[al], t), lcc[t * R2 + sl]), rs[t * R2]);
+    return row ? cmul(ds[al], acc) : make_double2(0.0, 0.0);
+  };
+  double2 gram[R2];
+#pragma unroll
+  for (int j = 0; j < R2; ++j) gram[j] = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int al = 0; al < 4; ++al)
+    for (int m = 0; m < kout[al]; ++m) {
+      const double2 w = zcol(al, m);
+#pragma unroll
+      for (int j = 0; j < R2; ++j) cfma(gram[j], w, conjd(shfl2(w, j)));
+    }
+  double lam[R2];
+  jacobi_eig<R2, kGroup>(gram, lam);
+  int pos[R2];
+  const int k = eig_rank<R2>(lam, tol, pos);
+  double2* rrow = Rnext + (q * R2 + sl) * R2;
+#pragma unroll
+  for (int j = 0; j < R2; ++j) {
+    const bool keep = pos[j] < k && lam[j] > 0.0;
+    if (row) rrow[pos[j]] = keep ? cscale(gram[j], 1.0 / sqrt(lam[j])) : make_double2(0.0, 0.0);
+  }
+  const int my_pos = sel<R2>(pos, sl);
+  const double my_lam = sel<R2>(lam, sl);
+  const double my_sc = (my_pos < k && my_lam > 0.0) ? pow(my_lam, -1.5) : 0.0;
+#pragma unroll
+  for (int al = 0; al < 4; ++al) {
+    double2* st = stage + (pout[al] * 4 + c) * R2 * R2;
+    for (int m = 0; m < R2; ++m) {
+      if (m < kout[al]) {
+        const double2 w = zcol(al, m);
+        double2 mine = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < R2; ++j) {
+          const double2 v = csum(cmul(conjd(gram[j]), w));
+          if (lane == j) mine = v;
+        }
+        if (row) st[m * R2 + my_pos] = cscale(conjd(mine), my_sc);
+      } else if (row) {
+        st[m * R2 + sl] = make_double2(0.0, 0.0);
+      }
+    }
+  }
+  if (lane == 0) {
+    rnext[q] = k;
+    atomicMax(kmax, k);
+    atomicAdd(nnz, (unsigned long long)k * (kout[0] + kout[1] + kout[2] + kout[3]));
+  }
+}
+
+// stored[p][c kin + s][t < kld] from stage[p][c][t][s] (FP64, R2 x R2 per child)
+template <typename FT>
+__global__ void k2_pack_stage(const double2* __restrict__ stage, FT* __restrict__ out,
+                              int64_t npairs, int R2, int kin, int kout, int kld) {
+  const int64_t per = (int64_t)4 * kin * kld;
+  const int64_t total = npairs * per;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = e / per;
+    const int rem = (int)(e - p * per);
+    const int rowi = rem / kld, t = rem - rowi * kld;
+    const int c = rowi / kin, s = rowi - c * kin;
+    const double2 v = t < kout ? stage[((p * 4 + c) * R2 + t) * R2 + s] : make_double2(0.0, 0.0);
+    store_factor(out, e, v);
+  }
+}
+
+// Vbar = R^{lV *} V^* (eqn:V0): one thread per (Omega point i, T_X box a @ lV)
+//   V^*[t][xi] = conj K(c_A, g^B_t) M^B_t(xi) K(c_A, xi)
+template <int R2, typename FT>
+__global__ __launch_bounds__(256) void k2_vbar(BoxDev B, const double* __restrict__ z, const double* __restrict__ xis,
+                        const int32_t* __restrict__ xileaf, int64_t m,
+                        const double2* __restrict__ Rb, const int* __restrict__ rk, int K,
+                        FT* __restrict__ vbar, unsigned long long* __restrict__ nnz) {
+  const int na = 1 << (2 * B.lV);
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * na) return;
+  const int64_t i = e / na;
+  const int a = (int)(e % na);
+  const int lO = B.L - B.lV;
+  const int64_t b = xileaf[i];
+  const int64_t p = ((int64_t)a << (2 * lO)) + b;
+  double ca1, ca2, cb1, cb2;
+  cx2(B.lV, a, ca1, ca2);
+  cxi2(B, lO, b, cb1, cb2);
+  const double wb = B.w / ldexp(1.0, lO);
+  const double x1 = xis[2 * i], x2 = xis[2 * i + 1];
+  double y1, y2;
+  {
+#pragma clang fp contract(off)
+    y1 = (x1 - cb1) / wb;
+    y2 = (x2 - cb2) / wb;
+  }
+  const double2 kx = kval2(B.ph, ca1, ca2, x1, x2);
+  const int r = B.r;
+  double2 acc[R2];
+#pragma unroll
+  for (int k = 0; k < R2; ++k) acc[k] = make_double2(0.0, 0.0);
+  for (int t = 0; t < R2; ++t) {
+    const double2 kb = conjd(kval2(B.ph, ca1, ca2, gpt(cb1, wb, z[t / r]), gpt(cb2, wb, z[t % r])));
+    const double2 v = cscale(cmul(kb, kx), lag2(z, r, t, y1, y2));
+    const double2* rr = Rb + (p * R2 + t) * R2;
+#pragma unroll
+    for (int k = 0; k < R2; ++k) cfma(acc[k], conjd(rr[k]), v);
+  }
+  FT* o = vbar + (i * na + a) * K;
+#pragma unroll
+  for (int k = 0; k < R2; ++k)
+    if (k < K) store_factor(o, k, acc[k]);
+  atomicAdd(nnz, (unsigned long long)rk[p]);
+}
+
+// Ubar = U C^L: one thread per X point (sorted into the level-L boxes)
+//   U[x][t] = K(x, c_B) M^A_t(x) conj K(g^A_t, c_B),  B = the box itself
+template <int R2, typename FT>
+__global__ __launch_bounds__(256) void k2_ubar(BoxDev B, const double* __restrict__ z, const double* __restrict__ xs,
+                        const int32_t* __restrict__ xleaf, int64_t n,
+                        const double2* __restrict__ Cb, const int* __restrict__ rk, int K,
+                        FT* __restrict__ ubar, unsigned long long* __restrict__ nnz) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t a = xleaf[i];
+  double ca1, ca2;
+  cx2(B.L, a, ca1, ca2);
+  const double wa = ldexp(1.0, -B.L);
+  double cb1, cb2;
+  {
+#pragma clang fp contract(off)
+    cb1 = B.o1 + B.w / 2.0;
+    cb2 = B.o2 + B.w / 2.0;
+  }
+  const double x1 = xs[2 * i], x2 = xs[2 * i + 1];
+  double y1, y2;
+  {
+#pragma clang fp contract(off)
+    y1 = (x1 - ca1) / wa;
+    y2 = (x2 - ca2) / wa;
+  }
+  const double2 kx = kval2(B.ph, x1, x2, cb1, cb2);
+  const int r = B.r;
+  double2 acc[R2];
+#pragma unroll
+  for (int k = 0; k < R2; ++k) acc[k] = make_double2(0.0, 0.0);
+  for (int t = 0; t < R2; ++t) {
+    const double2 kg =
+        conjd(kval2(B.ph, gpt(ca1, wa, z[t / r]), gpt(ca2, wa, z[t % r]), cb1, cb2));
+    const double2 u = cscale(cmul(kx, kg), lag2(z, r, t, y1, y2));
+    const double2* cr = Cb + (a * R2 + t) * R2;
+#pragma unroll
+    for (int k = 0; k < R2; ++k) cfma(acc[k], u, cr[k]);
+  }
+  FT* o = ubar + i * K;
+#pragma unroll
+  for (int k = 0; k < R2; ++k)
+    if (k < K) store_factor(o, k, acc[k]);
+  atomicAdd(nnz, (unsigned long long)rk[a]);
+}
+
+// Centre block K_C[x][j] = K(x, xi_j) for the centre points (stored like a factor)
+template <typename FT>
+__global__ void k2_centre(PhaseDesc ph, const double* __restrict__ x, int64_t nx,
+                          const double* __restrict__ xic, int nc, FT* __restrict__ kc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nx * nc) return;
+  const int64_t i = e / nc;
+  const int j = (int)(e % nc);
+  store_factor(kc, e, kval2(ph, x[2 * i], x[2 * i + 1], xic[2 * j], xic[2 * j + 1]));
+}
+
+// ---------------------------------------------------------------------------
+// Apply
+// ---------------------------------------------------------------------------
+template <typename VT> struct Zero2;
+template <> struct Zero2<double2> { __device__ static double2 v() { return make_double2(0, 0); } };
+template <> struct Zero2<float2> { __device__ static float2 v() { return make_float2(0, 0); } };
+
+// mu[(a, b)][k][n] = sum_{xi in leaf b} Vbar[xi][a][k] g[xi][n]
+template <typename VT, typename FT>
+__global__ void k2_apply_v(const VT* __restrict__ g, int64_t ldg, const int32_t* __restrict__ perm,
+                           const int32_t* __restrict__ off, const FT* __restrict__ vbar,
+                           VT* __restrict__ mu, int lV, int lO, int K, int nrhs) {
+  const int na = 1 << (2 * lV);
+  const int64_t nb = (int64_t)1 << (2 * lO);
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)na * nb * K * nrhs;
+  if (e >= total) return;
+  const int n = (int)(e % nrhs);
+  const int k = (int)((e / nrhs) % K);
+  const int64_t pp = e / ((int64_t)nrhs * K);          // pair (a, b) at level lV
+  const int64_t a = pp / nb, b = pp % nb;
+  VT acc = Zero2<VT>::v();
+  for (int32_t i = off[b]; i < off[b + 1]; ++i)
+    cfma(acc, load_factor(vbar, ((int64_t)i * na + a) * K + k), g[(int64_t)n * ldg + perm[i]]);
+  mu[e] = acc;
+}
+
+// out[(a, b)][t][n] = sum_{row < 4 kin} F[(a, b)][row][t] in[(a >> 2, 4b) row][n]
+template <typename VT, typename FT>
+__global__ void k2_apply_stage(const VT* __restrict__ in, VT* __restrict__ out,
+                               const FT* __restrict__ blk, int L, int l, int kin, int kout,
+                               int kld, int nrhs) {
+  const int64_t npairs = (int64_t)1 << (2 * L);
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= npairs * kout * nrhs) return;
+  const int n = (int)(e % nrhs);
+  const int t = (int)((e / nrhs) % kout);
+  const int64_t p = e / ((int64_t)nrhs * kout);
+  const int sh = 2 * (L - l);
+  const int64_t a = p >> sh, b = p & (((int64_t)1 << sh) - 1);
+  const int64_t pin0 = ((a >> 2) << (sh + 2)) + 4 * b;
+  const FT* f = blk + p * 4 * kin * kld + t;
+  const VT* x = in + pin0 * kin * nrhs + n;
+  VT acc = Zero2<VT>::v();
+  for (int row = 0; row < 4 * kin; ++row)
+    cfma(acc, load_factor(f, (int64_t)row * kld), x[(int64_t)row * nrhs]);
+  out[e] = acc;
+}
+
+// u[x][n] += sum_k Ubar[x][k] mu[(leaf(x), box)][k][n]
+template <typename VT, typename FT>
+__global__ void k2_apply_u(const VT* __restrict__ mu, const FT* __restrict__ ubar, int K,
+                           const int32_t* __restrict__ perm, const int32_t* __restrict__ leaf,
+                           int64_t n, VT* __restrict__ u, int64_t ldu, int nrhs) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * nrhs) return;
+  const int64_t i = e / nrhs;
+  const int c = (int)(e % nrhs);
+  const VT* m = mu + (int64_t)leaf[i] * K * nrhs + c;
+  VT acc = Zero2<VT>::v();
+  for (int k = 0; k < K; ++k) cfma(acc, load_factor(ubar, i * K + k), m[(int64_t)k * nrhs]);
+  VT* o = u + (int64_t)c * ldu + perm[i];
+  VT cur = *o;
+  cur.x += acc.x;
+  cur.y += acc.y;
+  *o = cur;
+}
+
+// u[x][n] = sum_j K_C[x][j] g[centre_j][n]   (writes u; runs first)
+template <typename VT, typename FT>
+__global__ void k2_apply_centre(const FT* __restrict__ kc, int nc,
+                                const int32_t* __restrict__ cidx, const VT* __restrict__ g,
+                                int64_t ldg, int64_t nx, VT* __restrict__ u, int64_t ldu,
+                                int nrhs) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nx * nrhs) return;
+  const int64_t i = e % nx;
+  const int c = (int)(e / nx);
+  VT acc = Zero2<VT>::v();
+  for (int j = 0; j < nc; ++j)
+    cfma(acc, load_factor(kc, i * nc + j), g[(int64_t)c * ldg + cidx[j]]);
+  u[(int64_t)c * ldu + i] = acc;
+}
+
+inline unsigned nblk(int64_t total) { return (unsigned)((total + kB2 - 1) / kB2); }
+
+}  // namespace
+}  // namespace ibf
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+namespace ibf {
+namespace {
+
+#define IBF2_DISPATCH_R2(R2V, LAUNCH)                      \
+  switch (R2V) {                                           \
+    case 4: LAUNCH(4); break;                              \
+    case 9: LAUNCH(9); break;                              \
+    case 16: LAUNCH(16); break;                            \
+    default: LAUNCH(25); break;                            \
+  }
+
+int64_t morton_host(int64_t i1, int64_t i2, int level) {
+  int64_t code = 0;
+  for (int j = 0; j < level; ++j) code |= (((i1 >> j) & 1) * 2 + ((i2 >> j) & 1)) << (2 * j);
+  return code;
+}
+
+// counting sort of codes in [0, nbin): perm (sorted -> input position), CSR offsets, bin per sorted
+void sort_codes(const std::vector<int64_t>& code, int64_t nbin, std::vector<int32_t>& perm,
+                std::vector<int32_t>& off, std::vector<int32_t>& bin) {
+  off.assign(nbin + 1, 0);
+  for (int64_t c : code) ++off[c + 1];
+  for (int64_t b = 0; b < nbin; ++b) off[b + 1] += off[b];
+  std::vector<int32_t> fill(off.begin(), off.end() - 1);
+  perm.assign(code.size(), 0);
+  bin.assign(code.size(), 0);
+  for (size_t i = 0; i < code.size(); ++i) {
+    const int32_t at = fill[code[i]]++;
+    perm[at] = (int32_t)i;
+    bin[at] = (int32_t)code[i];
+  }
+}
+
+template <typename T>
+int upload(T** d, const T* h, size_t n) {
+  IBF_HIP_CHECK(hipMalloc(d, std::max<size_t>(n * sizeof(T), 1)));
+  if (n) IBF_HIP_CHECK(hipMemcpy(*d, h, n * sizeof(T), hipMemcpyHostToDevice));
+  return IBF_OK;
+}
+
+struct Scratch2 {
+  double2* C[2] = {nullptr, nullptr};
+  double2* R[2] = {nullptr, nullptr};
+  int* rc[2] = {nullptr, nullptr};
+  int* rr[2] = {nullptr, nullptr};
+  double2* stage = nullptr;
+  int* kmax = nullptr;                    // [2][64]: G side at [l], H side at [64 + l]
+  unsigned long long* nnz = nullptr;
+  ~Scratch2() {
+    for (int i = 0; i < 2; ++i) {
+      if (C[i]) (void)hipFree(C[i]);
+      if (R[i]) (void)hipFree(R[i]);
+      if (rc[i]) (void)hipFree(rc[i]);
+      if (rr[i]) (void)hipFree(rr[i]);
+    }
+    if (stage) (void)hipFree(stage);
+    if (kmax) (void)hipFree(kmax);
+    if (nnz) (void)hipFree(nnz);
+  }
+};
+
+int read_int(const int* d, int* h, hipStream_t s) {
+  IBF_HIP_CHECK(hipMemcpyAsync(h, d, sizeof(int), hipMemcpyDeviceToHost, s));
+  IBF_HIP_CHECK(hipStreamSynchronize(s));
+  return IBF_OK;
+}
+
+template <typename FT>
+int pack_stage(Box2& bx, Mibf2D& M, const double2* stage, int level, int kin, int kout,
+               hipStream_t s) {
+  Stage2 st;
+  st.level = level;
+  st.kin = kin;
+  st.kout = kout;
+  st.kld = (kout + 1) & ~1;
+  const int64_t np = (int64_t)1 << (2 * bx.L);
+  const int64_t count = np * 4 * kin * st.kld;
+  st.bytes = (size_t)count * sizeof(FT);
+  IBF_HIP_CHECK(hipMalloc(&st.blk, std::max<size_t>(st.bytes, 1)));
+  const unsigned g = (unsigned)std::min<int64_t>((count + kB2 - 1) / kB2, 1 << 20);
+  hipLaunchKernelGGL((k2_pack_stage<FT>), dim3(std::max(g, 1u)), dim3(kB2), 0, s, stage,
+                     (FT*)st.blk, np, M.R2, kin, kout, st.kld);
+  IBF_HIP_CHECK(hipGetLastError());
+  bx.stages.push_back(st);
+  M.nnz_stored += count;
+  return IBF_OK;
+}
+
+template <typename FT>
+int build2d_t(ibf_plan_t p, hipStream_t s) {
+  Mibf2D& M = *p->mibf;
+  const int R2 = M.R2, r = M.r;
+  // tables and X points
+  IBF_HIP_CHECK(hipMalloc(&M.d_z, sizeof(double) * r));
+  IBF_HIP_CHECK(hipMalloc(&M.d_lc, sizeof(double) * 4 * R2 * R2));
+  hipLaunchKernelGGL(k2_tables, dim3((4 * R2 * R2 + kB2 - 1) / kB2), dim3(kB2), 0, s, r, M.d_z,
+                     M.d_lc);
+  IBF_HIP_CHECK(hipGetLastError());
+  // centre block
+  const int nc = (int)M.centre.size();
+  if (nc > 0) {
+    std::vector<double> xic(2 * (size_t)nc);
+    for (int j = 0; j < nc; ++j) {
+      xic[2 * j] = M.xi_host[2 * (size_t)M.centre[j]];
+      xic[2 * j + 1] = M.xi_host[2 * (size_t)M.centre[j] + 1];
+    }
+    double* d_xic = nullptr;
+    int rc;
+    if ((rc = upload(&d_xic, xic.data(), xic.size()))) return rc;
+    if ((rc = upload(&M.d_cidx, M.centre.data(), M.centre.size()))) return rc;
+    IBF_HIP_CHECK(hipMalloc(&M.d_kc, std::max<size_t>(sizeof(FT) * M.nx * nc, 1)));
+    hipLaunchKernelGGL((k2_centre<FT>), dim3(nblk(M.nx * nc)), dim3(kB2), 0, s, M.ph, M.d_x,
+                       M.nx, d_xic, nc, (FT*)M.d_kc);
+    IBF_HIP_CHECK(hipGetLastError());
+    IBF_HIP_CHECK(hipStreamSynchronize(s));
+    (void)hipFree(d_xic);
+    M.factor_bytes += (int64_t)(sizeof(FT) * M.nx * nc);
+    M.nnz_opt += M.nx * nc;
+    M.nnz_stored += M.nx * nc;
+  }
+  // scratch for the largest box
+  const int64_t npmax = (int64_t)1 << (2 * M.maxL);
+  Scratch2 S;
+  const size_t bsz = sizeof(double2) * (size_t)npmax * R2 * R2;
+  for (int i = 0; i < 2; ++i) {
+    IBF_HIP_CHECK(hipMalloc(&S.C[i], bsz));
+    IBF_HIP_CHECK(hipMalloc(&S.R[i], bsz));
+    IBF_HIP_CHECK(hipMalloc(&S.rc[i], sizeof(int) * npmax));
+    IBF_HIP_CHECK(hipMalloc(&S.rr[i], sizeof(int) * npmax));
+  }
+  IBF_HIP_CHECK(hipMalloc(&S.stage, 4 * bsz));
+  IBF_HIP_CHECK(hipMalloc(&S.kmax, sizeof(int) * 128));
+  IBF_HIP_CHECK(hipMalloc(&S.nnz, sizeof(unsigned long long)));
+
+  int rc;
+  for (Box2& bx : M.boxes) {
+    const BoxDev B{M.ph, bx.o1, bx.o2, bx.w, bx.L, bx.lV, bx.h, r};
+    const int L = bx.L, lV = bx.lV, h = bx.h;
+    const int64_t np = (int64_t)1 << (2 * L);
+    const unsigned gg = (unsigned)((np * kGroup + kB2 - 1) / kB2);
+    std::vector<int> kg(L + 1, 0), kh(L + 1, 0);
+    IBF_HIP_CHECK(hipMemsetAsync(S.kmax, 0, sizeof(int) * 128, s));
+    IBF_HIP_CHECK(hipMemsetAsync(S.nnz, 0, sizeof(unsigned long long), s));
+#define IBF2_MIDDLE(RR)                                                                          \
+  hipLaunchKernelGGL((k2_middle<RR>), dim3(gg), dim3(kB2), 0, s, B, M.d_z, S.C[0], S.R[0],      \
+                     S.rc[0], S.kmax + h, S.nnz, np, M.tol)
+    IBF2_DISPATCH_R2(R2, IBF2_MIDDLE);
+#undef IBF2_MIDDLE
+    IBF_HIP_CHECK(hipGetLastError());
+    IBF_HIP_CHECK(hipMemcpyAsync(S.rr[0], S.rc[0], sizeof(int) * np, hipMemcpyDeviceToDevice, s));
+    if ((rc = read_int(S.kmax + h, &kg[h], s))) return rc;
+    kh[h] = kg[h];
+    // toward U
+    int cc = 0;
+    std::vector<Stage2> gst;
+    for (int l = h + 1; l <= L; ++l) {
+#define IBF2_SWG(RR)                                                                             \
+  hipLaunchKernelGGL((k2_sweep_g<RR>), dim3(gg), dim3(kB2), 0, s, B, l, M.d_z, M.d_lc, S.C[cc], \
+                     S.rc[cc], S.C[cc ^ 1], S.rc[cc ^ 1], S.kmax + l, S.stage, S.nnz, np, M.tol)
+      IBF2_DISPATCH_R2(R2, IBF2_SWG);
+#undef IBF2_SWG
+      IBF_HIP_CHECK(hipGetLastError());
+      if ((rc = read_int(S.kmax + l, &kg[l], s))) return rc;
+      if ((rc = pack_stage<FT>(bx, M, S.stage, l, kg[l - 1], kg[l], s))) return rc;
+      gst.push_back(bx.stages.back());
+      bx.stages.pop_back();
+      cc ^= 1;
+    }
+    // toward V
+    int cr = 0;
+    std::vector<Stage2> hst;
+    for (int l = h; l > lV; --l) {
+#define IBF2_SWH(RR)                                                                             \
+  hipLaunchKernelGGL((k2_sweep_h<RR>), dim3(gg), dim3(kB2), 0, s, B, l, M.d_z, M.d_lc, S.R[cr], \
+                     S.rr[cr], S.R[cr ^ 1], S.rr[cr ^ 1], S.kmax + 64 + l - 1, S.stage, S.nnz, \
+                     np, M.tol)
+      IBF2_DISPATCH_R2(R2, IBF2_SWH);
+#undef IBF2_SWH
+      IBF_HIP_CHECK(hipGetLastError());
+      if ((rc = read_int(S.kmax + 64 + l - 1, &kh[l - 1], s))) return rc;
+      if ((rc = pack_stage<FT>(bx, M, S.stage, l, kh[l - 1], kh[l], s))) return rc;
+      hst.push_back(bx.stages.back());
+      bx.stages.pop_back();
+      cr ^= 1;
+    }
+    // apply order: H stages lV+1..h, then G stages h+1..L
+    bx.stages.clear();
+    for (auto it = hst.rbegin(); it != hst.rend(); ++it) bx.stages.push_back(*it);
+    for (auto& st : gst) bx.stages.push_back(st);
+    bx.rank.assign(L - lV + 1, 0);
+    for (int l = lV; l <= L; ++l) bx.rank[l - lV] = l <= h ? kh[l] : kg[l];
+    // outer factors
+    const XTree2& xt = M.xtrees[bx.xt];
+    bx.K_V = std::max(kh[lV], 1);
+    bx.K_U = std::max(kg[L], 1);
+    const int na = 1 << (2 * lV);
+    bx.vbar_bytes = sizeof(FT) * (size_t)bx.m * na * bx.K_V;
+    bx.ubar_bytes = sizeof(FT) * (size_t)M.nx * bx.K_U;
+    IBF_HIP_CHECK(hipMalloc(&bx.d_vbar, std::max<size_t>(bx.vbar_bytes, 1)));
+    IBF_HIP_CHECK(hipMalloc(&bx.d_ubar, std::max<size_t>(bx.ubar_bytes, 1)));
+    if (bx.m > 0) {
+#define IBF2_VBAR(RR)                                                                            \
+  hipLaunchKernelGGL((k2_vbar<RR, FT>), dim3(nblk(bx.m * na)), dim3(kB2), 0, s, B, M.d_z,       \
+                     bx.d_xis, bx.d_xileaf, bx.m, S.R[cr], S.rr[cr], bx.K_V, (FT*)bx.d_vbar,    \
+                     S.nnz)
+      IBF2_DISPATCH_R2(R2, IBF2_VBAR);
+#undef IBF2_VBAR
+      IBF_HIP_CHECK(hipGetLastError());
+    }
+#define IBF2_UBAR(RR)                                                                            \
+  hipLaunchKernelGGL((k2_ubar<RR, FT>), dim3(nblk(M.nx)), dim3(kB2), 0, s, B, M.d_z, xt.d_xs,   \
+                     xt.d_leaf, M.nx, S.C[cc], S.rc[cc], bx.K_U, (FT*)bx.d_ubar, S.nnz)
+    IBF2_DISPATCH_R2(R2, IBF2_UBAR);
+#undef IBF2_UBAR
+    IBF_HIP_CHECK(hipGetLastError());
+    unsigned long long nn = 0;
+    IBF_HIP_CHECK(hipMemcpyAsync(&nn, S.nnz, sizeof(nn), hipMemcpyDeviceToHost, s));
+    IBF_HIP_CHECK(hipStreamSynchronize(s));
+    bx.nnz_opt = (int64_t)nn;
+    M.nnz_opt += bx.nnz_opt;
+    M.nnz_stored += (int64_t)bx.m * na * bx.K_V + M.nx * bx.K_U;
+    M.factor_bytes += (int64_t)(bx.vbar_bytes + bx.ubar_bytes);
+    for (auto& st : bx.stages) M.factor_bytes += (int64_t)st.bytes;
+  }
+  M.built = true;
+  return IBF_OK;
+}
+
+template <typename VT, typename FT>
+int apply2d_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int nrhs,
+              hipStream_t s) {
+  Mibf2D& M = *p->mibf;
+  size_t need = 0;
+  for (const Box2& bx : M.boxes) {
+    int kmx = 1;
+    for (int k : bx.rank) kmx = std::max(kmx, k);
+    need = std::max(need, ((size_t)1 << (2 * bx.L)) * kmx * nrhs * sizeof(VT));
+  }
+  if (need > M.work_bytes) {
+    for (int i = 0; i < 2; ++i) {
+      if (M.d_work[i]) (void)hipFree(M.d_work[i]);
+      M.d_work[i] = nullptr;
+    }
+    M.work_bytes = 0;
+    IBF_HIP_CHECK(hipMalloc(&M.d_work[0], need));
+    IBF_HIP_CHECK(hipMalloc(&M.d_work[1], need));
+    M.work_bytes = need;
+  }
+  VT* w[2] = {(VT*)M.d_work[0], (VT*)M.d_work[1]};
+  const int nc = (int)M.centre.size();
+  // the centre block writes every entry of u; the boxes then accumulate
+  hipLaunchKernelGGL((k2_apply_centre<VT, FT>), dim3(nblk(M.nx * nrhs)), dim3(kB2), 0, s,
+                     (const FT*)M.d_kc, nc, M.d_cidx, (const VT*)g, ldg, M.nx, (VT*)u, ldu, nrhs);
+  IBF_HIP_CHECK(hipGetLastError());
+  for (const Box2& bx : M.boxes) {
+    const int lO = bx.L - bx.lV;
+    const int64_t npv = ((int64_t)1 << (2 * bx.lV)) * ((int64_t)1 << (2 * lO));
+    hipLaunchKernelGGL((k2_apply_v<VT, FT>), dim3(nblk(npv * bx.K_V * nrhs)), dim3(kB2), 0, s,
+                       (const VT*)g, ldg, bx.d_perm_xi, bx.d_xioff, (const FT*)bx.d_vbar, w[0],
+                       bx.lV, lO, bx.K_V, nrhs);
+    IBF_HIP_CHECK(hipGetLastError());
+    int cur = 0;
+    for (const Stage2& st : bx.stages) {
+      const int64_t np = (int64_t)1 << (2 * bx.L);
+      hipLaunchKernelGGL((k2_apply_stage<VT, FT>), dim3(nblk(np * st.kout * nrhs)), dim3(kB2),
+                         0, s, w[cur], w[cur ^ 1], (const FT*)st.blk, bx.L, st.level, st.kin,
+                         st.kout, st.kld, nrhs);
+      IBF_HIP_CHECK(hipGetLastError());
+      cur ^= 1;
+    }
+    const XTree2& xt = M.xtrees[bx.xt];
+    hipLaunchKernelGGL((k2_apply_u<VT, FT>), dim3(nblk(M.nx * nrhs)), dim3(kB2), 0, s, w[cur],
+                       (const FT*)bx.d_ubar, bx.K_U, xt.d_perm, xt.d_leaf, M.nx, (VT*)u, ldu,
+                       nrhs);
+    IBF_HIP_CHECK(hipGetLastError());
+  }
+  return IBF_OK;
+}
+
+}  // namespace
+
+int plan2d(const ibf_desc* d, ibf_plan_t* out) {
+  auto bad = [](const char* msg) {
+    set_error(msg);
+    return IBF_ERR_INVALID_ARG;
+  };
+  if (d->r < 2 || d->r > 5) {
+    set_error("ibf_plan: dim 2 supports r = 2 .. 5 (r^2 <= 25 grid points per box)");
+    return d->r < 2 ? IBF_ERR_INVALID_ARG : IBF_ERR_UNSUPPORTED;
+  }
+  if (!(d->tol >= 1e-7 && d->tol < 1.0))
+    return bad("ibf_plan: dim 2 needs 1e-7 <= tol < 1 (Gram-based compression)");
+  int leaf_side = 0;
+  for (int s = 1; s <= 8; s *= 2)
+    if (s * s == d->leaf) leaf_side = s;
+  if (leaf_side < 2) return bad("ibf_plan: dim 2 needs leaf = 4, 16 or 64 points (a square)");
+  if (d->precision < IBF_FP64 || d->precision > IBF_BF16X2)
+    return bad("ibf_plan: unknown precision");
+  if (d->sweep_in != 0) {
+    set_error("ibf_plan: the sweep-in stage is not provided for dim 2");
+    return IBF_ERR_UNSUPPORTED;
+  }
+  const double W = d->omega_width;
+  int Lw = 0;
+  while ((double)((int64_t)1 << Lw) < W) ++Lw;
+  if (!(W > 0) || (double)((int64_t)1 << Lw) != W || W < 2 * kCentreSide || Lw > 24)
+    return bad("ibf_plan: dim 2 needs omega_width a power of two >= 32");
+  if (d->omega_lo != -W / 2) return bad("ibf_plan: dim 2 needs omega_lo = -omega_width / 2");
+  PhaseDesc ph{};
+  ph.kind = d->phase_id;
+  const double* pp = d->phase_params;
+  const int np = d->n_params;
+  if (np < 0 || np > kMaxParams || (np > 0 && !pp)) return bad("ibf_plan: bad phase parameters");
+  switch (d->phase_id) {
+    case IBF_PHASE_DFT:
+      ph.p[0] = np >= 1 ? pp[0] : 1.0;
+      if (ph.p[0] != 1.0 && ph.p[0] != -1.0) return bad("ibf_plan: DFT sign must be +1 or -1");
+      break;
+    case IBF_PHASE_FIO2D:
+      ph.p[0] = np >= 1 ? pp[0] : 2.0;
+      ph.p[1] = np >= 2 ? pp[1] : 1.0;
+      ph.p[2] = np >= 3 ? pp[2] : 16.0;
+      if (ph.p[2] == 0.0) return bad("ibf_plan: p2 == 0");
+      break;
+    case IBF_PHASE_SEPARABLE:
+      ph.p[0] = np >= 1 ? pp[0] : 3.0;
+      ph.p[1] = np >= 2 ? pp[1] : 0.3125;
+      break;
+    default:
+      set_error("ibf_plan: unsupported phase for dim 2");
+      return IBF_ERR_UNSUPPORTED;
+  }
+  auto M = new Mibf2D();
+  M->ph = ph;
+  M->r = d->r;
+  M->R2 = d->r * d->r;
+  M->leaf_side = leaf_side;
+  M->precision = d->precision;
+  M->device = d->device;
+  M->tol = d->tol;
+  M->W = W;
+  M->nx = d->n_x;
+  M->nxi = d->n_xi;
+  for (int64_t i = 0; i < 2 * d->n_x; ++i)
+    if (!(d->x[i] >= 0.0 && d->x[i] < 1.0)) {
+      delete M;
+      return bad("ibf_plan: x outside [0, 1)^2");
+    }
+  M->xi_host.assign(d->xi, d->xi + 2 * d->n_xi);
+  // coronas (eq:domaindecomp): boxes of side W / 2^(t+2) between the squares of
+  // half-width W / 2^(t+1) and W / 2^(t+2); centre [-c/2, c/2)^2
+  struct BoxGeo { double o1, o2, w; };
+  std::vector<BoxGeo> geo;
+  std::vector<int> first_box;           // index of the first box of corona t
+  for (int t = 0;; ++t) {
+    const double hw = W / std::ldexp(1.0, t + 1), w = W / std::ldexp(1.0, t + 2);
+    if (!(hw > kCentreSide / 2) || w < leaf_side) break;
+    first_box.push_back((int)geo.size());
+    for (int i1 = 0; i1 < 4; ++i1)
+      for (int i2 = 0; i2 < 4; ++i2) {
+        if (i1 >= 1 && i1 <= 2 && i2 >= 1 && i2 <= 2) continue;
+        geo.push_back({-hw + i1 * w, -hw + i2 * w, w});
+      }
+  }
+  const double hc = W / std::ldexp(1.0, (int)first_box.size() + 1);   // centre half-side
+  M->box_pts.assign(geo.size(), {});
+  for (int64_t j = 0; j < d->n_xi; ++j) {
+    const double k1 = d->xi[2 * j], k2 = d->xi[2 * j + 1];
+    if (!(k1 >= -W / 2 && k1 < W / 2 && k2 >= -W / 2 && k2 < W / 2)) {
+      delete M;
+      return bad("ibf_plan: xi outside [omega_lo, omega_lo + omega_width)^2");
+    }
+    if (k1 >= -hc && k1 < hc && k2 >= -hc && k2 < hc) {
+      M->centre.push_back((int32_t)j);
+      continue;
+    }
+    int t = 0;
+    while (k1 >= -W / std::ldexp(1.0, t + 2) && k1 < W / std::ldexp(1.0, t + 2) &&
+           k2 >= -W / std::ldexp(1.0, t + 2) && k2 < W / std::ldexp(1.0, t + 2))
+      ++t;                              // inside the next inner square
+    const double hw = W / std::ldexp(1.0, t + 1), w = W / std::ldexp(1.0, t + 2);
+    const int i1 = (int)std::floor((k1 + hw) / w), i2 = (int)std::floor((k2 + hw) / w);
+    int idx = first_box[t];
+    for (int a1 = 0; a1 < 4; ++a1)
+      for (int a2 = 0; a2 < 4; ++a2) {
+        if (a1 >= 1 && a1 <= 2 && a2 >= 1 && a2 <= 2) continue;
+        if (a1 == i1 && a2 == i2) M->box_pts[idx].push_back((int32_t)j);
+        ++idx;
+      }
+  }
+  int lV = 0;
+  while ((1 << lV) < leaf_side) ++lV;
+  for (size_t i = 0; i < geo.size(); ++i) {
+    Box2 bx;
+    bx.o1 = geo[i].o1;
+    bx.o2 = geo[i].o2;
+    bx.w = geo[i].w;
+    int L = 0;
+    while ((double)(1 << L) < bx.w) ++L;
+    bx.L = L;
+    bx.lV = lV;
+    bx.h = (lV + L) / 2;
+    bx.m = (int64_t)M->box_pts[i].size();
+    M->maxL = std::max(M->maxL, L);
+    const int64_t R2 = M->R2;
+    bx.nnz_prelim = bx.m * ((int64_t)1 << (2 * lV)) * R2 + M->nx * R2 +
+                    (int64_t)(L - lV) * ((int64_t)1 << (2 * L)) * 4 * R2 * R2 +
+                    ((int64_t)1 << (2 * L)) * R2 * R2;
+    M->nnz_prelim += bx.nnz_prelim;
+    M->boxes.push_back(bx);
+  }
+  M->nnz_prelim += M->nx * (int64_t)M->centre.size();
+  auto pl = new ibf_plan_s();
+  pl->dim = 2;
+  pl->nx = d->n_x;
+  pl->nxi = d->n_xi;
+  pl->device = d->device;
+  pl->phase = ph;
+  pl->r = d->r;
+  pl->leaf = d->leaf;
+  pl->precision = d->precision;
+  pl->tol = d->tol;
+  pl->nnz_prelim = M->nnz_prelim;
+  pl->mibf = M;
+  // keep the caller's X for the device upload at build time
+  pl->xs.assign(d->x, d->x + 2 * d->n_x);
+  *out = pl;
+  return IBF_OK;
+}
+
+int build2d(ibf_plan_t p, hipStream_t s) {
+  Mibf2D& M = *p->mibf;
+  IBF_HIP_CHECK(hipSetDevice(M.device));
+  free2d_factors(p);
+  int rc;
+  if ((rc = upload(&M.d_x, p->xs.data(), p->xs.size()))) return rc;
+  // X trees, one per distinct box depth
+  for (Box2& bx : M.boxes) {
+    int found = -1;
+    for (size_t t = 0; t < M.xtrees.size(); ++t)
+      if (M.xtrees[t].L == bx.L) found = (int)t;
+    if (found < 0) {
+      XTree2 xt;
+      xt.L = bx.L;
+      const int64_t nb = (int64_t)1 << bx.L;
+      std::vector<int64_t> code(M.nx);
+      for (int64_t i = 0; i < M.nx; ++i) {
+        const int64_t i1 = std::min<int64_t>((int64_t)std::floor(p->xs[2 * i] * nb), nb - 1);
+        const int64_t i2 = std::min<int64_t>((int64_t)std::floor(p->xs[2 * i + 1] * nb), nb - 1);
+        code[i] = morton_host(i1, i2, bx.L);
+      }
+      std::vector<int32_t> perm, off, bin;
+      sort_codes(code, nb * nb, perm, off, bin);
+      std::vector<double> xs(2 * M.nx);
+      for (int64_t i = 0; i < M.nx; ++i) {
+        xs[2 * i] = p->xs[2 * (size_t)perm[i]];
+        xs[2 * i + 1] = p->xs[2 * (size_t)perm[i] + 1];
+      }
+      if ((rc = upload(&xt.d_xs, xs.data(), xs.size()))) return rc;
+      if ((rc = upload(&xt.d_perm, perm.data(), perm.size()))) return rc;
+      if ((rc = upload(&xt.d_leaf, bin.data(), bin.size()))) return rc;
+      M.xtrees.push_back(xt);
+      found = (int)M.xtrees.size() - 1;
+    }
+    bx.xt = found;
+  }
+  // Omega points of every box, sorted into its leaves
+  for (size_t i = 0; i < M.boxes.size(); ++i) {
+    Box2& bx = M.boxes[i];
+    const int lO = bx.L - bx.lV;
+    const int64_t nb = (int64_t)1 << lO;
+    const auto& pts = M.box_pts[i];
+    std::vector<int64_t> code(pts.size());
+    for (size_t j = 0; j < pts.size(); ++j) {
+      const double k1 = M.xi_host[2 * (size_t)pts[j]], k2 = M.xi_host[2 * (size_t)pts[j] + 1];
+      const int64_t j1 = std::min<int64_t>((int64_t)std::floor((k1 - bx.o1) * nb / bx.w), nb - 1);
+      const int64_t j2 = std::min<int64_t>((int64_t)std::floor((k2 - bx.o2) * nb / bx.w), nb - 1);
+      code[j] = morton_host(j1, j2, lO);
+    }
+    std::vector<int32_t> perm, off, bin;
+    sort_codes(code, nb * nb, perm, off, bin);
+    std::vector<double> xis(2 * pts.size());
+    std::vector<int32_t> cperm(pts.size());
+    for (size_t j = 0; j < pts.size(); ++j) {
+      cperm[j] = pts[perm[j]];
+      xis[2 * j] = M.xi_host[2 * (size_t)cperm[j]];
+      xis[2 * j + 1] = M.xi_host[2 * (size_t)cperm[j] + 1];
+    }
+    if ((rc = upload(&bx.d_xis, xis.data(), xis.size()))) return rc;
+    if ((rc = upload(&bx.d_perm_xi, cperm.data(), cperm.size()))) return rc;
+    if ((rc = upload(&bx.d_xileaf, bin.data(), bin.size()))) return rc;
+    if ((rc = upload(&bx.d_xioff, off.data(), off.size()))) return rc;
+  }
+  M.nnz_opt = M.nnz_stored = M.factor_bytes = 0;
+  switch (M.precision) {
+    case IBF_FP64: rc = build2d_t<double2>(p, s); break;
+    case IBF_FP32: rc = build2d_t<float2>(p, s); break;
+    default: rc = build2d_t<bf16x2c>(p, s); break;
+  }
+  if (rc) return rc;
+  IBF_HIP_CHECK(hipStreamSynchronize(s));
+  p->nnz_opt = M.nnz_opt;
+  p->nnz_stored = M.nnz_stored;
+  p->built = true;
+  return IBF_OK;
+}
+
+int apply2d(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int64_t nrhs,
+            hipStream_t s) {
+  IBF_HIP_CHECK(hipSetDevice(p->mibf->device));
+  if (nrhs > 65535) {
+    set_error("ibf_apply: nrhs too large for dim 2");
+    return IBF_ERR_INVALID_ARG;
+  }
+  switch (p->mibf->precision) {
+    case IBF_FP64: return apply2d_t<double2, double2>(p, g, ldg, u, ldu, (int)nrhs, s);
+    case IBF_FP32: return apply2d_t<float2, float2>(p, g, ldg, u, ldu, (int)nrhs, s);
+    default: return apply2d_t<float2, bf16x2c>(p, g, ldg, u, ldu, (int)nrhs, s);
+  }
+}
+
+void free2d_factors(ibf_plan_t p) {
+  if (!p->mibf) return;
+  Mibf2D& M = *p->mibf;
+  auto fr = [](void* b) {
+    if (b) (void)hipFree(b);
+  };
+  for (Box2& bx : M.boxes) {
+    for (auto& st : bx.stages) fr(st.blk);
+    bx.stages.clear();
+    fr(bx.d_vbar);
+    fr(bx.d_ubar);
+    fr(bx.d_xis);
+    fr(bx.d_perm_xi);
+    fr(bx.d_xileaf);
+    fr(bx.d_xioff);
+    bx.d_vbar = bx.d_ubar = nullptr;
+    bx.d_xis = nullptr;
+    bx.d_perm_xi = bx.d_xileaf = bx.d_xioff = nullptr;
+  }
+  for (XTree2& xt : M.xtrees) {
+    fr(xt.d_xs);
+    fr(xt.d_perm);
+    fr(xt.d_leaf);
+  }
+  M.xtrees.clear();
+  fr(M.d_x);
+  fr(M.d_cidx);
+  fr(M.d_kc);
+  fr(M.d_z);
+  fr(M.d_lc);
+  fr(M.d_work[0]);
+  fr(M.d_work[1]);
+  M.d_x = nullptr;
+  M.d_cidx = nullptr;
+  M.d_kc = nullptr;
+  M.d_z = M.d_lc = nullptr;
+  M.d_work[0] = M.d_work[1] = nullptr;
+  M.work_bytes = 0;
+  M.built = false;
+  p->built = false;
+}
+
+void destroy2d(ibf_plan_t p) {
+  if (!p->mibf) return;
+  const Mibf2D& M = *p->mibf;
+  bool touched = M.d_x || M.d_z || M.d_kc || M.d_work[0] || !M.xtrees.empty();
+  for (const Box2& bx : M.boxes) touched = touched || bx.d_xis || bx.d_vbar;
+  if (touched) {                       // a plan that never reached the device makes no HIP call
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(M.device);
+    free2d_factors(p);
+    (void)hipSetDevice(cur);
+  }
+  delete p->mibf;
+  p->mibf = nullptr;
+}
+
+void query2d(ibf_plan_t p, ibf_info* info) {
+  const Mibf2D& M = *p->mibf;
+  info->L = M.maxL;
+  info->l0 = M.boxes.empty() ? 0 : M.boxes[0].lV;
+  info->h = 0;
+  info->n_levels = 0;
+  info->n_pairs = 0;
+  for (const Box2& bx : M.boxes) info->n_pairs += (int64_t)1 << (2 * bx.L);
+  info->nnz_prelim = M.nnz_prelim;
+  info->nnz_opt = M.nnz_opt;
+  info->nnz_stored = M.nnz_stored;
+  info->factor_bytes = M.factor_bytes;
+  info->build_ms = p->build_ms;
+  // per-box level ranks of the outermost corona's first box
+  if (!M.boxes.empty()) {
+    const Box2& bx = M.boxes[0];
+    info->n_levels = (int)bx.rank.size();
+    for (size_t i = 0; i < bx.rank.size() && i < 64; ++i) info->rank[i] = bx.rank[i];
+  }
+}
+
+}  // namespace ibf

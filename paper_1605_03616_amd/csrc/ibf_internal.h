@@ -40,7 +40,12 @@ struct Stage {
 
 }  // namespace ibf
 
+namespace ibf {
+struct Mibf2D;            // 2-D multiscale plan (ibf2d.hip)
+}
+
 struct ibf_plan_s {
+  ibf::Mibf2D* mibf = nullptr;   // dim == 2: the corona boxes and the centre block
   // descriptor
   int dim = 1;
   int64_t nx = 0, nxi = 0;
@@ -94,6 +99,14 @@ int dense_apply(const PhaseDesc& ph, const double* x, int64_t nx, const double* 
 int eval_kernel(const PhaseDesc& ph, const double* x, const double* xi,
                 int64_t n, void* out, hipStream_t s);
 void free_factors(ibf_plan_t p);
+// dim == 2 (multiscale IBF over coronal boxes)
+int plan2d(const ibf_desc* d, ibf_plan_t* out);
+int build2d(ibf_plan_t p, hipStream_t s);
+int apply2d(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int64_t nrhs,
+            hipStream_t s);
+void free2d_factors(ibf_plan_t p);
+void destroy2d(ibf_plan_t p);
+void query2d(ibf_plan_t p, ibf_info* info);
 size_t complex_bytes(int precision);
 }  // namespace ibf
 

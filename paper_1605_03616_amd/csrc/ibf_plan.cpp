@@ -70,11 +70,13 @@ const char* ibf_last_error(void) { return g_last_error.c_str(); }
 int ibf_plan(const ibf_desc* d, ibf_plan_t* out) {
   if (!d || !out) return fail(IBF_ERR_INVALID_ARG, "ibf_plan: null argument");
   *out = nullptr;
-  if (d->dim != 1) return fail(IBF_ERR_UNSUPPORTED, "ibf_plan: only dim == 1 is supported");
+  if (d->dim != 1 && d->dim != 2)
+    return fail(IBF_ERR_UNSUPPORTED, "ibf_plan: dim must be 1 or 2");
   if (d->n_x < 1 || d->n_xi < 1) return fail(IBF_ERR_INVALID_ARG, "ibf_plan: empty point set");
   if (d->n_x > (int64_t)1 << 30 || d->n_xi > (int64_t)1 << 30)
     return fail(IBF_ERR_INVALID_ARG, "ibf_plan: more than 2^30 points");
   if (!d->x || !d->xi) return fail(IBF_ERR_INVALID_ARG, "ibf_plan: null point array");
+  if (d->dim == 2) return ibf::plan2d(d, out);
   if (d->r < 2) return fail(IBF_ERR_INVALID_ARG, "ibf_plan: r must be >= 2");
   if (d->r > ibf::kMaxR) return fail(IBF_ERR_UNSUPPORTED, "ibf_plan: r > 16 not supported");
   if (!(d->tol > 0.0 && d->tol < 1.0))
@@ -176,7 +178,8 @@ int ibf_plan(const ibf_desc* d, ibf_plan_t* out) {
 int ibf_build(ibf_plan_t p, void* stream) {
   if (!p) return fail(IBF_ERR_INVALID_ARG, "ibf_build: null plan");
   auto t0 = std::chrono::steady_clock::now();
-  int rc = ibf::build_plan(p, (hipStream_t)stream);
+  int rc = p->dim == 2 ? ibf::build2d(p, (hipStream_t)stream)
+                       : ibf::build_plan(p, (hipStream_t)stream);
   auto t1 = std::chrono::steady_clock::now();
   p->build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   return rc;
@@ -189,6 +192,7 @@ int ibf_apply(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu,
   if (!g || !u) return fail(IBF_ERR_INVALID_ARG, "ibf_apply: null vector");
   if (nrhs < 1) return fail(IBF_ERR_INVALID_ARG, "ibf_apply: nrhs < 1");
   if (ldg < p->nxi || ldu < p->nx) return fail(IBF_ERR_INVALID_ARG, "ibf_apply: leading dimension too small");
+  if (p->dim == 2) return ibf::apply2d(p, g, ldg, u, ldu, nrhs, (hipStream_t)stream);
   return ibf::apply_plan(p, g, ldg, u, ldu, nrhs, (hipStream_t)stream);
 }
 
@@ -202,12 +206,18 @@ int ibf_apply_profile(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t
   if (ldg < p->nxi || ldu < p->nx)
     return fail(IBF_ERR_INVALID_ARG, "ibf_apply_profile: leading dimension too small");
   std::memset(prof, 0, sizeof(*prof));
+  if (p->dim == 2)
+    return fail(IBF_ERR_UNSUPPORTED, "ibf_apply_profile: per-launch profile is for dim 1");
   return ibf::apply_plan(p, g, ldg, u, ldu, nrhs, (hipStream_t)stream, prof);
 }
 
 int ibf_query(ibf_plan_t p, ibf_info* info) {
   if (!p || !info) return fail(IBF_ERR_INVALID_ARG, "ibf_query: null argument");
   std::memset(info, 0, sizeof(*info));
+  if (p->dim == 2) {
+    ibf::query2d(p, info);
+    return IBF_OK;
+  }
   info->L = p->geo.L;
   info->l0 = p->geo.l0;
   info->h = p->geo.h;
@@ -231,6 +241,11 @@ int ibf_query(ibf_plan_t p, ibf_info* info) {
 
 int ibf_destroy(ibf_plan_t p) {
   if (!p) return IBF_OK;
+  if (p->dim == 2) {
+    ibf::destroy2d(p);
+    delete p;
+    return IBF_OK;
+  }
   if (!p->d_xs && !p->built) {   // never touched the device
     delete p;
     return IBF_OK;

@@ -159,11 +159,17 @@ def make_desc(x, xi, phase, params, r, tol, leaf, precision, sweep_in=0,
     xi = np.ascontiguousarray(xi, dtype=np.float64)
     prm = np.ascontiguousarray(params if params is not None else [], dtype=np.float64)
     d = IBFDesc()
-    d.dim = 1
+    d.dim = 2 if x.ndim == 2 else 1
     d.n_x = x.shape[0]
     d.n_xi = xi.shape[0]
     d.x = x.ctypes.data_as(C.POINTER(C.c_double))
     d.xi = xi.ctypes.data_as(C.POINTER(C.c_double))
+    if d.dim == 2:
+        # Omega = [-W/2, W/2)^2; W defaults to the smallest power of two holding xi
+        if not omega_width:
+            m = float(np.max(np.abs(xi))) if xi.size else 1.0
+            omega_width = 2.0 ** max(5, int(np.ceil(np.log2(2.0 * m + 1e-12))))
+        omega_lo = -omega_width / 2.0
     d.omega_lo = float(-(xi.shape[0] // 2) if omega_lo is None else omega_lo)
     d.omega_width = float(omega_width)
     d.phase_id = int(phase)
@@ -200,7 +206,8 @@ class Plan:
     def from_problem(cls, P, precision=None, sweep_in=None):
         return cls(P.x, P.xi, P.phase, P.params, P.r, P.tol, P.leaf,
                    P.precision if precision is None else precision,
-                   P.sweep_in if sweep_in is None else sweep_in)
+                   P.sweep_in if sweep_in is None else sweep_in,
+                   omega_width=P.extra.get("omega_width", 0.0))
 
     def build(self, stream=None):
         _check(self._lib.ibf_build(self.handle, _stream_handle(stream)))

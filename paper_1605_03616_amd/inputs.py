@@ -181,3 +181,33 @@ def workload_batched(count: int = 256, seed: int = 3, r: int = 12, lo: float = 1
                              PHASE_FIO1D, DEFAULT_PARAMS[PHASE_FIO1D], r, 1e-6, 16, k, g,
                              precision))
     return out
+
+
+def grid_x_2d(n: int) -> np.ndarray:
+    """x = (i1, i2) / n on the n x n grid of [0,1)^2, row-major in (i1, i2)."""
+    i1, i2 = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    return np.stack([i1.ravel() / n, i2.ravel() / n], axis=-1).astype(np.float64)
+
+
+def grid_xi_2d(n: int) -> np.ndarray:
+    """xi = (j1, j2) - n/2 on the integer grid [-n/2, n/2)^2, row-major."""
+    j1, j2 = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    return np.stack([j1.ravel() - n // 2, j2.ravel() - n // 2], axis=-1).astype(np.float64)
+
+
+def fio2d_grid(n: int, r: int, nrhs: int, seed: int, tol: float = 1e-4, leaf: int = 16,
+               precision: int = PREC_FP32, name: str | None = None) -> Problem1D:
+    """2-D FIO of Sec. 6.3 on the n x n grid (N = n^2 points), c1, c2 with /16,
+    tensor order r x r, right-hand sides from default_rng(seed); Omega is the
+    square of side n centred at the origin (the MIBF domain)."""
+    rng = np.random.default_rng(seed)
+    g = complex_normal(n * n, nrhs, rng)
+    return Problem1D(name or f"fio2d_n{n}x{n}_r{r}", grid_x_2d(n), grid_xi_2d(n), PHASE_FIO2D,
+                     DEFAULT_PARAMS[PHASE_FIO2D], r, tol, leaf, nrhs, g, precision,
+                     extra={"omega_width": float(n)})
+
+
+def workload_fio2d_256(nrhs: int = 8) -> Problem1D:
+    """2-D FIO on the 256 x 256 grid, r = 5 x 5, tol 1e-4, 8 RHS from seed 3, FP32."""
+    return fio2d_grid(256, 5, nrhs, 3, tol=1e-4, precision=PREC_FP32,
+                      name="fio2d_n256x256_r5_fp32")
