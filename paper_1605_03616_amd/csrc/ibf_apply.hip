@@ -372,25 +372,47 @@ __device__ __forceinline__ void apply_fused_body(const FusedDesc& D, int64_t lb)
         const float* f0 = reinterpret_cast<const float*>(F + (size_t)locp0 * fs) + fi;
         const float* f1 = reinterpret_cast<const float*>(F + (size_t)locp1 * fs) + fi;
         const int skip = (kmaxg - kin) * NB;
-#pragma unroll 1
-        for (int jj = 0; jj < 2 * kin; ++jj) {
+        const int n2 = 2 * kin;
+        // operands of input row jj: the two slots' x values and A-operand floats
+        auto load_row = [&](int jj, float (&A0)[KG], float (&A1)[KG], VT& X0, VT& X1) {
           const int soff = jj * NB + (jj >= kin ? skip : 0);
-          const VT x0 = src0[soff];
-          const VT x1 = src1[soff];
-          float a0v[KG], a1v[KG];
+          X0 = src0[soff];
+          X1 = src1[soff];
 #pragma unroll
           for (int gq = 0; gq < KG; ++gq) {
-            a0v[gq] = f0[(jj * ke + 2 * gq) * 2];
-            a1v[gq] = f1[(jj * ke + 2 * gq) * 2];
+            A0[gq] = f0[(jj * ke + 2 * gq) * 2];
+            A1[gq] = f1[(jj * ke + 2 * gq) * 2];
           }
+        };
+        auto mfma_row = [&](const float (&A0)[KG], const float (&A1)[KG], const VT& X0,
+                            const VT& X1) {
 #pragma unroll
           for (int gq = 0; gq < KG; ++gq) {
-            P[0][gq] = __builtin_amdgcn_mfma_f32_4x4x1f32(a0v[gq], x0.x, P[0][gq], 0, 0, 0);
-            Q[0][gq] = __builtin_amdgcn_mfma_f32_4x4x1f32(a0v[gq], x0.y, Q[0][gq], 0, 0, 0);
-            P[1][gq] = __builtin_amdgcn_mfma_f32_4x4x1f32(a1v[gq], x1.x, P[1][gq], 0, 0, 0);
-            Q[1][gq] = __builtin_amdgcn_mfma_f32_4x4x1f32(a1v[gq], x1.y, Q[1][gq], 0, 0, 0);
+            P[0][gq] = __builtin_amdgcn_mfma_f32_4x4x1f32(A0[gq], X0.x, P[0][gq], 0, 0, 0);
+            Q[0][gq] = __builtin_amdgcn_mfma_f32_4x4x1f32(A0[gq], X0.y, Q[0][gq], 0, 0, 0);
+            P[1][gq] = __builtin_amdgcn_mfma_f32_4x4x1f32(A1[gq], X1.x, P[1][gq], 0, 0, 0);
+            Q[1][gq] = __builtin_amdgcn_mfma_f32_4x4x1f32(A1[gq], X1.y, Q[1][gq], 0, 0, 0);
           }
+        };
+        // software-pipelined: the LDS reads of the next row are in flight
+        // while the MFMAs of the current row issue (rows past the end are
+        // clamped to the last one and their operands are not used)
+        float a0v[KG], a1v[KG], b0v[KG], b1v[KG];
+        VT x0, x1, y0, y1;
+        load_row(0, a0v, a1v, x0, x1);
+        int jj = 0;
+#pragma unroll 1
+        for (; jj + 1 < n2; jj += 2) {
+          load_row(jj + 1, b0v, b1v, y0, y1);
+          __builtin_amdgcn_sched_barrier(0);                  // keep the reads ahead
+          mfma_row(a0v, a1v, x0, x1);
+          __builtin_amdgcn_sched_barrier(0);
+          load_row(min(jj + 2, n2 - 1), a0v, a1v, x0, x1);
+          __builtin_amdgcn_sched_barrier(0);
+          mfma_row(b0v, b1v, y0, y1);
+          __builtin_amdgcn_sched_barrier(0);
         }
+        if (jj < n2) mfma_row(a0v, a1v, x0, x1);
       }
       if (j + 1 < k) {
         __syncthreads();                                      // S and F reads done
