@@ -13,13 +13,19 @@
 //
 // Kernels:
 //   k_apply_v      Omega leaf -> 2^l0 pairs:  mu = Vbar^* g   (per-leaf product, LDS-staged)
-//   k_apply_fused  k butterfly stages on one pair group in LDS; the FP32 variant
-//                  runs the complex block products on MFMA (v_mfma_f32_4x4x1f32,
-//                  16 blocks = 16 groups of 4 right-hand sides)
+//   k_apply_fused  k butterfly stages on one pair group in LDS (few right-hand
+//                  sides, vector FMA)
+//   k_apply_fused_mfma  the same for 64-column chunks in FP32 on MFMA
+//                  (v_mfma_f32_4x4x1f32, 16 blocks = 16 groups of 4 right-hand
+//                  sides), persistent over the groups with the next group's
+//                  loads in flight during the current group's last stage
 //   k_apply_mid    swept-in middle block Mdot (per pair)
 //   k_apply_u      2^l0 pairs -> X leaf:  u = Ubar mu        (per-leaf product, LDS-staged)
 #include <algorithm>
 #include <cstdio>
+#include <map>
+#include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "ibf_device.h"
@@ -240,8 +246,11 @@ __device__ __forceinline__ int fused_in0(int locp, int rem) {
 template <int NS, typename VT, typename FT>
 struct FactorBatch {
   VT v[NS][2];
+  // (slot counts and block sizes pass through an empty asm so that the slot
+  // and entry bounds are evaluated here, not hoisted into long-lived masks)
   __device__ __forceinline__ void load(const FT* blk, int fs, int s0, int nslot, int j, int rem,
                                        int64_t ap, int64_t bpp, int L, int l) {
+    asm volatile("" : "+s"(fs), "+s"(nslot));
 #pragma unroll
     for (int u = 0; u < NS; ++u) {
       const int slot = s0 + u;
@@ -256,6 +265,7 @@ struct FactorBatch {
     }
   }
   __device__ __forceinline__ void store(VT* F, int fs, int s0, int nslot) const {
+    asm volatile("" : "+s"(fs), "+s"(nslot));
 #pragma unroll
     for (int u = 0; u < NS; ++u) {
       const int slot = s0 + u;
@@ -276,18 +286,22 @@ struct FusedDesc {
   FusedArgs A;
 };
 
-template <typename VT, typename FT, int KT, bool MFMA>
+// Few right-hand sides (vector path): the stage is a stream of factor blocks,
+// each entry used by NB columns only.  One thread per output (slot, row t,
+// column n), n fastest; it reads its factor row entries straight from HBM (the
+// threads of one slot read whole rows together, and consecutive rows share
+// cache lines) and the inputs from the LDS state, which ping-pongs between two
+// buffers so that no output waits in registers.
+template <typename VT, typename FT, int KT>
 __device__ __forceinline__ void apply_fused_body(const FusedDesc& D, int64_t lb) {
-  static_assert(!MFMA || sizeof(VT) == 8, "MFMA variant computes in FP32");
-  constexpr int KG = KT / 2;                                  // row pairs (MFMA row groups)
   extern __shared__ __align__(16) unsigned char smem[];
   const VT* __restrict__ in = reinterpret_cast<const VT*>(D.in);
   VT* __restrict__ out = reinterpret_cast<VT*>(D.out);
   const FusedArgs& A = D.A;
-  const int k = A.nst, NB = MFMA ? 64 : A.NB, L = A.L, kmaxg = A.kmaxg;
+  const int k = A.nst, NB = A.NB, L = A.L, kmaxg = A.kmaxg;
   const int nslot = 1 << k;
   VT* S = reinterpret_cast<VT*>(smem);                        // [nslot][kmaxg][NB]
-  VT* F = S + (size_t)nslot * kmaxg * NB;                     // [nslot][fs] (+ KT slack)
+  VT* S1 = S + (size_t)nslot * kmaxg * NB;                    // second state buffer
   const int64_t gid = lb / A.nchunk;
   const int chunk = (int)(lb % A.nchunk);
   const int nb0 = chunk * NB;
@@ -328,182 +342,290 @@ __device__ __forceinline__ void apply_fused_body(const FusedDesc& D, int64_t lb)
       }
     }
   }
+  const FastDiv divNB(NB);
+  __syncthreads();                                            // the gathered group is in S
+  for (int j = 0; j < k; ++j) {
+    const int l = A.l_start + j;
+    const int kin = A.ranks[j], kout = A.ranks[j + 1], ke = A.kld[j];
+    const int fs = 2 * kin * ke;
+    const int rem = k - j - 1;
+    const FT* __restrict__ blk = reinterpret_cast<const FT*>(A.blk[j]);
+    const VT* Sin = (j & 1) ? S1 : S;
+    VT* Sout = (j & 1) ? S : S1;
+    const bool last = j == k - 1;
+    const int items = nslot * kout * NB;
+    const FastDiv divK(kout);
+    for (int item = threadIdx.x; item < items; item += kBlock) {
+      int r, nn, locp, t;
+      divNB.divmod(item, r, nn);
+      divK.divmod(r, locp, t);
+      const int64_t pout = fused_pout(locp, j, rem, ap, bpp, L, l);
+      const FT* f = blk + pout * fs + t;
+      const VT* x = Sin + (size_t)fused_in0(locp, rem) * kmaxg * NB + nn;
+      VT acc = Zero<VT>::v();
+      for (int c = 0; c < 2; ++c) {
+        const FT* fc = f + c * kin * ke;
+        const VT* xc = x + (size_t)c * kmaxg * NB;
+#pragma unroll 4
+        for (int s2 = 0; s2 < kin; ++s2) cfma(acc, load_factor(fc, s2 * ke), xc[s2 * NB]);
+      }
+      if (!last) Sout[(size_t)(locp * kmaxg + t) * NB + nn] = acc;
+      else if (nn < nbw) out[(pout * kout + t) * nrhs + nb0 + nn] = acc;
+    }
+    if (!last) __syncthreads();
+  }
+}
 
-  if constexpr (MFMA) {
-    // Lane l carries RHS column l of the chunk.  Block b = l >> 2 is a group
-    // of 4 columns; A-operand row i = l & 3 is the raw float i of the pair of
-    // complex entries (t = 2g, 2g+1): (re t0, im t0, re t1, im t1).  With
-    // P = sum f_i x_re and Q = sum f_i x_im, the complex outputs are
-    //   out[2g]   = (P0 - Q1, P1 + Q0),  out[2g+1] = (P2 - Q3, P3 + Q2).
-    // Wave v owns output slots v and v + 4; when the group has fewer than 8
-    // slots the second repeats the first (results discarded) so that the
-    // inner loop has no branches and all operand reads of an iteration batch.
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int fi = lane & 3;
-    FactorBatch<8, VT, FT> fb;
-    fb.load(reinterpret_cast<const FT*>(A.blk[0]), 2 * A.ranks[0] * A.kld[0], 0, nslot, 0, k - 1,
-            ap, bpp, L, A.l_start);
-    fb.store(F, 2 * A.ranks[0] * A.kld[0], 0, nslot);
+// Multi-RHS FP32 variant on MFMA, persistent: the block with logical index b
+// takes logical blocks b, b + lstep, ... below lend (logical block = pair group
+// x 64-column RHS chunk).  While a group's last stage computes, the loads of
+// the next group's input rows and first-stage factor blocks are already in
+// flight into registers, and each stage's computation overlaps the loads of
+// the next stage's factors, so HBM latency hides behind MFMA work.
+//
+// Lane l carries RHS column l of the chunk.  MFMA block b = l >> 2 is a group
+// of 4 columns; A-operand row i = l & 3 is the raw float i of the pair of
+// complex entries (t = 2g, 2g+1): (re t0, im t0, re t1, im t1).  With
+// P = sum f_i x_re and Q = sum f_i x_im, the complex outputs are
+//   out[2g]   = (P0 - Q1, P1 + Q0),  out[2g+1] = (P2 - Q3, P3 + Q2).
+// Wave v owns output slot v, and slot v + 4 when the group has 8 slots (the
+// two products run one after the other: they share no operands).
+template <typename VT, typename FT, int KT>
+__device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, int64_t lstep,
+                                                int64_t lend) {
+  static_assert(sizeof(VT) == 8, "MFMA variant computes in FP32");
+  constexpr int KG = KT / 2;                                  // row pairs (MFMA row groups)
+  constexpr int NB = 64;
+  // input rows held in flight per thread (row r goes to wave r mod 4); groups
+  // with more rows than 4 XR copy the rest synchronously
+  constexpr int XR = KT <= 12 ? 2 * KT : KT;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const VT* __restrict__ in = reinterpret_cast<const VT*>(D.in);
+  VT* __restrict__ out = reinterpret_cast<VT*>(D.out);
+  const FusedArgs& A = D.A;
+  const int k = A.nst, L = A.L, kmaxg = A.kmaxg, nrhs = A.nrhs, nchunk = A.nchunk;
+  const int nslot = 1 << k;
+  VT* S = reinterpret_cast<VT*>(smem);                        // [nslot][kmaxg][64]
+  VT* F = S + (size_t)nslot * kmaxg * NB;                     // [nslot][fs] (+ KT slack)
+  const int sh_end = L - (A.l_start + k - 1);
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int fi = lane & 3;
+  const int kin0 = A.ranks[0], rows0 = nslot * kin0, fs0 = 2 * kin0 * A.kld[0];
+  const FT* blk0 = reinterpret_cast<const FT*>(A.blk[0]);
+  const bool two = nslot > 4;
+
+  struct Grp {
+    int64_t gid, ap, bpp;
+    int nb0, nbw;
+  };
+  auto decode = [&](int64_t l) {
+    Grp g;
+    g.gid = l / nchunk;
+    g.nb0 = (int)(l - g.gid * nchunk) * NB;
+    g.nbw = min(NB, nrhs - g.nb0);
+    g.ap = g.gid >> sh_end;
+    g.bpp = g.gid & (((int64_t)1 << sh_end) - 1);
+    return g;
+  };
+  FactorBatch<8, VT, FT> fb;
+  VT xin[XR];
+  // issue the loads of a group's first-stage factor blocks and input rows
+  // (group row r = slot r / kin0, rank index r % kin0, from input pair
+  // (gid << k) | slot; columns >= nbw read as zero)
+  // The per-row offsets and bounds of fetch and deposit depend only on
+  // launch constants; passed through an empty asm they are recomputed at each
+  // call instead of being hoisted out of the group loop, where dozens of them
+  // would stay live in registers across every stage.
+  auto fetch = [&](const Grp& g) {
+    int kin_v = kin0, rows_v = rows0, fs_v = fs0, wave_v = wave;
+    int64_t ld_v = nrhs;
+    asm volatile("" : "+s"(kin_v), "+s"(rows_v), "+s"(fs_v), "+s"(wave_v), "+s"(ld_v));
+    fb.load(blk0, fs_v, 0, nslot, 0, k - 1, g.ap, g.bpp, L, A.l_start);
+    const VT* src = in + ((g.gid << k) * kin_v + wave_v) * ld_v + g.nb0 + lane;
+    const bool col = lane < g.nbw;
+#pragma unroll
+    for (int i = 0; i < XR; ++i)
+      if (wave_v + 4 * i < rows_v) xin[i] = col ? src[4 * i * ld_v] : Zero<VT>::v();
+  };
+  auto deposit = [&](const Grp& g) {
+    int kin_v = kin0, rows_v = rows0, fs_v = fs0, wave_v = wave, kmg_v = kmaxg;
+    asm volatile("" : "+s"(kin_v), "+s"(rows_v), "+s"(fs_v), "+s"(wave_v), "+s"(kmg_v));
+    int slot = 0, s = wave_v;
+    while (s >= kin_v) { s -= kin_v; ++slot; }
+#pragma unroll
+    for (int i = 0; i < XR; ++i) {
+      if (wave_v + 4 * i < rows_v) S[(slot * kmg_v + s) * NB + lane] = xin[i];
+      s += 4;
+      while (s >= kin_v) { s -= kin_v; ++slot; }
+    }
+    if (rows_v > 4 * XR) {
+      const VT* src = in + (g.gid << k) * kin_v * nrhs + g.nb0 + lane;
+      for (int r = 4 * XR + wave_v; r < rows_v; r += 4) {
+        const int sl = r / kin_v;
+        S[(sl * kmg_v + r - sl * kin_v) * NB + lane] =
+            lane < g.nbw ? src[(int64_t)r * nrhs] : Zero<VT>::v();
+      }
+    }
+    fb.store(F, fs_v, 0, nslot);
+  };
+
+  Grp cur = decode(lb);
+  fetch(cur);
+  while (true) {
+    deposit(cur);
     __syncthreads();
-    for (int j = 0; j < k; ++j) {
+    const int64_t nlb = lb + lstep;
+    const bool more = nlb < lend;
+    const Grp nxt = more ? decode(nlb) : cur;
+    // one stage; the last one is peeled off the stage loop so that the next
+    // group's prefetched rows are live only during it
+    auto stage = [&](int j, auto last_c) {
+      constexpr bool LAST = decltype(last_c)::value;
       const int l = A.l_start + j;
       const int kin = A.ranks[j], kout = A.ranks[j + 1], ke = A.kld[j];
       const int fs = 2 * kin * ke;
       const int rem = k - j - 1;
-      if (j + 1 < k)   // next stage's factor blocks: in flight during this stage
+      if constexpr (!LAST)   // next stage's factor blocks: in flight during this stage
         fb.load(reinterpret_cast<const FT*>(A.blk[j + 1]), 2 * kout * A.kld[j + 1], 0, nslot,
-                j + 1, rem - 1, ap, bpp, L, l + 1);
-      v4f P[2][KG], Q[2][KG];
-#pragma unroll
-      for (int m = 0; m < 2; ++m)
+                j + 1, rem - 1, cur.ap, cur.bpp, L, l + 1);
+      else if (more)         // the next group: in flight during the last stage
+        fetch(nxt);
+      const int skip = (kmaxg - kin) * NB;
+      const int n2 = 2 * kin;
+      v4f P[KG], Q[KG];
+      // the block product of output slot locp into P, Q: one flat loop over
+      // the 2 kin inputs of both children (child c = 1 starts kmaxg rows
+      // further in S, and its factor rows follow c = 0's)
+      auto product = [&](int locp) {
 #pragma unroll
         for (int gq = 0; gq < KG; ++gq) {
-          P[m][gq] = v4f{0.f, 0.f, 0.f, 0.f};
-          Q[m][gq] = v4f{0.f, 0.f, 0.f, 0.f};
+          P[gq] = v4f{0.f, 0.f, 0.f, 0.f};
+          Q[gq] = v4f{0.f, 0.f, 0.f, 0.f};
         }
-      const int locp0 = wave, locp1 = wave + 4 < nslot ? wave + 4 : wave;
-      const bool act0 = locp0 < nslot, act1 = wave + 4 < nslot;
-      if (act0) {
-        const int in00 = fused_in0(locp0, rem), in10 = fused_in0(locp1, rem);
-        // one flat loop over the 2 kin inputs of both children: child c = 1
-        // starts kmaxg rows further in S, and its factor rows follow c = 0's
-        const VT* src0 = S + (size_t)in00 * kmaxg * NB + lane;
-        const VT* src1 = S + (size_t)in10 * kmaxg * NB + lane;
-        const float* f0 = reinterpret_cast<const float*>(F + (size_t)locp0 * fs) + fi;
-        const float* f1 = reinterpret_cast<const float*>(F + (size_t)locp1 * fs) + fi;
-        const int skip = (kmaxg - kin) * NB;
-        const int n2 = 2 * kin;
-        // operands of input row jj: the two slots' x values and A-operand floats
-        auto load_row = [&](int jj, float (&A0)[KG], float (&A1)[KG], VT& X0, VT& X1) {
-          const int soff = jj * NB + (jj >= kin ? skip : 0);
-          X0 = src0[soff];
-          X1 = src1[soff];
+        const VT* src = S + (size_t)fused_in0(locp, rem) * kmaxg * NB + lane;
+        const float* f = reinterpret_cast<const float*>(F + (size_t)locp * fs) + fi;
+        auto load_row = [&](int jj, float (&Av)[KG], VT& X) {
+          X = src[jj * NB + (jj >= kin ? skip : 0)];
 #pragma unroll
-          for (int gq = 0; gq < KG; ++gq) {
-            A0[gq] = f0[(jj * ke + 2 * gq) * 2];
-            A1[gq] = f1[(jj * ke + 2 * gq) * 2];
-          }
+          for (int gq = 0; gq < KG; ++gq) Av[gq] = f[(jj * ke + 2 * gq) * 2];
         };
-        auto mfma_row = [&](const float (&A0)[KG], const float (&A1)[KG], const VT& X0,
-                            const VT& X1) {
+        auto mfma_row = [&](const float (&Av)[KG], const VT& X) {
 #pragma unroll
           for (int gq = 0; gq < KG; ++gq) {
-            P[0][gq] = __builtin_amdgcn_mfma_f32_4x4x1f32(A0[gq], X0.x, P[0][gq], 0, 0, 0);
-            Q[0][gq] = __builtin_amdgcn_mfma_f32_4x4x1f32(A0[gq], X0.y, Q[0][gq], 0, 0, 0);
-            P[1][gq] = __builtin_amdgcn_mfma_f32_4x4x1f32(A1[gq], X1.x, P[1][gq], 0, 0, 0);
-            Q[1][gq] = __builtin_amdgcn_mfma_f32_4x4x1f32(A1[gq], X1.y, Q[1][gq], 0, 0, 0);
+            P[gq] = __builtin_amdgcn_mfma_f32_4x4x1f32(Av[gq], X.x, P[gq], 0, 0, 0);
+            Q[gq] = __builtin_amdgcn_mfma_f32_4x4x1f32(Av[gq], X.y, Q[gq], 0, 0, 0);
           }
         };
         // software-pipelined: the LDS reads of the next row are in flight
         // while the MFMAs of the current row issue (rows past the end are
         // clamped to the last one and their operands are not used)
-        float a0v[KG], a1v[KG], b0v[KG], b1v[KG];
-        VT x0, x1, y0, y1;
-        load_row(0, a0v, a1v, x0, x1);
+        float av[KG], bv[KG];
+        VT xa, xb;
+        load_row(0, av, xa);
         int jj = 0;
 #pragma unroll 1
         for (; jj + 1 < n2; jj += 2) {
-          load_row(jj + 1, b0v, b1v, y0, y1);
+          load_row(jj + 1, bv, xb);
           __builtin_amdgcn_sched_barrier(0);                  // keep the reads ahead
-          mfma_row(a0v, a1v, x0, x1);
+          mfma_row(av, xa);
           __builtin_amdgcn_sched_barrier(0);
-          load_row(min(jj + 2, n2 - 1), a0v, a1v, x0, x1);
+          load_row(min(jj + 2, n2 - 1), av, xa);
           __builtin_amdgcn_sched_barrier(0);
-          mfma_row(b0v, b1v, y0, y1);
+          mfma_row(bv, xb);
           __builtin_amdgcn_sched_barrier(0);
         }
-        if (jj < n2) mfma_row(a0v, a1v, x0, x1);
-      }
-      if (j + 1 < k) {
+        if (jj < n2) mfma_row(av, xa);
+      };
+      // complex output rows 2 gq, 2 gq + 1 of the product
+      auto out_lo = [&](int gq) { return make_float2(P[gq][0] - Q[gq][1], P[gq][1] + Q[gq][0]); };
+      auto out_hi = [&](int gq) { return make_float2(P[gq][2] - Q[gq][3], P[gq][3] + Q[gq][2]); };
+      const int locp0 = wave, locp1 = wave + 4;
+      const bool act0 = locp0 < nslot;
+      if constexpr (!LAST) {
+        // outputs replace inputs in S once every wave has read its inputs: the
+        // first slot's outputs wait in registers while the second computes
+        VT hold[KT];
+        if (act0) {
+          product(locp0);
+#pragma unroll
+          for (int gq = 0; gq < KG; ++gq) {
+            hold[2 * gq] = out_lo(gq);
+            hold[2 * gq + 1] = out_hi(gq);
+          }
+          if (two) product(locp1);
+        }
         __syncthreads();                                      // S and F reads done
+        if (act0) {
+          VT* dst = S + (size_t)locp0 * kmaxg * NB + lane;
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          const int locp = m == 0 ? locp0 : locp1;
-          if (m == 0 ? act0 : act1) {
-            VT* dst = S + (size_t)locp * kmaxg * NB + lane;
+          for (int t = 0; t < KT; ++t)
+            if (t < kout) dst[t * NB] = hold[t];
+        }
+        if (two) {
+          VT* dst = S + (size_t)locp1 * kmaxg * NB + lane;
 #pragma unroll
-            for (int gq = 0; gq < KG; ++gq) {
-              const v4f p = P[m][gq], q = Q[m][gq];
-              if (2 * gq < kout) dst[(2 * gq) * NB] = make_float2(p[0] - q[1], p[1] + q[0]);
-              if (2 * gq + 1 < kout)
-                dst[(2 * gq + 1) * NB] = make_float2(p[2] - q[3], p[3] + q[2]);
-            }
+          for (int gq = 0; gq < KG; ++gq) {
+            if (2 * gq < kout) dst[(2 * gq) * NB] = out_lo(gq);
+            if (2 * gq + 1 < kout) dst[(2 * gq + 1) * NB] = out_hi(gq);
           }
         }
         fb.store(F, 2 * kout * A.kld[j + 1], 0, nslot);
         __syncthreads();
-      } else if (lane < nbw) {
-        // last stage: coalesced rows of 64 columns straight to HBM
+      } else {
+        // last stage: each slot's rows of 64 columns go straight to HBM
+        const bool col = lane < cur.nbw;
+#pragma unroll 1
+        for (int m = 0; m < (two ? 2 : 1); ++m) {
+          const int locp = wave + 4 * m;
+          if (locp < nslot) {
+            product(locp);
+            VT* dst = out + fused_pout(locp, j, 0, cur.ap, cur.bpp, L, l) * kout * nrhs +
+                      cur.nb0 + lane;
+            if (col) {
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          const int locp = m == 0 ? locp0 : locp1;
-          if (m == 0 ? act0 : act1) {
-            VT* dst = out + fused_pout(locp, j, 0, ap, bpp, L, l) * kout * nrhs + nb0 + lane;
-#pragma unroll
-            for (int gq = 0; gq < KG; ++gq) {
-              const v4f p = P[m][gq], q = Q[m][gq];
-              if (2 * gq < kout)
-                dst[(int64_t)(2 * gq) * nrhs] = make_float2(p[0] - q[1], p[1] + q[0]);
-              if (2 * gq + 1 < kout)
-                dst[(int64_t)(2 * gq + 1) * nrhs] = make_float2(p[2] - q[3], p[3] + q[2]);
+              for (int gq = 0; gq < KG; ++gq) {
+                if (2 * gq < kout) dst[(int64_t)(2 * gq) * nrhs] = out_lo(gq);
+                if (2 * gq + 1 < kout) dst[(int64_t)(2 * gq + 1) * nrhs] = out_hi(gq);
+              }
             }
           }
         }
       }
-    }
-  } else {
-    // Few right-hand sides: the stage is a stream of factor blocks, each
-    // entry used by NB columns only.  One thread per output (slot, row t,
-    // column n), n fastest; it reads its factor row entries straight from HBM
-    // (the threads of one slot read whole rows together, and consecutive
-    // rows share cache lines) and the inputs from the LDS state, which
-    // ping-pongs between two buffers so that no output waits in registers.
-    VT* S1 = S + (size_t)nslot * kmaxg * NB;
-    const FastDiv divNB(NB);
-    __syncthreads();                                          // the gathered group is in S
-    for (int j = 0; j < k; ++j) {
-      const int l = A.l_start + j;
-      const int kin = A.ranks[j], kout = A.ranks[j + 1], ke = A.kld[j];
-      const int fs = 2 * kin * ke;
-      const int rem = k - j - 1;
-      const FT* __restrict__ blk = reinterpret_cast<const FT*>(A.blk[j]);
-      const VT* Sin = (j & 1) ? S1 : S;
-      VT* Sout = (j & 1) ? S : S1;
-      const bool last = j == k - 1;
-      const int items = nslot * kout * NB;
-      const FastDiv divK(kout);
-      for (int item = threadIdx.x; item < items; item += kBlock) {
-        int r, nn, locp, t;
-        divNB.divmod(item, r, nn);
-        divK.divmod(r, locp, t);
-        const int64_t pout = fused_pout(locp, j, rem, ap, bpp, L, l);
-        const FT* f = blk + pout * fs + t;
-        const VT* x = Sin + (size_t)fused_in0(locp, rem) * kmaxg * NB + nn;
-        VT acc = Zero<VT>::v();
-        for (int c = 0; c < 2; ++c) {
-          const FT* fc = f + c * kin * ke;
-          const VT* xc = x + (size_t)c * kmaxg * NB;
-#pragma unroll 4
-          for (int s2 = 0; s2 < kin; ++s2) cfma(acc, load_factor(fc, s2 * ke), xc[s2 * NB]);
-        }
-        if (!last) Sout[(size_t)(locp * kmaxg + t) * NB + nn] = acc;
-        else if (nn < nbw) out[(pout * kout + t) * nrhs + nb0 + nn] = acc;
-      }
-      if (!last) __syncthreads();
-    }
+    };
+    for (int j = 0; j + 1 < k; ++j) stage(j, std::false_type{});
+    stage(k - 1, std::true_type{});
+    if (!more) break;
+    __syncthreads();                                          // last-stage LDS reads done
+    lb = nlb;
+    cur = nxt;
   }
 }
 
-template <typename VT, typename FT, int KT, bool MFMA>
+template <typename VT, typename FT, int KT>
 __global__ __launch_bounds__(kBlock) void k_apply_fused(FusedDesc D) {
-  apply_fused_body<VT, FT, KT, MFMA>(D, xcd_logical_block((int64_t)gridDim.x));
+  apply_fused_body<VT, FT, KT>(D, xcd_logical_block((int64_t)gridDim.x));
 }
-template <typename VT, typename FT, int KT, bool MFMA>
+template <typename VT, typename FT, int KT>
 __global__ __launch_bounds__(kBlock) void k_batch_fused(const FusedDesc* __restrict__ ds,
                                                         const int64_t* __restrict__ boff,
                                                         int count) {
   const int p = find_problem(boff, count, blockIdx.x);
-  apply_fused_body<VT, FT, KT, MFMA>(ds[p], (int64_t)blockIdx.x - boff[p]);
+  apply_fused_body<VT, FT, KT>(ds[p], (int64_t)blockIdx.x - boff[p]);
+}
+// persistent: a grid of resident blocks over `total` logical blocks
+template <typename VT, typename FT, int KT>
+__global__ __launch_bounds__(kBlock) void k_apply_fused_mfma(FusedDesc D, int64_t total) {
+  fused_mfma_body<VT, FT, KT>(D, xcd_logical_block((int64_t)gridDim.x), (int64_t)gridDim.x,
+                              total);
+}
+template <typename VT, typename FT, int KT>
+__global__ __launch_bounds__(kBlock) void k_batch_fused_mfma(const FusedDesc* __restrict__ ds,
+                                                             const int64_t* __restrict__ boff,
+                                                             int count) {
+  const int p = find_problem(boff, count, blockIdx.x);
+  const int64_t lb = (int64_t)blockIdx.x - boff[p];
+  fused_mfma_body<VT, FT, KT>(ds[p], lb, 1, lb + 1);
 }
 
 // Middle block of the swept-in factorization: out[p][t][n] = sum_s Mdot[p][t][s] in[p][s][n]
@@ -884,6 +1006,34 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
   return IBF_OK;
 }
 
+// Blocks of a kernel that fit on the device at once (occupancy x CUs), for
+// persistent launches; cached per kernel and LDS size.
+inline int resident_blocks(const void* func, size_t lds, int64_t* out) {
+  static std::mutex mu;
+  static std::map<std::pair<std::pair<const void*, size_t>, int>, int64_t> cache;
+  int dev = 0;
+  IBF_HIP_CHECK(hipGetDevice(&dev));
+  const auto key = std::make_pair(std::make_pair(func, lds), dev);
+  {
+    std::lock_guard<std::mutex> g(mu);
+    const auto it = cache.find(key);
+    if (it != cache.end()) {
+      *out = it->second;
+      return IBF_OK;
+    }
+  }
+  int per_cu = 0, ncu = 0;
+  IBF_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, func, kBlock, lds));
+  IBF_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int64_t n = (int64_t)std::max(1, per_cu) * std::max(1, ncu);
+  {
+    std::lock_guard<std::mutex> g(mu);
+    cache[key] = n;
+  }
+  *out = n;
+  return IBF_OK;
+}
+
 template <typename VT, typename FT>
 int launch_one(const Launch& x, hipStream_t s) {
   const dim3 grid((unsigned)x.nblocks), blk(kBlock);
@@ -896,14 +1046,23 @@ int launch_one(const Launch& x, hipStream_t s) {
     case kLaunchFused:
       if (x.mfma) {
         if constexpr (sizeof(VT) == 8) {
-#define IBF_LAUNCH_FM(KTC) \
-  hipLaunchKernelGGL((k_apply_fused<VT, FT, KTC, true>), grid, blk, x.lds, s, x.f)
+#define IBF_LAUNCH_FM(KTC)                                                          \
+  {                                                                                 \
+    int64_t nres = 0;                                                               \
+    const int rc = resident_blocks(reinterpret_cast<const void*>(                    \
+                                       &k_apply_fused_mfma<VT, FT, KTC>),            \
+                                   x.lds, &nres);                                   \
+    if (rc) return rc;                                                              \
+    const dim3 pgrid((unsigned)std::min<int64_t>(x.nblocks, nres));                  \
+    hipLaunchKernelGGL((k_apply_fused_mfma<VT, FT, KTC>), pgrid, blk, x.lds, s, x.f,  \
+                       x.nblocks);                                                  \
+  }
           IBF_DISPATCH_KT(x.kt, IBF_LAUNCH_FM);
 #undef IBF_LAUNCH_FM
         }
       } else {
 #define IBF_LAUNCH_FV(KTC) \
-  hipLaunchKernelGGL((k_apply_fused<VT, FT, KTC, false>), grid, blk, x.lds, s, x.f)
+  hipLaunchKernelGGL((k_apply_fused<VT, FT, KTC>), grid, blk, x.lds, s, x.f)
         IBF_DISPATCH_KT(x.kt, IBF_LAUNCH_FV);
 #undef IBF_LAUNCH_FV
       }
@@ -995,13 +1154,13 @@ int launch_phase(const ibf_batch_s* b, const BatchPhase& ph, hipStream_t s) {
       if (ph.mfma) {
         if constexpr (sizeof(VT) == 8) {
 #define IBF_LAUNCH_BFM(KTC) \
-  hipLaunchKernelGGL((k_batch_fused<VT, FT, KTC, true>), grid, blk, ph.lds, s, ds, boff, ph.count)
+  hipLaunchKernelGGL((k_batch_fused_mfma<VT, FT, KTC>), grid, blk, ph.lds, s, ds, boff, ph.count)
           IBF_DISPATCH_KT(ph.kt, IBF_LAUNCH_BFM);
 #undef IBF_LAUNCH_BFM
         }
       } else {
 #define IBF_LAUNCH_BFV(KTC) \
-  hipLaunchKernelGGL((k_batch_fused<VT, FT, KTC, false>), grid, blk, ph.lds, s, ds, boff, ph.count)
+  hipLaunchKernelGGL((k_batch_fused<VT, FT, KTC>), grid, blk, ph.lds, s, ds, boff, ph.count)
         IBF_DISPATCH_KT(ph.kt, IBF_LAUNCH_BFV);
 #undef IBF_LAUNCH_BFV
       }
