@@ -405,8 +405,11 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
   const FusedArgs& A = D.A;
   const int k = A.nst, L = A.L, kmaxg = A.kmaxg, nrhs = A.nrhs, nchunk = A.nchunk;
   const int nslot = 1 << k;
-  VT* S = reinterpret_cast<VT*>(smem);                        // [nslot][kmaxg][64]
-  VT* F = S + (size_t)nslot * kmaxg * NB;                     // [nslot][fs] (+ KT slack)
+  // S: the state of stage j as [slot][ranks[j]][64] (2 kin contiguous input
+  // rows per output slot); F: the stage's factor blocks [slot][2 kin kld],
+  // followed by 2 KT entries of slack for reads past the last row
+  VT* S = reinterpret_cast<VT*>(smem);
+  VT* F = S + (size_t)nslot * kmaxg * NB;
   const int sh_end = L - (A.l_start + k - 1);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -430,42 +433,34 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
   };
   FactorBatch<8, VT, FT> fb;
   VT xin[XR];
-  // issue the loads of a group's first-stage factor blocks and input rows
-  // (group row r = slot r / kin0, rank index r % kin0, from input pair
-  // (gid << k) | slot; columns >= nbw read as zero)
-  // The per-row offsets and bounds of fetch and deposit depend only on
-  // launch constants; passed through an empty asm they are recomputed at each
-  // call instead of being hoisted out of the group loop, where dozens of them
-  // would stay live in registers across every stage.
+  // The group's input rows are contiguous in HBM (pairs (gid << k) .. + nslot,
+  // kin0 rows each) and land contiguously in S.  Row r goes to wave r mod 4;
+  // columns >= nbw read as zero.  The per-row offsets and bounds depend only
+  // on launch constants; passed through an empty asm they are recomputed at
+  // each call instead of being hoisted out of the group loop, where dozens of
+  // them would stay live in registers across every stage.
   auto fetch = [&](const Grp& g) {
-    int kin_v = kin0, rows_v = rows0, fs_v = fs0, wave_v = wave;
+    int rows_v = rows0, fs_v = fs0, wave_v = wave;
     int64_t ld_v = nrhs;
-    asm volatile("" : "+s"(kin_v), "+s"(rows_v), "+s"(fs_v), "+s"(wave_v), "+s"(ld_v));
+    asm volatile("" : "+s"(rows_v), "+s"(fs_v), "+s"(wave_v), "+s"(ld_v));
     fb.load(blk0, fs_v, 0, nslot, 0, k - 1, g.ap, g.bpp, L, A.l_start);
-    const VT* src = in + ((g.gid << k) * kin_v + wave_v) * ld_v + g.nb0 + lane;
+    const VT* src = in + ((g.gid << k) * kin0 + wave_v) * ld_v + g.nb0 + lane;
     const bool col = lane < g.nbw;
 #pragma unroll
     for (int i = 0; i < XR; ++i)
       if (wave_v + 4 * i < rows_v) xin[i] = col ? src[4 * i * ld_v] : Zero<VT>::v();
   };
   auto deposit = [&](const Grp& g) {
-    int kin_v = kin0, rows_v = rows0, fs_v = fs0, wave_v = wave, kmg_v = kmaxg;
-    asm volatile("" : "+s"(kin_v), "+s"(rows_v), "+s"(fs_v), "+s"(wave_v), "+s"(kmg_v));
-    int slot = 0, s = wave_v;
-    while (s >= kin_v) { s -= kin_v; ++slot; }
+    int rows_v = rows0, fs_v = fs0, wave_v = wave;
+    asm volatile("" : "+s"(rows_v), "+s"(fs_v), "+s"(wave_v));
+    VT* dst = S + wave_v * NB + lane;
 #pragma unroll
-    for (int i = 0; i < XR; ++i) {
-      if (wave_v + 4 * i < rows_v) S[(slot * kmg_v + s) * NB + lane] = xin[i];
-      s += 4;
-      while (s >= kin_v) { s -= kin_v; ++slot; }
-    }
+    for (int i = 0; i < XR; ++i)
+      if (wave_v + 4 * i < rows_v) dst[4 * i * NB] = xin[i];
     if (rows_v > 4 * XR) {
-      const VT* src = in + (g.gid << k) * kin_v * nrhs + g.nb0 + lane;
-      for (int r = 4 * XR + wave_v; r < rows_v; r += 4) {
-        const int sl = r / kin_v;
-        S[(sl * kmg_v + r - sl * kin_v) * NB + lane] =
-            lane < g.nbw ? src[(int64_t)r * nrhs] : Zero<VT>::v();
-      }
+      const VT* src = in + (g.gid << k) * kin0 * nrhs + g.nb0 + lane;
+      for (int r = 4 * XR + wave_v; r < rows_v; r += 4)
+        S[r * NB + lane] = lane < g.nbw ? src[(int64_t)r * nrhs] : Zero<VT>::v();
     }
     fb.store(F, fs_v, 0, nslot);
   };
@@ -491,24 +486,23 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
                 j + 1, rem - 1, cur.ap, cur.bpp, L, l + 1);
       else if (more)         // the next group: in flight during the last stage
         fetch(nxt);
-      const int skip = (kmaxg - kin) * NB;
-      const int n2 = 2 * kin;
       v4f P[KG], Q[KG];
-      // the block product of output slot locp into P, Q: one flat loop over
-      // the 2 kin inputs of both children (child c = 1 starts kmaxg rows
-      // further in S, and its factor rows follow c = 0's)
+      // the block product of output slot locp into P, Q: one loop over the
+      // 2 kin input rows of its two children, which are adjacent slots and so
+      // contiguous rows in S, as are the block's factor rows in F
       auto product = [&](int locp) {
 #pragma unroll
         for (int gq = 0; gq < KG; ++gq) {
           P[gq] = v4f{0.f, 0.f, 0.f, 0.f};
           Q[gq] = v4f{0.f, 0.f, 0.f, 0.f};
         }
-        const VT* src = S + (size_t)fused_in0(locp, rem) * kmaxg * NB + lane;
-        const float* f = reinterpret_cast<const float*>(F + (size_t)locp * fs) + fi;
-        auto load_row = [&](int jj, float (&Av)[KG], VT& X) {
-          X = src[jj * NB + (jj >= kin ? skip : 0)];
+        const VT* xp = S + (size_t)fused_in0(locp, rem) * kin * NB + lane;
+        const float* fp = reinterpret_cast<const float*>(F + (size_t)locp * fs) + fi;
+        const int fstep = 2 * ke;                              // floats per factor row
+        auto load_row = [&](const VT* x, const float* f, float (&Av)[KG], VT& X) {
+          X = *x;
 #pragma unroll
-          for (int gq = 0; gq < KG; ++gq) Av[gq] = f[(jj * ke + 2 * gq) * 2];
+          for (int gq = 0; gq < KG; ++gq) Av[gq] = f[4 * gq];
         };
         auto mfma_row = [&](const float (&Av)[KG], const VT& X) {
 #pragma unroll
@@ -518,24 +512,24 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
           }
         };
         // software-pipelined: the LDS reads of the next row are in flight
-        // while the MFMAs of the current row issue (rows past the end are
-        // clamped to the last one and their operands are not used)
+        // while the MFMAs of the current row issue.  The last iteration reads
+        // one row past the end, inside the LDS allocation and never used.
         float av[KG], bv[KG];
         VT xa, xb;
-        load_row(0, av, xa);
-        int jj = 0;
+        load_row(xp, fp, av, xa);
 #pragma unroll 1
-        for (; jj + 1 < n2; jj += 2) {
-          load_row(jj + 1, bv, xb);
+        for (int left = 2 * kin; left > 0; left -= 2) {
+          load_row(xp + NB, fp + fstep, bv, xb);
           __builtin_amdgcn_sched_barrier(0);                  // keep the reads ahead
           mfma_row(av, xa);
           __builtin_amdgcn_sched_barrier(0);
-          load_row(min(jj + 2, n2 - 1), av, xa);
+          xp += 2 * NB;
+          fp += 2 * fstep;
+          load_row(xp, fp, av, xa);
           __builtin_amdgcn_sched_barrier(0);
           mfma_row(bv, xb);
           __builtin_amdgcn_sched_barrier(0);
         }
-        if (jj < n2) mfma_row(av, xa);
       };
       // complex output rows 2 gq, 2 gq + 1 of the product
       auto out_lo = [&](int gq) { return make_float2(P[gq][0] - Q[gq][1], P[gq][1] + Q[gq][0]); };
@@ -557,13 +551,13 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
         }
         __syncthreads();                                      // S and F reads done
         if (act0) {
-          VT* dst = S + (size_t)locp0 * kmaxg * NB + lane;
+          VT* dst = S + (size_t)locp0 * kout * NB + lane;
 #pragma unroll
           for (int t = 0; t < KT; ++t)
             if (t < kout) dst[t * NB] = hold[t];
         }
         if (two) {
-          VT* dst = S + (size_t)locp1 * kmaxg * NB + lane;
+          VT* dst = S + (size_t)locp1 * kout * NB + lane;
 #pragma unroll
           for (int gq = 0; gq < KG; ++gq) {
             if (2 * gq < kout) dst[(2 * gq) * NB] = out_lo(gq);
@@ -913,12 +907,13 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
     cur ^= 1;
   };
   // LDS bytes of a fused group of 2^k pairs: state [2^k][kmaxg][NB] + factors
-  // [2^k][2 kmaxg kld] with kld <= kt, + kt entries of slack (the compute loops
-  // read whole kt-wide rows; entries past a row feed only discarded outputs)
+  // [2^k][2 kmaxg kld] with kld <= kt, + 2 kt entries of slack (the compute
+  // loops read whole kt-wide rows and one row past a block's end; entries past
+  // a row feed only discarded outputs)
   // (vector path: two state buffers [2^k][kmaxg][NB], no factors)
   auto fused_lds = [&](int kk, int kmg, int kt) -> size_t {
     if (!mfma) return ((size_t)2 << kk) * kmg * NB * sizeof(VT);
-    return (((size_t)1 << kk) * ((size_t)kmg * NB + (size_t)2 * kmg * kt) + kt) * sizeof(VT);
+    return (((size_t)1 << kk) * ((size_t)kmg * NB + (size_t)2 * kmg * kt) + 2 * kt) * sizeof(VT);
   };
   auto add_stages = [&](int lo, int hi, bool gside) {   // output levels lo..hi
     int l = lo;
@@ -1250,7 +1245,7 @@ int apply_batch_t(ibf_batch_s* b, const void* const* g, const int64_t* ldg, void
         const FusedArgs& A = y.f.A;
         const size_t nbv = y.mfma ? 64 : (size_t)A.NB;
         y.lds = (((size_t)1 << A.nst) * ((size_t)A.kmaxg * nbv + (size_t)2 * A.kmaxg * ph.kt) +
-                 ph.kt) * sizeof(VT);
+                 2 * ph.kt) * sizeof(VT);
       }
       ph.lds = std::max(ph.lds, y.lds);
       adj[q].push_back(y);
