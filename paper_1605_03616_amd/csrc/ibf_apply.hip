@@ -15,10 +15,10 @@
 //   k_apply_v      Omega leaf -> 2^l0 pairs:  mu = Vbar^* g   (per-leaf product, LDS-staged)
 //   k_apply_fused  k butterfly stages on one pair group in LDS (few right-hand
 //                  sides, vector FMA)
-//   k_apply_fused_mfma  the same for 64-column chunks in FP32 on MFMA
-//                  (v_mfma_f32_4x4x1f32, 16 blocks = 16 groups of 4 right-hand
-//                  sides), persistent over the groups with the next group's
-//                  loads in flight during the current group's last stage
+//   k_apply_fused_mfma  the same for 32-column chunks in FP32 on MFMA
+//                  (v_mfma_f32_4x4x1f32, 16 blocks = 2 slots x 8 groups of 4
+//                  right-hand sides), persistent over the groups with the next
+//                  groups' loads in flight during the current last stage
 //   k_apply_mid    swept-in middle block Mdot (per pair)
 //   k_apply_u      2^l0 pairs -> X leaf:  u = Ubar mu        (per-leaf product, LDS-staged)
 #include <algorithm>
@@ -240,46 +240,6 @@ __device__ __forceinline__ int fused_in0(int locp, int rem) {
   return ((anew >> 1) << (rem + 1)) | (2 * q);
 }
 
-// Factor blocks of one stage for slots s0 .. s0+NS-1 (fs <= 2 kBlock entries
-// per slot): loads into registers, stores into F[slot][fs].  The slot loop is
-// uniform, so the HBM address of a block is a scalar base plus the thread id.
-template <int NS, typename VT, typename FT>
-struct FactorBatch {
-  VT v[NS][2];
-  // (slot counts and block sizes pass through an empty asm so that the slot
-  // and entry bounds are evaluated here, not hoisted into long-lived masks)
-  __device__ __forceinline__ void load(const FT* blk, int fs, int s0, int nslot, int j, int rem,
-                                       int64_t ap, int64_t bpp, int L, int l) {
-    asm volatile("" : "+s"(fs), "+s"(nslot));
-#pragma unroll
-    for (int u = 0; u < NS; ++u) {
-      const int slot = s0 + u;
-      if (slot < nslot) {
-        const FT* src = blk + fused_pout(slot, j, rem, ap, bpp, L, l) * fs;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int o = threadIdx.x + h * kBlock;
-          if (o < fs) v[u][h] = load_factor(src, o);
-        }
-      }
-    }
-  }
-  __device__ __forceinline__ void store(VT* F, int fs, int s0, int nslot) const {
-    asm volatile("" : "+s"(fs), "+s"(nslot));
-#pragma unroll
-    for (int u = 0; u < NS; ++u) {
-      const int slot = s0 + u;
-      if (slot < nslot) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int o = threadIdx.x + h * kBlock;
-          if (o < fs) F[slot * fs + o] = v[u][h];
-        }
-      }
-    }
-  }
-};
-
 struct FusedDesc {
   const void* in;
   void* out;
@@ -376,105 +336,140 @@ __device__ __forceinline__ void apply_fused_body(const FusedDesc& D, int64_t lb)
   }
 }
 
-// Multi-RHS FP32 variant on MFMA, persistent: the block with logical index b
-// takes logical blocks b, b + lstep, ... below lend (logical block = pair group
-// x 64-column RHS chunk).  While a group's last stage computes, the loads of
-// the next group's input rows and first-stage factor blocks are already in
-// flight into registers, and each stage's computation overlaps the loads of
-// the next stage's factors, so HBM latency hides behind MFMA work.
+// Factor blocks of one stage for the 8 virtual slots of an MFMA block (8 / 2^k
+// consecutive groups of 2^k slots): thread t stages entries (t & 31) + 32 i of
+// slot t >> 5, so each thread computes one block address per stage and a wave
+// moves two 256-byte runs per load.  NL = KT loads per thread cover blocks of
+// up to 2 * 16 * KT entries (input rank <= 16, row length <= KT).
+template <typename VT, typename FT, int NL>
+struct SlotFactors {
+  VT v[NL];
+  __device__ __forceinline__ void load(const FT* blk, int fs, int k, int j, int rem, int64_t gid0,
+                                       int sh_end, int L, int l) {
+    const int u = threadIdx.x >> 5, e = threadIdx.x & 31;
+    const int64_t g = gid0 + (u >> k);
+    const int64_t ap = g >> sh_end, bpp = g & (((int64_t)1 << sh_end) - 1);
+    const FT* src = blk + fused_pout(u & ((1 << k) - 1), j, rem, ap, bpp, L, l) * fs + e;
+#pragma unroll
+    for (int i = 0; i < NL; ++i)
+      if (e + 32 * i < fs) v[i] = load_factor(src, 32 * i);
+  }
+  __device__ __forceinline__ void store(VT* F, int fs) const {
+    const int u = threadIdx.x >> 5, e = threadIdx.x & 31;
+    VT* dst = F + u * fs + e;
+#pragma unroll
+    for (int i = 0; i < NL; ++i)
+      if (e + 32 * i < fs) dst[32 * i] = v[i];
+  }
+};
+
+// Multi-RHS FP32 variant on MFMA.  A block holds 8 virtual slots: one group of
+// 8 pairs (3 stages), or 8 / 2^k consecutive groups of 2^k pairs side by side,
+// for one 32-column RHS chunk.  It is persistent: the block with logical index
+// b takes logical blocks b, b + lstep, ... below lend (logical block = 8
+// consecutive input pairs x chunk; the chunks of the same pairs are adjacent
+// and so share the factor blocks through one XCD's L2).  While the last stage
+// computes, the loads of the next block's input rows and first-stage factors
+// are already in flight into registers, and each stage's computation overlaps
+// the loads of the next stage's factors.
 //
-// Lane l carries RHS column l of the chunk.  MFMA block b = l >> 2 is a group
-// of 4 columns; A-operand row i = l & 3 is the raw float i of the pair of
-// complex entries (t = 2g, 2g+1): (re t0, im t0, re t1, im t1).  With
-// P = sum f_i x_re and Q = sum f_i x_im, the complex outputs are
+// Wave w computes virtual slots 2w and 2w + 1 together: lane l belongs to slot
+// 2w + (l >> 5) and carries RHS column l & 31.  The 16 MFMA blocks of
+// v_mfma_f32_4x4x1f32 are groups of 4 columns, 8 per slot; A-operand row
+// i = l & 3 is the raw float i of the slot's pair of complex factor entries
+// (t = 2g, 2g+1): (re t0, im t0, re t1, im t1).  With P = sum f_i x_re and
+// Q = sum f_i x_im, the complex outputs are
 //   out[2g]   = (P0 - Q1, P1 + Q0),  out[2g+1] = (P2 - Q3, P3 + Q2).
-// Wave v owns output slot v, and slot v + 4 when the group has 8 slots (the
-// two products run one after the other: they share no operands).
 template <typename VT, typename FT, int KT>
 __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, int64_t lstep,
                                                 int64_t lend) {
   static_assert(sizeof(VT) == 8, "MFMA variant computes in FP32");
   constexpr int KG = KT / 2;                                  // row pairs (MFMA row groups)
-  constexpr int NB = 64;
-  // input rows held in flight per thread (row r goes to wave r mod 4); groups
-  // with more rows than 4 XR copy the rest synchronously
-  constexpr int XR = KT <= 12 ? 2 * KT : KT;
+  constexpr int NB = 32;                                      // RHS columns per chunk
+  constexpr int NV = 8;                                       // virtual slots per block
+  // input rows held in flight per thread (row r goes to thread row r mod 8);
+  // blocks with more input rows than 8 XR copy the rest synchronously
+  constexpr int XR = KT;
   extern __shared__ __align__(16) unsigned char smem[];
   const VT* __restrict__ in = reinterpret_cast<const VT*>(D.in);
   VT* __restrict__ out = reinterpret_cast<VT*>(D.out);
   const FusedArgs& A = D.A;
   const int k = A.nst, L = A.L, kmaxg = A.kmaxg, nrhs = A.nrhs, nchunk = A.nchunk;
   const int nslot = 1 << k;
-  // S: the state of stage j as [slot][ranks[j]][64] (2 kin contiguous input
-  // rows per output slot); F: the stage's factor blocks [slot][2 kin kld],
-  // followed by 2 KT entries of slack for reads past the last row
+  // S: the state of stage j as [virtual slot][ranks[j]][32] (the 2 kin input
+  // rows of an output slot are contiguous); F: the stage's factor blocks
+  // [virtual slot][2 kin kld], followed by 2 KT entries of slack for reads
+  // past the last row
   VT* S = reinterpret_cast<VT*>(smem);
-  VT* F = S + (size_t)nslot * kmaxg * NB;
+  VT* F = S + (size_t)NV * kmaxg * NB;
   const int sh_end = L - (A.l_start + k - 1);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int fi = lane & 3;
-  const int kin0 = A.ranks[0], rows0 = nslot * kin0, fs0 = 2 * kin0 * A.kld[0];
+  const int col = lane & 31, fi = lane & 3;
+  const int vs = 2 * wave + (lane >> 5);                      // this lane's virtual slot
+  const int grp = vs >> k, loc = vs & (nslot - 1);            // its group and local slot
+  const int trow = threadIdx.x >> 5;                          // row phase of the copies
+  const int kin0 = A.ranks[0], rows0 = NV * kin0, fs0 = 2 * kin0 * A.kld[0];
   const FT* blk0 = reinterpret_cast<const FT*>(A.blk[0]);
-  const bool two = nslot > 4;
 
-  struct Grp {
-    int64_t gid, ap, bpp;
+  struct Blk {
+    int64_t gid0;                                             // first group
     int nb0, nbw;
   };
   auto decode = [&](int64_t l) {
-    Grp g;
-    g.gid = l / nchunk;
-    g.nb0 = (int)(l - g.gid * nchunk) * NB;
+    Blk g;
+    const int64_t q = l / nchunk;
+    g.gid0 = q << (3 - k);
+    g.nb0 = (int)(l - q * nchunk) * NB;
     g.nbw = min(NB, nrhs - g.nb0);
-    g.ap = g.gid >> sh_end;
-    g.bpp = g.gid & (((int64_t)1 << sh_end) - 1);
     return g;
   };
-  FactorBatch<8, VT, FT> fb;
+  SlotFactors<VT, FT, KT> fb;
   VT xin[XR];
-  // The group's input rows are contiguous in HBM (pairs (gid << k) .. + nslot,
-  // kin0 rows each) and land contiguously in S.  Row r goes to wave r mod 4;
-  // columns >= nbw read as zero.  The per-row offsets and bounds depend only
-  // on launch constants; passed through an empty asm they are recomputed at
-  // each call instead of being hoisted out of the group loop, where dozens of
-  // them would stay live in registers across every stage.
-  auto fetch = [&](const Grp& g) {
-    int rows_v = rows0, fs_v = fs0, wave_v = wave;
+  // The block's input rows are contiguous in HBM (pairs (gid0 << k) .. + 8,
+  // kin0 rows each) and land contiguously in S; columns >= nbw read as zero.
+  // The per-row offsets and bounds depend only on launch constants; passed
+  // through an empty asm they are recomputed at each call instead of being
+  // hoisted out of the block loop, where dozens of them would stay live in
+  // registers across every stage.
+  auto fetch = [&](const Blk& g) {
+    int rows_v = rows0, fs_v = fs0, trow_v = trow;
     int64_t ld_v = nrhs;
-    asm volatile("" : "+s"(rows_v), "+s"(fs_v), "+s"(wave_v), "+s"(ld_v));
-    fb.load(blk0, fs_v, 0, nslot, 0, k - 1, g.ap, g.bpp, L, A.l_start);
-    const VT* src = in + ((g.gid << k) * kin0 + wave_v) * ld_v + g.nb0 + lane;
-    const bool col = lane < g.nbw;
+    asm volatile("" : "+s"(rows_v), "+s"(fs_v), "+v"(trow_v), "+s"(ld_v));
+    fb.load(blk0, fs_v, k, 0, k - 1, g.gid0, sh_end, L, A.l_start);
+    const VT* src = in + ((g.gid0 << k) * kin0 + trow_v) * ld_v + g.nb0 + col;
+    const bool ok = col < g.nbw;
 #pragma unroll
     for (int i = 0; i < XR; ++i)
-      if (wave_v + 4 * i < rows_v) xin[i] = col ? src[4 * i * ld_v] : Zero<VT>::v();
+      if (trow_v + 8 * i < rows_v) xin[i] = ok ? src[8 * i * ld_v] : Zero<VT>::v();
   };
-  auto deposit = [&](const Grp& g) {
-    int rows_v = rows0, fs_v = fs0, wave_v = wave;
-    asm volatile("" : "+s"(rows_v), "+s"(fs_v), "+s"(wave_v));
-    VT* dst = S + wave_v * NB + lane;
+  auto deposit = [&](const Blk& g) {
+    int rows_v = rows0, fs_v = fs0, trow_v = trow;
+    asm volatile("" : "+s"(rows_v), "+s"(fs_v), "+v"(trow_v));
+    VT* dst = S + trow_v * NB + col;
 #pragma unroll
     for (int i = 0; i < XR; ++i)
-      if (wave_v + 4 * i < rows_v) dst[4 * i * NB] = xin[i];
-    if (rows_v > 4 * XR) {
-      const VT* src = in + (g.gid << k) * kin0 * nrhs + g.nb0 + lane;
-      for (int r = 4 * XR + wave_v; r < rows_v; r += 4)
-        S[r * NB + lane] = lane < g.nbw ? src[(int64_t)r * nrhs] : Zero<VT>::v();
+      if (trow_v + 8 * i < rows_v) dst[8 * i * NB] = xin[i];
+    if (rows_v > 8 * XR) {
+      const VT* src = in + (g.gid0 << k) * kin0 * nrhs + g.nb0 + col;
+      for (int r = 8 * XR + trow_v; r < rows_v; r += 8)
+        S[r * NB + col] = col < g.nbw ? src[(int64_t)r * nrhs] : Zero<VT>::v();
     }
-    fb.store(F, fs_v, 0, nslot);
+    fb.store(F, fs_v);
   };
 
-  Grp cur = decode(lb);
+  Blk cur = decode(lb);
   fetch(cur);
   while (true) {
     deposit(cur);
     __syncthreads();
     const int64_t nlb = lb + lstep;
     const bool more = nlb < lend;
-    const Grp nxt = more ? decode(nlb) : cur;
+    const Blk nxt = more ? decode(nlb) : cur;
+    const int64_t gme = cur.gid0 + grp;                       // this lane's group
+    const int64_t ap = gme >> sh_end, bpp = gme & (((int64_t)1 << sh_end) - 1);
     // one stage; the last one is peeled off the stage loop so that the next
-    // group's prefetched rows are live only during it
+    // block's prefetched rows are live only during it
     auto stage = [&](int j, auto last_c) {
       constexpr bool LAST = decltype(last_c)::value;
       const int l = A.l_start + j;
@@ -482,23 +477,18 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
       const int fs = 2 * kin * ke;
       const int rem = k - j - 1;
       if constexpr (!LAST)   // next stage's factor blocks: in flight during this stage
-        fb.load(reinterpret_cast<const FT*>(A.blk[j + 1]), 2 * kout * A.kld[j + 1], 0, nslot,
-                j + 1, rem - 1, cur.ap, cur.bpp, L, l + 1);
-      else if (more)         // the next group: in flight during the last stage
+        fb.load(reinterpret_cast<const FT*>(A.blk[j + 1]), 2 * kout * A.kld[j + 1], k, j + 1,
+                rem - 1, cur.gid0, sh_end, L, l + 1);
+      else if (more)         // the next block: in flight during the last stage
         fetch(nxt);
       v4f P[KG], Q[KG];
-      // the block product of output slot locp into P, Q: one loop over the
-      // 2 kin input rows of its two children, which are adjacent slots and so
-      // contiguous rows in S, as are the block's factor rows in F
-      auto product = [&](int locp) {
-#pragma unroll
-        for (int gq = 0; gq < KG; ++gq) {
-          P[gq] = v4f{0.f, 0.f, 0.f, 0.f};
-          Q[gq] = v4f{0.f, 0.f, 0.f, 0.f};
-        }
-        const VT* xp = S + (size_t)fused_in0(locp, rem) * kin * NB + lane;
-        const float* fp = reinterpret_cast<const float*>(F + (size_t)locp * fs) + fi;
-        const int fstep = 2 * ke;                              // floats per factor row
+      {
+        // the block product of this lane's slot: one loop over the 2 kin
+        // input rows of its two children (adjacent slots, so contiguous rows
+        // in S), and the block's factor rows in F
+        const VT* xp = S + (size_t)((grp << k) + fused_in0(loc, rem)) * kin * NB + col;
+        const float* fp = reinterpret_cast<const float*>(F + (size_t)vs * fs) + fi;
+        const int fstep = 2 * ke;                             // floats per factor row
         auto load_row = [&](const VT* x, const float* f, float (&Av)[KG], VT& X) {
           X = *x;
 #pragma unroll
@@ -514,6 +504,13 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
         // software-pipelined: the LDS reads of the next row are in flight
         // while the MFMAs of the current row issue.  The last iteration reads
         // one row past the end, inside the LDS allocation and never used.
+        // (Starting the first row's MFMAs from an inline zero instead of
+        // clearing the accumulators costs more registers than it saves.)
+#pragma unroll
+        for (int gq = 0; gq < KG; ++gq) {
+          P[gq] = v4f{0.f, 0.f, 0.f, 0.f};
+          Q[gq] = v4f{0.f, 0.f, 0.f, 0.f};
+        }
         float av[KG], bv[KG];
         VT xa, xb;
         load_row(xp, fp, av, xa);
@@ -530,60 +527,29 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
           mfma_row(bv, xb);
           __builtin_amdgcn_sched_barrier(0);
         }
-      };
-      // complex output rows 2 gq, 2 gq + 1 of the product
-      auto out_lo = [&](int gq) { return make_float2(P[gq][0] - Q[gq][1], P[gq][1] + Q[gq][0]); };
-      auto out_hi = [&](int gq) { return make_float2(P[gq][2] - Q[gq][3], P[gq][3] + Q[gq][2]); };
-      const int locp0 = wave, locp1 = wave + 4;
-      const bool act0 = locp0 < nslot;
+      }
       if constexpr (!LAST) {
-        // outputs replace inputs in S once every wave has read its inputs: the
-        // first slot's outputs wait in registers while the second computes
-        VT hold[KT];
-        if (act0) {
-          product(locp0);
-#pragma unroll
-          for (int gq = 0; gq < KG; ++gq) {
-            hold[2 * gq] = out_lo(gq);
-            hold[2 * gq + 1] = out_hi(gq);
-          }
-          if (two) product(locp1);
-        }
-        __syncthreads();                                      // S and F reads done
-        if (act0) {
-          VT* dst = S + (size_t)locp0 * kout * NB + lane;
-#pragma unroll
-          for (int t = 0; t < KT; ++t)
-            if (t < kout) dst[t * NB] = hold[t];
-        }
-        if (two) {
-          VT* dst = S + (size_t)locp1 * kout * NB + lane;
-#pragma unroll
-          for (int gq = 0; gq < KG; ++gq) {
-            if (2 * gq < kout) dst[(2 * gq) * NB] = out_lo(gq);
-            if (2 * gq + 1 < kout) dst[(2 * gq + 1) * NB] = out_hi(gq);
-          }
-        }
-        fb.store(F, 2 * kout * A.kld[j + 1], 0, nslot);
+        // outputs replace inputs in S once every wave has read its inputs
         __syncthreads();
-      } else {
-        // last stage: each slot's rows of 64 columns go straight to HBM
-        const bool col = lane < cur.nbw;
-#pragma unroll 1
-        for (int m = 0; m < (two ? 2 : 1); ++m) {
-          const int locp = wave + 4 * m;
-          if (locp < nslot) {
-            product(locp);
-            VT* dst = out + fused_pout(locp, j, 0, cur.ap, cur.bpp, L, l) * kout * nrhs +
-                      cur.nb0 + lane;
-            if (col) {
+        VT* dst = S + (size_t)vs * kout * NB + col;
 #pragma unroll
-              for (int gq = 0; gq < KG; ++gq) {
-                if (2 * gq < kout) dst[(int64_t)(2 * gq) * nrhs] = out_lo(gq);
-                if (2 * gq + 1 < kout) dst[(int64_t)(2 * gq + 1) * nrhs] = out_hi(gq);
-              }
-            }
-          }
+        for (int gq = 0; gq < KG; ++gq) {
+          const v4f p = P[gq], q = Q[gq];
+          if (2 * gq < kout) dst[(2 * gq) * NB] = make_float2(p[0] - q[1], p[1] + q[0]);
+          if (2 * gq + 1 < kout) dst[(2 * gq + 1) * NB] = make_float2(p[2] - q[3], p[3] + q[2]);
+        }
+        fb.store(F, 2 * kout * A.kld[j + 1]);
+        __syncthreads();
+      } else if (col < cur.nbw) {
+        // last stage: rows of 32 columns straight to HBM
+        VT* dst = out + fused_pout(loc, j, 0, ap, bpp, L, l) * kout * nrhs + cur.nb0 + col;
+#pragma unroll
+        for (int gq = 0; gq < KG; ++gq) {
+          const v4f p = P[gq], q = Q[gq];
+          if (2 * gq < kout)
+            dst[(int64_t)(2 * gq) * nrhs] = make_float2(p[0] - q[1], p[1] + q[0]);
+          if (2 * gq + 1 < kout)
+            dst[(int64_t)(2 * gq + 1) * nrhs] = make_float2(p[2] - q[3], p[3] + q[2]);
         }
       }
     };
@@ -862,10 +828,10 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
   int lmax = 0, rc;
   if ((rc = lds_limit(p->device, &lmax))) return rc;
   const size_t budget_mfma = std::min<size_t>(kLdsBudgetMfma, (size_t)lmax);
-  // Multi-RHS FP32 stages run on MFMA with 64-column chunks; otherwise the
+  // Multi-RHS FP32 stages run on MFMA with 32-column chunks; otherwise the
   // vector kernels take chunks of up to 32 columns.
   const bool mfma = sizeof(VT) == 8 && nrhs >= 32;
-  const int NB = mfma ? 64 : std::min(nrhs, 32);
+  const int NB = mfma ? 32 : std::min(nrhs, 32);
   const int nchunk = (nrhs + NB - 1) / NB;
   const int NBo = std::min(nrhs, 32);                         // outer (V, U) kernels
   // V
@@ -906,14 +872,15 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
     seq.push_back(x);
     cur ^= 1;
   };
-  // LDS bytes of a fused group of 2^k pairs: state [2^k][kmaxg][NB] + factors
-  // [2^k][2 kmaxg kld] with kld <= kt, + 2 kt entries of slack (the compute
-  // loops read whole kt-wide rows and one row past a block's end; entries past
-  // a row feed only discarded outputs)
-  // (vector path: two state buffers [2^k][kmaxg][NB], no factors)
+  // LDS bytes of a fused block.  MFMA: 8 virtual slots (one group of 8 pairs or
+  // 8 / 2^k groups side by side), state [8][kmaxg][32] + factors
+  // [8][2 kmaxg kld] with kld <= kt, + 2 kt entries of slack (the compute loops
+  // read whole kt-wide rows and one row past a block's end; entries past a row
+  // feed only discarded outputs).  Vector path: a group of 2^k pairs in two
+  // state buffers [2^k][kmaxg][NB], no factors.
   auto fused_lds = [&](int kk, int kmg, int kt) -> size_t {
     if (!mfma) return ((size_t)2 << kk) * kmg * NB * sizeof(VT);
-    return (((size_t)1 << kk) * ((size_t)kmg * NB + (size_t)2 * kmg * kt) + 2 * kt) * sizeof(VT);
+    return ((size_t)8 * ((size_t)kmg * NB + (size_t)2 * kmg * kt) + 2 * kt) * sizeof(VT);
   };
   auto add_stages = [&](int lo, int hi, bool gside) {   // output levels lo..hi
     int l = lo;
@@ -926,7 +893,7 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
         if (next > L - l + 1) break;                          // group must fit the b bits
         int km = 1;
         for (int j = 0; j <= next; ++j) km = std::max(km, rank_at(l - 1 + j, gside));
-        // MFMA: 8 slots for 4 waves; vector: at most 4 outputs per thread and stage
+        // MFMA: at most 8 slots a block; vector: at most 4 outputs per thread and stage
         if (mfma ? (next > 3) : (((int64_t)1 << next) * km * NB > 4 * kBlock)) break;
         if (fused_lds(next, km, even_kt(km)) > (mfma ? budget_mfma : kLdsBudget)) break;
         kk = next;
@@ -957,7 +924,7 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
       }
       x.kt = even_kt(kom);
       x.lds = fused_lds(kk, km, x.kt);
-      x.nblocks = (p->npairs >> kk) * nchunk;
+      x.nblocks = (p->npairs >> (mfma ? 3 : kk)) * nchunk;
       x.f.in = w[cur];
       x.f.out = w[cur ^ 1];
       x.flops = 8.0 * nnz * nrhs;
@@ -1243,8 +1210,7 @@ int apply_batch_t(ibf_batch_s* b, const void* const* g, const int64_t* ldg, void
         y.lds = base + (y.v.stage_f ? fac : 0);
       } else if (y.kind == kLaunchFused && y.mfma) {
         const FusedArgs& A = y.f.A;
-        const size_t nbv = y.mfma ? 64 : (size_t)A.NB;
-        y.lds = (((size_t)1 << A.nst) * ((size_t)A.kmaxg * nbv + (size_t)2 * A.kmaxg * ph.kt) +
+        y.lds = ((size_t)8 * ((size_t)A.kmaxg * A.NB + (size_t)2 * A.kmaxg * ph.kt) +
                  2 * ph.kt) * sizeof(VT);
       }
       ph.lds = std::max(ph.lds, y.lds);
