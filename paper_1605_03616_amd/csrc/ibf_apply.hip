@@ -697,6 +697,216 @@ __global__ __launch_bounds__(kBlock) void k_batch_u(const UDesc* __restrict__ ds
   apply_u_body<VT, FT>(ds[p], (int64_t)blockIdx.x - boff[p]);
 }
 
+// ---------------------------------------------------------------------------
+// V and U on MFMA (FP32 state, 64-column RHS chunks, leaves of at most 16
+// points).  Both are small complex products per leaf with the same operand
+// layout as the butterfly stages: lane l carries RHS column l, MFMA block
+// b = l >> 2 a group of 4 columns, A-operand row i = l & 3 the raw float i of
+// a pair of complex factor entries, and the outputs of a row pair follow from
+// P = sum f_i x_re and Q = sum f_i x_im as
+//   out[2g] = (P0 - Q1, P1 + Q0),  out[2g+1] = (P2 - Q3, P3 + Q2).
+// ---------------------------------------------------------------------------
+constexpr int kLeafMfma = 16;          // leaf points handled by the MFMA V / U
+constexpr int kVChunk = 6;             // output row pairs per V accumulator set
+
+// V: the leaf's output rows t = a K + k (R = 2^l0 K of them, in pairs) over
+// its points.  LDS: g_leaf [16][64] (gathered, zero rows past the leaf's
+// points) and Vbar [cnt][R] (+ slack for the last chunk's reads past R).
+// Wave w computes row-pair chunks w, w + 4, ... with the 16 point rows of g
+// held in registers.
+template <typename FT>
+__device__ __forceinline__ void apply_v_mfma_body(const VDesc& d, int64_t lb) {
+  constexpr int NB = 64, CH = kVChunk, SM = kLeafMfma;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const float2* __restrict__ g = reinterpret_cast<const float2*>(d.g);
+  const FT* __restrict__ vbar = reinterpret_cast<const FT*>(d.vbar);
+  float2* __restrict__ mu = reinterpret_cast<float2*>(d.mu);
+  const int L = d.L, l0 = d.l0, K = d.K, nrhs = d.nrhs, nchunk = d.nchunk;
+  const int64_t ldg = d.ldg;
+  float2* gl = reinterpret_cast<float2*>(smem);               // [16][64]
+  float2* vl = gl + SM * NB;                                  // [cnt][R]
+  const int64_t b = lb / nchunk;
+  const int nb0 = (int)(lb - b * nchunk) * NB;
+  const int nbw = min(NB, nrhs - nb0);
+  const int32_t j0 = d.xioff[b], cnt = d.xioff[b + 1] - j0;
+  const int R = K << l0;
+  // gather g for the leaf (points fastest: contiguous within a column of g);
+  // rows and columns outside the leaf and the chunk are zero
+  staged_copy_to<8>(SM * NB, gl, [&](int e, int& off) {
+    const int n = e >> 4, j = e & 15;
+    off = j * NB + n;
+    return (j < cnt && n < nbw) ? g[(int64_t)(nb0 + n) * ldg + d.perm_xi[j0 + j]]
+                                : make_float2(0.f, 0.f);
+  });
+  const FT* vsrc = vbar + (int64_t)j0 * R;
+  staged_copy_to<8>(cnt * R, vl, [&](int e, int& off) {
+    off = e;
+    return load_factor(vsrc, e);
+  });
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int fi = lane & 3;
+  float2 xr[SM];
+#pragma unroll
+  for (int j = 0; j < SM; ++j) xr[j] = gl[j * NB + lane];
+  const int npair = R >> 1, nchk = (npair + CH - 1) / CH;
+  const int sh = L - l0;
+  const FastDiv divK(K);
+  for (int c = wave; c < nchk; c += 4) {
+    v4f P[CH], Q[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      P[q] = v4f{0.f, 0.f, 0.f, 0.f};
+      Q[q] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+    const float* f = reinterpret_cast<const float*>(vl) + 4 * c * CH + fi;
+#pragma unroll
+    for (int j = 0; j < SM; ++j) {
+      if (j < cnt) {
+        float av[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) av[q] = f[2 * j * R + 4 * q];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+          P[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(av[q], xr[j].x, P[q], 0, 0, 0);
+          Q[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(av[q], xr[j].y, Q[q], 0, 0, 0);
+        }
+      }
+    }
+    if (lane < nbw) {
+#pragma unroll
+      for (int q = 0; q < CH; ++q) {
+        const int rp = c * CH + q;
+        if (rp < npair) {
+          const v4f pp = P[q], qq = Q[q];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            int a, k;
+            divK.divmod(2 * rp + h, a, k);
+            const int64_t pr = ((int64_t)a << sh) | b;
+            mu[(pr * K + k) * nrhs + nb0 + lane] =
+                h == 0 ? make_float2(pp[0] - qq[1], pp[1] + qq[0])
+                       : make_float2(pp[2] - qq[3], pp[3] + qq[2]);
+          }
+        }
+      }
+    }
+  }
+}
+
+// U: u[x][n] = sum_r Ubar[x][r] mu[p0 + r / K][r % K][n] over the R = 2^l0 K
+// rows of the leaf's contiguous pairs (R a multiple of 16).  LDS: Ubar
+// transposed to [R][16] (rows past the leaf's points are zero) and a [16][64]
+// tile that turns the column-per-lane results into point-contiguous stores.
+// Wave w computes point pairs w and w + 4 over all R rows, reading the mu rows
+// straight from memory: the four waves read the same rows at about the same
+// time, so all but the first read of a row hit the CU's cache.
+template <typename FT>
+__device__ __forceinline__ void apply_u_mfma_body(const UDesc& d, int64_t lb) {
+  constexpr int NB = 64, SM = kLeafMfma, RB = 8;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const float2* __restrict__ mu = reinterpret_cast<const float2*>(d.mu);
+  float2* __restrict__ u = reinterpret_cast<float2*>(d.u);
+  const FT* __restrict__ ubar = reinterpret_cast<const FT*>(d.ubar);
+  const int l0 = d.l0, K = d.K, nrhs = d.nrhs, nchunk = d.nchunk;
+  const int64_t ldu = d.ldu;
+  const int R = K << l0;
+  float2* ul = reinterpret_cast<float2*>(smem);               // [R][16]
+  float2* ot = ul + (size_t)R * SM;                           // [16][64]
+  const int64_t a = lb / nchunk;
+  const int nb0 = (int)(lb - a * nchunk) * NB;
+  const int nbw = min(NB, nrhs - nb0);
+  const int32_t x0 = d.xoff[a], cnt = d.xoff[a + 1] - x0;
+  const int64_t p0 = a << l0;
+  const FT* usrc = ubar + (int64_t)x0 * R;
+  const FastDiv divR(R);
+  staged_copy_to<8>(R * SM, ul, [&](int e, int& off) {
+    int x, r;
+    divR.divmod(e, x, r);                                     // e = x R + r: reads coalesced
+    off = r * SM + x;
+    return x < cnt ? load_factor(usrc, e) : make_float2(0.f, 0.f);
+  });
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int fi = lane & 3;
+  v4f P[2], Q[2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    P[m] = v4f{0.f, 0.f, 0.f, 0.f};
+    Q[m] = v4f{0.f, 0.f, 0.f, 0.f};
+  }
+  // A operand of row r for point pairs wave and wave + 4: floats 4 wave + fi
+  // and 4 wave + 16 + fi of LDS row r
+  const float* f = reinterpret_cast<const float*>(ul) + 4 * wave + fi;
+  const bool col = lane < nbw;
+  const float2* src = mu + p0 * K * nrhs + nb0 + lane;
+  float2 xa[RB], xb[RB];
+  auto load_rows = [&](int r0, float2 (&X)[RB]) {
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+      X[i] = col ? src[(int64_t)(r0 + i) * nrhs] : make_float2(0.f, 0.f);
+  };
+  auto mfma_rows = [&](int r0, const float2 (&X)[RB]) {
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      const float* fr = f + 2 * SM * (r0 + i);
+      const float a0 = fr[0], a1 = fr[16];
+      P[0] = __builtin_amdgcn_mfma_f32_4x4x1f32(a0, X[i].x, P[0], 0, 0, 0);
+      Q[0] = __builtin_amdgcn_mfma_f32_4x4x1f32(a0, X[i].y, Q[0], 0, 0, 0);
+      P[1] = __builtin_amdgcn_mfma_f32_4x4x1f32(a1, X[i].x, P[1], 0, 0, 0);
+      Q[1] = __builtin_amdgcn_mfma_f32_4x4x1f32(a1, X[i].y, Q[1], 0, 0, 0);
+    }
+  };
+  // rows in batches of RB, the next batch's loads in flight during the MFMAs
+  load_rows(0, xa);
+#pragma unroll 1
+  for (int r0 = 0; r0 < R; r0 += 2 * RB) {
+    load_rows(r0 + RB, xb);
+    mfma_rows(r0, xa);
+    if (r0 + 2 * RB < R) load_rows(r0 + 2 * RB, xa);
+    mfma_rows(r0 + RB, xb);
+  }
+  // points 2 q + h of pair q (q = wave, wave + 4) to the [16][64] tile
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const int q = wave + 4 * m;
+    const v4f pp = P[m], qq = Q[m];
+    ot[(2 * q) * NB + lane] = make_float2(pp[0] - qq[1], pp[1] + qq[0]);
+    ot[(2 * q + 1) * NB + lane] = make_float2(pp[2] - qq[3], pp[3] + qq[2]);
+  }
+  __syncthreads();
+  // point-contiguous stores: item = n * 16 + x
+  for (int item = threadIdx.x; item < SM * NB; item += kBlock) {
+    const int x = item & 15, n = item >> 4;
+    if (x < cnt && n < nbw) u[(int64_t)(nb0 + n) * ldu + d.perm_x[x0 + x]] = ot[x * NB + n];
+  }
+}
+
+template <typename FT>
+__global__ __launch_bounds__(kBlock) void k_apply_v_mfma(VDesc d) {
+  apply_v_mfma_body<FT>(d, xcd_logical_block((int64_t)gridDim.x));
+}
+template <typename FT>
+__global__ __launch_bounds__(kBlock) void k_batch_v_mfma(const VDesc* __restrict__ ds,
+                                                         const int64_t* __restrict__ boff,
+                                                         int count) {
+  const int p = find_problem(boff, count, blockIdx.x);
+  apply_v_mfma_body<FT>(ds[p], (int64_t)blockIdx.x - boff[p]);
+}
+template <typename FT>
+__global__ __launch_bounds__(kBlock) void k_apply_u_mfma(UDesc d) {
+  apply_u_mfma_body<FT>(d, xcd_logical_block((int64_t)gridDim.x));
+}
+template <typename FT>
+__global__ __launch_bounds__(kBlock) void k_batch_u_mfma(const UDesc* __restrict__ ds,
+                                                         const int64_t* __restrict__ boff,
+                                                         int count) {
+  const int p = find_problem(boff, count, blockIdx.x);
+  apply_u_mfma_body<FT>(ds[p], (int64_t)blockIdx.x - boff[p]);
+}
+
 inline unsigned nblocks(int64_t total) { return (unsigned)((total + kBlock - 1) / kBlock); }
 
 // Records a hipEvent pair around each launch when profiling is requested.
@@ -770,10 +980,10 @@ struct Launch {
 
 inline const char* launch_name(const Launch& x) {
   switch (x.kind) {
-    case kLaunchV: return "apply_v";
+    case kLaunchV: return x.mfma ? "apply_v_mfma" : "apply_v";
     case kLaunchFused: return x.mfma ? "apply_fused_mfma" : "apply_fused";
     case kLaunchMid: return "apply_mid";
-    default: return "apply_u";
+    default: return x.mfma ? "apply_u_mfma" : "apply_u";
   }
 }
 
@@ -840,23 +1050,34 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
     x.kind = kLaunchV;
     const int K = p->k_vbar;
     x.kt = even_kt(K);
-    int NBv = NBo;
-    while (NBv > 1 && (size_t)p->smax_xi * NBv * sizeof(VT) > kLdsBudget / 2) NBv /= 2;
-    const int nchv = (nrhs + NBv - 1) / NBv;
-    const size_t base = (size_t)p->smax_xi * NBv * sizeof(VT);
-    const size_t fac = (size_t)p->smax_xi * (1 << l0) * x.kt * sizeof(VT);
-    if (base > kLdsBudget) {
-      set_error("ibf_apply: an Omega leaf holds too many points for the apply kernels");
-      return IBF_ERR_UNSUPPORTED;
-    }
-    const int stage_f = base + fac <= kLdsBudget ? 1 : 0;
-    x.lds = base + (stage_f ? fac : 0);
-    x.nblocks = p->nleaf * nchv;
-    x.v = VDesc{g, ldg, p->d_perm_xi, p->d_xioff, p->d_vbar, w[0], L, l0, K, nrhs, NBv, nchv,
-                p->smax_xi, stage_f};
     const double nnz = (double)p->nnz_vbar;
     x.flops = 8.0 * nnz * nrhs;
     x.bytes = nnz * fb + vb * nrhs * ((double)p->nxi + (double)p->npairs * K);
+    if (mfma && p->smax_xi <= kLeafMfma && ((K << l0) & 1) == 0) {
+      // MFMA leaf product, 64-column chunks
+      const int R = K << l0;
+      const int nchv = (nrhs + 63) / 64;
+      x.mfma = true;
+      x.lds = ((size_t)kLeafMfma * 64 + (size_t)p->smax_xi * R + 2 * kVChunk) * sizeof(VT);
+      x.nblocks = p->nleaf * nchv;
+      x.v = VDesc{g, ldg, p->d_perm_xi, p->d_xioff, p->d_vbar, w[0], L, l0, K, nrhs, 64, nchv,
+                  p->smax_xi, 1};
+    } else {
+      int NBv = NBo;
+      while (NBv > 1 && (size_t)p->smax_xi * NBv * sizeof(VT) > kLdsBudget / 2) NBv /= 2;
+      const int nchv = (nrhs + NBv - 1) / NBv;
+      const size_t base = (size_t)p->smax_xi * NBv * sizeof(VT);
+      const size_t fac = (size_t)p->smax_xi * (1 << l0) * x.kt * sizeof(VT);
+      if (base > kLdsBudget) {
+        set_error("ibf_apply: an Omega leaf holds too many points for the apply kernels");
+        return IBF_ERR_UNSUPPORTED;
+      }
+      const int stage_f = base + fac <= kLdsBudget ? 1 : 0;
+      x.lds = base + (stage_f ? fac : 0);
+      x.nblocks = p->nleaf * nchv;
+      x.v = VDesc{g, ldg, p->d_perm_xi, p->d_xioff, p->d_vbar, w[0], L, l0, K, nrhs, NBv, nchv,
+                  p->smax_xi, stage_f};
+    }
     seq.push_back(x);
   }
   int cur = 0;
@@ -946,23 +1167,34 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
     Launch x;
     x.kind = kLaunchU;
     const int K = p->k_ubar;
-    int NBu = NBo;
-    while (NBu > 1 && (size_t)(1 << l0) * K * NBu * sizeof(VT) > kLdsBudget / 2) NBu /= 2;
-    const int nchu = (nrhs + NBu - 1) / NBu;
-    const size_t base = (size_t)(1 << l0) * K * NBu * sizeof(VT);
-    const size_t fac = (size_t)p->smax_x * ((1 << l0) * K + 1) * sizeof(VT);
-    if (base > kLdsBudget) {
-      set_error("ibf_apply: leaf size too large for the apply kernels");
-      return IBF_ERR_UNSUPPORTED;
-    }
-    const int stage_f = base + fac <= kLdsBudget ? 1 : 0;
-    x.lds = base + (stage_f ? fac : 0);
-    x.nblocks = p->nleaf * nchu;
-    x.u = UDesc{w[cur], u, ldu, p->d_perm_x, p->d_xoff, p->d_ubar, l0, K, nrhs, NBu, nchu,
-                p->smax_x, stage_f};
     const double nnz = (double)p->nnz_ubar;
     x.flops = 8.0 * nnz * nrhs;
     x.bytes = nnz * fb + vb * nrhs * ((double)p->nx + (double)p->npairs * K);
+    if (mfma && p->smax_x <= kLeafMfma && ((K << l0) % 16) == 0) {
+      // MFMA leaf product, 64-column chunks
+      const int R = K << l0;
+      const int nchu = (nrhs + 63) / 64;
+      x.mfma = true;
+      x.lds = ((size_t)R * kLeafMfma + (size_t)kLeafMfma * 64) * sizeof(VT);
+      x.nblocks = p->nleaf * nchu;
+      x.u = UDesc{w[cur], u, ldu, p->d_perm_x, p->d_xoff, p->d_ubar, l0, K, nrhs, 64, nchu,
+                  p->smax_x, 1};
+    } else {
+      int NBu = NBo;
+      while (NBu > 1 && (size_t)(1 << l0) * K * NBu * sizeof(VT) > kLdsBudget / 2) NBu /= 2;
+      const int nchu = (nrhs + NBu - 1) / NBu;
+      const size_t base = (size_t)(1 << l0) * K * NBu * sizeof(VT);
+      const size_t fac = (size_t)p->smax_x * ((1 << l0) * K + 1) * sizeof(VT);
+      if (base > kLdsBudget) {
+        set_error("ibf_apply: leaf size too large for the apply kernels");
+        return IBF_ERR_UNSUPPORTED;
+      }
+      const int stage_f = base + fac <= kLdsBudget ? 1 : 0;
+      x.lds = base + (stage_f ? fac : 0);
+      x.nblocks = p->nleaf * nchu;
+      x.u = UDesc{w[cur], u, ldu, p->d_perm_x, p->d_xoff, p->d_ubar, l0, K, nrhs, NBu, nchu,
+                  p->smax_x, stage_f};
+    }
     seq.push_back(x);
   }
   return IBF_OK;
@@ -1001,6 +1233,11 @@ int launch_one(const Launch& x, hipStream_t s) {
   const dim3 grid((unsigned)x.nblocks), blk(kBlock);
   switch (x.kind) {
     case kLaunchV:
+      if (x.mfma) {
+        if constexpr (sizeof(VT) == 8)
+          hipLaunchKernelGGL((k_apply_v_mfma<FT>), grid, blk, x.lds, s, x.v);
+        break;
+      }
 #define IBF_LAUNCH_V(KTC) hipLaunchKernelGGL((k_apply_v<VT, FT, KTC>), grid, blk, x.lds, s, x.v)
       IBF_DISPATCH_KT(x.kt, IBF_LAUNCH_V);
 #undef IBF_LAUNCH_V
@@ -1033,6 +1270,11 @@ int launch_one(const Launch& x, hipStream_t s) {
       hipLaunchKernelGGL((k_apply_mid<VT, FT>), grid, blk, 0, s, x.m);
       break;
     default:
+      if (x.mfma) {
+        if constexpr (sizeof(VT) == 8)
+          hipLaunchKernelGGL((k_apply_u_mfma<FT>), grid, blk, x.lds, s, x.u);
+        break;
+      }
       hipLaunchKernelGGL((k_apply_u<VT, FT>), grid, blk, x.lds, s, x.u);
       break;
   }
@@ -1105,6 +1347,11 @@ int launch_phase(const ibf_batch_s* b, const BatchPhase& ph, hipStream_t s) {
   switch (ph.kind) {
     case kLaunchV: {
       const VDesc* ds = reinterpret_cast<const VDesc*>(base + ph.desc_off);
+      if (ph.mfma) {
+        if constexpr (sizeof(VT) == 8)
+          hipLaunchKernelGGL((k_batch_v_mfma<FT>), grid, blk, ph.lds, s, ds, boff, ph.count);
+        break;
+      }
 #define IBF_LAUNCH_BV(KTC) \
   hipLaunchKernelGGL((k_batch_v<VT, FT, KTC>), grid, blk, ph.lds, s, ds, boff, ph.count)
       IBF_DISPATCH_KT(ph.kt, IBF_LAUNCH_BV);
@@ -1130,6 +1377,11 @@ int launch_phase(const ibf_batch_s* b, const BatchPhase& ph, hipStream_t s) {
     }
     case kLaunchU: {
       const UDesc* ds = reinterpret_cast<const UDesc*>(base + ph.desc_off);
+      if (ph.mfma) {
+        if constexpr (sizeof(VT) == 8)
+          hipLaunchKernelGGL((k_batch_u_mfma<FT>), grid, blk, ph.lds, s, ds, boff, ph.count);
+        break;
+      }
       hipLaunchKernelGGL((k_batch_u<VT, FT>), grid, blk, ph.lds, s, ds, boff, ph.count);
       break;
     }
@@ -1203,7 +1455,7 @@ int apply_batch_t(ibf_batch_s* b, const void* const* g, const int64_t* ldg, void
     }
     for (const Launch* x : m) {
       Launch y = *x;
-      if (y.kind == kLaunchV) {
+      if (y.kind == kLaunchV && !y.mfma) {
         const size_t base = (size_t)y.v.smax * y.v.NB * sizeof(VT);
         const size_t fac = (size_t)y.v.smax * ((size_t)1 << y.v.l0) * ph.kt * sizeof(VT);
         y.v.stage_f = base + fac <= kLdsBudget ? 1 : 0;

@@ -144,6 +144,35 @@ def test_fp32_odd_nrhs_chunks(torch_dev):
     assert O.rel_error(u, u_ref) < 1e-5
 
 
+def test_fp32_mfma_uneven_leaves(torch_dev):
+    """96 right-hand sides on N = 3000: leaves of fewer than 16 points (ragged
+    at the end of the grid) through the MFMA leaf products and stages, over
+    two 64-column and three 32-column RHS chunks."""
+    _say("fp32 nrhs=96 fio3000_r9")
+    P0 = _problems()["fio3000_r9"]
+    g = I.complex_normal(P0.n, 96, np.random.default_rng(32))
+    P = I.Problem1D("fio3000_r9_96", P0.x, P0.xi, P0.phase, P0.params, P0.r, P0.tol, P0.leaf,
+                    96, g, I.PREC_FP32)
+    _, prob, Op, _ = _oracle("fio3000_r9")
+    u_ref = O.apply_optimal(Op, g)
+    u, q = _run_gpu(torch_dev, P, I.PREC_FP32)
+    assert O.rel_error(u, u_ref) < 1e-5
+
+
+def test_bf16x2_mfma_parity(torch_dev):
+    """BF16x2 factors with 64 right-hand sides: the MFMA kernels widen the
+    stored factors to FP32 as they stage them."""
+    _say("bf16x2 nrhs=64 fio4k_r12")
+    P0 = _problems()["fio4k_r12"]
+    g = I.complex_normal(P0.n, 64, np.random.default_rng(33))
+    P = I.Problem1D("fio4k_r12_64", P0.x, P0.xi, P0.phase, P0.params, P0.r, P0.tol, P0.leaf,
+                    64, g, I.PREC_BF16X2)
+    _, prob, Op, _ = _oracle("fio4k_r12")
+    u_ref = O.apply_optimal(Op, g)
+    u, q = _run_gpu(torch_dev, P, I.PREC_BF16X2)
+    assert O.rel_error(u, u_ref) < 1e-4
+
+
 def test_bf16x2_parity(torch_dev):
     _say("bf16x2 parity fio4k_r12")
     P, prob, Op, u_ref = _oracle("fio4k_r12")
