@@ -344,22 +344,26 @@ __device__ __forceinline__ void apply_fused_body(const FusedDesc& D, int64_t lb)
 template <typename VT, typename FT, int NL>
 struct SlotFactors {
   VT v[NL];
+  // rounds i < fs / 32 are full (a uniform bound); only round fs / 32 tests
+  // the entry index
   __device__ __forceinline__ void load(const FT* blk, int fs, int k, int j, int rem, int64_t gid0,
                                        int sh_end, int L, int l) {
     const int u = threadIdx.x >> 5, e = threadIdx.x & 31;
     const int64_t g = gid0 + (u >> k);
     const int64_t ap = g >> sh_end, bpp = g & (((int64_t)1 << sh_end) - 1);
     const FT* src = blk + fused_pout(u & ((1 << k) - 1), j, rem, ap, bpp, L, l) * fs + e;
+    const int full = fs >> 5;
 #pragma unroll
     for (int i = 0; i < NL; ++i)
-      if (e + 32 * i < fs) v[i] = load_factor(src, 32 * i);
+      if (i < full || (i == full && e < (fs & 31))) v[i] = load_factor(src, 32 * i);
   }
   __device__ __forceinline__ void store(VT* F, int fs) const {
     const int u = threadIdx.x >> 5, e = threadIdx.x & 31;
     VT* dst = F + u * fs + e;
+    const int full = fs >> 5;
 #pragma unroll
     for (int i = 0; i < NL; ++i)
-      if (e + 32 * i < fs) dst[32 * i] = v[i];
+      if (i < full || (i == full && e < (fs & 31))) dst[32 * i] = v[i];
   }
 };
 
@@ -433,23 +437,24 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
   // hoisted out of the block loop, where dozens of them would stay live in
   // registers across every stage.
   auto fetch = [&](const Blk& g) {
-    int rows_v = rows0, fs_v = fs0, trow_v = trow;
+    int kin_v = kin0, fs_v = fs0, trow_v = trow;
     int64_t ld_v = nrhs;
-    asm volatile("" : "+s"(rows_v), "+s"(fs_v), "+v"(trow_v), "+s"(ld_v));
+    asm volatile("" : "+s"(kin_v), "+s"(fs_v), "+v"(trow_v), "+s"(ld_v));
     fb.load(blk0, fs_v, k, 0, k - 1, g.gid0, sh_end, L, A.l_start);
     const VT* src = in + ((g.gid0 << k) * kin0 + trow_v) * ld_v + g.nb0 + col;
     const bool ok = col < g.nbw;
+    // row trow + 8 i < 8 kin0 exactly when i < kin0: a uniform bound
 #pragma unroll
     for (int i = 0; i < XR; ++i)
-      if (trow_v + 8 * i < rows_v) xin[i] = ok ? src[8 * i * ld_v] : Zero<VT>::v();
+      if (i < kin_v) xin[i] = ok ? src[8 * i * ld_v] : Zero<VT>::v();
   };
   auto deposit = [&](const Blk& g) {
-    int rows_v = rows0, fs_v = fs0, trow_v = trow;
-    asm volatile("" : "+s"(rows_v), "+s"(fs_v), "+v"(trow_v));
+    int kin_v = kin0, rows_v = rows0, fs_v = fs0, trow_v = trow;
+    asm volatile("" : "+s"(kin_v), "+s"(rows_v), "+s"(fs_v), "+v"(trow_v));
     VT* dst = S + trow_v * NB + col;
 #pragma unroll
     for (int i = 0; i < XR; ++i)
-      if (trow_v + 8 * i < rows_v) dst[8 * i * NB] = xin[i];
+      if (i < kin_v) dst[8 * i * NB] = xin[i];
     if (rows_v > 8 * XR) {
       const VT* src = in + (g.gid0 << k) * kin0 * nrhs + g.nb0 + col;
       for (int r = 8 * XR + trow_v; r < rows_v; r += 8)
