@@ -336,63 +336,71 @@ __device__ __forceinline__ void apply_fused_body(const FusedDesc& D, int64_t lb)
   }
 }
 
-// Factor blocks of one stage for the 8 virtual slots of an MFMA block (8 / 2^k
-// consecutive groups of 2^k slots): thread t stages entries (t & 31) + 32 i of
-// slot t >> 5, so each thread computes one block address per stage and a wave
-// moves two 256-byte runs per load.  NL = KT loads per thread cover blocks of
-// up to 2 * 16 * KT entries (input rank <= 16, row length <= KT).
-template <typename VT, typename FT, int NL>
+// Factor blocks of one stage for the NV virtual slots of an MFMA block (NV /
+// 2^k consecutive groups of 2^k slots): TPS = kBlock / NV threads per slot,
+// thread t stages entries (t mod TPS) + TPS i of slot t / TPS, so each thread
+// computes one block address per stage and loads move contiguous runs.  NL
+// loads per thread cover blocks of up to 2 * 16 * KT entries (input rank
+// <= 16, row length <= KT).
+template <typename VT, typename FT, int KT, int NV>
 struct SlotFactors {
+  static constexpr int TPS = kBlock / NV;
+  static constexpr int NL = (2 * 16 * KT + TPS - 1) / TPS;
   VT v[NL];
-  // rounds i < fs / 32 are full (a uniform bound); only round fs / 32 tests
+  // rounds i < fs / TPS are full (a uniform bound); only round fs / TPS tests
   // the entry index
   __device__ __forceinline__ void load(const FT* blk, int fs, int k, int j, int rem, int64_t gid0,
                                        int sh_end, int L, int l) {
-    const int u = threadIdx.x >> 5, e = threadIdx.x & 31;
+    const int u = threadIdx.x / TPS, e = threadIdx.x % TPS;
     const int64_t g = gid0 + (u >> k);
     const int64_t ap = g >> sh_end, bpp = g & (((int64_t)1 << sh_end) - 1);
     const FT* src = blk + fused_pout(u & ((1 << k) - 1), j, rem, ap, bpp, L, l) * fs + e;
-    const int full = fs >> 5;
+    const int full = fs / TPS, part = fs % TPS;
 #pragma unroll
     for (int i = 0; i < NL; ++i)
-      if (i < full || (i == full && e < (fs & 31))) v[i] = load_factor(src, 32 * i);
+      if (i < full || (i == full && e < part)) v[i] = load_factor(src, TPS * i);
   }
   __device__ __forceinline__ void store(VT* F, int fs) const {
-    const int u = threadIdx.x >> 5, e = threadIdx.x & 31;
+    const int u = threadIdx.x / TPS, e = threadIdx.x % TPS;
     VT* dst = F + u * fs + e;
-    const int full = fs >> 5;
+    const int full = fs / TPS, part = fs % TPS;
 #pragma unroll
     for (int i = 0; i < NL; ++i)
-      if (i < full || (i == full && e < (fs & 31))) dst[32 * i] = v[i];
+      if (i < full || (i == full && e < part)) dst[TPS * i] = v[i];
   }
 };
 
-// Multi-RHS FP32 variant on MFMA.  A block holds 8 virtual slots: one group of
-// 8 pairs (3 stages), or 8 / 2^k consecutive groups of 2^k pairs side by side,
-// for one 32-column RHS chunk.  It is persistent: the block with logical index
-// b takes logical blocks b, b + lstep, ... below lend (logical block = 8
-// consecutive input pairs x chunk; the chunks of the same pairs are adjacent
-// and so share the factor blocks through one XCD's L2).  While the last stage
-// computes, the loads of the next block's input rows and first-stage factors
-// are already in flight into registers, and each stage's computation overlaps
-// the loads of the next stage's factors.
+// Multi-RHS FP32 variant on MFMA for RHS chunks of NBC = 32 or 16 columns.
+// Each wave computes SPW = 64 / NBC virtual slots at once, and a block holds
+// NV = 4 SPW of them (8 or 16): one group of NV pairs (log2 NV stages), or
+// NV / 2^k consecutive groups of 2^k pairs side by side, for one RHS chunk.
+// It is persistent: the block with logical index b takes logical blocks b,
+// b + lstep, ... below lend (logical block = NV consecutive input pairs x
+// chunk; the chunks of the same pairs are adjacent and so share the factor
+// blocks through one XCD's L2).  While the last stage computes, the loads of
+// the next block's input rows and first-stage factors are already in flight
+// into registers, and each stage's computation overlaps the loads of the next
+// stage's factors.
 //
-// Wave w computes virtual slots 2w and 2w + 1 together: lane l belongs to slot
-// 2w + (l >> 5) and carries RHS column l & 31.  The 16 MFMA blocks of
-// v_mfma_f32_4x4x1f32 are groups of 4 columns, 8 per slot; A-operand row
-// i = l & 3 is the raw float i of the slot's pair of complex factor entries
-// (t = 2g, 2g+1): (re t0, im t0, re t1, im t1).  With P = sum f_i x_re and
-// Q = sum f_i x_im, the complex outputs are
+// Lane l of wave w belongs to virtual slot SPW w + l / NBC and carries RHS
+// column l mod NBC.  The 16 MFMA blocks of v_mfma_f32_4x4x1f32 are groups of
+// 4 columns, NBC / 4 per slot; A-operand row i = l & 3 is the raw float i of
+// the slot's pair of complex factor entries (t = 2g, 2g+1): (re t0, im t0,
+// re t1, im t1).  With P = sum f_i x_re and Q = sum f_i x_im, the complex
+// outputs are
 //   out[2g]   = (P0 - Q1, P1 + Q0),  out[2g+1] = (P2 - Q3, P3 + Q2).
-template <typename VT, typename FT, int KT>
+template <typename VT, typename FT, int KT, int NBC>
 __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, int64_t lstep,
                                                 int64_t lend) {
   static_assert(sizeof(VT) == 8, "MFMA variant computes in FP32");
+  static_assert(NBC == 32 || NBC == 16, "RHS chunks of 32 or 16 columns");
   constexpr int KG = KT / 2;                                  // row pairs (MFMA row groups)
-  constexpr int NB = 32;                                      // RHS columns per chunk
-  constexpr int NV = 8;                                       // virtual slots per block
-  // input rows held in flight per thread (row r goes to thread row r mod 8);
-  // blocks with more input rows than 8 XR copy the rest synchronously
+  constexpr int NB = NBC;                                     // RHS columns per chunk
+  constexpr int SPW = 64 / NBC;                               // slots per wave
+  constexpr int NV = 4 * SPW;                                 // virtual slots per block
+  constexpr int LNV = NV == 8 ? 3 : 4;
+  // input rows held in flight per thread (row r goes to thread row r mod NV);
+  // blocks with more input rows than NV XR copy the rest synchronously
   constexpr int XR = KT;
   extern __shared__ __align__(16) unsigned char smem[];
   const VT* __restrict__ in = reinterpret_cast<const VT*>(D.in);
@@ -400,7 +408,7 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
   const FusedArgs& A = D.A;
   const int k = A.nst, L = A.L, kmaxg = A.kmaxg, nrhs = A.nrhs, nchunk = A.nchunk;
   const int nslot = 1 << k;
-  // S: the state of stage j as [virtual slot][ranks[j]][32] (the 2 kin input
+  // S: the state of stage j as [virtual slot][ranks[j]][NB] (the 2 kin input
   // rows of an output slot are contiguous); F: the stage's factor blocks
   // [virtual slot][2 kin kld], followed by 2 KT entries of slack for reads
   // past the last row
@@ -409,10 +417,10 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
   const int sh_end = L - (A.l_start + k - 1);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int col = lane & 31, fi = lane & 3;
-  const int vs = 2 * wave + (lane >> 5);                      // this lane's virtual slot
+  const int col = lane % NB, fi = lane & 3;
+  const int vs = SPW * wave + lane / NB;                      // this lane's virtual slot
   const int grp = vs >> k, loc = vs & (nslot - 1);            // its group and local slot
-  const int trow = threadIdx.x >> 5;                          // row phase of the copies
+  const int trow = threadIdx.x / NB;                          // row phase of the copies
   const int kin0 = A.ranks[0], rows0 = NV * kin0, fs0 = 2 * kin0 * A.kld[0];
   const FT* blk0 = reinterpret_cast<const FT*>(A.blk[0]);
 
@@ -423,14 +431,14 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
   auto decode = [&](int64_t l) {
     Blk g;
     const int64_t q = l / nchunk;
-    g.gid0 = q << (3 - k);
+    g.gid0 = q << (LNV - k);
     g.nb0 = (int)(l - q * nchunk) * NB;
     g.nbw = min(NB, nrhs - g.nb0);
     return g;
   };
-  SlotFactors<VT, FT, KT> fb;
+  SlotFactors<VT, FT, KT, NV> fb;
   VT xin[XR];
-  // The block's input rows are contiguous in HBM (pairs (gid0 << k) .. + 8,
+  // The block's input rows are contiguous in HBM (pairs (gid0 << k) .. + NV,
   // kin0 rows each) and land contiguously in S; columns >= nbw read as zero.
   // The per-row offsets and bounds depend only on launch constants; passed
   // through an empty asm they are recomputed at each call instead of being
@@ -443,10 +451,10 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
     fb.load(blk0, fs_v, k, 0, k - 1, g.gid0, sh_end, L, A.l_start);
     const VT* src = in + ((g.gid0 << k) * kin0 + trow_v) * ld_v + g.nb0 + col;
     const bool ok = col < g.nbw;
-    // row trow + 8 i < 8 kin0 exactly when i < kin0: a uniform bound
+    // row trow + NV i < NV kin0 exactly when i < kin0: a uniform bound
 #pragma unroll
     for (int i = 0; i < XR; ++i)
-      if (i < kin_v) xin[i] = ok ? src[8 * i * ld_v] : Zero<VT>::v();
+      if (i < kin_v) xin[i] = ok ? src[NV * i * ld_v] : Zero<VT>::v();
   };
   auto deposit = [&](const Blk& g) {
     int kin_v = kin0, rows_v = rows0, fs_v = fs0, trow_v = trow;
@@ -454,10 +462,10 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
     VT* dst = S + trow_v * NB + col;
 #pragma unroll
     for (int i = 0; i < XR; ++i)
-      if (i < kin_v) dst[8 * i * NB] = xin[i];
-    if (rows_v > 8 * XR) {
+      if (i < kin_v) dst[NV * i * NB] = xin[i];
+    if (rows_v > NV * XR) {
       const VT* src = in + (g.gid0 << k) * kin0 * nrhs + g.nb0 + col;
-      for (int r = 8 * XR + trow_v; r < rows_v; r += 8)
+      for (int r = NV * XR + trow_v; r < rows_v; r += NV)
         S[r * NB + col] = col < g.nbw ? src[(int64_t)r * nrhs] : Zero<VT>::v();
     }
     fb.store(F, fs_v);
@@ -546,7 +554,7 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
         fb.store(F, 2 * kout * A.kld[j + 1]);
         __syncthreads();
       } else if (col < cur.nbw) {
-        // last stage: rows of 32 columns straight to HBM
+        // last stage: rows of NB columns straight to HBM
         VT* dst = out + fused_pout(loc, j, 0, ap, bpp, L, l) * kout * nrhs + cur.nb0 + col;
 #pragma unroll
         for (int gq = 0; gq < KG; ++gq) {
@@ -579,18 +587,18 @@ __global__ __launch_bounds__(kBlock) void k_batch_fused(const FusedDesc* __restr
   apply_fused_body<VT, FT, KT>(ds[p], (int64_t)blockIdx.x - boff[p]);
 }
 // persistent: a grid of resident blocks over `total` logical blocks
-template <typename VT, typename FT, int KT>
+template <typename VT, typename FT, int KT, int NBC>
 __global__ __launch_bounds__(kBlock) void k_apply_fused_mfma(FusedDesc D, int64_t total) {
-  fused_mfma_body<VT, FT, KT>(D, xcd_logical_block((int64_t)gridDim.x), (int64_t)gridDim.x,
-                              total);
+  fused_mfma_body<VT, FT, KT, NBC>(D, xcd_logical_block((int64_t)gridDim.x),
+                                   (int64_t)gridDim.x, total);
 }
-template <typename VT, typename FT, int KT>
+template <typename VT, typename FT, int KT, int NBC>
 __global__ __launch_bounds__(kBlock) void k_batch_fused_mfma(const FusedDesc* __restrict__ ds,
                                                              const int64_t* __restrict__ boff,
                                                              int count) {
   const int p = find_problem(boff, count, blockIdx.x);
   const int64_t lb = (int64_t)blockIdx.x - boff[p];
-  fused_mfma_body<VT, FT, KT>(ds[p], lb, 1, lb + 1);
+  fused_mfma_body<VT, FT, KT, NBC>(ds[p], lb, 1, lb + 1);
 }
 
 // Middle block of the swept-in factorization: out[p][t][n] = sum_s Mdot[p][t][s] in[p][s][n]
@@ -1043,10 +1051,14 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
   int lmax = 0, rc;
   if ((rc = lds_limit(p->device, &lmax))) return rc;
   const size_t budget_mfma = std::min<size_t>(kLdsBudgetMfma, (size_t)lmax);
-  // Multi-RHS FP32 stages run on MFMA with 32-column chunks; otherwise the
-  // vector kernels take chunks of up to 32 columns.
-  const bool mfma = sizeof(VT) == 8 && nrhs >= 32;
-  const int NB = mfma ? 32 : std::min(nrhs, 32);
+  // FP32-state stages with more than 8 RHS run on MFMA with 32-column chunks
+  // (more than 16 RHS) or 16-column chunks; otherwise the vector kernels take
+  // chunks of up to 32 columns.  The V and U leaf products use MFMA from 32 RHS.
+  const bool mfma = sizeof(VT) == 8 && nrhs > 8;
+  const bool mfma_vu = sizeof(VT) == 8 && nrhs >= 32;
+  const int NB = mfma ? (nrhs > 16 ? 32 : 16) : std::min(nrhs, 32);
+  const int NV = kBlock / NB;                                 // MFMA virtual slots a block
+  const int LNV = NV == 8 ? 3 : 4;
   const int nchunk = (nrhs + NB - 1) / NB;
   const int NBo = std::min(nrhs, 32);                         // outer (V, U) kernels
   // V
@@ -1058,7 +1070,7 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
     const double nnz = (double)p->nnz_vbar;
     x.flops = 8.0 * nnz * nrhs;
     x.bytes = nnz * fb + vb * nrhs * ((double)p->nxi + (double)p->npairs * K);
-    if (mfma && p->smax_xi <= kLeafMfma && ((K << l0) & 1) == 0) {
+    if (mfma_vu && p->smax_xi <= kLeafMfma && ((K << l0) & 1) == 0) {
       // MFMA leaf product, 64-column chunks
       const int R = K << l0;
       const int nchv = (nrhs + 63) / 64;
@@ -1106,7 +1118,7 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
   // state buffers [2^k][kmaxg][NB], no factors.
   auto fused_lds = [&](int kk, int kmg, int kt) -> size_t {
     if (!mfma) return ((size_t)2 << kk) * kmg * NB * sizeof(VT);
-    return ((size_t)8 * ((size_t)kmg * NB + (size_t)2 * kmg * kt) + 2 * kt) * sizeof(VT);
+    return ((size_t)NV * ((size_t)kmg * NB + (size_t)2 * kmg * kt) + 2 * kt) * sizeof(VT);
   };
   auto add_stages = [&](int lo, int hi, bool gside) {   // output levels lo..hi
     int l = lo;
@@ -1119,8 +1131,8 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
         if (next > L - l + 1) break;                          // group must fit the b bits
         int km = 1;
         for (int j = 0; j <= next; ++j) km = std::max(km, rank_at(l - 1 + j, gside));
-        // MFMA: at most 8 slots a block; vector: at most 4 outputs per thread and stage
-        if (mfma ? (next > 3) : (((int64_t)1 << next) * km * NB > 4 * kBlock)) break;
+        // MFMA: at most NV slots a block; vector: at most 4 outputs per thread and stage
+        if (mfma ? (next > LNV) : (((int64_t)1 << next) * km * NB > 4 * kBlock)) break;
         if (fused_lds(next, km, even_kt(km)) > (mfma ? budget_mfma : kLdsBudget)) break;
         kk = next;
       }
@@ -1150,7 +1162,7 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
       }
       x.kt = even_kt(kom);
       x.lds = fused_lds(kk, km, x.kt);
-      x.nblocks = (p->npairs >> (mfma ? 3 : kk)) * nchunk;
+      x.nblocks = (p->npairs >> (mfma ? LNV : kk)) * nchunk;
       x.f.in = w[cur];
       x.f.out = w[cur ^ 1];
       x.flops = 8.0 * nnz * nrhs;
@@ -1175,7 +1187,7 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
     const double nnz = (double)p->nnz_ubar;
     x.flops = 8.0 * nnz * nrhs;
     x.bytes = nnz * fb + vb * nrhs * ((double)p->nx + (double)p->npairs * K);
-    if (mfma && p->smax_x <= kLeafMfma && ((K << l0) % 16) == 0) {
+    if (mfma_vu && p->smax_x <= kLeafMfma && ((K << l0) % 16) == 0) {
       // MFMA leaf product, 64-column chunks
       const int R = K << l0;
       const int nchu = (nrhs + 63) / 64;
@@ -1250,19 +1262,27 @@ int launch_one(const Launch& x, hipStream_t s) {
     case kLaunchFused:
       if (x.mfma) {
         if constexpr (sizeof(VT) == 8) {
-#define IBF_LAUNCH_FM(KTC)                                                          \
+#define IBF_LAUNCH_FMN(KTC, NBC)                                                    \
   {                                                                                 \
     int64_t nres = 0;                                                               \
     const int rc = resident_blocks(reinterpret_cast<const void*>(                    \
-                                       &k_apply_fused_mfma<VT, FT, KTC>),            \
+                                       &k_apply_fused_mfma<VT, FT, KTC, NBC>),       \
                                    x.lds, &nres);                                   \
     if (rc) return rc;                                                              \
     const dim3 pgrid((unsigned)std::min<int64_t>(x.nblocks, nres));                  \
-    hipLaunchKernelGGL((k_apply_fused_mfma<VT, FT, KTC>), pgrid, blk, x.lds, s, x.f,  \
-                       x.nblocks);                                                  \
+    hipLaunchKernelGGL((k_apply_fused_mfma<VT, FT, KTC, NBC>), pgrid, blk, x.lds, s,  \
+                       x.f, x.nblocks);                                             \
   }
-          IBF_DISPATCH_KT(x.kt, IBF_LAUNCH_FM);
-#undef IBF_LAUNCH_FM
+#define IBF_LAUNCH_FM32(KTC) IBF_LAUNCH_FMN(KTC, 32)
+#define IBF_LAUNCH_FM16(KTC) IBF_LAUNCH_FMN(KTC, 16)
+          if (x.f.A.NB == 32) {
+            IBF_DISPATCH_KT(x.kt, IBF_LAUNCH_FM32);
+          } else {
+            IBF_DISPATCH_KT(x.kt, IBF_LAUNCH_FM16);
+          }
+#undef IBF_LAUNCH_FM16
+#undef IBF_LAUNCH_FM32
+#undef IBF_LAUNCH_FMN
         }
       } else {
 #define IBF_LAUNCH_FV(KTC) \
@@ -1315,6 +1335,7 @@ int apply_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int6
 struct BatchPhase {
   LaunchKind kind;
   bool mfma;
+  int nb;                                                    // MFMA stage chunk width
   int kt, count;
   size_t lds;
   int64_t nblocks;
@@ -1367,10 +1388,19 @@ int launch_phase(const ibf_batch_s* b, const BatchPhase& ph, hipStream_t s) {
       const FusedDesc* ds = reinterpret_cast<const FusedDesc*>(base + ph.desc_off);
       if (ph.mfma) {
         if constexpr (sizeof(VT) == 8) {
-#define IBF_LAUNCH_BFM(KTC) \
-  hipLaunchKernelGGL((k_batch_fused_mfma<VT, FT, KTC>), grid, blk, ph.lds, s, ds, boff, ph.count)
-          IBF_DISPATCH_KT(ph.kt, IBF_LAUNCH_BFM);
-#undef IBF_LAUNCH_BFM
+#define IBF_LAUNCH_BFM32(KTC)                                                           \
+  hipLaunchKernelGGL((k_batch_fused_mfma<VT, FT, KTC, 32>), grid, blk, ph.lds, s, ds, boff, \
+                     ph.count)
+#define IBF_LAUNCH_BFM16(KTC)                                                           \
+  hipLaunchKernelGGL((k_batch_fused_mfma<VT, FT, KTC, 16>), grid, blk, ph.lds, s, ds, boff, \
+                     ph.count)
+          if (ph.nb == 32) {
+            IBF_DISPATCH_KT(ph.kt, IBF_LAUNCH_BFM32);
+          } else {
+            IBF_DISPATCH_KT(ph.kt, IBF_LAUNCH_BFM16);
+          }
+#undef IBF_LAUNCH_BFM16
+#undef IBF_LAUNCH_BFM32
         }
       } else {
 #define IBF_LAUNCH_BFV(KTC) \
@@ -1419,14 +1449,19 @@ int apply_batch_t(ibf_batch_s* b, const void* const* g, const int64_t* ldg, void
   // phase membership: V (launch 0), fused launch j (1..), U (last launch)
   std::vector<std::vector<const Launch*>> members;
   auto add_phase_members = [&](auto pick) {
-    std::vector<const Launch*> mf, mv;
+    // one phase per kernel variant: vector, MFMA (V, U, or stages with 32- or
+    // 16-column chunks)
+    std::vector<const Launch*> mv, mf32, mf16;
     for (int i = 0; i < count; ++i) {
       const Launch* x = pick(seqs[i]);
       if (!x) continue;
-      (x->mfma ? mf : mv).push_back(x);
+      if (!x->mfma) mv.push_back(x);
+      else if (x->kind == kLaunchFused && x->f.A.NB == 16) mf16.push_back(x);
+      else mf32.push_back(x);
     }
     if (!mv.empty()) members.push_back(mv);
-    if (!mf.empty()) members.push_back(mf);
+    if (!mf32.empty()) members.push_back(mf32);
+    if (!mf16.empty()) members.push_back(mf16);
   };
   add_phase_members([](const std::vector<Launch>& q) { return &q.front(); });
   for (size_t j = 1; j + 1 < nmax; ++j)
@@ -1447,6 +1482,7 @@ int apply_batch_t(ibf_batch_s* b, const void* const* g, const int64_t* ldg, void
     BatchPhase ph{};
     ph.kind = m[0]->kind;
     ph.mfma = m[0]->mfma;
+    ph.nb = m[0]->kind == kLaunchFused ? m[0]->f.A.NB : 0;
     ph.count = (int)m.size();
     const size_t dsz = ph.kind == kLaunchV ? sizeof(VDesc)
                        : ph.kind == kLaunchU ? sizeof(UDesc) : sizeof(FusedDesc);
@@ -1467,8 +1503,9 @@ int apply_batch_t(ibf_batch_s* b, const void* const* g, const int64_t* ldg, void
         y.lds = base + (y.v.stage_f ? fac : 0);
       } else if (y.kind == kLaunchFused && y.mfma) {
         const FusedArgs& A = y.f.A;
-        y.lds = ((size_t)8 * ((size_t)A.kmaxg * A.NB + (size_t)2 * A.kmaxg * ph.kt) +
-                 2 * ph.kt) * sizeof(VT);
+        const size_t nv = (size_t)kBlock / (size_t)A.NB;     // virtual slots a block
+        y.lds = (nv * ((size_t)A.kmaxg * A.NB + (size_t)2 * A.kmaxg * ph.kt) + 2 * ph.kt) *
+                sizeof(VT);
       }
       ph.lds = std::max(ph.lds, y.lds);
       adj[q].push_back(y);

@@ -222,6 +222,35 @@ def test_sweep_in_parity(torch_dev, key, precision, tol):
     assert q["nnz_opt"] == O.nnz_optimal_in(Oi)
 
 
+@functools.lru_cache(maxsize=None)
+def _oracle_sweep_in(key):
+    P = _problems()[key]
+    prob, F, Op = O.build_optimal(P.phase, P.params, P.x, P.xi, P.r, P.tol, P.leaf)
+    return P, O.sweep_in(Op, P.tol)
+
+
+@pytest.mark.parametrize("nrhs,precision,tol", [(16, I.PREC_BF16X2, 1e-4),
+                                                (12, I.PREC_FP32, 1e-5)])
+def test_mfma16_sweep_in_parity(torch_dev, nrhs, precision, tol):
+    """9 to 16 right-hand sides run the butterfly stages on MFMA in 16-column
+    chunks (four slots a wave, up to four fused stages); random x with the
+    sweep-in on, as in the non-uniform DFT workload."""
+    _say(f"mfma16 sweep-in nudft4k_r10 nrhs={nrhs} precision={precision}")
+    P, Oi = _oracle_sweep_in("nudft4k_r10")
+    g = I.complex_normal(P.n, nrhs, np.random.default_rng(34))
+    u_ref = O.apply_optimal(Oi, g)
+    from paper_1605_03616_amd import ibf
+    torch = torch_dev
+    pl = ibf.Plan(P.x, P.xi, P.phase, P.params, P.r, P.tol, P.leaf, precision, 1)
+    pl.build()
+    gt = torch.from_numpy(np.ascontiguousarray(g.T)).to(torch.complex64).cuda()
+    u = pl.apply(gt).cpu().numpy().T.astype(np.complex128)
+    q = pl.query()
+    pl.destroy()
+    assert q["sweep_in"] == 1
+    assert O.rel_error(u, u_ref) < tol
+
+
 def test_determinism(torch_dev):
     _say("run-to-run determinism fio1k")
     P = I.workload_fio1d_1k()
