@@ -336,16 +336,21 @@ __device__ __forceinline__ void apply_fused_body(const FusedDesc& D, int64_t lb)
   }
 }
 
+// LDS stride of a slot's staged factor block of fs entries: a multiple of 16
+// entries plus 4, so that the A-operand reads of the slots that share a wave
+// start 8 banks apart instead of on the same bank.
+__device__ __forceinline__ int slot_stride(int fs) { return ((fs + 15) & ~15) + 4; }
+
 // Factor blocks of one stage for the NV virtual slots of an MFMA block (NV /
 // 2^k consecutive groups of 2^k slots): TPS = kBlock / NV threads per slot,
 // thread t stages entries (t mod TPS) + TPS i of slot t / TPS, so each thread
 // computes one block address per stage and loads move contiguous runs.  NL
-// loads per thread cover blocks of up to 2 * 16 * KT entries (input rank
-// <= 16, row length <= KT).
+// loads per thread cover blocks of up to 2 KT^2 entries (the launch's ranks
+// are at most KT).
 template <typename VT, typename FT, int KT, int NV>
 struct SlotFactors {
   static constexpr int TPS = kBlock / NV;
-  static constexpr int NL = (2 * 16 * KT + TPS - 1) / TPS;
+  static constexpr int NL = (2 * KT * KT + TPS - 1) / TPS;
   VT v[NL];
   // rounds i < fs / TPS are full (a uniform bound); only round fs / TPS tests
   // the entry index
@@ -362,7 +367,7 @@ struct SlotFactors {
   }
   __device__ __forceinline__ void store(VT* F, int fs) const {
     const int u = threadIdx.x / TPS, e = threadIdx.x % TPS;
-    VT* dst = F + u * fs + e;
+    VT* dst = F + u * slot_stride(fs) + e;
     const int full = fs / TPS, part = fs % TPS;
 #pragma unroll
     for (int i = 0; i < NL; ++i)
@@ -410,8 +415,8 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
   const int nslot = 1 << k;
   // S: the state of stage j as [virtual slot][ranks[j]][NB] (the 2 kin input
   // rows of an output slot are contiguous); F: the stage's factor blocks
-  // [virtual slot][2 kin kld], followed by 2 KT entries of slack for reads
-  // past the last row
+  // [virtual slot][2 kin kld] at slot_stride, followed by 2 KT entries of
+  // slack for reads past the last row
   VT* S = reinterpret_cast<VT*>(smem);
   VT* F = S + (size_t)NV * kmaxg * NB;
   const int sh_end = L - (A.l_start + k - 1);
@@ -500,7 +505,7 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
         // input rows of its two children (adjacent slots, so contiguous rows
         // in S), and the block's factor rows in F
         const VT* xp = S + (size_t)((grp << k) + fused_in0(loc, rem)) * kin * NB + col;
-        const float* fp = reinterpret_cast<const float*>(F + (size_t)vs * fs) + fi;
+        const float* fp = reinterpret_cast<const float*>(F + (size_t)vs * slot_stride(fs)) + fi;
         const int fstep = 2 * ke;                             // floats per factor row
         auto load_row = [&](const VT* x, const float* f, float (&Av)[KG], VT& X) {
           X = *x;
@@ -723,8 +728,9 @@ constexpr int kLeafMfma = 16;          // leaf points handled by the MFMA V / U
 constexpr int kVChunk = 6;             // output row pairs per V accumulator set
 
 // V: the leaf's output rows t = a K + k (R = 2^l0 K of them, in pairs) over
-// its points.  LDS: g_leaf [16][64] (gathered, zero rows past the leaf's
-// points) and Vbar [cnt][R] (+ slack for the last chunk's reads past R).
+// its points.  LDS: g_leaf [16][65] (gathered, zero rows past the leaf's
+// points; rows padded so that the gather's point-major stores spread over the
+// banks) and Vbar [cnt][R] (+ slack for the last chunk's reads past R).
 // Wave w computes row-pair chunks w, w + 4, ... with the 16 point rows of g
 // held in registers.
 template <typename FT>
@@ -736,8 +742,9 @@ __device__ __forceinline__ void apply_v_mfma_body(const VDesc& d, int64_t lb) {
   float2* __restrict__ mu = reinterpret_cast<float2*>(d.mu);
   const int L = d.L, l0 = d.l0, K = d.K, nrhs = d.nrhs, nchunk = d.nchunk;
   const int64_t ldg = d.ldg;
-  float2* gl = reinterpret_cast<float2*>(smem);               // [16][64]
-  float2* vl = gl + SM * NB;                                  // [cnt][R]
+  constexpr int GP = NB + 1;                                  // padded g row
+  float2* gl = reinterpret_cast<float2*>(smem);               // [16][GP]
+  float2* vl = gl + SM * GP;                                  // [cnt][R]
   const int64_t b = lb / nchunk;
   const int nb0 = (int)(lb - b * nchunk) * NB;
   const int nbw = min(NB, nrhs - nb0);
@@ -747,7 +754,7 @@ __device__ __forceinline__ void apply_v_mfma_body(const VDesc& d, int64_t lb) {
   // rows and columns outside the leaf and the chunk are zero
   staged_copy_to<8>(SM * NB, gl, [&](int e, int& off) {
     const int n = e >> 4, j = e & 15;
-    off = j * NB + n;
+    off = j * GP + n;
     return (j < cnt && n < nbw) ? g[(int64_t)(nb0 + n) * ldg + d.perm_xi[j0 + j]]
                                 : make_float2(0.f, 0.f);
   });
@@ -762,7 +769,7 @@ __device__ __forceinline__ void apply_v_mfma_body(const VDesc& d, int64_t lb) {
   const int fi = lane & 3;
   float2 xr[SM];
 #pragma unroll
-  for (int j = 0; j < SM; ++j) xr[j] = gl[j * NB + lane];
+  for (int j = 0; j < SM; ++j) xr[j] = gl[j * GP + lane];
   const int npair = R >> 1, nchk = (npair + CH - 1) / CH;
   const int sh = L - l0;
   const FastDiv divK(K);
@@ -810,8 +817,9 @@ __device__ __forceinline__ void apply_v_mfma_body(const VDesc& d, int64_t lb) {
 
 // U: u[x][n] = sum_r Ubar[x][r] mu[p0 + r / K][r % K][n] over the R = 2^l0 K
 // rows of the leaf's contiguous pairs (R a multiple of 16).  LDS: Ubar
-// transposed to [R][16] (rows past the leaf's points are zero) and a [16][64]
-// tile that turns the column-per-lane results into point-contiguous stores.
+// transposed to [R][17] (rows past the leaf's points are zero; the padding
+// spreads the transposing stores over the banks) and a [16][64] tile that
+// turns the column-per-lane results into point-contiguous stores.
 // Wave w computes point pairs w and w + 4 over all R rows, reading the mu rows
 // straight from memory: the four waves read the same rows at about the same
 // time, so all but the first read of a row hit the CU's cache.
@@ -825,8 +833,9 @@ __device__ __forceinline__ void apply_u_mfma_body(const UDesc& d, int64_t lb) {
   const int l0 = d.l0, K = d.K, nrhs = d.nrhs, nchunk = d.nchunk;
   const int64_t ldu = d.ldu;
   const int R = K << l0;
-  float2* ul = reinterpret_cast<float2*>(smem);               // [R][16]
-  float2* ot = ul + (size_t)R * SM;                           // [16][64]
+  constexpr int UP = SM + 1;                                  // padded Ubar row
+  float2* ul = reinterpret_cast<float2*>(smem);               // [R][UP]
+  float2* ot = ul + (size_t)R * UP;                           // [16][64]
   const int64_t a = lb / nchunk;
   const int nb0 = (int)(lb - a * nchunk) * NB;
   const int nbw = min(NB, nrhs - nb0);
@@ -837,7 +846,7 @@ __device__ __forceinline__ void apply_u_mfma_body(const UDesc& d, int64_t lb) {
   staged_copy_to<8>(R * SM, ul, [&](int e, int& off) {
     int x, r;
     divR.divmod(e, x, r);                                     // e = x R + r: reads coalesced
-    off = r * SM + x;
+    off = r * UP + x;
     return x < cnt ? load_factor(usrc, e) : make_float2(0.f, 0.f);
   });
   __syncthreads();
@@ -851,7 +860,7 @@ __device__ __forceinline__ void apply_u_mfma_body(const UDesc& d, int64_t lb) {
     Q[m] = v4f{0.f, 0.f, 0.f, 0.f};
   }
   // A operand of row r for point pairs wave and wave + 4: floats 4 wave + fi
-  // and 4 wave + 16 + fi of LDS row r
+  // and 4 wave + 16 + fi of LDS row r (2 UP floats a row)
   const float* f = reinterpret_cast<const float*>(ul) + 4 * wave + fi;
   const bool col = lane < nbw;
   const float2* src = mu + p0 * K * nrhs + nb0 + lane;
@@ -864,7 +873,7 @@ __device__ __forceinline__ void apply_u_mfma_body(const UDesc& d, int64_t lb) {
   auto mfma_rows = [&](int r0, const float2 (&X)[RB]) {
 #pragma unroll
     for (int i = 0; i < RB; ++i) {
-      const float* fr = f + 2 * SM * (r0 + i);
+      const float* fr = f + 2 * UP * (r0 + i);
       const float a0 = fr[0], a1 = fr[16];
       P[0] = __builtin_amdgcn_mfma_f32_4x4x1f32(a0, X[i].x, P[0], 0, 0, 0);
       Q[0] = __builtin_amdgcn_mfma_f32_4x4x1f32(a0, X[i].y, Q[0], 0, 0, 0);
@@ -1075,7 +1084,7 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
       const int R = K << l0;
       const int nchv = (nrhs + 63) / 64;
       x.mfma = true;
-      x.lds = ((size_t)kLeafMfma * 64 + (size_t)p->smax_xi * R + 2 * kVChunk) * sizeof(VT);
+      x.lds = ((size_t)kLeafMfma * 65 + (size_t)p->smax_xi * R + 2 * kVChunk) * sizeof(VT);
       x.nblocks = p->nleaf * nchv;
       x.v = VDesc{g, ldg, p->d_perm_xi, p->d_xioff, p->d_vbar, w[0], L, l0, K, nrhs, 64, nchv,
                   p->smax_xi, 1};
@@ -1118,7 +1127,7 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
   // state buffers [2^k][kmaxg][NB], no factors.
   auto fused_lds = [&](int kk, int kmg, int kt) -> size_t {
     if (!mfma) return ((size_t)2 << kk) * kmg * NB * sizeof(VT);
-    return ((size_t)NV * ((size_t)kmg * NB + (size_t)2 * kmg * kt) + 2 * kt) * sizeof(VT);
+    return ((size_t)NV * ((size_t)kmg * NB + (size_t)2 * kmg * kt + 20) + 2 * kt) * sizeof(VT);
   };
   auto add_stages = [&](int lo, int hi, bool gside) {   // output levels lo..hi
     int l = lo;
@@ -1160,7 +1169,9 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
         A.kld[j] = st.k_ld;
         nnz += (double)st.nnz;
       }
-      x.kt = even_kt(kom);
+      // (MFMA: KT also covers the launch's input rank, which bounds the
+      // staged factor blocks at 2 KT^2 entries)
+      x.kt = even_kt(mfma ? km : kom);
       x.lds = fused_lds(kk, km, x.kt);
       x.nblocks = (p->npairs >> (mfma ? LNV : kk)) * nchunk;
       x.f.in = w[cur];
@@ -1192,7 +1203,7 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
       const int R = K << l0;
       const int nchu = (nrhs + 63) / 64;
       x.mfma = true;
-      x.lds = ((size_t)R * kLeafMfma + (size_t)kLeafMfma * 64) * sizeof(VT);
+      x.lds = ((size_t)R * (kLeafMfma + 1) + (size_t)kLeafMfma * 64) * sizeof(VT);
       x.nblocks = p->nleaf * nchu;
       x.u = UDesc{w[cur], u, ldu, p->d_perm_x, p->d_xoff, p->d_ubar, l0, K, nrhs, 64, nchu,
                   p->smax_x, 1};
@@ -1504,7 +1515,7 @@ int apply_batch_t(ibf_batch_s* b, const void* const* g, const int64_t* ldg, void
       } else if (y.kind == kLaunchFused && y.mfma) {
         const FusedArgs& A = y.f.A;
         const size_t nv = (size_t)kBlock / (size_t)A.NB;     // virtual slots a block
-        y.lds = (nv * ((size_t)A.kmaxg * A.NB + (size_t)2 * A.kmaxg * ph.kt) + 2 * ph.kt) *
+        y.lds = (nv * ((size_t)A.kmaxg * A.NB + (size_t)2 * A.kmaxg * ph.kt + 20) + 2 * ph.kt) *
                 sizeof(VT);
       }
       ph.lds = std::max(ph.lds, y.lds);
