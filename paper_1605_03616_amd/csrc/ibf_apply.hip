@@ -352,26 +352,24 @@ struct SlotFactors {
   static constexpr int TPS = kBlock / NV;
   static constexpr int NL = (2 * KT * KT + TPS - 1) / TPS;
   VT v[NL];
-  // rounds i < fs / TPS are full (a uniform bound); only round fs / TPS tests
-  // the entry index
+  // Every round loads (entries past the block re-read its last entry), so
+  // loads and stores are straight-line code and the compiler can wait for
+  // exactly the loads a store needs.
   __device__ __forceinline__ void load(const FT* blk, int fs, int k, int j, int rem, int64_t gid0,
                                        int sh_end, int L, int l) {
     const int u = threadIdx.x / TPS, e = threadIdx.x % TPS;
     const int64_t g = gid0 + (u >> k);
     const int64_t ap = g >> sh_end, bpp = g & (((int64_t)1 << sh_end) - 1);
-    const FT* src = blk + fused_pout(u & ((1 << k) - 1), j, rem, ap, bpp, L, l) * fs + e;
-    const int full = fs / TPS, part = fs % TPS;
+    const FT* src = blk + fused_pout(u & ((1 << k) - 1), j, rem, ap, bpp, L, l) * fs;
 #pragma unroll
-    for (int i = 0; i < NL; ++i)
-      if (i < full || (i == full && e < part)) v[i] = load_factor(src, TPS * i);
+    for (int i = 0; i < NL; ++i) v[i] = load_factor(src, min(e + TPS * i, fs - 1));
   }
+  // rounds past the block rewrite its last entry with the same value
   __device__ __forceinline__ void store(VT* F, int fs) const {
     const int u = threadIdx.x / TPS, e = threadIdx.x % TPS;
-    VT* dst = F + u * slot_stride(fs) + e;
-    const int full = fs / TPS, part = fs % TPS;
+    VT* dst = F + u * slot_stride(fs);
 #pragma unroll
-    for (int i = 0; i < NL; ++i)
-      if (i < full || (i == full && e < part)) dst[TPS * i] = v[i];
+    for (int i = 0; i < NL; ++i) dst[min(e + TPS * i, fs - 1)] = v[i];
   }
 };
 
@@ -454,20 +452,23 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
     int64_t ld_v = nrhs;
     asm volatile("" : "+s"(kin_v), "+s"(fs_v), "+v"(trow_v), "+s"(ld_v));
     fb.load(blk0, fs_v, k, 0, k - 1, g.gid0, sh_end, L, A.l_start);
-    const VT* src = in + ((g.gid0 << k) * kin0 + trow_v) * ld_v + g.nb0 + col;
+    // straight-line loads (rows i >= kin0 re-read row kin0 - 1, columns past
+    // the chunk re-read column 0 and are zeroed after the load)
     const bool ok = col < g.nbw;
-    // row trow + NV i < NV kin0 exactly when i < kin0: a uniform bound
+    const VT* src = in + ((g.gid0 << k) * kin0 + trow_v) * ld_v + g.nb0 + (ok ? col : 0);
 #pragma unroll
-    for (int i = 0; i < XR; ++i)
-      if (i < kin_v) xin[i] = ok ? src[NV * i * ld_v] : Zero<VT>::v();
+    for (int i = 0; i < XR; ++i) {
+      const VT v = src[NV * min(i, kin_v - 1) * ld_v];
+      xin[i] = ok ? v : Zero<VT>::v();
+    }
   };
   auto deposit = [&](const Blk& g) {
     int kin_v = kin0, rows_v = rows0, fs_v = fs0, trow_v = trow;
     asm volatile("" : "+s"(kin_v), "+s"(rows_v), "+s"(fs_v), "+v"(trow_v));
     VT* dst = S + trow_v * NB + col;
+    // rows i >= kin0 hold row kin0 - 1 again and rewrite it (straight-line)
 #pragma unroll
-    for (int i = 0; i < XR; ++i)
-      if (i < kin_v) dst[NV * i * NB] = xin[i];
+    for (int i = 0; i < XR; ++i) dst[NV * min(i, kin_v - 1) * NB] = xin[i];
     if (rows_v > NV * XR) {
       const VT* src = in + (g.gid0 << k) * kin0 * nrhs + g.nb0 + col;
       for (int r = NV * XR + trow_v; r < rows_v; r += NV)
