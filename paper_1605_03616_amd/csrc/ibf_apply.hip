@@ -222,6 +222,11 @@ struct FusedArgs {
   int ranks[kMaxR + 1];
   int kld[kMaxR];
   const void* blk[kMaxR];
+  // MFMA launches only: the swept-in middle block Mdot [pair][kmid_out][kmid_in]
+  // applied to each input pair before the first stage (null: none), in which
+  // case the inputs hold kmid_in rows and ranks[0] == kmid_out
+  const void* mid;
+  int kmid_in, kmid_out;
 };
 
 // global output pair of local output slot `locp` after stage j (rem child bits left)
@@ -352,24 +357,44 @@ struct SlotFactors {
   static constexpr int TPS = kBlock / NV;
   static constexpr int NL = (2 * KT * KT + TPS - 1) / TPS;
   VT v[NL];
+  __device__ static __forceinline__ int slot() { return threadIdx.x / TPS; }
+  // HBM block of stage j's factors for this thread's slot
+  __device__ static __forceinline__ const FT* stage_block(const FT* blk, int fs, int k, int j,
+                                                          int rem, int64_t gid0, int sh_end, int L,
+                                                          int l) {
+    const int u = slot();
+    const int64_t g = gid0 + (u >> k);
+    const int64_t ap = g >> sh_end, bpp = g & (((int64_t)1 << sh_end) - 1);
+    return blk + fused_pout(u & ((1 << k) - 1), j, rem, ap, bpp, L, l) * fs;
+  }
   // Every round loads (entries past the block re-read its last entry), so
   // loads and stores are straight-line code and the compiler can wait for
   // exactly the loads a store needs.
-  __device__ __forceinline__ void load(const FT* blk, int fs, int k, int j, int rem, int64_t gid0,
-                                       int sh_end, int L, int l) {
-    const int u = threadIdx.x / TPS, e = threadIdx.x % TPS;
-    const int64_t g = gid0 + (u >> k);
-    const int64_t ap = g >> sh_end, bpp = g & (((int64_t)1 << sh_end) - 1);
-    const FT* src = blk + fused_pout(u & ((1 << k) - 1), j, rem, ap, bpp, L, l) * fs;
+  __device__ __forceinline__ void load(const FT* src, int fs) {
+    const int e = threadIdx.x % TPS;
 #pragma unroll
     for (int i = 0; i < NL; ++i) v[i] = load_factor(src, min(e + TPS * i, fs - 1));
   }
-  // rounds past the block rewrite its last entry with the same value
+  // Entries to F[slot] at slot_stride(fs); rounds past the block rewrite its
+  // last entry with the same value.
   __device__ __forceinline__ void store(VT* F, int fs) const {
-    const int u = threadIdx.x / TPS, e = threadIdx.x % TPS;
+    const int u = slot(), e = threadIdx.x % TPS;
     VT* dst = F + u * slot_stride(fs);
 #pragma unroll
     for (int i = 0; i < NL; ++i) dst[min(e + TPS * i, fs - 1)] = v[i];
+  }
+  // The fs entries form a [t][s] matrix of tk columns; store it transposed as
+  // [s][tld] at slot_stride(tk tld).
+  __device__ __forceinline__ void store_t(VT* F, int fs, int tk, int tld) const {
+    const int u = slot(), e = threadIdx.x % TPS;
+    VT* dst = F + u * slot_stride(tk * tld);
+    const float inv = 1.0f / (float)tk;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const int o = min(e + TPS * i, fs - 1);
+      const int t = (int)(((float)o + 0.5f) * inv);           // o / tk (exact, o < 2^22)
+      dst[(o - t * tk) * tld + t] = v[i];
+    }
   }
 };
 
@@ -392,7 +417,7 @@ struct SlotFactors {
 // re t1, im t1).  With P = sum f_i x_re and Q = sum f_i x_im, the complex
 // outputs are
 //   out[2g]   = (P0 - Q1, P1 + Q0),  out[2g+1] = (P2 - Q3, P3 + Q2).
-template <typename VT, typename FT, int KT, int NBC>
+template <typename VT, typename FT, int KT, int NBC, bool MID>
 __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, int64_t lstep,
                                                 int64_t lend) {
   static_assert(sizeof(VT) == 8, "MFMA variant computes in FP32");
@@ -424,8 +449,23 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
   const int vs = SPW * wave + lane / NB;                      // this lane's virtual slot
   const int grp = vs >> k, loc = vs & (nslot - 1);            // its group and local slot
   const int trow = threadIdx.x / NB;                          // row phase of the copies
-  const int kin0 = A.ranks[0], rows0 = NV * kin0, fs0 = 2 * kin0 * A.kld[0];
+  // A block's first factors: the swept-in middle block Mdot when the launch
+  // applies it (staged transposed, [s][kldm]), else stage 0's blocks.  The
+  // choice is a select, not a branch, so the staging stays straight-line.
+  using SF = SlotFactors<VT, FT, KT, NV>;
   const FT* blk0 = reinterpret_cast<const FT*>(A.blk[0]);
+  const FT* mdot = reinterpret_cast<const FT*>(A.mid);
+  constexpr bool has_mid = MID;                               // A.mid set by the host
+  const int kin0 = has_mid ? A.kmid_in : A.ranks[0];          // input rows per pair
+  const int rows0 = NV * kin0;
+  const int kmo = A.kmid_out, kldm = (A.kmid_out + 1) & ~1;
+  const int fs0 = 2 * A.ranks[0] * A.kld[0];                  // a stage-0 block
+  const int fsm = kmo * kin0, fsml = kin0 * kldm;             // an Mdot block: HBM, LDS
+  const int fsf = has_mid ? fsm : fs0;
+  auto first_src = [&](int64_t gid0) {
+    if constexpr (MID) return mdot + ((gid0 << k) + SF::slot()) * (int64_t)fsm;
+    else return SF::stage_block(blk0, fs0, k, 0, k - 1, gid0, sh_end, L, A.l_start);
+  };
 
   struct Blk {
     int64_t gid0;                                             // first group
@@ -439,7 +479,7 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
     g.nbw = min(NB, nrhs - g.nb0);
     return g;
   };
-  SlotFactors<VT, FT, KT, NV> fb;
+  SF fb;
   VT xin[XR];
   // The block's input rows are contiguous in HBM (pairs (gid0 << k) .. + NV,
   // kin0 rows each) and land contiguously in S; columns >= nbw read as zero.
@@ -448,10 +488,10 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
   // hoisted out of the block loop, where dozens of them would stay live in
   // registers across every stage.
   auto fetch = [&](const Blk& g) {
-    int kin_v = kin0, fs_v = fs0, trow_v = trow;
+    int kin_v = kin0, fs_v = fsf, trow_v = trow;
     int64_t ld_v = nrhs;
     asm volatile("" : "+s"(kin_v), "+s"(fs_v), "+v"(trow_v), "+s"(ld_v));
-    fb.load(blk0, fs_v, k, 0, k - 1, g.gid0, sh_end, L, A.l_start);
+    fb.load(first_src(g.gid0), fs_v);
     // straight-line loads (rows i >= kin0 re-read row kin0 - 1, columns past
     // the chunk re-read column 0 and are zeroed after the load)
     const bool ok = col < g.nbw;
@@ -463,7 +503,7 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
     }
   };
   auto deposit = [&](const Blk& g) {
-    int kin_v = kin0, rows_v = rows0, fs_v = fs0, trow_v = trow;
+    int kin_v = kin0, rows_v = rows0, fs_v = fsf, trow_v = trow;
     asm volatile("" : "+s"(kin_v), "+s"(rows_v), "+s"(fs_v), "+v"(trow_v));
     VT* dst = S + trow_v * NB + col;
     // rows i >= kin0 hold row kin0 - 1 again and rewrite it (straight-line)
@@ -474,7 +514,63 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
       for (int r = NV * XR + trow_v; r < rows_v; r += NV)
         S[r * NB + col] = col < g.nbw ? src[(int64_t)r * nrhs] : Zero<VT>::v();
     }
-    fb.store(F, fs_v);
+    if constexpr (MID) fb.store_t(F, fs_v, kin0, kldm);
+    else fb.store(F, fs_v);
+  };
+  // P, Q += F-block rows times the nrows state rows from xp (the lane's
+  // column); the factor rows start at fp (the lane's float fi), fstep floats
+  // apart.  Software-pipelined: the LDS reads of the next row are in flight
+  // while the MFMAs of the current row issue; for even nrows the last
+  // iteration reads one row past the end, inside the LDS allocation and never
+  // used.  (Starting the first row's MFMAs from an inline zero instead of
+  // clearing the accumulators costs more registers than it saves.)
+  auto product = [&](const VT* xp, const float* fp, int fstep, int nrows, v4f (&P)[KG],
+                     v4f (&Q)[KG]) {
+    auto load_row = [&](const VT* x, const float* f, float (&Av)[KG], VT& X) {
+      X = *x;
+#pragma unroll
+      for (int gq = 0; gq < KG; ++gq) Av[gq] = f[4 * gq];
+    };
+    auto mfma_row = [&](const float (&Av)[KG], const VT& X) {
+#pragma unroll
+      for (int gq = 0; gq < KG; ++gq) {
+        P[gq] = __builtin_amdgcn_mfma_f32_4x4x1f32(Av[gq], X.x, P[gq], 0, 0, 0);
+        Q[gq] = __builtin_amdgcn_mfma_f32_4x4x1f32(Av[gq], X.y, Q[gq], 0, 0, 0);
+      }
+    };
+#pragma unroll
+    for (int gq = 0; gq < KG; ++gq) {
+      P[gq] = v4f{0.f, 0.f, 0.f, 0.f};
+      Q[gq] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+    float av[KG], bv[KG];
+    VT xa, xb;
+    load_row(xp, fp, av, xa);
+    int left = nrows;
+#pragma unroll 1
+    for (; left >= 2; left -= 2) {
+      load_row(xp + NB, fp + fstep, bv, xb);
+      __builtin_amdgcn_sched_barrier(0);                      // keep the reads ahead
+      mfma_row(av, xa);
+      __builtin_amdgcn_sched_barrier(0);
+      xp += 2 * NB;
+      fp += 2 * fstep;
+      load_row(xp, fp, av, xa);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_row(bv, xb);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (left) mfma_row(av, xa);                               // odd nrows: the last row
+  };
+  // the kout output rows of P, Q (this lane's slot and column) to S
+  auto put_rows = [&](const v4f (&P)[KG], const v4f (&Q)[KG], int kout) {
+    VT* dst = S + (size_t)vs * kout * NB + col;
+#pragma unroll
+    for (int gq = 0; gq < KG; ++gq) {
+      const v4f p = P[gq], q = Q[gq];
+      if (2 * gq < kout) dst[(2 * gq) * NB] = make_float2(p[0] - q[1], p[1] + q[0]);
+      if (2 * gq + 1 < kout) dst[(2 * gq + 1) * NB] = make_float2(p[2] - q[3], p[3] + q[2]);
+    }
   };
 
   Blk cur = decode(lb);
@@ -487,6 +583,19 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
     const Blk nxt = more ? decode(nlb) : cur;
     const int64_t gme = cur.gid0 + grp;                       // this lane's group
     const int64_t ap = gme >> sh_end, bpp = gme & (((int64_t)1 << sh_end) - 1);
+    if constexpr (MID) {
+      // the middle block on each input pair (the lane's own slot), with
+      // stage 0's factors in flight
+      fb.load(SF::stage_block(blk0, fs0, k, 0, k - 1, cur.gid0, sh_end, L, A.l_start), fs0);
+      v4f P[KG], Q[KG];
+      product(S + (size_t)vs * kin0 * NB + col,
+              reinterpret_cast<const float*>(F + (size_t)vs * slot_stride(fsml)) + fi, 2 * kldm,
+              kin0, P, Q);
+      __syncthreads();                                        // S and F reads done
+      put_rows(P, Q, kmo);
+      fb.store(F, fs0);
+      __syncthreads();
+    }
     // one stage; the last one is peeled off the stage loop so that the next
     // block's prefetched rows are live only during it
     auto stage = [&](int j, auto last_c) {
@@ -495,68 +604,24 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
       const int kin = A.ranks[j], kout = A.ranks[j + 1], ke = A.kld[j];
       const int fs = 2 * kin * ke;
       const int rem = k - j - 1;
-      if constexpr (!LAST)   // next stage's factor blocks: in flight during this stage
-        fb.load(reinterpret_cast<const FT*>(A.blk[j + 1]), 2 * kout * A.kld[j + 1], k, j + 1,
-                rem - 1, cur.gid0, sh_end, L, l + 1);
-      else if (more)         // the next block: in flight during the last stage
+      if constexpr (!LAST) {  // next stage's factor blocks: in flight during this stage
+        const int fsn = 2 * kout * A.kld[j + 1];
+        fb.load(SF::stage_block(reinterpret_cast<const FT*>(A.blk[j + 1]), fsn, k, j + 1, rem - 1,
+                                cur.gid0, sh_end, L, l + 1),
+                fsn);
+      } else if (more) {      // the next block: in flight during the last stage
         fetch(nxt);
-      v4f P[KG], Q[KG];
-      {
-        // the block product of this lane's slot: one loop over the 2 kin
-        // input rows of its two children (adjacent slots, so contiguous rows
-        // in S), and the block's factor rows in F
-        const VT* xp = S + (size_t)((grp << k) + fused_in0(loc, rem)) * kin * NB + col;
-        const float* fp = reinterpret_cast<const float*>(F + (size_t)vs * slot_stride(fs)) + fi;
-        const int fstep = 2 * ke;                             // floats per factor row
-        auto load_row = [&](const VT* x, const float* f, float (&Av)[KG], VT& X) {
-          X = *x;
-#pragma unroll
-          for (int gq = 0; gq < KG; ++gq) Av[gq] = f[4 * gq];
-        };
-        auto mfma_row = [&](const float (&Av)[KG], const VT& X) {
-#pragma unroll
-          for (int gq = 0; gq < KG; ++gq) {
-            P[gq] = __builtin_amdgcn_mfma_f32_4x4x1f32(Av[gq], X.x, P[gq], 0, 0, 0);
-            Q[gq] = __builtin_amdgcn_mfma_f32_4x4x1f32(Av[gq], X.y, Q[gq], 0, 0, 0);
-          }
-        };
-        // software-pipelined: the LDS reads of the next row are in flight
-        // while the MFMAs of the current row issue.  The last iteration reads
-        // one row past the end, inside the LDS allocation and never used.
-        // (Starting the first row's MFMAs from an inline zero instead of
-        // clearing the accumulators costs more registers than it saves.)
-#pragma unroll
-        for (int gq = 0; gq < KG; ++gq) {
-          P[gq] = v4f{0.f, 0.f, 0.f, 0.f};
-          Q[gq] = v4f{0.f, 0.f, 0.f, 0.f};
-        }
-        float av[KG], bv[KG];
-        VT xa, xb;
-        load_row(xp, fp, av, xa);
-#pragma unroll 1
-        for (int left = 2 * kin; left > 0; left -= 2) {
-          load_row(xp + NB, fp + fstep, bv, xb);
-          __builtin_amdgcn_sched_barrier(0);                  // keep the reads ahead
-          mfma_row(av, xa);
-          __builtin_amdgcn_sched_barrier(0);
-          xp += 2 * NB;
-          fp += 2 * fstep;
-          load_row(xp, fp, av, xa);
-          __builtin_amdgcn_sched_barrier(0);
-          mfma_row(bv, xb);
-          __builtin_amdgcn_sched_barrier(0);
-        }
       }
+      // the block product of this lane's slot over the 2 kin input rows of
+      // its two children (adjacent slots, so contiguous rows in S)
+      v4f P[KG], Q[KG];
+      product(S + (size_t)((grp << k) + fused_in0(loc, rem)) * kin * NB + col,
+              reinterpret_cast<const float*>(F + (size_t)vs * slot_stride(fs)) + fi, 2 * ke,
+              2 * kin, P, Q);
       if constexpr (!LAST) {
         // outputs replace inputs in S once every wave has read its inputs
         __syncthreads();
-        VT* dst = S + (size_t)vs * kout * NB + col;
-#pragma unroll
-        for (int gq = 0; gq < KG; ++gq) {
-          const v4f p = P[gq], q = Q[gq];
-          if (2 * gq < kout) dst[(2 * gq) * NB] = make_float2(p[0] - q[1], p[1] + q[0]);
-          if (2 * gq + 1 < kout) dst[(2 * gq + 1) * NB] = make_float2(p[2] - q[3], p[3] + q[2]);
-        }
+        put_rows(P, Q, kout);
         fb.store(F, 2 * kout * A.kld[j + 1]);
         __syncthreads();
       } else if (col < cur.nbw) {
@@ -593,18 +658,21 @@ __global__ __launch_bounds__(kBlock) void k_batch_fused(const FusedDesc* __restr
   apply_fused_body<VT, FT, KT>(ds[p], (int64_t)blockIdx.x - boff[p]);
 }
 // persistent: a grid of resident blocks over `total` logical blocks
-template <typename VT, typename FT, int KT, int NBC>
+template <typename VT, typename FT, int KT, int NBC, bool MID>
 __global__ __launch_bounds__(kBlock) void k_apply_fused_mfma(FusedDesc D, int64_t total) {
-  fused_mfma_body<VT, FT, KT, NBC>(D, xcd_logical_block((int64_t)gridDim.x),
-                                   (int64_t)gridDim.x, total);
+  fused_mfma_body<VT, FT, KT, NBC, MID>(D, xcd_logical_block((int64_t)gridDim.x),
+                                        (int64_t)gridDim.x, total);
 }
+// (batched phases: one logical block per block; a member's launch carries the
+// middle block when its descriptor has one)
 template <typename VT, typename FT, int KT, int NBC>
 __global__ __launch_bounds__(kBlock) void k_batch_fused_mfma(const FusedDesc* __restrict__ ds,
                                                              const int64_t* __restrict__ boff,
                                                              int count) {
   const int p = find_problem(boff, count, blockIdx.x);
   const int64_t lb = (int64_t)blockIdx.x - boff[p];
-  fused_mfma_body<VT, FT, KT, NBC>(ds[p], lb, 1, lb + 1);
+  if (ds[p].A.mid) fused_mfma_body<VT, FT, KT, NBC, true>(ds[p], lb, 1, lb + 1);
+  else fused_mfma_body<VT, FT, KT, NBC, false>(ds[p], lb, 1, lb + 1);
 }
 
 // Middle block of the swept-in factorization: out[p][t][n] = sum_s Mdot[p][t][s] in[p][s][n]
@@ -1130,16 +1198,20 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
     if (!mfma) return ((size_t)2 << kk) * kmg * NB * sizeof(VT);
     return ((size_t)NV * ((size_t)kmg * NB + (size_t)2 * kmg * kt + 20) + 2 * kt) * sizeof(VT);
   };
+  // MFMA plans with the sweep-in apply the middle block inside the first
+  // G-side launch (before its first stage) instead of a launch of its own
+  bool fold_mid = false;
   auto add_stages = [&](int lo, int hi, bool gside) {   // output levels lo..hi
     int l = lo;
     while (l <= hi) {
+      const bool mid_here = fold_mid && l == lo;
       int kk = 1;
       while (true) {   // grow the fused group while it fits
         const int next = kk + 1;
         if (l + next - 1 > hi) break;
         if (next > kMaxR - 1) break;
         if (next > L - l + 1) break;                          // group must fit the b bits
-        int km = 1;
+        int km = mid_here ? p->k_mid_h : 1;
         for (int j = 0; j <= next; ++j) km = std::max(km, rank_at(l - 1 + j, gside));
         // MFMA: at most NV slots a block; vector: at most 4 outputs per thread and stage
         if (mfma ? (next > LNV) : (((int64_t)1 << next) * km * NB > 4 * kBlock)) break;
@@ -1163,6 +1235,17 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
         km = std::max(km, A.ranks[j]);
         if (j > 0) kom = std::max(kom, A.ranks[j]);
       }
+      A.mid = nullptr;
+      A.kmid_in = A.kmid_out = 0;
+      int kin_launch = A.ranks[0];
+      if (mid_here) {
+        A.mid = p->d_mdot;
+        A.kmid_in = p->k_mid_h;
+        A.kmid_out = p->k_mid_g;
+        km = std::max(km, p->k_mid_h);
+        kin_launch = p->k_mid_h;
+        nnz += (double)p->npairs * p->k_mid_g * p->k_mid_h;
+      }
       A.kmaxg = km;
       for (int j = 0; j < kk; ++j) {
         const Stage& st = p->stages[l + j - l0 - 1];
@@ -1178,15 +1261,18 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
       x.f.in = w[cur];
       x.f.out = w[cur ^ 1];
       x.flops = 8.0 * nnz * nrhs;
-      x.bytes = nnz * fb + (double)p->npairs * (A.ranks[0] + A.ranks[kk]) * nrhs * vb;
+      x.bytes = nnz * fb + (double)p->npairs * (kin_launch + A.ranks[kk]) * nrhs * vb;
       seq.push_back(x);
       cur ^= 1;
       l += kk;
     }
+    fold_mid = false;
   };
   if (swept) {
     add_stages(l0 + 1, h, false);
-    add_mid();
+    // the first G-side launch starts from the middle block's output rank
+    fold_mid = mfma && rank_at(h, true) == p->k_mid_g && h + 1 <= L - l0;
+    if (!fold_mid) add_mid();
     add_stages(h + 1, L - l0, true);
   } else {
     add_stages(l0 + 1, L - l0, true);
@@ -1274,17 +1360,20 @@ int launch_one(const Launch& x, hipStream_t s) {
     case kLaunchFused:
       if (x.mfma) {
         if constexpr (sizeof(VT) == 8) {
-#define IBF_LAUNCH_FMN(KTC, NBC)                                                    \
-  {                                                                                 \
-    int64_t nres = 0;                                                               \
-    const int rc = resident_blocks(reinterpret_cast<const void*>(                    \
-                                       &k_apply_fused_mfma<VT, FT, KTC, NBC>),       \
-                                   x.lds, &nres);                                   \
-    if (rc) return rc;                                                              \
-    const dim3 pgrid((unsigned)std::min<int64_t>(x.nblocks, nres));                  \
-    hipLaunchKernelGGL((k_apply_fused_mfma<VT, FT, KTC, NBC>), pgrid, blk, x.lds, s,  \
-                       x.f, x.nblocks);                                             \
+#define IBF_LAUNCH_FMNM(KTC, NBC, MIDC)                                               \
+  {                                                                                   \
+    int64_t nres = 0;                                                                 \
+    const int rc = resident_blocks(reinterpret_cast<const void*>(                      \
+                                       &k_apply_fused_mfma<VT, FT, KTC, NBC, MIDC>),   \
+                                   x.lds, &nres);                                     \
+    if (rc) return rc;                                                                \
+    const dim3 pgrid((unsigned)std::min<int64_t>(x.nblocks, nres));                    \
+    hipLaunchKernelGGL((k_apply_fused_mfma<VT, FT, KTC, NBC, MIDC>), pgrid, blk, x.lds, \
+                       s, x.f, x.nblocks);                                            \
   }
+#define IBF_LAUNCH_FMN(KTC, NBC)               \
+  if (x.f.A.mid) IBF_LAUNCH_FMNM(KTC, NBC, true) \
+  else IBF_LAUNCH_FMNM(KTC, NBC, false)
 #define IBF_LAUNCH_FM32(KTC) IBF_LAUNCH_FMN(KTC, 32)
 #define IBF_LAUNCH_FM16(KTC) IBF_LAUNCH_FMN(KTC, 16)
           if (x.f.A.NB == 32) {
@@ -1295,6 +1384,7 @@ int launch_one(const Launch& x, hipStream_t s) {
 #undef IBF_LAUNCH_FM16
 #undef IBF_LAUNCH_FM32
 #undef IBF_LAUNCH_FMN
+#undef IBF_LAUNCH_FMNM
         }
       } else {
 #define IBF_LAUNCH_FV(KTC) \
