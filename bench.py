@@ -41,8 +41,10 @@ APPLY_SRC = os.path.join(ROOT, "paper_1605_03616_amd", "csrc", "ibf_apply.hip")
 MEASURED_TRAFFIC = {
     # workload -> (sha1 of the apply source, kernel class,
     #              [(launches per step, FETCH_SIZE KiB, WRITE_SIZE KiB), ...])
-    "fio1d_n65536_r12_fp32": ("11610ed9aceabe796b706f8f9b76678cfe1b8349", "apply_fused_mfma",
-                              [(2, 324695, 344064), (1, 261203, 294912)]),
+    "fio1d_n65536_r12_fp32": ("bb5155738ff7e94ddefc35f9a452a0a6c0a18805", "apply_fused_mfma",
+                              [(2, 327955, 344064), (1, 264802, 294912)]),
+    "nudft_n1048576_r10": ("bb5155738ff7e94ddefc35f9a452a0a6c0a18805", "apply_fused_mfma",
+                           [(1, 2871410, 917504), (2, 1867860, 983040), (1, 1769560, 917504)]),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
