@@ -524,22 +524,25 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
   // iteration reads one row past the end, inside the LDS allocation and never
   // used.  (Starting the first row's MFMAs from an inline zero instead of
   // clearing the accumulators costs more registers than it saves.)
-  auto product = [&](const VT* xp, const float* fp, int fstep, int nrows, v4f (&P)[KG],
-                     v4f (&Q)[KG]) {
+  // Only the first NG = ceil(kout / 2) row pairs are computed: the caller
+  // picks NG = KG or KG - 1 for the stage (see run_product).
+  auto product = [&](auto ng_c, const VT* xp, const float* fp, int fstep, int nrows,
+                     v4f (&P)[KG], v4f (&Q)[KG]) {
+    constexpr int NG = decltype(ng_c)::value;
     auto load_row = [&](const VT* x, const float* f, float (&Av)[KG], VT& X) {
       X = *x;
 #pragma unroll
-      for (int gq = 0; gq < KG; ++gq) Av[gq] = f[4 * gq];
+      for (int gq = 0; gq < NG; ++gq) Av[gq] = f[4 * gq];
     };
     auto mfma_row = [&](const float (&Av)[KG], const VT& X) {
 #pragma unroll
-      for (int gq = 0; gq < KG; ++gq) {
+      for (int gq = 0; gq < NG; ++gq) {
         P[gq] = __builtin_amdgcn_mfma_f32_4x4x1f32(Av[gq], X.x, P[gq], 0, 0, 0);
         Q[gq] = __builtin_amdgcn_mfma_f32_4x4x1f32(Av[gq], X.y, Q[gq], 0, 0, 0);
       }
     };
 #pragma unroll
-    for (int gq = 0; gq < KG; ++gq) {
+    for (int gq = 0; gq < NG; ++gq) {
       P[gq] = v4f{0.f, 0.f, 0.f, 0.f};
       Q[gq] = v4f{0.f, 0.f, 0.f, 0.f};
     }
@@ -562,14 +565,29 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
     }
     if (left) mfma_row(av, xa);                               // odd nrows: the last row
   };
+  // stages whose output rank fits KT - 2 rows skip the last row pair: the
+  // launch's KT covers its largest rank, the other stages' ranks are often
+  // smaller (one uniform branch a stage)
+  auto run_product = [&](int kout, const VT* xp, const float* fp, int fstep, int nrows,
+                         v4f (&P)[KG], v4f (&Q)[KG]) {
+    if constexpr (KG > 1) {
+      if (kout <= KT - 2) {
+        product(std::integral_constant<int, KG - 1>{}, xp, fp, fstep, nrows, P, Q);
+        return;
+      }
+    }
+    product(std::integral_constant<int, KG>{}, xp, fp, fstep, nrows, P, Q);
+  };
   // the kout output rows of P, Q (this lane's slot and column) to S
   auto put_rows = [&](const v4f (&P)[KG], const v4f (&Q)[KG], int kout) {
     VT* dst = S + (size_t)vs * kout * NB + col;
 #pragma unroll
     for (int gq = 0; gq < KG; ++gq) {
-      const v4f p = P[gq], q = Q[gq];
-      if (2 * gq < kout) dst[(2 * gq) * NB] = make_float2(p[0] - q[1], p[1] + q[0]);
-      if (2 * gq + 1 < kout) dst[(2 * gq + 1) * NB] = make_float2(p[2] - q[3], p[3] + q[2]);
+      if (2 * gq < kout) {
+        const v4f p = P[gq], q = Q[gq];
+        dst[(2 * gq) * NB] = make_float2(p[0] - q[1], p[1] + q[0]);
+        if (2 * gq + 1 < kout) dst[(2 * gq + 1) * NB] = make_float2(p[2] - q[3], p[3] + q[2]);
+      }
     }
   };
 
@@ -588,9 +606,9 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
       // stage 0's factors in flight
       fb.load(SF::stage_block(blk0, fs0, k, 0, k - 1, cur.gid0, sh_end, L, A.l_start), fs0);
       v4f P[KG], Q[KG];
-      product(S + (size_t)vs * kin0 * NB + col,
-              reinterpret_cast<const float*>(F + (size_t)vs * slot_stride(fsml)) + fi, 2 * kldm,
-              kin0, P, Q);
+      run_product(kmo, S + (size_t)vs * kin0 * NB + col,
+                  reinterpret_cast<const float*>(F + (size_t)vs * slot_stride(fsml)) + fi,
+                  2 * kldm, kin0, P, Q);
       __syncthreads();                                        // S and F reads done
       put_rows(P, Q, kmo);
       fb.store(F, fs0);
@@ -615,9 +633,9 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
       // the block product of this lane's slot over the 2 kin input rows of
       // its two children (adjacent slots, so contiguous rows in S)
       v4f P[KG], Q[KG];
-      product(S + (size_t)((grp << k) + fused_in0(loc, rem)) * kin * NB + col,
-              reinterpret_cast<const float*>(F + (size_t)vs * slot_stride(fs)) + fi, 2 * ke,
-              2 * kin, P, Q);
+      run_product(kout, S + (size_t)((grp << k) + fused_in0(loc, rem)) * kin * NB + col,
+                  reinterpret_cast<const float*>(F + (size_t)vs * slot_stride(fs)) + fi, 2 * ke,
+                  2 * kin, P, Q);
       if constexpr (!LAST) {
         // outputs replace inputs in S once every wave has read its inputs
         __syncthreads();
@@ -629,11 +647,12 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
         VT* dst = out + fused_pout(loc, j, 0, ap, bpp, L, l) * kout * nrhs + cur.nb0 + col;
 #pragma unroll
         for (int gq = 0; gq < KG; ++gq) {
-          const v4f p = P[gq], q = Q[gq];
-          if (2 * gq < kout)
+          if (2 * gq < kout) {
+            const v4f p = P[gq], q = Q[gq];
             dst[(int64_t)(2 * gq) * nrhs] = make_float2(p[0] - q[1], p[1] + q[0]);
-          if (2 * gq + 1 < kout)
-            dst[(int64_t)(2 * gq + 1) * nrhs] = make_float2(p[2] - q[3], p[3] + q[2]);
+            if (2 * gq + 1 < kout)
+              dst[(int64_t)(2 * gq + 1) * nrhs] = make_float2(p[2] - q[3], p[3] + q[2]);
+          }
         }
       }
     };
