@@ -21,8 +21,10 @@
 //
 // Kernels: k2_tables (Chebyshev nodes, tensor child->parent Lagrange
 // matrices), k2_middle (eq:KeqUMV), k2_sweep_g (eqn:GC), k2_sweep_h (eqn:HR),
-// k2_pack_stage, k2_vbar (eqn:V0), k2_ubar, k2_centre; apply: k2_apply_v,
-// k2_apply_stage, k2_apply_u, k2_apply_centre.
+// k2_pack_stage, k2_vbar (eqn:V0), k2_ubar, k2_centre; apply (a thread per
+// output row and chunk of right-hand sides): k2_apply_v_rows,
+// k2_apply_stage_quad, k2_apply_u_rows, k2_apply_centre_rows (k2_apply_v,
+// k2_apply_stage, k2_apply_centre when the staged rows exceed LDS).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -55,7 +57,7 @@ struct Box2 {
   int32_t* d_perm_xi = nullptr;
   int32_t* d_xileaf = nullptr;
   int32_t* d_xioff = nullptr;  // Omega leaf CSR offsets (4^(L-lV) + 1)
-  int smax_xi = 0;
+  int smax_xi = 0;              // most points in one Omega leaf
   std::vector<Stage2> stages;  // H stages then G stages, in apply order
   void* d_vbar = nullptr;      // [Omega point][4^lV][K_V]
   void* d_ubar = nullptr;      // [X point (sorted at level L)][K_U]
@@ -696,6 +698,74 @@ __global__ void k2_apply_v(const VT* __restrict__ g, int64_t ldg, const int32_t*
   mu[e] = acc;
 }
 
+// One quadtree stage (eqn:GC / eqn:HR applied): out[(a, b)][t][n] =
+// sum_{row < 4 kin} F[(a, b)][row][t] in[(a >> 2, 4b) row][n].  The four
+// outputs a = 4 (a >> 2) + d, d = 0..3, with the same b read the same 4 kin
+// input rows (the four children 4b + c are adjacent pairs), so a block stages
+// the input rows of QB such quads in LDS once, for a chunk of NR right-hand
+// sides, and thread (quad, d, t) forms output row t of pair d for all NR
+// columns: per input row one factor entry (the threads t of a pair read a
+// contiguous factor row) and one broadcast LDS row.
+template <typename VT, typename FT, int NR>
+__global__ __launch_bounds__(kB2) void k2_apply_stage_quad(const VT* __restrict__ in,
+                                                          VT* __restrict__ out,
+                                                          const FT* __restrict__ blk, int L,
+                                                          int l, int kin, int kout, int kld,
+                                                          int nrhs, int qb, int nchunk) {
+  extern __shared__ __align__(16) unsigned char smem2[];
+  VT* xs = reinterpret_cast<VT*>(smem2);                      // [qb][4 kin][NR]
+  const int sh = 2 * (L - l);
+  const int64_t nquad = (int64_t)1 << (2 * L - 2);
+  const int64_t q0 = (int64_t)(blockIdx.x / nchunk) * qb;
+  const int n0 = (int)(blockIdx.x % nchunk) * NR;
+  const int nw = min(NR, nrhs - n0);
+  const int rows = 4 * kin;
+  // stage the quads' input rows (columns past the chunk are zero)
+  for (int e = threadIdx.x; e < qb * rows * NR; e += kB2) {
+    const int n = e % NR, r = (e / NR) % rows, qi = e / (NR * rows);
+    const int64_t q = q0 + qi;
+    VT v = Zero2<VT>::v();
+    if (q < nquad && n < nw) {
+      const int64_t pin0 = ((q >> sh) << (sh + 2)) + 4 * (q & (((int64_t)1 << sh) - 1));
+      v = in[(pin0 * kin + r) * nrhs + n0 + n];
+    }
+    xs[e] = v;
+  }
+  __syncthreads();
+  const int per = 4 * kout;                                   // threads a quad
+  const int qi = threadIdx.x / per, rr = threadIdx.x - qi * per;
+  const int64_t q = q0 + qi;
+  if (qi >= qb || q >= nquad) return;
+  const int d = rr / kout, t = rr - d * kout;
+  const int64_t a = ((q >> sh) << 2) + d, b = q & (((int64_t)1 << sh) - 1);
+  const int64_t pout = (a << sh) | b;
+  const FT* f = blk + pout * rows * kld + t;
+  const VT* x = xs + (size_t)qi * rows * NR;
+  VT acc[NR];
+#pragma unroll
+  for (int n = 0; n < NR; ++n) acc[n] = Zero2<VT>::v();
+  constexpr int U = 16;                                       // factor loads in flight
+  int r = 0;
+  for (; r + U <= rows; r += U) {
+    VT fv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) fv[u] = load_factor(f, (int64_t)(r + u) * kld);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int n = 0; n < NR; ++n) cfma(acc[n], fv[u], x[(r + u) * NR + n]);
+  }
+  for (; r < rows; ++r) {
+    const VT fv = load_factor(f, (int64_t)r * kld);
+#pragma unroll
+    for (int n = 0; n < NR; ++n) cfma(acc[n], fv, x[r * NR + n]);
+  }
+  VT* o = out + (pout * kout + t) * nrhs + n0;
+#pragma unroll
+  for (int n = 0; n < NR; ++n)
+    if (n < nw) o[n] = acc[n];
+}
+
 // out[(a, b)][t][n] = sum_{row < 4 kin} F[(a, b)][row][t] in[(a >> 2, 4b) row][n]
 template <typename VT, typename FT>
 __global__ void k2_apply_stage(const VT* __restrict__ in, VT* __restrict__ out,
@@ -718,25 +788,6 @@ __global__ void k2_apply_stage(const VT* __restrict__ in, VT* __restrict__ out,
   out[e] = acc;
 }
 
-// u[x][n] += sum_k Ubar[x][k] mu[(leaf(x), box)][k][n]
-template <typename VT, typename FT>
-__global__ void k2_apply_u(const VT* __restrict__ mu, const FT* __restrict__ ubar, int K,
-                           const int32_t* __restrict__ perm, const int32_t* __restrict__ leaf,
-                           int64_t n, VT* __restrict__ u, int64_t ldu, int nrhs) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * nrhs) return;
-  const int64_t i = e / nrhs;
-  const int c = (int)(e % nrhs);
-  const VT* m = mu + (int64_t)leaf[i] * K * nrhs + c;
-  VT acc = Zero2<VT>::v();
-  for (int k = 0; k < K; ++k) cfma(acc, load_factor(ubar, i * K + k), m[(int64_t)k * nrhs]);
-  VT* o = u + (int64_t)c * ldu + perm[i];
-  VT cur = *o;
-  cur.x += acc.x;
-  cur.y += acc.y;
-  *o = cur;
-}
-
 // u[x][n] = sum_j K_C[x][j] g[centre_j][n]   (writes u; runs first)
 template <typename VT, typename FT>
 __global__ void k2_apply_centre(const FT* __restrict__ kc, int nc,
@@ -751,6 +802,146 @@ __global__ void k2_apply_centre(const FT* __restrict__ kc, int nc,
   for (int j = 0; j < nc; ++j)
     cfma(acc, load_factor(kc, i * nc + j), g[(int64_t)c * ldg + cidx[j]]);
   u[(int64_t)c * ldu + i] = acc;
+}
+
+// Row-per-thread forms of the leaf and centre products: thread = one output
+// row for a chunk of NR right-hand sides (a factor entry is read once per
+// chunk, the shared operand rows come from LDS).
+
+// V for one Omega leaf b and RHS chunk: thread (a, k) forms mu[(a, b)][k][0..NR)
+// over the leaf's points; the leaf's g rows are staged in LDS, and the threads
+// of a point read its Vbar row [a][k] contiguously.
+template <typename VT, typename FT, int NR>
+__global__ __launch_bounds__(kB2) void k2_apply_v_rows(const VT* __restrict__ g, int64_t ldg,
+                                                      const int32_t* __restrict__ perm,
+                                                      const int32_t* __restrict__ off,
+                                                      const FT* __restrict__ vbar,
+                                                      VT* __restrict__ mu, int lV, int lO, int K,
+                                                      int nrhs, int smax, int nchunk) {
+  extern __shared__ __align__(16) unsigned char smem2[];
+  VT* gl = reinterpret_cast<VT*>(smem2);                      // [smax][NR]
+  const int na = 1 << (2 * lV);
+  const int64_t nb = (int64_t)1 << (2 * lO);
+  const int64_t b = blockIdx.x / nchunk;
+  const int n0 = (int)(blockIdx.x % nchunk) * NR, nw = min(NR, nrhs - n0);
+  const int32_t i0 = off[b], cnt = off[b + 1] - i0;
+  for (int e = threadIdx.x; e < cnt * NR; e += kB2) {
+    const int j = e / NR, n = e % NR;
+    gl[e] = n < nw ? g[(int64_t)(n0 + n) * ldg + perm[i0 + j]] : Zero2<VT>::v();
+  }
+  __syncthreads();
+  for (int item = threadIdx.x; item < na * K; item += kB2) {  // item = a K + k
+    VT acc[NR];
+#pragma unroll
+    for (int n = 0; n < NR; ++n) acc[n] = Zero2<VT>::v();
+    for (int j = 0; j < cnt; ++j) {
+      const VT f = load_factor(vbar, (int64_t)(i0 + j) * na * K + item);
+#pragma unroll
+      for (int n = 0; n < NR; ++n) cfma(acc[n], f, gl[j * NR + n]);
+    }
+    const int a = item / K, k = item - a * K;
+    VT* o = mu + (((int64_t)a * nb + b) * K + k) * nrhs + n0;
+#pragma unroll
+    for (int n = 0; n < NR; ++n)
+      if (n < nw) o[n] = acc[n];
+  }
+}
+
+// U: thread = one X point (sorted order), all NR columns of the chunk:
+// u[perm(i)][n] += sum_k Ubar[i][k] mu[leaf(i)][k][n].
+template <typename VT, typename FT, int NR>
+__global__ __launch_bounds__(kB2) void k2_apply_u_rows(const VT* __restrict__ mu,
+                                                      const FT* __restrict__ ubar, int K,
+                                                      const int32_t* __restrict__ perm,
+                                                      const int32_t* __restrict__ leaf, int64_t n,
+                                                      VT* __restrict__ u, int64_t ldu, int nrhs,
+                                                      int nchunk) {
+  const int64_t i = (int64_t)(blockIdx.x / nchunk) * kB2 + threadIdx.x;
+  const int n0 = (int)(blockIdx.x % nchunk) * NR, nw = min(NR, nrhs - n0);
+  if (i >= n) return;
+  const VT* m = mu + (int64_t)leaf[i] * K * nrhs + n0;
+  VT acc[NR];
+#pragma unroll
+  for (int c = 0; c < NR; ++c) acc[c] = Zero2<VT>::v();
+  // rows in batches of UB with all their loads issued before the products
+  constexpr int UB = 4;
+  int k = 0;
+  for (; k + UB <= K; k += UB) {
+    VT f[UB], mv[UB][NR];
+#pragma unroll
+    for (int b = 0; b < UB; ++b) {
+      f[b] = load_factor(ubar, i * K + k + b);
+#pragma unroll
+      for (int c = 0; c < NR; ++c) mv[b][c] = m[(int64_t)(k + b) * nrhs + min(c, nw - 1)];
+    }
+#pragma unroll
+    for (int b = 0; b < UB; ++b)
+#pragma unroll
+      for (int c = 0; c < NR; ++c) cfma(acc[c], f[b], mv[b][c]);
+  }
+  for (; k < K; ++k) {
+    const VT f = load_factor(ubar, i * K + k);
+#pragma unroll
+    for (int c = 0; c < NR; ++c) cfma(acc[c], f, m[(int64_t)k * nrhs + min(c, nw - 1)]);
+  }
+  const int64_t pi = perm[i];
+#pragma unroll
+  for (int c = 0; c < NR; ++c) {
+    if (c < nw) {
+      VT* o = u + (int64_t)(n0 + c) * ldu + pi;
+      VT cur = *o;
+      cur.x += acc[c].x;
+      cur.y += acc[c].y;
+      *o = cur;
+    }
+  }
+}
+
+// Centre: u[x][n] = sum_j K_C[x][j] g[centre_j][n] for 256 consecutive x a
+// block and NR columns.  The centre's g rows [nc][NR] sit in LDS; K_C is read
+// in tiles of JT columns staged through LDS (coalesced row segments), then
+// each thread runs its own row of the tile.
+template <typename VT, typename FT, int NR>
+__global__ __launch_bounds__(kB2) void k2_apply_centre_rows(const FT* __restrict__ kc, int nc,
+                                                           const int32_t* __restrict__ cidx,
+                                                           const VT* __restrict__ g, int64_t ldg,
+                                                           int64_t nx, VT* __restrict__ u,
+                                                           int64_t ldu, int nrhs, int nchunk) {
+  constexpr int JT = 16;
+  extern __shared__ __align__(16) unsigned char smem2[];
+  VT* gc = reinterpret_cast<VT*>(smem2);                      // [nc][NR]
+  VT* kt = gc + (size_t)nc * NR;                              // [kB2][JT + 1]
+  const int64_t x0 = (int64_t)(blockIdx.x / nchunk) * kB2;
+  const int n0 = (int)(blockIdx.x % nchunk) * NR, nw = min(NR, nrhs - n0);
+  for (int e = threadIdx.x; e < nc * NR; e += kB2) {
+    const int j = e / NR, n = e % NR;
+    gc[e] = n < nw ? g[(int64_t)(n0 + n) * ldg + cidx[j]] : Zero2<VT>::v();
+  }
+  VT acc[NR];
+#pragma unroll
+  for (int n = 0; n < NR; ++n) acc[n] = Zero2<VT>::v();
+  const int64_t xi = x0 + threadIdx.x;
+  for (int j0 = 0; j0 < nc; j0 += JT) {
+    __syncthreads();                                          // previous tile consumed
+    for (int e = threadIdx.x; e < kB2 * JT; e += kB2) {
+      const int r = e / JT, c = e % JT;
+      const int64_t x = x0 + r;
+      kt[r * (JT + 1) + c] = (x < nx && j0 + c < nc) ? load_factor(kc, x * nc + j0 + c)
+                                                     : Zero2<VT>::v();
+    }
+    __syncthreads();
+    const int jn = min(JT, nc - j0);
+    for (int c = 0; c < jn; ++c) {
+      const VT f = kt[threadIdx.x * (JT + 1) + c];
+#pragma unroll
+      for (int n = 0; n < NR; ++n) cfma(acc[n], f, gc[(j0 + c) * NR + n]);
+    }
+  }
+  if (xi < nx) {
+#pragma unroll
+    for (int n = 0; n < NR; ++n)
+      if (n < nw) u[(int64_t)(n0 + n) * ldu + xi] = acc[n];
+  }
 }
 
 inline unsigned nblk(int64_t total) { return (unsigned)((total + kB2 - 1) / kB2); }
@@ -1012,29 +1203,67 @@ int apply2d_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, in
   VT* w[2] = {(VT*)M.d_work[0], (VT*)M.d_work[1]};
   const int nc = (int)M.centre.size();
   // the centre block writes every entry of u; the boxes then accumulate
-  hipLaunchKernelGGL((k2_apply_centre<VT, FT>), dim3(nblk(M.nx * nrhs)), dim3(kB2), 0, s,
-                     (const FT*)M.d_kc, nc, M.d_cidx, (const VT*)g, ldg, M.nx, (VT*)u, ldu, nrhs);
-  IBF_HIP_CHECK(hipGetLastError());
+  constexpr int NR = 8;                                       // RHS columns a pass
+  const int nchunk = (nrhs + NR - 1) / NR;
+  {
+    const size_t lds = ((size_t)nc * NR + (size_t)kB2 * 17) * sizeof(VT);
+    if (lds <= 64 * 1024) {
+      hipLaunchKernelGGL((k2_apply_centre_rows<VT, FT, NR>),
+                         dim3((unsigned)((M.nx + kB2 - 1) / kB2 * nchunk)), dim3(kB2), lds, s,
+                         (const FT*)M.d_kc, nc, M.d_cidx, (const VT*)g, ldg, M.nx, (VT*)u, ldu,
+                         nrhs, nchunk);
+    } else {
+      hipLaunchKernelGGL((k2_apply_centre<VT, FT>), dim3(nblk(M.nx * nrhs)), dim3(kB2), 0, s,
+                         (const FT*)M.d_kc, nc, M.d_cidx, (const VT*)g, ldg, M.nx, (VT*)u, ldu,
+                         nrhs);
+    }
+    IBF_HIP_CHECK(hipGetLastError());
+  }
   for (const Box2& bx : M.boxes) {
     const int lO = bx.L - bx.lV;
     const int64_t npv = ((int64_t)1 << (2 * bx.lV)) * ((int64_t)1 << (2 * lO));
-    hipLaunchKernelGGL((k2_apply_v<VT, FT>), dim3(nblk(npv * bx.K_V * nrhs)), dim3(kB2), 0, s,
-                       (const VT*)g, ldg, bx.d_perm_xi, bx.d_xioff, (const FT*)bx.d_vbar, w[0],
-                       bx.lV, lO, bx.K_V, nrhs);
-    IBF_HIP_CHECK(hipGetLastError());
+    {
+      const size_t lds = (size_t)bx.smax_xi * NR * sizeof(VT);
+      if (lds <= 64 * 1024) {
+        const int64_t nleafb = (int64_t)1 << (2 * lO);
+        hipLaunchKernelGGL((k2_apply_v_rows<VT, FT, NR>), dim3((unsigned)(nleafb * nchunk)),
+                           dim3(kB2), lds, s, (const VT*)g, ldg, bx.d_perm_xi, bx.d_xioff,
+                           (const FT*)bx.d_vbar, w[0], bx.lV, lO, bx.K_V, nrhs, bx.smax_xi,
+                           nchunk);
+      } else {
+        hipLaunchKernelGGL((k2_apply_v<VT, FT>), dim3(nblk(npv * bx.K_V * nrhs)), dim3(kB2), 0,
+                           s, (const VT*)g, ldg, bx.d_perm_xi, bx.d_xioff, (const FT*)bx.d_vbar,
+                           w[0], bx.lV, lO, bx.K_V, nrhs);
+      }
+      IBF_HIP_CHECK(hipGetLastError());
+    }
     int cur = 0;
     for (const Stage2& st : bx.stages) {
-      const int64_t np = (int64_t)1 << (2 * bx.L);
-      hipLaunchKernelGGL((k2_apply_stage<VT, FT>), dim3(nblk(np * st.kout * nrhs)), dim3(kB2),
-                         0, s, w[cur], w[cur ^ 1], (const FT*)st.blk, bx.L, st.level, st.kin,
-                         st.kout, st.kld, nrhs);
+      const int64_t nquad = (int64_t)1 << (2 * bx.L - 2);
+      // quads a block: threads (4 kout each) and staged rows (<= 48 KB)
+      const int qb = std::max(1, std::min(kB2 / (4 * st.kout),
+                                          (int)((48 * 1024) / ((size_t)4 * st.kin * NR *
+                                                               sizeof(VT)))));
+      const size_t lds = (size_t)qb * 4 * st.kin * NR * sizeof(VT);
+      const int64_t nb = (nquad + qb - 1) / qb * nchunk;
+      if (4 * st.kout <= kB2 && lds <= 64 * 1024 && nb < 0x7fffffff) {
+        hipLaunchKernelGGL((k2_apply_stage_quad<VT, FT, NR>), dim3((unsigned)nb), dim3(kB2),
+                           lds, s, w[cur], w[cur ^ 1], (const FT*)st.blk, bx.L, st.level,
+                           st.kin, st.kout, st.kld, nrhs, qb, nchunk);
+      } else {
+        const int64_t np = (int64_t)1 << (2 * bx.L);
+        hipLaunchKernelGGL((k2_apply_stage<VT, FT>), dim3(nblk(np * st.kout * nrhs)), dim3(kB2),
+                           0, s, w[cur], w[cur ^ 1], (const FT*)st.blk, bx.L, st.level, st.kin,
+                           st.kout, st.kld, nrhs);
+      }
       IBF_HIP_CHECK(hipGetLastError());
       cur ^= 1;
     }
     const XTree2& xt = M.xtrees[bx.xt];
-    hipLaunchKernelGGL((k2_apply_u<VT, FT>), dim3(nblk(M.nx * nrhs)), dim3(kB2), 0, s, w[cur],
+    hipLaunchKernelGGL((k2_apply_u_rows<VT, FT, NR>),
+                       dim3((unsigned)((M.nx + kB2 - 1) / kB2 * nchunk)), dim3(kB2), 0, s, w[cur],
                        (const FT*)bx.d_ubar, bx.K_U, xt.d_perm, xt.d_leaf, M.nx, (VT*)u, ldu,
-                       nrhs);
+                       nrhs, nchunk);
     IBF_HIP_CHECK(hipGetLastError());
   }
   return IBF_OK;
@@ -1253,6 +1482,9 @@ int build2d(ibf_plan_t p, hipStream_t s) {
     if ((rc = upload(&bx.d_perm_xi, cperm.data(), cperm.size()))) return rc;
     if ((rc = upload(&bx.d_xileaf, bin.data(), bin.size()))) return rc;
     if ((rc = upload(&bx.d_xioff, off.data(), off.size()))) return rc;
+    bx.smax_xi = 0;
+    for (size_t b = 0; b + 1 < off.size(); ++b)
+      bx.smax_xi = std::max<int>(bx.smax_xi, off[b + 1] - off[b]);
   }
   M.nnz_opt = M.nnz_stored = M.factor_bytes = 0;
   switch (M.precision) {
