@@ -82,8 +82,13 @@ struct Mibf2D {
   void* d_kc = nullptr;        // [x][centre point] kernel values, storage precision
   double* d_z = nullptr;       // Chebyshev nodes [r]
   double* d_lc = nullptr;      // [4][R2][R2] child -> parent Lagrange matrices
-  void* d_work[2] = {nullptr, nullptr};
+  void* d_work = nullptr;      // per box two coefficient buffers (apply)
   size_t work_bytes = 0;
+  // the boxes' V and stage launches run on worker streams forked from the
+  // caller's stream; their U launches accumulate into u in box order
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> ev_u;  // per box: its U launch done
+  hipEvent_t ev_start = nullptr;
   bool built = false;
   int64_t nnz_prelim = 0, nnz_opt = 0, nnz_stored = 0, factor_bytes = 0;
   int maxL = 0;
@@ -1184,23 +1189,35 @@ template <typename VT, typename FT>
 int apply2d_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int nrhs,
               hipStream_t s) {
   Mibf2D& M = *p->mibf;
-  size_t need = 0;
-  for (const Box2& bx : M.boxes) {
+  const int nbox = (int)M.boxes.size();
+  // one pair of coefficient buffers per box (boxes run concurrently)
+  std::vector<size_t> off(nbox + 1, 0);
+  for (int i = 0; i < nbox; ++i) {
+    const Box2& bx = M.boxes[i];
     int kmx = 1;
     for (int k : bx.rank) kmx = std::max(kmx, k);
-    need = std::max(need, ((size_t)1 << (2 * bx.L)) * kmx * nrhs * sizeof(VT));
+    const size_t one = ((((size_t)1 << (2 * bx.L)) * kmx * nrhs * sizeof(VT)) + 255) & ~(size_t)255;
+    off[i + 1] = off[i] + 2 * one;
   }
-  if (need > M.work_bytes) {
-    for (int i = 0; i < 2; ++i) {
-      if (M.d_work[i]) (void)hipFree(M.d_work[i]);
-      M.d_work[i] = nullptr;
-    }
+  if (off[nbox] > M.work_bytes) {
+    if (M.d_work) IBF_HIP_CHECK(hipFree(M.d_work));
+    M.d_work = nullptr;
     M.work_bytes = 0;
-    IBF_HIP_CHECK(hipMalloc(&M.d_work[0], need));
-    IBF_HIP_CHECK(hipMalloc(&M.d_work[1], need));
-    M.work_bytes = need;
+    IBF_HIP_CHECK(hipMalloc(&M.d_work, off[nbox]));
+    M.work_bytes = off[nbox];
   }
-  VT* w[2] = {(VT*)M.d_work[0], (VT*)M.d_work[1]};
+  if (M.streams.empty() && nbox > 0) {
+    constexpr int kStreams = 8;
+    for (int i = 0; i < std::min(kStreams, nbox); ++i) {
+      hipStream_t st = nullptr;
+      IBF_HIP_CHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      M.streams.push_back(st);
+    }
+    IBF_HIP_CHECK(hipEventCreateWithFlags(&M.ev_start, hipEventDisableTiming));
+    M.ev_u.assign(nbox, nullptr);
+    for (int i = 0; i < nbox; ++i)
+      IBF_HIP_CHECK(hipEventCreateWithFlags(&M.ev_u[i], hipEventDisableTiming));
+  }
   const int nc = (int)M.centre.size();
   // the centre block writes every entry of u; the boxes then accumulate
   constexpr int NR = 8;                                       // RHS columns a pass
@@ -1219,7 +1236,13 @@ int apply2d_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, in
     }
     IBF_HIP_CHECK(hipGetLastError());
   }
-  for (const Box2& bx : M.boxes) {
+  if (nbox) IBF_HIP_CHECK(hipEventRecord(M.ev_start, s));
+  for (int ib = 0; ib < nbox; ++ib) {
+    const Box2& bx = M.boxes[ib];
+    hipStream_t bs = M.streams[ib % M.streams.size()];
+    IBF_HIP_CHECK(hipStreamWaitEvent(bs, M.ev_start, 0));
+    char* wb = static_cast<char*>(M.d_work) + off[ib];
+    VT* w[2] = {reinterpret_cast<VT*>(wb), reinterpret_cast<VT*>(wb + (off[ib + 1] - off[ib]) / 2)};
     const int lO = bx.L - bx.lV;
     const int64_t npv = ((int64_t)1 << (2 * bx.lV)) * ((int64_t)1 << (2 * lO));
     {
@@ -1227,12 +1250,12 @@ int apply2d_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, in
       if (lds <= 64 * 1024) {
         const int64_t nleafb = (int64_t)1 << (2 * lO);
         hipLaunchKernelGGL((k2_apply_v_rows<VT, FT, NR>), dim3((unsigned)(nleafb * nchunk)),
-                           dim3(kB2), lds, s, (const VT*)g, ldg, bx.d_perm_xi, bx.d_xioff,
+                           dim3(kB2), lds, bs, (const VT*)g, ldg, bx.d_perm_xi, bx.d_xioff,
                            (const FT*)bx.d_vbar, w[0], bx.lV, lO, bx.K_V, nrhs, bx.smax_xi,
                            nchunk);
       } else {
         hipLaunchKernelGGL((k2_apply_v<VT, FT>), dim3(nblk(npv * bx.K_V * nrhs)), dim3(kB2), 0,
-                           s, (const VT*)g, ldg, bx.d_perm_xi, bx.d_xioff, (const FT*)bx.d_vbar,
+                           bs, (const VT*)g, ldg, bx.d_perm_xi, bx.d_xioff, (const FT*)bx.d_vbar,
                            w[0], bx.lV, lO, bx.K_V, nrhs);
       }
       IBF_HIP_CHECK(hipGetLastError());
@@ -1248,24 +1271,29 @@ int apply2d_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, in
       const int64_t nb = (nquad + qb - 1) / qb * nchunk;
       if (4 * st.kout <= kB2 && lds <= 64 * 1024 && nb < 0x7fffffff) {
         hipLaunchKernelGGL((k2_apply_stage_quad<VT, FT, NR>), dim3((unsigned)nb), dim3(kB2),
-                           lds, s, w[cur], w[cur ^ 1], (const FT*)st.blk, bx.L, st.level,
+                           lds, bs, w[cur], w[cur ^ 1], (const FT*)st.blk, bx.L, st.level,
                            st.kin, st.kout, st.kld, nrhs, qb, nchunk);
       } else {
         const int64_t np = (int64_t)1 << (2 * bx.L);
         hipLaunchKernelGGL((k2_apply_stage<VT, FT>), dim3(nblk(np * st.kout * nrhs)), dim3(kB2),
-                           0, s, w[cur], w[cur ^ 1], (const FT*)st.blk, bx.L, st.level, st.kin,
+                           0, bs, w[cur], w[cur ^ 1], (const FT*)st.blk, bx.L, st.level, st.kin,
                            st.kout, st.kld, nrhs);
       }
       IBF_HIP_CHECK(hipGetLastError());
       cur ^= 1;
     }
     const XTree2& xt = M.xtrees[bx.xt];
+    // u accumulates box by box: this box's U waits for the previous one's
+    if (ib > 0) IBF_HIP_CHECK(hipStreamWaitEvent(bs, M.ev_u[ib - 1], 0));
     hipLaunchKernelGGL((k2_apply_u_rows<VT, FT, NR>),
-                       dim3((unsigned)((M.nx + kB2 - 1) / kB2 * nchunk)), dim3(kB2), 0, s, w[cur],
+                       dim3((unsigned)((M.nx + kB2 - 1) / kB2 * nchunk)), dim3(kB2), 0, bs, w[cur],
                        (const FT*)bx.d_ubar, bx.K_U, xt.d_perm, xt.d_leaf, M.nx, (VT*)u, ldu,
                        nrhs, nchunk);
     IBF_HIP_CHECK(hipGetLastError());
+    IBF_HIP_CHECK(hipEventRecord(M.ev_u[ib], bs));
   }
+  // join: the caller's stream continues after the last box's U
+  if (nbox) IBF_HIP_CHECK(hipStreamWaitEvent(s, M.ev_u[nbox - 1], 0));
   return IBF_OK;
 }
 
@@ -1544,13 +1572,18 @@ void free2d_factors(ibf_plan_t p) {
   fr(M.d_kc);
   fr(M.d_z);
   fr(M.d_lc);
-  fr(M.d_work[0]);
-  fr(M.d_work[1]);
+  fr(M.d_work);
+  for (hipStream_t st : M.streams) (void)hipStreamDestroy(st);
+  M.streams.clear();
+  for (hipEvent_t e : M.ev_u) (void)hipEventDestroy(e);
+  M.ev_u.clear();
+  if (M.ev_start) (void)hipEventDestroy(M.ev_start);
+  M.ev_start = nullptr;
   M.d_x = nullptr;
   M.d_cidx = nullptr;
   M.d_kc = nullptr;
   M.d_z = M.d_lc = nullptr;
-  M.d_work[0] = M.d_work[1] = nullptr;
+  M.d_work = nullptr;
   M.work_bytes = 0;
   M.built = false;
   p->built = false;
@@ -1559,7 +1592,7 @@ void free2d_factors(ibf_plan_t p) {
 void destroy2d(ibf_plan_t p) {
   if (!p->mibf) return;
   const Mibf2D& M = *p->mibf;
-  bool touched = M.d_x || M.d_z || M.d_kc || M.d_work[0] || !M.xtrees.empty();
+  bool touched = M.d_x || M.d_z || M.d_kc || M.d_work || !M.xtrees.empty();
   for (const Box2& bx : M.boxes) touched = touched || bx.d_xis || bx.d_vbar;
   if (touched) {                       // a plan that never reached the device makes no HIP call
     int cur = 0;
