@@ -23,8 +23,9 @@
 // matrices), k2_middle (eq:KeqUMV), k2_sweep_g (eqn:GC), k2_sweep_h (eqn:HR),
 // k2_pack_stage, k2_vbar (eqn:V0), k2_ubar, k2_centre; apply (a thread per
 // output row and chunk of right-hand sides): k2_apply_v_rows,
-// k2_apply_stage_quad, k2_apply_u_rows, k2_apply_centre_rows (k2_apply_v,
-// k2_apply_stage, k2_apply_centre when the staged rows exceed LDS).
+// k2_apply_stage_quad, k2_apply_u_tree (the boxes of one X tree together),
+// k2_apply_centre_rows (k2_apply_v, k2_apply_stage, k2_apply_centre when the
+// staged rows exceed LDS).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -87,7 +88,7 @@ struct Mibf2D {
   // the boxes' V and stage launches run on worker streams forked from the
   // caller's stream; their U launches accumulate into u in box order
   std::vector<hipStream_t> streams;
-  std::vector<hipEvent_t> ev_u;  // per box: its U launch done
+  std::vector<hipEvent_t> ev_u;  // per box: its stages done
   hipEvent_t ev_start = nullptr;
   bool built = false;
   int64_t nnz_prelim = 0, nnz_opt = 0, nnz_stored = 0, factor_bytes = 0;
@@ -852,42 +853,54 @@ __global__ __launch_bounds__(kB2) void k2_apply_v_rows(const VT* __restrict__ g,
   }
 }
 
-// U: thread = one X point (sorted order), all NR columns of the chunk:
-// u[perm(i)][n] += sum_k Ubar[i][k] mu[leaf(i)][k][n].
+// U of the boxes that share one X tree, in one launch: thread = one X point
+// (the tree's sorted order), all NR columns of the chunk:
+//   u[perm(i)][n] += sum_boxes sum_k Ubar_box[i][k] mu_box[leaf(i)][k][n]
+// (the boxes in the order given, then one read-modify-write of u).
+constexpr int kTreeBoxes = 16;
+struct UTree {
+  const void* mu[kTreeBoxes];
+  const void* ubar[kTreeBoxes];
+  int K[kTreeBoxes];
+  int nb;
+};
 template <typename VT, typename FT, int NR>
-__global__ __launch_bounds__(kB2) void k2_apply_u_rows(const VT* __restrict__ mu,
-                                                      const FT* __restrict__ ubar, int K,
-                                                      const int32_t* __restrict__ perm,
+__global__ __launch_bounds__(kB2) void k2_apply_u_tree(UTree T, const int32_t* __restrict__ perm,
                                                       const int32_t* __restrict__ leaf, int64_t n,
                                                       VT* __restrict__ u, int64_t ldu, int nrhs,
                                                       int nchunk) {
   const int64_t i = (int64_t)(blockIdx.x / nchunk) * kB2 + threadIdx.x;
   const int n0 = (int)(blockIdx.x % nchunk) * NR, nw = min(NR, nrhs - n0);
   if (i >= n) return;
-  const VT* m = mu + (int64_t)leaf[i] * K * nrhs + n0;
+  const int64_t li = leaf[i];
   VT acc[NR];
 #pragma unroll
   for (int c = 0; c < NR; ++c) acc[c] = Zero2<VT>::v();
-  // rows in batches of UB with all their loads issued before the products
-  constexpr int UB = 4;
-  int k = 0;
-  for (; k + UB <= K; k += UB) {
-    VT f[UB], mv[UB][NR];
+  for (int bx = 0; bx < T.nb; ++bx) {
+    const int K = T.K[bx];
+    const VT* m = reinterpret_cast<const VT*>(T.mu[bx]) + li * K * nrhs + n0;
+    const FT* ub = reinterpret_cast<const FT*>(T.ubar[bx]);
+    // rows in batches of UB with all their loads issued before the products
+    constexpr int UB = 4;
+    int k = 0;
+    for (; k + UB <= K; k += UB) {
+      VT f[UB], mv[UB][NR];
 #pragma unroll
-    for (int b = 0; b < UB; ++b) {
-      f[b] = load_factor(ubar, i * K + k + b);
+      for (int b = 0; b < UB; ++b) {
+        f[b] = load_factor(ub, i * K + k + b);
 #pragma unroll
-      for (int c = 0; c < NR; ++c) mv[b][c] = m[(int64_t)(k + b) * nrhs + min(c, nw - 1)];
+        for (int c = 0; c < NR; ++c) mv[b][c] = m[(int64_t)(k + b) * nrhs + min(c, nw - 1)];
+      }
+#pragma unroll
+      for (int b = 0; b < UB; ++b)
+#pragma unroll
+        for (int c = 0; c < NR; ++c) cfma(acc[c], f[b], mv[b][c]);
     }
+    for (; k < K; ++k) {
+      const VT f = load_factor(ub, i * K + k);
 #pragma unroll
-    for (int b = 0; b < UB; ++b)
-#pragma unroll
-      for (int c = 0; c < NR; ++c) cfma(acc[c], f[b], mv[b][c]);
-  }
-  for (; k < K; ++k) {
-    const VT f = load_factor(ubar, i * K + k);
-#pragma unroll
-    for (int c = 0; c < NR; ++c) cfma(acc[c], f, m[(int64_t)k * nrhs + min(c, nw - 1)]);
+      for (int c = 0; c < NR; ++c) cfma(acc[c], f, m[(int64_t)k * nrhs + min(c, nw - 1)]);
+    }
   }
   const int64_t pi = perm[i];
 #pragma unroll
@@ -1237,6 +1250,7 @@ int apply2d_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, in
     IBF_HIP_CHECK(hipGetLastError());
   }
   if (nbox) IBF_HIP_CHECK(hipEventRecord(M.ev_start, s));
+  std::vector<const void*> mu_final(nbox, nullptr);
   for (int ib = 0; ib < nbox; ++ib) {
     const Box2& bx = M.boxes[ib];
     hipStream_t bs = M.streams[ib % M.streams.size()];
@@ -1282,18 +1296,39 @@ int apply2d_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, in
       IBF_HIP_CHECK(hipGetLastError());
       cur ^= 1;
     }
-    const XTree2& xt = M.xtrees[bx.xt];
-    // u accumulates box by box: this box's U waits for the previous one's
-    if (ib > 0) IBF_HIP_CHECK(hipStreamWaitEvent(bs, M.ev_u[ib - 1], 0));
-    hipLaunchKernelGGL((k2_apply_u_rows<VT, FT, NR>),
-                       dim3((unsigned)((M.nx + kB2 - 1) / kB2 * nchunk)), dim3(kB2), 0, bs, w[cur],
-                       (const FT*)bx.d_ubar, bx.K_U, xt.d_perm, xt.d_leaf, M.nx, (VT*)u, ldu,
-                       nrhs, nchunk);
-    IBF_HIP_CHECK(hipGetLastError());
+    mu_final[ib] = w[cur];
     IBF_HIP_CHECK(hipEventRecord(M.ev_u[ib], bs));
   }
-  // join: the caller's stream continues after the last box's U
-  if (nbox) IBF_HIP_CHECK(hipStreamWaitEvent(s, M.ev_u[nbox - 1], 0));
+  // U on the caller's stream, one launch per X tree (at most kTreeBoxes boxes
+  // a launch), each after its boxes' stages: u accumulates in tree order,
+  // then box order, and the caller's stream continues after the last one
+  for (int t = 0; t < (int)M.xtrees.size(); ++t) {
+    const XTree2& xt = M.xtrees[t];
+    UTree T{};
+    auto flush = [&]() -> int {
+      if (!T.nb) return IBF_OK;
+      hipLaunchKernelGGL((k2_apply_u_tree<VT, FT, NR>),
+                         dim3((unsigned)((M.nx + kB2 - 1) / kB2 * nchunk)), dim3(kB2), 0, s, T,
+                         xt.d_perm, xt.d_leaf, M.nx, (VT*)u, ldu, nrhs, nchunk);
+      IBF_HIP_CHECK(hipGetLastError());
+      T.nb = 0;
+      return IBF_OK;
+    };
+    for (int ib = 0; ib < nbox; ++ib) {
+      const Box2& bx = M.boxes[ib];
+      if (bx.xt != t) continue;
+      IBF_HIP_CHECK(hipStreamWaitEvent(s, M.ev_u[ib], 0));
+      T.mu[T.nb] = mu_final[ib];
+      T.ubar[T.nb] = bx.d_ubar;
+      T.K[T.nb] = bx.K_U;
+      if (++T.nb == kTreeBoxes) {
+        int rc;
+        if ((rc = flush())) return rc;
+      }
+    }
+    int rc;
+    if ((rc = flush())) return rc;
+  }
   return IBF_OK;
 }
 
