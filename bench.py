@@ -171,6 +171,15 @@ def _bench_batched(args):
     qs = [pl.query() for pl in plans]
     gs = [torch.from_numpy(np.ascontiguousarray(P.g.T)).to(torch.complex64).cuda() for P in probs]
     us = [torch.empty((P.nrhs, P.n), dtype=torch.complex64, device="cuda") for P in probs]
+    tune_info = None
+    if not args.no_tune:     # schedule autotuner per plan, before the timed region
+        t0 = time.perf_counter()
+        picks = [pl.tune(g, u) for pl, g, u in zip(plans, gs, us)]
+        torch.cuda.synchronize()
+        kinds = [f"{t['path']}/{t['chunk']}/{t['max_fused']}" for t in picks]
+        tune_info = {"tune_s": round(time.perf_counter() - t0, 3),
+                     "choices": {k: kinds.count(k) for k in sorted(set(kinds))}}
+        print(f"[bench] tuning: {tune_info}", file=sys.stderr, flush=True)
     B = ibf.Batch(plans)
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
@@ -210,6 +219,8 @@ def _bench_batched(args):
     }
     if pred_info:
         out["predictor"] = pred_info
+    if tune_info:
+        out["tuning"] = tune_info
     if not args.no_accuracy:
         worst = 0.0
         for P, u in zip(probs, us):
@@ -333,6 +344,11 @@ def main():
     ap.add_argument("--nrhs", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the schedule autotuner (apply with the default rule)")
+    ap.add_argument("--schedule", default=None, metavar="PATH/CHUNK/MAX_FUSED",
+                    help="install this apply schedule instead of tuning (e.g. mfma/32/3; "
+                         "fixes the launches for profiling)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 256 MiB elementwise copy first (HBM counter calibration)")
     ap.add_argument("--batch-count", type=int, default=256)
@@ -379,6 +395,15 @@ def main():
         torch.mul(a, 1.0, out=b)          # reads 256 MiB, writes 256 MiB
         torch.cuda.synchronize()
         del a, b
+    tuning = None
+    if args.schedule:        # a fixed schedule: no trial launches in a profile
+        path, chunk, fused = args.schedule.split("/")
+        pl.set_tuning(P.nrhs, path, int(chunk), int(fused))
+        tuning = {"path": path, "chunk": int(chunk), "max_fused": int(fused), "fixed": True}
+    elif not args.no_tune:   # schedule autotuner, before the timed region
+        tuning = pl.tune(g, u)
+        torch.cuda.synchronize()
+        print(f"[bench] tuning: {tuning}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         pl.apply(g, u)
     torch.cuda.synchronize()
@@ -401,8 +426,8 @@ def main():
         bound, peak = ("hbm", HBM_PEAK_GBS) if P.nrhs < 8 else ("mfma", FP64_PEAK_TFS)
     elif P.precision == I.PREC_FP32:
         bound, peak = ("mfma", FP32_PEAK_TFS) if P.nrhs >= 32 else ("hbm", HBM_PEAK_GBS)
-    else:
-        bound, peak = ("hbm", HBM_PEAK_GBS) if P.nrhs < 64 else ("mfma", BF16_PEAK_TFS)
+    else:   # BF16X2 factors are widened to FP32 and multiplied on FP32 MFMA
+        bound, peak = ("hbm", HBM_PEAK_GBS) if P.nrhs < 64 else ("mfma", FP32_PEAK_TFS)
     unit = "TFLOP/s" if bound == "mfma" else "GB/s"
     dom, roof, per_class = _roofline(launches, bound, peak, unit)
     roof["traffic"] = _measured_traffic(P.name, dom)
@@ -426,6 +451,7 @@ def main():
                    "leaf": P.leaf, "phase": P.phase, "parallelism": "single-gpu"},
         "build_ms": round(q["build_ms"], 3),
         "build_wall_ms": round(build_wall_ms, 3),
+        "tuning": tuning,
         "ranks": q["rank"],
         "R_comp": round(q["R_comp"], 4),
         "nnz_opt": q["nnz_opt"],

@@ -156,6 +156,42 @@ int ibf_apply_profile(ibf_plan_t plan, const void* g, int64_t ldg, void* u,
                       int64_t ldu, int64_t nrhs, void* hip_stream,
                       ibf_profile* prof);
 
+/*
+ * Schedule autotuner for the apply (the product of Sec. 4, eqn:IBFout /
+ * eqn:IBFin, unchanged; only how its stages are grouped into launches
+ * changes).  Times every candidate schedule of a 1-D plan for `nrhs`
+ * right-hand sides on the caller's vectors (same arguments and layout as
+ * ibf_apply; u is overwritten with the product) and keeps the fastest in the
+ * plan: later ibf_apply calls with this nrhs, and batches containing the plan,
+ * use it.  Candidates: the default rule; butterfly stages on the vector
+ * kernels; on MFMA (FP32 state) with 32- or 16-column RHS chunks; at most 2 or
+ * 3 stages fused per launch.  Every candidate computes the same product (to
+ * FP32 rounding).  Synchronises the stream (not for use under graph capture).
+ * *best receives the chosen schedule and its time, *dflt the default rule's
+ * time (either may be NULL).
+ * Errors: as ibf_apply; UNSUPPORTED for dim-2 plans.
+ */
+typedef struct {
+  int path;        /* 0 default rule, 1 vector stage kernels, 2 MFMA stage kernels */
+  int chunk;       /* MFMA RHS chunk width (32 or 16; 0 = by nrhs) */
+  int max_fused;   /* most stages fused per launch (0 = as LDS allows) */
+  float ms;        /* measured time of one apply */
+} ibf_tuning;
+int ibf_tune(ibf_plan_t plan, const void* g, int64_t ldg, void* u, int64_t ldu,
+             int64_t nrhs, void* hip_stream, ibf_tuning* best, ibf_tuning* dflt);
+
+/*
+ * Installs a schedule for applies with `nrhs` right-hand sides without
+ * timing anything (a choice saved from an earlier ibf_tune, or a fixed
+ * schedule for profiling); t == NULL returns that nrhs to the default rule.
+ * t->ms is ignored.  Same product as ibf_apply (Sec. 4).  Host only: no
+ * device call, no allocation.
+ * Errors: INVALID_ARG (NULL plan, nrhs < 1, path outside 0..2, chunk not 0,
+ * 16 or 32, max_fused < 0); UNSUPPORTED for dim-2 plans and for path 2 on
+ * FP64 plans (no FP64 MFMA stage kernel).
+ */
+int ibf_set_tuning(ibf_plan_t plan, int64_t nrhs, const ibf_tuning* t);
+
 /* Sizes, ranks and build time of a plan.  Errors: INVALID_ARG. */
 int ibf_query(ibf_plan_t plan, ibf_info* info);
 

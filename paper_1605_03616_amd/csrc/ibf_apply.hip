@@ -1148,12 +1148,25 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
   int lmax = 0, rc;
   if ((rc = lds_limit(p->device, &lmax))) return rc;
   const size_t budget_mfma = std::min<size_t>(kLdsBudgetMfma, (size_t)lmax);
-  // FP32-state stages with more than 8 RHS run on MFMA with 32-column chunks
-  // (more than 16 RHS) or 16-column chunks; otherwise the vector kernels take
-  // chunks of up to 32 columns.  The V and U leaf products use MFMA from 32 RHS.
-  const bool mfma = sizeof(VT) == 8 && nrhs > 8;
+  // Default rule: FP32-state stages with more than 8 RHS run on MFMA with
+  // 32-column chunks (more than 16 RHS) or 16-column chunks; otherwise the
+  // vector kernels take chunks of up to 32 columns.  A tuned schedule for this
+  // nrhs (ibf_tune), or the candidate under trial, overrides the path, the
+  // chunk width and the fusion depth.  The V and U leaf products use MFMA
+  // from 32 RHS.
+  Tuning tn{};
+  if (p->trial_on) {
+    tn = p->trial;
+  } else {
+    const auto it = p->tuned.find(nrhs);
+    if (it != p->tuned.end()) tn = it->second;
+  }
+  bool mfma = sizeof(VT) == 8 && nrhs > 8;
+  if (sizeof(VT) == 8 && tn.path == 1) mfma = false;
+  if (sizeof(VT) == 8 && tn.path == 2) mfma = true;
   const bool mfma_vu = sizeof(VT) == 8 && nrhs >= 32;
-  const int NB = mfma ? (nrhs > 16 ? 32 : 16) : std::min(nrhs, 32);
+  const int NB = mfma ? (tn.chunk == 16 || tn.chunk == 32 ? tn.chunk : (nrhs > 16 ? 32 : 16))
+                      : std::min(nrhs, 32);
   const int NV = kBlock / NB;                                 // MFMA virtual slots a block
   const int LNV = NV == 8 ? 3 : 4;
   const int nchunk = (nrhs + NB - 1) / NB;
@@ -1230,6 +1243,7 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
         if (l + next - 1 > hi) break;
         if (next > kMaxR - 1) break;
         if (next > L - l + 1) break;                          // group must fit the b bits
+        if (tn.max_fused > 0 && next > tn.max_fused) break;
         int km = mid_here ? p->k_mid_h : 1;
         for (int j = 0; j <= next; ++j) km = std::max(km, rank_at(l - 1 + j, gside));
         // MFMA: at most NV slots a block; vector: at most 4 outputs per thread and stage
@@ -1735,9 +1749,120 @@ int apply_plan(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, i
   }
 }
 
+// Time every candidate schedule for nrhs right-hand sides (one warm-up apply,
+// then the mean of three) and keep the fastest for later applies.
+int tune_plan(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int64_t nrhs,
+              hipStream_t s, ibf_tuning* best, ibf_tuning* dflt) {
+  IBF_HIP_CHECK(hipSetDevice(p->device));
+  std::vector<Tuning> cand;
+  cand.push_back(Tuning{0, 0, 0});                            // the default rule first
+  cand.push_back(Tuning{1, 0, 0});
+  cand.push_back(Tuning{1, 0, 2});
+  if (p->precision != IBF_FP64) {
+    const int chunks[2] = {32, 16};
+    for (int c : chunks) {
+      if (c == 32 && nrhs <= 16) continue;                    // half-empty 32-column chunks
+      cand.push_back(Tuning{2, c, 0});
+      cand.push_back(Tuning{2, c, 3});
+      cand.push_back(Tuning{2, c, 2});
+    }
+  }
+  // the plan leaves trial mode and the events are released on every exit
+  struct Guard {
+    ibf_plan_t p;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Guard() {
+      p->trial_on = false;
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  } gd{p};
+  IBF_HIP_CHECK(hipEventCreate(&gd.e0));
+  IBF_HIP_CHECK(hipEventCreate(&gd.e1));
+  hipEvent_t e0 = gd.e0, e1 = gd.e1;
+  int rc = IBF_OK, ibest = -1;
+  float tbest = 0, tdef = 0;
+  constexpr int kReps = 3;
+  for (size_t i = 0; i < cand.size() && rc == IBF_OK; ++i) {
+    p->trial = cand[i];
+    p->trial_on = true;
+    int r = apply_plan(p, g, ldg, u, ldu, nrhs, s);           // warm-up (and workspace)
+    if (r == IBF_OK) IBF_HIP_CHECK(hipEventRecord(e0, s));
+    for (int k = 0; k < kReps && r == IBF_OK; ++k) r = apply_plan(p, g, ldg, u, ldu, nrhs, s);
+    if (r == IBF_OK) {
+      IBF_HIP_CHECK(hipEventRecord(e1, s));
+      IBF_HIP_CHECK(hipEventSynchronize(e1));
+      float ms = 0;
+      IBF_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+      ms /= kReps;
+      if (i == 0) tdef = ms;
+      if (ibest < 0 || ms < tbest) {
+        ibest = (int)i;
+        tbest = ms;
+      }
+    } else if (i == 0) {
+      rc = r;                                                 // the default rule must run
+    }
+  }
+  p->trial_on = false;
+  if (rc != IBF_OK) return rc;
+  p->tuned[nrhs] = cand[ibest];
+  if (best) *best = ibf_tuning{cand[ibest].path, cand[ibest].chunk, cand[ibest].max_fused, tbest};
+  if (dflt) *dflt = ibf_tuning{0, 0, 0, tdef};
+  // leave u holding the product of the chosen schedule
+  return apply_plan(p, g, ldg, u, ldu, nrhs, s);
+}
+
 }  // namespace ibf
 
 extern "C" {
+
+int ibf_tune(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int64_t nrhs,
+             void* stream, ibf_tuning* best, ibf_tuning* dflt) {
+  if (!p) {
+    ibf::set_error("ibf_tune: null plan");
+    return IBF_ERR_INVALID_ARG;
+  }
+  if (!p->built) {
+    ibf::set_error("ibf_tune: plan not built");
+    return IBF_ERR_NOT_BUILT;
+  }
+  if (!g || !u || nrhs < 1 || ldg < p->nxi || ldu < p->nx) {
+    ibf::set_error("ibf_tune: null vector, nrhs < 1 or leading dimension too small");
+    return IBF_ERR_INVALID_ARG;
+  }
+  if (p->dim != 1) {
+    ibf::set_error("ibf_tune: the schedule tuner is provided for 1-D plans");
+    return IBF_ERR_UNSUPPORTED;
+  }
+  return ibf::tune_plan(p, g, ldg, u, ldu, nrhs, (hipStream_t)stream, best, dflt);
+}
+
+int ibf_set_tuning(ibf_plan_t p, int64_t nrhs, const ibf_tuning* t) {
+  if (!p || nrhs < 1) {
+    ibf::set_error("ibf_set_tuning: null plan or nrhs < 1");
+    return IBF_ERR_INVALID_ARG;
+  }
+  if (p->dim != 1) {
+    ibf::set_error("ibf_set_tuning: schedules are provided for 1-D plans");
+    return IBF_ERR_UNSUPPORTED;
+  }
+  if (!t) {
+    p->tuned.erase(nrhs);
+    return IBF_OK;
+  }
+  if (t->path < 0 || t->path > 2 || (t->chunk != 0 && t->chunk != 16 && t->chunk != 32) ||
+      t->max_fused < 0) {
+    ibf::set_error("ibf_set_tuning: path outside 0..2, chunk not 0/16/32 or max_fused < 0");
+    return IBF_ERR_INVALID_ARG;
+  }
+  if (t->path == 2 && p->precision == IBF_FP64) {
+    ibf::set_error("ibf_set_tuning: no MFMA stage kernel for FP64 plans");
+    return IBF_ERR_UNSUPPORTED;
+  }
+  p->tuned[nrhs] = ibf::Tuning{t->path, t->chunk, t->max_fused};
+  return IBF_OK;
+}
 
 int ibf_batch_create(const ibf_plan_t* plans, int count, ibf_batch_t* out) {
   if (!out) {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -12,6 +13,13 @@
 namespace ibf {
 
 constexpr int kMaxR = 16;          // Chebyshev points per box supported on device
+
+// Apply schedule knobs (ibf_tune): path 0 default rule / 1 vector / 2 MFMA
+// stage kernels, MFMA chunk width (0: by nrhs), most stages fused (0: as LDS
+// allows)
+struct Tuning {
+  int path = 0, chunk = 0, max_fused = 0;
+};
 constexpr int kMaxParams = 6;
 
 struct PhaseDesc {
@@ -88,6 +96,10 @@ struct ibf_plan_s {
   // apply workspace (ping-pong coefficient buffers)
   void* d_work[2] = {nullptr, nullptr};
   size_t work_bytes = 0;
+  // tuned schedules per nrhs (ibf_tune), and the candidate under trial
+  std::map<int64_t, ibf::Tuning> tuned;
+  ibf::Tuning trial{};
+  bool trial_on = false;
 };
 
 namespace ibf {

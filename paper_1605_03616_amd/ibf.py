@@ -24,7 +24,7 @@ EXPORTED = ["ibf_plan", "ibf_build", "ibf_apply", "ibf_apply_profile", "ibf_quer
             "ibf_destroy", "ibf_last_error", "ibf_eval_kernel", "ibf_batch_create",
             "ibf_apply_batch", "ibf_batch_destroy", "ibf_dense_apply", "ibf_mlp_n_params",
             "ibf_mlp_features", "ibf_mlp_forward", "ibf_mlp_grad_work", "ibf_mlp_loss_grad",
-            "ibf_mlp_adam", "ibf_mlp_select"]
+            "ibf_mlp_adam", "ibf_mlp_select", "ibf_tune", "ibf_set_tuning"]
 MLP_FEATURES = 5
 BATCH_GRAPH = 1
 PROFILE_MAX = 64
@@ -66,6 +66,10 @@ class IBFInfo(C.Structure):
         ("rank_in_g", C.c_int * 64),
         ("rank_in_h", C.c_int * 64),
     ]
+
+
+class IBFTuning(C.Structure):
+    _fields_ = [("path", C.c_int), ("chunk", C.c_int), ("max_fused", C.c_int), ("ms", C.c_float)]
 
 
 class IBFProfile(C.Structure):
@@ -124,11 +128,14 @@ def load(path: str = LIB_PATH):
     lib.ibf_mlp_select.argtypes = [vp, C.c_int, i64, C.c_int, C.c_double, C.c_double,
                                    C.c_int, C.c_int, C.POINTER(C.c_int),
                                    C.POINTER(C.c_double), vp]
+    lib.ibf_tune.argtypes = [vp, vp, i64, vp, i64, i64, vp, C.POINTER(IBFTuning),
+                             C.POINTER(IBFTuning)]
+    lib.ibf_set_tuning.argtypes = [vp, i64, C.POINTER(IBFTuning)]
     for name in ("ibf_plan", "ibf_build", "ibf_apply", "ibf_apply_profile", "ibf_query",
                  "ibf_destroy", "ibf_eval_kernel", "ibf_batch_create", "ibf_apply_batch",
                  "ibf_batch_destroy", "ibf_dense_apply", "ibf_mlp_n_params",
                  "ibf_mlp_features", "ibf_mlp_forward", "ibf_mlp_loss_grad", "ibf_mlp_adam",
-                 "ibf_mlp_select"):
+                 "ibf_mlp_select", "ibf_tune", "ibf_set_tuning"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -236,6 +243,32 @@ class Plan:
     def apply_raw(self, g_ptr, ldg, u_ptr, ldu, nrhs, stream=None):
         _check(self._lib.ibf_apply(self.handle, C.c_void_p(g_ptr), ldg, C.c_void_p(u_ptr), ldu,
                                    nrhs, _stream_handle(stream)))
+
+    def tune(self, g, u=None, stream=None) -> dict:
+        """ibf_tune on (nrhs, n) tensors: times the candidate schedules, keeps
+        the fastest for later applies with this nrhs (u receives the product);
+        returns the choice and the default rule's time."""
+        import torch
+        if g.dtype != self.vector_dtype() or not g.is_contiguous() or g.dim() != 2:
+            raise ValueError("g must be a contiguous (nrhs, n) tensor of the plan's complex dtype")
+        if u is None:
+            u = torch.empty((g.shape[0], self.n_x), dtype=g.dtype, device=g.device)
+        best, dflt = IBFTuning(), IBFTuning()
+        _check(self._lib.ibf_tune(self.handle, C.c_void_p(g.data_ptr()), g.shape[1],
+                                  C.c_void_p(u.data_ptr()), u.shape[1], g.shape[0],
+                                  _stream_handle(stream), C.byref(best), C.byref(dflt)))
+        return {"path": ["default", "vector", "mfma"][best.path], "chunk": best.chunk,
+                "max_fused": best.max_fused, "ms": float(best.ms), "default_ms": float(dflt.ms)}
+
+    def set_tuning(self, nrhs, path=None, chunk=0, max_fused=0):
+        """ibf_set_tuning: installs a schedule for `nrhs` right-hand sides
+        (path "default", "vector" or "mfma"); path None returns to the
+        default rule."""
+        if path is None:
+            _check(self._lib.ibf_set_tuning(self.handle, nrhs, None))
+            return
+        t = IBFTuning(["default", "vector", "mfma"].index(path), chunk, max_fused, 0.0)
+        _check(self._lib.ibf_set_tuning(self.handle, nrhs, C.byref(t)))
 
     def apply_profile(self, g, u, stream=None):
         """ibf_apply_profile on (nrhs, n) tensors; returns a list of launches
