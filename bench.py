@@ -39,21 +39,23 @@ BF16_PEAK_TFS = 2500.0
 # for the apply source it was measured on: any change to it voids the figure.
 APPLY_SRC = os.path.join(ROOT, "paper_1605_03616_amd", "csrc", "ibf_apply.hip")
 MEASURED_TRAFFIC = {
-    # workload -> (sha1 of the apply source, kernel class,
-    #              [(launches per step, FETCH_SIZE KiB, WRITE_SIZE KiB), ...])
-    "fio1d_n65536_r12_fp32": ("bb5155738ff7e94ddefc35f9a452a0a6c0a18805", "apply_fused_mfma",
-                              [(2, 327955, 344064), (1, 264802, 294912)]),
-    "nudft_n1048576_r10": ("bb5155738ff7e94ddefc35f9a452a0a6c0a18805", "apply_fused_mfma",
-                           [(1, 2871410, 917504), (2, 1867860, 983040), (1, 1769560, 917504)]),
+    # (workload, schedule path/chunk/max_fused) -> (sha1 of the apply source,
+    #   kernel class, [(launches per step, FETCH_SIZE KiB, WRITE_SIZE KiB), ...])
+    ("fio1d_n65536_r12_fp32", "default/0/0"): (
+        "0e60dabb76c2152ea497e4802e20f88d7a758134", "apply_fused_mfma",
+        [(2, 331771, 344064), (1, 263474, 294912)]),
+    ("nudft_n1048576_r10", "default/0/0"): (
+        "0e60dabb76c2152ea497e4802e20f88d7a758134", "apply_fused_mfma",
+        [(1, 2871430, 917504), (2, 1867880, 983040), (1, 1769580, 917504)]),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
 
-def _measured_traffic(workload, kernel):
+def _measured_traffic(workload, schedule, kernel):
     """Average HBM bytes per launch of `kernel`, or None if not measured for
-    this exact apply source."""
+    this exact apply source and schedule."""
     import hashlib
-    ent = MEASURED_TRAFFIC.get(workload)
+    ent = MEASURED_TRAFFIC.get((workload, schedule))
     if not ent or ent[1] != kernel:
         return None
     with open(APPLY_SRC, "rb") as f:
@@ -339,7 +341,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=100,
+                    help="untimed steps first (the clocks ramp up over the first ~0.1 s)")
     ap.add_argument("--workload", default="fio1d_64k")
     ap.add_argument("--nrhs", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -430,7 +433,9 @@ def main():
         bound, peak = ("hbm", HBM_PEAK_GBS) if P.nrhs < 64 else ("mfma", FP32_PEAK_TFS)
     unit = "TFLOP/s" if bound == "mfma" else "GB/s"
     dom, roof, per_class = _roofline(launches, bound, peak, unit)
-    roof["traffic"] = _measured_traffic(P.name, dom)
+    sched = (f"{tuning['path']}/{tuning['chunk']}/{tuning['max_fused']}" if tuning
+             else "default/0/0")
+    roof["traffic"] = _measured_traffic(P.name, sched, dom)
     if roof["traffic"] is not None:
         roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)"
 

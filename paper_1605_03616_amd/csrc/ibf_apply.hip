@@ -1749,8 +1749,36 @@ int apply_plan(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, i
   }
 }
 
-// Time every candidate schedule for nrhs right-hand sides (one warm-up apply,
-// then the mean of three) and keep the fastest for later applies.
+// The launch list a schedule produces (kernel, tile, grid, LDS, stage span
+// and chunk width per launch): two knob settings with equal signatures run
+// the same launches.
+template <typename VT, typename FT>
+int schedule_signature(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu,
+                       int nrhs, std::vector<int64_t>& sig) {
+  std::vector<Launch> seq;
+  const int rc = make_schedule<VT, FT>(p, g, ldg, u, ldu, nrhs, seq);
+  if (rc != IBF_OK) return rc;
+  sig.clear();
+  for (const Launch& x : seq) {
+    sig.insert(sig.end(), {(int64_t)x.kind, (int64_t)x.kt, (int64_t)x.mfma, x.nblocks,
+                           (int64_t)x.lds});
+    if (x.kind == kLaunchFused) sig.insert(sig.end(), {x.f.A.l_start, x.f.A.nst, x.f.A.NB});
+  }
+  return IBF_OK;
+}
+
+int schedule_signature(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu,
+                       int nrhs, std::vector<int64_t>& sig) {
+  switch (p->precision) {
+    case IBF_FP64: return schedule_signature<double2, double2>(p, g, ldg, u, ldu, nrhs, sig);
+    case IBF_FP32: return schedule_signature<float2, float2>(p, g, ldg, u, ldu, nrhs, sig);
+    default: return schedule_signature<float2, bf16x2c>(p, g, ldg, u, ldu, nrhs, sig);
+  }
+}
+
+// Time every distinct candidate schedule for nrhs right-hand sides
+// (interleaved rounds, median per candidate) and keep the fastest for later
+// applies; the default rule is kept unless another is 2% faster.
 int tune_plan(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int64_t nrhs,
               hipStream_t s, ibf_tuning* best, ibf_tuning* dflt) {
   IBF_HIP_CHECK(hipSetDevice(p->device));
@@ -1768,6 +1796,28 @@ int tune_plan(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, in
     }
   }
   // the plan leaves trial mode and the events are released on every exit
+  struct TrialOff {
+    ibf_plan_t p;
+    ~TrialOff() { p->trial_on = false; }
+  } off{p};
+  {  // drop knob settings that produce a launch list seen before
+    std::vector<std::vector<int64_t>> seen;
+    std::vector<Tuning> uniq;
+    for (const Tuning& c : cand) {
+      p->trial = c;
+      p->trial_on = true;
+      std::vector<int64_t> sig;
+      const int r = schedule_signature(p, g, ldg, u, ldu, (int)nrhs, sig);
+      if (r != IBF_OK) {
+        if (uniq.empty()) return r;                           // the default rule must plan
+        continue;
+      }
+      if (std::find(seen.begin(), seen.end(), sig) != seen.end()) continue;
+      seen.push_back(sig);
+      uniq.push_back(c);
+    }
+    cand.swap(uniq);
+  }
   struct Guard {
     ibf_plan_t p;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1779,33 +1829,51 @@ int tune_plan(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, in
   } gd{p};
   IBF_HIP_CHECK(hipEventCreate(&gd.e0));
   IBF_HIP_CHECK(hipEventCreate(&gd.e1));
-  hipEvent_t e0 = gd.e0, e1 = gd.e1;
-  int rc = IBF_OK, ibest = -1;
-  float tbest = 0, tdef = 0;
-  constexpr int kReps = 3;
-  for (size_t i = 0; i < cand.size() && rc == IBF_OK; ++i) {
+  const size_t nc = cand.size();
+  // one untimed apply per candidate (workspace, clocks), then interleaved
+  // timed rounds so that no candidate profits from coming later
+  std::vector<bool> ok(nc, false);
+  for (size_t i = 0; i < nc; ++i) {
     p->trial = cand[i];
     p->trial_on = true;
-    int r = apply_plan(p, g, ldg, u, ldu, nrhs, s);           // warm-up (and workspace)
-    if (r == IBF_OK) IBF_HIP_CHECK(hipEventRecord(e0, s));
-    for (int k = 0; k < kReps && r == IBF_OK; ++k) r = apply_plan(p, g, ldg, u, ldu, nrhs, s);
-    if (r == IBF_OK) {
-      IBF_HIP_CHECK(hipEventRecord(e1, s));
-      IBF_HIP_CHECK(hipEventSynchronize(e1));
-      float ms = 0;
-      IBF_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
-      ms /= kReps;
-      if (i == 0) tdef = ms;
-      if (ibest < 0 || ms < tbest) {
-        ibest = (int)i;
-        tbest = ms;
+    const int r = apply_plan(p, g, ldg, u, ldu, nrhs, s);
+    if (i == 0 && r != IBF_OK) return r;                      // the default rule must run
+    ok[i] = r == IBF_OK;
+  }
+  constexpr int kRounds = 5;
+  std::vector<std::vector<float>> t(nc);
+  for (int k = 0; k < kRounds; ++k) {
+    for (size_t i = 0; i < nc; ++i) {
+      if (!ok[i]) continue;
+      p->trial = cand[i];
+      p->trial_on = true;
+      IBF_HIP_CHECK(hipEventRecord(gd.e0, s));
+      const int r = apply_plan(p, g, ldg, u, ldu, nrhs, s);
+      if (r != IBF_OK) {
+        if (i == 0) return r;
+        ok[i] = false;
+        continue;
       }
-    } else if (i == 0) {
-      rc = r;                                                 // the default rule must run
+      IBF_HIP_CHECK(hipEventRecord(gd.e1, s));
+      IBF_HIP_CHECK(hipEventSynchronize(gd.e1));
+      float ms = 0;
+      IBF_HIP_CHECK(hipEventElapsedTime(&ms, gd.e0, gd.e1));
+      t[i].push_back(ms);
     }
   }
   p->trial_on = false;
-  if (rc != IBF_OK) return rc;
+  std::vector<float> med(nc, 0.f);
+  for (size_t i = 0; i < nc; ++i) {
+    if (!ok[i]) continue;
+    std::vector<float> v = t[i];
+    std::sort(v.begin(), v.end());
+    med[i] = v[v.size() / 2];
+  }
+  // another candidate replaces the default rule only when it is 2% faster
+  int ibest = 0;
+  for (size_t i = 1; i < nc; ++i)
+    if (ok[i] && med[i] < med[ibest] && med[i] < 0.98f * med[0]) ibest = (int)i;
+  const float tbest = med[ibest], tdef = med[0];
   p->tuned[nrhs] = cand[ibest];
   if (best) *best = ibf_tuning{cand[ibest].path, cand[ibest].chunk, cand[ibest].max_fused, tbest};
   if (dflt) *dflt = ibf_tuning{0, 0, 0, tdef};
