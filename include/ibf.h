@@ -129,7 +129,12 @@ int ibf_build(ibf_plan_t plan, void* hip_stream);
  * ldg >= n_xi and ldu >= n_x, in the caller's point order, complex
  * interleaved in the plan's vector type.  g and u must not overlap.  The
  * plan's apply workspace grows on demand (one hipMalloc when nrhs exceeds
- * every previous call); only one apply per plan may be in flight.
+ * every previous call); only one apply per plan may be in flight.  A dim-2
+ * plan (the multiscale sum of Sec. 5, eq:domaindecomp) captures its launch
+ * sequence (centre block, the boxes on worker streams, U per X tree) into a
+ * HIP graph the first time it sees a given (g, u, ldg, ldu, nrhs) and
+ * workspace, and replays that graph on hip_stream afterwards; the
+ * environment variable IBF_NO_GRAPH (any value) makes it launch directly.
  * Errors: NOT_BUILT, INVALID_ARG (nrhs < 1, bad ld, NULL), OOM, DEVICE.
  */
 int ibf_apply(ibf_plan_t plan, const void* g, int64_t ldg, void* u,

@@ -29,6 +29,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -90,6 +91,13 @@ struct Mibf2D {
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> ev_u;  // per box: its stages done
   hipEvent_t ev_start = nullptr;
+  // the whole launch sequence captured once per (g, u, leading dimensions,
+  // nrhs, workspace) on a private stream and replayed on the caller's stream
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<int64_t> graph_key;
+  bool graph_failed = false;   // capture refused once: direct launches from then on
   bool built = false;
   int64_t nnz_prelim = 0, nnz_opt = 0, nnz_stored = 0, factor_bytes = 0;
   int maxL = 0;
@@ -1199,6 +1207,10 @@ int build2d_t(ibf_plan_t p, hipStream_t s) {
 }
 
 template <typename VT, typename FT>
+int launch2d_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int nrhs,
+               hipStream_t s, const std::vector<size_t>& off);
+
+template <typename VT, typename FT>
 int apply2d_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int nrhs,
               hipStream_t s) {
   Mibf2D& M = *p->mibf;
@@ -1231,6 +1243,48 @@ int apply2d_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, in
     for (int i = 0; i < nbox; ++i)
       IBF_HIP_CHECK(hipEventCreateWithFlags(&M.ev_u[i], hipEventDisableTiming));
   }
+  if (M.graph_failed || std::getenv("IBF_NO_GRAPH"))
+    return launch2d_t<VT, FT>(p, g, ldg, u, ldu, nrhs, s, off);
+  const std::vector<int64_t> key = {(int64_t)(uintptr_t)g, ldg, (int64_t)(uintptr_t)u, ldu,
+                                    nrhs, (int64_t)(uintptr_t)M.d_work};
+  if (!M.exec || key != M.graph_key) {
+    if (M.exec) (void)hipGraphExecDestroy(M.exec);
+    if (M.graph) (void)hipGraphDestroy(M.graph);
+    M.exec = nullptr;
+    M.graph = nullptr;
+    M.graph_key.clear();
+    if (!M.cap) IBF_HIP_CHECK(hipStreamCreateWithFlags(&M.cap, hipStreamNonBlocking));
+    IBF_HIP_CHECK(hipStreamBeginCapture(M.cap, hipStreamCaptureModeThreadLocal));
+    const int lrc = launch2d_t<VT, FT>(p, g, ldg, u, ldu, nrhs, M.cap, off);
+    hipGraph_t gr = nullptr;
+    const hipError_t ec = hipStreamEndCapture(M.cap, &gr);
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = (lrc == IBF_OK && ec == hipSuccess && gr)
+                              ? hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0)
+                              : hipErrorUnknown;
+    if (ei != hipSuccess) {
+      // capture or instantiation refused: clear the error and launch directly
+      if (gr) (void)hipGraphDestroy(gr);
+      (void)hipGetLastError();
+      M.graph_failed = true;
+      return launch2d_t<VT, FT>(p, g, ldg, u, ldu, nrhs, s, off);
+    }
+    M.graph = gr;
+    M.exec = ex;
+    M.graph_key = key;
+  }
+  IBF_HIP_CHECK(hipGraphLaunch(M.exec, s));
+  return IBF_OK;
+}
+
+// The launch sequence of one 2-D apply on stream s: the centre block, then
+// per box V and the quadtree stages on a worker stream, then U per X tree
+// back on s.
+template <typename VT, typename FT>
+int launch2d_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int nrhs,
+               hipStream_t s, const std::vector<size_t>& off) {
+  Mibf2D& M = *p->mibf;
+  const int nbox = (int)M.boxes.size();
   const int nc = (int)M.centre.size();
   // the centre block writes every entry of u; the boxes then accumulate
   constexpr int NR = 8;                                       // RHS columns a pass
@@ -1614,6 +1668,13 @@ void free2d_factors(ibf_plan_t p) {
   M.ev_u.clear();
   if (M.ev_start) (void)hipEventDestroy(M.ev_start);
   M.ev_start = nullptr;
+  if (M.exec) (void)hipGraphExecDestroy(M.exec);
+  if (M.graph) (void)hipGraphDestroy(M.graph);
+  if (M.cap) (void)hipStreamDestroy(M.cap);
+  M.exec = nullptr;
+  M.graph = nullptr;
+  M.cap = nullptr;
+  M.graph_key.clear();
   M.d_x = nullptr;
   M.d_cidx = nullptr;
   M.d_kc = nullptr;

@@ -778,8 +778,10 @@ __device__ __forceinline__ void apply_u_body(const UDesc& d, int64_t lb) {
     });
   }
   __syncthreads();
+  // point-major items: a wave covers 64 / nbw points, so its lanes read few
+  // distinct factor rows
   for (int item = threadIdx.x; item < cnt * nbw; item += blockDim.x) {
-    const int x = item % cnt, n = item / cnt;
+    const int x = item / nbw, n = item - x * nbw;
     VT acc = Zero<VT>::v();
     if (stage_factor) {
       const VT* ur = ul + (size_t)x * urow;
@@ -1332,13 +1334,15 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
       while (NBu > 1 && (size_t)(1 << l0) * K * NBu * sizeof(VT) > kLdsBudget / 2) NBu /= 2;
       const int nchu = (nrhs + NBu - 1) / NBu;
       const size_t base = (size_t)(1 << l0) * K * NBu * sizeof(VT);
-      const size_t fac = (size_t)p->smax_x * ((1 << l0) * K + 1) * sizeof(VT);
       if (base > kLdsBudget) {
         set_error("ibf_apply: leaf size too large for the apply kernels");
         return IBF_ERR_UNSUPPORTED;
       }
-      const int stage_f = base + fac <= kLdsBudget ? 1 : 0;
-      x.lds = base + (stage_f ? fac : 0);
+      // the factor rows are read from memory (each by the nbw lanes of its
+      // point): staging them sized the LDS by the largest leaf and cost
+      // occupancy (measured slower)
+      const int stage_f = 0;
+      x.lds = base;
       x.nblocks = p->nleaf * nchu;
       x.u = UDesc{w[cur], u, ldu, p->d_perm_x, p->d_xoff, p->d_ubar, l0, K, nrhs, NBu, nchu,
                   p->smax_x, stage_f};

@@ -8,6 +8,7 @@ factorizations agree to the FP64 rounding of the shared ranks), FP32 1e-5,
 BF16X2 1e-4 against the oracle; the x-independent phase exactly (1e-12).
 """
 import functools
+import os
 import sys
 
 import numpy as np
@@ -105,3 +106,36 @@ def test_2d_full_size_fp32(torch_dev):
     _say(f"2-D full size: error vs dense {err:.3g}, R_comp {q32['R_comp']:.3f}")
     assert err < 3e-2
     assert q32["R_comp"] > 1.0
+
+
+def test_2d_graph_replays_match_direct_launches(torch_dev):
+    """The 2-D apply is captured once per (g, u, nrhs, workspace) and replayed:
+    every replay, with other GPU work and synchronisations between them, and a
+    replay into a new output (a new capture), equals the direct launches
+    (IBF_NO_GRAPH) bit for bit; all against the oracle at the FP32 bar."""
+    torch = torch_dev
+    from paper_1605_03616_amd import ibf
+    _say("2-D graph replay vs direct launches n=64 r=5 FP32")
+    P, uo, _, _ = _case(64, 5)
+    pl = ibf.Plan.from_problem(P, precision=I.PREC_FP32).build()
+    g = torch.from_numpy(np.ascontiguousarray(P.g.T)).to(torch.complex64).cuda()
+    u = torch.empty((g.shape[0], len(P.x)), dtype=torch.complex64, device="cuda")
+    os.environ["IBF_NO_GRAPH"] = "1"
+    try:
+        pl.apply(g, u)
+        torch.cuda.synchronize()
+        ref = u.cpu().clone()
+    finally:
+        del os.environ["IBF_NO_GRAPH"]
+    assert _rel(ref.numpy().T, uo) <= 1e-5
+    junk = torch.randn(1 << 20, device="cuda")
+    for i in range(4):
+        u.zero_()
+        pl.apply(g, u)
+        junk.mul_(1.0001).add_(0.5)                    # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(u.cpu(), ref), f"replay {i}"
+    u2 = pl.apply(g)                                   # new output: captured again
+    torch.cuda.synchronize()
+    assert torch.equal(u2.cpu(), ref)
+    pl.destroy()

@@ -251,6 +251,30 @@ def test_mfma16_sweep_in_parity(torch_dev, nrhs, precision, tol):
     assert O.rel_error(u, u_ref) < tol
 
 
+@pytest.mark.parametrize("nrhs,precision", [(20, I.PREC_FP32), (19, I.PREC_FP64),
+                                         (33, I.PREC_BF16X2)])
+def test_u_leaf_column_chunks(torch_dev, nrhs, precision):
+    """16 or more right-hand sides with leaves of more than 16 points (random
+    x) run U on the block-per-leaf vector kernel in column chunks (one chunk
+    of 19 or 20 columns; 32 + a ragged 1 for 33) against the oracle's
+    sweep-in IBF."""
+    _say(f"u column chunks nudft4k_r10 nrhs={nrhs} precision={precision}")
+    P, Oi = _oracle_sweep_in("nudft4k_r10")
+    g = I.complex_normal(P.n, nrhs, np.random.default_rng(35))
+    u_ref = O.apply_optimal(Oi, g)
+    from paper_1605_03616_amd import ibf
+    torch = torch_dev
+    pl = ibf.Plan(P.x, P.xi, P.phase, P.params, P.r, P.tol, P.leaf, precision, 1)
+    pl.build()
+    assert pl.query()["smax_x"] > 16
+    dt = torch.complex128 if precision == I.PREC_FP64 else torch.complex64
+    gt = torch.from_numpy(np.ascontiguousarray(g.T)).to(dt).cuda()
+    u = pl.apply(gt).cpu().numpy().T.astype(np.complex128)
+    pl.destroy()
+    tol = {I.PREC_FP64: fp64_tol(P.n), I.PREC_FP32: 1e-5, I.PREC_BF16X2: 1e-4}[precision]
+    assert O.rel_error(u, u_ref) < tol
+
+
 def test_determinism(torch_dev):
     _say("run-to-run determinism fio1k")
     P = I.workload_fio1d_1k()
