@@ -200,6 +200,21 @@ int ibf_set_tuning(ibf_plan_t plan, int64_t nrhs, const ibf_tuning* t);
 /* Sizes, ranks and build time of a plan.  Errors: INVALID_ARG. */
 int ibf_query(ibf_plan_t plan, ibf_info* info);
 
+/*
+ * Device memory hook, for callers that manage device memory themselves (a
+ * framework's caching allocator): plans and batches then take their factor,
+ * workspace and table memory from alloc(bytes, NULL) and return it with
+ * free_fn(ptr, NULL) instead of hipMalloc / hipFree.  Process-wide; applies
+ * to allocations made after the call; every block goes back through the pair
+ * that allocated it, after a device synchronisation.  alloc must return
+ * memory of the current device aligned to 256 bytes, or NULL (reported as
+ * OOM).  NULL for both restores hipMalloc / hipFree.
+ * Errors: INVALID_ARG if exactly one of the two is NULL.
+ */
+typedef void* (*ibf_alloc_fn)(size_t bytes, void* hip_stream);
+typedef void (*ibf_free_fn)(void* ptr, void* hip_stream);
+int ibf_set_allocator(ibf_alloc_fn alloc, ibf_free_fn free_fn);
+
 /* Free every host and device resource of the plan (NULL is a no-op). */
 int ibf_destroy(ibf_plan_t plan);
 

@@ -1013,7 +1013,7 @@ void sort_codes(const std::vector<int64_t>& code, int64_t nbin, std::vector<int3
 
 template <typename T>
 int upload(T** d, const T* h, size_t n) {
-  IBF_HIP_CHECK(hipMalloc(d, std::max<size_t>(n * sizeof(T), 1)));
+  IBF_HIP_CHECK(ibf::dev_malloc(d, std::max<size_t>(n * sizeof(T), 1)));
   if (n) IBF_HIP_CHECK(hipMemcpy(*d, h, n * sizeof(T), hipMemcpyHostToDevice));
   return IBF_OK;
 }
@@ -1028,14 +1028,14 @@ struct Scratch2 {
   unsigned long long* nnz = nullptr;
   ~Scratch2() {
     for (int i = 0; i < 2; ++i) {
-      if (C[i]) (void)hipFree(C[i]);
-      if (R[i]) (void)hipFree(R[i]);
-      if (rc[i]) (void)hipFree(rc[i]);
-      if (rr[i]) (void)hipFree(rr[i]);
+      if (C[i]) (void)ibf::dev_free(C[i]);
+      if (R[i]) (void)ibf::dev_free(R[i]);
+      if (rc[i]) (void)ibf::dev_free(rc[i]);
+      if (rr[i]) (void)ibf::dev_free(rr[i]);
     }
-    if (stage) (void)hipFree(stage);
-    if (kmax) (void)hipFree(kmax);
-    if (nnz) (void)hipFree(nnz);
+    if (stage) (void)ibf::dev_free(stage);
+    if (kmax) (void)ibf::dev_free(kmax);
+    if (nnz) (void)ibf::dev_free(nnz);
   }
 };
 
@@ -1056,7 +1056,7 @@ int pack_stage(Box2& bx, Mibf2D& M, const double2* stage, int level, int kin, in
   const int64_t np = (int64_t)1 << (2 * bx.L);
   const int64_t count = np * 4 * kin * st.kld;
   st.bytes = (size_t)count * sizeof(FT);
-  IBF_HIP_CHECK(hipMalloc(&st.blk, std::max<size_t>(st.bytes, 1)));
+  IBF_HIP_CHECK(ibf::dev_malloc(&st.blk, std::max<size_t>(st.bytes, 1)));
   const unsigned g = (unsigned)std::min<int64_t>((count + kB2 - 1) / kB2, 1 << 20);
   hipLaunchKernelGGL((k2_pack_stage<FT>), dim3(std::max(g, 1u)), dim3(kB2), 0, s, stage,
                      (FT*)st.blk, np, M.R2, kin, kout, st.kld);
@@ -1071,8 +1071,8 @@ int build2d_t(ibf_plan_t p, hipStream_t s) {
   Mibf2D& M = *p->mibf;
   const int R2 = M.R2, r = M.r;
   // tables and X points
-  IBF_HIP_CHECK(hipMalloc(&M.d_z, sizeof(double) * r));
-  IBF_HIP_CHECK(hipMalloc(&M.d_lc, sizeof(double) * 4 * R2 * R2));
+  IBF_HIP_CHECK(ibf::dev_malloc(&M.d_z, sizeof(double) * r));
+  IBF_HIP_CHECK(ibf::dev_malloc(&M.d_lc, sizeof(double) * 4 * R2 * R2));
   hipLaunchKernelGGL(k2_tables, dim3((4 * R2 * R2 + kB2 - 1) / kB2), dim3(kB2), 0, s, r, M.d_z,
                      M.d_lc);
   IBF_HIP_CHECK(hipGetLastError());
@@ -1088,12 +1088,12 @@ int build2d_t(ibf_plan_t p, hipStream_t s) {
     int rc;
     if ((rc = upload(&d_xic, xic.data(), xic.size()))) return rc;
     if ((rc = upload(&M.d_cidx, M.centre.data(), M.centre.size()))) return rc;
-    IBF_HIP_CHECK(hipMalloc(&M.d_kc, std::max<size_t>(sizeof(FT) * M.nx * nc, 1)));
+    IBF_HIP_CHECK(ibf::dev_malloc(&M.d_kc, std::max<size_t>(sizeof(FT) * M.nx * nc, 1)));
     hipLaunchKernelGGL((k2_centre<FT>), dim3(nblk(M.nx * nc)), dim3(kB2), 0, s, M.ph, M.d_x,
                        M.nx, d_xic, nc, (FT*)M.d_kc);
     IBF_HIP_CHECK(hipGetLastError());
     IBF_HIP_CHECK(hipStreamSynchronize(s));
-    (void)hipFree(d_xic);
+    (void)ibf::dev_free(d_xic);
     M.factor_bytes += (int64_t)(sizeof(FT) * M.nx * nc);
     M.nnz_opt += M.nx * nc;
     M.nnz_stored += M.nx * nc;
@@ -1103,14 +1103,14 @@ int build2d_t(ibf_plan_t p, hipStream_t s) {
   Scratch2 S;
   const size_t bsz = sizeof(double2) * (size_t)npmax * R2 * R2;
   for (int i = 0; i < 2; ++i) {
-    IBF_HIP_CHECK(hipMalloc(&S.C[i], bsz));
-    IBF_HIP_CHECK(hipMalloc(&S.R[i], bsz));
-    IBF_HIP_CHECK(hipMalloc(&S.rc[i], sizeof(int) * npmax));
-    IBF_HIP_CHECK(hipMalloc(&S.rr[i], sizeof(int) * npmax));
+    IBF_HIP_CHECK(ibf::dev_malloc(&S.C[i], bsz));
+    IBF_HIP_CHECK(ibf::dev_malloc(&S.R[i], bsz));
+    IBF_HIP_CHECK(ibf::dev_malloc(&S.rc[i], sizeof(int) * npmax));
+    IBF_HIP_CHECK(ibf::dev_malloc(&S.rr[i], sizeof(int) * npmax));
   }
-  IBF_HIP_CHECK(hipMalloc(&S.stage, 4 * bsz));
-  IBF_HIP_CHECK(hipMalloc(&S.kmax, sizeof(int) * 128));
-  IBF_HIP_CHECK(hipMalloc(&S.nnz, sizeof(unsigned long long)));
+  IBF_HIP_CHECK(ibf::dev_malloc(&S.stage, 4 * bsz));
+  IBF_HIP_CHECK(ibf::dev_malloc(&S.kmax, sizeof(int) * 128));
+  IBF_HIP_CHECK(ibf::dev_malloc(&S.nnz, sizeof(unsigned long long)));
 
   int rc;
   for (Box2& bx : M.boxes) {
@@ -1176,8 +1176,8 @@ int build2d_t(ibf_plan_t p, hipStream_t s) {
     const int na = 1 << (2 * lV);
     bx.vbar_bytes = sizeof(FT) * (size_t)bx.m * na * bx.K_V;
     bx.ubar_bytes = sizeof(FT) * (size_t)M.nx * bx.K_U;
-    IBF_HIP_CHECK(hipMalloc(&bx.d_vbar, std::max<size_t>(bx.vbar_bytes, 1)));
-    IBF_HIP_CHECK(hipMalloc(&bx.d_ubar, std::max<size_t>(bx.ubar_bytes, 1)));
+    IBF_HIP_CHECK(ibf::dev_malloc(&bx.d_vbar, std::max<size_t>(bx.vbar_bytes, 1)));
+    IBF_HIP_CHECK(ibf::dev_malloc(&bx.d_ubar, std::max<size_t>(bx.ubar_bytes, 1)));
     if (bx.m > 0) {
 #define IBF2_VBAR(RR)                                                                            \
   hipLaunchKernelGGL((k2_vbar<RR, FT>), dim3(nblk(bx.m * na)), dim3(kB2), 0, s, B, M.d_z,       \
@@ -1225,10 +1225,10 @@ int apply2d_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, in
     off[i + 1] = off[i] + 2 * one;
   }
   if (off[nbox] > M.work_bytes) {
-    if (M.d_work) IBF_HIP_CHECK(hipFree(M.d_work));
+    if (M.d_work) IBF_HIP_CHECK(ibf::dev_free(M.d_work));
     M.d_work = nullptr;
     M.work_bytes = 0;
-    IBF_HIP_CHECK(hipMalloc(&M.d_work, off[nbox]));
+    IBF_HIP_CHECK(ibf::dev_malloc(&M.d_work, off[nbox]));
     M.work_bytes = off[nbox];
   }
   if (M.streams.empty() && nbox > 0) {
@@ -1635,7 +1635,7 @@ void free2d_factors(ibf_plan_t p) {
   if (!p->mibf) return;
   Mibf2D& M = *p->mibf;
   auto fr = [](void* b) {
-    if (b) (void)hipFree(b);
+    if (b) (void)ibf::dev_free(b);
   };
   for (Box2& bx : M.boxes) {
     for (auto& st : bx.stages) fr(st.blk);

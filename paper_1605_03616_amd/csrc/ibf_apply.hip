@@ -1137,12 +1137,12 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
   const size_t need = (size_t)p->npairs * kmax * nrhs * sizeof(VT);
   if (need > p->work_bytes) {
     for (int i = 0; i < 2; ++i) {
-      if (p->d_work[i]) (void)hipFree(p->d_work[i]);
+      if (p->d_work[i]) (void)ibf::dev_free(p->d_work[i]);
       p->d_work[i] = nullptr;
     }
     p->work_bytes = 0;
-    IBF_HIP_CHECK(hipMalloc(&p->d_work[0], need));
-    IBF_HIP_CHECK(hipMalloc(&p->d_work[1], need));
+    IBF_HIP_CHECK(ibf::dev_malloc(&p->d_work[0], need));
+    IBF_HIP_CHECK(ibf::dev_malloc(&p->d_work[1], need));
     p->work_bytes = need;
   }
   void* w[2] = {p->d_work[0], p->d_work[1]};
@@ -1658,11 +1658,11 @@ int apply_batch_t(ibf_batch_s* b, const void* const* g, const int64_t* ldg, void
   if (bytes > b->table_cap) {
     if (b->table_pending) IBF_HIP_CHECK(hipEventSynchronize(b->table_ev));
     b->table_pending = false;
-    if (b->d_table) IBF_HIP_CHECK(hipFree(b->d_table));
+    if (b->d_table) IBF_HIP_CHECK(ibf::dev_free(b->d_table));
     if (b->h_table) IBF_HIP_CHECK(hipHostFree(b->h_table));
     b->d_table = b->h_table = nullptr;
     b->table_cap = 0;
-    IBF_HIP_CHECK(hipMalloc(&b->d_table, bytes));
+    IBF_HIP_CHECK(ibf::dev_malloc(&b->d_table, bytes));
     IBF_HIP_CHECK(hipHostMalloc(&b->h_table, bytes, hipHostMallocDefault));
     b->table_cap = bytes;
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -2010,7 +2010,7 @@ int ibf_batch_destroy(ibf_batch_t b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap) (void)hipStreamDestroy(b->cap);
   if (b->table_ev) (void)hipEventDestroy(b->table_ev);
-  if (b->d_table) (void)hipFree(b->d_table);
+  if (b->d_table) (void)ibf::dev_free(b->d_table);
   if (b->h_table) (void)hipHostFree(b->h_table);
   delete b;
   return IBF_OK;

@@ -39,10 +39,10 @@ struct DevBuf {
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   DevBuf(DevBuf&& o) noexcept : ptr(o.ptr), n(o.n) { o.ptr = nullptr; o.n = 0; }
-  ~DevBuf() { if (ptr) (void)hipFree(ptr); }
+  ~DevBuf() { if (ptr) (void)ibf::dev_free(ptr); }
   hipError_t alloc(size_t count) {
     n = count;
-    return hipMalloc((void**)&ptr, std::max<size_t>(count, 1) * sizeof(T));
+    return ibf::dev_malloc((void**)&ptr, std::max<size_t>(count, 1) * sizeof(T));
   }
 };
 
@@ -271,7 +271,7 @@ int pack_all(ibf_plan_t p, const std::vector<DevBuf<double2>>& stages, const dou
     st.k_ld = (st.k_out + 1) & ~1;
     const int64_t count = p->npairs * st.k_ld * 2 * st.k_in;
     st.bytes = (size_t)count * fb;
-    IBF_HIP_CHECK(hipMalloc(&st.blk, std::max<size_t>(st.bytes, 1)));
+    IBF_HIP_CHECK(ibf::dev_malloc(&st.blk, std::max<size_t>(st.bytes, 1)));
     p->stages.push_back(st);
     const unsigned blocks = (unsigned)std::min<int64_t>((count + kBlock - 1) / kBlock, 1 << 20);
     hipLaunchKernelGGL((k_pack_stage<FT>), dim3(std::max(blocks, 1u)), dim3(kBlock), 0, s,
@@ -284,8 +284,8 @@ int pack_all(ibf_plan_t p, const std::vector<DevBuf<double2>>& stages, const dou
   p->k_vbar = p->rank[0];
   p->ubar_bytes = (size_t)(p->nx << l0) * p->k_ubar * fb;
   p->vbar_bytes = (size_t)(p->nxi << l0) * p->k_vbar * fb;
-  IBF_HIP_CHECK(hipMalloc(&p->d_ubar, std::max<size_t>(p->ubar_bytes, 1)));
-  IBF_HIP_CHECK(hipMalloc(&p->d_vbar, std::max<size_t>(p->vbar_bytes, 1)));
+  IBF_HIP_CHECK(ibf::dev_malloc(&p->d_ubar, std::max<size_t>(p->ubar_bytes, 1)));
+  IBF_HIP_CHECK(ibf::dev_malloc(&p->d_vbar, std::max<size_t>(p->vbar_bytes, 1)));
   {
     const int64_t n = p->nx << l0;
     hipLaunchKernelGGL((k_ubar<FT>), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
@@ -405,7 +405,7 @@ int sweep_in_pack(ibf_plan_t p, std::vector<DevBuf<double2>>& stages, const doub
     st.k_ld = (st.k_out + 1) & ~1;
     const int64_t count = np * st.k_ld * 2 * st.k_in;
     st.bytes = (size_t)count * fb;
-    IBF_HIP_CHECK(hipMalloc(&st.blk, std::max<size_t>(st.bytes, 1)));
+    IBF_HIP_CHECK(ibf::dev_malloc(&st.blk, std::max<size_t>(st.bytes, 1)));
     p->stages.push_back(st);
     const unsigned blocks = (unsigned)std::min<int64_t>((count + kBlock - 1) / kBlock, 1 << 20);
     hipLaunchKernelGGL((k_pack_stage<FT>), dim3(std::max(blocks, 1u)), dim3(kBlock), 0, s,
@@ -417,7 +417,7 @@ int sweep_in_pack(ibf_plan_t p, std::vector<DevBuf<double2>>& stages, const doub
   {
     const int64_t count = np * p->k_mid_g * p->k_mid_h;
     p->mdot_bytes = (size_t)count * fb;
-    IBF_HIP_CHECK(hipMalloc(&p->d_mdot, std::max<size_t>(p->mdot_bytes, 1)));
+    IBF_HIP_CHECK(ibf::dev_malloc(&p->d_mdot, std::max<size_t>(p->mdot_bytes, 1)));
     hipLaunchKernelGGL((k_sweepin_mid<FT>), dim3((unsigned)((count + kBlock - 1) / kBlock)),
                        dim3(kBlock), 0, s, R, np, cb[cg].ptr, rb[ch].ptr, rkg[cg].ptr,
                        rkh[ch].ptr, p->k_mid_g, p->k_mid_h, (FT*)p->d_mdot, cnt.ptr + nst);
@@ -427,8 +427,8 @@ int sweep_in_pack(ibf_plan_t p, std::vector<DevBuf<double2>>& stages, const doub
   p->k_vbar = rh[0];
   p->ubar_bytes = (size_t)(p->nx << l0) * p->k_ubar * fb;
   p->vbar_bytes = (size_t)(p->nxi << l0) * p->k_vbar * fb;
-  IBF_HIP_CHECK(hipMalloc(&p->d_ubar, std::max<size_t>(p->ubar_bytes, 1)));
-  IBF_HIP_CHECK(hipMalloc(&p->d_vbar, std::max<size_t>(p->vbar_bytes, 1)));
+  IBF_HIP_CHECK(ibf::dev_malloc(&p->d_ubar, std::max<size_t>(p->ubar_bytes, 1)));
+  IBF_HIP_CHECK(ibf::dev_malloc(&p->d_vbar, std::max<size_t>(p->vbar_bytes, 1)));
   {
     const int64_t rows = p->nx << l0;
     hipLaunchKernelGGL((k_pack_outer<FT>),
@@ -462,7 +462,7 @@ int sweep_in_pack(ibf_plan_t p, std::vector<DevBuf<double2>>& stages, const doub
 template <typename T>
 int upload(T** dst, const std::vector<T>& src) {
   if (*dst) return IBF_OK;
-  IBF_HIP_CHECK(hipMalloc((void**)dst, std::max<size_t>(src.size(), 1) * sizeof(T)));
+  IBF_HIP_CHECK(ibf::dev_malloc((void**)dst, std::max<size_t>(src.size(), 1) * sizeof(T)));
   if (!src.empty())
     IBF_HIP_CHECK(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
   return IBF_OK;

@@ -36,6 +36,16 @@ struct Geo {
 
 void set_error(const std::string& msg);
 
+// Device memory owned by plans and batches: from the caller's allocator when
+// one is installed (ibf_set_allocator), else hipMalloc / hipFree.  A block is
+// released through the allocator that made it.
+hipError_t dev_malloc_raw(void** ptr, size_t bytes);
+hipError_t dev_free(void* ptr);
+template <typename T>
+inline hipError_t dev_malloc(T** ptr, size_t bytes) {
+  return dev_malloc_raw(reinterpret_cast<void**>(ptr), bytes);
+}
+
 // Stored factors of one compressed level stage, in the plan's precision.
 struct Stage {
   int level_out;     // output coefficient level (l0+1 .. L-l0)

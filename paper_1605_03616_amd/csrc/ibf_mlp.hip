@@ -302,7 +302,7 @@ int ibf_mlp_select(const float* params, int n_hidden, int64_t n, int phase_id, d
   }
   const hipStream_t s = static_cast<hipStream_t>(stream);
   float* d = nullptr;
-  IBF_HIP_CHECK(hipMalloc(&d, sizeof(float) * (X.size() + Y.size())));
+  IBF_HIP_CHECK(ibf::dev_malloc(&d, sizeof(float) * (X.size() + Y.size())));
   int rc = IBF_OK;
   hipError_t e = hipMemcpyAsync(d, X.data(), sizeof(float) * X.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) {
@@ -313,7 +313,7 @@ int ibf_mlp_select(const float* params, int n_hidden, int64_t n, int phase_id, d
       if (e == hipSuccess) e = hipStreamSynchronize(s);
     }
   }
-  (void)hipFree(d);
+  (void)ibf::dev_free(d);
   if (rc) return rc;
   IBF_HIP_CHECK(e);
   const double lt = std::log10(tol);

@@ -11,6 +11,9 @@
 #include <cstring>
 #include <numeric>
 
+#include <mutex>
+#include <unordered_map>
+
 #include "ibf_internal.h"
 
 namespace {
@@ -44,18 +47,61 @@ void sort_into_leaves(const std::vector<int64_t>& leaf_of, int64_t nleaf,
 }
 }  // namespace
 
+namespace {
+// the installed allocator pair, and the pair that made each live block
+std::mutex g_alloc_mu;
+ibf_alloc_fn g_alloc = nullptr;
+ibf_free_fn g_free = nullptr;
+std::unordered_map<void*, ibf_free_fn> g_hooked;
+}  // namespace
+
 namespace ibf {
 void set_error(const std::string& msg) { g_last_error = msg; }
+
+hipError_t dev_malloc_raw(void** ptr, size_t bytes) {
+  ibf_alloc_fn a;
+  ibf_free_fn f;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    a = g_alloc;
+    f = g_free;
+  }
+  if (!a) return hipMalloc(ptr, bytes);
+  void* q = a(bytes, nullptr);
+  *ptr = q;
+  if (!q) return hipErrorOutOfMemory;
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_hooked[q] = f;
+  return hipSuccess;
+}
+
+hipError_t dev_free(void* ptr) {
+  if (!ptr) return hipSuccess;
+  ibf_free_fn f = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    auto it = g_hooked.find(ptr);
+    if (it != g_hooked.end()) {
+      f = it->second;
+      g_hooked.erase(it);
+    }
+  }
+  if (!f) return hipFree(ptr);
+  // hipFree waits for the device; an allocator's free need not
+  const hipError_t e = hipDeviceSynchronize();
+  f(ptr, nullptr);
+  return e;
+}
 
 size_t complex_bytes(int precision) { return precision == IBF_FP64 ? 16 : 8; }
 
 void free_factors(ibf_plan_t p) {
   for (auto& st : p->stages)
-    if (st.blk) (void)hipFree(st.blk);
+    if (st.blk) (void)ibf::dev_free(st.blk);
   p->stages.clear();
   void** bufs[] = {&p->d_vbar, &p->d_ubar, &p->d_mdot, &p->d_work[0], &p->d_work[1]};
   for (void** b : bufs) {
-    if (*b) (void)hipFree(*b);
+    if (*b) (void)ibf::dev_free(*b);
     *b = nullptr;
   }
   p->work_bytes = 0;
@@ -239,6 +285,17 @@ int ibf_query(ibf_plan_t p, ibf_info* info) {
   return IBF_OK;
 }
 
+int ibf_set_allocator(ibf_alloc_fn alloc, ibf_free_fn free_fn) {
+  if (!alloc != !free_fn) {
+    ibf::set_error("ibf_set_allocator: give both functions or neither");
+    return IBF_ERR_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc = alloc;
+  g_free = free_fn;
+  return IBF_OK;
+}
+
 int ibf_destroy(ibf_plan_t p) {
   if (!p) return IBF_OK;
   if (p->dim == 2) {
@@ -257,7 +314,7 @@ int ibf_destroy(ibf_plan_t p) {
   void* bufs[] = {p->d_xs, p->d_xis, p->d_perm_x, p->d_perm_xi,
                   p->d_xoff, p->d_xioff, p->d_xleaf, p->d_xileaf};
   for (void* b : bufs)
-    if (b) (void)hipFree(b);
+    if (b) (void)ibf::dev_free(b);
   (void)hipSetDevice(cur);
   delete p;
   return IBF_OK;

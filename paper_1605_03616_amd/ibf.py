@@ -24,7 +24,7 @@ EXPORTED = ["ibf_plan", "ibf_build", "ibf_apply", "ibf_apply_profile", "ibf_quer
             "ibf_destroy", "ibf_last_error", "ibf_eval_kernel", "ibf_batch_create",
             "ibf_apply_batch", "ibf_batch_destroy", "ibf_dense_apply", "ibf_mlp_n_params",
             "ibf_mlp_features", "ibf_mlp_forward", "ibf_mlp_grad_work", "ibf_mlp_loss_grad",
-            "ibf_mlp_adam", "ibf_mlp_select", "ibf_tune", "ibf_set_tuning"]
+            "ibf_mlp_adam", "ibf_mlp_select", "ibf_tune", "ibf_set_tuning", "ibf_set_allocator"]
 MLP_FEATURES = 5
 BATCH_GRAPH = 1
 PROFILE_MAX = 64
@@ -131,14 +131,45 @@ def load(path: str = LIB_PATH):
     lib.ibf_tune.argtypes = [vp, vp, i64, vp, i64, i64, vp, C.POINTER(IBFTuning),
                              C.POINTER(IBFTuning)]
     lib.ibf_set_tuning.argtypes = [vp, i64, C.POINTER(IBFTuning)]
+    lib.ibf_set_allocator.argtypes = [ALLOC_FN, FREE_FN]
     for name in ("ibf_plan", "ibf_build", "ibf_apply", "ibf_apply_profile", "ibf_query",
                  "ibf_destroy", "ibf_eval_kernel", "ibf_batch_create", "ibf_apply_batch",
                  "ibf_batch_destroy", "ibf_dense_apply", "ibf_mlp_n_params",
                  "ibf_mlp_features", "ibf_mlp_forward", "ibf_mlp_loss_grad", "ibf_mlp_adam",
-                 "ibf_mlp_select", "ibf_tune", "ibf_set_tuning"):
+                 "ibf_mlp_select", "ibf_tune", "ibf_set_tuning", "ibf_set_allocator"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+# every allocator pair ever installed stays referenced: blocks it made are
+# returned through it, possibly long after another pair was installed
+_installed_allocators = []
+
+
+def use_torch_allocator(enable: bool = True):
+    """ibf_set_allocator with PyTorch's caching allocator (enable=True) or
+    back to hipMalloc / hipFree (enable=False)."""
+    lib = load()
+    if not enable:
+        _check(lib.ibf_set_allocator(ALLOC_FN(), FREE_FN()))
+        return
+    import torch
+
+    def _alloc(nbytes, _stream):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device())
+        except Exception:                      # reported as OOM by the library
+            return None
+
+    def _free(ptr, _stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    pair = (ALLOC_FN(_alloc), FREE_FN(_free))
+    _installed_allocators.append(pair)
+    _check(lib.ibf_set_allocator(*pair))
 
 
 def last_error() -> str:

@@ -114,6 +114,14 @@ def test_set_tuning_validates_host_only():
     p64.destroy()
 
 
+def test_set_allocator_arguments():
+    # host only: installs or clears the hook, no device call
+    lib = ibf.load()
+    a = ibf.ALLOC_FN(lambda n, s: None)
+    assert lib.ibf_set_allocator(a, ibf.FREE_FN()) == -1          # one of the two
+    assert lib.ibf_set_allocator(ibf.ALLOC_FN(), ibf.FREE_FN()) == 0
+
+
 def test_mlp_feature_map_matches_oracle():
     # host-only entry point: the predictor's features against the oracle's
     from oracle import mlp_oracle as M
