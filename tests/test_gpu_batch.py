@@ -128,3 +128,32 @@ def test_batch_rejects_bad_input(torch_dev, built):
     with pytest.raises(RuntimeError, match="INVALID_ARG"):
         B.apply(gs[:-1] + [gs[0]], graph=False)   # wrong leading dimension for the last plan
     B.destroy()
+
+
+def test_batch_mixed_installed_schedules(torch_dev):
+    """Members with installed schedules in one batch: 16-column MFMA chunks
+    for 1 to 8 RHS (some with at most 3 stages a launch) mixed with default
+    (vector) members, problems of about 2^14 to 2^15.5 points: eager and
+    graph-replayed batches against the single-plan applies with the same
+    schedules."""
+    from paper_1605_03616_amd import ibf
+    torch = torch_dev
+    probs = I.workload_batched(count=8, seed=5, r=10, lo=13.5, hi=15.5)
+    _say(f"mixed-schedule batch, N={[p.n for p in probs]}")
+    plans = [ibf.Plan.from_problem(P).build() for P in probs]
+    for i, (pl, P) in enumerate(zip(plans, probs)):
+        if i % 3 != 2:
+            pl.set_tuning(P.nrhs, "mfma", 16, 3 if i % 2 else 0)
+    gs = [torch.from_numpy(np.ascontiguousarray(P.g.T)).to(torch.complex64).cuda()
+          for P in probs]
+    ref = [pl.apply(g).cpu().numpy() for pl, g in zip(plans, gs)]
+    B = ibf.Batch(plans)
+    for graph in (False, True, True):
+        us = B.apply(gs, graph=graph)
+        torch.cuda.synchronize()
+        for i, (u, r) in enumerate(zip(us, ref)):
+            err = _rel(u.cpu().numpy(), r)
+            assert err <= 1e-6, (graph, i, probs[i].n, err)
+    B.destroy()
+    for pl in plans:
+        pl.destroy()
