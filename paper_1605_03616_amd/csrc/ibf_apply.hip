@@ -604,14 +604,19 @@ __device__ __forceinline__ void fused_mfma_body(const FusedDesc& D, int64_t lb, 
     if constexpr (MID) {
       // the middle block on each input pair (the lane's own slot), with
       // stage 0's factors in flight
-      fb.load(SF::stage_block(blk0, fs0, k, 0, k - 1, cur.gid0, sh_end, L, A.l_start), fs0);
+      // fs0 laundered: its clamped offsets are not hoisted out of the
+      // persistent loop (they would stay live in VGPRs across every stage)
+      int fs0_v = fs0;
+      asm volatile("" : "+s"(fs0_v));
+      fb.load(SF::stage_block(blk0, fs0_v, k, 0, k - 1, cur.gid0, sh_end, L, A.l_start), fs0_v);
       v4f P[KG], Q[KG];
       run_product(kmo, S + (size_t)vs * kin0 * NB + col,
                   reinterpret_cast<const float*>(F + (size_t)vs * slot_stride(fsml)) + fi,
                   2 * kldm, kin0, P, Q);
       __syncthreads();                                        // S and F reads done
       put_rows(P, Q, kmo);
-      fb.store(F, fs0);
+      asm volatile("" : "+s"(fs0_v));
+      fb.store(F, fs0_v);
       __syncthreads();
     }
     // one stage; the last one is peeled off the stage loop so that the next
