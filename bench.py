@@ -42,11 +42,11 @@ MEASURED_TRAFFIC = {
     # (workload, schedule path/chunk/max_fused) -> (sha1 of the apply source,
     #   kernel class, [(launches per step, FETCH_SIZE KiB, WRITE_SIZE KiB), ...])
     ("fio1d_n65536_r12_fp32", "default/0/0"): (
-        "2c5a5d96d6f052181be52c40b9a4d9b100511895", "apply_fused_mfma",
-        [(2, 332306, 344064), (1, 263447, 294912)]),
+        "c75cded0119bda077fedd7ea8c9d8b2494e4c4c7", "apply_fused_mfma",
+        [(2, 332253, 344064), (1, 263626, 294912)]),
     ("nudft_n1048576_r10", "default/0/0"): (
-        "2c5a5d96d6f052181be52c40b9a4d9b100511895", "apply_fused_mfma",
-        [(1, 2871420, 917504), (2, 1867870, 983040), (1, 1769580, 917504)]),
+        "c75cded0119bda077fedd7ea8c9d8b2494e4c4c7", "apply_fused_mfma",
+        [(1, 2871420, 917504), (2, 1867870, 983040), (1, 1769570, 917504)]),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
