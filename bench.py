@@ -107,7 +107,7 @@ def _roofline(launches, bound, peak, unit):
     }, {k: {"ms": round(v[0], 4), "launches": v[3]} for k, v in by.items()}
 
 
-def _cpu_baseline(P, nrhs_sample=4):
+def _cpu_baseline(P, nrhs_sample=20):
     """Time the FP64 oracle's IBF apply on the host: full oracle build (not
     timed), then the apply of `nrhs_sample` columns, scaled to the metric."""
     from oracle import ibf_oracle as O
