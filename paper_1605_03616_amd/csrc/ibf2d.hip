@@ -69,6 +69,14 @@ struct Box2 {
   int64_t nnz_prelim = 0, nnz_opt = 0;
 };
 
+// one batched launch of the 2-D apply: V of every box, or stage j of every
+// box that has one (descriptor array and block offsets in the plan's table)
+struct Launch2 {
+  size_t desc_off = 0, boff_off = 0, lds = 0;
+  int count = 0;
+  int64_t nblocks = 0;
+};
+
 struct Mibf2D {
   PhaseDesc ph{};
   int r = 0, R2 = 0, leaf_side = 0, precision = 0, device = 0;
@@ -98,6 +106,14 @@ struct Mibf2D {
   hipGraphExec_t exec = nullptr;
   std::vector<int64_t> graph_key;
   bool graph_failed = false;   // capture refused once: direct launches from then on
+  // batched launches (V, then one launch per stage index over the boxes),
+  // their table written for table_key = (nrhs, workspace); batched == false
+  // when some box needs the unbatched kernels
+  void* d_table = nullptr;
+  size_t table_bytes = 0;
+  std::vector<int64_t> table_key;
+  std::vector<Launch2> launches;
+  bool batched = false;
   bool built = false;
   int64_t nnz_prelim = 0, nnz_opt = 0, nnz_stored = 0, factor_bytes = 0;
   int maxL = 0;
@@ -721,17 +737,16 @@ __global__ void k2_apply_v(const VT* __restrict__ g, int64_t ldg, const int32_t*
 // columns: per input row one factor entry (the threads t of a pair read a
 // contiguous factor row) and one broadcast LDS row.
 template <typename VT, typename FT, int NR>
-__global__ __launch_bounds__(kB2) void k2_apply_stage_quad(const VT* __restrict__ in,
-                                                          VT* __restrict__ out,
-                                                          const FT* __restrict__ blk, int L,
-                                                          int l, int kin, int kout, int kld,
-                                                          int nrhs, int qb, int nchunk) {
+__device__ __forceinline__ void stage_quad_body(const VT* __restrict__ in, VT* __restrict__ out,
+                                                const FT* __restrict__ blk, int L, int l,
+                                                int kin, int kout, int kld, int nrhs, int qb,
+                                                int nchunk, int64_t lb) {
   extern __shared__ __align__(16) unsigned char smem2[];
   VT* xs = reinterpret_cast<VT*>(smem2);                      // [qb][4 kin][NR]
   const int sh = 2 * (L - l);
   const int64_t nquad = (int64_t)1 << (2 * L - 2);
-  const int64_t q0 = (int64_t)(blockIdx.x / nchunk) * qb;
-  const int n0 = (int)(blockIdx.x % nchunk) * NR;
+  const int64_t q0 = (lb / nchunk) * qb;
+  const int n0 = (int)(lb % nchunk) * NR;
   const int nw = min(NR, nrhs - n0);
   const int rows = 4 * kin;
   // stage the quads' input rows (columns past the chunk are zero)
@@ -778,6 +793,46 @@ __global__ __launch_bounds__(kB2) void k2_apply_stage_quad(const VT* __restrict_
 #pragma unroll
   for (int n = 0; n < NR; ++n)
     if (n < nw) o[n] = acc[n];
+}
+template <typename VT, typename FT, int NR>
+__global__ __launch_bounds__(kB2) void k2_apply_stage_quad(const VT* __restrict__ in,
+                                                          VT* __restrict__ out,
+                                                          const FT* __restrict__ blk, int L,
+                                                          int l, int kin, int kout, int kld,
+                                                          int nrhs, int qb, int nchunk) {
+  stage_quad_body<VT, FT, NR>(in, out, blk, L, l, kin, kout, kld, nrhs, qb, nchunk,
+                              blockIdx.x);
+}
+
+// Batched launches over the boxes: box p owns logical blocks [boff[p], boff[p+1]).
+__device__ __forceinline__ int box_of_block(const int64_t* __restrict__ boff, int count,
+                                            int64_t b) {
+  int lo = 0, hi = count - 1;                                 // largest p with boff[p] <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (boff[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// one box's quadtree stage in a batched launch (the boxes' stages of one
+// index together: a box's stages run in launch order)
+struct Stage2Desc {
+  const void* in;
+  void* out;
+  const void* blk;
+  int L, l, kin, kout, kld, qb;
+};
+template <typename VT, typename FT, int NR>
+__global__ __launch_bounds__(kB2) void k2_batch_stage_quad(const Stage2Desc* __restrict__ ds,
+                                                          const int64_t* __restrict__ boff,
+                                                          int count, int nrhs, int nchunk) {
+  const int p = box_of_block(boff, count, blockIdx.x);
+  const Stage2Desc& D = ds[p];
+  stage_quad_body<VT, FT, NR>(reinterpret_cast<const VT*>(D.in), reinterpret_cast<VT*>(D.out),
+                              reinterpret_cast<const FT*>(D.blk), D.L, D.l, D.kin, D.kout, D.kld,
+                              nrhs, D.qb, nchunk, (int64_t)blockIdx.x - boff[p]);
 }
 
 // out[(a, b)][t][n] = sum_{row < 4 kin} F[(a, b)][row][t] in[(a >> 2, 4b) row][n]
@@ -826,18 +881,18 @@ __global__ void k2_apply_centre(const FT* __restrict__ kc, int nc,
 // over the leaf's points; the leaf's g rows are staged in LDS, and the threads
 // of a point read its Vbar row [a][k] contiguously.
 template <typename VT, typename FT, int NR>
-__global__ __launch_bounds__(kB2) void k2_apply_v_rows(const VT* __restrict__ g, int64_t ldg,
-                                                      const int32_t* __restrict__ perm,
-                                                      const int32_t* __restrict__ off,
-                                                      const FT* __restrict__ vbar,
-                                                      VT* __restrict__ mu, int lV, int lO, int K,
-                                                      int nrhs, int smax, int nchunk) {
+__device__ __forceinline__ void v_rows_body(const VT* __restrict__ g, int64_t ldg,
+                                            const int32_t* __restrict__ perm,
+                                            const int32_t* __restrict__ off,
+                                            const FT* __restrict__ vbar, VT* __restrict__ mu,
+                                            int lV, int lO, int K, int nrhs, int nchunk,
+                                            int64_t lb) {
   extern __shared__ __align__(16) unsigned char smem2[];
   VT* gl = reinterpret_cast<VT*>(smem2);                      // [smax][NR]
   const int na = 1 << (2 * lV);
   const int64_t nb = (int64_t)1 << (2 * lO);
-  const int64_t b = blockIdx.x / nchunk;
-  const int n0 = (int)(blockIdx.x % nchunk) * NR, nw = min(NR, nrhs - n0);
+  const int64_t b = lb / nchunk;
+  const int n0 = (int)(lb % nchunk) * NR, nw = min(NR, nrhs - n0);
   const int32_t i0 = off[b], cnt = off[b + 1] - i0;
   for (int e = threadIdx.x; e < cnt * NR; e += kB2) {
     const int j = e / NR, n = e % NR;
@@ -859,6 +914,35 @@ __global__ __launch_bounds__(kB2) void k2_apply_v_rows(const VT* __restrict__ g,
     for (int n = 0; n < NR; ++n)
       if (n < nw) o[n] = acc[n];
   }
+}
+template <typename VT, typename FT, int NR>
+__global__ __launch_bounds__(kB2) void k2_apply_v_rows(const VT* __restrict__ g, int64_t ldg,
+                                                      const int32_t* __restrict__ perm,
+                                                      const int32_t* __restrict__ off,
+                                                      const FT* __restrict__ vbar,
+                                                      VT* __restrict__ mu, int lV, int lO, int K,
+                                                      int nrhs, int smax, int nchunk) {
+  (void)smax;
+  v_rows_body<VT, FT, NR>(g, ldg, perm, off, vbar, mu, lV, lO, K, nrhs, nchunk, blockIdx.x);
+}
+// V of every box in one launch
+struct V2Desc {
+  const int32_t* perm;
+  const int32_t* off;
+  const void* vbar;
+  void* mu;
+  int lV, lO, K;
+};
+template <typename VT, typename FT, int NR>
+__global__ __launch_bounds__(kB2) void k2_batch_v_rows(const V2Desc* __restrict__ ds,
+                                                      const int64_t* __restrict__ boff, int count,
+                                                      const VT* __restrict__ g, int64_t ldg,
+                                                      int nrhs, int nchunk) {
+  const int p = box_of_block(boff, count, blockIdx.x);
+  const V2Desc& D = ds[p];
+  v_rows_body<VT, FT, NR>(g, ldg, D.perm, D.off, reinterpret_cast<const FT*>(D.vbar),
+                          reinterpret_cast<VT*>(D.mu), D.lV, D.lO, D.K, nrhs, nchunk,
+                          (int64_t)blockIdx.x - boff[p]);
 }
 
 // U of the boxes that share one X tree, in one launch: thread = one X point
@@ -1210,6 +1294,104 @@ template <typename VT, typename FT>
 int launch2d_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int nrhs,
                hipStream_t s, const std::vector<size_t>& off);
 
+constexpr int kNR2 = 8;                                       // RHS columns a pass
+
+// quads a block of the quad-grouped stage kernel: threads (4 kout each) and
+// staged rows (<= 48 KB)
+template <typename VT>
+int stage_qb(const Stage2& st) {
+  return std::max(1, std::min(kB2 / (4 * st.kout),
+                              (int)((48 * 1024) / ((size_t)4 * st.kin * kNR2 * sizeof(VT)))));
+}
+
+// The batched launch plan and its descriptor table for nrhs right-hand sides
+// and the current workspace (box ib's coefficient buffers at off[ib]).
+// Written only when (nrhs, workspace) changes, after the stream has drained.
+template <typename VT, typename FT>
+int prepare_batched2d(ibf_plan_t p, int nrhs, const std::vector<size_t>& off, hipStream_t s) {
+  Mibf2D& M = *p->mibf;
+  const std::vector<int64_t> key = {nrhs, (int64_t)(uintptr_t)M.d_work};
+  if (key == M.table_key) return IBF_OK;
+  const int nbox = (int)M.boxes.size();
+  const int nchunk = (nrhs + kNR2 - 1) / kNR2;
+  bool ok = nbox > 0;
+  size_t maxs = 0;
+  for (const Box2& bx : M.boxes) maxs = std::max(maxs, bx.stages.size());
+  std::vector<Launch2> launches(1 + maxs);
+  std::vector<unsigned char> host;
+  auto align16 = [](size_t v) { return (v + 15) & ~(size_t)15; };
+  auto buf = [&](int ib, int which) {
+    char* wb = static_cast<char*>(M.d_work) + off[ib];
+    return static_cast<void*>(wb + which * ((off[ib + 1] - off[ib]) / 2));
+  };
+  // V of every box
+  {
+    std::vector<V2Desc> d;
+    std::vector<int64_t> bo{0};
+    Launch2& x = launches[0];
+    for (int ib = 0; ib < nbox; ++ib) {
+      const Box2& bx = M.boxes[ib];
+      const int lO = bx.L - bx.lV;
+      d.push_back(V2Desc{bx.d_perm_xi, bx.d_xioff, bx.d_vbar, buf(ib, 0), bx.lV, lO, bx.K_V});
+      bo.push_back(bo.back() + ((int64_t)1 << (2 * lO)) * nchunk);
+      x.lds = std::max(x.lds, (size_t)bx.smax_xi * kNR2 * sizeof(VT));
+    }
+    x.count = nbox;
+    x.nblocks = bo.back();
+    x.desc_off = host.size();
+    host.resize(align16(host.size() + d.size() * sizeof(V2Desc)));
+    std::memcpy(host.data() + x.desc_off, d.data(), d.size() * sizeof(V2Desc));
+    x.boff_off = host.size();
+    host.resize(align16(host.size() + bo.size() * sizeof(int64_t)));
+    std::memcpy(host.data() + x.boff_off, bo.data(), bo.size() * sizeof(int64_t));
+    ok = ok && x.lds <= 64 * 1024;
+  }
+  // stage j of every box that has one: box ib reads buffer j % 2, writes the other
+  for (size_t j = 0; j < maxs; ++j) {
+    std::vector<Stage2Desc> d;
+    std::vector<int64_t> bo{0};
+    Launch2& x = launches[1 + j];
+    for (int ib = 0; ib < nbox; ++ib) {
+      const Box2& bx = M.boxes[ib];
+      if (j >= bx.stages.size()) continue;
+      const Stage2& st = bx.stages[j];
+      const int qb = stage_qb<VT>(st);
+      const size_t lds = (size_t)qb * 4 * st.kin * kNR2 * sizeof(VT);
+      const int64_t nquad = (int64_t)1 << (2 * bx.L - 2);
+      ok = ok && 4 * st.kout <= kB2 && lds <= 64 * 1024;
+      d.push_back(Stage2Desc{buf(ib, (int)(j & 1)), buf(ib, (int)((j + 1) & 1)), st.blk, bx.L,
+                             st.level, st.kin, st.kout, st.kld, qb});
+      bo.push_back(bo.back() + (nquad + qb - 1) / qb * nchunk);
+      x.lds = std::max(x.lds, lds);
+    }
+    x.count = (int)d.size();
+    x.nblocks = bo.back();
+    x.desc_off = host.size();
+    host.resize(align16(host.size() + d.size() * sizeof(Stage2Desc)));
+    std::memcpy(host.data() + x.desc_off, d.data(), d.size() * sizeof(Stage2Desc));
+    x.boff_off = host.size();
+    host.resize(align16(host.size() + bo.size() * sizeof(int64_t)));
+    std::memcpy(host.data() + x.boff_off, bo.data(), bo.size() * sizeof(int64_t));
+  }
+  for (const Launch2& x : launches) ok = ok && x.nblocks < 0x7fffffff;
+  M.batched = false;
+  if (ok) {
+    IBF_HIP_CHECK(hipStreamSynchronize(s));                   // no apply still reads the table
+    if (host.size() > M.table_bytes) {
+      if (M.d_table) IBF_HIP_CHECK(ibf::dev_free(M.d_table));
+      M.d_table = nullptr;
+      M.table_bytes = 0;
+      IBF_HIP_CHECK(ibf::dev_malloc(&M.d_table, host.size()));
+      M.table_bytes = host.size();
+    }
+    IBF_HIP_CHECK(hipMemcpy(M.d_table, host.data(), host.size(), hipMemcpyHostToDevice));
+    M.launches = launches;
+    M.batched = true;
+  }
+  M.table_key = key;
+  return IBF_OK;
+}
+
 template <typename VT, typename FT>
 int apply2d_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int nrhs,
               hipStream_t s) {
@@ -1243,10 +1425,15 @@ int apply2d_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, in
     for (int i = 0; i < nbox; ++i)
       IBF_HIP_CHECK(hipEventCreateWithFlags(&M.ev_u[i], hipEventDisableTiming));
   }
+  {
+    const int rc = prepare_batched2d<VT, FT>(p, nrhs, off, s);
+    if (rc) return rc;
+  }
   if (M.graph_failed || std::getenv("IBF_NO_GRAPH"))
     return launch2d_t<VT, FT>(p, g, ldg, u, ldu, nrhs, s, off);
   const std::vector<int64_t> key = {(int64_t)(uintptr_t)g, ldg, (int64_t)(uintptr_t)u, ldu,
-                                    nrhs, (int64_t)(uintptr_t)M.d_work};
+                                    nrhs, (int64_t)(uintptr_t)M.d_work,
+                                    (int64_t)(uintptr_t)M.d_table, (int64_t)M.batched};
   if (!M.exec || key != M.graph_key) {
     if (M.exec) (void)hipGraphExecDestroy(M.exec);
     if (M.graph) (void)hipGraphDestroy(M.graph);
@@ -1287,7 +1474,7 @@ int launch2d_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, i
   const int nbox = (int)M.boxes.size();
   const int nc = (int)M.centre.size();
   // the centre block writes every entry of u; the boxes then accumulate
-  constexpr int NR = 8;                                       // RHS columns a pass
+  constexpr int NR = kNR2;
   const int nchunk = (nrhs + NR - 1) / NR;
   {
     const size_t lds = ((size_t)nc * NR + (size_t)kB2 * 17) * sizeof(VT);
@@ -1303,8 +1490,33 @@ int launch2d_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, i
     }
     IBF_HIP_CHECK(hipGetLastError());
   }
-  if (nbox) IBF_HIP_CHECK(hipEventRecord(M.ev_start, s));
   std::vector<const void*> mu_final(nbox, nullptr);
+  if (M.batched) {
+    // one stream: V of every box, then stage j of every box per launch
+    const char* base = static_cast<const char*>(M.d_table);
+    {
+      const Launch2& x = M.launches[0];
+      hipLaunchKernelGGL((k2_batch_v_rows<VT, FT, NR>), dim3((unsigned)x.nblocks), dim3(kB2),
+                         x.lds, s, reinterpret_cast<const V2Desc*>(base + x.desc_off),
+                         reinterpret_cast<const int64_t*>(base + x.boff_off), x.count,
+                         (const VT*)g, ldg, nrhs, nchunk);
+      IBF_HIP_CHECK(hipGetLastError());
+    }
+    for (size_t j = 1; j < M.launches.size(); ++j) {
+      const Launch2& x = M.launches[j];
+      hipLaunchKernelGGL((k2_batch_stage_quad<VT, FT, NR>), dim3((unsigned)x.nblocks),
+                         dim3(kB2), x.lds, s,
+                         reinterpret_cast<const Stage2Desc*>(base + x.desc_off),
+                         reinterpret_cast<const int64_t*>(base + x.boff_off), x.count, nrhs,
+                         nchunk);
+      IBF_HIP_CHECK(hipGetLastError());
+    }
+    for (int ib = 0; ib < nbox; ++ib) {
+      char* wb = static_cast<char*>(M.d_work) + off[ib];
+      mu_final[ib] = wb + (M.boxes[ib].stages.size() & 1) * ((off[ib + 1] - off[ib]) / 2);
+    }
+  } else {
+  if (nbox) IBF_HIP_CHECK(hipEventRecord(M.ev_start, s));
   for (int ib = 0; ib < nbox; ++ib) {
     const Box2& bx = M.boxes[ib];
     hipStream_t bs = M.streams[ib % M.streams.size()];
@@ -1331,10 +1543,7 @@ int launch2d_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, i
     int cur = 0;
     for (const Stage2& st : bx.stages) {
       const int64_t nquad = (int64_t)1 << (2 * bx.L - 2);
-      // quads a block: threads (4 kout each) and staged rows (<= 48 KB)
-      const int qb = std::max(1, std::min(kB2 / (4 * st.kout),
-                                          (int)((48 * 1024) / ((size_t)4 * st.kin * NR *
-                                                               sizeof(VT)))));
+      const int qb = stage_qb<VT>(st);
       const size_t lds = (size_t)qb * 4 * st.kin * NR * sizeof(VT);
       const int64_t nb = (nquad + qb - 1) / qb * nchunk;
       if (4 * st.kout <= kB2 && lds <= 64 * 1024 && nb < 0x7fffffff) {
@@ -1352,6 +1561,7 @@ int launch2d_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, i
     }
     mu_final[ib] = w[cur];
     IBF_HIP_CHECK(hipEventRecord(M.ev_u[ib], bs));
+  }
   }
   // U on the caller's stream, one launch per X tree (at most kTreeBoxes boxes
   // a launch), each after its boxes' stages: u accumulates in tree order,
@@ -1371,7 +1581,7 @@ int launch2d_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, i
     for (int ib = 0; ib < nbox; ++ib) {
       const Box2& bx = M.boxes[ib];
       if (bx.xt != t) continue;
-      IBF_HIP_CHECK(hipStreamWaitEvent(s, M.ev_u[ib], 0));
+      if (!M.batched) IBF_HIP_CHECK(hipStreamWaitEvent(s, M.ev_u[ib], 0));
       T.mu[T.nb] = mu_final[ib];
       T.ubar[T.nb] = bx.d_ubar;
       T.K[T.nb] = bx.K_U;
@@ -1671,6 +1881,12 @@ void free2d_factors(ibf_plan_t p) {
   if (M.exec) (void)hipGraphExecDestroy(M.exec);
   if (M.graph) (void)hipGraphDestroy(M.graph);
   if (M.cap) (void)hipStreamDestroy(M.cap);
+  fr(M.d_table);
+  M.d_table = nullptr;
+  M.table_bytes = 0;
+  M.table_key.clear();
+  M.launches.clear();
+  M.batched = false;
   M.exec = nullptr;
   M.graph = nullptr;
   M.cap = nullptr;
