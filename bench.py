@@ -352,6 +352,8 @@ def main():
     ap.add_argument("--schedule", default=None, metavar="PATH/CHUNK/MAX_FUSED",
                     help="install this apply schedule instead of tuning (e.g. mfma/32/3; "
                          "fixes the launches for profiling)")
+    ap.add_argument("--no-measured-peak", action="store_true",
+                    help="skip the measured copy / MFMA-loop peaks in the roofline")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 256 MiB elementwise copy first (HBM counter calibration)")
     ap.add_argument("--batch-count", type=int, default=256)
@@ -438,6 +440,15 @@ def main():
     roof["traffic"] = _measured_traffic(P.name, sched, dom)
     if roof["traffic"] is not None:
         roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)"
+    if not args.no_measured_peak:
+        # the same bound measured on this device: a plain 1 GiB copy, or a loop
+        # of the FP32 4x4x1 MFMA instruction the stage kernels issue
+        what = ibf.PEAK_HBM_COPY if bound == "hbm" else ibf.PEAK_MFMA_F32
+        mp = ibf.measure_peak(what)
+        roof["measured_peak"] = round(mp, 3)
+        roof["frac_measured"] = round(roof["achieved"] / mp, 4)
+        roof["measured_peak_kind"] = ("plain device copy, read + write" if bound == "hbm"
+                                      else "v_mfma_f32_4x4x1f32 loop, all CUs")
 
     out = {
         "metric": "IBF apply G(complex samples*RHS)/s at rel err 1e-5 vs plain FP64; build ms",

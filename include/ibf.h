@@ -215,6 +215,19 @@ typedef void* (*ibf_alloc_fn)(size_t bytes, void* hip_stream);
 typedef void (*ibf_free_fn)(void* ptr, void* hip_stream);
 int ibf_set_allocator(ibf_alloc_fn alloc, ibf_free_fn free_fn);
 
+/*
+ * Measured device peaks for roofline fractions (measurement support, not part
+ * of the method): IBF_PEAK_HBM_COPY times a plain 1 GiB device-to-device copy
+ * kernel and writes the read + write bandwidth in GB/s; IBF_PEAK_MFMA_F32
+ * times a loop of the FP32 MFMA instruction the stage kernels use
+ * (4 x 4 x 1, 16 blocks) on every compute unit and writes TFLOP/s.  Best of
+ * 5 timed runs after one warm-up, HIP events on hip_stream; synchronises the
+ * stream.  Allocates and frees its buffers (2 GiB for the copy).
+ * Errors: INVALID_ARG (NULL result, unknown `what`), OOM, DEVICE.
+ */
+enum { IBF_PEAK_HBM_COPY = 0, IBF_PEAK_MFMA_F32 = 1 };
+int ibf_measure_peak(int what, void* hip_stream, double* result);
+
 /* Free every host and device resource of the plan (NULL is a no-op). */
 int ibf_destroy(ibf_plan_t plan);
 

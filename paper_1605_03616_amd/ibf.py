@@ -24,7 +24,8 @@ EXPORTED = ["ibf_plan", "ibf_build", "ibf_apply", "ibf_apply_profile", "ibf_quer
             "ibf_destroy", "ibf_last_error", "ibf_eval_kernel", "ibf_batch_create",
             "ibf_apply_batch", "ibf_batch_destroy", "ibf_dense_apply", "ibf_mlp_n_params",
             "ibf_mlp_features", "ibf_mlp_forward", "ibf_mlp_grad_work", "ibf_mlp_loss_grad",
-            "ibf_mlp_adam", "ibf_mlp_select", "ibf_tune", "ibf_set_tuning", "ibf_set_allocator"]
+            "ibf_mlp_adam", "ibf_mlp_select", "ibf_tune", "ibf_set_tuning", "ibf_set_allocator",
+            "ibf_measure_peak"]
 MLP_FEATURES = 5
 BATCH_GRAPH = 1
 PROFILE_MAX = 64
@@ -132,11 +133,12 @@ def load(path: str = LIB_PATH):
                              C.POINTER(IBFTuning)]
     lib.ibf_set_tuning.argtypes = [vp, i64, C.POINTER(IBFTuning)]
     lib.ibf_set_allocator.argtypes = [ALLOC_FN, FREE_FN]
+    lib.ibf_measure_peak.argtypes = [C.c_int, vp, C.POINTER(C.c_double)]
     for name in ("ibf_plan", "ibf_build", "ibf_apply", "ibf_apply_profile", "ibf_query",
                  "ibf_destroy", "ibf_eval_kernel", "ibf_batch_create", "ibf_apply_batch",
                  "ibf_batch_destroy", "ibf_dense_apply", "ibf_mlp_n_params",
                  "ibf_mlp_features", "ibf_mlp_forward", "ibf_mlp_loss_grad", "ibf_mlp_adam",
-                 "ibf_mlp_select", "ibf_tune", "ibf_set_tuning", "ibf_set_allocator"):
+                 "ibf_mlp_select", "ibf_tune", "ibf_set_tuning", "ibf_set_allocator", "ibf_measure_peak"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -170,6 +172,18 @@ def use_torch_allocator(enable: bool = True):
     pair = (ALLOC_FN(_alloc), FREE_FN(_free))
     _installed_allocators.append(pair)
     _check(lib.ibf_set_allocator(*pair))
+
+
+PEAK_HBM_COPY, PEAK_MFMA_F32 = 0, 1
+
+
+def measure_peak(what: int, stream=None) -> float:
+    """ibf_measure_peak: GB/s of a plain device copy (PEAK_HBM_COPY) or
+    TFLOP/s of the FP32 4x4x1 MFMA loop (PEAK_MFMA_F32)."""
+    lib = load()
+    v = C.c_double()
+    _check(lib.ibf_measure_peak(int(what), _stream_handle(stream), C.byref(v)))
+    return float(v.value)
 
 
 def last_error() -> str:
