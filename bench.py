@@ -42,11 +42,11 @@ MEASURED_TRAFFIC = {
     # (workload, schedule path/chunk/max_fused) -> (sha1 of the apply source,
     #   kernel class, [(launches per step, FETCH_SIZE KiB, WRITE_SIZE KiB), ...])
     ("fio1d_n65536_r12_fp32", "default/0/0"): (
-        "c75cded0119bda077fedd7ea8c9d8b2494e4c4c7", "apply_fused_mfma",
-        [(2, 332253, 344064), (1, 263626, 294912)]),
+        "6adb7b1b64c8069682f65917087d52e5f0d94ea1", "apply_fused_mfma",
+        [(2, 331925, 344064), (1, 263465, 294912)]),
     ("nudft_n1048576_r10", "default/0/0"): (
-        "c75cded0119bda077fedd7ea8c9d8b2494e4c4c7", "apply_fused_mfma",
-        [(1, 2871420, 917504), (2, 1867870, 983040), (1, 1769570, 917504)]),
+        "6adb7b1b64c8069682f65917087d52e5f0d94ea1", "apply_fused_mfma",
+        [(2, 2424930, 983040), (1, 1769570, 917504), (1, 1822840, 1048576)]),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
@@ -178,7 +178,7 @@ def _bench_batched(args):
         t0 = time.perf_counter()
         picks = [pl.tune(g, u) for pl, g, u in zip(plans, gs, us)]
         torch.cuda.synchronize()
-        kinds = [f"{t['path']}/{t['chunk']}/{t['max_fused']}" for t in picks]
+        kinds = [f"{t['path']}/{t['chunk']}/{t['max_fused']}" + (f"/{t['split']}" if t['split'] else "") for t in picks]
         tune_info = {"tune_s": round(time.perf_counter() - t0, 3),
                      "choices": {k: kinds.count(k) for k in sorted(set(kinds))}}
         print(f"[bench] tuning: {tune_info}", file=sys.stderr, flush=True)
@@ -349,7 +349,7 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the schedule autotuner (apply with the default rule)")
-    ap.add_argument("--schedule", default=None, metavar="PATH/CHUNK/MAX_FUSED",
+    ap.add_argument("--schedule", default=None, metavar="PATH/CHUNK/MAX_FUSED[/SPLIT]",
                     help="install this apply schedule instead of tuning (e.g. mfma/32/3; "
                          "fixes the launches for profiling)")
     ap.add_argument("--no-measured-peak", action="store_true",
@@ -402,9 +402,12 @@ def main():
         del a, b
     tuning = None
     if args.schedule:        # a fixed schedule: no trial launches in a profile
-        path, chunk, fused = args.schedule.split("/")
-        pl.set_tuning(P.nrhs, path, int(chunk), int(fused))
-        tuning = {"path": path, "chunk": int(chunk), "max_fused": int(fused), "fixed": True}
+        f = args.schedule.split("/")
+        path, chunk, fused = f[0], int(f[1]), int(f[2])
+        split = int(f[3]) if len(f) > 3 else 0
+        pl.set_tuning(P.nrhs, path, chunk, fused, split)
+        tuning = {"path": path, "chunk": chunk, "max_fused": fused, "split": split,
+                  "fixed": True}
     elif not args.no_tune:   # schedule autotuner, before the timed region
         tuning = pl.tune(g, u)
         torch.cuda.synchronize()
@@ -437,6 +440,8 @@ def main():
     dom, roof, per_class = _roofline(launches, bound, peak, unit)
     sched = (f"{tuning['path']}/{tuning['chunk']}/{tuning['max_fused']}" if tuning
              else "default/0/0")
+    if tuning and tuning.get("split"):
+        sched += f"/{tuning['split']}"
     roof["traffic"] = _measured_traffic(P.name, sched, dom)
     if roof["traffic"] is not None:
         roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)"

@@ -170,7 +170,8 @@ int ibf_apply_profile(ibf_plan_t plan, const void* g, int64_t ldg, void* u,
  * plan: later ibf_apply calls with this nrhs, and batches containing the plan,
  * use it.  Candidates: the default rule; butterfly stages on the vector
  * kernels; on MFMA (FP32 state) with 32- or 16-column RHS chunks; at most 2 or
- * 3 stages fused per launch.  Every candidate computes the same product (to
+ * 3 stages fused per launch; fused groups ending where the stage tile (the
+ * even cover of the ranks) changes.  Every candidate computes the same product (to
  * FP32 rounding).  Synchronises the stream (not for use under graph capture).
  * *best receives the chosen schedule and its time, *dflt the default rule's
  * time (either may be NULL).
@@ -181,6 +182,9 @@ typedef struct {
   int chunk;       /* MFMA RHS chunk width (32 or 16; 0 = by nrhs) */
   int max_fused;   /* most stages fused per launch (0 = as LDS allows) */
   float ms;        /* measured time of one apply */
+  int split;       /* fused groups end: 0 as they fit (the default rule: 1
+                      for MFMA stages); 1 before a stage whose ranks fit a
+                      smaller tile; 2 before any tile change */
 } ibf_tuning;
 int ibf_tune(ibf_plan_t plan, const void* g, int64_t ldg, void* u, int64_t ldu,
              int64_t nrhs, void* hip_stream, ibf_tuning* best, ibf_tuning* dflt);
@@ -192,7 +196,7 @@ int ibf_tune(ibf_plan_t plan, const void* g, int64_t ldg, void* u, int64_t ldu,
  * t->ms is ignored.  Same product as ibf_apply (Sec. 4).  Host only: no
  * device call, no allocation.
  * Errors: INVALID_ARG (NULL plan, nrhs < 1, path outside 0..2, chunk not 0,
- * 16 or 32, max_fused < 0); UNSUPPORTED for dim-2 plans and for path 2 on
+ * 16 or 32, max_fused < 0, split outside 0..2); UNSUPPORTED for dim-2 plans and for path 2 on
  * FP64 plans (no FP64 MFMA stage kernel).
  */
 int ibf_set_tuning(ibf_plan_t plan, int64_t nrhs, const ibf_tuning* t);

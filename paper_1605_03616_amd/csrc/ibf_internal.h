@@ -16,9 +16,10 @@ constexpr int kMaxR = 16;          // Chebyshev points per box supported on devi
 
 // Apply schedule knobs (ibf_tune): path 0 default rule / 1 vector / 2 MFMA
 // stage kernels, MFMA chunk width (0: by nrhs), most stages fused (0: as LDS
-// allows)
+// allows), where fused groups end (0: as they fit; 1: before a stage whose
+// own block rows fit a smaller tile; 2: before any stage of another tile)
 struct Tuning {
-  int path = 0, chunk = 0, max_fused = 0;
+  int path = 0, chunk = 0, max_fused = 0, split = 0;
 };
 constexpr int kMaxParams = 6;
 

@@ -70,7 +70,8 @@ class IBFInfo(C.Structure):
 
 
 class IBFTuning(C.Structure):
-    _fields_ = [("path", C.c_int), ("chunk", C.c_int), ("max_fused", C.c_int), ("ms", C.c_float)]
+    _fields_ = [("path", C.c_int), ("chunk", C.c_int), ("max_fused", C.c_int), ("ms", C.c_float),
+                ("split", C.c_int)]
 
 
 class IBFProfile(C.Structure):
@@ -303,16 +304,17 @@ class Plan:
                                   C.c_void_p(u.data_ptr()), u.shape[1], g.shape[0],
                                   _stream_handle(stream), C.byref(best), C.byref(dflt)))
         return {"path": ["default", "vector", "mfma"][best.path], "chunk": best.chunk,
-                "max_fused": best.max_fused, "ms": float(best.ms), "default_ms": float(dflt.ms)}
+                "max_fused": best.max_fused, "split": best.split, "ms": float(best.ms),
+                "default_ms": float(dflt.ms)}
 
-    def set_tuning(self, nrhs, path=None, chunk=0, max_fused=0):
+    def set_tuning(self, nrhs, path=None, chunk=0, max_fused=0, split=0):
         """ibf_set_tuning: installs a schedule for `nrhs` right-hand sides
         (path "default", "vector" or "mfma"); path None returns to the
         default rule."""
         if path is None:
             _check(self._lib.ibf_set_tuning(self.handle, nrhs, None))
             return
-        t = IBFTuning(["default", "vector", "mfma"].index(path), chunk, max_fused, 0.0)
+        t = IBFTuning(["default", "vector", "mfma"].index(path), chunk, max_fused, 0.0, split)
         _check(self._lib.ibf_set_tuning(self.handle, nrhs, C.byref(t)))
 
     def apply_profile(self, g, u, stream=None):

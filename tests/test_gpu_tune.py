@@ -59,7 +59,8 @@ def test_tune_then_apply_parity(torch_dev, nrhs):
 
 
 @pytest.mark.parametrize("sched", [("vector", 0, 2), ("mfma", 16, 3), ("mfma", 32, 2),
-                                   ("mfma", 16, 0)])
+                                   ("mfma", 16, 0), ("mfma", 16, 0, 1), ("mfma", 32, 0, 2),
+                                   ("default", 0, 0, 2)])
 def test_fixed_schedule_parity(torch_dev, sched):
     # ibf_set_tuning installs a schedule without timing: same product
     torch = torch_dev
