@@ -1,7 +1,7 @@
 """Predictor kernels on the GPU against the FP64 oracle, the device dense
 product against the oracle's dense product, and the trained predictor's
-gain over the fixed-order fallback (r = 12) with the dense oracle as the
-judge: every chosen (r, truncation) meets its target, the build's
+gain over the fixed-order fallback (r = 12), checked with the dense oracle:
+every chosen (r, truncation) meets its target, the build's
 preliminary work shrinks, the stored entries do not grow.
 
 Bars: FP32 gradient and forward against FP64 <= 1e-4 relative; one Adam step
@@ -111,7 +111,7 @@ def test_predictor_trains_and_gains(torch_dev):
     rmse = float(np.sqrt(np.mean((pred.predict(data.X) - data.Y) ** 2)))
     _say(f"predictor: training loss {final:.4g}, rmse {rmse:.3f} decades")
     assert rmse <= 0.2
-    # held-out sizes and targets, each choice judged by the oracle's dense product.
+    # held-out sizes and targets, each choice checked against the oracle's dense product.
     # The gain: the stored (apply) entries follow the truncation tolerance and
     # stay the same, while the build's work (preliminary entries ~ r^2 per
     # pair and level, SVDs of r x 2r blocks) shrinks with the smaller order.
