@@ -802,6 +802,43 @@ def apply_optimal(O: OptimalIBF, g):
     return _scatter_u(prob, O.x_idx, u_leaf)
 
 
+def _stage_adjoint(blk, out):
+    """Conjugate transpose of _stage: lam[a', 2b+c] = sum_d blk[2a'+d, b, c]^H out[2a'+d, b]."""
+    na, nb, kin = blk.shape[0], blk.shape[1], blk.shape[4]
+    lam = np.zeros((na // 2, 2 * nb, kin, out.shape[-1]), dtype=np.complex128)
+    for c in (0, 1):
+        contrib = np.einsum("abts,abtn->absn", blk[:, :, c].conj(), out)
+        lam[:, c::2] = contrib[0::2] + contrib[1::2]
+    return lam
+
+
+def apply_optimal_adjoint(O: OptimalIBF, h):
+    """v = (IBF)^* h: the factors of apply_optimal conjugate-transposed in
+    reverse order (Ubar^*, Gbar^*, Mdot^*, F^*, Vbar); h has one entry per
+    row point x, v one per column point xi (the type-I orientation of the
+    non-uniform DFT of Sec. 6.1)."""
+    prob = O.prob
+    T = prob.tree
+    h = np.asarray(h, dtype=np.complex128)
+    if h.ndim == 1:
+        h = h[:, None]
+    hl = _leaf_gather(O.x_idx, h[T.perm_x])                     # [a, slot, n]
+    mu = np.einsum("abik,ain->abkn", O.Ubar.conj(), hl)
+    for l in range(T.L - T.l0, T.h, -1):
+        mu = _stage_adjoint(O.Gbar[l], mu)
+    if O.Mdot is not None:
+        mu = np.einsum("abts,abtn->absn", O.Mdot.conj(), mu)
+    for l in range(T.h, T.l0, -1):
+        mu = _stage_adjoint(O.F[l], mu)
+    v_leaf = np.einsum("abks,abkn->bsn", O.Vbar.conj(), mu)    # [b, slot, n]
+    v_s = np.zeros((len(T.xis), v_leaf.shape[-1]), dtype=np.complex128)
+    ok = O.xi_idx >= 0
+    v_s[O.xi_idx[ok]] = v_leaf[ok]
+    v = np.empty_like(v_s)
+    v[T.perm_xi] = v_s
+    return v
+
+
 # ----------------------------------------------------------------------------
 # Sizes, ranks and error metrics (Sec. 6)
 # ----------------------------------------------------------------------------

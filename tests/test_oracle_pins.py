@@ -306,6 +306,45 @@ def _fio_err(monkeypatch_fn=None):
     return O.rel_error(O.apply_prelim(F, g), ud)
 
 
+@pytest.mark.parametrize("sweep_in_on", [False, True])
+def test_adjoint_inner_product_identity(sweep_in_on):
+    """<IBF g, h> = <g, IBF^* h> to rounding: the adjoint's factors are the
+    forward ones conjugate-transposed in reverse order (random x, ragged
+    leaves, with and without the sweep-in)."""
+    P = I.nudft_random(2048, 8, 3, 11)
+    _, _, Op = O.build_optimal(P.phase, P.params, P.x, P.xi, P.r, P.tol, P.leaf,
+                               sweep_in_on=sweep_in_on)
+    rng = np.random.default_rng(12)
+    h = I.complex_normal(len(P.x), 3, rng)
+    lhs = np.vdot(h, O.apply_optimal(Op, P.g))
+    rhs = np.vdot(O.apply_optimal_adjoint(Op, h), P.g)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def test_adjoint_dft_closed_form():
+    """x_i = i/N, xi_j = j - N/2, Phi = x xi: K^* h = fft((-1)^i h); the IBF
+    adjoint reaches it to the interpolation error at r = 12."""
+    n = 1024
+    P = I.dft_uniform(n, 12, 2, 13)
+    _, _, Op = O.build_optimal(P.phase, P.params, P.x, P.xi, P.r, 1e-12, P.leaf)
+    h = I.complex_normal(n, 2, np.random.default_rng(14))
+    ref = np.fft.fft(((-1.0) ** np.arange(n))[:, None] * h, axis=0)
+    v = O.apply_optimal_adjoint(Op, h)
+    assert O.rel_error(v, ref) < 1e-8
+
+
+def test_adjoint_against_dense_fio():
+    """FIO phase, N = 1024, r = 8: the adjoint's error against the dense
+    conjugate transpose is of the forward error's size."""
+    P = I.workload_fio1d_1k()
+    _, _, Op = O.build_optimal(P.phase, P.params, P.x, P.xi, P.r, P.tol, P.leaf)
+    K = O.kernel(P.phase, P.params, P.x[:, None], P.xi[None, :])
+    h = I.complex_normal(len(P.x), 2, np.random.default_rng(15))
+    e_adj = O.rel_error(O.apply_optimal_adjoint(Op, h), K.conj().T @ h)
+    e_fwd = O.rel_error(O.apply_optimal(Op, P.g), K @ P.g)
+    assert e_adj < 3e-3 and e_adj < 5 * e_fwd
+
+
 def test_planted_mistakes_are_caught():
     assert _fio_err() < 1e-5
 
