@@ -140,6 +140,22 @@ int ibf_build(ibf_plan_t plan, void* hip_stream);
 int ibf_apply(ibf_plan_t plan, const void* g, int64_t ldg, void* u,
               int64_t ldu, int64_t nrhs, void* hip_stream);
 
+/*
+ * v = K_IBF^* h: the adjoint of the applied factorization (its factors
+ * conjugate-transposed in reverse order, Sec. 4 eqn:IBFout), the type-I
+ * orientation of the non-uniform DFT of Sec. 6.1.  h (device, read) is
+ * n_x x nrhs with ldh >= n_x, v (device, written) n_xi x nrhs with
+ * ldv >= n_xi, column-major, caller point order, the plan's vector type.
+ * The first call after a build makes the transposed factor copies (as much
+ * device memory again as the stage and outer factors) and the adjoint's
+ * workspace; it runs on the same apply kernels.  One apply or adjoint apply
+ * per plan in flight.  Errors: NOT_BUILT, INVALID_ARG (nrhs < 1, bad ld,
+ * NULL), UNSUPPORTED (dim-2 plans, plans built with the sweep-in), OOM,
+ * DEVICE.
+ */
+int ibf_apply_adjoint(ibf_plan_t plan, const void* h, int64_t ldh, void* v,
+                      int64_t ldv, int64_t nrhs, void* hip_stream);
+
 /* Per-launch timings of one profiled application (see ibf_apply_profile). */
 #define IBF_PROFILE_MAX 64
 typedef struct {

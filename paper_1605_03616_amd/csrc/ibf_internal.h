@@ -111,6 +111,10 @@ struct ibf_plan_s {
   std::map<int64_t, ibf::Tuning> tuned;
   ibf::Tuning trial{};
   bool trial_on = false;
+  // the adjoint (ibf_apply_adjoint): a plan over the transposed pair labels
+  // that shares this plan's point maps and owns conjugate-transposed copies
+  // of the factors; made on the first adjoint apply, dropped with the factors
+  ibf_plan_s* adj = nullptr;
 };
 
 namespace ibf {
@@ -122,6 +126,9 @@ int dense_apply(const PhaseDesc& ph, const double* x, int64_t nx, const double* 
 int eval_kernel(const PhaseDesc& ph, const double* x, const double* xi,
                 int64_t n, void* out, hipStream_t s);
 void free_factors(ibf_plan_t p);
+void free_adjoint(ibf_plan_t p);
+int apply_adjoint(ibf_plan_t p, const void* h, int64_t ldh, void* v, int64_t ldv, int64_t nrhs,
+                  hipStream_t s);
 // dim == 2 (multiscale IBF over coronal boxes)
 int plan2d(const ibf_desc* d, ibf_plan_t* out);
 int build2d(ibf_plan_t p, hipStream_t s);

@@ -96,6 +96,7 @@ hipError_t dev_free(void* ptr) {
 size_t complex_bytes(int precision) { return precision == IBF_FP64 ? 16 : 8; }
 
 void free_factors(ibf_plan_t p) {
+  free_adjoint(p);
   for (auto& st : p->stages)
     if (st.blk) (void)ibf::dev_free(st.blk);
   p->stages.clear();
@@ -240,6 +241,20 @@ int ibf_apply(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu,
   if (ldg < p->nxi || ldu < p->nx) return fail(IBF_ERR_INVALID_ARG, "ibf_apply: leading dimension too small");
   if (p->dim == 2) return ibf::apply2d(p, g, ldg, u, ldu, nrhs, (hipStream_t)stream);
   return ibf::apply_plan(p, g, ldg, u, ldu, nrhs, (hipStream_t)stream);
+}
+
+int ibf_apply_adjoint(ibf_plan_t p, const void* h, int64_t ldh, void* v, int64_t ldv,
+                      int64_t nrhs, void* stream) {
+  if (!p) return fail(IBF_ERR_INVALID_ARG, "ibf_apply_adjoint: null plan");
+  if (!p->built) return fail(IBF_ERR_NOT_BUILT, "ibf_apply_adjoint: plan not built");
+  if (!h || !v) return fail(IBF_ERR_INVALID_ARG, "ibf_apply_adjoint: null vector");
+  if (nrhs < 1) return fail(IBF_ERR_INVALID_ARG, "ibf_apply_adjoint: nrhs < 1");
+  if (ldh < p->nx || ldv < p->nxi)
+    return fail(IBF_ERR_INVALID_ARG, "ibf_apply_adjoint: leading dimension too small");
+  if (p->dim != 1) return fail(IBF_ERR_UNSUPPORTED, "ibf_apply_adjoint: provided for dim 1");
+  if (p->d_mdot)
+    return fail(IBF_ERR_UNSUPPORTED, "ibf_apply_adjoint: not provided for sweep-in plans");
+  return ibf::apply_adjoint(p, h, ldh, v, ldv, nrhs, (hipStream_t)stream);
 }
 
 int ibf_apply_profile(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu,

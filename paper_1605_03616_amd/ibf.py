@@ -25,7 +25,7 @@ EXPORTED = ["ibf_plan", "ibf_build", "ibf_apply", "ibf_apply_profile", "ibf_quer
             "ibf_apply_batch", "ibf_batch_destroy", "ibf_dense_apply", "ibf_mlp_n_params",
             "ibf_mlp_features", "ibf_mlp_forward", "ibf_mlp_grad_work", "ibf_mlp_loss_grad",
             "ibf_mlp_adam", "ibf_mlp_select", "ibf_tune", "ibf_set_tuning", "ibf_set_allocator",
-            "ibf_measure_peak"]
+            "ibf_measure_peak", "ibf_apply_adjoint"]
 MLP_FEATURES = 5
 BATCH_GRAPH = 1
 PROFILE_MAX = 64
@@ -135,11 +135,13 @@ def load(path: str = LIB_PATH):
     lib.ibf_set_tuning.argtypes = [vp, i64, C.POINTER(IBFTuning)]
     lib.ibf_set_allocator.argtypes = [ALLOC_FN, FREE_FN]
     lib.ibf_measure_peak.argtypes = [C.c_int, vp, C.POINTER(C.c_double)]
+    lib.ibf_apply_adjoint.argtypes = [vp, vp, i64, vp, i64, i64, vp]
     for name in ("ibf_plan", "ibf_build", "ibf_apply", "ibf_apply_profile", "ibf_query",
                  "ibf_destroy", "ibf_eval_kernel", "ibf_batch_create", "ibf_apply_batch",
                  "ibf_batch_destroy", "ibf_dense_apply", "ibf_mlp_n_params",
                  "ibf_mlp_features", "ibf_mlp_forward", "ibf_mlp_loss_grad", "ibf_mlp_adam",
-                 "ibf_mlp_select", "ibf_tune", "ibf_set_tuning", "ibf_set_allocator", "ibf_measure_peak"):
+                 "ibf_mlp_select", "ibf_tune", "ibf_set_tuning", "ibf_set_allocator", "ibf_measure_peak",
+                 "ibf_apply_adjoint"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -285,6 +287,23 @@ class Plan:
                                    C.c_void_p(u.data_ptr()), u.shape[1], nrhs,
                                    _stream_handle(stream)))
         return u[0] if squeeze else u
+
+    def apply_adjoint(self, h, v=None, stream=None):
+        """ibf_apply_adjoint: h device tensor (nrhs, n_x) or (n_x,); returns
+        v = K^* h as (nrhs, n_xi)."""
+        import torch
+        squeeze = h.dim() == 1
+        if squeeze:
+            h = h.unsqueeze(0)
+        if h.dtype != self.vector_dtype() or not h.is_contiguous():
+            raise ValueError("h must be a contiguous tensor of the plan's complex dtype")
+        nrhs = h.shape[0]
+        if v is None:
+            v = torch.empty((nrhs, self.n_xi), dtype=h.dtype, device=h.device)
+        _check(self._lib.ibf_apply_adjoint(self.handle, C.c_void_p(h.data_ptr()), h.shape[1],
+                                           C.c_void_p(v.data_ptr()), v.shape[1], nrhs,
+                                           _stream_handle(stream)))
+        return v[0] if squeeze else v
 
     def apply_raw(self, g_ptr, ldg, u_ptr, ldu, nrhs, stream=None):
         _check(self._lib.ibf_apply(self.handle, C.c_void_p(g_ptr), ldg, C.c_void_p(u_ptr), ldu,
