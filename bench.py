@@ -337,6 +337,69 @@ def _cores():
         return os.cpu_count()
 
 
+def _bench_adjoint(args):
+    """The adjoint apply v = K^* h on a 1-D workload (built without the
+    sweep-in): throughput, the whole-step roofline, and the error against the
+    FP64 adjoint of the same factorization."""
+    import torch
+
+    from paper_1605_03616_amd import ibf
+    from paper_1605_03616_amd import inputs as I
+
+    ibf.load()
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    P = _workload(args.workload, args.nrhs)
+    dt = torch.complex128 if P.precision == I.PREC_FP64 else torch.complex64
+    pl = ibf.Plan(P.x, P.xi, P.phase, P.params, P.r, P.tol, P.leaf, P.precision, 0).build()
+    q = pl.query()
+    rng = np.random.default_rng(7)
+    h = I.complex_normal(P.n, P.nrhs, rng)
+    ht = torch.from_numpy(np.ascontiguousarray(h.T)).to(dt).cuda()
+    v = torch.empty((P.nrhs, P.n), dtype=dt, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        pl.apply_adjoint(ht, v)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        pl.apply_adjoint(ht, v)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    flops = 8.0 * q["nnz_opt"] * P.nrhs
+    bound, peak, unit = (("mfma", FP32_PEAK_TFS, "TFLOP/s") if P.nrhs >= 32 else
+                         ("hbm", HBM_PEAK_GBS, "GB/s"))
+    fb = 16.0 if P.precision == I.PREC_FP64 else 8.0
+    byts = fb * q["nnz_opt"] + 2 * fb * P.n * P.nrhs
+    achieved = flops / (ms * 1e-3) / 1e12 if bound == "mfma" else byts / (ms * 1e-3) / 1e9
+    out = {
+        "metric": "IBF adjoint apply G(complex samples*RHS)/s (v = K^* h)",
+        "value": round(P.n * P.nrhs / (ms * 1e-3) / 1e9, 4),
+        "unit": "G(complex samples*RHS)/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {I.PREC_FP64: "f64", I.PREC_FP32: "f32", I.PREC_BF16X2: "bf16x2+f32"}[P.precision],
+        "data": "synthetic",
+        "config": {"workload": P.name + "_adjoint", "N": P.n, "r": P.r, "nrhs": P.nrhs,
+                   "tol": P.tol, "sweep_in": 0, "parallelism": "single-gpu"},
+        "roofline": {"kernel": "whole adjoint apply", "bound": bound,
+                     "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+                     "frac": round(achieved / peak, 4), "traffic": None},
+    }
+    if not args.no_accuracy and P.precision != I.PREC_FP64:
+        pl64 = ibf.Plan(P.x, P.xi, P.phase, P.params, P.r, P.tol, P.leaf, I.PREC_FP64, 0).build()
+        v64 = pl64.apply_adjoint(torch.from_numpy(np.ascontiguousarray(h.T)).cuda())
+        torch.cuda.synchronize()
+        a = v.cpu().numpy().astype(np.complex128)
+        b = v64.cpu().numpy()
+        out["rel_err_vs_fp64"] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        pl64.destroy()
+    pl.destroy()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -352,6 +415,8 @@ def main():
     ap.add_argument("--schedule", default=None, metavar="PATH/CHUNK/MAX_FUSED[/SPLIT]",
                     help="install this apply schedule instead of tuning (e.g. mfma/32/3; "
                          "fixes the launches for profiling)")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="time the adjoint apply v = K^* h instead (1-D workloads, no sweep-in)")
     ap.add_argument("--no-measured-peak", action="store_true",
                     help="skip the measured copy / MFMA-loop peaks in the roofline")
     ap.add_argument("--calib-copy", action="store_true",
@@ -369,6 +434,9 @@ def main():
         return
     if args.workload == "fio2d_256":
         _bench_2d(args)
+        return
+    if args.adjoint:
+        _bench_adjoint(args)
         return
 
     import torch
