@@ -42,11 +42,11 @@ MEASURED_TRAFFIC = {
     # (workload, schedule path/chunk/max_fused) -> (sha1 of the apply source,
     #   kernel class, [(launches per step, FETCH_SIZE KiB, WRITE_SIZE KiB), ...])
     ("fio1d_n65536_r12_fp32", "default/0/0"): (
-        "d94c23d2cc357d747e418f62a76fa11a277444ab", "apply_fused_mfma",
-        [(2, 331298, 344064), (1, 263248, 294912)]),
+        "6adb7b1b64c8069682f65917087d52e5f0d94ea1", "apply_fused_mfma",
+        [(2, 331925, 344064), (1, 263465, 294912)]),
     ("nudft_n1048576_r10", "default/0/0"): (
-        "d94c23d2cc357d747e418f62a76fa11a277444ab", "apply_fused_mfma",
-        [(2, 2424930, 983040), (1, 1769580, 917504), (1, 1822850, 1048576)]),
+        "6adb7b1b64c8069682f65917087d52e5f0d94ea1", "apply_fused_mfma",
+        [(2, 2424930, 983040), (1, 1769570, 917504), (1, 1822840, 1048576)]),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
@@ -338,9 +338,10 @@ def _cores():
 
 
 def _bench_adjoint(args):
-    """The adjoint apply v = K^* h on a 1-D workload (built without the
-    sweep-in): throughput, the whole-step roofline, and the error against the
-    FP64 adjoint of the same factorization."""
+    """The adjoint apply v = K^* h on a 1-D workload (built as the forward
+    bench builds it, the sweep-in included): throughput, the whole-step
+    roofline, and the error against the FP64 adjoint of the same
+    factorization."""
     import torch
 
     from paper_1605_03616_amd import ibf
@@ -350,7 +351,8 @@ def _bench_adjoint(args):
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     P = _workload(args.workload, args.nrhs)
     dt = torch.complex128 if P.precision == I.PREC_FP64 else torch.complex64
-    pl = ibf.Plan(P.x, P.xi, P.phase, P.params, P.r, P.tol, P.leaf, P.precision, 0).build()
+    sw = int(getattr(P, "sweep_in", 0) or 0)
+    pl = ibf.Plan(P.x, P.xi, P.phase, P.params, P.r, P.tol, P.leaf, P.precision, sw).build()
     q = pl.query()
     rng = np.random.default_rng(7)
     h = I.complex_normal(P.n, P.nrhs, rng)
@@ -383,13 +385,13 @@ def _bench_adjoint(args):
         "dtype": {I.PREC_FP64: "f64", I.PREC_FP32: "f32", I.PREC_BF16X2: "bf16x2+f32"}[P.precision],
         "data": "synthetic",
         "config": {"workload": P.name + "_adjoint", "N": P.n, "r": P.r, "nrhs": P.nrhs,
-                   "tol": P.tol, "sweep_in": 0, "parallelism": "single-gpu"},
+                   "tol": P.tol, "sweep_in": q["sweep_in"], "parallelism": "single-gpu"},
         "roofline": {"kernel": "whole adjoint apply", "bound": bound,
                      "achieved": round(achieved, 3), "peak": peak, "unit": unit,
                      "frac": round(achieved / peak, 4), "traffic": None},
     }
     if not args.no_accuracy and P.precision != I.PREC_FP64:
-        pl64 = ibf.Plan(P.x, P.xi, P.phase, P.params, P.r, P.tol, P.leaf, I.PREC_FP64, 0).build()
+        pl64 = ibf.Plan(P.x, P.xi, P.phase, P.params, P.r, P.tol, P.leaf, I.PREC_FP64, sw).build()
         v64 = pl64.apply_adjoint(torch.from_numpy(np.ascontiguousarray(h.T)).cuda())
         torch.cuda.synchronize()
         a = v.cpu().numpy().astype(np.complex128)
@@ -416,7 +418,7 @@ def main():
                     help="install this apply schedule instead of tuning (e.g. mfma/32/3; "
                          "fixes the launches for profiling)")
     ap.add_argument("--adjoint", action="store_true",
-                    help="time the adjoint apply v = K^* h instead (1-D workloads, no sweep-in)")
+                    help="time the adjoint apply v = K^* h instead (1-D workloads)")
     ap.add_argument("--no-measured-peak", action="store_true",
                     help="skip the measured copy / MFMA-loop peaks in the roofline")
     ap.add_argument("--calib-copy", action="store_true",

@@ -149,9 +149,9 @@ int ibf_apply(ibf_plan_t plan, const void* g, int64_t ldg, void* u,
  * The first call after a build makes the transposed factor copies (as much
  * device memory again as the stage and outer factors) and the adjoint's
  * workspace; it runs on the same apply kernels.  One apply or adjoint apply
- * per plan in flight.  Errors: NOT_BUILT, INVALID_ARG (nrhs < 1, bad ld,
- * NULL), UNSUPPORTED (dim-2 plans, plans built with the sweep-in), OOM,
- * DEVICE.
+ * per plan in flight; plans built with the sweep-in (Sec. 4.3) transpose
+ * their middle block Mdot too.  Errors: NOT_BUILT, INVALID_ARG (nrhs < 1,
+ * bad ld, NULL), UNSUPPORTED (dim-2 plans), OOM, DEVICE.
  */
 int ibf_apply_adjoint(ibf_plan_t plan, const void* h, int64_t ldh, void* v,
                       int64_t ldv, int64_t nrhs, void* hip_stream);

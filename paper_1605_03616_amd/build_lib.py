@@ -18,7 +18,8 @@ LIB = os.path.join(HERE, "libibf.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["ibf_plan.cpp", "ibf_build.hip", "ibf_sweep.hip", "ibf_sweepin.hip", "ibf_apply.hip",
-           "ibf_mlp.hip", "ibf2d.hip", "ibf_peak.hip"]
+           "ibf_mlp.hip", "ibf2d.hip", "ibf_peak.hip",
+           "ibf_adjoint.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include")]

@@ -252,8 +252,6 @@ int ibf_apply_adjoint(ibf_plan_t p, const void* h, int64_t ldh, void* v, int64_t
   if (ldh < p->nx || ldv < p->nxi)
     return fail(IBF_ERR_INVALID_ARG, "ibf_apply_adjoint: leading dimension too small");
   if (p->dim != 1) return fail(IBF_ERR_UNSUPPORTED, "ibf_apply_adjoint: provided for dim 1");
-  if (p->d_mdot)
-    return fail(IBF_ERR_UNSUPPORTED, "ibf_apply_adjoint: not provided for sweep-in plans");
   return ibf::apply_adjoint(p, h, ldh, v, ldv, nrhs, (hipStream_t)stream);
 }
 

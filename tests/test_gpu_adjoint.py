@@ -1,9 +1,9 @@
 """Adjoint apply (ibf_apply_adjoint, v = K_IBF^* h) against the oracle's
 adjoint (the factors conjugate-transposed in reverse order): FP64 to the FP64
 bar, FP32 1e-5 on the vector and MFMA paths, BF16X2 1e-4 with ragged random
-leaves; the inner-product identity between the GPU forward and adjoint
-applies; a rebuild drops the transposed copies; unsupported plan kinds are
-refused."""
+leaves, with and without the sweep-in; the inner-product identity between
+the GPU forward and adjoint applies; a rebuild drops the transposed copies;
+2-D plans are refused."""
 import functools
 import sys
 
@@ -36,6 +36,14 @@ def _fp64_tol(n):
 
 
 @functools.lru_cache(maxsize=None)
+def _case_swept(key):
+    P = I.nudft_random(4096, 10, 16, 27) if key == "nudft4k_r10" else I.fio1d_uniform(3000, 9, 4, 29)
+    _, _, Op = O.build_optimal(P.phase, P.params, P.x, P.xi, P.r, P.tol, P.leaf,
+                               sweep_in_on=False)
+    return P, O.sweep_in(Op, P.tol)
+
+
+@functools.lru_cache(maxsize=None)
 def _case(key):
     if key == "fio1k":
         P = I.workload_fio1d_1k()
@@ -48,9 +56,9 @@ def _case(key):
     return P, Op
 
 
-def _adjoint(torch, P, precision, h):
+def _adjoint(torch, P, precision, h, sweep_in=0):
     from paper_1605_03616_amd import ibf
-    pl = ibf.Plan(P.x, P.xi, P.phase, P.params, P.r, P.tol, P.leaf, precision, 0).build()
+    pl = ibf.Plan(P.x, P.xi, P.phase, P.params, P.r, P.tol, P.leaf, precision, sweep_in).build()
     dt = torch.complex128 if precision == I.PREC_FP64 else torch.complex64
     ht = torch.from_numpy(np.ascontiguousarray(h.T)).to(dt).cuda()
     v = pl.apply_adjoint(ht).cpu().numpy().T.astype(np.complex128)
@@ -77,6 +85,28 @@ def test_adjoint_parity(torch_dev, key, precision, nrhs):
     assert O.rel_error(v, v_ref) < tol
 
 
+@pytest.mark.parametrize("key,precision,nrhs", [
+    ("nudft4k_r10", I.PREC_FP64, 2),
+    ("nudft4k_r10", I.PREC_FP32, 16),
+    ("nudft4k_r10", I.PREC_BF16X2, 16),
+    ("nudft4k_r10", I.PREC_FP32, 40),
+    ("fio3000_r9", I.PREC_FP32, 12),
+])
+def test_adjoint_sweep_in_parity(torch_dev, key, precision, nrhs):
+    """Plans built with the sweep-in (Sec. 4.3): the adjoint also transposes
+    the middle block Mdot and exchanges the two sides' sweep-in ranks."""
+    _say(f"adjoint sweep-in parity {key} precision={precision} nrhs={nrhs}")
+    P, Oi = _case_swept(key)
+    h = I.complex_normal(len(P.x), nrhs, np.random.default_rng(70 + nrhs))
+    v_ref = O.apply_optimal_adjoint(Oi, h)
+    pl, v = _adjoint(torch_dev, P, precision, h, sweep_in=1)
+    q = pl.query()
+    pl.destroy()
+    assert q["sweep_in"] == 1
+    tol = {I.PREC_FP64: _fp64_tol(P.n), I.PREC_FP32: 1e-5, I.PREC_BF16X2: 1e-4}[precision]
+    assert O.rel_error(v, v_ref) < tol
+
+
 def test_adjoint_identity_and_rebuild(torch_dev):
     """<K g, h> = <g, K^* h> with the GPU's own forward and adjoint (FP64), and
     the same adjoint after a rebuild of the plan."""
@@ -99,14 +129,7 @@ def test_adjoint_identity_and_rebuild(torch_dev):
 def test_adjoint_unsupported(torch_dev):
     torch = torch_dev
     from paper_1605_03616_amd import ibf
-    _say("adjoint unsupported: sweep-in plan, 2-D plan")
-    P, _ = _case("nudft4k_r10")
-    pl = ibf.Plan(P.x, P.xi, P.phase, P.params, P.r, P.tol, P.leaf, I.PREC_FP32, 1).build()
-    h = torch.zeros((1, len(P.x)), dtype=torch.complex64, device="cuda")
-    with pytest.raises(ibf.IBFError) as e1:
-        pl.apply_adjoint(h)
-    assert e1.value.code == -2
-    pl.destroy()
+    _say("adjoint unsupported: 2-D plan")
     P2 = I.fio2d_grid(32, 3, 1, 42, tol=1e-4, precision=I.PREC_FP32)
     pl2 = ibf.Plan.from_problem(P2, precision=I.PREC_FP32).build()
     h2 = torch.zeros((1, len(P2.x)), dtype=torch.complex64, device="cuda")
