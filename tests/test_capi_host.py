@@ -86,6 +86,16 @@ def test_apply_before_build_is_not_built():
     pl.destroy()
 
 
+def test_adjoint_validates_before_device_work():
+    lib = ibf.load()
+    assert lib.ibf_apply_adjoint(None, C.c_void_p(1), 1024, C.c_void_p(2), 1024, 1, None) == -1
+    pl = _plan()
+    rc = lib.ibf_apply_adjoint(pl.handle, C.c_void_p(1), 1024, C.c_void_p(2), 1024, 1, None)
+    assert rc == -5                                  # not built
+    assert "not built" in ibf.last_error()
+    pl.destroy()
+
+
 def test_null_arguments():
     lib = ibf.load()
     assert lib.ibf_plan(None, None) == -1
