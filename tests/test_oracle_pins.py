@@ -359,3 +359,34 @@ def test_planted_mistakes_are_caught():
 
     for bad in (transpose_lc, swap_children, shift_nodes):
         assert _fio_err(bad) > 1e-2, bad.__name__
+
+
+def test_planted_adjoint_mistakes_are_caught(monkeypatch):
+    """The adjoint pins fail for plausible mistakes planted in the oracle's
+    adjoint stage: a dropped conjugation, children gathered in the wrong
+    order, the two outputs of a child pair taken from the wrong rows."""
+    P = I.nudft_random(1024, 8, 2, 16)
+    _, _, Op = O.build_optimal(P.phase, P.params, P.x, P.xi, P.r, P.tol, P.leaf)
+    h = I.complex_normal(len(P.x), 2, np.random.default_rng(17))
+    lhs = np.vdot(h, O.apply_optimal(Op, P.g))
+
+    def gap():
+        return abs(lhs - np.vdot(O.apply_optimal_adjoint(Op, h), P.g)) / abs(lhs)
+
+    assert gap() < 1e-13
+    good = O._stage_adjoint
+
+    def no_conj(blk, out):
+        return good(blk.conj(), out)
+
+    def swapped_children(blk, out):
+        return good(blk[:, :, ::-1], out)
+
+    def wrong_parents(blk, out):
+        return good(blk, out[::-1])
+
+    for bad in (no_conj, swapped_children, wrong_parents):
+        monkeypatch.setattr(O, "_stage_adjoint", bad)
+        assert gap() > 1e-3, bad.__name__
+    monkeypatch.setattr(O, "_stage_adjoint", good)
+    assert gap() < 1e-13
