@@ -174,7 +174,12 @@ def _bench_batched(args):
     gs = [torch.from_numpy(np.ascontiguousarray(P.g.T)).to(torch.complex64).cuda() for P in probs]
     us = [torch.empty((P.nrhs, P.n), dtype=torch.complex64, device="cuda") for P in probs]
     tune_info = None
-    if not args.no_tune:     # schedule autotuner per plan, before the timed region
+    if args.schedule:        # one installed schedule for every plan
+        f = args.schedule.split("/")
+        for pl, P in zip(plans, probs):
+            pl.set_tuning(P.nrhs, f[0], int(f[1]), int(f[2]), int(f[3]) if len(f) > 3 else 0)
+        tune_info = {"fixed": args.schedule}
+    elif not args.no_tune:   # schedule autotuner per plan, before the timed region
         t0 = time.perf_counter()
         picks = [pl.tune(g, u) for pl, g, u in zip(plans, gs, us)]
         torch.cuda.synchronize()
