@@ -8,6 +8,9 @@ Everything is complex128 / float64, written for readability, vectorised over
 box pairs with numpy (a library matmul, einsum and SVD serve as steps; there
 is no blocking or fusion).  The passages followed are cited per function:
 
+* Sec. 1    -- the kernel a(x, xi) exp(2 pi i Phi(x, xi)) of eqn:FIO; the
+  paper then sets a == 1, here a general smooth amplitude is also kept
+  (it enters only the switch blocks, see prelim_factors).
 * Sec. 2.1  -- Chebyshev grid, Lagrange polynomials, the split of Phi
   (eqn:RAB, eqn:terms) and the interpolative factors (eqn:ab1, eqn:ab2).
 * Sec. 2.2  -- Algorithm 2.1, the butterfly algorithm (eqn:1, eqn:2, the
@@ -26,7 +29,8 @@ notes): leaves hold `leaf` points while every box pair keeps w_A * w_B <= 1
 last log2(leaf) levels collapse into exact leaf <-> grid blocks); boxes are
 half-open with geometric centres; Chebyshev grids are 0-based with t = 0 at
 +1/2; the middle level is h = floor(L/2); truncation keeps sigma_i >
-tol * sigma_1 per block; the middle block splits Sigma^(1/2) to both sides,
+tol * sigma_1 per block (optionally capped per level, cap_rank); the middle
+block splits Sigma^(1/2) to both sides,
 the sweep-out recursion keeps U_k Sigma_k on the basis side, the sweep-in
 keeps Sigma_k V_k^* on the basis side.
 """
@@ -110,11 +114,45 @@ def kernel(kind, params, x, xi):
 
 
 # ----------------------------------------------------------------------------
+# Amplitude a(x, xi) of eqn:FIO (Sec. 1)
+# ----------------------------------------------------------------------------
+
+AMP_NONE, AMP_SEPARABLE, AMP_WAVE = 0, 1, 2
+
+
+def amplitude(amp, x, xi):
+    """a(x, xi) of the kernel a(x, xi) exp(2 pi i Phi(x, xi)) (eqn:FIO).
+
+    The paper assumes a == 1 after noting that a smooth symbol of order zero
+    is numerically low-rank (Sec. 1).  amp = (kind, params) or None:
+    kind 0: a == 1
+    kind 1: a = (q0 + q1 sin 2 pi x + q2 cos 2 pi x) (q3 + q4 xi / sqrt(xi^2 + q5^2)),
+            a product of a smooth function of x and an order-zero symbol in xi
+    kind 2: a = q0 + q1 cos(2 pi (x + xi / q2)), smooth and not separable
+            when q2 is at least the width of Omega
+    """
+    x = np.asarray(x, dtype=np.float64)
+    xi = np.asarray(xi, dtype=np.float64)
+    x, xi = np.broadcast_arrays(x, xi)
+    if amp is None or amp[0] == AMP_NONE:
+        return np.ones(x.shape)
+    kind, q = amp[0], amp[1]
+    if kind == AMP_SEPARABLE:
+        fx = q[0] + q[1] * np.sin(TWO_PI * x) + q[2] * np.cos(TWO_PI * x)
+        fxi = q[3] + q[4] * xi / np.sqrt(xi * xi + q[5] * q[5])
+        return fx * fxi
+    if kind == AMP_WAVE:
+        return q[0] + q[1] * np.cos(TWO_PI * (x + xi / q[2]))
+    raise ValueError(f"unsupported amplitude kind {kind}")
+
+
+# ----------------------------------------------------------------------------
 # Dense direct product (the definition u = K g, eqn:DFIO)
 # ----------------------------------------------------------------------------
 
-def dense_apply(kind, params, x, xi, g, rows=None, chunk=None):
-    """u(x_i) = sum_j K(x_i, xi_j) g_j for the selected rows (all by default).
+def dense_apply(kind, params, x, xi, g, rows=None, chunk=None, amp=None):
+    """u(x_i) = sum_j a(x_i, xi_j) K(x_i, xi_j) g_j for the selected rows (all
+    by default); a == 1 unless `amp` is given.
 
     g has shape (n_xi,) or (n_xi, nrhs).  O(rows * n_xi) work, chunked so that
     one chunk of the kernel matrix holds about 2^22 entries.
@@ -130,6 +168,8 @@ def dense_apply(kind, params, x, xi, g, rows=None, chunk=None):
     for s in range(0, len(rows), chunk):
         rr = rows[s:s + chunk]
         K = kernel(kind, params, x[rr][:, None], xi[None, :])
+        if amp is not None:
+            K = K * amplitude(amp, x[rr][:, None], xi[None, :])
         out[s:s + chunk] = K @ g
     return out[:, 0] if squeeze else out
 
@@ -271,15 +311,22 @@ class IBFProblem:
     r: int
     z: np.ndarray
     Lc: np.ndarray          # child -> parent Lagrange matrices [2, r, r]
+    amp: tuple | None = None   # amplitude (kind, params), None for a == 1
 
     def K(self, x, xi):
         return kernel(self.kind, self.params, x, xi)
 
+    def Ka(self, x, xi):
+        """The full kernel a(x, xi) exp(2 pi i Phi(x, xi)) (eqn:FIO)."""
+        if self.amp is None:
+            return self.K(x, xi)
+        return amplitude(self.amp, x, xi) * self.K(x, xi)
 
-def make_problem(kind, params, x, xi, r, leaf=16, lo=None, W=None):
+
+def make_problem(kind, params, x, xi, r, leaf=16, lo=None, W=None, amp=None):
     tree = build_tree(x, xi, leaf, lo, W)
     z = cheb_nodes(r)
-    return IBFProblem(kind, tuple(params), tree, r, z, child_to_parent(z))
+    return IBFProblem(kind, tuple(params), tree, r, z, child_to_parent(z), amp)
 
 
 def _g_sorted(prob, g):
@@ -346,10 +393,12 @@ def butterfly_algorithm(prob: IBFProblem, g):
         new *= np.conj(prob.K(cA[:, None, None], gB[None, :, :]))[..., None]
         lam = new
 
-    # Switch at the middle level h.
+    # Switch at the middle level h: the only place where the amplitude enters
+    # (the interpolation steps carry a(x, xi) exp(2 pi i R^{AB}) implicitly
+    # through kernel values at grid points).
     gA = T.cx(h)[:, None] + T.wx(h) * z[None, :]
     gB = T.cxi(L - h)[:, None] + T.wxi(L - h) * z[None, :]
-    Msw = prob.K(gA[:, None, :, None], gB[None, :, None, :])   # [a, b, t, s]
+    Msw = prob.Ka(gA[:, None, :, None], gB[None, :, None, :])   # [a, b, t, s]
     lam = np.einsum("abts,absn->abtn", Msw, lam)
 
     # Recursion in x (eqn:3) for l = h+1 .. L-l0.
@@ -407,7 +456,10 @@ def prelim_factors(prob: IBFProblem) -> PrelimIBF:
 
     V^*  : eqn:PIBF1  e^{-2pi i Phi(c_A,g^B_t)} M^B_t(xi) e^{2pi i Phi(c_A,xi)}
     H^l  : eqn:PIBF2  e^{-2pi i Phi(c_A,g^B_t)} M^B_t(g^C_s) e^{2pi i Phi(c_A,g^C_s)}
-    M^h  : eqn:switchlocM  e^{2pi i Phi(g^A_t, g^B_s)}
+    M^h  : eqn:switchlocM  K(g^A_t, g^B_s) = a(g^A_t, g^B_s) e^{2pi i Phi(g^A_t, g^B_s)}
+           (with a general amplitude the interpolation of eqn:ab1 / eqn:ab2 is
+           applied to a(x, xi) exp(2 pi i R^{AB}); a cancels from every other
+           block because they only move between interpolation grids)
     G^l  : eqn:PIBF3  e^{2pi i Phi(g^A_t,c_C)} M^P_s(g^A_t) e^{-2pi i Phi(g^P_s,c_C)}
     U^L  : eqn:PIBFbf3  e^{2pi i Phi(x,c_B)} M^A_t(x) e^{-2pi i Phi(g^A_t,c_B)}
     """
@@ -444,7 +496,7 @@ def prelim_factors(prob: IBFProblem) -> PrelimIBF:
 
     gA = T.cx(h)[:, None] + T.wx(h) * z[None, :]
     gB = T.cxi(L - h)[:, None] + T.wxi(L - h) * z[None, :]
-    M = prob.K(gA[:, None, :, None], gB[None, :, None, :])
+    M = prob.Ka(gA[:, None, :, None], gB[None, :, None, :])
 
     G = {}
     for l in range(h + 1, L - l0 + 1):
@@ -616,6 +668,25 @@ def truncated_svd(Z, tol):
     return U, S, Vh, k
 
 
+def cap_rank(S, k, cap):
+    """Fixed-rank mode: per block keep min(k, cap) singular values, where k
+    comes from the tolerance rule.  When the cap cuts through a cluster of
+    equal singular values (sigma_k' >= (1 - 1e-10) sigma_{k'-1}, 0-based,
+    i.e. the first dropped value equals the last kept one) the cut moves
+    down until it does not: the kept subspace of a degenerate cluster is not
+    unique, so splitting it would make the factorization ill-defined."""
+    kk = np.minimum(k, cap)
+    S = np.asarray(S)
+    while True:
+        cut = (kk < k) & (kk > 1)
+        first = np.take_along_axis(S, np.clip(kk, 0, S.shape[-1] - 1)[..., None], -1)[..., 0]
+        last = np.take_along_axis(S, np.clip(kk - 1, 0, S.shape[-1] - 1)[..., None], -1)[..., 0]
+        move = cut & (first >= (1.0 - 1e-10) * last)
+        if not move.any():
+            return kk
+        kk = np.where(move, kk - 1, kk)
+
+
 def _keep(k, width):
     """Mask [..., width] keeping the first k entries."""
     return (np.arange(width) < k[..., None]).astype(np.float64)
@@ -635,18 +706,26 @@ class OptimalIBF:
     ranks_in: dict | None = None   # sweep-in ranks (level -> ([a,b] G side, [a,b] H side))
 
 
-def sweep_out(F: PrelimIBF, tol: float) -> OptimalIBF:
+def sweep_out(F: PrelimIBF, tol: float, caps=None) -> OptimalIBF:
     """Sweep-out stage of Sec. 4.2: middle SVDs then recursions toward U and V.
 
     Blocks are kept at width r with exact zero padding beyond each pair's rank.
+    `caps` (level -> rank), when given, bounds the rank of every block whose
+    basis lives at that level (fixed-rank mode, cap_rank).
     """
     prob = F.prob
     T, r = prob.tree, prob.r
     L, l0, h = T.L, T.l0, T.h
     ranks = {}
 
+    def trunc(Z, level):
+        U, S, Vh, k = truncated_svd(Z, tol)
+        if caps is not None and level in caps:
+            k = cap_rank(S, k, int(caps[level]))
+        return U, S, Vh, k
+
     # Middle level factorisation (eq:KeqUMV, eq:lowrankSVD): M~ = C (R)^*.
-    Um, Sm, Vhm, km = truncated_svd(F.M, tol)
+    Um, Sm, Vhm, km = trunc(F.M, h)
     keep = _keep(km, r)
     sq = np.sqrt(Sm) * keep
     C = Um * sq[..., None, :]                                        # [a,b,t,k]
@@ -666,7 +745,7 @@ def sweep_out(F: PrelimIBF, tol: float) -> OptimalIBF:
             src = Cprev[par][:, 2 * np.arange(nb) + c]                   # [a,b,s,k]
             parts.append(F.G[l][:, :, c] @ src)
         W = np.concatenate(parts, axis=-1)                               # [a,b,r,2r]
-        Uw, Sw, Vhw, kw = truncated_svd(W, tol)
+        Uw, Sw, Vhw, kw = trunc(W, l)
         keep = _keep(kw, r)
         Cl[l] = Uw[..., :r] * (Sw[..., :r] * keep)[..., None, :]
         Vk = Vhw[..., :r, :] * keep[..., :, None]                        # [a,b,k,2r]
@@ -688,7 +767,7 @@ def sweep_out(F: PrelimIBF, tol: float) -> OptimalIBF:
             parts.append(Hs @ Rc[:, alpha][:, :, None])
         Z = np.concatenate(parts, axis=-1)                               # [a', b, c, r, 2r]
         Z = Z.reshape(na // 2, 2 * nb, r, 2 * r)                         # input pair (a', 2b+c)
-        Uz, Sz, Vhz, kz = truncated_svd(Z, tol)
+        Uz, Sz, Vhz, kz = trunc(Z, l - 1)
         keep = _keep(kz, r)
         Rl[l - 1] = Uz[..., :r] * (Sz[..., :r] * keep)[..., None, :]
         Vk = np.conj(np.swapaxes(Vhz[..., :r, :], -1, -2)) * keep[..., None, :]   # [a', j, 2r, k]
@@ -907,11 +986,11 @@ def rel_error(u, u_ref):
 
 
 def build_optimal(kind, params, x, xi, r, tol, leaf=16, sweep_in_on=False,
-                  lo=None, W=None):
+                  lo=None, W=None, amp=None, caps=None):
     """Convenience: geometry, preliminary factors, sweep-out [, sweep-in]."""
-    prob = make_problem(kind, params, x, xi, r, leaf, lo, W)
+    prob = make_problem(kind, params, x, xi, r, leaf, lo, W, amp)
     F = prelim_factors(prob)
-    O = sweep_out(F, tol)
+    O = sweep_out(F, tol, caps)
     if sweep_in_on:
         O = sweep_in(O, tol)
     return prob, F, O

@@ -103,3 +103,45 @@ def test_features_tree_quantities():
     f = M.features(3000, M.PHASE_DFT, 8, 1e-4)
     assert math.isclose(f[0], 3000 / 4096) and f[1] == 0.0 and f[2] == 1.0
     assert np.allclose(M.features(65536, M.PHASE_DFT, 8, 1e-4), M.features(256, M.PHASE_DFT, 8, 1e-4))
+
+
+def _step_network():
+    """A hand-set network (2 hidden units) whose output is a step function of
+    the features: h1[0] = sign(r - 7.5), h1[1] = sign(-log10(svd_tol) - 6.5)
+    (saturated tanh), h2 = sign(h1), y = -4.5 - h2[0] - h2[1].  So y = -6.5
+    exactly when r >= 8 and svd_tol < 10^-6.5, and y >= -4.5 otherwise."""
+    nf, nh = M.N_FEATURES, 2
+    p = np.zeros(M.n_params(nf, nh))
+    W1, b1, W2, b2, w3, _ = M.unpack(p, nf, nh)
+    K = 1e5
+    W1[0, 3], b1[0] = K, -K * 7.5 / 16          # feature 3 is r / 16
+    W1[1, 4], b1[1] = K, -K * 6.5 / 16          # feature 4 is -log10(tol) / 16
+    W2[0, 0] = W2[1, 1] = 50.0
+    w3[:] = -1.0
+    p[-1] = -4.5
+    return p, nh
+
+
+def test_select_order_on_a_hand_set_network():
+    """The selection tries truncation tolerances 3 tol, tol, tol/3, tol/10
+    (those below 1) loosest first and r ascending within each, and returns
+    the first whose prediction + margin <= log10 tol: here only
+    (r >= 8, svd_tol < 10^-6.5) predicts 10^-6.5, so tol = 1e-6 selects
+    (8, 1e-7) -- the first three tolerances (3e-6, 1e-6, 3.3e-7) fail and the
+    fourth passes at its smallest qualifying r."""
+    p, nh = _step_network()
+    y = M.forward(p, np.stack([M.features(1024, 1, r, st) for r in (7, 8)
+                               for st in (1e-6, 1e-7)]), nh)
+    assert np.allclose(y, [-2.5, -4.5, -4.5, -6.5], atol=1e-12)
+    assert M.select(p, nh, 1024, 1, 1e-6) == (8, 1e-7)
+    # a target the network never predicts: no candidate (fixed-order fallback)
+    assert M.select(p, nh, 1024, 1, 1e-8) is None
+    # target 10^-4.4 with margin 0: -4.5 qualifies, so the loosest truncation
+    # (3 tol) is kept and r = 8 is the smallest r reaching it
+    t = 10.0 ** -4.4
+    r, st = M.select(p, nh, 1024, 1, t, margin=0.0)
+    assert r == 8 and abs(st - 3 * t) < 1e-18
+    # rmin above 8 moves the answer to rmin
+    assert M.select(p, nh, 1024, 1, 1e-6, rmin=11) == (11, 1e-7)
+    # a target of 0.5: 3 tol = 1.5 is skipped (truncation tolerances stay below 1)
+    assert M.select(p, nh, 1024, 1, 0.5, margin=-10.0) == (2, 0.5)

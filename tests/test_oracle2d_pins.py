@@ -4,6 +4,10 @@ x-independent phase, interpolation error decaying with r, compression
 within the truncation tolerance, the corona partition as a set identity,
 linearity of the multiscale sum over the parts, and the MIBF against the
 dense product at the magnitude expected for r = 5 (Sec. 6.3)."""
+import json
+import math
+import os
+
 import numpy as np
 import pytest
 
@@ -19,6 +23,9 @@ def _grid_x(n):
 def _grid_xi(lo, w):
     j1, j2 = np.meshgrid(np.arange(w), np.arange(w), indexing="ij")
     return np.stack([lo[0] + j1.ravel(), lo[1] + j2.ravel()], -1).astype(np.float64)
+
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")
 
 
 def _cn(m, k, seed):
@@ -132,3 +139,54 @@ def test_mibf_against_dense():
         pre, opt = D.nnz_mibf(built, cidx, len(x))
         assert pre > opt
     assert errs[1] < errs[0] and errs[1] < 3e-2
+
+
+def test_fio2d_phase_at_special_points():
+    """Phi of Sec. 6.3 where c1, c2 are known by hand: at x = (0, 0) the
+    sines vanish and the cosines are 1 (c1 = p0/p2, c2 = (p0+p1)/p2); at
+    x = (1/4, 1/4) the reverse (c1 = (p0+p1)/p2, c2 = p0/p2); at x = (1/2, 1/4)
+    both products vanish (c1 = c2 = p0/p2).  Frequencies are picked so the
+    square root is an integer or a simple fraction; swapped sin/cos, a
+    wrong divisor or a dropped x.xi term all change the reduced phase."""
+    p = (2.0, 1.0, 16.0)
+    cases = [
+        # x, xi, exact Phi
+        ((0.0, 0.0), (64.0, 0.0), 64 * 2 / 16),                      # c1 |xi1| = 8
+        ((0.0, 0.0), (0.0, 80.0), 80 * 3 / 16),                      # c2 |xi2| = 15
+        ((0.0, 0.0), (96.0, 64.0), math.sqrt(12.0 ** 2 + 12.0 ** 2)),  # c1 = 1/8, c2 = 3/16
+        ((0.25, 0.25), (64.0, 0.0), 16 + 64 * 3 / 16),               # x.xi + c1 |xi1|
+        ((0.25, 0.25), (0.0, -80.0), -20 + 80 * 2 / 16),             # x.xi + c2 |xi2|
+        ((0.5, 0.25), (48.0, 64.0), 24 + 16 + math.hypot(6.0, 8.0)),  # c1 = c2 = 1/8
+    ]
+    for x, xi, phi in cases:
+        t = D.phase_frac_2d(2, p, np.array([x]), np.array([xi]))[0]
+        ref = phi - round(phi)
+        d = abs(t - ref)
+        assert min(d, 1 - d) < 1e-12, (x, xi, t, ref)
+    # the divisor is a parameter: /32 halves the root term
+    t32 = D.phase_frac_2d(2, (2.0, 1.0, 32.0), np.array([(0.0, 0.0)]), np.array([(0.0, 80.0)]))[0]
+    assert abs(t32 - (7.5 - 8.0)) < 1e-12
+
+
+@pytest.mark.parametrize("n,r,tol", [(32, 6, 1e-3), (64, 6, 1e-3), (32, 9, 3e-6)])
+def test_mibf_matches_table4(n, r, tol):
+    """Table 4 (Sec. 6.3), the paper's own setting (c1, c2 with /32, centre
+    16 x 16): with the truncation near the interpolation error of the order
+    (1e-3 at r = 6, 3e-6 at r = 9 per dimension; the paper does not state its
+    tolerance) the MIBF's R_comp is within 10 % and its sampled error (256
+    rows, eq:relativeerr) within a factor 4 of the printed values."""
+    golden = json.load(open(GOLDEN))
+    paper = {(row[0], row[1]): (row[2], row[3]) for row in golden["table4_fio2d_mibf"]}
+    eps_p, rc_p = paper[(n, r)]
+    prm = (2.0, 1.0, 32.0)
+    x = _grid_x(n)
+    xi = _grid_xi((-n // 2, -n // 2), n)
+    g = _cn(len(xi), 1, 8)
+    rows = np.random.default_rng(9).choice(len(x), 256, replace=False)
+    ud = D.dense_apply_2d(2, prm, x, xi, g, rows=rows)
+    part, built, cidx = D.mibf_build(2, prm, x, xi, n, r, tol)
+    u = D.mibf_apply(2, prm, x, xi, g, built, cidx)
+    pre, opt = D.nnz_mibf(built, cidx, len(x))
+    eps = O.rel_error(u[rows], ud)
+    assert abs(pre / opt / rc_p - 1) < 0.10, (pre / opt, rc_p)
+    assert eps_p / 4 < eps < 1.5 * eps_p, (eps, eps_p)
