@@ -42,16 +42,35 @@ extern "C" {
 #define IBF_ERR_NOT_BUILT     -5   /* ibf_apply/ibf_query before ibf_build */
 
 /* ---- phase functions (paper Sec. 6) ----
- * IBF_PHASE_DFT       Phi = s x xi,  s = params[0] (default +1)        Sec. 6.1
+ * IBF_PHASE_DFT       Phi = s x.xi,  s = params[0] (default +1)       Sec. 6.1
  * IBF_PHASE_FIO1D     Phi = x xi + c(x)|xi|, c = (p0 + p1 sin 2 pi x)/p2 Sec. 6.2
- *                     (defaults 2, 1, 8 as in eqn:1D-FIO-kernal)
- * IBF_PHASE_SEPARABLE Phi = p0 x + p1 xi; the remainder R^{AB} of
- *                     eqn:RAB vanishes, so the factorization is exact.
+ *                     (defaults 2, 1, 8 as in eqn:1D-FIO-kernal); dim 1
+ * IBF_PHASE_FIO2D     Phi = x.xi + sqrt(c1^2 xi1^2 + c2^2 xi2^2),       Sec. 6.3
+ *                     c1 = (p0 + p1 sin 2 pi x1 sin 2 pi x2)/p2,
+ *                     c2 = (p0 + p1 cos 2 pi x1 cos 2 pi x2)/p2
+ *                     (defaults 2, 1, 16; the paper's Table 4 uses p2 = 32); dim 2
+ * IBF_PHASE_SEPARABLE dim 1: Phi = p0 x + p1 xi; dim 2: Phi = p0 xi1 + p1 xi2.
+ *                     The remainder R^{AB} of eqn:RAB vanishes, so the
+ *                     factorization is exact.
  */
 #define IBF_PHASE_DFT        0
 #define IBF_PHASE_FIO1D      1
 #define IBF_PHASE_FIO2D      2
 #define IBF_PHASE_SEPARABLE  3
+
+/* ---- amplitude a(x, xi) of the kernel a exp(2 pi i Phi) (eqn:FIO, Sec. 1) ----
+ * The paper sets a == 1 after noting that a smooth symbol of order zero is
+ * numerically low-rank.  With a smooth amplitude the interpolation of Sec. 2.1
+ * is applied to a(x, xi) exp(2 pi i R^{AB}), and a enters only the switch
+ * blocks K(g^A_t, g^B_s) of eqn:switchlocM.  dim 1 only.
+ * IBF_AMP_NONE       a == 1
+ * IBF_AMP_SEPARABLE  a = (q0 + q1 sin 2 pi x + q2 cos 2 pi x)(q3 + q4 xi / sqrt(xi^2 + q5^2)),
+ *                    q5 != 0 (6 parameters)
+ * IBF_AMP_WAVE       a = q0 + q1 cos(2 pi (x + xi / q2)), q2 != 0 (3 parameters)
+ */
+#define IBF_AMP_NONE       0
+#define IBF_AMP_SEPARABLE  1
+#define IBF_AMP_WAVE       2
 
 /* ---- factor storage / apply precision ---- */
 #define IBF_FP64    0   /* complex double factors and vectors */
@@ -61,29 +80,60 @@ extern "C" {
 typedef struct ibf_plan_s* ibf_plan_t;
 
 /*
- * Problem descriptor (1-D).  X lies in [0, 1) and Omega in
- * [omega_lo, omega_lo + omega_width).  Tree depth L = ceil(log2 omega_width)
- * keeps w_A * w_B <= 1 for every box pair (A at level l of T_X, B at level
- * L - l of T_Omega, Sec. 2.1 and Sec. 3).  Leaves hold about `leaf` points;
- * the butterfly runs from level l0 = log2(leaf) to L - l0.
+ * Problem descriptor.
+ *
+ * dim 1: X lies in [0, 1) and Omega in [omega_lo, omega_lo + omega_width).
+ * Tree depth L = ceil(log2 omega_width) keeps w_A * w_B <= 1 for every box
+ * pair (A at level l of T_X, B at level L - l of T_Omega, Sec. 2.1 and Sec. 3).
+ * Leaves hold about `leaf` points; the butterfly runs from level
+ * l0 = log2(leaf) to L - l0.
+ *
+ * dim 2 (Sec. 5, the multiscale IBF of eq:domaindecomp / eq:f1): x and xi are
+ * row-major [n][2] arrays; X lies in [0, 1)^2 and Omega in the square
+ * [-W/2, W/2)^2 with W = omega_width (a power of two >= 32, omega_lo = -W/2).  Omega is split into coronas of 12 dyadic boxes each, down to a
+ * 16 x 16 centre square summed directly; every box runs its own quadtree IBF
+ * with a tensor r x r Chebyshev grid.  phase_id IBF_PHASE_DFT, FIO2D or
+ * SEPARABLE; 2 <= r <= 5 (r^2 grid rows on one 32-lane group); tol >= 1e-7
+ * (the compression resolves singular values through Gram matrices); leaf is
+ * the side of an Omega leaf box: 4, 16 or 64 points; no sweep-in, amplitude,
+ * fixed ranks or learned order.
  */
 typedef struct {
-  int dim;                   /* 1 (2 reserved) */
+  int dim;                   /* 1 or 2 */
   int64_t n_x;               /* |X|  (rows)    */
   int64_t n_xi;              /* |Omega| (cols) */
-  const double* x;           /* host, n_x values in [0, 1), any order */
-  const double* xi;          /* host, n_xi values in the Omega domain, any order */
-  double omega_lo;           /* Omega domain start; use -n_xi/2 for the paper's grid */
-  double omega_width;        /* Omega domain width; <= 0 selects n_xi */
+  const double* x;           /* host, n_x points (dim values each), any order */
+  const double* xi;          /* host, n_xi points (dim values each), any order */
+  double omega_lo;           /* dim 1: Omega domain start; -n_xi/2 for the paper's grid */
+  double omega_width;        /* Omega domain width; <= 0 selects n_xi (dim 1) */
   int phase_id;              /* IBF_PHASE_* */
   const double* phase_params;/* host, may be NULL for defaults */
   int n_params;
-  int r;                     /* Chebyshev points per box, 2 <= r <= 16 (Sec. 2.1) */
-  double tol;                /* relative singular-value cut per block, 0 < tol < 1 */
+  int r;                     /* Chebyshev points per box (per dimension), 2 <= r <= 16
+                                (Sec. 2.1).  dim 1: r <= 0 selects the order with the
+                                learned predictor (`predictor`), or r = 12 without one */
+  double tol;                /* relative singular-value cut per block, 0 < tol < 1; with
+                                r <= 0 the accuracy target the predictor aims at */
   int leaf;                  /* points per leaf, a power of two >= 2 */
   int precision;             /* IBF_FP64 | IBF_FP32 | IBF_BF16X2 */
-  int sweep_in;              /* 0 off, 1 on (Sec. 4.3) */
+  int sweep_in;              /* 0 off, 1 on (Sec. 4.3), -1 auto: on iff some leaf holds
+                                fewer than r points and none more than 64 (the
+                                sweep-in's leaf limit) */
   int device;                /* HIP device ordinal the plan lives on */
+  /* optional (zero / NULL: not used) */
+  const int* fixed_ranks;    /* host, L - 2 l0 + 1 entries, one per coefficient level
+                                l0 .. L - l0: every block whose basis lives at level l
+                                keeps at most fixed_ranks[l - l0] singular values (the
+                                tolerance rule still applies below the cap; a cut never
+                                splits a cluster of equal singular values, it moves
+                                below it); entries <= 0 leave a level uncapped.  The
+                                array is read by ibf_plan.  dim 1 */
+  int amp_id;                /* IBF_AMP_* */
+  const double* amp_params;  /* host, n_amp_params values (read by ibf_plan) */
+  int n_amp_params;
+  const float* predictor;    /* device, parameters of the learned order predictor
+                                (ibf_mlp_*; read by ibf_build when r <= 0) */
+  int predictor_hidden;      /* its hidden width (8, 16 or 32) */
 } ibf_desc;
 
 /* Per-plan sizes and timings (filled by ibf_query). */
@@ -101,14 +151,21 @@ typedef struct {
   int sweep_in;              /* 1 when the sweep-in stage ran */
   int rank_in_g[64];         /* sweep-in ranks, U/G side, index l - l0 (levels h .. L-l0) */
   int rank_in_h[64];         /* sweep-in ranks, V/H side, index l - l0 (levels l0 .. h) */
+  int r;                     /* Chebyshev order the build used (0 before a learned
+                                plan's first build) */
+  double tol;                /* truncation tolerance the build used */
+  int learned;               /* 1 when the order came from the predictor */
 } ibf_info;
 
 /*
  * Validate the descriptor, build the dyadic trees on the host (sort points
- * into leaves, Sec. 3 "Preliminaries") and size every buffer.  No device
- * work.  Errors: INVALID_ARG if n < leaf^2, r < 2, tol outside (0,1), a
- * point outside its domain, leaf not a power of two; UNSUPPORTED for dim != 1,
- * r > 16 or an unknown phase.  On success *out owns the plan.
+ * into leaves, Sec. 3 "Preliminaries"; quadtrees and coronas for dim 2,
+ * Sec. 5) and size every buffer.  No device work.  Errors: INVALID_ARG if
+ * n < leaf^2, tol outside (0,1), a point outside its domain, leaf not a power
+ * of two, sweep_in outside -1..1, a bad amplitude or fixed_ranks entry count;
+ * UNSUPPORTED for dim other than 1 or 2, r > 16 (r > 5 for dim 2), an unknown
+ * phase or amplitude, or an option dim 2 does not provide.  On success *out
+ * owns the plan.
  */
 int ibf_plan(const ibf_desc* desc, ibf_plan_t* out);
 
@@ -117,9 +174,12 @@ int ibf_plan(const ibf_desc* desc, ibf_plan_t* out);
  * evaluation with exact mod-1 reduction, FP64 Lagrange weights, the middle
  * SVDs (eq:KeqUMV), the sweep toward U (eqn:GC) and toward V (eqn:HR), the
  * outer factors (Ubar = U C, Vbar = V R, eqn:V0), the optional sweep-in, and
- * conversion to the storage precision.  `hip_stream` orders the work and is
- * synchronised before return.  Rebuilding frees the previous factors.
- * Errors: OOM, DEVICE.
+ * conversion to the storage precision.  A plan with r <= 0 first picks its
+ * order and truncation with the predictor (as ibf_mlp_select with margin 0.3,
+ * r in 2..16), falling back to r = 12 at tol.  `hip_stream` orders the work
+ * and is synchronised before return.  Rebuilding frees the previous factors.
+ * Errors: OOM, DEVICE; UNSUPPORTED when the sweep-in meets a leaf of more
+ * than 64 points.
  */
 int ibf_build(ibf_plan_t plan, void* hip_stream);
 
@@ -275,6 +335,19 @@ int ibf_dense_apply(int phase_id, const double* phase_params, int n_params,
                     const double* x, int64_t n_x, const double* xi, int64_t n_xi,
                     const void* g, int64_t ldg, void* u, int64_t ldu, int64_t nrhs,
                     void* hip_stream);
+
+/*
+ * Relative error of eq:relativeerr on the device: out[0] =
+ * ||u - ref||_F / ||ref||_F over all nrhs columns, out[1] = the largest
+ * per-column ratio ||u_c - ref_c|| / ||ref_c||.  u and ref are device
+ * arrays, column-major n x nrhs with leading dimensions ldu, ldr >= n,
+ * complex double2 for IBF_FP64 and float2 otherwise (both the same type);
+ * sums run in FP64.  out is host memory (2 doubles).  Allocates a small
+ * device buffer and synchronises the stream.  Used for the predictor's
+ * training labels and by the tests.  Errors: INVALID_ARG, OOM, DEVICE.
+ */
+int ibf_rel_error(const void* u, int64_t ldu, const void* ref, int64_t ldr, int64_t n,
+                  int64_t nrhs, int precision, double* out, void* hip_stream);
 
 /*
  * Learned Chebyshev-order predictor.  The paper fixes one order r and reports

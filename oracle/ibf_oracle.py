@@ -985,6 +985,13 @@ def rel_error(u, u_ref):
     return float(np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref))
 
 
+def rel_error_cols(u, u_ref):
+    """eq:relativeerr per right-hand side (column); returns the largest."""
+    u = np.asarray(u).reshape(len(u), -1)
+    u_ref = np.asarray(u_ref).reshape(len(u_ref), -1)
+    return float(np.max(np.linalg.norm(u - u_ref, axis=0) / np.linalg.norm(u_ref, axis=0)))
+
+
 def build_optimal(kind, params, x, xi, r, tol, leaf=16, sweep_in_on=False,
                   lo=None, W=None, amp=None, caps=None):
     """Convenience: geometry, preliminary factors, sweep-out [, sweep-in]."""

@@ -1615,8 +1615,13 @@ int plan2d(const ibf_desc* d, ibf_plan_t* out) {
   if (leaf_side < 2) return bad("ibf_plan: dim 2 needs leaf = 4, 16 or 64 points (a square)");
   if (d->precision < IBF_FP64 || d->precision > IBF_BF16X2)
     return bad("ibf_plan: unknown precision");
-  if (d->sweep_in != 0) {
+  if (d->sweep_in > 0) {   // -1 (auto) resolves to off: grid leaves are full
     set_error("ibf_plan: the sweep-in stage is not provided for dim 2");
+    return IBF_ERR_UNSUPPORTED;
+  }
+  if (d->sweep_in < -1) return bad("ibf_plan: sweep_in must be -1, 0 or 1");
+  if (d->amp_id != IBF_AMP_NONE || d->fixed_ranks) {
+    set_error("ibf_plan: amplitudes and fixed ranks are provided for dim 1");
     return IBF_ERR_UNSUPPORTED;
   }
   const double W = d->omega_width;

@@ -16,6 +16,7 @@
 // All arithmetic is FP64; the stored factors are converted to the plan's
 // storage precision at the end (k_pack_stage / k_ubar / k_vbar).
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -474,6 +475,22 @@ int build_plan(ibf_plan_t p, hipStream_t s) {
   IBF_HIP_CHECK(hipSetDevice(p->device));
   free_factors(p);
   int rc;
+  if (p->learned && p->r == 0) {
+    // order and truncation from the learned error model (a plan with no
+    // predictor, or no qualifying candidate, falls back to r = 12 at tol)
+    int r = 0;
+    double st = p->target_tol;
+    if (p->predictor) {
+      rc = ibf_mlp_select(p->predictor, p->predictor_hidden, p->nxi, p->phase.kind, p->target_tol,
+                          0.3, 2, kMaxR, &r, &st, s);
+      if (rc) return rc;
+    }
+    if (r == 0) {
+      r = 12;
+      st = p->target_tol;
+    }
+    set_order(p, r, st);
+  }
   if ((rc = upload(&p->d_xs, p->xs)) || (rc = upload(&p->d_xis, p->xis)) ||
       (rc = upload(&p->d_perm_x, p->perm_x)) || (rc = upload(&p->d_perm_xi, p->perm_xi)) ||
       (rc = upload(&p->d_xoff, p->xoff)) || (rc = upload(&p->d_xioff, p->xioff)) ||
@@ -508,7 +525,8 @@ int build_plan(ibf_plan_t p, hipStream_t s) {
   std::vector<DevBuf<double2>> stages(nst);
   for (int i = 0; i < nst; ++i) IBF_HIP_CHECK(stages[i].alloc((size_t)np * R * 2 * R));
 
-  SweepArgs A{p->phase, geo, cheb.ptr, p->tol, np, rank_max.ptr, nnz.ptr + nst};
+  SweepArgs A{p->phase, geo, cheb.ptr, p->tol, np, rank_max.ptr, nnz.ptr + nst,
+              p->caps.empty() ? nullptr : p->caps.data()};
   kern::middle(R, A, Cb[0].ptr, Rb[0].ptr, rk_mid.ptr, s);
 
   // sweep toward U
@@ -620,6 +638,69 @@ int dense_apply(const PhaseDesc& ph, const double* x, int64_t nx, const double* 
   hipLaunchKernelGGL(k_dense, dim3((unsigned)((nx + 255) / 256), (unsigned)nrhs), dim3(256), 0, s,
                      ph, x, nx, xi, nxi, (const double2*)g, ldg, (double2*)u, ldu);
   IBF_HIP_CHECK(hipGetLastError());
+  return IBF_OK;
+}
+
+// Squared norms for the relative error of eq:relativeerr: per column c,
+// acc[2c] += sum |u - ref|^2 and acc[2c+1] += sum |ref|^2 over this block's
+// rows (FP64 sums of the block, one atomic per block and column).
+template <typename T>
+__global__ __launch_bounds__(256) void k_err_sums(const T* __restrict__ u, int64_t ldu,
+                                                  const T* __restrict__ ref, int64_t ldr,
+                                                  int64_t n, double* acc) {
+  const int64_t c = blockIdx.y;
+  double d2 = 0.0, r2 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const T a = u[c * ldu + i], b = ref[c * ldr + i];
+    const double dx = (double)a.x - (double)b.x, dy = (double)a.y - (double)b.y;
+    d2 += dx * dx + dy * dy;
+    r2 += (double)b.x * (double)b.x + (double)b.y * (double)b.y;
+  }
+  __shared__ double sd[256], sr[256];
+  sd[threadIdx.x] = d2;
+  sr[threadIdx.x] = r2;
+  __syncthreads();
+  for (int m = 128; m > 0; m >>= 1) {
+    if ((int)threadIdx.x < m) {
+      sd[threadIdx.x] += sd[threadIdx.x + m];
+      sr[threadIdx.x] += sr[threadIdx.x + m];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(&acc[2 * c], sd[0]);
+    atomicAdd(&acc[2 * c + 1], sr[0]);
+  }
+}
+
+int rel_error(const void* u, int64_t ldu, const void* ref, int64_t ldr, int64_t n, int64_t nrhs,
+              int precision, double* out, hipStream_t s) {
+  DevBuf<double> acc;
+  IBF_HIP_CHECK(acc.alloc((size_t)2 * nrhs));
+  IBF_HIP_CHECK(hipMemsetAsync(acc.ptr, 0, sizeof(double) * 2 * nrhs, s));
+  const unsigned bx = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
+  if (n > 0) {
+    if (precision == IBF_FP64)
+      hipLaunchKernelGGL((k_err_sums<double2>), dim3(bx, (unsigned)nrhs), dim3(256), 0, s,
+                         (const double2*)u, ldu, (const double2*)ref, ldr, n, acc.ptr);
+    else
+      hipLaunchKernelGGL((k_err_sums<float2>), dim3(bx, (unsigned)nrhs), dim3(256), 0, s,
+                         (const float2*)u, ldu, (const float2*)ref, ldr, n, acc.ptr);
+    IBF_HIP_CHECK(hipGetLastError());
+  }
+  std::vector<double> h((size_t)2 * nrhs);
+  IBF_HIP_CHECK(hipMemcpyAsync(h.data(), acc.ptr, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+  IBF_HIP_CHECK(hipStreamSynchronize(s));
+  double d2 = 0.0, r2 = 0.0, cmax = 0.0;
+  for (int64_t c = 0; c < nrhs; ++c) {
+    d2 += h[2 * c];
+    r2 += h[2 * c + 1];
+    const double e = h[2 * c + 1] > 0 ? std::sqrt(h[2 * c] / h[2 * c + 1]) : (h[2 * c] > 0 ? INFINITY : 0.0);
+    cmax = std::max(cmax, e);
+  }
+  out[0] = r2 > 0 ? std::sqrt(d2 / r2) : (d2 > 0 ? INFINITY : 0.0);
+  out[1] = cmax;
   return IBF_OK;
 }
 

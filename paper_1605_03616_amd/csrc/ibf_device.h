@@ -61,6 +61,21 @@ __device__ inline double phase_frac(const PhaseDesc& P, double x, double xi) {
   return t - rint(t);
 }
 
+// Amplitude a(x, xi) of the kernel a exp(2 pi i Phi) (paper eqn:FIO); 1 when
+// the descriptor has none.  Real-valued families:
+//   separable: (q0 + q1 sin 2 pi x + q2 cos 2 pi x)(q3 + q4 xi / sqrt(xi^2 + q5^2))
+//   wave:      q0 + q1 cos(2 pi (x + xi / q2))
+__device__ inline double amp_val(const PhaseDesc& P, double x, double xi) {
+#pragma clang fp contract(off)
+  if (P.amp == IBF_AMP_SEPARABLE) {
+    const double fx = P.q[0] + P.q[1] * sinpi(2.0 * x) + P.q[2] * cospi(2.0 * x);
+    const double fxi = P.q[3] + P.q[4] * xi / sqrt(xi * xi + P.q[5] * P.q[5]);
+    return fx * fxi;
+  }
+  if (P.amp == IBF_AMP_WAVE) return P.q[0] + P.q[1] * cospi(2.0 * (x + xi / P.q[2]));
+  return 1.0;
+}
+
 // exp(2 pi i Phi(x, xi))
 __device__ inline double2 kval(const PhaseDesc& P, double x, double xi) {
   double t = phase_frac(P, x, xi);
@@ -214,6 +229,28 @@ __device__ __forceinline__ int rank_positions(const double (&sig)[R], double tol
     k += (smax > 0.0 && sig[j] > tol * smax) ? 1 : 0;
   }
   return k;
+}
+
+// Fixed-rank mode: at most `cap` of the k kept values (cap <= 0: no cap).  A
+// cut that would split a cluster of equal singular values (the first dropped
+// value >= (1 - 1e-10) times the last kept one) moves down until it does not:
+// the kept subspace of a degenerate cluster is not unique.
+template <int R>
+__device__ __forceinline__ int cap_rank(const double (&sig)[R], const int (&pos)[R], int k,
+                                        int cap) {
+  if (cap <= 0 || cap >= k) return k;
+  int kk = cap;
+  for (int it = 0; it < R && kk > 1; ++it) {
+    double first = 0.0, last = 0.0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      first = pos[j] == kk ? sig[j] : first;
+      last = pos[j] == kk - 1 ? sig[j] : last;
+    }
+    if (first >= (1.0 - 1e-10) * last) --kk;
+    else break;
+  }
+  return kk;
 }
 
 // ---------------------------------------------------------------------------

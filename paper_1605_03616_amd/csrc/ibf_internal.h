@@ -26,6 +26,8 @@ constexpr int kMaxParams = 6;
 struct PhaseDesc {
   int kind;
   double p[kMaxParams];
+  int amp;                 // IBF_AMP_* (amplitude of eqn:FIO; enters the switch blocks only)
+  double q[kMaxParams];
 };
 
 // Device-side geometry of one tree pair: T_X on [0,1), T_Omega on
@@ -72,6 +74,14 @@ struct ibf_plan_s {
   ibf::PhaseDesc phase{};
   int r = 0, leaf = 0, precision = 0, sweep_in = 0;
   double tol = 0;
+  // learned order (r <= 0 in the descriptor): chosen by ibf_build from the
+  // predictor (device parameters, not owned), r = 12 without one
+  bool learned = false;
+  const float* predictor = nullptr;
+  int predictor_hidden = 0;
+  double target_tol = 0;       // the accuracy target of a learned plan
+  int sweep_auto = 0;          // sweep_in = -1: decided when r is known
+  std::vector<int> caps;       // fixed-rank caps per level l0..L-l0 (empty: none)
   ibf::Geo geo{};
   int64_t npairs = 0, nleaf = 0;
 
@@ -125,6 +135,8 @@ int dense_apply(const PhaseDesc& ph, const double* x, int64_t nx, const double* 
                 const void* g, int64_t ldg, void* u, int64_t ldu, int64_t nrhs, hipStream_t s);
 int eval_kernel(const PhaseDesc& ph, const double* x, const double* xi,
                 int64_t n, void* out, hipStream_t s);
+int rel_error(const void* u, int64_t ldu, const void* ref, int64_t ldr, int64_t n, int64_t nrhs,
+              int precision, double* out, hipStream_t s);
 void free_factors(ibf_plan_t p);
 void free_adjoint(ibf_plan_t p);
 int apply_adjoint(ibf_plan_t p, const void* h, int64_t ldh, void* v, int64_t ldv, int64_t nrhs,
@@ -138,6 +150,9 @@ void free2d_factors(ibf_plan_t p);
 void destroy2d(ibf_plan_t p);
 void query2d(ibf_plan_t p, ibf_info* info);
 size_t complex_bytes(int precision);
+// the Chebyshev order and truncation of a dim-1 plan: sets r, tol, the
+// preliminary entry count and the automatic sweep-in choice
+void set_order(ibf_plan_t p, int r, double tol);
 }  // namespace ibf
 
 #define IBF_HIP_CHECK(expr)                                                   \

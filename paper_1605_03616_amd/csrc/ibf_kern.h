@@ -53,6 +53,8 @@ struct SweepArgs {
   int64_t npairs;
   int* rank_max;
   unsigned long long* nnz;
+  const int* caps;     // host: fixed-rank cap per level l0..L-l0 (null: none)
+  int cap_at(int level) const { return caps ? caps[level - geo.l0] : 0; }
 };
 
 template <int R>

@@ -7,6 +7,7 @@
 // integer / FP64 bookkeeping; all factor arithmetic runs on the device.
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -95,6 +96,27 @@ hipError_t dev_free(void* ptr) {
 
 size_t complex_bytes(int precision) { return precision == IBF_FP64 ? 16 : 8; }
 
+void set_order(ibf_plan_t p, int r, double tol) {
+  p->r = r;
+  p->geo.r = r;
+  p->tol = tol;
+  const int L = p->geo.L, l0 = p->geo.l0;
+  // Preliminary non-zeros (memory numerator of the compression ratio).
+  const int nstages = L - 2 * l0;
+  p->nnz_prelim = (p->nx + p->nxi) * ((int64_t)1 << l0) * r +
+                  (int64_t)nstages * p->npairs * 2 * r * r + p->npairs * r * r;
+  // sweep_in = -1: on iff a leaf holds fewer than r points (Sec. 4.3: the
+  // sweep-in is what keeps the ranks of such leaves below r) and no leaf
+  // exceeds the sweep-in kernels' 64 points
+  if (p->sweep_auto) {
+    int32_t mn = INT32_MAX;
+    for (size_t b = 0; b + 1 < p->xoff.size(); ++b) mn = std::min(mn, p->xoff[b + 1] - p->xoff[b]);
+    for (size_t b = 0; b + 1 < p->xioff.size(); ++b)
+      mn = std::min(mn, p->xioff[b + 1] - p->xioff[b]);
+    p->sweep_in = (mn < r && p->smax_x <= 64 && p->smax_xi <= 64) ? 1 : 0;
+  }
+}
+
 void free_factors(ibf_plan_t p) {
   free_adjoint(p);
   for (auto& st : p->stages)
@@ -124,16 +146,20 @@ int ibf_plan(const ibf_desc* d, ibf_plan_t* out) {
     return fail(IBF_ERR_INVALID_ARG, "ibf_plan: more than 2^30 points");
   if (!d->x || !d->xi) return fail(IBF_ERR_INVALID_ARG, "ibf_plan: null point array");
   if (d->dim == 2) return ibf::plan2d(d, out);
-  if (d->r < 2) return fail(IBF_ERR_INVALID_ARG, "ibf_plan: r must be >= 2");
+  const bool learned = d->r <= 0;
+  if (!learned && d->r < 2) return fail(IBF_ERR_INVALID_ARG, "ibf_plan: r must be >= 2");
   if (d->r > ibf::kMaxR) return fail(IBF_ERR_UNSUPPORTED, "ibf_plan: r > 16 not supported");
+  if (learned && d->predictor && d->predictor_hidden != 8 && d->predictor_hidden != 16 &&
+      d->predictor_hidden != 32)
+    return fail(IBF_ERR_INVALID_ARG, "ibf_plan: predictor_hidden must be 8, 16 or 32");
   if (!(d->tol > 0.0 && d->tol < 1.0))
     return fail(IBF_ERR_INVALID_ARG, "ibf_plan: tol must lie in (0, 1)");
   if (d->leaf < 2 || (d->leaf & (d->leaf - 1)))
     return fail(IBF_ERR_INVALID_ARG, "ibf_plan: leaf must be a power of two >= 2");
   if (d->precision < IBF_FP64 || d->precision > IBF_BF16X2)
     return fail(IBF_ERR_INVALID_ARG, "ibf_plan: unknown precision");
-  if (d->sweep_in != 0 && d->sweep_in != 1)
-    return fail(IBF_ERR_INVALID_ARG, "ibf_plan: sweep_in must be 0 or 1");
+  if (d->sweep_in < -1 || d->sweep_in > 1)
+    return fail(IBF_ERR_INVALID_ARG, "ibf_plan: sweep_in must be -1, 0 or 1");
 
   ibf::PhaseDesc ph{};
   ph.kind = d->phase_id;
@@ -160,6 +186,32 @@ int ibf_plan(const ibf_desc* d, ibf_plan_t* out) {
     default:
       return fail(IBF_ERR_UNSUPPORTED, "ibf_plan: unsupported phase for dim 1");
   }
+  // amplitude a(x, xi) of eqn:FIO
+  ph.amp = d->amp_id;
+  {
+    const int na = d->n_amp_params;
+    const double* q = d->amp_params;
+    if (na < 0 || na > ibf::kMaxParams || (na > 0 && !q))
+      return fail(IBF_ERR_INVALID_ARG, "ibf_plan: bad amplitude parameters");
+    switch (d->amp_id) {
+      case IBF_AMP_NONE:
+        break;
+      case IBF_AMP_SEPARABLE:
+        if (na != 6 || q[5] == 0.0)
+          return fail(IBF_ERR_INVALID_ARG, "ibf_plan: separable amplitude takes 6 parameters, q5 != 0");
+        for (int i = 0; i < 6; ++i) ph.q[i] = q[i];
+        break;
+      case IBF_AMP_WAVE:
+        if (na != 3 || q[2] == 0.0)
+          return fail(IBF_ERR_INVALID_ARG, "ibf_plan: wave amplitude takes 3 parameters, q2 != 0");
+        for (int i = 0; i < 3; ++i) ph.q[i] = q[i];
+        break;
+      default:
+        return fail(IBF_ERR_UNSUPPORTED, "ibf_plan: unknown amplitude");
+    }
+    for (int i = 0; i < na; ++i)
+      if (!std::isfinite(q[i])) return fail(IBF_ERR_INVALID_ARG, "ibf_plan: amplitude parameter not finite");
+  }
 
   const double W = d->omega_width > 0 ? d->omega_width : (double)d->n_xi;
   const double lo = d->omega_lo;
@@ -179,9 +231,19 @@ int ibf_plan(const ibf_desc* d, ibf_plan_t* out) {
   p->r = d->r;
   p->leaf = d->leaf;
   p->precision = d->precision;
-  p->sweep_in = d->sweep_in;
+  p->sweep_in = d->sweep_in > 0 ? 1 : 0;
+  p->sweep_auto = d->sweep_in < 0 ? 1 : 0;
   p->tol = d->tol;
-  p->geo = ibf::Geo{L, l0, L / 2, d->r, lo, W};
+  p->learned = learned;
+  p->predictor = d->predictor;
+  p->predictor_hidden = d->predictor_hidden;
+  p->target_tol = d->tol;
+  if (learned) p->r = 0;
+  p->geo = ibf::Geo{L, l0, L / 2, p->r, lo, W};
+  if (d->fixed_ranks) {
+    p->caps.assign(d->fixed_ranks, d->fixed_ranks + (L - 2 * l0 + 1));
+    for (int& c : p->caps) c = std::max(c, 0);
+  }
   p->npairs = (int64_t)1 << L;
   p->nleaf = (int64_t)1 << (L - l0);
 
@@ -213,11 +275,7 @@ int ibf_plan(const ibf_desc* d, ibf_plan_t* out) {
   for (int64_t i = 0; i < d->n_x; ++i) p->xs[i] = d->x[p->perm_x[i]];
   for (int64_t j = 0; j < d->n_xi; ++j) p->xis[j] = d->xi[p->perm_xi[j]];
 
-  // Preliminary non-zeros (memory numerator of the compression ratio).
-  const int r = d->r;
-  const int nstages = L - 2 * l0;
-  p->nnz_prelim = (d->n_x + d->n_xi) * ((int64_t)1 << l0) * r +
-                  (int64_t)nstages * p->npairs * 2 * r * r + p->npairs * r * r;
+  if (!learned) ibf::set_order(p, p->r, p->tol);
   *out = p;
   return IBF_OK;
 }
@@ -292,9 +350,13 @@ int ibf_query(ibf_plan_t p, ibf_info* info) {
   info->build_ms = p->build_ms;
   info->smax_x = p->smax_x;
   info->smax_xi = p->smax_xi;
-  info->sweep_in = p->rank_in_g.empty() ? 0 : 1;
+  // built: whether the sweep-in ran; before: whether it will (sweep_in = -1 resolved)
+  info->sweep_in = p->built ? (p->rank_in_g.empty() ? 0 : 1) : p->sweep_in;
   for (size_t i = 0; i < p->rank_in_g.size() && i < 64; ++i) info->rank_in_g[i] = p->rank_in_g[i];
   for (size_t i = 0; i < p->rank_in_h.size() && i < 64; ++i) info->rank_in_h[i] = p->rank_in_h[i];
+  info->r = p->r;
+  info->tol = p->tol;
+  info->learned = p->learned ? 1 : 0;
   return IBF_OK;
 }
 
@@ -357,6 +419,14 @@ int ibf_eval_kernel(int phase_id, const double* params, int n_params,
   if (rc) return rc;
   if (n == 0) return IBF_OK;
   return ibf::eval_kernel(ph, x, xi, n, out, (hipStream_t)stream);
+}
+
+int ibf_rel_error(const void* u, int64_t ldu, const void* ref, int64_t ldr, int64_t n,
+                  int64_t nrhs, int precision, double* out, void* stream) {
+  if (!u || !ref || !out || n < 0 || nrhs < 1 || nrhs > 65535 || ldu < n || ldr < n ||
+      precision < IBF_FP64 || precision > IBF_BF16X2)
+    return fail(IBF_ERR_INVALID_ARG, "ibf_rel_error: bad argument");
+  return ibf::rel_error(u, ldu, ref, ldr, n, nrhs, precision, out, (hipStream_t)stream);
 }
 
 int ibf_dense_apply(int phase_id, const double* params, int n_params, const double* x,

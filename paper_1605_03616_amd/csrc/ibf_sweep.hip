@@ -15,9 +15,9 @@ namespace {
 // ---------------------------------------------------------------------------
 template <int R, int G>
 __global__ __launch_bounds__(kBlock) void k_middle(PhaseDesc ph, Geo geo, const double* cheb,
-                                                   double tol, int64_t npairs, double2* Cout,
-                                                   double2* Rout, int* rk, int* rank_max,
-                                                   unsigned long long* nnz) {
+                                                   double tol, int cap, int64_t npairs,
+                                                   double2* Cout, double2* Rout, int* rk,
+                                                   int* rank_max, unsigned long long* nnz) {
   __shared__ double z[R];
   __shared__ double Lc[2 * R * R];
   load_cheb<R>(cheb, z, Lc);
@@ -37,13 +37,17 @@ __global__ __launch_bounds__(kBlock) void k_middle(PhaseDesc ph, Geo geo, const 
 #pragma unroll
   for (int t = 0; t < R; ++t) {
     double2 val = make_double2(0.0, 0.0);
-    if (row_ok) val = conjd(kval(ph, grid_pt(cA, wA, z[t]), gBs));
+    if (row_ok) {
+      // K(g^A_t, g^B_s) = a exp(2 pi i Phi): the amplitude enters here only
+      const double gAt = grid_pt(cA, wA, z[t]);
+      val = cscale(conjd(kval(ph, gAt, gBs)), ph.amp ? amp_val(ph, gAt, gBs) : 1.0);
+    }
     arow[t] = val;
   }
   double sig[R];
   jacobi_svd<R, G>(arow, v, lane, R, sig);
   int pos[R];
-  const int k = rank_positions<R>(sig, tol, pos);
+  const int k = cap_rank<R>(sig, pos, rank_positions<R>(sig, tol, pos), cap);
   if (valid && lane < R) {
     double2* Cp = Cout + (p * R + lane) * R;
     double2* Rp = Rout + (p * R + lane) * R;
@@ -69,7 +73,7 @@ __global__ __launch_bounds__(kBlock) void k_middle(PhaseDesc ph, Geo geo, const 
 // ---------------------------------------------------------------------------
 template <int R, int G>
 __global__ __launch_bounds__(kBlock) void k_sweep_g(PhaseDesc ph, Geo geo, const double* cheb,
-                                                    double tol, int l, int64_t npairs,
+                                                    double tol, int cap, int l, int64_t npairs,
                                                     const double2* Cin, double2* Cout,
                                                     double2* stage, const int* rk_in, int* rk_out,
                                                     int* rank_max, unsigned long long* nnz) {
@@ -122,7 +126,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_g(PhaseDesc ph, Geo geo, const
   double sig[R];
   jacobi_svd<R, G>(arow, v, lane, 2 * R, sig);
   int pos[R];
-  const int k = rank_positions<R>(sig, tol, pos);
+  const int k = cap_rank<R>(sig, pos, rank_positions<R>(sig, tol, pos), cap);
   if (valid && lane < R) {
     double2* Cp = Cout + (p * R + lane) * R;
 #pragma unroll
@@ -158,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_g(PhaseDesc ph, Geo geo, const
 // ---------------------------------------------------------------------------
 template <int R, int G>
 __global__ __launch_bounds__(kBlock) void k_sweep_h(PhaseDesc ph, Geo geo, const double* cheb,
-                                                    double tol, int l, int64_t npairs,
+                                                    double tol, int cap, int l, int64_t npairs,
                                                     const double2* Rin, double2* Rout,
                                                     double2* stage, const int* rk_in, int* rk_out,
                                                     int* rank_max, unsigned long long* nnz) {
@@ -209,7 +213,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_h(PhaseDesc ph, Geo geo, const
   double sig[R];
   jacobi_svd<R, G>(arow, v, lane, 2 * R, sig);
   int pos[R];
-  const int k = rank_positions<R>(sig, tol, pos);
+  const int k = cap_rank<R>(sig, pos, rank_positions<R>(sig, tol, pos), cap);
   if (valid && lane < R) {
     double2* Rp = Rout + (q * R + lane) * R;
 #pragma unroll
@@ -244,7 +248,8 @@ void launch_middle(const SweepArgs& A, double2* C, double2* Rm, int* rk, hipStre
   const int64_t threads = A.npairs * G;
   const unsigned blocks = (unsigned)((threads + kBlock - 1) / kBlock);
   hipLaunchKernelGGL((k_middle<R, G>), dim3(blocks), dim3(kBlock), 0, s, A.ph, A.geo, A.cheb,
-                     A.tol, A.npairs, C, Rm, rk, A.rank_max + (A.geo.h - A.geo.l0), A.nnz);
+                     A.tol, A.cap_at(A.geo.h), A.npairs, C, Rm, rk,
+                     A.rank_max + (A.geo.h - A.geo.l0), A.nnz);
 }
 
 template <int R>
@@ -255,7 +260,7 @@ void launch_sweep_g(const SweepArgs& A, int l, const double2* Cin, double2* Cout
   const int64_t threads = A.npairs * G;
   const unsigned blocks = (unsigned)((threads + kBlock - 1) / kBlock);
   hipLaunchKernelGGL((k_sweep_g<R, G>), dim3(blocks), dim3(kBlock), 0, s, A.ph, A.geo, A.cheb,
-                     A.tol, l, A.npairs, Cin, Cout, stage, rk_in, rk_out,
+                     A.tol, A.cap_at(l), l, A.npairs, Cin, Cout, stage, rk_in, rk_out,
                      A.rank_max + (l - A.geo.l0), nnz);
 }
 
@@ -267,7 +272,7 @@ void launch_sweep_h(const SweepArgs& A, int l, const double2* Rin, double2* Rout
   const int64_t threads = A.npairs * G;
   const unsigned blocks = (unsigned)((threads + kBlock - 1) / kBlock);
   hipLaunchKernelGGL((k_sweep_h<R, G>), dim3(blocks), dim3(kBlock), 0, s, A.ph, A.geo, A.cheb,
-                     A.tol, l, A.npairs, Rin, Rout, stage, rk_in, rk_out,
+                     A.tol, A.cap_at(l - 1), l, A.npairs, Rin, Rout, stage, rk_in, rk_out,
                      A.rank_max + (l - 1 - A.geo.l0), nnz);
 }
 

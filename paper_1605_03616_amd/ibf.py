@@ -25,7 +25,7 @@ EXPORTED = ["ibf_plan", "ibf_build", "ibf_apply", "ibf_apply_profile", "ibf_quer
             "ibf_apply_batch", "ibf_batch_destroy", "ibf_dense_apply", "ibf_mlp_n_params",
             "ibf_mlp_features", "ibf_mlp_forward", "ibf_mlp_grad_work", "ibf_mlp_loss_grad",
             "ibf_mlp_adam", "ibf_mlp_select", "ibf_tune", "ibf_set_tuning", "ibf_set_allocator",
-            "ibf_measure_peak", "ibf_apply_adjoint"]
+            "ibf_measure_peak", "ibf_apply_adjoint", "ibf_rel_error"]
 MLP_FEATURES = 5
 BATCH_GRAPH = 1
 PROFILE_MAX = 64
@@ -49,6 +49,12 @@ class IBFDesc(C.Structure):
         ("precision", C.c_int),
         ("sweep_in", C.c_int),
         ("device", C.c_int),
+        ("fixed_ranks", C.POINTER(C.c_int)),
+        ("amp_id", C.c_int),
+        ("amp_params", C.POINTER(C.c_double)),
+        ("n_amp_params", C.c_int),
+        ("predictor", C.c_void_p),
+        ("predictor_hidden", C.c_int),
     ]
 
 
@@ -66,6 +72,9 @@ class IBFInfo(C.Structure):
         ("sweep_in", C.c_int),
         ("rank_in_g", C.c_int * 64),
         ("rank_in_h", C.c_int * 64),
+        ("r", C.c_int),
+        ("tol", C.c_double),
+        ("learned", C.c_int),
     ]
 
 
@@ -136,12 +145,13 @@ def load(path: str = LIB_PATH):
     lib.ibf_set_allocator.argtypes = [ALLOC_FN, FREE_FN]
     lib.ibf_measure_peak.argtypes = [C.c_int, vp, C.POINTER(C.c_double)]
     lib.ibf_apply_adjoint.argtypes = [vp, vp, i64, vp, i64, i64, vp]
+    lib.ibf_rel_error.argtypes = [vp, i64, vp, i64, i64, i64, C.c_int, C.POINTER(C.c_double), vp]
     for name in ("ibf_plan", "ibf_build", "ibf_apply", "ibf_apply_profile", "ibf_query",
                  "ibf_destroy", "ibf_eval_kernel", "ibf_batch_create", "ibf_apply_batch",
                  "ibf_batch_destroy", "ibf_dense_apply", "ibf_mlp_n_params",
                  "ibf_mlp_features", "ibf_mlp_forward", "ibf_mlp_loss_grad", "ibf_mlp_adam",
                  "ibf_mlp_select", "ibf_tune", "ibf_set_tuning", "ibf_set_allocator", "ibf_measure_peak",
-                 "ibf_apply_adjoint"):
+                 "ibf_apply_adjoint", "ibf_rel_error"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -208,11 +218,18 @@ def _stream_handle(stream):
 
 
 def make_desc(x, xi, phase, params, r, tol, leaf, precision, sweep_in=0,
-              omega_lo=None, omega_width=0.0, device=0):
-    """Build an ibf_desc; returns (desc, keepalive) -- keep both alive."""
+              omega_lo=None, omega_width=0.0, device=0, fixed_ranks=None, amp=None,
+              predictor=None):
+    """Build an ibf_desc; returns (desc, keepalive) -- keep both alive.
+
+    fixed_ranks: per-level rank caps (levels l0 .. L - l0) or None; amp:
+    (amp_id, params) or None; predictor: (device float tensor, hidden width)
+    for r <= 0, or None."""
     x = np.ascontiguousarray(x, dtype=np.float64)
     xi = np.ascontiguousarray(xi, dtype=np.float64)
     prm = np.ascontiguousarray(params if params is not None else [], dtype=np.float64)
+    caps = None if fixed_ranks is None else np.ascontiguousarray(fixed_ranks, dtype=np.int32)
+    aprm = np.ascontiguousarray(amp[1] if amp is not None else [], dtype=np.float64)
     d = IBFDesc()
     d.dim = 2 if x.ndim == 2 else 1
     d.n_x = x.shape[0]
@@ -236,7 +253,14 @@ def make_desc(x, xi, phase, params, r, tol, leaf, precision, sweep_in=0,
     d.precision = int(precision)
     d.sweep_in = int(sweep_in)
     d.device = int(device)
-    return d, (x, xi, prm)
+    d.fixed_ranks = caps.ctypes.data_as(C.POINTER(C.c_int)) if caps is not None else None
+    d.amp_id = int(amp[0]) if amp is not None else 0
+    d.amp_params = aprm.ctypes.data_as(C.POINTER(C.c_double)) if aprm.size else None
+    d.n_amp_params = int(aprm.size)
+    if predictor is not None:
+        d.predictor = C.c_void_p(predictor[0].data_ptr())
+        d.predictor_hidden = int(predictor[1])
+    return d, (x, xi, prm, caps, aprm)
 
 
 class Plan:
@@ -244,11 +268,14 @@ class Plan:
     ibf_query / ibf_destroy; device vectors are torch tensors."""
 
     def __init__(self, x, xi, phase, params, r, tol, leaf=16, precision=PREC_FP64,
-                 sweep_in=0, omega_lo=None, omega_width=0.0, device=0):
+                 sweep_in=0, omega_lo=None, omega_width=0.0, device=0, fixed_ranks=None,
+                 amp=None, predictor=None):
         lib = load()
         self._lib = lib
         d, keep = make_desc(x, xi, phase, params, r, tol, leaf, precision, sweep_in,
-                            omega_lo, omega_width, device)
+                            omega_lo, omega_width, device, fixed_ranks, amp, predictor)
+        # the predictor's parameters are read by ibf_build: keep them alive
+        self._predictor = predictor
         h = C.c_void_p()
         _check(lib.ibf_plan(C.byref(d), C.byref(h)))
         self.handle = h
@@ -361,6 +388,7 @@ class Plan:
             "sweep_in": info.sweep_in,
             "rank_in_g": [info.rank_in_g[i] for i in range(n)],
             "rank_in_h": [info.rank_in_h[i] for i in range(n)],
+            "r": info.r, "tol": info.tol, "learned": info.learned,
         }
 
     def destroy(self):
@@ -447,6 +475,23 @@ def dense_apply(phase, params, x_dev, xi_dev, g, stream=None):
                                C.c_void_p(g.data_ptr()), g.shape[1], C.c_void_p(u.data_ptr()),
                                u.shape[1], nrhs, _stream_handle(stream)))
     return u
+
+
+def rel_error(u, ref, stream=None):
+    """ibf_rel_error on (nrhs, n) device tensors of one complex dtype:
+    (Frobenius relative error over all columns, largest per-column one)."""
+    if u.shape != ref.shape or u.dtype != ref.dtype:
+        raise ValueError("u and ref must have the same shape and dtype")
+    if u.dim() == 1:
+        u, ref = u.unsqueeze(0), ref.unsqueeze(0)
+    import torch
+    prec = PREC_FP64 if u.dtype == torch.complex128 else PREC_FP32
+    u, ref = u.contiguous(), ref.contiguous()
+    out = (C.c_double * 2)()
+    _check(load().ibf_rel_error(C.c_void_p(u.data_ptr()), u.shape[1], C.c_void_p(ref.data_ptr()),
+                                ref.shape[1], u.shape[1], u.shape[0], prec, out,
+                                _stream_handle(stream)))
+    return float(out[0]), float(out[1])
 
 
 def mlp_n_params(n_hidden):

@@ -8,6 +8,7 @@ import re
 import numpy as np
 import pytest
 
+from oracle import ibf_oracle as O
 from paper_1605_03616_amd import ibf
 from paper_1605_03616_amd import inputs as I
 
@@ -44,8 +45,10 @@ def test_plan_and_query_geometry():
     assert (q["L"], q["l0"], q["h"], q["n_levels"]) == (10, 4, 5, 3)
     assert q["n_pairs"] == 1024
     assert q["smax_x"] == 16 and q["smax_xi"] == 16
-    r = 8
-    assert q["nnz_prelim"] == 2 * 1024 * 16 * r + 2 * 1024 * 2 * r * r + 1024 * r * r
+    # the oracle's count, itself recounted from the explicit sparse factors
+    P = I.workload_fio1d_1k()
+    assert q["nnz_prelim"] == O.nnz_prelim(O.make_problem(P.phase, P.params, P.x, P.xi, P.r, P.leaf))
+    assert (q["r"], q["learned"], q["sweep_in"]) == (8, 0, 0)
     pl.destroy()
 
 
@@ -147,3 +150,69 @@ def test_mlp_feature_map_matches_oracle():
         ibf.mlp_n_params(12)
     with pytest.raises(ibf.IBFError):
         ibf.mlp_features(1024, 1, 8, 0.0)
+
+
+def test_sweep_in_auto_follows_leaf_populations():
+    """sweep_in = -1 turns the sweep-in on iff a leaf holds fewer than r points
+    (Sec. 4.3): off on the uniform grid (every leaf full), on for random x
+    with r = 12 (Poisson(16) leaves), off again there at r = 4."""
+    pl = _plan(sweep_in=-1)
+    assert pl.query()["sweep_in"] == 0
+    pl.destroy()
+    P = I.nudft_random(4096, 12, 1, 2)
+    cnt = np.bincount(np.floor(P.x * 256).astype(int), minlength=256)
+    for r in (12, 4):
+        pl = ibf.Plan(P.x, P.xi, P.phase, P.params, r, 1e-6, 16, I.PREC_FP32, sweep_in=-1)
+        assert pl.query()["sweep_in"] == int(cnt.min() < r), (r, cnt.min())
+        pl.destroy()
+    assert cnt.min() < 12 and cnt.min() >= 4
+
+
+def test_learned_order_plan_defers_r_to_the_build():
+    """r <= 0: the plan is valid, the order is chosen at build time."""
+    pl = _plan(r=0)
+    q = pl.query()
+    assert (q["r"], q["learned"], q["nnz_prelim"]) == (0, 1, 0)
+    pl.destroy()
+    with pytest.raises(ibf.IBFError) as e:
+        _plan(r=0, predictor=(_FakeTensor(), 7))
+    assert e.value.code == -1
+
+
+class _FakeTensor:
+    def __init__(self):
+        self.buf = np.zeros(4, dtype=np.float32)
+
+    def data_ptr(self):
+        return self.buf.ctypes.data
+
+
+@pytest.mark.parametrize("amp,code", [((1, (1.0, 0.5, 0.0, 1.0, 0.5)), -1),     # 5 of 6 params
+                                      ((1, (1.0, 0.5, 0.0, 1.0, 0.5, 0.0)), -1),  # q5 == 0
+                                      ((2, (1.0, 0.5, 0.0)), -1),                 # q2 == 0
+                                      ((7, (1.0,)), -2)])                          # unknown
+def test_amplitude_descriptor_validation(amp, code):
+    with pytest.raises(ibf.IBFError) as e:
+        _plan(amp=amp)
+    assert e.value.code == code
+
+
+def test_amplitude_and_caps_rejected_for_dim2():
+    n = 32
+    i1, i2 = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    x = np.stack([i1.ravel() / n, i2.ravel() / n], -1)
+    xi = np.stack([i1.ravel() - n // 2, i2.ravel() - n // 2], -1).astype(np.float64)
+    for kw in (dict(amp=(2, (1.0, 0.5, 64.0))), dict(fixed_ranks=[3] * 8)):
+        with pytest.raises(ibf.IBFError) as e:
+            ibf.Plan(x, xi, 2, (2.0, 1.0, 16.0), 5, 1e-4, 16, I.PREC_FP32, **kw)
+        assert e.value.code == -2
+
+
+def test_rel_error_validates_on_the_host():
+    lib = ibf.load()
+    out = (C.c_double * 2)()
+    assert lib.ibf_rel_error(None, 4, None, 4, 4, 1, 0, out, None) == -1
+    buf = np.zeros(8)
+    ptr = C.c_void_p(buf.ctypes.data)
+    assert lib.ibf_rel_error(ptr, 2, ptr, 4, 4, 1, 0, out, None) == -1     # ldu < n
+    assert lib.ibf_rel_error(ptr, 4, ptr, 4, 4, 0, 0, out, None) == -1     # nrhs < 1
