@@ -223,8 +223,12 @@ typedef struct {
   char name[IBF_PROFILE_MAX][24];   /* kernel class: "apply_v", "apply_stage", "apply_u", ... */
   float ms[IBF_PROFILE_MAX];        /* device duration of each launch (hipEvent pairs) */
   double flops[IBF_PROFILE_MAX];    /* algorithmic flops: 8 per complex MAC of unpadded blocks */
-  double bytes[IBF_PROFILE_MAX];    /* algorithmic HBM bytes: unpadded factors read once plus
-                                       the launch's own input and output vectors */
+  double bytes[IBF_PROFILE_MAX];    /* algorithmic HBM bytes: unpadded factors read once, plus
+                                       the samples g read (V launch) and u written (U launch);
+                                       summed over an apply: b_f nnz + 2 b_s N nrhs */
+  double vec_bytes[IBF_PROFILE_MAX];/* intermediate coefficient vectors the launch reads and
+                                       writes at their stored (level-maximum) ranks: traffic of
+                                       this design's launch boundaries, not of the method */
 } ibf_profile;
 
 /*
@@ -244,17 +248,20 @@ int ibf_apply_profile(ibf_plan_t plan, const void* g, int64_t ldg, void* u,
  * right-hand sides on the caller's vectors (same arguments and layout as
  * ibf_apply; u is overwritten with the product) and keeps the fastest in the
  * plan: later ibf_apply calls with this nrhs, and batches containing the plan,
- * use it.  Candidates: the default rule; butterfly stages on the vector
- * kernels; on MFMA (FP32 state) with 32- or 16-column RHS chunks; at most 2 or
- * 3 stages fused per launch; fused groups ending where the stage tile (the
- * even cover of the ranks) changes.  Every candidate computes the same product (to
+ * use it (batches run path 3 as path 2).  Candidates: the default rule;
+ * butterfly stages on the vector kernels; on MFMA (FP32 state) with 32- or
+ * 16-column RHS chunks; on MFMA at each pair's own ranks; at most 2 or 3
+ * stages fused per launch; fused groups ending where the stage tile (the even
+ * cover of the ranks) changes.  Every candidate computes the same product (to
  * FP32 rounding).  Synchronises the stream (not for use under graph capture).
  * *best receives the chosen schedule and its time, *dflt the default rule's
  * time (either may be NULL).
  * Errors: as ibf_apply; UNSUPPORTED for dim-2 plans.
  */
 typedef struct {
-  int path;        /* 0 default rule, 1 vector stage kernels, 2 MFMA stage kernels */
+  int path;        /* 0 default rule, 1 vector stage kernels, 2 MFMA stage kernels,
+                      3 MFMA stage kernels at each pair's own ranks (64-column chunks,
+                      up to 4 stages a launch; plans built with the sweep-in run path 2) */
   int chunk;       /* MFMA RHS chunk width (32 or 16; 0 = by nrhs) */
   int max_fused;   /* most stages fused per launch (0 = as LDS allows) */
   float ms;        /* measured time of one apply */
@@ -271,9 +278,9 @@ int ibf_tune(ibf_plan_t plan, const void* g, int64_t ldg, void* u, int64_t ldu,
  * schedule for profiling); t == NULL returns that nrhs to the default rule.
  * t->ms is ignored.  Same product as ibf_apply (Sec. 4).  Host only: no
  * device call, no allocation.
- * Errors: INVALID_ARG (NULL plan, nrhs < 1, path outside 0..2, chunk not 0,
- * 16 or 32, max_fused < 0, split outside 0..2); UNSUPPORTED for dim-2 plans and for path 2 on
- * FP64 plans (no FP64 MFMA stage kernel).
+ * Errors: INVALID_ARG (NULL plan, nrhs < 1, path outside 0..3, chunk not 0,
+ * 16 or 32, max_fused < 0, split outside 0..2); UNSUPPORTED for dim-2 plans and for paths 2
+ * and 3 on FP64 plans (no FP64 MFMA stage kernel).
  */
 int ibf_set_tuning(ibf_plan_t plan, int64_t nrhs, const ibf_tuning* t);
 

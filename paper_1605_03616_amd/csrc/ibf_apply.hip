@@ -699,6 +699,265 @@ __global__ __launch_bounds__(kBlock) void k_batch_fused_mfma(const FusedDesc* __
   else fused_mfma_body<VT, FT, KT, NBC, false>(ds[p], lb, 1, lb + 1);
 }
 
+// ---------------------------------------------------------------------------
+// Butterfly stages on MFMA at each pair's own ranks (FP32 state, RHS chunks
+// of 64 columns).  A level's blocks are stored at the level's largest rank
+// with exact zero padding (rows past an input pair's rank, columns past the
+// output pair's rank); at the 1-D FIO workloads the padding is about 40 % of
+// the stored entries.  Here each wave owns one output pair of a stage and
+// runs its product over exactly the two input pairs' ranks and the output
+// pair's rank: the padding is neither read nor multiplied.
+//
+// A block of 64 * 2^k threads owns one group of 2^k contiguous input pairs
+// (one RHS chunk) and carries it through k stages, one wave per slot, lane =
+// RHS column; the group's state [slot][row][64] lives in LDS.  The kernel is
+// persistent over groups: the next group's input rows and first factor rows
+// are loaded into registers during the current group's last stage, and each
+// stage's factor rows during the previous stage.
+//
+// Factor operands come straight from memory, two rows per coalesced 32-bit
+// load (lanes 0-31 row s, lanes 32-63 row s + 1, float e of the row in lane
+// e), and each v_mfma_f32_4x4x1f32 broadcasts the four floats of one (row,
+// row pair g) to all 16 blocks (cbsz 4, abid 8 rsel + g): one register feeds
+// the 2 x 8 (row, g) products of a window.  Per-pair ranks come from byte
+// arrays kept by the build (prk[j][pair] at level l_start - 1 + j).
+// ---------------------------------------------------------------------------
+struct TightArgs {
+  int L, l_start, nst, nrhs, nchunk;
+  int KS;                            // rows per LDS slot: largest stored rank of the levels
+  int kst[kMaxR + 1];                // stored rank at level l_start - 1 + j (HBM row stride)
+  int kld[kMaxR];                    // stored row length of stage j's blocks
+  const void* blk[kMaxR];
+  const uint8_t* prk[kMaxR + 1];     // per-pair ranks at level l_start - 1 + j
+};
+struct TightDesc {
+  const void* in;
+  void* out;
+  TightArgs A;
+};
+
+// float number fl of a stored block (FP32 as stored; BF16X2 widened hi + lo)
+__device__ __forceinline__ float block_float(const float2* blk, int64_t fl) {
+  return reinterpret_cast<const float*>(blk)[fl];
+}
+__device__ __forceinline__ float block_float(const bf16x2c* blk, int64_t fl) {
+  const unsigned short* h = reinterpret_cast<const unsigned short*>(blk);
+  const int64_t c = fl >> 1;
+  const int comp = (int)(fl & 1);
+  return bf2f(h[4 * c + comp]) + bf2f(h[4 * c + 2 + comp]);
+}
+
+// P[g], Q[g] += (row rsel of the window, row pair g) x (x_re, x_im) for g < ng:
+// abid 8 rsel + g selects the four floats (re t0, im t0, re t1, im t1) of
+// entries t = 2g, 2g + 1 held by lanes 32 rsel + 4g .. + 3.
+template <int RS, int KG, int G = 0>
+__device__ __forceinline__ void tight_row(float a, float2 x, v4f (&P)[KG], v4f (&Q)[KG], int ng) {
+  if constexpr (G < KG) {
+    if (G < ng) {
+      P[G] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, x.x, P[G], 4, 8 * RS + G, 0);
+      Q[G] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, x.y, Q[G], 4, 8 * RS + G, 0);
+      tight_row<RS, KG, G + 1>(a, x, P, Q, ng);
+    }
+  }
+}
+
+template <typename FT, int KT>
+__device__ __forceinline__ void tight_body(const TightDesc& D, int64_t lb, int64_t lstep,
+                                           int64_t lend) {
+  constexpr int NB = 64;
+  constexpr int KG = KT / 2;                                  // most row pairs of an output
+  constexpr int WC = KT / 2;                                  // most windows per child
+  extern __shared__ __align__(16) unsigned char smem[];
+  const float2* __restrict__ in = reinterpret_cast<const float2*>(D.in);
+  float2* __restrict__ out = reinterpret_cast<float2*>(D.out);
+  const TightArgs& A = D.A;
+  const int L = A.L, nrhs = A.nrhs, nchunk = A.nchunk, KS = A.KS;
+  const int K4 = A.nst;                                       // stages = log2(waves)
+  float2* S = reinterpret_cast<float2*>(smem);                // [2^k][KS][64]
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int half = lane >> 5, e = lane & 31;
+  const int sh_end = L - (A.l_start + K4 - 1);
+
+  struct Grp {
+    int64_t gid;
+    int nb0, nbw;
+  };
+  auto decode = [&](int64_t l) {
+    Grp g;
+    g.gid = l / nchunk;
+    g.nb0 = (int)(l - g.gid * nchunk) * NB;
+    g.nbw = min(NB, nrhs - g.nb0);
+    return g;
+  };
+  // the global pairs of stage j: inputs of output slot w and the output
+  struct StageWork {
+    int64_t pout;
+    int in0, kin0, kin1, kout;
+  };
+  auto stage_work = [&](const Grp& g, int j) {
+    StageWork s;
+    const int rem = K4 - j - 1;
+    const int l = A.l_start + j;
+    const int64_t gme = g.gid;
+    const int64_t ap = gme >> sh_end, bpp = gme & (((int64_t)1 << sh_end) - 1);
+    s.in0 = fused_in0(w, rem);
+    int64_t p0, p1;
+    if (j == 0) {
+      p0 = (g.gid << K4) | s.in0;
+      p1 = p0 + 1;
+    } else {
+      p0 = fused_pout(s.in0, j - 1, rem + 1, ap, bpp, L, l - 1);
+      p1 = fused_pout(s.in0 + 1, j - 1, rem + 1, ap, bpp, L, l - 1);
+    }
+    s.kin0 = A.prk[j][p0];
+    s.kin1 = A.prk[j][p1];
+    s.pout = fused_pout(w, j, rem, ap, bpp, L, l);
+    s.kout = A.prk[j + 1][s.pout];
+    return s;
+  };
+  // factor windows of stage j for output pair pout: child c window i holds
+  // rows 2i, 2i + 1 of child c's block rows (clamped to the live rows, so the
+  // loads are straight-line)
+  auto load_windows = [&](int j, const StageWork& s, float (&aw)[2 * WC]) {
+    const int kld = A.kld[j], Kin = A.kst[j];
+    const int rowf = 2 * kld;                                 // floats a row
+    const FT* fb = reinterpret_cast<const FT*>(A.blk[j]) + s.pout * (int64_t)(2 * Kin * kld);
+    const int last = 4 * Kin * kld - 1;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int kin = c ? s.kin1 : s.kin0;
+      const int rmax = max(kin - 1, 0);
+#pragma unroll
+      for (int i = 0; i < WC; ++i) {
+        const int row = c * Kin + min(2 * i + half, rmax);
+        aw[c * WC + i] = block_float(fb, min(row * rowf + e, last));
+      }
+    }
+  };
+  float2 xin[KT];
+  // input rows of slot w of group g (rows past the pair's rank re-read its last row)
+  auto fetch_inputs = [&](const Grp& g) {
+    const int64_t pin = (g.gid << K4) | w;
+    const int kin = A.prk[0][pin];
+    const bool ok = lane < g.nbw;
+    const float2* src = in + pin * A.kst[0] * (int64_t)nrhs + g.nb0 + (ok ? lane : 0);
+    const int rmax = max(kin - 1, 0);
+#pragma unroll
+    for (int i = 0; i < KT; ++i) {
+      const float2 v = src[(int64_t)min(i, rmax) * nrhs];
+      xin[i] = ok ? v : make_float2(0.f, 0.f);
+    }
+  };
+  auto deposit_inputs = [&](const Grp& g) {
+    const int kin = A.prk[0][(g.gid << K4) | w];
+    float2* dst = S + (size_t)w * KS * NB + lane;
+#pragma unroll
+    for (int i = 0; i < KT; ++i)
+      if (i < kin) dst[i * NB] = xin[i];
+  };
+
+  Grp cur = decode(lb);
+  fetch_inputs(cur);
+  float aw[2 * WC], an[2 * WC];
+  StageWork sw = stage_work(cur, 0);
+  load_windows(0, sw, aw);
+  deposit_inputs(cur);
+  __syncthreads();
+  while (true) {
+    const int64_t nlb = lb + lstep;
+    const bool more = nlb < lend;
+    const Grp nxt = more ? decode(nlb) : cur;
+#pragma unroll 1
+    for (int j = 0; j < K4; ++j) {
+      const bool last = j == K4 - 1;
+      // the next stage's (or the next group's first) factor rows: in flight
+      // during this stage's products
+      StageWork sn;
+      if (!last) {
+        sn = stage_work(cur, j + 1);
+        load_windows(j + 1, sn, an);
+      } else if (more) {
+        sn = stage_work(nxt, 0);
+        load_windows(0, sn, an);
+        fetch_inputs(nxt);
+      }
+      const int ng = (sw.kout + 1) >> 1;
+      v4f P[KG], Q[KG];
+#pragma unroll
+      for (int g = 0; g < KG; ++g) {
+        P[g] = v4f{0.f, 0.f, 0.f, 0.f};
+        Q[g] = v4f{0.f, 0.f, 0.f, 0.f};
+      }
+      // the rows of each child in windows of two; the next window's state
+      // rows are read from LDS while the current window's MFMAs issue
+      // (reads past the child's rank re-read its last row: in bounds, unused)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int kin = c ? sw.kin1 : sw.kin0;
+        const int kmax = max(kin - 1, 0);
+        const float2* X = S + (size_t)(sw.in0 + c) * KS * NB + lane;
+        float2 x0 = X[0], x1 = X[min(1, kmax) * NB];
+#pragma unroll
+        for (int i = 0; i < WC; ++i) {
+          if (2 * i >= kin) break;
+          const float2 y0 = X[min(2 * i + 2, kmax) * NB], y1 = X[min(2 * i + 3, kmax) * NB];
+          const float a = aw[c * WC + i];
+          tight_row<0, KG>(a, x0, P, Q, ng);
+          if (2 * i + 1 < kin) tight_row<1, KG>(a, x1, P, Q, ng);
+          x0 = y0;
+          x1 = y1;
+        }
+      }
+      __syncthreads();                                        // every wave read its inputs
+      if (!last) {
+        float2* dst = S + (size_t)w * KS * NB + lane;
+#pragma unroll
+        for (int g = 0; g < KG; ++g) {
+          if (2 * g < sw.kout) {
+            const v4f pp = P[g], qq = Q[g];
+            dst[(2 * g) * NB] = make_float2(pp[0] - qq[1], pp[1] + qq[0]);
+            if (2 * g + 1 < sw.kout) dst[(2 * g + 1) * NB] = make_float2(pp[2] - qq[3], pp[3] + qq[2]);
+          }
+        }
+      } else if (lane < cur.nbw) {
+        // last stage: all stored rows of the output pair to HBM (zero past its rank)
+        const int Kout = A.kst[K4];
+        float2* dst = out + sw.pout * Kout * (int64_t)nrhs + cur.nb0 + lane;
+#pragma unroll
+        for (int g = 0; g < KG; ++g) {
+          if (2 * g < Kout) {
+            const v4f pp = P[g], qq = Q[g];
+            const bool live = g < ng;
+            dst[(int64_t)(2 * g) * nrhs] = live ? make_float2(pp[0] - qq[1], pp[1] + qq[0])
+                                                : make_float2(0.f, 0.f);
+            if (2 * g + 1 < Kout)
+              dst[(int64_t)(2 * g + 1) * nrhs] = live ? make_float2(pp[2] - qq[3], pp[3] + qq[2])
+                                                      : make_float2(0.f, 0.f);
+          }
+        }
+      }
+      if (!last || more) {
+        sw = sn;
+#pragma unroll
+        for (int i = 0; i < 2 * WC; ++i) aw[i] = an[i];
+      }
+      if (!last) __syncthreads();                             // outputs in place
+    }
+    if (!more) break;
+    deposit_inputs(nxt);
+    __syncthreads();
+    lb = nlb;
+    cur = nxt;
+  }
+}
+
+// a block of 64 * 2^nst threads (at most 16 waves); persistent over `total` groups
+template <typename FT, int KT>
+__global__ __launch_bounds__(1024) void k_apply_tight(TightDesc D, int64_t total) {
+  tight_body<FT, KT>(D, blockIdx.x, (int64_t)gridDim.x, total);
+}
+
 // Middle block of the swept-in factorization: out[p][t][n] = sum_s Mdot[p][t][s] in[p][s][n]
 struct MidDesc {
   const void* in;
@@ -1064,7 +1323,7 @@ struct LaunchTimer {
     IBF_HIP_CHECK(hipEventRecord(a, s));
     return IBF_OK;
   }
-  int end(const char* name, double flops, double bytes) {
+  int end(const char* name, double flops, double bytes, double vec_bytes) {
     if (!prof || prof->n_launches >= IBF_PROFILE_MAX) return IBF_OK;
     hipEvent_t b;
     IBF_HIP_CHECK(hipEventCreate(&b));
@@ -1074,6 +1333,7 @@ struct LaunchTimer {
     std::snprintf(prof->name[i], sizeof(prof->name[i]), "%s", name);
     prof->flops[i] = flops;
     prof->bytes[i] = bytes;
+    prof->vec_bytes[i] = vec_bytes;
     return IBF_OK;
   }
   int finish() {
@@ -1102,18 +1362,19 @@ struct LaunchTimer {
 inline int even_kt(int k) { return std::min(16, std::max(2, (k + 1) & ~1)); }
 
 // One kernel launch of an apply, with everything it needs.
-enum LaunchKind { kLaunchV = 0, kLaunchFused = 1, kLaunchMid = 2, kLaunchU = 3 };
+enum LaunchKind { kLaunchV = 0, kLaunchFused = 1, kLaunchMid = 2, kLaunchU = 3, kLaunchTight = 4 };
 struct Launch {
   LaunchKind kind;
   int kt = 2;
   bool mfma = false;
   size_t lds = 0;
   int64_t nblocks = 0;
-  double flops = 0, bytes = 0;
+  double flops = 0, bytes = 0, vec_bytes = 0;
   VDesc v{};
   FusedDesc f{};
   MidDesc m{};
   UDesc u{};
+  TightDesc t{};
 };
 
 inline const char* launch_name(const Launch& x) {
@@ -1121,6 +1382,7 @@ inline const char* launch_name(const Launch& x) {
     case kLaunchV: return x.mfma ? "apply_v_mfma" : "apply_v";
     case kLaunchFused: return x.mfma ? "apply_fused_mfma" : "apply_fused";
     case kLaunchMid: return "apply_mid";
+    case kLaunchTight: return "apply_stage_tight";
     default: return x.mfma ? "apply_u_mfma" : "apply_u";
   }
 }
@@ -1144,7 +1406,7 @@ inline int lds_limit(int device, int* out) {
 // for nrhs, so it must run outside any graph capture.
 template <typename VT, typename FT>
 int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int nrhs,
-                  std::vector<Launch>& seq) {
+                  std::vector<Launch>& seq, bool batch = false) {
   seq.clear();
   const Geo& geo = p->geo;
   const int L = geo.L, l0 = geo.l0, h = geo.h;
@@ -1192,6 +1454,11 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
   bool mfma = sizeof(VT) == 8 && nrhs > 8;
   if (sizeof(VT) == 8 && tn.path == 1) mfma = false;
   if (sizeof(VT) == 8 && tn.path == 2) mfma = true;
+  // stages at per-pair ranks (64-column chunks): the default from 64 RHS,
+  // any FP32-state plan on path 3; needs the build's per-pair ranks (plans
+  // without the sweep-in); not in batches
+  const bool tight = sizeof(VT) == 8 && p->d_prank && !batch &&
+                     ((tn.path == 0 && nrhs >= 64) || tn.path == 3);
   const bool mfma_vu = sizeof(VT) == 8 && nrhs >= 32;
   const int NB = mfma ? (tn.chunk == 16 || tn.chunk == 32 ? tn.chunk : (nrhs > 16 ? 32 : 16))
                       : std::min(nrhs, 32);
@@ -1207,7 +1474,8 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
     x.kt = even_kt(K);
     const double nnz = (double)p->nnz_vbar;
     x.flops = 8.0 * nnz * nrhs;
-    x.bytes = nnz * fb + vb * nrhs * ((double)p->nxi + (double)p->npairs * K);
+    x.bytes = nnz * fb + vb * nrhs * (double)p->nxi;
+    x.vec_bytes = vb * nrhs * (double)p->npairs * K;
     if (mfma_vu && p->smax_xi <= kLeafMfma && ((K << l0) & 1) == 0) {
       // MFMA leaf product, 64-column chunks
       const int R = K << l0;
@@ -1244,7 +1512,8 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
     x.m = MidDesc{w[cur], w[cur ^ 1], p->d_mdot, p->k_mid_h, p->k_mid_g, nrhs, total};
     const double nnz = (double)p->npairs * p->k_mid_g * p->k_mid_h;
     x.flops = 8.0 * nnz * nrhs;
-    x.bytes = nnz * fb + (double)p->npairs * (p->k_mid_g + p->k_mid_h) * nrhs * vb;
+    x.bytes = nnz * fb;
+    x.vec_bytes = (double)p->npairs * (p->k_mid_g + p->k_mid_h) * nrhs * vb;
     seq.push_back(x);
     cur ^= 1;
   };
@@ -1263,6 +1532,51 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
   bool fold_mid = false;
   auto add_stages = [&](int lo, int hi, bool gside) {   // output levels lo..hi
     int l = lo;
+    if (tight) {
+      while (l <= hi) {
+        int kk = std::min(4, std::min(hi - l + 1, L - l + 1));
+        if (tn.max_fused > 0) kk = std::min(kk, tn.max_fused);
+        int km = 1;
+        for (int j = 0; j <= kk; ++j) km = std::max(km, rank_at(l - 1 + j, gside));
+        while (kk > 1 && ((size_t)km << kk) * 64 * sizeof(VT) > (size_t)lmax) --kk;
+        Launch x;
+        x.kind = kLaunchTight;
+        x.mfma = true;
+        TightArgs& T = x.t.A;
+        T.L = L;
+        T.l_start = l;
+        T.nst = kk;
+        T.nrhs = nrhs;
+        T.nchunk = (nrhs + 63) / 64;
+        km = 1;
+        double nnz = 0;
+        for (int j = 0; j <= kk; ++j) {
+          T.kst[j] = rank_at(l - 1 + j, gside);
+          T.prk[j] = p->d_prank + (size_t)(l - 1 + j - l0) * p->npairs;
+          km = std::max(km, T.kst[j]);
+        }
+        for (int j = 0; j < kk; ++j) {
+          const Stage& st = p->stages[l + j - l0 - 1];
+          T.blk[j] = st.blk;
+          T.kld[j] = st.k_ld;
+          nnz += (double)st.nnz;
+        }
+        T.KS = km;
+        x.kt = even_kt(km);
+        x.lds = ((size_t)km << kk) * 64 * sizeof(VT);
+        x.nblocks = (p->npairs >> kk) * T.nchunk;
+        x.t.in = w[cur];
+        x.t.out = w[cur ^ 1];
+        x.flops = 8.0 * nnz * nrhs;
+        x.bytes = nnz * fb;
+        x.vec_bytes = (double)p->npairs * (T.kst[0] + T.kst[kk]) * nrhs * vb;
+        seq.push_back(x);
+        cur ^= 1;
+        l += kk;
+      }
+      fold_mid = false;
+      return;
+    }
     while (l <= hi) {
       const bool mid_here = fold_mid && l == lo;
       int kk = 1;
@@ -1333,7 +1647,8 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
       x.f.in = w[cur];
       x.f.out = w[cur ^ 1];
       x.flops = 8.0 * nnz * nrhs;
-      x.bytes = nnz * fb + (double)p->npairs * (kin_launch + A.ranks[kk]) * nrhs * vb;
+      x.bytes = nnz * fb;
+      x.vec_bytes = (double)p->npairs * (kin_launch + A.ranks[kk]) * nrhs * vb;
       seq.push_back(x);
       cur ^= 1;
       l += kk;
@@ -1356,7 +1671,8 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
     const int K = p->k_ubar;
     const double nnz = (double)p->nnz_ubar;
     x.flops = 8.0 * nnz * nrhs;
-    x.bytes = nnz * fb + vb * nrhs * ((double)p->nx + (double)p->npairs * K);
+    x.bytes = nnz * fb + vb * nrhs * (double)p->nx;
+    x.vec_bytes = vb * nrhs * (double)p->npairs * K;
     if (mfma_vu && p->smax_x <= kLeafMfma && ((K << l0) % 16) == 0) {
       // MFMA leaf product, 64-column chunks
       const int R = K << l0;
@@ -1391,12 +1707,12 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
 
 // Blocks of a kernel that fit on the device at once (occupancy x CUs), for
 // persistent launches; cached per kernel and LDS size.
-inline int resident_blocks(const void* func, size_t lds, int64_t* out) {
+inline int resident_blocks(const void* func, size_t lds, int64_t* out, int block = kBlock) {
   static std::mutex mu;
   static std::map<std::pair<std::pair<const void*, size_t>, int>, int64_t> cache;
   int dev = 0;
   IBF_HIP_CHECK(hipGetDevice(&dev));
-  const auto key = std::make_pair(std::make_pair(func, lds), dev);
+  const auto key = std::make_pair(std::make_pair(func, lds), dev * 4096 + block);
   {
     std::lock_guard<std::mutex> g(mu);
     const auto it = cache.find(key);
@@ -1406,7 +1722,7 @@ inline int resident_blocks(const void* func, size_t lds, int64_t* out) {
     }
   }
   int per_cu = 0, ncu = 0;
-  IBF_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, func, kBlock, lds));
+  IBF_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, func, block, lds));
   IBF_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   const int64_t n = (int64_t)std::max(1, per_cu) * std::max(1, ncu);
   {
@@ -1470,6 +1786,22 @@ int launch_one(const Launch& x, hipStream_t s) {
     case kLaunchMid:
       hipLaunchKernelGGL((k_apply_mid<VT, FT>), grid, blk, 0, s, x.m);
       break;
+    case kLaunchTight:
+      if constexpr (sizeof(VT) == 8) {
+        const int tb = 64 << x.t.A.nst;
+#define IBF_LAUNCH_TIGHT(KTC)                                                                  \
+  {                                                                                            \
+    int64_t nres = 0;                                                                          \
+    const int rc = resident_blocks(reinterpret_cast<const void*>(&k_apply_tight<FT, KTC>),     \
+                                   x.lds, &nres, tb);                                          \
+    if (rc) return rc;                                                                         \
+    const dim3 pgrid((unsigned)std::min<int64_t>(x.nblocks, nres));                             \
+    hipLaunchKernelGGL((k_apply_tight<FT, KTC>), pgrid, dim3(tb), x.lds, s, x.t, x.nblocks);   \
+  }
+        IBF_DISPATCH_KT(x.kt, IBF_LAUNCH_TIGHT);
+#undef IBF_LAUNCH_TIGHT
+      }
+      break;
     default:
       if (x.mfma) {
         if constexpr (sizeof(VT) == 8)
@@ -1493,7 +1825,7 @@ int apply_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int6
   for (const Launch& x : seq) {
     if ((rc = T.begin())) return rc;
     if ((rc = launch_one<VT, FT>(x, s))) return rc;
-    if ((rc = T.end(launch_name(x), x.flops, x.bytes))) return rc;
+    if ((rc = T.end(launch_name(x), x.flops, x.bytes, x.vec_bytes))) return rc;
   }
   return T.finish();
 }
@@ -1613,7 +1945,7 @@ int apply_batch_t(ibf_batch_s* b, const void* const* g, const int64_t* ldg, void
   size_t nmax = 0;
   for (int i = 0; i < count; ++i) {
     if ((rc = make_schedule<VT, FT>(b->plans[i], g[i], ldg[i], u[i], ldu[i], (int)nrhs[i],
-                                    seqs[i])))
+                                    seqs[i], true)))
       return rc;
     for (const Launch& x : seqs[i])
       if (x.kind == kLaunchMid) {
@@ -1804,6 +2136,7 @@ int schedule_signature(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_
     sig.insert(sig.end(), {(int64_t)x.kind, (int64_t)x.kt, (int64_t)x.mfma, x.nblocks,
                            (int64_t)x.lds});
     if (x.kind == kLaunchFused) sig.insert(sig.end(), {x.f.A.l_start, x.f.A.nst, x.f.A.NB});
+    if (x.kind == kLaunchTight) sig.insert(sig.end(), {x.t.A.l_start, x.t.A.nst, 64});
   }
   return IBF_OK;
 }
@@ -1838,6 +2171,11 @@ int tune_plan(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, in
       cand.push_back(Tuning{2, c, 0, 2});
       cand.push_back(Tuning{2, c, 3, 0});
       cand.push_back(Tuning{2, c, 2, 0});
+    }
+    if (p->d_prank && nrhs > 8) {                             // stages at per-pair ranks
+      cand.push_back(Tuning{3, 0, 0, 0});
+      cand.push_back(Tuning{3, 0, 3, 0});
+      cand.push_back(Tuning{3, 0, 2, 0});
     }
   }
   // the plan leaves trial mode and the events are released on every exit
@@ -1966,14 +2304,14 @@ int ibf_set_tuning(ibf_plan_t p, int64_t nrhs, const ibf_tuning* t) {
     p->tuned.erase(nrhs);
     return IBF_OK;
   }
-  if (t->path < 0 || t->path > 2 || (t->chunk != 0 && t->chunk != 16 && t->chunk != 32) ||
+  if (t->path < 0 || t->path > 3 || (t->chunk != 0 && t->chunk != 16 && t->chunk != 32) ||
       t->max_fused < 0 || t->split < 0 || t->split > 2) {
     ibf::set_error(
-        "ibf_set_tuning: path outside 0..2, chunk not 0/16/32, max_fused < 0 or split outside "
+        "ibf_set_tuning: path outside 0..3, chunk not 0/16/32, max_fused < 0 or split outside "
         "0..2");
     return IBF_ERR_INVALID_ARG;
   }
-  if (t->path == 2 && p->precision == IBF_FP64) {
+  if ((t->path == 2 || t->path == 3) && p->precision == IBF_FP64) {
     ibf::set_error("ibf_set_tuning: no MFMA stage kernel for FP64 plans");
     return IBF_ERR_UNSUPPORTED;
   }

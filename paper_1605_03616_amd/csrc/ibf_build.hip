@@ -250,6 +250,12 @@ __global__ void k_count_outer(const int32_t* leaf_of, int64_t npts, int l0, int 
   if (threadIdx.x == 0 && s_sum) atomicAdd(nnz, s_sum);
 }
 
+// Per-pair ranks of one level kept for the apply (bytes; ranks are <= 16).
+__global__ void k_save_rank(const int* rk, uint8_t* dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (uint8_t)rk[i];
+}
+
 __global__ void k_eval(PhaseDesc ph, const double* x, const double* xi, int64_t n, double2* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = kval(ph, x[i], xi[i]);
@@ -527,7 +533,17 @@ int build_plan(ibf_plan_t p, hipStream_t s) {
 
   SweepArgs A{p->phase, geo, cheb.ptr, p->tol, np, rank_max.ptr, nnz.ptr + nst,
               p->caps.empty() ? nullptr : p->caps.data()};
+  // per-pair ranks of every level, kept for the apply when no sweep-in follows
+  uint8_t* prank = nullptr;
+  if (!p->sweep_in) IBF_HIP_CHECK(ibf::dev_malloc(&prank, (size_t)nlev * np));
+  p->d_prank = prank;
+  auto save_rank = [&](const int* rk, int level) {
+    if (prank)
+      hipLaunchKernelGGL(k_save_rank, dim3((unsigned)((np + kBlock - 1) / kBlock)), dim3(kBlock),
+                         0, s, rk, prank + (size_t)(level - l0) * np, np);
+  };
   kern::middle(R, A, Cb[0].ptr, Rb[0].ptr, rk_mid.ptr, s);
+  save_rank(rk_mid.ptr, h);
 
   // sweep toward U
   const double2* Ccur = Cb[0].ptr;
@@ -540,6 +556,7 @@ int build_plan(ibf_plan_t p, hipStream_t s) {
     int* rkout = rkG[gi].ptr;
     kern::sweep_g(R, A, l, Ccur, Cout, stages[l - l0 - 1].ptr, rkcur, rkout,
                    nnz.ptr + (l - l0 - 1), s);
+    save_rank(rkout, l);
     Ccur = Cout;
     Cout_last = Cout;
     rkcur = rkout;
@@ -557,6 +574,7 @@ int build_plan(ibf_plan_t p, hipStream_t s) {
     int* rkout = rkH[hi].ptr;
     kern::sweep_h(R, A, l, Rcur, Rout, stages[l - l0 - 1].ptr, rkcur, rkout,
                    nnz.ptr + (l - l0 - 1), s);
+    save_rank(rkout, l - 1);
     Rcur = Rout;
     Rout_last = Rout;
     rkcur = rkout;

@@ -108,6 +108,9 @@ struct ibf_plan_s {
   void* d_ubar = nullptr;           // [x point][2^l0][K_{L-l0}]
   size_t ubar_bytes = 0;
   void* d_mdot = nullptr;           // sweep-in middle block [pair][KG][KH] or null
+  uint8_t* d_prank = nullptr;       // sweep-out rank of every pair: [level l0..L-l0][pair]
+                                    // (plans without the sweep-in; read by the stage kernels
+                                    // that skip each block's zero padding)
   size_t mdot_bytes = 0;
   int k_vbar = 0, k_ubar = 0, k_mid_g = 0, k_mid_h = 0;
   int64_t nnz_vbar = 0, nnz_ubar = 0;   // unpadded outer-factor entries

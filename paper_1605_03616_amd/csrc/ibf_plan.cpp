@@ -122,7 +122,8 @@ void free_factors(ibf_plan_t p) {
   for (auto& st : p->stages)
     if (st.blk) (void)ibf::dev_free(st.blk);
   p->stages.clear();
-  void** bufs[] = {&p->d_vbar, &p->d_ubar, &p->d_mdot, &p->d_work[0], &p->d_work[1]};
+  void** bufs[] = {&p->d_vbar, &p->d_ubar, &p->d_mdot, &p->d_work[0], &p->d_work[1],
+                   reinterpret_cast<void**>(&p->d_prank)};
   for (void** b : bufs) {
     if (*b) (void)ibf::dev_free(*b);
     *b = nullptr;

@@ -27,6 +27,7 @@ EXPORTED = ["ibf_plan", "ibf_build", "ibf_apply", "ibf_apply_profile", "ibf_quer
             "ibf_mlp_adam", "ibf_mlp_select", "ibf_tune", "ibf_set_tuning", "ibf_set_allocator",
             "ibf_measure_peak", "ibf_apply_adjoint", "ibf_rel_error"]
 MLP_FEATURES = 5
+PATHS = ["default", "vector", "mfma", "tight"]      # ibf_tuning.path
 BATCH_GRAPH = 1
 PROFILE_MAX = 64
 
@@ -90,6 +91,7 @@ class IBFProfile(C.Structure):
         ("ms", C.c_float * PROFILE_MAX),
         ("flops", C.c_double * PROFILE_MAX),
         ("bytes", C.c_double * PROFILE_MAX),
+        ("vec_bytes", C.c_double * PROFILE_MAX),
     ]
 
 
@@ -349,29 +351,30 @@ class Plan:
         _check(self._lib.ibf_tune(self.handle, C.c_void_p(g.data_ptr()), g.shape[1],
                                   C.c_void_p(u.data_ptr()), u.shape[1], g.shape[0],
                                   _stream_handle(stream), C.byref(best), C.byref(dflt)))
-        return {"path": ["default", "vector", "mfma"][best.path], "chunk": best.chunk,
+        return {"path": PATHS[best.path], "chunk": best.chunk,
                 "max_fused": best.max_fused, "split": best.split, "ms": float(best.ms),
                 "default_ms": float(dflt.ms)}
 
     def set_tuning(self, nrhs, path=None, chunk=0, max_fused=0, split=0):
         """ibf_set_tuning: installs a schedule for `nrhs` right-hand sides
-        (path "default", "vector" or "mfma"); path None returns to the
-        default rule."""
+        (path "default", "vector", "mfma" or "tight" -- MFMA stages at each
+        pair's own ranks); path None returns to the default rule."""
         if path is None:
             _check(self._lib.ibf_set_tuning(self.handle, nrhs, None))
             return
-        t = IBFTuning(["default", "vector", "mfma"].index(path), chunk, max_fused, 0.0, split)
+        t = IBFTuning(PATHS.index(path), chunk, max_fused, 0.0, split)
         _check(self._lib.ibf_set_tuning(self.handle, nrhs, C.byref(t)))
 
     def apply_profile(self, g, u, stream=None):
         """ibf_apply_profile on (nrhs, n) tensors; returns a list of launches
-        (name, ms, flops, bytes)."""
+        (name, ms, flops, bytes, vec_bytes)."""
         prof = IBFProfile()
         _check(self._lib.ibf_apply_profile(self.handle, C.c_void_p(g.data_ptr()), g.shape[1],
                                            C.c_void_p(u.data_ptr()), u.shape[1], g.shape[0],
                                            _stream_handle(stream), C.byref(prof)))
         return [(bytes(prof.name[i]).split(b"\0")[0].decode(), float(prof.ms[i]),
-                 float(prof.flops[i]), float(prof.bytes[i])) for i in range(prof.n_launches)]
+                 float(prof.flops[i]), float(prof.bytes[i]), float(prof.vec_bytes[i]))
+                for i in range(prof.n_launches)]
 
     def query(self) -> dict:
         info = IBFInfo()

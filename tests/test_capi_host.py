@@ -114,17 +114,19 @@ def test_set_tuning_validates_host_only():
     T = ibf.IBFTuning
     assert lib.ibf_set_tuning(None, 8, C.byref(T(0, 0, 0, 0.0))) == -1
     assert lib.ibf_set_tuning(pl.handle, 0, C.byref(T(0, 0, 0, 0.0))) == -1
-    for bad in [T(3, 0, 0, 0.0), T(-1, 0, 0, 0.0), T(2, 8, 0, 0.0), T(1, 0, -1, 0.0),
+    for bad in [T(4, 0, 0, 0.0), T(-1, 0, 0, 0.0), T(2, 8, 0, 0.0), T(1, 0, -1, 0.0),
                 T(0, 0, 0, 0.0, 3)]:
         assert lib.ibf_set_tuning(pl.handle, 8, C.byref(bad)) == -1
     assert lib.ibf_set_tuning(pl.handle, 8, C.byref(T(2, 32, 3, 0.0))) == 0
     assert lib.ibf_set_tuning(pl.handle, 8, None) == 0          # back to the default rule
     pl.set_tuning(12, "vector", 0, 2)
     pl.set_tuning(12, "mfma", 16, 0, 2)
+    pl.set_tuning(64, "tight", 0, 3)
     pl.set_tuning(12)
     pl.destroy()
     p64 = _plan(precision=I.PREC_FP64)
     assert lib.ibf_set_tuning(p64.handle, 8, C.byref(T(2, 16, 0, 0.0))) == -2
+    assert lib.ibf_set_tuning(p64.handle, 8, C.byref(T(3, 0, 0, 0.0))) == -2
     assert lib.ibf_set_tuning(p64.handle, 8, C.byref(T(1, 0, 2, 0.0))) == 0
     p64.destroy()
 

@@ -50,7 +50,7 @@ def test_tune_then_apply_parity(torch_dev, nrhs):
     gt = torch.from_numpy(np.ascontiguousarray(g.T)).to(torch.complex64).cuda()
     res = pl.tune(gt)
     torch.cuda.synchronize()
-    assert res["path"] in ("default", "vector", "mfma")
+    assert res["path"] in ("default", "vector", "mfma", "tight")
     assert res["ms"] > 0 and res["default_ms"] > 0
     assert res["ms"] <= res["default_ms"] * (1 + 1e-6)       # the default is a candidate
     u = pl.apply(gt).cpu().numpy().T.astype(np.complex128)   # with the tuned schedule
@@ -60,7 +60,8 @@ def test_tune_then_apply_parity(torch_dev, nrhs):
 
 @pytest.mark.parametrize("sched", [("vector", 0, 2), ("mfma", 16, 3), ("mfma", 32, 2),
                                    ("mfma", 16, 0), ("mfma", 16, 0, 1), ("mfma", 32, 0, 2),
-                                   ("default", 0, 0, 2)])
+                                   ("default", 0, 0, 2), ("tight", 0, 0), ("tight", 0, 3),
+                                   ("tight", 0, 1)])
 def test_fixed_schedule_parity(torch_dev, sched):
     # ibf_set_tuning installs a schedule without timing: same product
     torch = torch_dev
