@@ -736,28 +736,31 @@ struct TightDesc {
   TightArgs A;
 };
 
-// float number fl of a stored block (FP32 as stored; BF16X2 widened hi + lo)
-__device__ __forceinline__ float block_float(const float2* blk, int64_t fl) {
-  return reinterpret_cast<const float*>(blk)[fl];
+// Float fu + fl of a stored block, fu uniform across the wave (a scalar
+// base) and fl the lane's offset (FP32 as stored; BF16X2 widened hi + lo;
+// fu even, so the complex entry of fl alone picks the component)
+// (the lane offset enters as a 32-bit byte offset, so the load takes the
+// scalar-base + 32-bit-offset form: one VGPR per load in flight)
+__device__ __forceinline__ float block_float(const float2* blk, int64_t fu, unsigned fl) {
+  const char* b = reinterpret_cast<const char*>(reinterpret_cast<const float*>(blk) + fu);
+  return *reinterpret_cast<const float*>(b + (fl * 4u));
 }
-__device__ __forceinline__ float block_float(const bf16x2c* blk, int64_t fl) {
-  const unsigned short* h = reinterpret_cast<const unsigned short*>(blk);
-  const int64_t c = fl >> 1;
-  const int comp = (int)(fl & 1);
-  return bf2f(h[4 * c + comp]) + bf2f(h[4 * c + 2 + comp]);
+__device__ __forceinline__ float block_float(const bf16x2c* blk, int64_t fu, unsigned fl) {
+  const char* b = reinterpret_cast<const char*>(reinterpret_cast<const unsigned short*>(blk) + 2 * fu);
+  const unsigned o = (4u * (fl >> 1) + (fl & 1u)) * 2u;
+  return bf2f(*reinterpret_cast<const unsigned short*>(b + o)) +
+         bf2f(*reinterpret_cast<const unsigned short*>(b + o + 4u));
 }
 
-// P[g], Q[g] += (row rsel of the window, row pair g) x (x_re, x_im) for g < ng:
+// P[g], Q[g] += (row rsel of the window, row pair g) x (x_re, x_im) for g < NG:
 // abid 8 rsel + g selects the four floats (re t0, im t0, re t1, im t1) of
 // entries t = 2g, 2g + 1 held by lanes 32 rsel + 4g .. + 3.
-template <int RS, int KG, int G = 0>
-__device__ __forceinline__ void tight_row(float a, float2 x, v4f (&P)[KG], v4f (&Q)[KG], int ng) {
-  if constexpr (G < KG) {
-    if (G < ng) {
-      P[G] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, x.x, P[G], 4, 8 * RS + G, 0);
-      Q[G] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, x.y, Q[G], 4, 8 * RS + G, 0);
-      tight_row<RS, KG, G + 1>(a, x, P, Q, ng);
-    }
+template <int RS, int NG, int KG, int G = 0>
+__device__ __forceinline__ void tight_row(float a, float2 x, v4f (&P)[KG], v4f (&Q)[KG]) {
+  if constexpr (G < NG) {
+    P[G] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, x.x, P[G], 4, 8 * RS + G, 0);
+    Q[G] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, x.y, Q[G], 4, 8 * RS + G, 0);
+    tight_row<RS, NG, KG, G + 1>(a, x, P, Q);
   }
 }
 
@@ -817,21 +820,21 @@ __device__ __forceinline__ void tight_body(const TightDesc& D, int64_t lb, int64
     return s;
   };
   // factor windows of stage j for output pair pout: child c window i holds
-  // rows 2i, 2i + 1 of child c's block rows (clamped to the live rows, so the
-  // loads are straight-line)
+  // rows 2i, 2i + 1 of child c's block rows (rows clamped to the child's
+  // rank, so every window loads and the code is straight-line; the lanes
+  // past a row's 2 kld floats read the next row or the slack past the
+  // stage's blocks, and are never used)
   auto load_windows = [&](int j, const StageWork& s, float (&aw)[2 * WC]) {
     const int kld = A.kld[j], Kin = A.kst[j];
     const int rowf = 2 * kld;                                 // floats a row
     const FT* fb = reinterpret_cast<const FT*>(A.blk[j]) + s.pout * (int64_t)(2 * Kin * kld);
-    const int last = 4 * Kin * kld - 1;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-      const int kin = c ? s.kin1 : s.kin0;
-      const int rmax = max(kin - 1, 0);
+      const int rmax = max((c ? s.kin1 : s.kin0) - 1, 0);
 #pragma unroll
       for (int i = 0; i < WC; ++i) {
         const int row = c * Kin + min(2 * i + half, rmax);
-        aw[c * WC + i] = block_float(fb, min(row * rowf + e, last));
+        aw[c * WC + i] = block_float(fb, 0, (unsigned)(row * rowf + e));
       }
     }
   };
@@ -891,23 +894,42 @@ __device__ __forceinline__ void tight_body(const TightDesc& D, int64_t lb, int64
       }
       // the rows of each child in windows of two; the next window's state
       // rows are read from LDS while the current window's MFMAs issue
-      // (reads past the child's rank re-read its last row: in bounds, unused)
+      // (reads past the child's rank re-read its last row: in bounds, unused).
+      // One instantiation per output row-pair count, chosen once per stage:
+      // no per-MFMA branches (uniform branches cost scalar-unit slots, which
+      // the four SIMDs of a CU share)
+      auto product = [&](auto ng_c) {
+        constexpr int NG = decltype(ng_c)::value;
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const int kin = c ? sw.kin1 : sw.kin0;
-        const int kmax = max(kin - 1, 0);
-        const float2* X = S + (size_t)(sw.in0 + c) * KS * NB + lane;
-        float2 x0 = X[0], x1 = X[min(1, kmax) * NB];
+        for (int c = 0; c < 2; ++c) {
+          const int kin = c ? sw.kin1 : sw.kin0;
+          // rows at constant offsets (immediate LDS offsets); the rows read
+          // past the child's rank (at most 3, inside the slot region and its
+          // slack) are never used
+          const float2* X = S + (size_t)(sw.in0 + c) * KS * NB + lane;
+          float2 x0 = X[0], x1 = X[NB];
 #pragma unroll
-        for (int i = 0; i < WC; ++i) {
-          if (2 * i >= kin) break;
-          const float2 y0 = X[min(2 * i + 2, kmax) * NB], y1 = X[min(2 * i + 3, kmax) * NB];
-          const float a = aw[c * WC + i];
-          tight_row<0, KG>(a, x0, P, Q, ng);
-          if (2 * i + 1 < kin) tight_row<1, KG>(a, x1, P, Q, ng);
-          x0 = y0;
-          x1 = y1;
+          for (int i = 0; i < WC; ++i) {
+            if (2 * i >= kin) break;
+            const float2 y0 = X[(2 * i + 2) * NB], y1 = X[(2 * i + 3) * NB];
+            const float a = aw[c * WC + i];
+            tight_row<0, NG, KG>(a, x0, P, Q);
+            if (2 * i + 1 < kin) tight_row<1, NG, KG>(a, x1, P, Q);
+            x0 = y0;
+            x1 = y1;
+          }
         }
+      };
+      switch (ng) {
+        case 1: product(std::integral_constant<int, 1>{}); break;
+        case 2: if constexpr (KG >= 2) product(std::integral_constant<int, 2>{}); break;
+        case 3: if constexpr (KG >= 3) product(std::integral_constant<int, 3>{}); break;
+        case 4: if constexpr (KG >= 4) product(std::integral_constant<int, 4>{}); break;
+        case 5: if constexpr (KG >= 5) product(std::integral_constant<int, 5>{}); break;
+        case 6: if constexpr (KG >= 6) product(std::integral_constant<int, 6>{}); break;
+        case 7: if constexpr (KG >= 7) product(std::integral_constant<int, 7>{}); break;
+        case 8: if constexpr (KG >= 8) product(std::integral_constant<int, 8>{}); break;
+        default: break;                                       // rank 0: a zero output
       }
       __syncthreads();                                        // every wave read its inputs
       if (!last) {
@@ -952,9 +974,13 @@ __device__ __forceinline__ void tight_body(const TightDesc& D, int64_t lb, int64
   }
 }
 
-// a block of 64 * 2^nst threads (at most 16 waves); persistent over `total` groups
+// a block of 64 * 2^nst threads, at most 16 waves (8 for KT > 12, whose
+// registers would not fit 16 waves); persistent over `total` groups
+template <int KT>
+constexpr int tight_max_waves() { return KT > 12 ? 8 : 16; }
 template <typename FT, int KT>
-__global__ __launch_bounds__(1024) void k_apply_tight(TightDesc D, int64_t total) {
+__global__ __launch_bounds__(64 * tight_max_waves<KT>()) void k_apply_tight(TightDesc D,
+                                                                            int64_t total) {
   tight_body<FT, KT>(D, blockIdx.x, (int64_t)gridDim.x, total);
 }
 
@@ -1536,9 +1562,16 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
       while (l <= hi) {
         int kk = std::min(4, std::min(hi - l + 1, L - l + 1));
         if (tn.max_fused > 0) kk = std::min(kk, tn.max_fused);
-        int km = 1;
-        for (int j = 0; j <= kk; ++j) km = std::max(km, rank_at(l - 1 + j, gside));
-        while (kk > 1 && ((size_t)km << kk) * 64 * sizeof(VT) > (size_t)lmax) --kk;
+        auto kmax_of = [&](int n) {
+          int m = 1;
+          for (int j = 0; j <= n; ++j) m = std::max(m, rank_at(l - 1 + j, gside));
+          return m;
+        };
+        // tiles above 12 rows run 8 waves a block (3 stages), and the state must fit LDS
+        while (kk > 1 && ((even_kt(kmax_of(kk)) > 12 && kk > 3) ||
+                          (((size_t)kmax_of(kk) << kk) + 4) * 64 * sizeof(VT) > (size_t)lmax))
+          --kk;
+        int km = kmax_of(kk);
         Launch x;
         x.kind = kLaunchTight;
         x.mfma = true;
@@ -1563,7 +1596,8 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
         }
         T.KS = km;
         x.kt = even_kt(km);
-        x.lds = ((size_t)km << kk) * 64 * sizeof(VT);
+        // + 4 rows: the product reads up to 3 rows past a slot's live rows
+        x.lds = (((size_t)km << kk) + 4) * 64 * sizeof(VT);
         x.nblocks = (p->npairs >> kk) * T.nchunk;
         x.t.in = w[cur];
         x.t.out = w[cur ^ 1];

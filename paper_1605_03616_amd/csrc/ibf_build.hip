@@ -278,7 +278,7 @@ int pack_all(ibf_plan_t p, const std::vector<DevBuf<double2>>& stages, const dou
     st.k_ld = (st.k_out + 1) & ~1;
     const int64_t count = p->npairs * st.k_ld * 2 * st.k_in;
     st.bytes = (size_t)count * fb;
-    IBF_HIP_CHECK(ibf::dev_malloc(&st.blk, std::max<size_t>(st.bytes, 1)));
+    IBF_HIP_CHECK(ibf::dev_malloc(&st.blk, st.bytes + kStageSlack));
     p->stages.push_back(st);
     const unsigned blocks = (unsigned)std::min<int64_t>((count + kBlock - 1) / kBlock, 1 << 20);
     hipLaunchKernelGGL((k_pack_stage<FT>), dim3(std::max(blocks, 1u)), dim3(kBlock), 0, s,
