@@ -874,6 +874,10 @@ __device__ __forceinline__ void tight_body(const TightDesc& D, int64_t lb, int64
 #pragma unroll 1
     for (int j = 0; j < K4; ++j) {
       const bool last = j == K4 - 1;
+      // this stage's factor rows (loaded during the previous stage) have
+      // arrived; waiting here, before the next loads issue, spares the
+      // products below waits on the loads still in flight
+      __builtin_amdgcn_s_waitcnt(0x0F70);                     // vmcnt(0)
       // the next stage's (or the next group's first) factor rows: in flight
       // during this stage's products
       StageWork sn;
@@ -892,31 +896,36 @@ __device__ __forceinline__ void tight_body(const TightDesc& D, int64_t lb, int64
         P[g] = v4f{0.f, 0.f, 0.f, 0.f};
         Q[g] = v4f{0.f, 0.f, 0.f, 0.f};
       }
-      // the rows of each child in windows of two; the next window's state
-      // rows are read from LDS while the current window's MFMAs issue
-      // (reads past the child's rank re-read its last row: in bounds, unused).
-      // One instantiation per output row-pair count, chosen once per stage:
-      // no per-MFMA branches (uniform branches cost scalar-unit slots, which
-      // the four SIMDs of a CU share)
+      // the rows of each child in windows of two, the last window first (a
+      // chain of guarded blocks with one exit: an early exit from the
+      // unrolled loop would have the compiler duplicate the rest of the stage
+      // into every exit); the next window's state rows are read from LDS
+      // while the current window's MFMAs issue.  One instantiation per output
+      // row-pair count, chosen once per stage: no per-MFMA branches (uniform
+      // branches take scalar-unit issue slots, which the SIMDs of a CU share)
       auto product = [&](auto ng_c) {
         constexpr int NG = decltype(ng_c)::value;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
           const int kin = c ? sw.kin1 : sw.kin0;
-          // rows at constant offsets (immediate LDS offsets); the rows read
-          // past the child's rank (at most 3, inside the slot region and its
-          // slack) are never used
+          const int nwin = (kin + 1) >> 1;
           const float2* X = S + (size_t)(sw.in0 + c) * KS * NB + lane;
-          float2 x0 = X[0], x1 = X[NB];
+          const int rl = max(2 * nwin - 2, 0);
+          float2 x0 = X[rl * NB], x1 = X[(rl + 1) * NB];
 #pragma unroll
-          for (int i = 0; i < WC; ++i) {
-            if (2 * i >= kin) break;
-            const float2 y0 = X[(2 * i + 2) * NB], y1 = X[(2 * i + 3) * NB];
-            const float a = aw[c * WC + i];
-            tight_row<0, NG, KG>(a, x0, P, Q);
-            if (2 * i + 1 < kin) tight_row<1, NG, KG>(a, x1, P, Q);
-            x0 = y0;
-            x1 = y1;
+          for (int i = WC - 1; i >= 0; --i) {
+            if (i < nwin) {
+              float2 y0 = x0, y1 = x1;
+              if (i > 0) {
+                y0 = X[(2 * i - 2) * NB];
+                y1 = X[(2 * i - 1) * NB];
+              }
+              const float a = aw[c * WC + i];
+              tight_row<0, NG, KG>(a, x0, P, Q);
+              if (2 * i + 1 < kin) tight_row<1, NG, KG>(a, x1, P, Q);
+              x0 = y0;
+              x1 = y1;
+            }
           }
         }
       };
