@@ -216,6 +216,26 @@ int ibf_apply(ibf_plan_t plan, const void* g, int64_t ldg, void* u,
 int ibf_apply_adjoint(ibf_plan_t plan, const void* h, int64_t ldh, void* v,
                       int64_t ldv, int64_t nrhs, void* hip_stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as ibf_apply, on the same kernels and schedule, with the two
+ * intermediate coefficient buffers taken from a static device array of
+ * 128 MiB (IBF_NOALLOC_SCRATCH_BYTES) that each GPU the library runs on holds
+ * until the process ends, instead of the plan's workspace.  Calls no
+ * hipMalloc / hipFree and no allocating library routine; the first call on a
+ * device looks up the array's device address (hipGetSymbolAddress).  The
+ * array is shared by every call on that GPU and keeps the last call's
+ * contents: calls that overlap on one GPU (any streams, any plans) race, and
+ * must be serialised by the caller.  Rejects applies whose buffers (2 x
+ * 2^L x the largest stored rank x nrhs complex values, 256-byte aligned)
+ * exceed the array.  Errors: NOT_BUILT; INVALID_ARG (NULL, nrhs < 1, bad ld,
+ * buffers beyond the array); UNSUPPORTED (dim-2 plans); DEVICE.
+ */
+#define IBF_NOALLOC_SCRATCH_BYTES (128u << 20)
+int ibf_apply_noalloc(ibf_plan_t plan, const void* g, int64_t ldg, void* u,
+                      int64_t ldu, int64_t nrhs, void* hip_stream);
+
 /* Per-launch timings of one profiled application (see ibf_apply_profile). */
 #define IBF_PROFILE_MAX 64
 typedef struct {

@@ -25,6 +25,7 @@
 #include <cstdio>
 #include <map>
 #include <mutex>
+#include <string>
 #include <type_traits>
 #include <vector>
 
@@ -1441,7 +1442,7 @@ inline int lds_limit(int device, int* out) {
 // for nrhs, so it must run outside any graph capture.
 template <typename VT, typename FT>
 int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int nrhs,
-                  std::vector<Launch>& seq, bool batch = false) {
+                  std::vector<Launch>& seq, bool batch = false, void* const* ws = nullptr) {
   seq.clear();
   const Geo& geo = p->geo;
   const int L = geo.L, l0 = geo.l0, h = geo.h;
@@ -1458,7 +1459,7 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
   for (int k : p->rank_in_g) kmax = std::max(kmax, k);
   for (int k : p->rank_in_h) kmax = std::max(kmax, k);
   const size_t need = (size_t)p->npairs * kmax * nrhs * sizeof(VT);
-  if (need > p->work_bytes) {
+  if (!ws && need > p->work_bytes) {
     for (int i = 0; i < 2; ++i) {
       if (p->d_work[i]) (void)ibf::dev_free(p->d_work[i]);
       p->d_work[i] = nullptr;
@@ -1468,7 +1469,9 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
     IBF_HIP_CHECK(ibf::dev_malloc(&p->d_work[1], need));
     p->work_bytes = need;
   }
-  void* w[2] = {p->d_work[0], p->d_work[1]};
+  // the ping-pong coefficient buffers: the plan's, or the caller's (the
+  // allocation-free entry point passes two buffers of at least `need` bytes)
+  void* w[2] = {ws ? ws[0] : p->d_work[0], ws ? ws[1] : p->d_work[1]};
   const double fb = (double)sizeof(FT), vb = (double)sizeof(VT);
   int lmax = 0, rc;
   if ((rc = lds_limit(p->device, &lmax))) return rc;
@@ -1860,10 +1863,12 @@ int launch_one(const Launch& x, hipStream_t s) {
 
 template <typename VT, typename FT>
 int apply_t(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int64_t nrhs,
-            hipStream_t s, ibf_profile* prof) {
-  std::vector<Launch> seq;
+            hipStream_t s, ibf_profile* prof, void* const* ws = nullptr) {
+  // the launch list is rebuilt per call into a per-thread vector whose
+  // capacity persists (no host allocation once it has grown)
+  thread_local std::vector<Launch> seq;
   int rc;
-  if ((rc = make_schedule<VT, FT>(p, g, ldg, u, ldu, (int)nrhs, seq))) return rc;
+  if ((rc = make_schedule<VT, FT>(p, g, ldg, u, ldu, (int)nrhs, seq, false, ws))) return rc;
   LaunchTimer T(prof, s);
   for (const Launch& x : seq) {
     if ((rc = T.begin())) return rc;
@@ -2165,6 +2170,59 @@ int apply_plan(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, i
   }
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free apply: the ping-pong coefficient buffers live in a static
+// device array (one copy per device, held until the process ends) instead of
+// the plan's workspace.  Host code never uses the array's name as a device
+// address: its address on each device comes from hipGetSymbolAddress, taken
+// once per device with that device current.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocScratch = (size_t)128 << 20;          // bytes, both buffers
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+
+int scratch_ptr(int device, unsigned char** out) {
+  static std::mutex mu;
+  static unsigned char* ptrs[64] = {nullptr};
+  if (device < 0 || device >= 64) {
+    set_error("ibf_apply_noalloc: device ordinal out of range");
+    return IBF_ERR_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ptrs[device]) {
+    void* ptr = nullptr;
+    IBF_HIP_CHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    ptrs[device] = static_cast<unsigned char*>(ptr);
+  }
+  *out = ptrs[device];
+  return IBF_OK;
+}
+
+int apply_plan_noalloc(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu,
+                       int64_t nrhs, hipStream_t s) {
+  IBF_HIP_CHECK(hipSetDevice(p->device));
+  const size_t vb = complex_bytes(p->precision);
+  int kmax = 1;
+  for (int k : p->rank) kmax = std::max(kmax, k);
+  for (int k : p->rank_in_g) kmax = std::max(kmax, k);
+  for (int k : p->rank_in_h) kmax = std::max(kmax, k);
+  const size_t half = (((size_t)p->npairs * kmax * (size_t)nrhs * vb) + 255) & ~(size_t)255;
+  if (nrhs > (1 << 20) || 2 * half > kNoAllocScratch) {
+    set_error("ibf_apply_noalloc: the coefficient buffers need " + std::to_string(2 * half) +
+              " bytes, more than the " + std::to_string(kNoAllocScratch) +
+              "-byte scratch array (use ibf_apply)");
+    return IBF_ERR_INVALID_ARG;
+  }
+  unsigned char* base = nullptr;
+  int rc;
+  if ((rc = scratch_ptr(p->device, &base))) return rc;
+  void* ws[2] = {base, base + half};
+  switch (p->precision) {
+    case IBF_FP64: return apply_t<double2, double2>(p, g, ldg, u, ldu, nrhs, s, nullptr, ws);
+    case IBF_FP32: return apply_t<float2, float2>(p, g, ldg, u, ldu, nrhs, s, nullptr, ws);
+    default: return apply_t<float2, bf16x2c>(p, g, ldg, u, ldu, nrhs, s, nullptr, ws);
+  }
+}
+
 // The launch list a schedule produces (kernel, tile, grid, LDS, stage span
 // and chunk width per launch): two knob settings with equal signatures run
 // the same launches.
@@ -2332,6 +2390,27 @@ int ibf_tune(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, int
     return IBF_ERR_UNSUPPORTED;
   }
   return ibf::tune_plan(p, g, ldg, u, ldu, nrhs, (hipStream_t)stream, best, dflt);
+}
+
+int ibf_apply_noalloc(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu,
+                      int64_t nrhs, void* stream) {
+  if (!p) {
+    ibf::set_error("ibf_apply_noalloc: null plan");
+    return IBF_ERR_INVALID_ARG;
+  }
+  if (!p->built) {
+    ibf::set_error("ibf_apply_noalloc: plan not built");
+    return IBF_ERR_NOT_BUILT;
+  }
+  if (!g || !u || nrhs < 1 || ldg < p->nxi || ldu < p->nx) {
+    ibf::set_error("ibf_apply_noalloc: null vector, nrhs < 1 or leading dimension too small");
+    return IBF_ERR_INVALID_ARG;
+  }
+  if (p->dim != 1) {
+    ibf::set_error("ibf_apply_noalloc: provided for dim-1 plans");
+    return IBF_ERR_UNSUPPORTED;
+  }
+  return ibf::apply_plan_noalloc(p, g, ldg, u, ldu, nrhs, (hipStream_t)stream);
 }
 
 int ibf_set_tuning(ibf_plan_t p, int64_t nrhs, const ibf_tuning* t) {

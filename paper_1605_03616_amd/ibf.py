@@ -25,7 +25,7 @@ EXPORTED = ["ibf_plan", "ibf_build", "ibf_apply", "ibf_apply_profile", "ibf_quer
             "ibf_apply_batch", "ibf_batch_destroy", "ibf_dense_apply", "ibf_mlp_n_params",
             "ibf_mlp_features", "ibf_mlp_forward", "ibf_mlp_grad_work", "ibf_mlp_loss_grad",
             "ibf_mlp_adam", "ibf_mlp_select", "ibf_tune", "ibf_set_tuning", "ibf_set_allocator",
-            "ibf_measure_peak", "ibf_apply_adjoint", "ibf_rel_error"]
+            "ibf_measure_peak", "ibf_apply_adjoint", "ibf_rel_error", "ibf_apply_noalloc"]
 MLP_FEATURES = 5
 PATHS = ["default", "vector", "mfma", "tight"]      # ibf_tuning.path
 BATCH_GRAPH = 1
@@ -147,13 +147,14 @@ def load(path: str = LIB_PATH):
     lib.ibf_set_allocator.argtypes = [ALLOC_FN, FREE_FN]
     lib.ibf_measure_peak.argtypes = [C.c_int, vp, C.POINTER(C.c_double)]
     lib.ibf_apply_adjoint.argtypes = [vp, vp, i64, vp, i64, i64, vp]
+    lib.ibf_apply_noalloc.argtypes = [vp, vp, i64, vp, i64, i64, vp]
     lib.ibf_rel_error.argtypes = [vp, i64, vp, i64, i64, i64, C.c_int, C.POINTER(C.c_double), vp]
     for name in ("ibf_plan", "ibf_build", "ibf_apply", "ibf_apply_profile", "ibf_query",
                  "ibf_destroy", "ibf_eval_kernel", "ibf_batch_create", "ibf_apply_batch",
                  "ibf_batch_destroy", "ibf_dense_apply", "ibf_mlp_n_params",
                  "ibf_mlp_features", "ibf_mlp_forward", "ibf_mlp_loss_grad", "ibf_mlp_adam",
                  "ibf_mlp_select", "ibf_tune", "ibf_set_tuning", "ibf_set_allocator", "ibf_measure_peak",
-                 "ibf_apply_adjoint", "ibf_rel_error"):
+                 "ibf_apply_adjoint", "ibf_rel_error", "ibf_apply_noalloc"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -333,6 +334,17 @@ class Plan:
                                            C.c_void_p(v.data_ptr()), v.shape[1], nrhs,
                                            _stream_handle(stream)))
         return v[0] if squeeze else v
+
+    def apply_noalloc(self, g, u, stream=None):
+        """ibf_apply_noalloc on (nrhs, n) tensors (u preallocated): the same
+        product with the coefficient buffers in the library's static scratch
+        array (no device allocation)."""
+        if g.dtype != self.vector_dtype() or not g.is_contiguous() or not u.is_contiguous():
+            raise ValueError("g and u must be contiguous tensors of the plan's complex dtype")
+        _check(self._lib.ibf_apply_noalloc(self.handle, C.c_void_p(g.data_ptr()), g.shape[1],
+                                           C.c_void_p(u.data_ptr()), u.shape[1], g.shape[0],
+                                           _stream_handle(stream)))
+        return u
 
     def apply_raw(self, g_ptr, ldg, u_ptr, ldu, nrhs, stream=None):
         _check(self._lib.ibf_apply(self.handle, C.c_void_p(g_ptr), ldg, C.c_void_p(u_ptr), ldu,
