@@ -13,11 +13,14 @@
 // contiguous pairs (a >> 2, 4b + c) at level l - 1, and a pair index is
 // p = a 4^(L-l) + b.  Tensor grid index t = t1 r + t2.
 //
-// Compression (Sec. 4.2): every block is reduced through its 25 x 25 (r^2 x
-// r^2) Gram matrix, eigen-decomposed by one-sided Jacobi in FP64 (the
-// normalised orthogonalised columns are the eigenvectors): singular values
-// sqrt(lambda) are resolved down to about 1e-8 of the largest, so this path
-// requires tol >= 1e-7.  One 32-lane group per pair, rows on lanes.
+// Compression (Sec. 4.2): every block W (r^2 rows, its columns produced one
+// at a time) is reduced to the triangular factor R of W^* = Q R by Givens
+// rotations applied as each column arrives (backward stable), and the small
+// R^* is orthogonalised by one-sided Jacobi in FP64: W = R^* Q^*, so the left
+// singular vectors and singular values of W are those of R^*, accurate to
+// rounding in FP64 (no Gram matrix, whose eigenvalues would lose singular
+// values below about 1e-8 of the largest).  One 32-lane group per pair
+// (r^2 <= 25 grid points, r <= 5); rows on lanes.
 //
 // Kernels: k2_tables (Chebyshev nodes, tensor child->parent Lagrange
 // matrices), k2_middle (eq:KeqUMV), k2_sweep_g (eqn:GC), k2_sweep_h (eqn:HR),
@@ -122,7 +125,6 @@ struct Mibf2D {
 namespace {
 
 constexpr int kB2 = 256;
-constexpr int kGroup = 32;                 // lanes per pair in the build kernels
 constexpr int kCentreSide = 16;            // centre square side (Sec. 6.3: down to 16 x 16)
 
 struct BoxDev {
@@ -199,16 +201,48 @@ __device__ inline double lag2(const double* z, int r, int t, double y1, double y
   return lagrange_t(z, r, t / r, y1) * lagrange_t(z, r, t % r, y2);
 }
 
+template <int G>
 __device__ __forceinline__ double2 shfl2(double2 v, int src) {
-  return make_double2(__shfl(v.x, src, kGroup), __shfl(v.y, src, kGroup));
+  return make_double2(__shfl(v.x, src, G), __shfl(v.y, src, G));
 }
+template <int G>
 __device__ __forceinline__ double2 csum(double2 v) {
-  return make_double2(group_sum<kGroup>(v.x), group_sum<kGroup>(v.y));
+  return make_double2(group_sum<G>(v.x), group_sum<G>(v.y));
 }
 
-// One-sided Jacobi on a Hermitian positive semidefinite matrix held one row
-// per lane (columns in a[]): afterwards column j is lambda_j u_j with u_j an
-// eigenvector, and lam[j] = ||column j|| = lambda_j.
+// Lanes per pair of the build kernels for R2 tensor grid points.
+template <int R2>
+constexpr int group2() { return R2 <= 32 ? 32 : 64; }
+
+// One column of a block W arrives (lane t holds W[t][m]): the row
+// a = W[:, m]^* of A = W^* is folded into the upper-triangular R of A = Q R
+// by R2 complex Givens rotations.  Lane k holds column k of R (rr[j] =
+// R[j][k]) and a_k.  Rotation j mixes row j of R with a so that a_j becomes
+// zero: with x = R[j][j], y = a_j, nu = sqrt(|x|^2 + |y|^2),
+//   c = |x| / nu,  s = (x / |x|) conj(y) / nu   (c = 0, s = conj(y) / |y| if x = 0),
+//   R[j][k] <- c R[j][k] + s a_k,  a_k <- -conj(s) R[j][k] + c a_k.
+// Every lane computes c, s from the broadcast x, y (the same numbers); the
+// lanes k < j hold zeros on both rows, which stay zero.
+template <int R2, int G, int J = 0>
+__device__ __forceinline__ void givens_fold(double2 (&rr)[R2], double2& a) {
+  if constexpr (J < R2) {
+    const double2 x = shfl2<G>(rr[J], J), y = shfl2<G>(a, J);
+    const double ax2 = x.x * x.x + x.y * x.y, ay2 = y.x * y.x + y.y * y.y;
+    const double ax = sqrt(ax2), nu = sqrt(ax2 + ay2);
+    // branch-free: nu = 0 (nothing to eliminate) gives c = 1, s = 0; x = 0
+    // gives c = 0, s = conj(y) / |y|
+    const double inv = nu > 0.0 ? 1.0 / nu : 0.0;
+    const double c = nu > 0.0 ? ax * inv : 1.0;
+    const double2 ph = ax > 0.0 ? make_double2(x.x / ax, x.y / ax) : make_double2(1.0, 0.0);
+    const double2 sv = cscale(cmul(ph, conjd(y)), inv);
+    const double2 rj = rr[J];
+    rr[J] = cadd(cscale(rj, c), cmul(sv, a));
+    a = cadd(cscale(a, c), cscale(cmul(conjd(sv), rj), -1.0));
+    givens_fold<R2, G, J + 1>(rr, a);
+  }
+}
+
+// Complex Jacobi rotation of columns (p, q) of a matrix held one row per lane.
 template <int G>
 __device__ __forceinline__ void jrot(double2& ap_, double2& aq_, double& np_, double& nq_,
                                      double thresh, double small, bool& rotated) {
@@ -243,6 +277,8 @@ __device__ __forceinline__ void jsweep(double2 (&a)[R], double (&nrm)[R], double
   }
 }
 
+// One-sided Jacobi on a matrix held one row per lane (columns in a[]):
+// afterwards the columns are mutually orthogonal and lam[j] = ||column j||.
 template <int R, int G>
 __device__ __forceinline__ void jacobi_eig(double2 (&a)[R], double (&lam)[R]) {
   const double thresh = 4.0 * (double)(R > 8 ? R : 8) * 1.1102230246251565e-16;
@@ -274,15 +310,6 @@ __device__ __forceinline__ T sel(const T (&v)[R], int i) {
   return out;
 }
 
-// Ranks from eigenvalues: sigma_j = sqrt(lambda_j) > tol * sigma_max.
-template <int R>
-__device__ __forceinline__ int eig_rank(const double (&lam)[R], double tol, int (&pos)[R]) {
-  double sig[R];
-#pragma unroll
-  for (int j = 0; j < R; ++j) sig[j] = sqrt(lam[j]);
-  return rank_positions<R>(sig, tol, pos);
-}
-
 // ---------------------------------------------------------------------------
 // Tables: Chebyshev nodes and the tensor child -> parent Lagrange matrices
 //   lc[c][t][s] = M^B_t(g^{C_c}_s) = M_t1((2c1-1)/4 + z_s1/2) M_t2((2c2-1)/4 + z_s2/2)
@@ -305,10 +332,11 @@ __global__ void k2_tables(int r, double* z, double* lc) {
   lc[e] = lagrange_t(zz, r, t / r, y1) * lagrange_t(zz, r, t % r, y2);
 }
 
-// Thread -> (pair, lane) of the 32-lane groups
+// Thread -> (pair, lane) of the G-lane groups
 #define IBF2_GROUP_INDEX                                                        \
-  const int lane = threadIdx.x & (kGroup - 1);                                  \
-  const int64_t p = ((int64_t)blockIdx.x * kB2 + threadIdx.x) / kGroup;         \
+  constexpr int G = group2<R2>();                                               \
+  const int lane = threadIdx.x & (G - 1);                                       \
+  const int64_t p = ((int64_t)blockIdx.x * kB2 + threadIdx.x) / G;              \
   if (p >= npairs) return;                                                      \
   const bool row = lane < R2;
 
@@ -333,38 +361,43 @@ __global__ __launch_bounds__(kB2) void k2_middle(BoxDev B, const double* __restr
   const double wa = ldexp(1.0, -h), wb = B.w / ldexp(1.0, L - h);
   const int tl = row ? lane : 0;
   const double ga1 = gpt(ca1, wa, z[tl / r]), ga2 = gpt(ca2, wa, z[tl % r]);
+  // M^* = Q R by Givens rotations, one column of M at a time; gram = R^*
   double2 gram[R2];
 #pragma unroll
   for (int j = 0; j < R2; ++j) gram[j] = make_double2(0.0, 0.0);
   for (int s = 0; s < R2; ++s) {
     const double2 w = row ? kval2(B.ph, ga1, ga2, gpt(cb1, wb, z[s / r]), gpt(cb2, wb, z[s % r]))
                           : make_double2(0.0, 0.0);
-#pragma unroll
-    for (int j = 0; j < R2; ++j) cfma(gram[j], w, conjd(shfl2(w, j)));
+    double2 av = conjd(w);
+    givens_fold<R2, G>(gram, av);
   }
-  double lam[R2];
-  jacobi_eig<R2, kGroup>(gram, lam);
+#pragma unroll
+  for (int j = 0; j < R2; ++j) gram[j] = conjd(gram[j]);
+  // columns of R^* orthogonalised: column j = sigma_j u_j, sig[j] = sigma_j
+  double sig[R2];
+  jacobi_eig<R2, G>(gram, sig);
   int pos[R2];
-  const int k = eig_rank<R2>(lam, tol, pos);
-  // C row t: Q[t][j] lambda_j^(-3/4)
+  const int k = rank_positions<R2>(sig, tol, pos);
+  // C row t: u_j[t] sigma_j^(1/2)
   double2* crow = Cb + (p * R2 + tl) * R2;
 #pragma unroll
   for (int j = 0; j < R2; ++j) {
-    const bool keep = pos[j] < k && lam[j] > 0.0;
-    const double sc = keep ? pow(lam[j], -0.75) : 0.0;
+    const bool keep = pos[j] < k && sig[j] > 0.0;
+    const double sc = keep ? 1.0 / sqrt(sig[j]) : 0.0;
     if (row) crow[pos[j]] = cscale(gram[j], sc);
   }
-  // R row s: (sum_t conj(M[t][s]) Q[t][j]) lambda_j^(-5/4); lane j keeps column j
+  // R row s: (sum_t conj(M[t][s]) sigma_j u_j[t]) sigma_j^(-3/2) = v_j[s] sigma_j^(1/2);
+  // lane j keeps column j
   const int my_pos = sel<R2>(pos, tl);
-  const double my_lam = sel<R2>(lam, tl);
-  const double my_sc = (my_pos < k && my_lam > 0.0) ? pow(my_lam, -1.25) : 0.0;
+  const double my_sig = sel<R2>(sig, tl);
+  const double my_sc = (my_pos < k && my_sig > 0.0) ? pow(my_sig, -1.5) : 0.0;
   for (int s = 0; s < R2; ++s) {
     const double2 mts = row ? kval2(B.ph, ga1, ga2, gpt(cb1, wb, z[s / r]), gpt(cb2, wb, z[s % r]))
                             : make_double2(0.0, 0.0);
     double2 mine = make_double2(0.0, 0.0);
 #pragma unroll
     for (int j = 0; j < R2; ++j) {
-      const double2 v = csum(cmul(conjd(mts), gram[j]));
+      const double2 v = csum<G>(cmul(conjd(mts), gram[j]));
       if (lane == j) mine = v;
     }
     if (row) Rb[(p * R2 + s) * R2 + my_pos] = cscale(mine, my_sc);
@@ -418,7 +451,7 @@ __global__ __launch_bounds__(kB2) void k2_sweep_g(BoxDev B, int l, const double*
     const double2* cs = Cprev + (pin0 + c) * R2 * R2 + m;
     double2 acc = make_double2(0.0, 0.0);
     for (int s = 0; s < R2; ++s)
-      cfma(acc, cscale(shfl2(bs, s), la[s * R2 + tl]), cs[s * R2]);
+      cfma(acc, cscale(shfl2<G>(bs, s), la[s * R2 + tl]), cs[s * R2]);
     return row ? cmul(at, acc) : make_double2(0.0, 0.0);
   };
   double2 gram[R2];
@@ -432,26 +465,29 @@ __global__ __launch_bounds__(kB2) void k2_sweep_g(BoxDev B, int l, const double*
     at[c] = kval2(B.ph, ga1, ga2, cc1, cc2);
     bs[c] = conjd(kval2(B.ph, gp1, gp2, cc1, cc2));    // lane s holds B_s
   }
+  // W^* = Q R by Givens rotations, one column of W at a time; gram = R^*
 #pragma unroll
   for (int c = 0; c < 4; ++c)
     for (int m = 0; m < kin[c]; ++m) {
-      const double2 w = wcol(c, m, at[c], bs[c]);
-#pragma unroll
-      for (int j = 0; j < R2; ++j) cfma(gram[j], w, conjd(shfl2(w, j)));
+      double2 av = conjd(wcol(c, m, at[c], bs[c]));
+      givens_fold<R2, G>(gram, av);
     }
-  double lam[R2];
-  jacobi_eig<R2, kGroup>(gram, lam);
+#pragma unroll
+  for (int j = 0; j < R2; ++j) gram[j] = conjd(gram[j]);
+  double sig[R2];
+  jacobi_eig<R2, G>(gram, sig);                          // column j = sigma_j u_j
   int pos[R2];
-  const int k = eig_rank<R2>(lam, tol, pos);
-  double2* crow = Cout + (p * R2 + tl) * R2;
+  const int k = rank_positions<R2>(sig, tol, pos);
+  double2* crow = Cout + (p * R2 + tl) * R2;             // C^l = U_k S_k
 #pragma unroll
   for (int j = 0; j < R2; ++j) {
-    const bool keep = pos[j] < k && lam[j] > 0.0;
-    if (row) crow[pos[j]] = keep ? cscale(gram[j], 1.0 / sqrt(lam[j])) : make_double2(0.0, 0.0);
+    const bool keep = pos[j] < k && sig[j] > 0.0;
+    if (row) crow[pos[j]] = keep ? gram[j] : make_double2(0.0, 0.0);
   }
+  // Gbar row j = sigma_j^-1 u_j^* W = (sigma_j u_j)^* W sigma_j^-2
   const int my_pos = sel<R2>(pos, tl);
-  const double my_lam = sel<R2>(lam, tl);
-  const double my_sc = (my_pos < k && my_lam > 0.0) ? pow(my_lam, -1.5) : 0.0;
+  const double my_sig = sel<R2>(sig, tl);
+  const double my_sc = (my_pos < k && my_sig > 0.0) ? 1.0 / (my_sig * my_sig) : 0.0;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     double2* st = stage + (p * 4 + c) * R2 * R2;
@@ -461,7 +497,7 @@ __global__ __launch_bounds__(kB2) void k2_sweep_g(BoxDev B, int l, const double*
         double2 mine = make_double2(0.0, 0.0);
 #pragma unroll
         for (int j = 0; j < R2; ++j) {
-          const double2 v = csum(cmul(conjd(gram[j]), w));
+          const double2 v = csum<G>(cmul(conjd(gram[j]), w));
           if (lane == j) mine = v;
         }
         if (row) st[my_pos * R2 + m] = cscale(mine, my_sc);
@@ -531,32 +567,34 @@ __global__ __launch_bounds__(kB2) void k2_sweep_h(BoxDev B, int l, const double*
     const double2* rs = Rcur + pout[al] * R2 * R2 + m;
     double2 acc = make_double2(0.0, 0.0);
     for (int t = 0; t < R2; ++t)
-      cfma(acc, cscale(shfl2(et[al], t), lcc[t * R2 + sl]), rs[t * R2]);
+      cfma(acc, cscale(shfl2<G>(et[al], t), lcc[t * R2 + sl]), rs[t * R2]);
     return row ? cmul(ds[al], acc) : make_double2(0.0, 0.0);
   };
+  // Z^* = Q R by Givens rotations, one column of Z at a time; gram = R^*
   double2 gram[R2];
 #pragma unroll
   for (int j = 0; j < R2; ++j) gram[j] = make_double2(0.0, 0.0);
 #pragma unroll
   for (int al = 0; al < 4; ++al)
     for (int m = 0; m < kout[al]; ++m) {
-      const double2 w = zcol(al, m);
-#pragma unroll
-      for (int j = 0; j < R2; ++j) cfma(gram[j], w, conjd(shfl2(w, j)));
+      double2 av = conjd(zcol(al, m));
+      givens_fold<R2, G>(gram, av);
     }
-  double lam[R2];
-  jacobi_eig<R2, kGroup>(gram, lam);
+#pragma unroll
+  for (int j = 0; j < R2; ++j) gram[j] = conjd(gram[j]);
+  double sig[R2];
+  jacobi_eig<R2, G>(gram, sig);                          // column j = sigma_j u_j
   int pos[R2];
-  const int k = eig_rank<R2>(lam, tol, pos);
-  double2* rrow = Rnext + (q * R2 + sl) * R2;
+  const int k = rank_positions<R2>(sig, tol, pos);
+  double2* rrow = Rnext + (q * R2 + sl) * R2;            // R^{l-1} = U_k S_k
 #pragma unroll
   for (int j = 0; j < R2; ++j) {
-    const bool keep = pos[j] < k && lam[j] > 0.0;
-    if (row) rrow[pos[j]] = keep ? cscale(gram[j], 1.0 / sqrt(lam[j])) : make_double2(0.0, 0.0);
+    const bool keep = pos[j] < k && sig[j] > 0.0;
+    if (row) rrow[pos[j]] = keep ? gram[j] : make_double2(0.0, 0.0);
   }
   const int my_pos = sel<R2>(pos, sl);
-  const double my_lam = sel<R2>(lam, sl);
-  const double my_sc = (my_pos < k && my_lam > 0.0) ? pow(my_lam, -1.5) : 0.0;
+  const double my_sig = sel<R2>(sig, sl);
+  const double my_sc = (my_pos < k && my_sig > 0.0) ? 1.0 / (my_sig * my_sig) : 0.0;
 #pragma unroll
   for (int al = 0; al < 4; ++al) {
     double2* st = stage + (pout[al] * 4 + c) * R2 * R2;
@@ -566,7 +604,7 @@ __global__ __launch_bounds__(kB2) void k2_sweep_h(BoxDev B, int l, const double*
         double2 mine = make_double2(0.0, 0.0);
 #pragma unroll
         for (int j = 0; j < R2; ++j) {
-          const double2 v = csum(cmul(conjd(gram[j]), w));
+          const double2 v = csum<G>(cmul(conjd(gram[j]), w));
           if (lane == j) mine = v;
         }
         if (row) st[m * R2 + my_pos] = cscale(conjd(mine), my_sc);
@@ -1201,7 +1239,8 @@ int build2d_t(ibf_plan_t p, hipStream_t s) {
     const BoxDev B{M.ph, bx.o1, bx.o2, bx.w, bx.L, bx.lV, bx.h, r};
     const int L = bx.L, lV = bx.lV, h = bx.h;
     const int64_t np = (int64_t)1 << (2 * L);
-    const unsigned gg = (unsigned)((np * kGroup + kB2 - 1) / kB2);
+    const int G = R2 <= 32 ? 32 : 64;                        // lanes per pair (group2<R2>)
+    const unsigned gg = (unsigned)((np * G + kB2 - 1) / kB2);
     std::vector<int> kg(L + 1, 0), kh(L + 1, 0);
     IBF_HIP_CHECK(hipMemsetAsync(S.kmax, 0, sizeof(int) * 128, s));
     IBF_HIP_CHECK(hipMemsetAsync(S.nnz, 0, sizeof(unsigned long long), s));
@@ -1607,8 +1646,7 @@ int plan2d(const ibf_desc* d, ibf_plan_t* out) {
     set_error("ibf_plan: dim 2 supports r = 2 .. 5 (r^2 <= 25 grid points per box)");
     return d->r < 2 ? IBF_ERR_INVALID_ARG : IBF_ERR_UNSUPPORTED;
   }
-  if (!(d->tol >= 1e-7 && d->tol < 1.0))
-    return bad("ibf_plan: dim 2 needs 1e-7 <= tol < 1 (Gram-based compression)");
+  if (!(d->tol > 0.0 && d->tol < 1.0)) return bad("ibf_plan: tol must lie in (0, 1)");
   int leaf_side = 0;
   for (int s = 1; s <= 8; s *= 2)
     if (s * s == d->leaf) leaf_side = s;

@@ -2,10 +2,11 @@
 stored entry counts of the compressed factors), plus the full-size 256 x 256
 workload against sampled rows of the dense product.
 
-Bars: FP64 1e-9 relative (the Gram eigen-solves resolve singular values to
-about 1e-8 of the largest, and the truncation tolerance is 1e-4, so the two
-factorizations agree to the FP64 rounding of the shared ranks), FP32 1e-5,
-BF16X2 1e-4 against the oracle; the x-independent phase exactly (1e-12).
+Bars: FP64 max(1e-12, 8 N 2^-53) relative with N = n^2 points (the phase
+evaluation floor: the two libraries' sin / cos / sqrt differ by an ulp and
+|Phi| grows with n), FP32 1e-5, BF16X2 1e-4 against the oracle, Frobenius
+and per column; the x-independent phase exactly (1e-12).  The 128 x 128
+case reaches the 32-wide boxes (three and four stages) of the coronas.
 """
 import functools
 import os
@@ -40,9 +41,13 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a, np.complex128) - b) / np.linalg.norm(b))
 
 
+def fp64_bar(n):
+    return max(1e-12, 8 * n * n * 2.0 ** -53)
+
+
 @functools.lru_cache(maxsize=None)
-def _case(n, r, phase=I.PHASE_FIO2D, nrhs=2, seed=41):
-    P = I.fio2d_grid(n, r, nrhs, seed, tol=1e-4, precision=I.PREC_FP64)
+def _case(n, r, phase=I.PHASE_FIO2D, nrhs=2, seed=41, tol=1e-4):
+    P = I.fio2d_grid(n, r, nrhs, seed, tol=tol, precision=I.PREC_FP64)
     P.phase = phase
     P.params = I.DEFAULT_PARAMS[phase]
     part, built, cidx = D.mibf_build(P.phase, P.params, P.x, P.xi, n, r, P.tol)
@@ -63,15 +68,18 @@ def _gpu(torch, P, precision):
     return u.cpu().numpy().T.astype(np.complex128), q
 
 
-@pytest.mark.parametrize("n,r,phase", [(32, 4, I.PHASE_FIO2D), (64, 5, I.PHASE_FIO2D),
-                                       (32, 5, I.PHASE_DFT)])
-def test_2d_fp64_parity(torch_dev, n, r, phase):
-    _say(f"2-D FP64 parity n={n} r={r} phase={phase}")
-    P, uo, pre, opt = _case(n, r, phase)
+@pytest.mark.parametrize("n,r,phase,tol", [(32, 4, I.PHASE_FIO2D, 1e-4),
+                                           (64, 5, I.PHASE_FIO2D, 1e-4),
+                                           (32, 5, I.PHASE_DFT, 1e-4),
+                                           (32, 5, I.PHASE_FIO2D, 1e-9)])
+def test_2d_fp64_parity(torch_dev, n, r, phase, tol):
+    _say(f"2-D FP64 parity n={n} r={r} phase={phase} tol={tol}")
+    P, uo, pre, opt = _case(n, r, phase, tol=tol)
     ug, q = _gpu(torch_dev, P, I.PREC_FP64)
     assert q["nnz_prelim"] == pre
     assert q["nnz_opt"] == opt
-    assert _rel(ug, uo) <= 1e-9
+    assert _rel(ug, uo) <= fp64_bar(n)
+    assert O.rel_error_cols(ug, uo) <= fp64_bar(n)
 
 
 @pytest.mark.parametrize("precision,bar", [(I.PREC_FP32, 1e-5), (I.PREC_BF16X2, 1e-4)])
@@ -80,6 +88,21 @@ def test_2d_reduced_precision(torch_dev, precision, bar):
     P, uo, _, _ = _case(64, 5)
     ug, _ = _gpu(torch_dev, P, precision)
     assert _rel(ug, uo) <= bar
+    assert O.rel_error_cols(ug, uo) <= bar
+
+
+@pytest.mark.parametrize("precision", [I.PREC_FP64, I.PREC_FP32])
+def test_2d_128_against_oracle(torch_dev, precision):
+    """128 x 128 grid, r = 5, tol 1e-4: the coronas' 32-wide boxes (three H
+    and four G stages per box, the batched stage indices 2 and 3) against
+    the oracle MIBF, FP64 at its bar and FP32 at 1e-5."""
+    _say(f"2-D n=128 r=5 precision={precision}: oracle MIBF (about 30 s)")
+    P, uo, pre, opt = _case(128, 5, nrhs=3, seed=44)
+    ug, q = _gpu(torch_dev, P, precision)
+    bar = fp64_bar(128) if precision == I.PREC_FP64 else 1e-5
+    assert _rel(ug, uo) <= bar
+    assert O.rel_error_cols(ug, uo) <= bar
+    assert q["nnz_prelim"] == pre and q["nnz_opt"] == opt
 
 
 def test_2d_x_independent_phase_exact(torch_dev):
@@ -93,8 +116,10 @@ def test_2d_x_independent_phase_exact(torch_dev):
 
 
 def test_2d_full_size_fp32(torch_dev):
-    """256 x 256 grid, r = 5 x 5, tol 1e-4, 8 RHS FP32: sampled rows against the
-    dense product (about 1e-2 at r = 5) and against the FP64 GPU plan."""
+    """256 x 256 grid, r = 5 x 5, tol 1e-4, 8 RHS FP32 (the benchmark's 2-D
+    workload): sampled rows against the dense product (about 1e-2 at r = 5;
+    the oracle's factorization at this size is covered by the 128 x 128 case
+    above, which has every box width but the 64-wide ring)."""
     P = I.workload_fio2d_256()
     _say("2-D full size 256x256 r=5 FP32 + FP64")
     u32, q32 = _gpu(torch_dev, P, I.PREC_FP32)
@@ -102,6 +127,7 @@ def test_2d_full_size_fp32(torch_dev):
     assert _rel(u32, u64) <= 1e-5
     rows = np.random.default_rng(1234).choice(len(P.x), 256, replace=False)
     ud = D.dense_apply_2d(P.phase, P.params, P.x, P.xi, P.g, rows=rows)
+    assert _rel(u32[rows], ud) < 3e-2
     err = _rel(u64[rows], ud)
     _say(f"2-D full size: error vs dense {err:.3g}, R_comp {q32['R_comp']:.3f}")
     assert err < 3e-2
