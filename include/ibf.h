@@ -93,10 +93,12 @@ typedef struct ibf_plan_s* ibf_plan_t;
  * [-W/2, W/2)^2 with W = omega_width (a power of two >= 32, omega_lo = -W/2).  Omega is split into coronas of 12 dyadic boxes each, down to a
  * 16 x 16 centre square summed directly; every box runs its own quadtree IBF
  * with a tensor r x r Chebyshev grid.  phase_id IBF_PHASE_DFT, FIO2D or
- * SEPARABLE; 2 <= r <= 5 (r^2 grid rows on one 32-lane group); tol >= 1e-7
- * (the compression resolves singular values through Gram matrices); leaf is
+ * SEPARABLE; 2 <= r <= 5 (r^2 grid rows on one 32-lane group); 0 < tol < 1
+ * (each block is reduced by Givens QR and its triangular factor orthogonalised
+ * by one-sided Jacobi, so singular values resolve to FP64 rounding); leaf is
  * the side of an Omega leaf box: 4, 16 or 64 points; no sweep-in, amplitude,
- * fixed ranks or learned order.
+ * fixed ranks or learned order (sweep_in = -1 selects off, 1 is rejected
+ * with IBF_ERR_UNSUPPORTED).
  */
 typedef struct {
   int dim;                   /* 1 or 2 */
