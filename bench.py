@@ -42,11 +42,11 @@ MEASURED_TRAFFIC = {
     # (workload, schedule path/chunk/max_fused) -> (sha1 of the apply source,
     #   kernel class, [(launches per step, FETCH_SIZE KiB, WRITE_SIZE KiB), ...])
     ("fio1d_n65536_r12_fp32", "default/0/0"): (
-        "b8d99bd69ab656292685d1beb6fa23e3be1cde7b", "apply_fused_mfma",
-        [(2, 332073, 344064), (1, 263421, 294912)]),
+        "5efd6b5c8edb6ef729c21598e35e266e4d220e14", "apply_stage_tight",
+        [(2, 323579, 295936)]),
     ("nudft_n1048576_r10", "default/0/0"): (
-        "b8d99bd69ab656292685d1beb6fa23e3be1cde7b", "apply_fused_mfma",
-        [(2, 2424920, 983040), (1, 1769570, 917504), (1, 1822850, 1048576)]),
+        "5efd6b5c8edb6ef729c21598e35e266e4d220e14", "apply_fused_mfma",
+        [(2, 2424927, 983040), (1, 1769571, 917504), (1, 1822842, 1048576)]),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
