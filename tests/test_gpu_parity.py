@@ -180,12 +180,14 @@ def test_bf16x2_mfma_parity(torch_dev):
     ("fio4k_r12", 64, I.PREC_FP32, 0), ("fio4k_r12", 130, I.PREC_FP32, 0),
     ("fio4k_r12", 64, I.PREC_BF16X2, 0), ("fio3000_r9", 70, I.PREC_FP32, 3),
     ("fio8k_r16", 64, I.PREC_FP32, 0), ("fio2k_r2", 64, I.PREC_FP32, 2),
-    ("nudft4k_r10", 64, I.PREC_FP32, 0)])
+    ("nudft4k_r10", 64, I.PREC_FP32, 0), ("fio4k_r12", 64, I.PREC_FP32, 1),
+    ("nudft4k_r10", 130, I.PREC_FP32, 3), ("fio3000_r9", 64, I.PREC_BF16X2, 2)])
 def test_tight_stage_parity(torch_dev, key, nrhs, precision, fused):
     """MFMA stages at each pair's own ranks (64-column chunks, up to 4 stages a
     launch): ragged last chunk (130 = 2 x 64 + 2, 70), ragged leaves (N =
     3000), the widest tile (r = 16), the smallest (r = 2), random x, BF16X2
-    factors, and fixed fusion depths, against the oracle IBF."""
+    factors, and fixed fusion depths (1 to 3 stages a launch), against the
+    oracle IBF."""
     torch = torch_dev
     from paper_1605_03616_amd import ibf
     _say(f"tight stages {key} nrhs={nrhs} precision={precision} fused={fused}")
