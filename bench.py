@@ -173,7 +173,8 @@ def _bench_batched(args):
         print(f"[bench] predictor: {pred_info}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plans = [ibf.Plan.from_problem(P).build() for P in probs]
+    # the plans are independent: built concurrently, one HIP stream per host thread
+    plans = ibf.build_batch([ibf.Plan.from_problem(P) for P in probs])
     build_s = time.perf_counter() - t0
     qs = [pl.query() for pl in plans]
     gs = [torch.from_numpy(np.ascontiguousarray(P.g.T)).to(torch.complex64).cuda() for P in probs]
@@ -221,8 +222,8 @@ def _bench_batched(args):
                    "target_tol": 1e-6,
                    "count": len(probs), "sum_N": sum(P.n for P in probs),
                    "sum_N_x_nrhs": units, "parallelism": "single-gpu"},
-        "build_ms": round(sum(q["build_ms"] for q in qs), 3),
-        "build_wall_ms": round(build_s * 1e3, 3),
+        "build_ms": round(build_s * 1e3, 3),
+        "build_ms_sum_over_plans": round(sum(q["build_ms"] for q in qs), 3),
         "nnz_opt": sum(q["nnz_opt"] for q in qs),
         "roofline": {"kernel": "whole batched apply (graph of phase launches)", "bound": "hbm",
                      "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -465,6 +466,12 @@ def main():
 
     pl = ibf.Plan.from_problem(P)
     torch.cuda.synchronize()
+    # the first build in a process also loads the library's GPU code and warms
+    # the allocator; it is reported apart, and the factorization is built
+    # again from scratch for the build time
+    t0 = time.perf_counter()
+    pl.build()
+    build_first_ms = (time.perf_counter() - t0) * 1e3
     t0 = time.perf_counter()
     pl.build()
     build_wall_ms = (time.perf_counter() - t0) * 1e3
@@ -551,6 +558,7 @@ def main():
                    "leaf": P.leaf, "phase": P.phase, "parallelism": "single-gpu"},
         "build_ms": round(q["build_ms"], 3),
         "build_wall_ms": round(build_wall_ms, 3),
+        "build_first_in_process_ms": round(build_first_ms, 3),
         "tuning": tuning,
         "ranks": q["rank"],
         "R_comp": round(q["R_comp"], 4),

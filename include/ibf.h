@@ -186,6 +186,23 @@ int ibf_plan(const ibf_desc* desc, ibf_plan_t* out);
 int ibf_build(ibf_plan_t plan, void* hip_stream);
 
 /*
+ * Build `count` plans of one device concurrently (the problems of a batch,
+ * ibf_batch_create): `hip_stream` is synchronised first (work the builds
+ * depend on, such as predictor parameters), then `nthreads` host threads
+ * (<= 0: 8; at most 64) each create a non-blocking HIP stream of their own
+ * and run ibf_build on the plans in turn (each build as above, with its
+ * stream).  Every build has finished when the call returns.  `plans` is a
+ * host array of distinct plans owned by the caller.  On the first failure
+ * the workers take no further plans; the call returns that error, its
+ * message is ibf_last_error() on the calling thread and `*failed` (if not
+ * NULL) is the index of the failed plan (-1 otherwise).  Plans not reached
+ * keep their previous state.  Errors: INVALID_ARG (no or null plans, a plan
+ * twice, plans on different devices), DEVICE, and those of ibf_build.
+ */
+int ibf_build_batch(ibf_plan_t* plans, int count, int nthreads, void* hip_stream,
+                    int* failed);
+
+/*
  * u = K_IBF g for nrhs right-hand sides.  g (device, read) and u (device,
  * written) are column-major, n_xi x nrhs and n_x x nrhs, leading dimensions
  * ldg >= n_xi and ldu >= n_x, in the caller's point order, complex

@@ -12,7 +12,9 @@
 #include <cstring>
 #include <numeric>
 
+#include <atomic>
 #include <mutex>
+#include <thread>
 #include <unordered_map>
 
 #include "ibf_internal.h"
@@ -289,6 +291,71 @@ int ibf_build(ibf_plan_t p, void* stream) {
   auto t1 = std::chrono::steady_clock::now();
   p->build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   return rc;
+}
+
+int ibf_build_batch(ibf_plan_t* plans, int count, int nthreads, void* stream, int* failed) {
+  if (failed) *failed = -1;
+  if (!plans || count < 1) return fail(IBF_ERR_INVALID_ARG, "ibf_build_batch: no plans");
+  for (int i = 0; i < count; ++i)
+    if (!plans[i]) return fail(IBF_ERR_INVALID_ARG, "ibf_build_batch: null plan");
+  const int dev = plans[0]->device;
+  for (int i = 1; i < count; ++i)
+    if (plans[i]->device != dev)
+      return fail(IBF_ERR_INVALID_ARG, "ibf_build_batch: plans on different devices");
+  for (int i = 0; i < count; ++i)
+    for (int j = 0; j < i; ++j)
+      if (plans[i] == plans[j]) return fail(IBF_ERR_INVALID_ARG, "ibf_build_batch: a plan twice");
+  const int nt = std::max(1, std::min(count, nthreads > 0 ? std::min(nthreads, 64) : 8));
+  // the caller's earlier work (inputs, predictor parameters) first
+  {
+    const hipError_t e = hipSetDevice(dev);
+    if (e != hipSuccess) return fail(IBF_ERR_DEVICE, std::string("ibf_build_batch: ") + hipGetErrorString(e));
+    const hipError_t e2 = hipStreamSynchronize((hipStream_t)stream);
+    if (e2 != hipSuccess) return fail(IBF_ERR_DEVICE, std::string("ibf_build_batch: ") + hipGetErrorString(e2));
+  }
+  std::atomic<int> next{0};
+  std::atomic<bool> stop{false};
+  std::mutex mu;
+  int err_rc = IBF_OK, err_at = -1;
+  std::string err_msg;
+  auto worker = [&]() {
+    hipStream_t st = nullptr;
+    if (hipSetDevice(dev) != hipSuccess ||
+        hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      std::lock_guard<std::mutex> g(mu);
+      if (err_rc == IBF_OK) {
+        err_rc = IBF_ERR_DEVICE;
+        err_msg = "ibf_build_batch: cannot create a worker stream";
+      }
+      stop = true;
+      return;
+    }
+    while (!stop) {
+      const int i = next.fetch_add(1);
+      if (i >= count) break;
+      const int rc = ibf_build(plans[i], st);
+      if (rc != IBF_OK) {
+        std::lock_guard<std::mutex> g(mu);
+        if (err_rc == IBF_OK || i < err_at) {
+          err_rc = rc;
+          err_at = i;
+          err_msg = g_last_error;
+        }
+        stop = true;
+      }
+    }
+    hipStreamSynchronize(st);
+    hipStreamDestroy(st);
+  };
+  std::vector<std::thread> pool;
+  pool.reserve(nt);
+  for (int t = 0; t < nt; ++t) pool.emplace_back(worker);
+  for (auto& t : pool) t.join();
+  if (err_rc != IBF_OK) {
+    if (failed) *failed = err_at;
+    return fail(err_rc, err_msg);
+  }
+  return IBF_OK;
 }
 
 int ibf_apply(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu,

@@ -25,7 +25,8 @@ EXPORTED = ["ibf_plan", "ibf_build", "ibf_apply", "ibf_apply_profile", "ibf_quer
             "ibf_apply_batch", "ibf_batch_destroy", "ibf_dense_apply", "ibf_mlp_n_params",
             "ibf_mlp_features", "ibf_mlp_forward", "ibf_mlp_grad_work", "ibf_mlp_loss_grad",
             "ibf_mlp_adam", "ibf_mlp_select", "ibf_tune", "ibf_set_tuning", "ibf_set_allocator",
-            "ibf_measure_peak", "ibf_apply_adjoint", "ibf_rel_error", "ibf_apply_noalloc"]
+            "ibf_measure_peak", "ibf_apply_adjoint", "ibf_rel_error", "ibf_apply_noalloc",
+            "ibf_build_batch"]
 MLP_FEATURES = 5
 PATHS = ["default", "vector", "mfma", "tight"]      # ibf_tuning.path
 BATCH_GRAPH = 1
@@ -128,6 +129,8 @@ def load(path: str = LIB_PATH):
                                     C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
                                     C.POINTER(C.c_int64), C.c_int, C.c_void_p]
     lib.ibf_batch_destroy.argtypes = [C.c_void_p]
+    lib.ibf_build_batch.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_void_p,
+                                    C.POINTER(C.c_int)]
     vp, i64, f32 = C.c_void_p, C.c_int64, C.c_float
     lib.ibf_dense_apply.argtypes = [C.c_int, C.POINTER(C.c_double), C.c_int, vp, i64, vp, i64,
                                     vp, i64, vp, i64, i64, vp]
@@ -191,6 +194,19 @@ def use_torch_allocator(enable: bool = True):
 
 
 PEAK_HBM_COPY, PEAK_MFMA_F32 = 0, 1
+
+
+def build_batch(plans, nthreads: int = 0, stream=None):
+    """ibf_build_batch: build the plans concurrently on worker streams.
+    Returns the plans; raises IBFError naming the failed plan's index."""
+    lib = load()
+    arr = (C.c_void_p * len(plans))(*[pl.handle for pl in plans])
+    failed = C.c_int(-1)
+    rc = lib.ibf_build_batch(arr, len(plans), int(nthreads), _stream_handle(stream),
+                             C.byref(failed))
+    if rc != IBF_OK:
+        raise IBFError(rc, f"plan {failed.value}: {last_error()}")
+    return plans
 
 
 def measure_peak(what: int, stream=None) -> float:

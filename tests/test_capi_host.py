@@ -218,3 +218,18 @@ def test_rel_error_validates_on_the_host():
     ptr = C.c_void_p(buf.ctypes.data)
     assert lib.ibf_rel_error(ptr, 2, ptr, 4, 4, 1, 0, out, None) == -1     # ldu < n
     assert lib.ibf_rel_error(ptr, 4, ptr, 4, 4, 0, 0, out, None) == -1     # nrhs < 1
+
+
+def test_build_batch_validates_on_the_host():
+    """ibf_build_batch rejects bad plan lists before any device call."""
+    lib = ibf.load()
+    pl = _plan()
+    failed = C.c_int(7)
+    twice = (C.c_void_p * 2)(pl.handle, pl.handle)
+    assert lib.ibf_build_batch(twice, 2, 0, None, C.byref(failed)) == -1
+    assert failed.value == -1 and "twice" in ibf.last_error()
+    assert lib.ibf_build_batch(twice, 0, 0, None, None) == -1
+    assert lib.ibf_build_batch(None, 2, 0, None, None) == -1
+    holes = (C.c_void_p * 2)(pl.handle, None)
+    assert lib.ibf_build_batch(holes, 2, 0, None, None) == -1
+    pl.destroy()

@@ -158,3 +158,32 @@ def test_batch_mixed_installed_schedules(torch_dev):
     B.destroy()
     for pl in plans:
         pl.destroy()
+
+
+def test_concurrent_build_matches_sequential(torch_dev, built):
+    """ibf_build_batch (worker threads, one stream each) builds the same
+    factorizations as one-at-a-time builds: identical ranks, entry counts and
+    applied outputs (the builds are deterministic), on 3 worker threads for
+    the 12 plans so that each thread builds several."""
+    from paper_1605_03616_amd import ibf
+    torch = torch_dev
+    probs, plans, gs, ref = built
+    _say("concurrent build of the batch's plans")
+    twins = [ibf.Plan.from_problem(P) for P in probs]
+    ibf.build_batch(twins, nthreads=3)
+    for i, (a, b) in enumerate(zip(plans, twins)):
+        qa, qb = a.query(), b.query()
+        assert (qa["rank"], qa["nnz_opt"], qa["nnz_prelim"]) == \
+            (qb["rank"], qb["nnz_opt"], qb["nnz_prelim"]), i
+    outs = [pl.apply(g) for pl, g in zip(twins, gs)]
+    torch.cuda.synchronize()
+    for i, (u, r) in enumerate(zip(outs, ref)):
+        assert np.array_equal(u.cpu().numpy(), r), i
+    # rebuilding some of them again in one call (the previous factors are freed)
+    ibf.build_batch(twins[:5], nthreads=8)
+    outs = [pl.apply(g) for pl, g in zip(twins[:5], gs[:5])]
+    torch.cuda.synchronize()
+    for i, (u, r) in enumerate(zip(outs, ref[:5])):
+        assert np.array_equal(u.cpu().numpy(), r), i
+    for pl in twins:
+        pl.destroy()
