@@ -120,12 +120,29 @@ __device__ inline double lagrange_t(const double* z, int r, int t, double y) {
 
 // ---------------------------------------------------------------------------
 // Group reductions over G lanes (G a power of two, groups aligned in the
-// wavefront).  The xor butterfly leaves bitwise-identical sums in every lane.
+// wavefront, every lane of a group active).  Within a row of 16 lanes the
+// partners come from DPP lane moves (quad permutes [1,0,3,2] and [2,3,0,1],
+// the half-row and row mirrors), across rows from lane shuffles.  Every
+// step pairs each lane with a partner that pairs back with it, so both add
+// the same two values: the sums are bitwise identical in every lane of the
+// group (the rotation decisions of a Jacobi sweep depend on it).
 // ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned long long)(unsigned)lo));
+}
 template <int G>
 __device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-  for (int m = G / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, G);
+  if constexpr (G >= 2) v += dpp_move<0xB1>(v);               // quad_perm [1,0,3,2]
+  if constexpr (G >= 4) v += dpp_move<0x4E>(v);               // quad_perm [2,3,0,1]
+  if constexpr (G >= 8) v += dpp_move<0x141>(v);              // row_half_mirror
+  if constexpr (G >= 16) v += dpp_move<0x140>(v);             // row_mirror
+  if constexpr (G >= 32) v += __shfl_xor(v, 16, G);
+  if constexpr (G >= 64) v += __shfl_xor(v, 32, G);
   return v;
 }
 
