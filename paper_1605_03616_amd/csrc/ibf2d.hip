@@ -620,6 +620,330 @@ __global__ __launch_bounds__(kB2) void k2_sweep_h(BoxDev B, int l, const double*
   }
 }
 
+// ---------------------------------------------------------------------------
+// Build kernels for 36, 49 or 64 tensor grid points (r = 6, 7, 8).  The
+// arithmetic is that of the kernels above (streaming Givens QR of W^*, then
+// one-sided Jacobi on R^*, rows on the 64 lanes of a wave, one pair a wave),
+// but the triangular factor R (row J in LDS row J, lane = column) and then
+// the columns of R^* live in LDS, and the Givens folds and the Jacobi
+// rotations run as loops: in registers they would need R2 rows of R2
+// complex values a lane and R2 (R2 - 1) / 2 unrolled rotations.  A block
+// holds NW waves (pairs) and NW (64 R2 complex + R2 real) values of LDS;
+// the child -> parent Lagrange table is read from memory (it would not fit
+// beside the factors).
+// ---------------------------------------------------------------------------
+constexpr int kWaveL = 64;
+
+__device__ __forceinline__ double rl_d(double v, int j) {        // lane j's v (j uniform)
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, j);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), j);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double2 rl2(double2 v, int j) { return make_double2(rl_d(v.x, j), rl_d(v.y, j)); }
+
+// givens_fold with R's rows in LDS (rr points at row 0, this lane's column;
+// rows are kWaveL entries apart)
+template <int R2>
+__device__ __forceinline__ void givens_fold_l(double2* rr, double2& a) {
+#pragma unroll 2
+  for (int J = 0; J < R2; ++J) {
+    const double2 rj = rr[J * kWaveL];
+    const double2 x = rl2(rj, J), y = rl2(a, J);
+    const double ax2 = x.x * x.x + x.y * x.y, ay2 = y.x * y.x + y.y * y.y;
+    const double ax = sqrt(ax2), nu = sqrt(ax2 + ay2);
+    const double inv = nu > 0.0 ? 1.0 / nu : 0.0;
+    const double c = nu > 0.0 ? ax * inv : 1.0;
+    const double2 ph = ax > 0.0 ? make_double2(x.x / ax, x.y / ax) : make_double2(1.0, 0.0);
+    const double2 sv = cscale(cmul(ph, conjd(y)), inv);
+    rr[J * kWaveL] = cadd(cscale(rj, c), cmul(sv, a));
+    a = cadd(cscale(a, c), cscale(cmul(conjd(sv), rj), -1.0));
+  }
+}
+
+// jacobi_eig with the columns in LDS (col j at gm[j kWaveL], this lane's
+// row) and their squared norms in nl[j] (the same in every lane)
+template <int R2>
+__device__ __forceinline__ void jacobi_eig_l(double2* gm, double* nl, double (&lam)[R2]) {
+  const double thresh = 4.0 * (double)(R2 > 8 ? R2 : 8) * 1.1102230246251565e-16;
+  auto norms = [&]() {
+    for (int j = 0; j < R2; ++j) {
+      const double2 v = gm[j * kWaveL];
+      nl[j] = group_sum<kWaveL>(v.x * v.x + v.y * v.y);
+    }
+  };
+  norms();
+  double fro2 = 0.0;
+  for (int j = 0; j < R2; ++j) fro2 += nl[j];
+  const double small = 1e-30 * fro2;
+  for (int sweep = 0; sweep < kJacobiMaxSweeps; ++sweep) {
+    bool rotated = false;
+    for (int p = 0; p < R2 - 1; ++p) {
+      double2 ap = gm[p * kWaveL];
+      double np = nl[p];
+      for (int q = p + 1; q < R2; ++q) {
+        double2 aq = gm[q * kWaveL];
+        double nq = nl[q];
+        jrot<kWaveL>(ap, aq, np, nq, thresh, small, rotated);
+        gm[q * kWaveL] = aq;
+        nl[q] = nq;
+      }
+      gm[p * kWaveL] = ap;
+      nl[p] = np;
+    }
+    norms();
+    if (!__any(rotated)) break;
+  }
+#pragma unroll
+  for (int j = 0; j < R2; ++j) lam[j] = sqrt(nl[j]);
+}
+
+// LDS of one wave: [R2][kWaveL] complex, then R2 norms
+template <int R2>
+constexpr size_t k2l_wave_lds() { return (size_t)R2 * kWaveL * sizeof(double2) + R2 * sizeof(double); }
+
+#define IBF2L_WAVE_INDEX                                                        \
+  extern __shared__ __align__(16) unsigned char smem2l[];                       \
+  const int lane = threadIdx.x & (kWaveL - 1);                                  \
+  const int wv = threadIdx.x / kWaveL;                                          \
+  const int64_t p = (int64_t)blockIdx.x * (blockDim.x / kWaveL) + wv;           \
+  if (p >= npairs) return;                                                      \
+  const bool row = lane < R2;                                                   \
+  double2* gm = reinterpret_cast<double2*>(smem2l + wv * k2l_wave_lds<R2>()) + lane; \
+  double* nl = reinterpret_cast<double*>(smem2l + wv * k2l_wave_lds<R2>() +     \
+                                         (size_t)R2 * kWaveL * sizeof(double2));  \
+  for (int j = 0; j < R2; ++j) gm[j * kWaveL] = make_double2(0.0, 0.0);
+
+template <int R2>
+__global__ __launch_bounds__(256) void k2l_middle(BoxDev B, const double* __restrict__ z,
+                                                  double2* __restrict__ Cb,
+                                                  double2* __restrict__ Rb,
+                                                  int* __restrict__ rank, int* __restrict__ kmax,
+                                                  unsigned long long* __restrict__ nnz,
+                                                  int64_t npairs, double tol) {
+  IBF2L_WAVE_INDEX
+  const int r = B.r, L = B.L, h = B.h;
+  const int64_t a = p >> (2 * (L - h)), b = p & (((int64_t)1 << (2 * (L - h))) - 1);
+  double ca1, ca2, cb1, cb2;
+  cx2(h, a, ca1, ca2);
+  cxi2(B, L - h, b, cb1, cb2);
+  const double wa = ldexp(1.0, -h), wb = B.w / ldexp(1.0, L - h);
+  const int tl = row ? lane : 0;
+  const double ga1 = gpt(ca1, wa, z[tl / r]), ga2 = gpt(ca2, wa, z[tl % r]);
+  for (int s = 0; s < R2; ++s) {
+    const double2 w = row ? kval2(B.ph, ga1, ga2, gpt(cb1, wb, z[s / r]), gpt(cb2, wb, z[s % r]))
+                          : make_double2(0.0, 0.0);
+    double2 av = conjd(w);
+    givens_fold_l<R2>(gm, av);
+  }
+  for (int j = 0; j < R2; ++j) gm[j * kWaveL] = conjd(gm[j * kWaveL]);
+  double sig[R2];
+  jacobi_eig_l<R2>(gm, nl, sig);
+  int pos[R2];
+  const int k = rank_positions<R2>(sig, tol, pos);
+  double2* crow = Cb + (p * R2 + tl) * R2;
+#pragma unroll
+  for (int j = 0; j < R2; ++j) {
+    const bool keep = pos[j] < k && sig[j] > 0.0;
+    const double sc = keep ? 1.0 / sqrt(sig[j]) : 0.0;
+    if (row) crow[pos[j]] = cscale(gm[j * kWaveL], sc);
+  }
+  const int my_pos = sel<R2>(pos, tl);
+  const double my_sig = sel<R2>(sig, tl);
+  const double my_sc = (my_pos < k && my_sig > 0.0) ? pow(my_sig, -1.5) : 0.0;
+  for (int s = 0; s < R2; ++s) {
+    const double2 mts = row ? kval2(B.ph, ga1, ga2, gpt(cb1, wb, z[s / r]), gpt(cb2, wb, z[s % r]))
+                            : make_double2(0.0, 0.0);
+    double2 mine = make_double2(0.0, 0.0);
+    for (int j = 0; j < R2; ++j) {
+      const double2 v = csum<kWaveL>(cmul(conjd(mts), gm[j * kWaveL]));
+      if (lane == j) mine = v;
+    }
+    if (row) Rb[(p * R2 + s) * R2 + my_pos] = cscale(mine, my_sc);
+  }
+  if (lane == 0) {
+    rank[p] = k;
+    atomicMax(kmax, k);
+    atomicAdd(nnz, (unsigned long long)k);
+  }
+}
+
+template <int R2>
+__global__ __launch_bounds__(256) void k2l_sweep_g(BoxDev B, int l, const double* __restrict__ z,
+                                                   const double* __restrict__ lc,
+                                                   const double2* __restrict__ Cprev,
+                                                   const int* __restrict__ rprev,
+                                                   double2* __restrict__ Cout,
+                                                   int* __restrict__ rout, int* __restrict__ kmax,
+                                                   double2* __restrict__ stage,
+                                                   unsigned long long* __restrict__ nnz,
+                                                   int64_t npairs, double tol) {
+  IBF2L_WAVE_INDEX
+  const int r = B.r, L = B.L;
+  const int sh = 2 * (L - l);
+  const int64_t a = p >> sh, b = p & (((int64_t)1 << sh) - 1);
+  const int64_t par = a >> 2;
+  const int alpha = (int)(a & 3);
+  const int64_t pin0 = (par << (sh + 2)) + 4 * b;
+  double ca1, ca2, cp1, cp2;
+  cx2(l, a, ca1, ca2);
+  cx2(l - 1, par, cp1, cp2);
+  const double wa = ldexp(1.0, -l), wp = ldexp(1.0, -(l - 1));
+  const int tl = row ? lane : 0;
+  const double ga1 = gpt(ca1, wa, z[tl / r]), ga2 = gpt(ca2, wa, z[tl % r]);
+  const double gp1 = gpt(cp1, wp, z[tl / r]), gp2 = gpt(cp2, wp, z[tl % r]);
+  const double* la = lc + alpha * R2 * R2;               // la[s * R2 + t] = M^P_s(g^A_t)
+  int kin[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) kin[c] = rprev[pin0 + c];
+  auto wcol = [&](int c, int m, double2 at, double2 bs) -> double2 {
+    const double2* cs = Cprev + (pin0 + c) * R2 * R2 + m;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int s = 0; s < R2; ++s)
+      cfma(acc, cscale(rl2(bs, s), la[s * R2 + tl]), cs[s * R2]);
+    return row ? cmul(at, acc) : make_double2(0.0, 0.0);
+  };
+  double2 at[4], bs[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double cc1, cc2;
+    cxi2(B, L - l + 1, 4 * b + c, cc1, cc2);
+    at[c] = kval2(B.ph, ga1, ga2, cc1, cc2);
+    bs[c] = conjd(kval2(B.ph, gp1, gp2, cc1, cc2));
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    for (int m = 0; m < kin[c]; ++m) {
+      double2 av = conjd(wcol(c, m, at[c], bs[c]));
+      givens_fold_l<R2>(gm, av);
+    }
+  for (int j = 0; j < R2; ++j) gm[j * kWaveL] = conjd(gm[j * kWaveL]);
+  double sig[R2];
+  jacobi_eig_l<R2>(gm, nl, sig);
+  int pos[R2];
+  const int k = rank_positions<R2>(sig, tol, pos);
+  double2* crow = Cout + (p * R2 + tl) * R2;
+#pragma unroll
+  for (int j = 0; j < R2; ++j) {
+    const bool keep = pos[j] < k && sig[j] > 0.0;
+    if (row) crow[pos[j]] = keep ? gm[j * kWaveL] : make_double2(0.0, 0.0);
+  }
+  const int my_pos = sel<R2>(pos, tl);
+  const double my_sig = sel<R2>(sig, tl);
+  const double my_sc = (my_pos < k && my_sig > 0.0) ? 1.0 / (my_sig * my_sig) : 0.0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double2* st = stage + (p * 4 + c) * R2 * R2;
+    for (int m = 0; m < R2; ++m) {
+      if (m < kin[c]) {
+        const double2 w = wcol(c, m, at[c], bs[c]);
+        double2 mine = make_double2(0.0, 0.0);
+        for (int j = 0; j < R2; ++j) {
+          const double2 v = csum<kWaveL>(cmul(conjd(gm[j * kWaveL]), w));
+          if (lane == j) mine = v;
+        }
+        if (row) st[my_pos * R2 + m] = cscale(mine, my_sc);
+      } else if (row) {
+        st[tl * R2 + m] = make_double2(0.0, 0.0);
+      }
+    }
+  }
+  if (lane == 0) {
+    rout[p] = k;
+    atomicMax(kmax, k);
+    atomicAdd(nnz, (unsigned long long)k * (kin[0] + kin[1] + kin[2] + kin[3]));
+  }
+}
+
+template <int R2>
+__global__ __launch_bounds__(256) void k2l_sweep_h(BoxDev B, int l, const double* __restrict__ z,
+                                                   const double* __restrict__ lc,
+                                                   const double2* __restrict__ Rcur,
+                                                   const int* __restrict__ rcur,
+                                                   double2* __restrict__ Rnext,
+                                                   int* __restrict__ rnext, int* __restrict__ kmax,
+                                                   double2* __restrict__ stage,
+                                                   unsigned long long* __restrict__ nnz,
+                                                   int64_t npairs, double tol) {
+  IBF2L_WAVE_INDEX
+  const int r = B.r, L = B.L;
+  const int shq = 2 * (L - l + 1);
+  const int64_t q = p;
+  const int64_t P = q >> shq, C = q & (((int64_t)1 << shq) - 1);
+  const int64_t Bb = C >> 2;
+  const int c = (int)(C & 3);
+  double cc1, cc2, cb1, cb2;
+  cxi2(B, L - l + 1, C, cc1, cc2);
+  cxi2(B, L - l, Bb, cb1, cb2);
+  const double wc = B.w / ldexp(1.0, L - l + 1), wb = B.w / ldexp(1.0, L - l);
+  const int sl = row ? lane : 0;
+  const double gc1 = gpt(cc1, wc, z[sl / r]), gc2 = gpt(cc2, wc, z[sl % r]);
+  const double gb1 = gpt(cb1, wb, z[sl / r]), gb2 = gpt(cb2, wb, z[sl % r]);
+  const double* lcc = lc + c * R2 * R2;                  // lcc[t * R2 + s] = M^B_t(g^C_s)
+  int64_t pout[4];
+  int kout[4];
+  double2 ds[4], et[4];
+#pragma unroll
+  for (int al = 0; al < 4; ++al) {
+    const int64_t A = 4 * P + al;
+    pout[al] = (A << (2 * (L - l))) + Bb;
+    kout[al] = rcur[pout[al]];
+    double ca1, ca2;
+    cx2(l, A, ca1, ca2);
+    ds[al] = conjd(kval2(B.ph, ca1, ca2, gc1, gc2));
+    et[al] = kval2(B.ph, ca1, ca2, gb1, gb2);
+  }
+  auto zcol = [&](int al, int m) -> double2 {
+    const double2* rs = Rcur + pout[al] * R2 * R2 + m;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int t = 0; t < R2; ++t)
+      cfma(acc, cscale(rl2(et[al], t), lcc[t * R2 + sl]), rs[t * R2]);
+    return row ? cmul(ds[al], acc) : make_double2(0.0, 0.0);
+  };
+#pragma unroll
+  for (int al = 0; al < 4; ++al)
+    for (int m = 0; m < kout[al]; ++m) {
+      double2 av = conjd(zcol(al, m));
+      givens_fold_l<R2>(gm, av);
+    }
+  for (int j = 0; j < R2; ++j) gm[j * kWaveL] = conjd(gm[j * kWaveL]);
+  double sig[R2];
+  jacobi_eig_l<R2>(gm, nl, sig);
+  int pos[R2];
+  const int k = rank_positions<R2>(sig, tol, pos);
+  double2* rrow = Rnext + (q * R2 + sl) * R2;
+#pragma unroll
+  for (int j = 0; j < R2; ++j) {
+    const bool keep = pos[j] < k && sig[j] > 0.0;
+    if (row) rrow[pos[j]] = keep ? gm[j * kWaveL] : make_double2(0.0, 0.0);
+  }
+  const int my_pos = sel<R2>(pos, sl);
+  const double my_sig = sel<R2>(sig, sl);
+  const double my_sc = (my_pos < k && my_sig > 0.0) ? 1.0 / (my_sig * my_sig) : 0.0;
+#pragma unroll
+  for (int al = 0; al < 4; ++al) {
+    double2* st = stage + (pout[al] * 4 + c) * R2 * R2;
+    for (int m = 0; m < R2; ++m) {
+      if (m < kout[al]) {
+        const double2 w = zcol(al, m);
+        double2 mine = make_double2(0.0, 0.0);
+        for (int j = 0; j < R2; ++j) {
+          const double2 v = csum<kWaveL>(cmul(conjd(gm[j * kWaveL]), w));
+          if (lane == j) mine = v;
+        }
+        if (row) st[m * R2 + my_pos] = cscale(conjd(mine), my_sc);
+      } else if (row) {
+        st[m * R2 + sl] = make_double2(0.0, 0.0);
+      }
+    }
+  }
+  if (lane == 0) {
+    rnext[q] = k;
+    atomicMax(kmax, k);
+    atomicAdd(nnz, (unsigned long long)k * (kout[0] + kout[1] + kout[2] + kout[3]));
+  }
+}
+
 // stored[p][c kin + s][t < kld] from stage[p][c][t][s] (FP64, R2 x R2 per child)
 template <typename FT>
 __global__ void k2_pack_stage(const double2* __restrict__ stage, FT* __restrict__ out,
@@ -1108,8 +1432,30 @@ namespace {
     case 4: LAUNCH(4); break;                              \
     case 9: LAUNCH(9); break;                              \
     case 16: LAUNCH(16); break;                            \
+    case 25: LAUNCH(25); break;                            \
+    case 36: LAUNCH(36); break;                            \
+    case 49: LAUNCH(49); break;                            \
+    default: LAUNCH(64); break;                            \
+  }
+// register-resident compression kernels (r <= 5) / LDS-resident ones (r = 6 .. 8)
+#define IBF2_DISPATCH_SMALL(R2V, LAUNCH)                   \
+  switch (R2V) {                                           \
+    case 4: LAUNCH(4); break;                              \
+    case 9: LAUNCH(9); break;                              \
+    case 16: LAUNCH(16); break;                            \
     default: LAUNCH(25); break;                            \
   }
+#define IBF2_DISPATCH_BIG(R2V, LAUNCH)                     \
+  switch (R2V) {                                           \
+    case 36: LAUNCH(36); break;                            \
+    case 49: LAUNCH(49); break;                            \
+    default: LAUNCH(64); break;                            \
+  }
+// pairs (waves) a block of the LDS-resident kernels: as many as 160 KiB hold, at most 4
+inline int k2l_waves(int R2) {
+  const size_t per = (size_t)R2 * kWaveL * sizeof(double2) + R2 * sizeof(double);
+  return (int)std::max<size_t>(1, std::min<size_t>(4, (160u << 10) / per));
+}
 
 int64_t morton_host(int64_t i1, int64_t i2, int level) {
   int64_t code = 0;
@@ -1244,11 +1590,23 @@ int build2d_t(ibf_plan_t p, hipStream_t s) {
     std::vector<int> kg(L + 1, 0), kh(L + 1, 0);
     IBF_HIP_CHECK(hipMemsetAsync(S.kmax, 0, sizeof(int) * 128, s));
     IBF_HIP_CHECK(hipMemsetAsync(S.nnz, 0, sizeof(unsigned long long), s));
+    const bool big = R2 > 25;
+    const int nwl = k2l_waves(R2);
+    const unsigned ggl = (unsigned)((np + nwl - 1) / nwl);
+    const size_t ldsl = (size_t)nwl * ((size_t)R2 * kWaveL * sizeof(double2) + R2 * sizeof(double));
 #define IBF2_MIDDLE(RR)                                                                          \
   hipLaunchKernelGGL((k2_middle<RR>), dim3(gg), dim3(kB2), 0, s, B, M.d_z, S.C[0], S.R[0],      \
                      S.rc[0], S.kmax + h, S.nnz, np, M.tol)
-    IBF2_DISPATCH_R2(R2, IBF2_MIDDLE);
+#define IBF2L_MIDDLE(RR)                                                                         \
+  hipLaunchKernelGGL((k2l_middle<RR>), dim3(ggl), dim3(kWaveL * nwl), ldsl, s, B, M.d_z, S.C[0], \
+                     S.R[0], S.rc[0], S.kmax + h, S.nnz, np, M.tol)
+    if (big) {
+      IBF2_DISPATCH_BIG(R2, IBF2L_MIDDLE);
+    } else {
+      IBF2_DISPATCH_SMALL(R2, IBF2_MIDDLE);
+    }
 #undef IBF2_MIDDLE
+#undef IBF2L_MIDDLE
     IBF_HIP_CHECK(hipGetLastError());
     IBF_HIP_CHECK(hipMemcpyAsync(S.rr[0], S.rc[0], sizeof(int) * np, hipMemcpyDeviceToDevice, s));
     if ((rc = read_int(S.kmax + h, &kg[h], s))) return rc;
@@ -1260,8 +1618,17 @@ int build2d_t(ibf_plan_t p, hipStream_t s) {
 #define IBF2_SWG(RR)                                                                             \
   hipLaunchKernelGGL((k2_sweep_g<RR>), dim3(gg), dim3(kB2), 0, s, B, l, M.d_z, M.d_lc, S.C[cc], \
                      S.rc[cc], S.C[cc ^ 1], S.rc[cc ^ 1], S.kmax + l, S.stage, S.nnz, np, M.tol)
-      IBF2_DISPATCH_R2(R2, IBF2_SWG);
+#define IBF2L_SWG(RR)                                                                            \
+  hipLaunchKernelGGL((k2l_sweep_g<RR>), dim3(ggl), dim3(kWaveL * nwl), ldsl, s, B, l, M.d_z,     \
+                     M.d_lc, S.C[cc], S.rc[cc], S.C[cc ^ 1], S.rc[cc ^ 1], S.kmax + l, S.stage,  \
+                     S.nnz, np, M.tol)
+      if (big) {
+        IBF2_DISPATCH_BIG(R2, IBF2L_SWG);
+      } else {
+        IBF2_DISPATCH_SMALL(R2, IBF2_SWG);
+      }
 #undef IBF2_SWG
+#undef IBF2L_SWG
       IBF_HIP_CHECK(hipGetLastError());
       if ((rc = read_int(S.kmax + l, &kg[l], s))) return rc;
       if ((rc = pack_stage<FT>(bx, M, S.stage, l, kg[l - 1], kg[l], s))) return rc;
@@ -1277,8 +1644,17 @@ int build2d_t(ibf_plan_t p, hipStream_t s) {
   hipLaunchKernelGGL((k2_sweep_h<RR>), dim3(gg), dim3(kB2), 0, s, B, l, M.d_z, M.d_lc, S.R[cr], \
                      S.rr[cr], S.R[cr ^ 1], S.rr[cr ^ 1], S.kmax + 64 + l - 1, S.stage, S.nnz, \
                      np, M.tol)
-      IBF2_DISPATCH_R2(R2, IBF2_SWH);
+#define IBF2L_SWH(RR)                                                                            \
+  hipLaunchKernelGGL((k2l_sweep_h<RR>), dim3(ggl), dim3(kWaveL * nwl), ldsl, s, B, l, M.d_z,     \
+                     M.d_lc, S.R[cr], S.rr[cr], S.R[cr ^ 1], S.rr[cr ^ 1], S.kmax + 64 + l - 1,  \
+                     S.stage, S.nnz, np, M.tol)
+      if (big) {
+        IBF2_DISPATCH_BIG(R2, IBF2L_SWH);
+      } else {
+        IBF2_DISPATCH_SMALL(R2, IBF2_SWH);
+      }
 #undef IBF2_SWH
+#undef IBF2L_SWH
       IBF_HIP_CHECK(hipGetLastError());
       if ((rc = read_int(S.kmax + 64 + l - 1, &kh[l - 1], s))) return rc;
       if ((rc = pack_stage<FT>(bx, M, S.stage, l, kh[l - 1], kh[l], s))) return rc;
@@ -1642,8 +2018,8 @@ int plan2d(const ibf_desc* d, ibf_plan_t* out) {
     set_error(msg);
     return IBF_ERR_INVALID_ARG;
   };
-  if (d->r < 2 || d->r > 5) {
-    set_error("ibf_plan: dim 2 supports r = 2 .. 5 (r^2 <= 25 grid points per box)");
+  if (d->r < 2 || d->r > 8) {
+    set_error("ibf_plan: dim 2 supports r = 2 .. 8 (r^2 <= 64 grid points per box)");
     return d->r < 2 ? IBF_ERR_INVALID_ARG : IBF_ERR_UNSUPPORTED;
   }
   if (!(d->tol > 0.0 && d->tol < 1.0)) return bad("ibf_plan: tol must lie in (0, 1)");
