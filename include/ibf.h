@@ -93,7 +93,8 @@ typedef struct ibf_plan_s* ibf_plan_t;
  * [-W/2, W/2)^2 with W = omega_width (a power of two >= 32, omega_lo = -W/2).  Omega is split into coronas of 12 dyadic boxes each, down to a
  * 16 x 16 centre square summed directly; every box runs its own quadtree IBF
  * with a tensor r x r Chebyshev grid.  phase_id IBF_PHASE_DFT, FIO2D or
- * SEPARABLE; 2 <= r <= 5 (r^2 grid rows on one 32-lane group); 0 < tol < 1
+ * SEPARABLE; 2 <= r <= 9 (r^2 <= 81 grid rows on the lanes of one wave, held
+ * in registers up to r = 5 and in LDS from r = 6); 0 < tol < 1
  * (each block is reduced by Givens QR and its triangular factor orthogonalised
  * by one-sided Jacobi, so singular values resolve to FP64 rounding); leaf is
  * the side of an Omega leaf box: 4, 16 or 64 points; no sweep-in, amplitude,
@@ -165,7 +166,7 @@ typedef struct {
  * Sec. 5) and size every buffer.  No device work.  Errors: INVALID_ARG if
  * n < leaf^2, tol outside (0,1), a point outside its domain, leaf not a power
  * of two, sweep_in outside -1..1, a bad amplitude or fixed_ranks entry count;
- * UNSUPPORTED for dim other than 1 or 2, r > 16 (r > 5 for dim 2), an unknown
+ * UNSUPPORTED for dim other than 1 or 2, r > 16 (r > 9 for dim 2), an unknown
  * phase or amplitude, or an option dim 2 does not provide.  On success *out
  * owns the plan.
  */

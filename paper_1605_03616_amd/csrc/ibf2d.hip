@@ -19,8 +19,9 @@
 // R^* is orthogonalised by one-sided Jacobi in FP64: W = R^* Q^*, so the left
 // singular vectors and singular values of W are those of R^*, accurate to
 // rounding in FP64 (no Gram matrix, whose eigenvalues would lose singular
-// values below about 1e-8 of the largest).  One 32-lane group per pair
-// (r^2 <= 25 grid points, r <= 5); rows on lanes.
+// values below about 1e-8 of the largest).  Rows on lanes: one 32-lane group
+// per pair in registers for r <= 5 (r^2 <= 25), one wave per pair with the
+// factor in LDS for r = 6 .. 9 (two rows a lane at r = 9).
 //
 // Kernels: k2_tables (Chebyshev nodes, tensor child->parent Lagrange
 // matrices), k2_middle (eq:KeqUMV), k2_sweep_g (eqn:GC), k2_sweep_h (eqn:HR),
@@ -621,18 +622,28 @@ __global__ __launch_bounds__(kB2) void k2_sweep_h(BoxDev B, int l, const double*
 }
 
 // ---------------------------------------------------------------------------
-// Build kernels for 36, 49 or 64 tensor grid points (r = 6, 7, 8).  The
-// arithmetic is that of the kernels above (streaming Givens QR of W^*, then
-// one-sided Jacobi on R^*, rows on the 64 lanes of a wave, one pair a wave),
-// but the triangular factor R (row J in LDS row J, lane = column) and then
-// the columns of R^* live in LDS, and the Givens folds and the Jacobi
-// rotations run as loops: in registers they would need R2 rows of R2
-// complex values a lane and R2 (R2 - 1) / 2 unrolled rotations.  A block
-// holds NW waves (pairs) and NW (64 R2 complex + R2 real) values of LDS;
-// the child -> parent Lagrange table is read from memory (it would not fit
-// beside the factors).
+// Build kernels for 36 to 81 tensor grid points (r = 6 .. 9).  The arithmetic
+// is that of the kernels above (streaming Givens QR of W^*, then one-sided
+// Jacobi on R^*, one pair a wave), but the triangular factor R and then the
+// columns of R^* live in LDS and the Givens folds and the Jacobi rotations
+// run as loops: in registers they would need R2 complex values a lane and
+// R2 (R2 - 1) / 2 unrolled rotations.  A lane holds the rows (and columns)
+// k = lane + 64 h, h < RPL (two for 81 points).  Entry (j, k) of a wave's
+// matrix is at LDS j S + k (S = 64, or R2 when a lane holds two); a block
+// holds NW waves (pairs) of R2 S complex + R2 real values each.  The child
+// -> parent Lagrange table is read from memory (it would not fit beside the
+// factors).
 // ---------------------------------------------------------------------------
 constexpr int kWaveL = 64;
+template <int R2>
+constexpr int k2l_rpl() { return R2 > kWaveL ? 2 : 1; }
+template <int R2>
+constexpr int k2l_stride() { return R2 > kWaveL ? R2 : kWaveL; }
+template <int R2>
+constexpr size_t k2l_wave_lds() {                                 // 16-byte aligned per wave
+  return ((size_t)R2 * k2l_stride<R2>() * sizeof(double2) + R2 * (sizeof(double) + sizeof(int)) +
+          15) & ~(size_t)15;
+}
 
 __device__ __forceinline__ double rl_d(double v, int j) {        // lane j's v (j uniform)
   const unsigned long long u = (unsigned long long)__double_as_longlong(v);
@@ -640,36 +651,104 @@ __device__ __forceinline__ double rl_d(double v, int j) {        // lane j's v (
   const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), j);
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
-__device__ __forceinline__ double2 rl2(double2 v, int j) { return make_double2(rl_d(v.x, j), rl_d(v.y, j)); }
+__device__ __forceinline__ double2 rl2(double2 v, int j) {
+  return make_double2(rl_d(v.x, j), rl_d(v.y, j));
+}
+// entry k (uniform) of a lane-distributed vector v[h] = component lane + 64 h
+template <int RPL>
+__device__ __forceinline__ double2 rl_k(const double2 (&v)[RPL], int k) {
+  return (RPL > 1 && k >= kWaveL) ? rl2(v[RPL - 1], k - kWaveL) : rl2(v[0], k);
+}
 
-// givens_fold with R's rows in LDS (rr points at row 0, this lane's column;
-// rows are kWaveL entries apart)
+// givens_fold with R's rows in LDS (gm: the wave's matrix; row J at J S)
 template <int R2>
-__device__ __forceinline__ void givens_fold_l(double2* rr, double2& a) {
+__device__ __forceinline__ void givens_fold_l(double2* gm, int lane,
+                                              double2 (&a)[k2l_rpl<R2>()]) {
+  constexpr int RPL = k2l_rpl<R2>(), S = k2l_stride<R2>();
 #pragma unroll 2
   for (int J = 0; J < R2; ++J) {
-    const double2 rj = rr[J * kWaveL];
-    const double2 x = rl2(rj, J), y = rl2(a, J);
+    double2 rj[RPL];
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) {
+      const int k = lane + kWaveL * h;
+      rj[h] = k < R2 ? gm[J * S + k] : make_double2(0.0, 0.0);
+    }
+    const double2 x = rl_k<RPL>(rj, J), y = rl_k<RPL>(a, J);
     const double ax2 = x.x * x.x + x.y * x.y, ay2 = y.x * y.x + y.y * y.y;
     const double ax = sqrt(ax2), nu = sqrt(ax2 + ay2);
     const double inv = nu > 0.0 ? 1.0 / nu : 0.0;
     const double c = nu > 0.0 ? ax * inv : 1.0;
     const double2 ph = ax > 0.0 ? make_double2(x.x / ax, x.y / ax) : make_double2(1.0, 0.0);
     const double2 sv = cscale(cmul(ph, conjd(y)), inv);
-    rr[J * kWaveL] = cadd(cscale(rj, c), cmul(sv, a));
-    a = cadd(cscale(a, c), cscale(cmul(conjd(sv), rj), -1.0));
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) {
+      const int k = lane + kWaveL * h;
+      if (k < R2) gm[J * S + k] = cadd(cscale(rj[h], c), cmul(sv, a[h]));
+      a[h] = cadd(cscale(a[h], c), cscale(cmul(conjd(sv), rj[h]), -1.0));
+    }
   }
 }
 
-// jacobi_eig with the columns in LDS (col j at gm[j kWaveL], this lane's
-// row) and their squared norms in nl[j] (the same in every lane)
+// Complex Jacobi rotation of columns (p, q) whose rows are spread RPL a lane
+template <int RPL>
+__device__ __forceinline__ void jrot_l(double2 (&ap_)[RPL], double2 (&aq_)[RPL], double& np_,
+                                       double& nq_, double thresh, double small, bool& rotated) {
+  double pr = 0.0, pi = 0.0;
+#pragma unroll
+  for (int h = 0; h < RPL; ++h) {
+    pr += ap_[h].x * aq_[h].x + ap_[h].y * aq_[h].y;
+    pi += ap_[h].x * aq_[h].y - ap_[h].y * aq_[h].x;
+  }
+  const double gr = group_sum<kWaveL>(pr);
+  const double gi = group_sum<kWaveL>(pi);
+  const double ag = sqrt(gr * gr + gi * gi);
+  if (np_ > small && nq_ > small && ag > thresh * sqrt(np_ * nq_)) {
+    const double zeta = (nq_ - np_) / (2.0 * ag);
+    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    const double c = 1.0 / sqrt(1.0 + t * t);
+    const double s = c * t;
+    const double2 e = make_double2(gr / ag, -gi / ag);
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) {
+      const double2 eq = cmul(e, aq_[h]);
+      const double2 ap = ap_[h];
+      ap_[h] = make_double2(c * ap.x - s * eq.x, c * ap.y - s * eq.y);
+      aq_[h] = make_double2(s * ap.x + c * eq.x, s * ap.y + c * eq.y);
+    }
+    np_ -= t * ag;
+    nq_ += t * ag;
+    rotated = true;
+  }
+}
+
+// jacobi_eig with the columns in LDS (column j at gm[j S + k], row k) and
+// their squared norms in nl[j] (the same in every lane)
 template <int R2>
-__device__ __forceinline__ void jacobi_eig_l(double2* gm, double* nl, double (&lam)[R2]) {
+__device__ __forceinline__ void jacobi_eig_l(double2* gm, double* nl, int lane) {
+  constexpr int RPL = k2l_rpl<R2>(), S = k2l_stride<R2>();
   const double thresh = 4.0 * (double)(R2 > 8 ? R2 : 8) * 1.1102230246251565e-16;
+  auto load = [&](int j, double2 (&v)[RPL]) {
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) {
+      const int k = lane + kWaveL * h;
+      v[h] = k < R2 ? gm[j * S + k] : make_double2(0.0, 0.0);
+    }
+  };
+  auto store = [&](int j, const double2 (&v)[RPL]) {
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) {
+      const int k = lane + kWaveL * h;
+      if (k < R2) gm[j * S + k] = v[h];
+    }
+  };
   auto norms = [&]() {
     for (int j = 0; j < R2; ++j) {
-      const double2 v = gm[j * kWaveL];
-      nl[j] = group_sum<kWaveL>(v.x * v.x + v.y * v.y);
+      double2 v[RPL];
+      load(j, v);
+      double s2 = 0.0;
+#pragma unroll
+      for (int h = 0; h < RPL; ++h) s2 += v[h].x * v[h].x + v[h].y * v[h].y;
+      nl[j] = group_sum<kWaveL>(s2);
     }
   };
   norms();
@@ -679,40 +758,79 @@ __device__ __forceinline__ void jacobi_eig_l(double2* gm, double* nl, double (&l
   for (int sweep = 0; sweep < kJacobiMaxSweeps; ++sweep) {
     bool rotated = false;
     for (int p = 0; p < R2 - 1; ++p) {
-      double2 ap = gm[p * kWaveL];
+      double2 ap[RPL];
+      load(p, ap);
       double np = nl[p];
       for (int q = p + 1; q < R2; ++q) {
-        double2 aq = gm[q * kWaveL];
+        double2 aq[RPL];
+        load(q, aq);
         double nq = nl[q];
-        jrot<kWaveL>(ap, aq, np, nq, thresh, small, rotated);
-        gm[q * kWaveL] = aq;
+        jrot_l<RPL>(ap, aq, np, nq, thresh, small, rotated);
+        store(q, aq);
         nl[q] = nq;
       }
-      gm[p * kWaveL] = ap;
+      store(p, ap);
       nl[p] = np;
     }
     norms();
     if (!__any(rotated)) break;
   }
-#pragma unroll
-  for (int j = 0; j < R2; ++j) lam[j] = sqrt(nl[j]);
 }
 
-// LDS of one wave: [R2][kWaveL] complex, then R2 norms
+// rank_positions on the LDS norms: pl[j] = position of column j in
+// descending order of sigma_j = sqrt(nl[j]) (ties by index); returns the
+// number of sigma_j > tol * max sigma (the same comparisons in the same
+// precision as the register kernels)
 template <int R2>
-constexpr size_t k2l_wave_lds() { return (size_t)R2 * kWaveL * sizeof(double2) + R2 * sizeof(double); }
+__device__ __forceinline__ int k2l_rank(const double* nl, int* pl, int lane, double tol) {
+  double smax = 0.0;
+  for (int i = 0; i < R2; ++i) smax = fmax(smax, sqrt(nl[i]));
+  int k = 0;
+  for (int i = 0; i < R2; ++i) k += (smax > 0.0 && sqrt(nl[i]) > tol * smax) ? 1 : 0;
+#pragma unroll
+  for (int h = 0; h < k2l_rpl<R2>(); ++h) {
+    const int j = lane + kWaveL * h;
+    if (j < R2) {
+      const double sj = sqrt(nl[j]);
+      int cnt = 0;
+      for (int i = 0; i < R2; ++i) {
+        const double si = sqrt(nl[i]);
+        cnt += (si > sj || (si == sj && i < j)) ? 1 : 0;
+      }
+      pl[j] = cnt;
+    }
+  }
+  return k;
+}
+
+// entry (j, row k) of the wave's matrix, zero past the rows
+template <int R2>
+__device__ __forceinline__ double2 k2l_at(const double2* gm, int j, int k) {
+  return k < R2 ? gm[j * k2l_stride<R2>() + k] : make_double2(0.0, 0.0);
+}
+// sum over the rows of conj(column j) . w (w[h] at row lane + 64 h)
+template <int R2>
+__device__ __forceinline__ double2 k2l_dot(const double2* gm, int j, int lane,
+                                           const double2 (&w)[k2l_rpl<R2>()]) {
+  double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int h = 0; h < k2l_rpl<R2>(); ++h)
+    acc = cadd(acc, cmul(conjd(k2l_at<R2>(gm, j, lane + kWaveL * h)), w[h]));
+  return csum<kWaveL>(acc);
+}
 
 #define IBF2L_WAVE_INDEX                                                        \
+  constexpr int RPL = k2l_rpl<R2>();                                            \
   extern __shared__ __align__(16) unsigned char smem2l[];                       \
   const int lane = threadIdx.x & (kWaveL - 1);                                  \
   const int wv = threadIdx.x / kWaveL;                                          \
   const int64_t p = (int64_t)blockIdx.x * (blockDim.x / kWaveL) + wv;           \
   if (p >= npairs) return;                                                      \
-  const bool row = lane < R2;                                                   \
-  double2* gm = reinterpret_cast<double2*>(smem2l + wv * k2l_wave_lds<R2>()) + lane; \
+  double2* gm = reinterpret_cast<double2*>(smem2l + wv * k2l_wave_lds<R2>());   \
   double* nl = reinterpret_cast<double*>(smem2l + wv * k2l_wave_lds<R2>() +     \
-                                         (size_t)R2 * kWaveL * sizeof(double2));  \
-  for (int j = 0; j < R2; ++j) gm[j * kWaveL] = make_double2(0.0, 0.0);
+                                         (size_t)R2 * k2l_stride<R2>() * sizeof(double2)); \
+  int* pl = reinterpret_cast<int*>(nl + R2);                                    \
+  for (int e = lane; e < R2 * k2l_stride<R2>(); e += kWaveL) gm[e] = make_double2(0.0, 0.0);
 
 template <int R2>
 __global__ __launch_bounds__(256) void k2l_middle(BoxDev B, const double* __restrict__ z,
@@ -722,44 +840,70 @@ __global__ __launch_bounds__(256) void k2l_middle(BoxDev B, const double* __rest
                                                   unsigned long long* __restrict__ nnz,
                                                   int64_t npairs, double tol) {
   IBF2L_WAVE_INDEX
-  const int r = B.r, L = B.L, h = B.h;
-  const int64_t a = p >> (2 * (L - h)), b = p & (((int64_t)1 << (2 * (L - h))) - 1);
+  const int r = B.r, L = B.L, h0 = B.h;
+  const int64_t a = p >> (2 * (L - h0)), b = p & (((int64_t)1 << (2 * (L - h0))) - 1);
   double ca1, ca2, cb1, cb2;
-  cx2(h, a, ca1, ca2);
-  cxi2(B, L - h, b, cb1, cb2);
-  const double wa = ldexp(1.0, -h), wb = B.w / ldexp(1.0, L - h);
-  const int tl = row ? lane : 0;
-  const double ga1 = gpt(ca1, wa, z[tl / r]), ga2 = gpt(ca2, wa, z[tl % r]);
-  for (int s = 0; s < R2; ++s) {
-    const double2 w = row ? kval2(B.ph, ga1, ga2, gpt(cb1, wb, z[s / r]), gpt(cb2, wb, z[s % r]))
-                          : make_double2(0.0, 0.0);
-    double2 av = conjd(w);
-    givens_fold_l<R2>(gm, av);
-  }
-  for (int j = 0; j < R2; ++j) gm[j * kWaveL] = conjd(gm[j * kWaveL]);
-  double sig[R2];
-  jacobi_eig_l<R2>(gm, nl, sig);
-  int pos[R2];
-  const int k = rank_positions<R2>(sig, tol, pos);
-  double2* crow = Cb + (p * R2 + tl) * R2;
+  cx2(h0, a, ca1, ca2);
+  cxi2(B, L - h0, b, cb1, cb2);
+  const double wa = ldexp(1.0, -h0), wb = B.w / ldexp(1.0, L - h0);
+  double ga1[RPL], ga2[RPL];
+  bool row[RPL];
 #pragma unroll
-  for (int j = 0; j < R2; ++j) {
-    const bool keep = pos[j] < k && sig[j] > 0.0;
-    const double sc = keep ? 1.0 / sqrt(sig[j]) : 0.0;
-    if (row) crow[pos[j]] = cscale(gm[j * kWaveL], sc);
+  for (int h = 0; h < RPL; ++h) {
+    const int t = lane + kWaveL * h;
+    row[h] = t < R2;
+    const int tl = row[h] ? t : 0;
+    ga1[h] = gpt(ca1, wa, z[tl / r]);
+    ga2[h] = gpt(ca2, wa, z[tl % r]);
   }
-  const int my_pos = sel<R2>(pos, tl);
-  const double my_sig = sel<R2>(sig, tl);
-  const double my_sc = (my_pos < k && my_sig > 0.0) ? pow(my_sig, -1.5) : 0.0;
+  auto mcol = [&](int s, double2 (&w)[RPL]) {
+    const double gb1 = gpt(cb1, wb, z[s / r]), gb2 = gpt(cb2, wb, z[s % r]);
+#pragma unroll
+    for (int h = 0; h < RPL; ++h)
+      w[h] = row[h] ? kval2(B.ph, ga1[h], ga2[h], gb1, gb2) : make_double2(0.0, 0.0);
+  };
   for (int s = 0; s < R2; ++s) {
-    const double2 mts = row ? kval2(B.ph, ga1, ga2, gpt(cb1, wb, z[s / r]), gpt(cb2, wb, z[s % r]))
-                            : make_double2(0.0, 0.0);
-    double2 mine = make_double2(0.0, 0.0);
+    double2 av[RPL];
+    mcol(s, av);
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) av[h] = conjd(av[h]);
+    givens_fold_l<R2>(gm, lane, av);
+  }
+  for (int e = lane; e < R2 * k2l_stride<R2>(); e += kWaveL) gm[e] = conjd(gm[e]);
+  jacobi_eig_l<R2>(gm, nl, lane);
+  const int k = k2l_rank<R2>(nl, pl, lane, tol);
+#pragma unroll
+  for (int h = 0; h < RPL; ++h) {
+    const int t = lane + kWaveL * h;
+    if (!row[h]) continue;
+    double2* crow = Cb + (p * R2 + t) * R2;
     for (int j = 0; j < R2; ++j) {
-      const double2 v = csum<kWaveL>(cmul(conjd(mts), gm[j * kWaveL]));
-      if (lane == j) mine = v;
+      const double sj = sqrt(nl[j]);
+      const int pj = pl[j];
+      const bool keep = pj < k && sj > 0.0;
+      const double sc = keep ? 1.0 / sqrt(sj) : 0.0;
+      crow[pj] = cscale(k2l_at<R2>(gm, j, t), sc);
     }
-    if (row) Rb[(p * R2 + s) * R2 + my_pos] = cscale(mine, my_sc);
+  }
+  for (int s = 0; s < R2; ++s) {
+    double2 mts[RPL];
+    mcol(s, mts);
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) mts[h] = conjd(mts[h]);
+    // column j of R^* dotted with conj(M[:, s]): lane j % 64 keeps it
+    for (int j = 0; j < R2; ++j) {
+      double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int h = 0; h < RPL; ++h)
+        acc = cadd(acc, cmul(mts[h], k2l_at<R2>(gm, j, lane + kWaveL * h)));
+      const double2 v = csum<kWaveL>(acc);
+      if (lane == (j & (kWaveL - 1))) {
+        const int pj = pl[j];
+        const double sj = sqrt(nl[j]);
+        const double sc = (pj < k && sj > 0.0) ? pow(sj, -1.5) : 0.0;
+        Rb[(p * R2 + s) * R2 + pj] = cscale(v, sc);
+      }
+    }
   }
   if (lane == 0) {
     rank[p] = k;
@@ -789,62 +933,85 @@ __global__ __launch_bounds__(256) void k2l_sweep_g(BoxDev B, int l, const double
   cx2(l, a, ca1, ca2);
   cx2(l - 1, par, cp1, cp2);
   const double wa = ldexp(1.0, -l), wp = ldexp(1.0, -(l - 1));
-  const int tl = row ? lane : 0;
-  const double ga1 = gpt(ca1, wa, z[tl / r]), ga2 = gpt(ca2, wa, z[tl % r]);
-  const double gp1 = gpt(cp1, wp, z[tl / r]), gp2 = gpt(cp2, wp, z[tl % r]);
   const double* la = lc + alpha * R2 * R2;               // la[s * R2 + t] = M^P_s(g^A_t)
   int kin[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) kin[c] = rprev[pin0 + c];
-  auto wcol = [&](int c, int m, double2 at, double2 bs) -> double2 {
-    const double2* cs = Cprev + (pin0 + c) * R2 * R2 + m;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int s = 0; s < R2; ++s)
-      cfma(acc, cscale(rl2(bs, s), la[s * R2 + tl]), cs[s * R2]);
-    return row ? cmul(at, acc) : make_double2(0.0, 0.0);
-  };
-  double2 at[4], bs[4];
+  bool row[RPL];
+  int tl[RPL];
+  double2 at[4][RPL], bs[4][RPL];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    double cc1, cc2;
-    cxi2(B, L - l + 1, 4 * b + c, cc1, cc2);
-    at[c] = kval2(B.ph, ga1, ga2, cc1, cc2);
-    bs[c] = conjd(kval2(B.ph, gp1, gp2, cc1, cc2));
+  for (int h = 0; h < RPL; ++h) {
+    const int t = lane + kWaveL * h;
+    row[h] = t < R2;
+    tl[h] = row[h] ? t : 0;
+    const double ga1 = gpt(ca1, wa, z[tl[h] / r]), ga2 = gpt(ca2, wa, z[tl[h] % r]);
+    const double gp1 = gpt(cp1, wp, z[tl[h] / r]), gp2 = gpt(cp2, wp, z[tl[h] % r]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double cc1, cc2;
+      cxi2(B, L - l + 1, 4 * b + c, cc1, cc2);
+      at[c][h] = kval2(B.ph, ga1, ga2, cc1, cc2);
+      bs[c][h] = conjd(kval2(B.ph, gp1, gp2, cc1, cc2));   // entry s = lane + 64 h: B_s
+    }
   }
+  // W_c[t][m] for this lane's rows t
+  auto wcol = [&](int c, int m, double2 (&w)[RPL]) {
+    const double2* cs = Cprev + (pin0 + c) * R2 * R2 + m;
+    double2 acc[RPL];
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) acc[h] = make_double2(0.0, 0.0);
+    for (int s = 0; s < R2; ++s) {
+      const double2 bsv = rl_k<RPL>(bs[c], s);
+      const double2 cv = cs[s * R2];
+#pragma unroll
+      for (int h = 0; h < RPL; ++h) cfma(acc[h], cscale(bsv, la[s * R2 + tl[h]]), cv);
+    }
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) w[h] = row[h] ? cmul(at[c][h], acc[h]) : make_double2(0.0, 0.0);
+  };
 #pragma unroll
   for (int c = 0; c < 4; ++c)
     for (int m = 0; m < kin[c]; ++m) {
-      double2 av = conjd(wcol(c, m, at[c], bs[c]));
-      givens_fold_l<R2>(gm, av);
-    }
-  for (int j = 0; j < R2; ++j) gm[j * kWaveL] = conjd(gm[j * kWaveL]);
-  double sig[R2];
-  jacobi_eig_l<R2>(gm, nl, sig);
-  int pos[R2];
-  const int k = rank_positions<R2>(sig, tol, pos);
-  double2* crow = Cout + (p * R2 + tl) * R2;
+      double2 av[RPL];
+      wcol(c, m, av);
 #pragma unroll
-  for (int j = 0; j < R2; ++j) {
-    const bool keep = pos[j] < k && sig[j] > 0.0;
-    if (row) crow[pos[j]] = keep ? gm[j * kWaveL] : make_double2(0.0, 0.0);
+      for (int h = 0; h < RPL; ++h) av[h] = conjd(av[h]);
+      givens_fold_l<R2>(gm, lane, av);
+    }
+  for (int e = lane; e < R2 * k2l_stride<R2>(); e += kWaveL) gm[e] = conjd(gm[e]);
+  jacobi_eig_l<R2>(gm, nl, lane);
+  const int k = k2l_rank<R2>(nl, pl, lane, tol);
+#pragma unroll
+  for (int h = 0; h < RPL; ++h) {
+    if (!row[h]) continue;
+    double2* crow = Cout + (p * R2 + tl[h]) * R2;        // C^l = U_k S_k
+    for (int j = 0; j < R2; ++j) {
+      const bool keep = pl[j] < k && sqrt(nl[j]) > 0.0;
+      crow[pl[j]] = keep ? k2l_at<R2>(gm, j, tl[h]) : make_double2(0.0, 0.0);
+    }
   }
-  const int my_pos = sel<R2>(pos, tl);
-  const double my_sig = sel<R2>(sig, tl);
-  const double my_sc = (my_pos < k && my_sig > 0.0) ? 1.0 / (my_sig * my_sig) : 0.0;
+  // Gbar row j = sigma_j^-2 (sigma_j u_j)^* W; lane j % 64 keeps column j
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     double2* st = stage + (p * 4 + c) * R2 * R2;
     for (int m = 0; m < R2; ++m) {
       if (m < kin[c]) {
-        const double2 w = wcol(c, m, at[c], bs[c]);
-        double2 mine = make_double2(0.0, 0.0);
+        double2 w[RPL];
+        wcol(c, m, w);
         for (int j = 0; j < R2; ++j) {
-          const double2 v = csum<kWaveL>(cmul(conjd(gm[j * kWaveL]), w));
-          if (lane == j) mine = v;
+          const double2 v = k2l_dot<R2>(gm, j, lane, w);
+          if (lane == (j & (kWaveL - 1))) {
+            const int pj = pl[j];
+            const double sj = sqrt(nl[j]);
+            const double sc = (pj < k && sj > 0.0) ? 1.0 / (sj * sj) : 0.0;
+            st[pj * R2 + m] = cscale(v, sc);
+          }
         }
-        if (row) st[my_pos * R2 + m] = cscale(mine, my_sc);
-      } else if (row) {
-        st[tl * R2 + m] = make_double2(0.0, 0.0);
+      } else {
+#pragma unroll
+        for (int h = 0; h < RPL; ++h)
+          if (row[h]) st[tl[h] * R2 + m] = make_double2(0.0, 0.0);
       }
     }
   }
@@ -876,64 +1043,89 @@ __global__ __launch_bounds__(256) void k2l_sweep_h(BoxDev B, int l, const double
   cxi2(B, L - l + 1, C, cc1, cc2);
   cxi2(B, L - l, Bb, cb1, cb2);
   const double wc = B.w / ldexp(1.0, L - l + 1), wb = B.w / ldexp(1.0, L - l);
-  const int sl = row ? lane : 0;
-  const double gc1 = gpt(cc1, wc, z[sl / r]), gc2 = gpt(cc2, wc, z[sl % r]);
-  const double gb1 = gpt(cb1, wb, z[sl / r]), gb2 = gpt(cb2, wb, z[sl % r]);
   const double* lcc = lc + c * R2 * R2;                  // lcc[t * R2 + s] = M^B_t(g^C_s)
   int64_t pout[4];
   int kout[4];
-  double2 ds[4], et[4];
 #pragma unroll
   for (int al = 0; al < 4; ++al) {
     const int64_t A = 4 * P + al;
     pout[al] = (A << (2 * (L - l))) + Bb;
     kout[al] = rcur[pout[al]];
-    double ca1, ca2;
-    cx2(l, A, ca1, ca2);
-    ds[al] = conjd(kval2(B.ph, ca1, ca2, gc1, gc2));
-    et[al] = kval2(B.ph, ca1, ca2, gb1, gb2);
   }
-  auto zcol = [&](int al, int m) -> double2 {
+  bool row[RPL];
+  int sl[RPL];
+  double2 ds[4][RPL], et[4][RPL];
+#pragma unroll
+  for (int h = 0; h < RPL; ++h) {
+    const int s = lane + kWaveL * h;
+    row[h] = s < R2;
+    sl[h] = row[h] ? s : 0;
+    const double gc1 = gpt(cc1, wc, z[sl[h] / r]), gc2 = gpt(cc2, wc, z[sl[h] % r]);
+    const double gb1 = gpt(cb1, wb, z[sl[h] / r]), gb2 = gpt(cb2, wb, z[sl[h] % r]);
+#pragma unroll
+    for (int al = 0; al < 4; ++al) {
+      const int64_t A = 4 * P + al;
+      double ca1, ca2;
+      cx2(l, A, ca1, ca2);
+      ds[al][h] = conjd(kval2(B.ph, ca1, ca2, gc1, gc2));  // row s of this lane
+      et[al][h] = kval2(B.ph, ca1, ca2, gb1, gb2);         // entry t = lane + 64 h: E_t
+    }
+  }
+  auto zcol = [&](int al, int m, double2 (&w)[RPL]) {
     const double2* rs = Rcur + pout[al] * R2 * R2 + m;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int t = 0; t < R2; ++t)
-      cfma(acc, cscale(rl2(et[al], t), lcc[t * R2 + sl]), rs[t * R2]);
-    return row ? cmul(ds[al], acc) : make_double2(0.0, 0.0);
+    double2 acc[RPL];
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) acc[h] = make_double2(0.0, 0.0);
+    for (int t = 0; t < R2; ++t) {
+      const double2 ev = rl_k<RPL>(et[al], t);
+      const double2 rv = rs[t * R2];
+#pragma unroll
+      for (int h = 0; h < RPL; ++h) cfma(acc[h], cscale(ev, lcc[t * R2 + sl[h]]), rv);
+    }
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) w[h] = row[h] ? cmul(ds[al][h], acc[h]) : make_double2(0.0, 0.0);
   };
 #pragma unroll
   for (int al = 0; al < 4; ++al)
     for (int m = 0; m < kout[al]; ++m) {
-      double2 av = conjd(zcol(al, m));
-      givens_fold_l<R2>(gm, av);
-    }
-  for (int j = 0; j < R2; ++j) gm[j * kWaveL] = conjd(gm[j * kWaveL]);
-  double sig[R2];
-  jacobi_eig_l<R2>(gm, nl, sig);
-  int pos[R2];
-  const int k = rank_positions<R2>(sig, tol, pos);
-  double2* rrow = Rnext + (q * R2 + sl) * R2;
+      double2 av[RPL];
+      zcol(al, m, av);
 #pragma unroll
-  for (int j = 0; j < R2; ++j) {
-    const bool keep = pos[j] < k && sig[j] > 0.0;
-    if (row) rrow[pos[j]] = keep ? gm[j * kWaveL] : make_double2(0.0, 0.0);
+      for (int h = 0; h < RPL; ++h) av[h] = conjd(av[h]);
+      givens_fold_l<R2>(gm, lane, av);
+    }
+  for (int e = lane; e < R2 * k2l_stride<R2>(); e += kWaveL) gm[e] = conjd(gm[e]);
+  jacobi_eig_l<R2>(gm, nl, lane);
+  const int k = k2l_rank<R2>(nl, pl, lane, tol);
+#pragma unroll
+  for (int h = 0; h < RPL; ++h) {
+    if (!row[h]) continue;
+    double2* rrow = Rnext + (q * R2 + sl[h]) * R2;       // R^{l-1} = U_k S_k
+    for (int j = 0; j < R2; ++j) {
+      const bool keep = pl[j] < k && sqrt(nl[j]) > 0.0;
+      rrow[pl[j]] = keep ? k2l_at<R2>(gm, j, sl[h]) : make_double2(0.0, 0.0);
+    }
   }
-  const int my_pos = sel<R2>(pos, sl);
-  const double my_sig = sel<R2>(sig, sl);
-  const double my_sc = (my_pos < k && my_sig > 0.0) ? 1.0 / (my_sig * my_sig) : 0.0;
 #pragma unroll
   for (int al = 0; al < 4; ++al) {
     double2* st = stage + (pout[al] * 4 + c) * R2 * R2;
     for (int m = 0; m < R2; ++m) {
       if (m < kout[al]) {
-        const double2 w = zcol(al, m);
-        double2 mine = make_double2(0.0, 0.0);
+        double2 w[RPL];
+        zcol(al, m, w);
         for (int j = 0; j < R2; ++j) {
-          const double2 v = csum<kWaveL>(cmul(conjd(gm[j * kWaveL]), w));
-          if (lane == j) mine = v;
+          const double2 v = k2l_dot<R2>(gm, j, lane, w);
+          if (lane == (j & (kWaveL - 1))) {
+            const int pj = pl[j];
+            const double sj = sqrt(nl[j]);
+            const double sc = (pj < k && sj > 0.0) ? 1.0 / (sj * sj) : 0.0;
+            st[m * R2 + pj] = cscale(conjd(v), sc);
+          }
         }
-        if (row) st[m * R2 + my_pos] = cscale(conjd(mine), my_sc);
-      } else if (row) {
-        st[m * R2 + sl] = make_double2(0.0, 0.0);
+      } else {
+#pragma unroll
+        for (int h = 0; h < RPL; ++h)
+          if (row[h]) st[m * R2 + sl[h]] = make_double2(0.0, 0.0);
       }
     }
   }
@@ -1435,7 +1627,8 @@ namespace {
     case 25: LAUNCH(25); break;                            \
     case 36: LAUNCH(36); break;                            \
     case 49: LAUNCH(49); break;                            \
-    default: LAUNCH(64); break;                            \
+    case 64: LAUNCH(64); break;                            \
+    default: LAUNCH(81); break;                            \
   }
 // register-resident compression kernels (r <= 5) / LDS-resident ones (r = 6 .. 8)
 #define IBF2_DISPATCH_SMALL(R2V, LAUNCH)                   \
@@ -1449,12 +1642,18 @@ namespace {
   switch (R2V) {                                           \
     case 36: LAUNCH(36); break;                            \
     case 49: LAUNCH(49); break;                            \
-    default: LAUNCH(64); break;                            \
+    case 64: LAUNCH(64); break;                            \
+    default: LAUNCH(81); break;                            \
   }
-// pairs (waves) a block of the LDS-resident kernels: as many as 160 KiB hold, at most 4
+// LDS bytes of one pair (wave) of the LDS-resident kernels, and pairs a
+// block: as many as 160 KiB hold, at most 4
+inline size_t k2l_lds_per_wave(int R2) {
+  const size_t stride = R2 > kWaveL ? (size_t)R2 : (size_t)kWaveL;
+  return ((size_t)R2 * stride * sizeof(double2) + (size_t)R2 * (sizeof(double) + sizeof(int)) +
+          15) & ~(size_t)15;
+}
 inline int k2l_waves(int R2) {
-  const size_t per = (size_t)R2 * kWaveL * sizeof(double2) + R2 * sizeof(double);
-  return (int)std::max<size_t>(1, std::min<size_t>(4, (160u << 10) / per));
+  return (int)std::max<size_t>(1, std::min<size_t>(4, (160u << 10) / k2l_lds_per_wave(R2)));
 }
 
 int64_t morton_host(int64_t i1, int64_t i2, int level) {
@@ -1593,7 +1792,7 @@ int build2d_t(ibf_plan_t p, hipStream_t s) {
     const bool big = R2 > 25;
     const int nwl = k2l_waves(R2);
     const unsigned ggl = (unsigned)((np + nwl - 1) / nwl);
-    const size_t ldsl = (size_t)nwl * ((size_t)R2 * kWaveL * sizeof(double2) + R2 * sizeof(double));
+    const size_t ldsl = (size_t)nwl * k2l_lds_per_wave(R2);
 #define IBF2_MIDDLE(RR)                                                                          \
   hipLaunchKernelGGL((k2_middle<RR>), dim3(gg), dim3(kB2), 0, s, B, M.d_z, S.C[0], S.R[0],      \
                      S.rc[0], S.kmax + h, S.nnz, np, M.tol)
@@ -2018,8 +2217,8 @@ int plan2d(const ibf_desc* d, ibf_plan_t* out) {
     set_error(msg);
     return IBF_ERR_INVALID_ARG;
   };
-  if (d->r < 2 || d->r > 8) {
-    set_error("ibf_plan: dim 2 supports r = 2 .. 8 (r^2 <= 64 grid points per box)");
+  if (d->r < 2 || d->r > 9) {
+    set_error("ibf_plan: dim 2 supports r = 2 .. 9 (r^2 <= 81 grid points per box)");
     return d->r < 2 ? IBF_ERR_INVALID_ARG : IBF_ERR_UNSUPPORTED;
   }
   if (!(d->tol > 0.0 && d->tol < 1.0)) return bad("ibf_plan: tol must lie in (0, 1)");

@@ -208,8 +208,8 @@ def test_amplitude_and_caps_rejected_for_dim2():
         with pytest.raises(ibf.IBFError) as e:
             ibf.Plan(x, xi, 2, (2.0, 1.0, 16.0), 5, 1e-4, 16, I.PREC_FP32, **kw)
         assert e.value.code == -2
-    # orders 2 .. 8 (up to 64 tensor grid points a box)
-    for r, code in ((8, 0), (9, -2), (1, -1)):
+    # orders 2 .. 9 (up to 81 tensor grid points a box)
+    for r, code in ((9, 0), (10, -2), (1, -1)):
         if code == 0:
             ibf.Plan(x, xi, 2, (2.0, 1.0, 16.0), r, 1e-4, 16, I.PREC_FP32).destroy()
             continue

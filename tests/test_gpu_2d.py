@@ -184,14 +184,16 @@ def _case_high(n, r, tol, table4):
 @pytest.mark.parametrize("n,r,tol,table4,precision", [
     (32, 6, 1e-3, True, I.PREC_FP64), (32, 6, 1e-3, True, I.PREC_FP32),
     (64, 6, 1e-3, True, I.PREC_FP64), (32, 7, 1e-4, False, I.PREC_FP64),
-    (32, 8, 1e-4, False, I.PREC_FP64)])
+    (32, 8, 1e-4, False, I.PREC_FP64), (32, 9, 3e-6, True, I.PREC_FP64),
+    (32, 9, 3e-6, True, I.PREC_FP32)])
 def test_2d_high_order_against_oracle(torch_dev, n, r, tol, table4, precision):
-    """r = 6, 7, 8 (36 to 64 grid points a box: the compression runs with its
-    triangular factor and Jacobi columns in LDS) against the oracle MIBF:
-    identical preliminary and stored entry counts, FP64 at its bar, FP32 at
-    1e-5.  r = 6 at tol 1e-3 with c/32 is Table 4's setting: there the GPU
-    factorization also reproduces the printed R_comp (within 10 %) and error
-    (within a factor 4, 256 sampled rows against the dense product)."""
+    """r = 6 .. 9 (36 to 81 grid points a box: the compression runs with its
+    triangular factor and Jacobi columns in LDS, two rows a lane at r = 9)
+    against the oracle MIBF: identical preliminary and stored entry counts,
+    FP64 at its bar, FP32 at 1e-5.  r = 6 at tol 1e-3 and r = 9 at 3e-6 with
+    c/32 are Table 4's settings: there the GPU factorization also reproduces
+    the printed R_comp (within 10 %) and error (within a factor 4, 256
+    sampled rows against the dense product)."""
     _say(f"2-D high order n={n} r={r} tol={tol} table4={table4} precision={precision}")
     P, uo, pre, opt = _case_high(n, r, tol, table4)
     ug, q = _gpu(torch_dev, P, precision)
