@@ -27,6 +27,19 @@ L = log2 w, has width product 1 per coordinate; V pairs the Omega leaves
 (side `leaf_side`, level L - lV) with the T_X boxes at level lV =
 log2(leaf_side), U pairs the T_X boxes at level L with the box itself, and
 the middle level is h = floor((lV + L) / 2).
+
+Randomized low-rank approximation (Sec. 2.1, f2): the paper computes large
+low-rank approximations by sampling the matrix randomly and defers the
+algorithm to its references.  `sweep_out_2d(..., sample=(seed, S))` takes
+the column-sampling reading: every block W (the middle M~, the W of eqn:GC,
+the Z of eqn:HR) keeps each of its n real columns with probability
+min(1, S / n), independently, by a counter-based draw (the (i + 1)-th
+output of SplitMix64 started at `seed`, Steele, Lea and Flood 2014, for the
+column's index i); the left singular vectors U and singular values of the
+s kept columns, scaled by sqrt(n / s), stand for W's; the rank is the
+tolerance rule on them, and the right factor is the projection of all of W,
+V_k S_k = W^* U_k (linear in n).  With S >= n every column is kept and the
+compression is the direct one.
 """
 from __future__ import annotations
 
@@ -374,18 +387,98 @@ class Optimal2D:
     ranks: dict              # level -> per-pair ranks [a, b]
 
 
-def sweep_out_2d(F: Prelim2D, tol: float) -> Optimal2D:
+_SM_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_SM_MUL1 = np.uint64(0xBF58476D1CE4E5B9)
+_SM_MUL2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64_uniform(seed, index):
+    """u in [0, 1) from the top 53 bits of the (index + 1)-th output of
+    SplitMix64 started at `seed` (state seed + n gamma, then the mix
+    function), elementwise over `index` (uint64 arithmetic modulo 2^64)."""
+    idx = np.asarray(index, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (idx + np.uint64(1)) * _SM_GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _SM_MUL1
+        z = (z ^ (z >> np.uint64(27))) * _SM_MUL2
+        z = z ^ (z >> np.uint64(31))
+    return (z >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+
+
+# block families of the draws: the middle, the sweep toward U producing level
+# l, the sweep toward V producing level l - 1
+SAMPLE_TAG_MIDDLE = 0
+
+
+def sample_tag_g(l):
+    return 1 + l
+
+
+def sample_tag_h(l):
+    return 64 + l
+
+
+def sample_columns(seed, S, tag, real):
+    """Mask of the kept columns: real[..., n_cols] marks the block's real
+    columns (pairs enumerated in C order over the leading axes, columns by
+    their index j); column j of pair p is kept iff it is real and
+    u(seed, j + 2^9 p + 2^41 tag) < min(1, S / n_real)."""
+    real = np.asarray(real, dtype=bool)
+    npair = int(np.prod(real.shape[:-1]))
+    ncol = real.shape[-1]
+    pidx = np.arange(npair, dtype=np.uint64).reshape(real.shape[:-1] + (1,))
+    j = np.arange(ncol, dtype=np.uint64)
+    index = j + (pidx << np.uint64(9)) + (np.uint64(tag) << np.uint64(41))
+    u = splitmix64_uniform(seed, index)
+    n = real.sum(axis=-1)
+    rho = np.minimum(1.0, S / np.maximum(n, 1).astype(np.float64))
+    return real & (u < rho[..., None])
+
+
+def sampled_svd(W, real, tol, seed, S, tag):
+    """Randomized low-rank approximation of the blocks W[..., R2, n] from
+    their sampled columns: U, the scaled singular values, and the rank k by
+    the tolerance rule on the sampled values (scale-free)."""
+    mask = sample_columns(seed, S, tag, real)
+    U, Sv, _ = np.linalg.svd(W * mask[..., None, :], full_matrices=False)
+    s1 = Sv[..., :1]
+    k = np.where(s1[..., 0] > 0, np.sum(Sv > tol * s1, axis=-1), 0)
+    nreal = real.sum(axis=-1).astype(np.float64)
+    nkept = mask.sum(axis=-1).astype(np.float64)
+    f = np.where(nkept > 0, np.sqrt(nreal / np.maximum(nkept, 1.0)), 0.0)
+    return U, Sv * f[..., None], k
+
+
+def _proj(W, U, Ssc, keep):
+    """V_k^* = S_k^-1 U_k^* W for the kept columns of U (zero rows otherwise)."""
+    inv = np.where(keep > 0, 1.0 / np.where(Ssc > 0, Ssc, 1.0), 0.0)
+    return (np.conj(np.swapaxes(U, -1, -2)) @ W) * inv[..., :, None]
+
+
+def sweep_out_2d(F: Prelim2D, tol: float, sample=None) -> Optimal2D:
     """Middle SVDs (eq:KeqUMV with Sigma^(1/2) on both sides), then
-    eqn:GC toward U (C^{l} = U_k S_k, Gbar = V_k^*) and eqn:HR toward V."""
+    eqn:GC toward U (C^{l} = U_k S_k, Gbar = V_k^*) and eqn:HR toward V.
+    sample = (seed, S): the randomized low-rank approximation by column
+    sampling described in the module header, for every block."""
     P = F.prob
     L, lV, h = P.L, P.lV, P.h
     R2 = P.r * P.r
     ranks = {}
-    Um, Sm, Vhm, km = truncated_svd(F.M, tol)
-    keep = _keep(km, R2)
-    sq = np.sqrt(Sm) * keep
-    Cl = {h: Um * sq[..., None, :]}
-    Rl = {h: np.conj(np.swapaxes(Vhm, -1, -2)) * sq[..., None, :]}
+    if sample is None:
+        Um, Sm, Vhm, km = truncated_svd(F.M, tol)
+        keep = _keep(km, R2)
+        sq = np.sqrt(Sm) * keep
+        Cl = {h: Um * sq[..., None, :]}
+        Rl = {h: np.conj(np.swapaxes(Vhm, -1, -2)) * sq[..., None, :]}
+    else:
+        real = np.ones(F.M.shape[:-2] + (R2,), dtype=bool)
+        Um, Sm, km = sampled_svd(F.M, real, tol, sample[0], sample[1], SAMPLE_TAG_MIDDLE)
+        keep = _keep(km, R2)
+        sq = np.sqrt(Sm) * keep
+        Cl = {h: Um * sq[..., None, :]}
+        # V_k S_k^(1/2) = M^* U_k S_k^(-1/2)
+        isq = np.where(keep > 0, 1.0 / np.where(sq > 0, sq, 1.0), 0.0)
+        Rl = {h: (np.conj(np.swapaxes(F.M, -1, -2)) @ Um) * isq[..., None, :]}
     ranks[h] = km
 
     Gbar = {}
@@ -395,10 +488,19 @@ def sweep_out_2d(F: Prelim2D, tol: float) -> Optimal2D:
         par = np.arange(na) >> 2
         W = np.concatenate([F.G[l][:, :, c] @ Cprev[par][:, 4 * np.arange(nb) + c]
                             for c in range(4)], axis=-1)                     # [a, b, R2, 4 R2]
-        Uw, Sw, Vhw, kw = truncated_svd(W, tol)
-        keep = _keep(kw, R2)
-        Cl[l] = Uw[..., :R2] * (Sw[..., :R2] * keep)[..., None, :]
-        Vk = Vhw[..., :R2, :] * keep[..., :, None]                           # [a, b, k, 4 R2]
+        if sample is None:
+            Uw, Sw, Vhw, kw = truncated_svd(W, tol)
+            keep = _keep(kw, R2)
+            Cl[l] = Uw[..., :R2] * (Sw[..., :R2] * keep)[..., None, :]
+            Vk = Vhw[..., :R2, :] * keep[..., :, None]                       # [a, b, k, 4 R2]
+        else:
+            kprev = ranks[l - 1][par][:, 4 * np.arange(nb)[:, None] + np.arange(4)]   # [a, b, c]
+            real = np.arange(R2)[None, None, None, :] < kprev[..., None]             # [a, b, c, m]
+            real = real.reshape(na, nb, 4 * R2)
+            Uw, Sw, kw = sampled_svd(W, real, tol, sample[0], sample[1], sample_tag_g(l))
+            keep = _keep(kw, R2)
+            Cl[l] = Uw[..., :R2] * (Sw[..., :R2] * keep)[..., None, :]
+            Vk = _proj(W, Uw[..., :R2], Sw[..., :R2], keep)                  # [a, b, k, 4 R2]
         Gbar[l] = np.stack([Vk[..., c * R2:(c + 1) * R2] for c in range(4)], axis=2)
         ranks[l] = kw
 
@@ -416,10 +518,18 @@ def sweep_out_2d(F: Prelim2D, tol: float) -> Optimal2D:
             Hs = np.conj(np.swapaxes(F.H[l][A, j >> 2, j & 3], -1, -2))     # [p, j, s, t]
             parts.append(Hs @ Rcur[A, j >> 2])
         Z = np.concatenate(parts, axis=-1)                                   # [p, j, R2, 4 R2]
-        Uz, Sz, Vhz, kz = truncated_svd(Z, tol)
-        keep = _keep(kz, R2)
-        Rl[l - 1] = Uz[..., :R2] * (Sz[..., :R2] * keep)[..., None, :]
-        Vk = np.conj(np.swapaxes(Vhz[..., :R2, :], -1, -2)) * keep[..., None, :]   # [p, j, 4 R2, k]
+        if sample is None:
+            Uz, Sz, Vhz, kz = truncated_svd(Z, tol)
+            keep = _keep(kz, R2)
+            Rl[l - 1] = Uz[..., :R2] * (Sz[..., :R2] * keep)[..., None, :]
+            Vk = np.conj(np.swapaxes(Vhz[..., :R2, :], -1, -2)) * keep[..., None, :]   # [p, j, 4 R2, k]
+        else:
+            kcur = np.stack([ranks[l][4 * p + alpha, j >> 2] for alpha in range(4)], -1)  # [p, j, 4]
+            real = (np.arange(R2)[None, None, None, :] < kcur[..., None]).reshape(npar, nin, 4 * R2)
+            Uz, Sz, kz = sampled_svd(Z, real, tol, sample[0], sample[1], sample_tag_h(l))
+            keep = _keep(kz, R2)
+            Rl[l - 1] = Uz[..., :R2] * (Sz[..., :R2] * keep)[..., None, :]
+            Vk = np.conj(np.swapaxes(_proj(Z, Uz[..., :R2], Sz[..., :R2], keep), -1, -2))
         blk = np.empty((na, nb, 4, R2, R2), dtype=np.complex128)
         for alpha in range(4):
             blk[(4 * p + alpha), j >> 2, j & 3] = Vk[:, :, alpha * R2:(alpha + 1) * R2, :]
@@ -469,10 +579,10 @@ def nnz_optimal_2d(O: Optimal2D):
     return tot
 
 
-def build_box(kind, params, x, xi, o, w, r, tol, leaf_side=4):
+def build_box(kind, params, x, xi, o, w, r, tol, leaf_side=4, sample=None):
     P = make_box_problem(kind, params, x, xi, o, w, r, leaf_side)
     F = prelim_factors_2d(P)
-    return P, F, sweep_out_2d(F, tol)
+    return P, F, sweep_out_2d(F, tol, sample)
 
 
 # ----------------------------------------------------------------------------
@@ -509,13 +619,13 @@ def mibf_partition(xi, n: int, centre: int = 16):
     return part
 
 
-def mibf_build(kind, params, x, xi, n, r, tol, leaf_side=4, centre=16):
+def mibf_build(kind, params, x, xi, n, r, tol, leaf_side=4, centre=16, sample=None):
     part = mibf_partition(xi, n, centre)
     boxes, hc = mibf_boxes(n, centre)
     built = []
     for i, (o, w) in enumerate(boxes):
         idx = np.nonzero(part == i)[0]
-        P, F, O = build_box(kind, params, x, xi[idx], o, w, r, tol, leaf_side)
+        P, F, O = build_box(kind, params, x, xi[idx], o, w, r, tol, leaf_side, sample)
         built.append((idx, P, F, O))
     return part, built, np.nonzero(part == -1)[0]
 
@@ -537,7 +647,7 @@ def nnz_mibf(built, centre_idx, n_x):
     return pre, opt
 
 
-__all__ = ["phase_frac_2d", "kernel_2d", "dense_apply_2d", "morton_encode", "morton_decode",
+__all__ = ["splitmix64_uniform", "sample_columns", "sampled_svd", "phase_frac_2d", "kernel_2d", "dense_apply_2d", "morton_encode", "morton_decode",
            "make_box_problem", "prelim_factors_2d", "apply_prelim_2d", "sweep_out_2d",
            "apply_optimal_2d", "build_box", "mibf_boxes", "mibf_partition", "mibf_build",
            "mibf_apply", "nnz_mibf", "rel_error", "level_ranks_2d"]

@@ -190,3 +190,88 @@ def test_mibf_matches_table4(n, r, tol):
     eps = O.rel_error(u[rows], ud)
     assert abs(pre / opt / rc_p - 1) < 0.10, (pre / opt, rc_p)
     assert eps_p / 4 < eps < 1.5 * eps_p, (eps, eps_p)
+
+
+# ---------------------------------------------------------------------------
+# Randomized low-rank approximation by column sampling (Sec. 2.1)
+# ---------------------------------------------------------------------------
+
+def test_splitmix64_reference_outputs():
+    """The counter-based draws are SplitMix64 (Steele, Lea and Flood 2014):
+    its published first outputs from seed 1234567, whose top 53 bits give the
+    uniforms."""
+    ref = [6457827717110365317, 3203168211198807973, 9817491932198370423]
+    u = D.splitmix64_uniform(1234567, np.arange(3))
+    assert list(u) == [(v >> 11) * 2.0 ** -53 for v in ref]
+
+
+def test_sample_columns_rate_and_real_columns():
+    """Each real column is kept with probability min(1, S / n): the kept
+    counts over 4096 blocks sit within 5 standard deviations of the mean,
+    padding columns are never kept, and S >= n keeps every real column."""
+    rng = np.random.default_rng(3)
+    nreal = rng.integers(20, 80, size=(64, 64))
+    real = np.arange(100)[None, None, :] < nreal[..., None]
+    S = 30
+    m = D.sample_columns(99, S, 5, real)
+    assert not np.any(m & ~real)
+    rho = np.minimum(1.0, S / nreal)
+    mean = np.sum(rho * nreal)
+    sd = math.sqrt(np.sum(nreal * rho * (1 - rho)))
+    assert abs(m.sum() - mean) < 5 * sd
+    assert np.array_equal(D.sample_columns(99, 1000, 5, real), real)
+    # a different family tag or seed draws differently
+    assert not np.array_equal(m, D.sample_columns(99, S, 6, real))
+    assert not np.array_equal(m, D.sample_columns(98, S, 5, real))
+
+
+def _mibf(n, r, tol, prm, sample, g):
+    x, xi = _grid_x(n), _grid_xi((-n // 2, -n // 2), n)
+    part, built, cidx = D.mibf_build(2, prm, x, xi, n, r, tol, sample=sample)
+    return x, xi, D.mibf_apply(2, prm, x, xi, g, built, cidx), D.nnz_mibf(built, cidx, len(x))
+
+
+def test_sampling_every_column_is_the_direct_svd():
+    """With S at least every block's column count every column is kept: the
+    sampled factorization is the direct one (same counts, same product up to
+    rounding)."""
+    g = _cn(32 * 32, 2, 11)
+    _, _, ud, nd = _mibf(32, 5, 1e-4, (2.0, 1.0, 16.0), None, g)
+    _, _, us, ns = _mibf(32, 5, 1e-4, (2.0, 1.0, 16.0), (7, 10 ** 6), g)
+    assert nd == ns
+    assert O.rel_error(us, ud) < 1e-13
+
+
+def test_sampling_exact_on_rank_one_blocks():
+    """The x-independent phase (kind 3: Phi = p0 xi1 + p1 xi2) makes every
+    block rank one: any kept column spans it, and the sampled MIBF equals
+    the dense product to rounding.  S = 12 of the middle blocks' 16 columns
+    (each kept with probability 3/4: a block keeps none with probability
+    4^-16); the sweeps' blocks have 4 real columns and keep all."""
+    n = 32
+    x, xi = _grid_x(n), _grid_xi((-n // 2, -n // 2), n)
+    g = _cn(n * n, 1, 12)
+    prm = (0.3, -0.7)
+    part, built, cidx = D.mibf_build(3, prm, x, xi, n, 4, 1e-10, sample=(5, 12))
+    u = D.mibf_apply(3, prm, x, xi, g, built, cidx)
+    ud = D.dense_apply_2d(3, prm, x, xi, g)
+    assert O.rel_error(u, ud) < 1e-12
+    assert all(int(np.max(k)) == 1 for _, _, _, O2 in built for k in O2.ranks.values())
+
+
+def test_sampled_accuracy_at_table4_r9():
+    """Table 4's r = 9 setting (32 x 32, c/32, tol 3e-6): sampling about 1.9
+    times the block ranks (S = 96) keeps the error within 1.5 times the
+    direct SVD's, 1.25 times (S = 64) within 4 times, both against the dense
+    product on 256 sampled rows; the compression ratio does not drop."""
+    n, prm = 32, (2.0, 1.0, 32.0)
+    g = _cn(n * n, 1, 8)
+    x, xi, ud, (pd, od) = _mibf(n, 9, 3e-6, prm, None, g)
+    rows = np.random.default_rng(9).choice(len(x), 256, replace=False)
+    dense = D.dense_apply_2d(2, prm, x, xi, g, rows=rows)
+    eps_d = O.rel_error(ud[rows], dense)
+    for S, fac in ((96, 1.5), (64, 4.0)):
+        _, _, us, (ps, os_) = _mibf(n, 9, 3e-6, prm, (12345, S), g)
+        eps_s = O.rel_error(us[rows], dense)
+        assert eps_s < fac * eps_d, (S, eps_s, eps_d)
+        assert ps / os_ >= pd / od
