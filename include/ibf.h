@@ -137,6 +137,18 @@ typedef struct {
   const float* predictor;    /* device, parameters of the learned order predictor
                                 (ibf_mlp_*; read by ibf_build when r <= 0) */
   int predictor_hidden;      /* its hidden width (8, 16 or 32) */
+  int svd_samples;           /* dim 2: > 0 selects the randomized low-rank approximation
+                                by column sampling (Sec. 2.1): every compressed block of
+                                n real columns keeps each column with probability
+                                min(1, svd_samples / n), its SVD stands for the block's
+                                (singular values scaled by sqrt(n / kept)), and the right
+                                factor is the projection of all columns; 0: the direct SVD */
+  uint64_t svd_seed;         /* the draws: column j of pair p in block family t (0 the
+                                middle, 1 + l the sweep toward U producing level l, 64 + l
+                                the one toward V producing level l - 1) is kept iff the
+                                top 53 bits of the (i + 1)-th SplitMix64 output from
+                                svd_seed, i = j + 2^9 p + 2^41 t, fall below that
+                                probability */
 } ibf_desc;
 
 /* Per-plan sizes and timings (filled by ibf_query). */
@@ -165,9 +177,10 @@ typedef struct {
  * into leaves, Sec. 3 "Preliminaries"; quadtrees and coronas for dim 2,
  * Sec. 5) and size every buffer.  No device work.  Errors: INVALID_ARG if
  * n < leaf^2, tol outside (0,1), a point outside its domain, leaf not a power
- * of two, sweep_in outside -1..1, a bad amplitude or fixed_ranks entry count;
- * UNSUPPORTED for dim other than 1 or 2, r > 16 (r > 9 for dim 2), an unknown
- * phase or amplitude, or an option dim 2 does not provide.  On success *out
+ * of two, sweep_in outside -1..1, a bad amplitude or fixed_ranks entry count,
+ * svd_samples < 0; UNSUPPORTED for dim other than 1 or 2, r > 16 (r > 9 for
+ * dim 2), an unknown phase or amplitude, an option dim 2 does not provide, or
+ * svd_samples > 0 for dim 1.  On success *out
  * owns the plan.
  */
 int ibf_plan(const ibf_desc* desc, ibf_plan_t* out);

@@ -85,6 +85,8 @@ struct Mibf2D {
   PhaseDesc ph{};
   int r = 0, R2 = 0, leaf_side = 0, precision = 0, device = 0;
   double tol = 0, W = 0;
+  int ssamp = 0;               // > 0: sampled low-rank approximation (columns kept ~ ssamp)
+  uint64_t sseed = 0;
   int64_t nx = 0, nxi = 0;
   double* d_x = nullptr;       // caller order [n][2]
   std::vector<XTree2> xtrees;
@@ -132,7 +134,35 @@ struct BoxDev {
   PhaseDesc ph;
   double o1, o2, w;
   int L, lV, h, r;
+  int ssamp;                   // > 0: column sampling of the compressed blocks (Sec. 2.1)
+  uint64_t sseed;
 };
+
+// Randomized low-rank approximation by column sampling (Sec. 2.1): column j
+// of pair p in block family `tag` (0 the middle, 1 + l the sweep toward U
+// producing level l, 64 + l the one toward V producing level l - 1) is kept
+// iff u < min(1, S / n) for its n real columns, u the top 53 bits of the
+// (i + 1)-th output of SplitMix64 (Steele, Lea and Flood 2014) started at the
+// seed, i = j + 2^9 p + 2^41 tag.  The kept columns' SVD stands for the
+// block's, with singular values scaled by sqrt(n / kept).
+__device__ __forceinline__ double splitmix64_u(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + (i + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (double)(z >> 11) * 0x1.0p-53;
+}
+__device__ __forceinline__ bool sample_kept(const BoxDev& B, int tag, int64_t pair, int col,
+                                            int nreal) {
+  if (B.ssamp <= 0) return true;
+  const double rho = fmin(1.0, (double)B.ssamp / (double)(nreal > 1 ? nreal : 1));
+  const uint64_t i = (uint64_t)col + ((uint64_t)pair << 9) + ((uint64_t)tag << 41);
+  return splitmix64_u(B.sseed, i) < rho;
+}
+// sqrt(n / kept), 0 when nothing was kept
+__device__ __forceinline__ double sample_scale(int nreal, int kept) {
+  return kept > 0 ? sqrt((double)nreal / (double)kept) : 0.0;
+}
 
 // ---------------------------------------------------------------------------
 // 2-D phase (Sec. 6.3) with exact mod-1 reduction of the coordinate products
@@ -366,7 +396,10 @@ __global__ __launch_bounds__(kB2) void k2_middle(BoxDev B, const double* __restr
   double2 gram[R2];
 #pragma unroll
   for (int j = 0; j < R2; ++j) gram[j] = make_double2(0.0, 0.0);
+  int kept = 0;
   for (int s = 0; s < R2; ++s) {
+    if (!sample_kept(B, 0, p, s, R2)) continue;
+    ++kept;
     const double2 w = row ? kval2(B.ph, ga1, ga2, gpt(cb1, wb, z[s / r]), gpt(cb2, wb, z[s % r]))
                           : make_double2(0.0, 0.0);
     double2 av = conjd(w);
@@ -379,6 +412,14 @@ __global__ __launch_bounds__(kB2) void k2_middle(BoxDev B, const double* __restr
   jacobi_eig<R2, G>(gram, sig);
   int pos[R2];
   const int k = rank_positions<R2>(sig, tol, pos);
+  if (B.ssamp > 0) {                                     // sampled: scale to the block
+    const double f = sample_scale(R2, kept);
+#pragma unroll
+    for (int j = 0; j < R2; ++j) {
+      gram[j] = cscale(gram[j], f);
+      sig[j] *= f;
+    }
+  }
   // C row t: u_j[t] sigma_j^(1/2)
   double2* crow = Cb + (p * R2 + tl) * R2;
 #pragma unroll
@@ -467,9 +508,13 @@ __global__ __launch_bounds__(kB2) void k2_sweep_g(BoxDev B, int l, const double*
     bs[c] = conjd(kval2(B.ph, gp1, gp2, cc1, cc2));    // lane s holds B_s
   }
   // W^* = Q R by Givens rotations, one column of W at a time; gram = R^*
+  const int nreal = kin[0] + kin[1] + kin[2] + kin[3];
+  int kept = 0;
 #pragma unroll
   for (int c = 0; c < 4; ++c)
     for (int m = 0; m < kin[c]; ++m) {
+      if (!sample_kept(B, 1 + l, p, c * R2 + m, nreal)) continue;
+      ++kept;
       double2 av = conjd(wcol(c, m, at[c], bs[c]));
       givens_fold<R2, G>(gram, av);
     }
@@ -479,6 +524,14 @@ __global__ __launch_bounds__(kB2) void k2_sweep_g(BoxDev B, int l, const double*
   jacobi_eig<R2, G>(gram, sig);                          // column j = sigma_j u_j
   int pos[R2];
   const int k = rank_positions<R2>(sig, tol, pos);
+  if (B.ssamp > 0) {
+    const double f = sample_scale(nreal, kept);
+#pragma unroll
+    for (int j = 0; j < R2; ++j) {
+      gram[j] = cscale(gram[j], f);
+      sig[j] *= f;
+    }
+  }
   double2* crow = Cout + (p * R2 + tl) * R2;             // C^l = U_k S_k
 #pragma unroll
   for (int j = 0; j < R2; ++j) {
@@ -575,9 +628,13 @@ __global__ __launch_bounds__(kB2) void k2_sweep_h(BoxDev B, int l, const double*
   double2 gram[R2];
 #pragma unroll
   for (int j = 0; j < R2; ++j) gram[j] = make_double2(0.0, 0.0);
+  const int nreal = kout[0] + kout[1] + kout[2] + kout[3];
+  int kept = 0;
 #pragma unroll
   for (int al = 0; al < 4; ++al)
     for (int m = 0; m < kout[al]; ++m) {
+      if (!sample_kept(B, 64 + l, q, al * R2 + m, nreal)) continue;
+      ++kept;
       double2 av = conjd(zcol(al, m));
       givens_fold<R2, G>(gram, av);
     }
@@ -587,6 +644,14 @@ __global__ __launch_bounds__(kB2) void k2_sweep_h(BoxDev B, int l, const double*
   jacobi_eig<R2, G>(gram, sig);                          // column j = sigma_j u_j
   int pos[R2];
   const int k = rank_positions<R2>(sig, tol, pos);
+  if (B.ssamp > 0) {
+    const double f = sample_scale(nreal, kept);
+#pragma unroll
+    for (int j = 0; j < R2; ++j) {
+      gram[j] = cscale(gram[j], f);
+      sig[j] *= f;
+    }
+  }
   double2* rrow = Rnext + (q * R2 + sl) * R2;            // R^{l-1} = U_k S_k
 #pragma unroll
   for (int j = 0; j < R2; ++j) {
@@ -803,6 +868,18 @@ __device__ __forceinline__ int k2l_rank(const double* nl, int* pl, int lane, dou
   return k;
 }
 
+// sampled blocks: the kept columns' singular values and left vectors scaled
+// to the block's (after the rank and positions are taken from the unscaled
+// values, as in the oracle)
+template <int R2>
+__device__ __forceinline__ void k2l_scale(double2* gm, double* nl, int lane, const BoxDev& B,
+                                          int nreal, int kept) {
+  if (B.ssamp <= 0) return;
+  const double f = sample_scale(nreal, kept);
+  for (int e = lane; e < R2 * k2l_stride<R2>(); e += kWaveL) gm[e] = cscale(gm[e], f);
+  for (int j = 0; j < R2; ++j) nl[j] *= f * f;
+}
+
 // entry (j, row k) of the wave's matrix, zero past the rows
 template <int R2>
 __device__ __forceinline__ double2 k2l_at(const double2* gm, int j, int k) {
@@ -862,7 +939,10 @@ __global__ __launch_bounds__(256) void k2l_middle(BoxDev B, const double* __rest
     for (int h = 0; h < RPL; ++h)
       w[h] = row[h] ? kval2(B.ph, ga1[h], ga2[h], gb1, gb2) : make_double2(0.0, 0.0);
   };
+  int kept = 0;
   for (int s = 0; s < R2; ++s) {
+    if (!sample_kept(B, 0, p, s, R2)) continue;
+    ++kept;
     double2 av[RPL];
     mcol(s, av);
 #pragma unroll
@@ -872,6 +952,7 @@ __global__ __launch_bounds__(256) void k2l_middle(BoxDev B, const double* __rest
   for (int e = lane; e < R2 * k2l_stride<R2>(); e += kWaveL) gm[e] = conjd(gm[e]);
   jacobi_eig_l<R2>(gm, nl, lane);
   const int k = k2l_rank<R2>(nl, pl, lane, tol);
+  k2l_scale<R2>(gm, nl, lane, B, R2, kept);
 #pragma unroll
   for (int h = 0; h < RPL; ++h) {
     const int t = lane + kWaveL * h;
@@ -970,9 +1051,13 @@ __global__ __launch_bounds__(256) void k2l_sweep_g(BoxDev B, int l, const double
 #pragma unroll
     for (int h = 0; h < RPL; ++h) w[h] = row[h] ? cmul(at[c][h], acc[h]) : make_double2(0.0, 0.0);
   };
+  const int nreal = kin[0] + kin[1] + kin[2] + kin[3];
+  int kept = 0;
 #pragma unroll
   for (int c = 0; c < 4; ++c)
     for (int m = 0; m < kin[c]; ++m) {
+      if (!sample_kept(B, 1 + l, p, c * R2 + m, nreal)) continue;
+      ++kept;
       double2 av[RPL];
       wcol(c, m, av);
 #pragma unroll
@@ -982,6 +1067,7 @@ __global__ __launch_bounds__(256) void k2l_sweep_g(BoxDev B, int l, const double
   for (int e = lane; e < R2 * k2l_stride<R2>(); e += kWaveL) gm[e] = conjd(gm[e]);
   jacobi_eig_l<R2>(gm, nl, lane);
   const int k = k2l_rank<R2>(nl, pl, lane, tol);
+  k2l_scale<R2>(gm, nl, lane, B, nreal, kept);
 #pragma unroll
   for (int h = 0; h < RPL; ++h) {
     if (!row[h]) continue;
@@ -1085,9 +1171,13 @@ __global__ __launch_bounds__(256) void k2l_sweep_h(BoxDev B, int l, const double
 #pragma unroll
     for (int h = 0; h < RPL; ++h) w[h] = row[h] ? cmul(ds[al][h], acc[h]) : make_double2(0.0, 0.0);
   };
+  const int nreal = kout[0] + kout[1] + kout[2] + kout[3];
+  int kept = 0;
 #pragma unroll
   for (int al = 0; al < 4; ++al)
     for (int m = 0; m < kout[al]; ++m) {
+      if (!sample_kept(B, 64 + l, q, al * R2 + m, nreal)) continue;
+      ++kept;
       double2 av[RPL];
       zcol(al, m, av);
 #pragma unroll
@@ -1097,6 +1187,7 @@ __global__ __launch_bounds__(256) void k2l_sweep_h(BoxDev B, int l, const double
   for (int e = lane; e < R2 * k2l_stride<R2>(); e += kWaveL) gm[e] = conjd(gm[e]);
   jacobi_eig_l<R2>(gm, nl, lane);
   const int k = k2l_rank<R2>(nl, pl, lane, tol);
+  k2l_scale<R2>(gm, nl, lane, B, nreal, kept);
 #pragma unroll
   for (int h = 0; h < RPL; ++h) {
     if (!row[h]) continue;
@@ -1781,7 +1872,7 @@ int build2d_t(ibf_plan_t p, hipStream_t s) {
 
   int rc;
   for (Box2& bx : M.boxes) {
-    const BoxDev B{M.ph, bx.o1, bx.o2, bx.w, bx.L, bx.lV, bx.h, r};
+    const BoxDev B{M.ph, bx.o1, bx.o2, bx.w, bx.L, bx.lV, bx.h, r, M.ssamp, M.sseed};
     const int L = bx.L, lV = bx.lV, h = bx.h;
     const int64_t np = (int64_t)1 << (2 * L);
     const int G = R2 <= 32 ? 32 : 64;                        // lanes per pair (group2<R2>)
@@ -2237,6 +2328,7 @@ int plan2d(const ibf_desc* d, ibf_plan_t* out) {
     set_error("ibf_plan: amplitudes and fixed ranks are provided for dim 1");
     return IBF_ERR_UNSUPPORTED;
   }
+  if (d->svd_samples < 0) return bad("ibf_plan: svd_samples < 0");
   const double W = d->omega_width;
   int Lw = 0;
   while ((double)((int64_t)1 << Lw) < W) ++Lw;
@@ -2275,6 +2367,8 @@ int plan2d(const ibf_desc* d, ibf_plan_t* out) {
   M->precision = d->precision;
   M->device = d->device;
   M->tol = d->tol;
+  M->ssamp = d->svd_samples;
+  M->sseed = d->svd_seed;
   M->W = W;
   M->nx = d->n_x;
   M->nxi = d->n_xi;

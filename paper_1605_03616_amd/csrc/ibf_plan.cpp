@@ -163,6 +163,11 @@ int ibf_plan(const ibf_desc* d, ibf_plan_t* out) {
     return fail(IBF_ERR_INVALID_ARG, "ibf_plan: unknown precision");
   if (d->sweep_in < -1 || d->sweep_in > 1)
     return fail(IBF_ERR_INVALID_ARG, "ibf_plan: sweep_in must be -1, 0 or 1");
+  if (d->svd_samples < 0) return fail(IBF_ERR_INVALID_ARG, "ibf_plan: svd_samples < 0");
+  if (d->svd_samples > 0)
+    return fail(IBF_ERR_UNSUPPORTED,
+                "ibf_plan: the sampled low-rank approximation is provided for dim 2 (the 1-D "
+                "blocks have at most 32 columns)");
 
   ibf::PhaseDesc ph{};
   ph.kind = d->phase_id;

@@ -57,6 +57,8 @@ class IBFDesc(C.Structure):
         ("n_amp_params", C.c_int),
         ("predictor", C.c_void_p),
         ("predictor_hidden", C.c_int),
+        ("svd_samples", C.c_int),
+        ("svd_seed", C.c_uint64),
     ]
 
 
@@ -238,12 +240,13 @@ def _stream_handle(stream):
 
 def make_desc(x, xi, phase, params, r, tol, leaf, precision, sweep_in=0,
               omega_lo=None, omega_width=0.0, device=0, fixed_ranks=None, amp=None,
-              predictor=None):
+              predictor=None, svd_sample=None):
     """Build an ibf_desc; returns (desc, keepalive) -- keep both alive.
 
     fixed_ranks: per-level rank caps (levels l0 .. L - l0) or None; amp:
     (amp_id, params) or None; predictor: (device float tensor, hidden width)
-    for r <= 0, or None."""
+    for r <= 0, or None; svd_sample: (seed, samples) for the randomized
+    low-rank approximation (dim 2), or None."""
     x = np.ascontiguousarray(x, dtype=np.float64)
     xi = np.ascontiguousarray(xi, dtype=np.float64)
     prm = np.ascontiguousarray(params if params is not None else [], dtype=np.float64)
@@ -279,6 +282,9 @@ def make_desc(x, xi, phase, params, r, tol, leaf, precision, sweep_in=0,
     if predictor is not None:
         d.predictor = C.c_void_p(predictor[0].data_ptr())
         d.predictor_hidden = int(predictor[1])
+    if svd_sample is not None:
+        d.svd_seed = int(svd_sample[0]) & 0xFFFFFFFFFFFFFFFF
+        d.svd_samples = int(svd_sample[1])
     return d, (x, xi, prm, caps, aprm)
 
 
@@ -288,11 +294,12 @@ class Plan:
 
     def __init__(self, x, xi, phase, params, r, tol, leaf=16, precision=PREC_FP64,
                  sweep_in=0, omega_lo=None, omega_width=0.0, device=0, fixed_ranks=None,
-                 amp=None, predictor=None):
+                 amp=None, predictor=None, svd_sample=None):
         lib = load()
         self._lib = lib
         d, keep = make_desc(x, xi, phase, params, r, tol, leaf, precision, sweep_in,
-                            omega_lo, omega_width, device, fixed_ranks, amp, predictor)
+                            omega_lo, omega_width, device, fixed_ranks, amp, predictor,
+                            svd_sample)
         # the predictor's parameters are read by ibf_build: keep them alive
         self._predictor = predictor
         h = C.c_void_p()
@@ -304,11 +311,11 @@ class Plan:
         self.device = device
 
     @classmethod
-    def from_problem(cls, P, precision=None, sweep_in=None):
+    def from_problem(cls, P, precision=None, sweep_in=None, svd_sample=None):
         return cls(P.x, P.xi, P.phase, P.params, P.r, P.tol, P.leaf,
                    P.precision if precision is None else precision,
                    P.sweep_in if sweep_in is None else sweep_in,
-                   omega_width=P.extra.get("omega_width", 0.0))
+                   omega_width=P.extra.get("omega_width", 0.0), svd_sample=svd_sample)
 
     def build(self, stream=None):
         _check(self._lib.ibf_build(self.handle, _stream_handle(stream)))

@@ -241,3 +241,23 @@ def test_build_batch_validates_on_the_host():
     holes = (C.c_void_p * 2)(pl.handle, None)
     assert lib.ibf_build_batch(holes, 2, 0, None, None) == -1
     pl.destroy()
+
+
+def test_sampled_svd_descriptor_validation():
+    """svd_samples: negative is INVALID_ARG; the 1-D plans (blocks of at most
+    32 columns) leave the sampled approximation out: UNSUPPORTED; dim 2
+    accepts it on the host."""
+    with pytest.raises(ibf.IBFError) as e:
+        _plan(svd_sample=(1, -3))
+    assert e.value.code == -1
+    with pytest.raises(ibf.IBFError) as e:
+        _plan(svd_sample=(1, 16))
+    assert e.value.code == -2
+    n = 32
+    i1, i2 = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    x = np.stack([i1.ravel() / n, i2.ravel() / n], -1)
+    xi = np.stack([i1.ravel() - n // 2, i2.ravel() - n // 2], -1).astype(np.float64)
+    ibf.Plan(x, xi, 2, (2.0, 1.0, 16.0), 6, 1e-3, 16, I.PREC_FP32, svd_sample=(7, 24)).destroy()
+    with pytest.raises(ibf.IBFError) as e:
+        ibf.Plan(x, xi, 2, (2.0, 1.0, 16.0), 6, 1e-3, 16, I.PREC_FP32, svd_sample=(7, -1))
+    assert e.value.code == -1

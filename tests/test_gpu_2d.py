@@ -212,3 +212,41 @@ def test_2d_high_order_against_oracle(torch_dev, n, r, tol, table4, precision):
         ud = D.dense_apply_2d(P.phase, P.params, P.x, P.xi, P.g[:, :1], rows=rows)
         eps = O.rel_error(ug[rows, :1], ud)
         assert eps_p / 4 < eps < 1.5 * eps_p, (eps, eps_p)
+
+
+@functools.lru_cache(maxsize=None)
+def _case_sampled(n, r, tol, table4, seed, S):
+    P = I.fio2d_grid(n, r, 2, 48, tol=tol, precision=I.PREC_FP64)
+    if table4:
+        P.params = TABLE4_PARAMS
+    part, built, cidx = D.mibf_build(P.phase, P.params, P.x, P.xi, n, r, P.tol,
+                                     sample=(seed, S))
+    u = D.mibf_apply(P.phase, P.params, P.x, P.xi, P.g, built, cidx)
+    pre, opt = D.nnz_mibf(built, cidx, len(P.x))
+    return P, u, pre, opt
+
+
+@pytest.mark.parametrize("n,r,tol,table4,S,precision", [
+    (32, 5, 1e-4, False, 16, I.PREC_FP64), (32, 9, 3e-6, True, 64, I.PREC_FP64),
+    (32, 9, 3e-6, True, 96, I.PREC_FP32), (32, 6, 1e-3, True, 30, I.PREC_FP64)])
+def test_2d_sampled_svd_against_oracle(torch_dev, n, r, tol, table4, S, precision):
+    """The randomized low-rank approximation (column sampling, svd_samples =
+    S) on the register (r = 5) and LDS (r = 6, 9) compression kernels against
+    the oracle's sampled factorization with the same seed: identical
+    preliminary and stored entry counts (the same columns kept and the same
+    ranks), FP64 at its bar, FP32 at 1e-5."""
+    from paper_1605_03616_amd import ibf
+    torch = torch_dev
+    seed = 0x5EED0000 + 17 * r + S
+    _say(f"2-D sampled SVD n={n} r={r} tol={tol} S={S} precision={precision}")
+    P, uo, pre, opt = _case_sampled(n, r, tol, table4, seed, S)
+    pl = ibf.Plan.from_problem(P, precision=precision, svd_sample=(seed, S)).build()
+    dt = torch.complex128 if precision == I.PREC_FP64 else torch.complex64
+    g = torch.from_numpy(np.ascontiguousarray(P.g.T)).to(dt).cuda()
+    ug = pl.apply(g).cpu().numpy().T.astype(np.complex128)
+    q = pl.query()
+    pl.destroy()
+    bar = fp64_bar(n) if precision == I.PREC_FP64 else 1e-5
+    assert q["nnz_prelim"] == pre and q["nnz_opt"] == opt
+    assert _rel(ug, uo) <= bar
+    assert O.rel_error_cols(ug, uo) <= bar
