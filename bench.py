@@ -66,15 +66,26 @@ def _measured_traffic(workload, schedule, kernel):
     return tot / n
 
 
-def _workload(name, nrhs=None):
+def _workload(name, nrhs=None, precision=None):
+    """The named workload; `precision` ("fp32", "bf16x2", "fp64") replaces
+    the storage precision of its factors (the workload name then carries it)."""
+    import dataclasses
+
     from paper_1605_03616_amd import inputs as I
     if name == "fio1d_64k":
-        return I.workload_fio1d_64k(nrhs=nrhs or 64)
-    if name == "nudft_1m":
-        return I.workload_nudft_1m(nrhs=nrhs or 16)
-    if name == "fio1d_1k":
-        return I.workload_fio1d_1k()
-    raise SystemExit(f"unknown workload {name}")
+        P = I.workload_fio1d_64k(nrhs=nrhs or 64)
+    elif name == "nudft_1m":
+        P = I.workload_nudft_1m(nrhs=nrhs or 16)
+    elif name == "fio1d_1k":
+        P = I.workload_fio1d_1k()
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    if precision:
+        prec = {"fp64": I.PREC_FP64, "fp32": I.PREC_FP32, "bf16x2": I.PREC_BF16X2}[precision]
+        if prec != P.precision:
+            base = P.name[:-5] if P.name.endswith("_fp32") else P.name
+            P = dataclasses.replace(P, precision=prec, name=f"{base}_{precision}")
+    return P
 
 
 def _roofline(launches, bound, peak, unit):
@@ -359,7 +370,7 @@ def _bench_adjoint(args):
 
     ibf.load()
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
-    P = _workload(args.workload, args.nrhs)
+    P = _workload(args.workload, args.nrhs, args.precision)
     dt = torch.complex128 if P.precision == I.PREC_FP64 else torch.complex64
     sw = int(getattr(P, "sweep_in", 0) or 0)
     pl = ibf.Plan(P.x, P.xi, P.phase, P.params, P.r, P.tol, P.leaf, P.precision, sw).build()
@@ -420,6 +431,8 @@ def main():
                     help="untimed steps first (the clocks ramp up over the first ~0.1 s)")
     ap.add_argument("--workload", default="fio1d_64k")
     ap.add_argument("--nrhs", type=int, default=None)
+    ap.add_argument("--precision", choices=["fp32", "bf16x2", "fp64"], default=None,
+                    help="factor storage precision in place of the workload's own (1-D)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
@@ -459,7 +472,7 @@ def main():
 
     ibf.load()
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
-    P = _workload(args.workload, args.nrhs)
+    P = _workload(args.workload, args.nrhs, args.precision)
     dt = torch.complex128 if P.precision == I.PREC_FP64 else torch.complex64
     print(f"[bench] workload {P.name} N={P.n} r={P.r} nrhs={P.nrhs} precision={P.precision}",
           file=sys.stderr, flush=True)
@@ -520,8 +533,13 @@ def main():
         bound, peak = ("hbm", HBM_PEAK_GBS) if P.nrhs < 8 else ("mfma", FP64_PEAK_TFS)
     elif P.precision == I.PREC_FP32:
         bound, peak = ("mfma", FP32_PEAK_TFS) if P.nrhs >= 32 else ("hbm", HBM_PEAK_GBS)
-    else:   # BF16X2 factors are widened to FP32 and multiplied on FP32 MFMA
-        bound, peak = ("hbm", HBM_PEAK_GBS) if P.nrhs < 64 else ("mfma", FP32_PEAK_TFS)
+    else:
+        # BF16X2: the per-pair-rank stages multiply BF16 split products on the
+        # bf16 MFMA (three bf16 products per algorithmic one, priced at the
+        # published bf16 peak); the other stage kernels widen to FP32
+        split = any(x[0] == "apply_stage_tight_split" for x in launches)
+        bound, peak = ("hbm", HBM_PEAK_GBS) if P.nrhs < 64 else (
+            "mfma", BF16_PEAK_TFS if split else FP32_PEAK_TFS)
     unit = "TFLOP/s" if bound == "mfma" else "GB/s"
     dom, roof, per_class = _roofline(launches, bound, peak, unit)
     sched = (f"{tuning['path']}/{tuning['chunk']}/{tuning['max_fused']}" if tuning
@@ -531,7 +549,7 @@ def main():
     roof["traffic"] = _measured_traffic(P.name, sched, dom)
     if roof["traffic"] is not None:
         roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)"
-    if not args.no_measured_peak:
+    if not args.no_measured_peak and peak != BF16_PEAK_TFS:
         # the same bound measured on this device: a plain 1 GiB copy, or a loop
         # of the FP32 4x4x1 MFMA instruction the stage kernels issue
         what = ibf.PEAK_HBM_COPY if bound == "hbm" else ibf.PEAK_MFMA_F32

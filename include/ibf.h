@@ -160,7 +160,9 @@ typedef struct {
   int64_t nnz_prelim;        /* complex entries of the preliminary IBF */
   int64_t nnz_opt;           /* complex entries of the compressed IBF, each block at its own rank */
   int64_t nnz_stored;        /* complex entries stored (blocks padded to the level rank) */
-  int64_t factor_bytes;      /* device bytes of the stored factors */
+  int64_t factor_bytes;      /* device bytes of the stored factors (BF16X2 plans without
+                                the sweep-in include the stage blocks' second copy as
+                                16-byte quad records for the BF16 split products) */
   double build_ms;           /* wall time of the last ibf_build */
   int smax_x, smax_xi;       /* largest leaf populations */
   int sweep_in;              /* 1 when the sweep-in stage ran */
@@ -301,12 +303,13 @@ int ibf_apply_profile(ibf_plan_t plan, const void* g, int64_t ldg, void* u,
  * right-hand sides on the caller's vectors (same arguments and layout as
  * ibf_apply; u is overwritten with the product) and keeps the fastest in the
  * plan: later ibf_apply calls with this nrhs, and batches containing the plan,
- * use it (batches run path 3 as path 2).  Candidates: the default rule;
+ * use it (batches run paths 3 and 4 as path 2).  Candidates: the default rule;
  * butterfly stages on the vector kernels; on MFMA (FP32 state) with 32- or
- * 16-column RHS chunks; on MFMA at each pair's own ranks; at most 2 or 3
+ * 16-column RHS chunks; on MFMA at each pair's own ranks (for BF16X2 plans
+ * with FP32 and with BF16 split products); at most 2 or 3
  * stages fused per launch; fused groups ending where the stage tile (the even
  * cover of the ranks) changes.  Every candidate computes the same product (to
- * FP32 rounding).  Synchronises the stream (not for use under graph capture).
+ * FP32 rounding; BF16 split products to about 2^-16 relative).  Synchronises the stream (not for use under graph capture).
  * *best receives the chosen schedule and its time, *dflt the default rule's
  * time (either may be NULL).
  * Errors: as ibf_apply; UNSUPPORTED for dim-2 plans.
@@ -314,7 +317,12 @@ int ibf_apply_profile(ibf_plan_t plan, const void* g, int64_t ldg, void* u,
 typedef struct {
   int path;        /* 0 default rule, 1 vector stage kernels, 2 MFMA stage kernels,
                       3 MFMA stage kernels at each pair's own ranks (64-column chunks,
-                      up to 4 stages a launch; plans built with the sweep-in run path 2) */
+                      up to 4 stages a launch; plans built with the sweep-in run path 2;
+                      BF16X2 factors widened to FP32), 4 the same with BF16 split
+                      products (BF16X2 plans only: the stored bf16 hi and lo parts
+                      against a bf16 hi/lo split of the FP32 state, hi.hi + hi.lo +
+                      lo.hi on the bf16 MFMA with FP32 accumulation; the default rule
+                      for BF16X2 plans from 64 RHS) */
   int chunk;       /* MFMA RHS chunk width (32 or 16; 0 = by nrhs) */
   int max_fused;   /* most stages fused per launch (0 = as LDS allows) */
   float ms;        /* measured time of one apply */
@@ -331,9 +339,10 @@ int ibf_tune(ibf_plan_t plan, const void* g, int64_t ldg, void* u, int64_t ldu,
  * schedule for profiling); t == NULL returns that nrhs to the default rule.
  * t->ms is ignored.  Same product as ibf_apply (Sec. 4).  Host only: no
  * device call, no allocation.
- * Errors: INVALID_ARG (NULL plan, nrhs < 1, path outside 0..3, chunk not 0,
- * 16 or 32, max_fused < 0, split outside 0..2); UNSUPPORTED for dim-2 plans and for paths 2
- * and 3 on FP64 plans (no FP64 MFMA stage kernel).
+ * Errors: INVALID_ARG (NULL plan, nrhs < 1, path outside 0..4, chunk not 0,
+ * 16 or 32, max_fused < 0, split outside 0..2); UNSUPPORTED for dim-2 plans, for paths 2
+ * and 3 on FP64 plans (no FP64 MFMA stage kernel) and for path 4 on plans that are
+ * not BF16X2.
  */
 int ibf_set_tuning(ibf_plan_t plan, int64_t nrhs, const ibf_tuning* t);
 

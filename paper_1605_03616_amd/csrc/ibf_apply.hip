@@ -729,6 +729,7 @@ struct TightArgs {
   int kst[kMaxR + 1];                // stored rank at level l_start - 1 + j (HBM row stride)
   int kld[kMaxR];                    // stored row length of stage j's blocks
   const void* blk[kMaxR];
+  const void* qblk[kMaxR];           // split products: stage j's quad records
   const uint8_t* prk[kMaxR + 1];     // per-pair ranks at level l_start - 1 + j
 };
 struct TightDesc {
@@ -765,12 +766,83 @@ __device__ __forceinline__ void tight_row(float a, float2 x, v4f (&P)[KG], v4f (
   }
 }
 
-template <typename FT, int KT>
+// ---------------------------------------------------------------------------
+// BF16 split products (BF16X2 plans).  A stored factor entry is bf16 hi + lo
+// (the FP64 value rounded to bf16, then the rest rounded to bf16); the FP32
+// state is split the same way when it is written to LDS.  One
+// v_mfma_f32_4x4x4_16b_bf16 multiplies four state rows at once (the K index
+// of the instruction runs over the rows), and a product is the three terms
+// hi.hi + hi.lo + lo.hi accumulated in FP32 (the dropped lo.lo term is
+// below 2^-16 of the product).  A block of 4 rows x 4 floats of the factor
+// (the 4 floats (re t0, im t0, re t1, im t1) of an output row pair, K = the 4
+// input rows) is broadcast from lanes 32 h + 4 g + i to all 16 blocks, as in
+// the FP32 form above.
+//
+// State layout in LDS: per slot and 4-row quad, a record of 16 bytes a lane
+// (column) for the hi parts {re rows 0-1, re rows 2-3, im rows 0-1, im rows
+// 2-3} followed by the same for the lo parts: [slot][quad][hi|lo][64] uint4.
+// Rows past a pair's rank inside its last quad hold zeros.
+// ---------------------------------------------------------------------------
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned pack_bf16x2(float a, float b) {
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(unsigned, __builtin_convertvector((f2v){a, b}, b2v));
+}
+// hi = (bf16(a), bf16(b)) rounded to nearest even, lo = the same of the rests
+// (a - hi is exact in FP32)
+__device__ __forceinline__ void split_bf16(float a, float b, unsigned& hi, unsigned& lo) {
+  hi = pack_bf16x2(a, b);
+  lo = pack_bf16x2(a - __uint_as_float(hi << 16), b - __uint_as_float(hi & 0xffff0000u));
+}
+
+// P[g] += A x B_re, Q[g] += A x B_im for g < NG, A broadcast from block 8 H + g
+template <int H, int NG, int KG, int G = 0>
+__device__ __forceinline__ void split_terms(v4s a, v4s bre, v4s bim, v4f (&P)[KG], v4f (&Q)[KG]) {
+  if constexpr (G < NG) {
+    P[G] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(a, bre, P[G], 4, 8 * H + G, 0);
+    Q[G] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(a, bim, Q[G], 4, 8 * H + G, 0);
+    split_terms<H, NG, KG, G + 1>(a, bre, bim, P, Q);
+  }
+}
+// one 4-row window: factor hi/lo (ah, al) against the state record (xh, xl)
+template <int H, int NG, int KG>
+__device__ __forceinline__ void split_window(uint2 ah, uint2 al, uint4 xh, uint4 xl,
+                                             v4f (&P)[KG], v4f (&Q)[KG]) {
+  const v4s Ah = __builtin_bit_cast(v4s, ah), Al = __builtin_bit_cast(v4s, al);
+  const v4s Rh = __builtin_bit_cast(v4s, make_uint2(xh.x, xh.y));
+  const v4s Ih = __builtin_bit_cast(v4s, make_uint2(xh.z, xh.w));
+  const v4s Rl = __builtin_bit_cast(v4s, make_uint2(xl.x, xl.y));
+  const v4s Il = __builtin_bit_cast(v4s, make_uint2(xl.z, xl.w));
+  split_terms<H, NG, KG>(Ah, Rh, Ih, P, Q);
+  split_terms<H, NG, KG>(Ah, Rl, Il, P, Q);
+  split_terms<H, NG, KG>(Al, Rh, Ih, P, Q);
+}
+// a quad record from four complex rows (zeros past `live` rows)
+__device__ __forceinline__ void split_quad(const float2 (&v)[4], uint4& h, uint4& l) {
+  split_bf16(v[0].x, v[1].x, h.x, l.x);
+  split_bf16(v[2].x, v[3].x, h.y, l.y);
+  split_bf16(v[0].y, v[1].y, h.z, l.z);
+  split_bf16(v[2].y, v[3].y, h.w, l.w);
+}
+
+// factor windows held in registers: FP32 form, 2 rows a window (one float a
+// lane); split form, 8 rows a register pair (hi and lo, 4 bf16 a lane each)
+template <bool SPLIT, int KT> struct TightWin { float a[KT]; };
+template <int KT> struct TightWin<true, KT> {
+  uint2 h[(KT + 3) / 4], l[(KT + 3) / 4];
+};
+
+template <typename FT, int KT, bool SPLIT>
 __device__ __forceinline__ void tight_body(const TightDesc& D, int64_t lb, int64_t lstep,
                                            int64_t lend) {
   constexpr int NB = 64;
   constexpr int KG = KT / 2;                                  // most row pairs of an output
   constexpr int WC = KT / 2;                                  // most windows per child
+  constexpr int WQ = (KT + 3) / 4;                            // split: most quads per child
+  constexpr int WR = WQ;                                      // split: window registers (2 quads each)
+  static_assert(!SPLIT || std::is_same<FT, bf16x2c>::value, "split products need BF16X2 factors");
   extern __shared__ __align__(16) unsigned char smem[];
   const float2* __restrict__ in = reinterpret_cast<const float2*>(D.in);
   float2* __restrict__ out = reinterpret_cast<float2*>(D.out);
@@ -778,6 +850,8 @@ __device__ __forceinline__ void tight_body(const TightDesc& D, int64_t lb, int64
   const int L = A.L, nrhs = A.nrhs, nchunk = A.nchunk, KS = A.KS;
   const int K4 = A.nst;                                       // stages = log2(waves)
   float2* S = reinterpret_cast<float2*>(smem);                // [2^k][KS][64]
+  uint4* S4 = reinterpret_cast<uint4*>(smem);                 // split: [2^k][KQ][2][64]
+  const int KQ = (KS + 3) >> 2;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int half = lane >> 5, e = lane & 31;
@@ -825,17 +899,37 @@ __device__ __forceinline__ void tight_body(const TightDesc& D, int64_t lb, int64
   // rank, so every window loads and the code is straight-line; the lanes
   // past a row's 2 kld floats read the next row or the slack past the
   // stage's blocks, and are never used)
-  auto load_windows = [&](int j, const StageWork& s, float (&aw)[2 * WC]) {
+  auto load_windows = [&](int j, const StageWork& s, TightWin<SPLIT, KT>& W) {
     const int kld = A.kld[j], Kin = A.kst[j];
-    const int rowf = 2 * kld;                                 // floats a row
-    const FT* fb = reinterpret_cast<const FT*>(A.blk[j]) + s.pout * (int64_t)(2 * Kin * kld);
+    if constexpr (SPLIT) {
+      // The 2 WQ quads of the two children, child 0 first, are numbered
+      // v = c WQ + i; register m holds quads 2 m (lanes 0-31) and 2 m + 1
+      // (lanes 32-63).  Lane 32 h + 4 g + i takes the record of float
+      // f = 4 g + i of quad 2 m + h: bf16 hi and lo of rows 4 q .. 4 q + 3,
+      // already in operand order.  f is clamped into the row and q into the
+      // child's quads, so every load stays inside the pair's records (the
+      // clamped ones feed only unused blocks or rows that meet zero state).
+      const int nq = (Kin + 3) >> 2, nf = 2 * kld;
+      const uint4* qb = reinterpret_cast<const uint4*>(A.qblk[j]) + s.pout * (int64_t)(2 * nq * nf);
+      const int f = min(e, nf - 1);
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const int rmax = max((c ? s.kin1 : s.kin0) - 1, 0);
+      for (int m = 0; m < WR; ++m) {
+        const int v = 2 * m + half, c = v >= WQ ? 1 : 0, q = min(v - c * WQ, nq - 1);
+        const uint4 d = qb[(c * nq + q) * nf + f];
+        W.h[m] = make_uint2(d.x, d.y);
+        W.l[m] = make_uint2(d.z, d.w);
+      }
+    } else {
+      const int rowf = 2 * kld;                               // floats a row
+      const FT* fb = reinterpret_cast<const FT*>(A.blk[j]) + s.pout * (int64_t)(2 * Kin * kld);
 #pragma unroll
-      for (int i = 0; i < WC; ++i) {
-        const int row = c * Kin + min(2 * i + half, rmax);
-        aw[c * WC + i] = block_float(fb, 0, (unsigned)(row * rowf + e));
+      for (int c = 0; c < 2; ++c) {
+        const int rmax = max((c ? s.kin1 : s.kin0) - 1, 0);
+#pragma unroll
+        for (int i = 0; i < WC; ++i) {
+          const int row = c * Kin + min(2 * i + half, rmax);
+          W.a[c * WC + i] = block_float(fb, 0, (unsigned)(row * rowf + e));
+        }
       }
     }
   };
@@ -855,6 +949,26 @@ __device__ __forceinline__ void tight_body(const TightDesc& D, int64_t lb, int64
   };
   auto deposit_inputs = [&](const Grp& g) {
     const int kin = A.prk[0][(g.gid << K4) | w];
+    if constexpr (SPLIT) {
+      uint4* dst = S4 + (size_t)w * KQ * 128 + lane;
+#pragma unroll
+      for (int q = 0; q < WQ; ++q) {
+        if (4 * q < kin) {
+          float2 v[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int r = 4 * q + k;
+            v[k] = make_float2(0.f, 0.f);
+            if (r < KT) v[k] = r < kin ? xin[r < KT ? r : 0] : make_float2(0.f, 0.f);
+          }
+          uint4 h, l;
+          split_quad(v, h, l);
+          dst[q * 128] = h;
+          dst[q * 128 + 64] = l;
+        }
+      }
+      return;
+    }
     float2* dst = S + (size_t)w * KS * NB + lane;
 #pragma unroll
     for (int i = 0; i < KT; ++i)
@@ -863,7 +977,7 @@ __device__ __forceinline__ void tight_body(const TightDesc& D, int64_t lb, int64
 
   Grp cur = decode(lb);
   fetch_inputs(cur);
-  float aw[2 * WC], an[2 * WC];
+  TightWin<SPLIT, KT> aw, an;
   StageWork sw = stage_work(cur, 0);
   load_windows(0, sw, aw);
   deposit_inputs(cur);
@@ -906,6 +1020,26 @@ __device__ __forceinline__ void tight_body(const TightDesc& D, int64_t lb, int64
       // branches take scalar-unit issue slots, which the SIMDs of a CU share)
       auto product = [&](auto ng_c) {
         constexpr int NG = decltype(ng_c)::value;
+        if constexpr (SPLIT) {
+          // the child's quads, the last first (a chain of guarded blocks);
+          // a quad's state records are read from LDS just before its MFMAs
+          // (the other waves of the SIMD keep the MFMA unit busy meanwhile)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const int nwin = ((c ? sw.kin1 : sw.kin0) + 3) >> 2;
+            const uint4* X = S4 + (size_t)(sw.in0 + c) * KQ * 128 + lane;
+#pragma unroll
+            for (int i = WQ - 1; i >= 0; --i) {
+              if (i < nwin) {
+                const uint4 xh = X[i * 128], xl = X[i * 128 + 64];
+                const int v = c * WQ + i;
+                const uint2 ah = aw.h[v >> 1], al = aw.l[v >> 1];
+                if (v & 1) split_window<1, NG, KG>(ah, al, xh, xl, P, Q);
+                else split_window<0, NG, KG>(ah, al, xh, xl, P, Q);
+              }
+            }
+          }
+        } else {
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
           const int kin = c ? sw.kin1 : sw.kin0;
@@ -921,13 +1055,14 @@ __device__ __forceinline__ void tight_body(const TightDesc& D, int64_t lb, int64
                 y0 = X[(2 * i - 2) * NB];
                 y1 = X[(2 * i - 1) * NB];
               }
-              const float a = aw[c * WC + i];
+              const float a = aw.a[c * WC + i];
               tight_row<0, NG, KG>(a, x0, P, Q);
               if (2 * i + 1 < kin) tight_row<1, NG, KG>(a, x1, P, Q);
               x0 = y0;
               x1 = y1;
             }
           }
+        }
         }
       };
       switch (ng) {
@@ -942,7 +1077,32 @@ __device__ __forceinline__ void tight_body(const TightDesc& D, int64_t lb, int64
         default: break;                                       // rank 0: a zero output
       }
       __syncthreads();                                        // every wave read its inputs
-      if (!last) {
+      if (!last && SPLIT) {
+        // outputs as quad records (rows past the output's rank zero)
+        uint4* dst = S4 + (size_t)w * KQ * 128 + lane;
+#pragma unroll
+        for (int q = 0; q < (KG + 1) / 2; ++q) {
+          if (4 * q < sw.kout) {
+            float2 v[4];
+#pragma unroll
+            for (int s2 = 0; s2 < 2; ++s2) {
+              const int g = 2 * q + s2;
+              v4f pp = v4f{0.f, 0.f, 0.f, 0.f}, qq = v4f{0.f, 0.f, 0.f, 0.f};
+              if (g < KG) {
+                pp = P[g < KG ? g : 0];
+                qq = Q[g < KG ? g : 0];
+              }
+              const bool l0 = 2 * g < sw.kout, l1 = 2 * g + 1 < sw.kout;
+              v[2 * s2] = l0 ? make_float2(pp[0] - qq[1], pp[1] + qq[0]) : make_float2(0.f, 0.f);
+              v[2 * s2 + 1] = l1 ? make_float2(pp[2] - qq[3], pp[3] + qq[2]) : make_float2(0.f, 0.f);
+            }
+            uint4 h, l;
+            split_quad(v, h, l);
+            dst[q * 128] = h;
+            dst[q * 128 + 64] = l;
+          }
+        }
+      } else if (!last) {
         float2* dst = S + (size_t)w * KS * NB + lane;
 #pragma unroll
         for (int g = 0; g < KG; ++g) {
@@ -971,8 +1131,7 @@ __device__ __forceinline__ void tight_body(const TightDesc& D, int64_t lb, int64
       }
       if (!last || more) {
         sw = sn;
-#pragma unroll
-        for (int i = 0; i < 2 * WC; ++i) aw[i] = an[i];
+        aw = an;
       }
       if (!last) __syncthreads();                             // outputs in place
     }
@@ -991,7 +1150,12 @@ constexpr int tight_max_waves() { return KT > 12 ? 8 : 16; }
 template <typename FT, int KT>
 __global__ __launch_bounds__(64 * tight_max_waves<KT>()) void k_apply_tight(TightDesc D,
                                                                             int64_t total) {
-  tight_body<FT, KT>(D, blockIdx.x, (int64_t)gridDim.x, total);
+  tight_body<FT, KT, false>(D, blockIdx.x, (int64_t)gridDim.x, total);
+}
+template <int KT>
+__global__ __launch_bounds__(64 * tight_max_waves<KT>()) void k_apply_tight_split(TightDesc D,
+                                                                                  int64_t total) {
+  tight_body<bf16x2c, KT, true>(D, blockIdx.x, (int64_t)gridDim.x, total);
 }
 
 // Middle block of the swept-in factorization: out[p][t][n] = sum_s Mdot[p][t][s] in[p][s][n]
@@ -1403,6 +1567,7 @@ struct Launch {
   LaunchKind kind;
   int kt = 2;
   bool mfma = false;
+  bool split = false;                // per-pair-rank stages with BF16 split products
   size_t lds = 0;
   int64_t nblocks = 0;
   double flops = 0, bytes = 0, vec_bytes = 0;
@@ -1418,7 +1583,7 @@ inline const char* launch_name(const Launch& x) {
     case kLaunchV: return x.mfma ? "apply_v_mfma" : "apply_v";
     case kLaunchFused: return x.mfma ? "apply_fused_mfma" : "apply_fused";
     case kLaunchMid: return "apply_mid";
-    case kLaunchTight: return "apply_stage_tight";
+    case kLaunchTight: return x.split ? "apply_stage_tight_split" : "apply_stage_tight";
     default: return x.mfma ? "apply_u_mfma" : "apply_u";
   }
 }
@@ -1496,7 +1661,12 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
   // any FP32-state plan on path 3; needs the build's per-pair ranks (plans
   // without the sweep-in); not in batches
   const bool tight = sizeof(VT) == 8 && p->d_prank && !batch &&
-                     ((tn.path == 0 && nrhs >= 64) || tn.path == 3);
+                     ((tn.path == 0 && nrhs >= 64) || tn.path == 3 || tn.path == 4);
+  // BF16X2 plans: the per-pair-rank stages multiply with BF16 split products
+  // (path 4, and the default rule) or widen the factors to FP32 (path 3)
+  const bool split = tight && std::is_same<FT, bf16x2c>::value && tn.path != 3 &&
+                     std::all_of(p->stages.begin(), p->stages.end(),
+                                 [](const Stage& st) { return st.qblk != nullptr; });
   const bool mfma_vu = sizeof(VT) == 8 && nrhs >= 32;
   const int NB = mfma ? (tn.chunk == 16 || tn.chunk == 32 ? tn.chunk : (nrhs > 16 ? 32 : 16))
                       : std::min(nrhs, 32);
@@ -1579,14 +1749,21 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
           for (int j = 0; j <= n; ++j) m = std::max(m, rank_at(l - 1 + j, gside));
           return m;
         };
+        // LDS state: FP32 [2^k][km][64] + 4 rows (the product reads up to 3 rows
+        // past a slot's live rows); split [2^k][quads][hi|lo][64] 16-byte records
+        auto tight_lds = [&](int km_, int kk_) -> size_t {
+          if (split) return ((size_t)((km_ + 3) / 4) << kk_) * 2 * 64 * 16;
+          return (((size_t)km_ << kk_) + 4) * 64 * sizeof(VT);
+        };
         // tiles above 12 rows run 8 waves a block (3 stages), and the state must fit LDS
         while (kk > 1 && ((even_kt(kmax_of(kk)) > 12 && kk > 3) ||
-                          (((size_t)kmax_of(kk) << kk) + 4) * 64 * sizeof(VT) > (size_t)lmax))
+                          tight_lds(kmax_of(kk), kk) > (size_t)lmax))
           --kk;
         int km = kmax_of(kk);
         Launch x;
         x.kind = kLaunchTight;
         x.mfma = true;
+        x.split = split;
         TightArgs& T = x.t.A;
         T.L = L;
         T.l_start = l;
@@ -1603,13 +1780,13 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
         for (int j = 0; j < kk; ++j) {
           const Stage& st = p->stages[l + j - l0 - 1];
           T.blk[j] = st.blk;
+          T.qblk[j] = st.qblk;
           T.kld[j] = st.k_ld;
           nnz += (double)st.nnz;
         }
         T.KS = km;
         x.kt = even_kt(km);
-        // + 4 rows: the product reads up to 3 rows past a slot's live rows
-        x.lds = (((size_t)km << kk) + 4) * 64 * sizeof(VT);
+        x.lds = tight_lds(km, kk);
         x.nblocks = (p->npairs >> kk) * T.nchunk;
         x.t.in = w[cur];
         x.t.out = w[cur ^ 1];
@@ -1844,8 +2021,24 @@ int launch_one(const Launch& x, hipStream_t s) {
     const dim3 pgrid((unsigned)std::min<int64_t>(x.nblocks, nres));                             \
     hipLaunchKernelGGL((k_apply_tight<FT, KTC>), pgrid, dim3(tb), x.lds, s, x.t, x.nblocks);   \
   }
+#define IBF_LAUNCH_TIGHT_SPLIT(KTC)                                                            \
+  {                                                                                            \
+    int64_t nres = 0;                                                                          \
+    const int rc = resident_blocks(reinterpret_cast<const void*>(&k_apply_tight_split<KTC>),   \
+                                   x.lds, &nres, tb);                                          \
+    if (rc) return rc;                                                                         \
+    const dim3 pgrid((unsigned)std::min<int64_t>(x.nblocks, nres));                             \
+    hipLaunchKernelGGL((k_apply_tight_split<KTC>), pgrid, dim3(tb), x.lds, s, x.t, x.nblocks); \
+  }
+        if constexpr (std::is_same<FT, bf16x2c>::value) {
+          if (x.split) {
+            IBF_DISPATCH_KT(x.kt, IBF_LAUNCH_TIGHT_SPLIT);
+            break;
+          }
+        }
         IBF_DISPATCH_KT(x.kt, IBF_LAUNCH_TIGHT);
 #undef IBF_LAUNCH_TIGHT
+#undef IBF_LAUNCH_TIGHT_SPLIT
       }
       break;
     default:
@@ -2237,7 +2430,8 @@ int schedule_signature(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_
     sig.insert(sig.end(), {(int64_t)x.kind, (int64_t)x.kt, (int64_t)x.mfma, x.nblocks,
                            (int64_t)x.lds});
     if (x.kind == kLaunchFused) sig.insert(sig.end(), {x.f.A.l_start, x.f.A.nst, x.f.A.NB});
-    if (x.kind == kLaunchTight) sig.insert(sig.end(), {x.t.A.l_start, x.t.A.nst, 64});
+    if (x.kind == kLaunchTight)
+      sig.insert(sig.end(), {x.t.A.l_start, x.t.A.nst, 64, (int64_t)x.split});
   }
   return IBF_OK;
 }
@@ -2277,6 +2471,11 @@ int tune_plan(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu, in
       cand.push_back(Tuning{3, 0, 0, 0});
       cand.push_back(Tuning{3, 0, 3, 0});
       cand.push_back(Tuning{3, 0, 2, 0});
+      if (p->precision == IBF_BF16X2) {                      // BF16 split products
+        cand.push_back(Tuning{4, 0, 0, 0});
+        cand.push_back(Tuning{4, 0, 3, 0});
+        cand.push_back(Tuning{4, 0, 2, 0});
+      }
     }
   }
   // the plan leaves trial mode and the events are released on every exit
@@ -2426,15 +2625,19 @@ int ibf_set_tuning(ibf_plan_t p, int64_t nrhs, const ibf_tuning* t) {
     p->tuned.erase(nrhs);
     return IBF_OK;
   }
-  if (t->path < 0 || t->path > 3 || (t->chunk != 0 && t->chunk != 16 && t->chunk != 32) ||
+  if (t->path < 0 || t->path > 4 || (t->chunk != 0 && t->chunk != 16 && t->chunk != 32) ||
       t->max_fused < 0 || t->split < 0 || t->split > 2) {
     ibf::set_error(
-        "ibf_set_tuning: path outside 0..3, chunk not 0/16/32, max_fused < 0 or split outside "
+        "ibf_set_tuning: path outside 0..4, chunk not 0/16/32, max_fused < 0 or split outside "
         "0..2");
     return IBF_ERR_INVALID_ARG;
   }
   if ((t->path == 2 || t->path == 3) && p->precision == IBF_FP64) {
     ibf::set_error("ibf_set_tuning: no MFMA stage kernel for FP64 plans");
+    return IBF_ERR_UNSUPPORTED;
+  }
+  if (t->path == 4 && p->precision != IBF_BF16X2) {
+    ibf::set_error("ibf_set_tuning: BF16 split products (path 4) need a BF16X2 plan");
     return IBF_ERR_UNSUPPORTED;
   }
   p->tuned[nrhs] = ibf::Tuning{t->path, t->chunk, t->max_fused, t->split};

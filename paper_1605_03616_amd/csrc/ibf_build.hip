@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "ibf_kern.h"
@@ -262,6 +263,39 @@ __global__ void k_eval(PhaseDesc ph, const double* x, const double* xi, int64_t 
 }
 
 
+// The quad records of a BF16X2 stage (the layout of Stage::qblk): one thread
+// per 16-byte record (pair, child c, quad q, float f) gathers the hi and lo
+// bf16 parts of float f of rows 4q .. 4q+3 of child c's block rows.
+__global__ __launch_bounds__(kBlock) void k_quad_split(const bf16x2c* __restrict__ blk,
+                                                       uint4* __restrict__ q, int64_t npairs,
+                                                       int k_in, int k_ld) {
+  const int nq = (k_in + 3) / 4, nf = 2 * k_ld;
+  const int64_t total = npairs * 2 * nq * nf;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int f = (int)(i % nf);
+    const int64_t cq = i / nf;
+    const int qq = (int)(cq % nq);
+    const int64_t pc = cq / nq;                               // pair * 2 + child
+    const int c = (int)(pc & 1);
+    const int64_t pair = pc >> 1;
+    const unsigned short* b = reinterpret_cast<const unsigned short*>(blk) +
+                              pair * (int64_t)(2 * k_in * k_ld) * 4;
+    unsigned h[4], l[4];
+    for (int k = 0; k < 4; ++k) {
+      const int s = 4 * qq + k;
+      h[k] = l[k] = 0u;
+      if (s < k_in) {
+        const int64_t e = ((int64_t)(c * k_in + s) * k_ld + (f >> 1)) * 4 + (f & 1);
+        h[k] = b[e];
+        l[k] = b[e + 2];
+      }
+    }
+    q[i] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), l[0] | (l[1] << 16),
+                      l[2] | (l[3] << 16));
+  }
+}
+
 template <typename FT>
 int pack_all(ibf_plan_t p, const std::vector<DevBuf<double2>>& stages, const double2* Cu,
              const double2* Rv, const int* rkU, const int* rkV, const double* cheb,
@@ -285,6 +319,16 @@ int pack_all(ibf_plan_t p, const std::vector<DevBuf<double2>>& stages, const dou
                        stages[l - l0 - 1].ptr, (FT*)st.blk, p->npairs, R, st.k_out, st.k_in,
                        st.k_ld);
     p->nnz_stored += count;
+    if (std::is_same<FT, bf16x2c>::value && p->d_prank) {
+      // quad records for the per-pair-rank stages with BF16 split products
+      Stage& sq = p->stages.back();
+      const int64_t nrec = p->npairs * 2 * ((sq.k_in + 3) / 4) * 2 * sq.k_ld;
+      sq.qbytes = (size_t)nrec * sizeof(uint4);
+      IBF_HIP_CHECK(ibf::dev_malloc(&sq.qblk, std::max<size_t>(sq.qbytes, 16)));
+      const unsigned qb = (unsigned)std::min<int64_t>((nrec + kBlock - 1) / kBlock, 1 << 20);
+      hipLaunchKernelGGL(k_quad_split, dim3(std::max(qb, 1u)), dim3(kBlock), 0, s,
+                         (const bf16x2c*)sq.blk, (uint4*)sq.qblk, p->npairs, sq.k_in, sq.k_ld);
+    }
   }
   // Ubar at level L-l0, Vbar at level l0
   p->k_ubar = p->rank[L - l0 - l0];

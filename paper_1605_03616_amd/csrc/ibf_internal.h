@@ -61,6 +61,12 @@ struct Stage {
   void* blk;         // [pair][c k_in + s][k_ld] complex (input-major rows)
   size_t bytes;
   int64_t nnz;       // unpadded entries (each block at its own ranks)
+  // BF16X2 plans with per-pair ranks: the same blocks for the BF16 split
+  // products, [pair][c][quad q < ceil(k_in / 4)][float f < 2 k_ld] 16-byte
+  // records {bf16 hi of rows 4q .. 4q+3, bf16 lo of the same rows} of float f
+  // (re or im of entry f / 2; rows past k_in are zero); null otherwise
+  void* qblk = nullptr;
+  size_t qbytes = 0;
 };
 
 }  // namespace ibf

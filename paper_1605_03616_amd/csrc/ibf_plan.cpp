@@ -121,8 +121,10 @@ void set_order(ibf_plan_t p, int r, double tol) {
 
 void free_factors(ibf_plan_t p) {
   free_adjoint(p);
-  for (auto& st : p->stages)
+  for (auto& st : p->stages) {
     if (st.blk) (void)ibf::dev_free(st.blk);
+    if (st.qblk) (void)ibf::dev_free(st.qblk);
+  }
   p->stages.clear();
   void** bufs[] = {&p->d_vbar, &p->d_ubar, &p->d_mdot, &p->d_work[0], &p->d_work[1],
                    reinterpret_cast<void**>(&p->d_prank)};
@@ -418,7 +420,7 @@ int ibf_query(ibf_plan_t p, ibf_info* info) {
   info->nnz_opt = p->nnz_opt;
   info->nnz_stored = p->nnz_stored;
   int64_t fb = (int64_t)(p->vbar_bytes + p->ubar_bytes + p->mdot_bytes);
-  for (auto& st : p->stages) fb += (int64_t)st.bytes;
+  for (auto& st : p->stages) fb += (int64_t)(st.bytes + st.qbytes);
   info->factor_bytes = fb;
   info->build_ms = p->build_ms;
   info->smax_x = p->smax_x;

@@ -28,7 +28,7 @@ EXPORTED = ["ibf_plan", "ibf_build", "ibf_apply", "ibf_apply_profile", "ibf_quer
             "ibf_measure_peak", "ibf_apply_adjoint", "ibf_rel_error", "ibf_apply_noalloc",
             "ibf_build_batch"]
 MLP_FEATURES = 5
-PATHS = ["default", "vector", "mfma", "tight"]      # ibf_tuning.path
+PATHS = ["default", "vector", "mfma", "tight", "tight_split"]      # ibf_tuning.path
 BATCH_GRAPH = 1
 PROFILE_MAX = 64
 
@@ -392,8 +392,9 @@ class Plan:
 
     def set_tuning(self, nrhs, path=None, chunk=0, max_fused=0, split=0):
         """ibf_set_tuning: installs a schedule for `nrhs` right-hand sides
-        (path "default", "vector", "mfma" or "tight" -- MFMA stages at each
-        pair's own ranks); path None returns to the default rule."""
+        (path "default", "vector", "mfma", "tight" -- MFMA stages at each
+        pair's own ranks -- or "tight_split" -- the same with BF16 split
+        products, BF16X2 plans); path None returns to the default rule."""
         if path is None:
             _check(self._lib.ibf_set_tuning(self.handle, nrhs, None))
             return

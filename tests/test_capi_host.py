@@ -114,7 +114,7 @@ def test_set_tuning_validates_host_only():
     T = ibf.IBFTuning
     assert lib.ibf_set_tuning(None, 8, C.byref(T(0, 0, 0, 0.0))) == -1
     assert lib.ibf_set_tuning(pl.handle, 0, C.byref(T(0, 0, 0, 0.0))) == -1
-    for bad in [T(4, 0, 0, 0.0), T(-1, 0, 0, 0.0), T(2, 8, 0, 0.0), T(1, 0, -1, 0.0),
+    for bad in [T(5, 0, 0, 0.0), T(-1, 0, 0, 0.0), T(2, 8, 0, 0.0), T(1, 0, -1, 0.0),
                 T(0, 0, 0, 0.0, 3)]:
         assert lib.ibf_set_tuning(pl.handle, 8, C.byref(bad)) == -1
     assert lib.ibf_set_tuning(pl.handle, 8, C.byref(T(2, 32, 3, 0.0))) == 0
@@ -123,10 +123,17 @@ def test_set_tuning_validates_host_only():
     pl.set_tuning(12, "mfma", 16, 0, 2)
     pl.set_tuning(64, "tight", 0, 3)
     pl.set_tuning(12)
+    # BF16 split products (path 4) need BF16X2 factors
+    assert lib.ibf_set_tuning(pl.handle, 64, C.byref(T(4, 0, 0, 0.0))) == -2
     pl.destroy()
+    pbf = _plan(precision=I.PREC_BF16X2)
+    pbf.set_tuning(64, "tight_split", 0, 2)
+    pbf.set_tuning(64, "tight", 0, 0)
+    pbf.destroy()
     p64 = _plan(precision=I.PREC_FP64)
     assert lib.ibf_set_tuning(p64.handle, 8, C.byref(T(2, 16, 0, 0.0))) == -2
     assert lib.ibf_set_tuning(p64.handle, 8, C.byref(T(3, 0, 0, 0.0))) == -2
+    assert lib.ibf_set_tuning(p64.handle, 8, C.byref(T(4, 0, 0, 0.0))) == -2
     assert lib.ibf_set_tuning(p64.handle, 8, C.byref(T(1, 0, 2, 0.0))) == 0
     p64.destroy()
 

@@ -176,34 +176,43 @@ def test_bf16x2_mfma_parity(torch_dev):
     assert O.rel_error_cols(u, u_ref) < 1e-4
 
 
-@pytest.mark.parametrize("key,nrhs,precision,fused", [
-    ("fio4k_r12", 64, I.PREC_FP32, 0), ("fio4k_r12", 130, I.PREC_FP32, 0),
-    ("fio4k_r12", 64, I.PREC_BF16X2, 0), ("fio3000_r9", 70, I.PREC_FP32, 3),
-    ("fio8k_r16", 64, I.PREC_FP32, 0), ("fio2k_r2", 64, I.PREC_FP32, 2),
-    ("nudft4k_r10", 64, I.PREC_FP32, 0), ("fio4k_r12", 64, I.PREC_FP32, 1),
-    ("nudft4k_r10", 130, I.PREC_FP32, 3), ("fio3000_r9", 64, I.PREC_BF16X2, 2)])
-def test_tight_stage_parity(torch_dev, key, nrhs, precision, fused):
+@pytest.mark.parametrize("key,nrhs,precision,fused,path", [
+    ("fio4k_r12", 64, I.PREC_FP32, 0, "tight"), ("fio4k_r12", 130, I.PREC_FP32, 0, "tight"),
+    ("fio4k_r12", 64, I.PREC_BF16X2, 0, "tight"), ("fio3000_r9", 70, I.PREC_FP32, 3, "tight"),
+    ("fio8k_r16", 64, I.PREC_FP32, 0, "tight"), ("fio2k_r2", 64, I.PREC_FP32, 2, "tight"),
+    ("nudft4k_r10", 64, I.PREC_FP32, 0, "tight"), ("fio4k_r12", 64, I.PREC_FP32, 1, "tight"),
+    ("nudft4k_r10", 130, I.PREC_FP32, 3, "tight"), ("fio3000_r9", 64, I.PREC_BF16X2, 2, "tight"),
+    ("fio4k_r12", 64, I.PREC_BF16X2, 0, "tight_split"),
+    ("fio4k_r12", 16, I.PREC_BF16X2, 0, "tight_split"),
+    ("fio3000_r9", 70, I.PREC_BF16X2, 3, "tight_split"),
+    ("fio8k_r16", 64, I.PREC_BF16X2, 0, "tight_split"),
+    ("fio2k_r2", 64, I.PREC_BF16X2, 2, "tight_split"),
+    ("nudft4k_r10", 130, I.PREC_BF16X2, 1, "tight_split")])
+def test_tight_stage_parity(torch_dev, key, nrhs, precision, fused, path):
     """MFMA stages at each pair's own ranks (64-column chunks, up to 4 stages a
-    launch): ragged last chunk (130 = 2 x 64 + 2, 70), ragged leaves (N =
-    3000), the widest tile (r = 16), the smallest (r = 2), random x, BF16X2
-    factors, and fixed fusion depths (1 to 3 stages a launch), against the
-    oracle IBF."""
+    launch): ragged last chunk (130 = 2 x 64 + 2, 70, 16 of 64 columns live),
+    ragged leaves (N = 3000), the widest tile (r = 16), the smallest (r = 2),
+    random x, BF16X2 factors widened to FP32 ("tight") and multiplied as BF16
+    split products ("tight_split"), and fixed fusion depths (1 to 3 stages a
+    launch), against the oracle IBF."""
     torch = torch_dev
     from paper_1605_03616_amd import ibf
-    _say(f"tight stages {key} nrhs={nrhs} precision={precision} fused={fused}")
+    _say(f"tight stages {key} nrhs={nrhs} precision={precision} fused={fused} path={path}")
     P0 = _problems()[key]
     _, prob, Op, _ = _oracle(key)
     g = I.complex_normal(P0.n, nrhs, np.random.default_rng(36))
     u_ref = O.apply_optimal(Op, g)
     pl = ibf.Plan(P0.x, P0.xi, P0.phase, P0.params, P0.r, P0.tol, P0.leaf, precision, 0)
     pl.build()
-    pl.set_tuning(nrhs, "tight", 0, fused)
+    pl.set_tuning(nrhs, path, 0, fused)
     gt = torch.from_numpy(np.ascontiguousarray(g.T)).to(torch.complex64).cuda()
     u = pl.apply(gt).cpu().numpy().T.astype(np.complex128)
     prof_u = torch.empty((nrhs, P0.n), dtype=torch.complex64, device="cuda")
     names = {x[0] for x in pl.apply_profile(gt, prof_u)}
     pl.destroy()
-    assert "apply_stage_tight" in names, names
+    want = "apply_stage_tight_split" if path == "tight_split" else "apply_stage_tight"
+    other = "apply_stage_tight" if path == "tight_split" else "apply_stage_tight_split"
+    assert want in names and other not in names, names
     tol = 1e-5 if precision == I.PREC_FP32 else 1e-4
     assert O.rel_error(u, u_ref) < tol
     assert O.rel_error_cols(u, u_ref) < tol
