@@ -1041,28 +1041,28 @@ __device__ __forceinline__ void tight_body(const TightDesc& D, int64_t lb, int64
           }
         } else {
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          const int kin = c ? sw.kin1 : sw.kin0;
-          const int nwin = (kin + 1) >> 1;
-          const float2* X = S + (size_t)(sw.in0 + c) * KS * NB + lane;
-          const int rl = max(2 * nwin - 2, 0);
-          float2 x0 = X[rl * NB], x1 = X[(rl + 1) * NB];
+          for (int c = 0; c < 2; ++c) {
+            const int kin = c ? sw.kin1 : sw.kin0;
+            const int nwin = (kin + 1) >> 1;
+            const float2* X = S + (size_t)(sw.in0 + c) * KS * NB + lane;
+            const int rl = max(2 * nwin - 2, 0);
+            float2 x0 = X[rl * NB], x1 = X[(rl + 1) * NB];
 #pragma unroll
-          for (int i = WC - 1; i >= 0; --i) {
-            if (i < nwin) {
-              float2 y0 = x0, y1 = x1;
-              if (i > 0) {
-                y0 = X[(2 * i - 2) * NB];
-                y1 = X[(2 * i - 1) * NB];
+            for (int i = WC - 1; i >= 0; --i) {
+              if (i < nwin) {
+                float2 y0 = x0, y1 = x1;
+                if (i > 0) {
+                  y0 = X[(2 * i - 2) * NB];
+                  y1 = X[(2 * i - 1) * NB];
+                }
+                const float a = aw.a[c * WC + i];
+                tight_row<0, NG, KG>(a, x0, P, Q);
+                if (2 * i + 1 < kin) tight_row<1, NG, KG>(a, x1, P, Q);
+                x0 = y0;
+                x1 = y1;
               }
-              const float a = aw.a[c * WC + i];
-              tight_row<0, NG, KG>(a, x0, P, Q);
-              if (2 * i + 1 < kin) tight_row<1, NG, KG>(a, x1, P, Q);
-              x0 = y0;
-              x1 = y1;
             }
           }
-        }
         }
       };
       switch (ng) {
@@ -1393,14 +1393,26 @@ __device__ __forceinline__ void apply_v_mfma_body(const VDesc& d, int64_t lb) {
 // U: u[x][n] = sum_r Ubar[x][r] mu[p0 + r / K][r % K][n] over the R = 2^l0 K
 // rows of the leaf's contiguous pairs (R a multiple of 16).  LDS: Ubar
 // transposed to [R][17] (rows past the leaf's points are zero; the padding
-// spreads the transposing stores over the banks) and a [16][64] tile that
-// turns the column-per-lane results into point-contiguous stores.
-// Wave w computes point pairs w and w + 4 over all R rows, reading the mu rows
-// straight from memory: the four waves read the same rows at about the same
-// time, so all but the first read of a row hit the CU's cache.
+// spreads the transposing stores over the banks) and four partial [16][64]
+// tiles.  Wave w takes rows w R/4 .. (w+1) R/4 - 1 for all 16 points: its mu
+// rows come straight from memory, all loads in flight at once, and each
+// v_mfma_f32_4x4x1f32 broadcasts the four floats of one point pair of one
+// row (lanes 0-31 hold row r, lanes 32-63 row r + 1, float e in lane e: the
+// A block of point pair q is lanes 32 h + 4 q .. + 3, abid 8 h + q).  The
+// four partial tiles are summed by the point-contiguous stores.
+template <int H, int G = 0>
+__device__ __forceinline__ void u_row(float a, float2 x, v4f (&P)[8], v4f (&Q)[8]) {
+  if constexpr (G < 8) {
+    P[G] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, x.x, P[G], 4, 8 * H + G, 0);
+    Q[G] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, x.y, Q[G], 4, 8 * H + G, 0);
+    u_row<H, G + 1>(a, x, P, Q);
+  }
+}
+
 template <typename FT>
 __device__ __forceinline__ void apply_u_mfma_body(const UDesc& d, int64_t lb) {
   constexpr int NB = 64, SM = kLeafMfma, RB = 8;
+  static_assert(SM == 16, "one point pair per MFMA block: 8 pairs of a 32-float row");
   extern __shared__ __align__(16) unsigned char smem[];
   const float2* __restrict__ mu = reinterpret_cast<const float2*>(d.mu);
   float2* __restrict__ u = reinterpret_cast<float2*>(d.u);
@@ -1410,7 +1422,7 @@ __device__ __forceinline__ void apply_u_mfma_body(const UDesc& d, int64_t lb) {
   const int R = K << l0;
   constexpr int UP = SM + 1;                                  // padded Ubar row
   float2* ul = reinterpret_cast<float2*>(smem);               // [R][UP]
-  float2* ot = ul + (size_t)R * UP;                           // [16][64]
+  float2* ot = ul + (size_t)R * UP;                           // [4][16][64]
   const int64_t a = lb / nchunk;
   const int nb0 = (int)(lb - a * nchunk) * NB;
   const int nbw = min(NB, nrhs - nb0);
@@ -1424,60 +1436,69 @@ __device__ __forceinline__ void apply_u_mfma_body(const UDesc& d, int64_t lb) {
     off = r * UP + x;
     return x < cnt ? load_factor(usrc, e) : make_float2(0.f, 0.f);
   });
-  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int fi = lane & 3;
-  v4f P[2], Q[2];
-#pragma unroll
-  for (int m = 0; m < 2; ++m) {
-    P[m] = v4f{0.f, 0.f, 0.f, 0.f};
-    Q[m] = v4f{0.f, 0.f, 0.f, 0.f};
-  }
-  // A operand of row r for point pairs wave and wave + 4: floats 4 wave + fi
-  // and 4 wave + 16 + fi of LDS row r (2 UP floats a row)
-  const float* f = reinterpret_cast<const float*>(ul) + 4 * wave + fi;
+  const int half = lane >> 5;
   const bool col = lane < nbw;
-  const float2* src = mu + p0 * K * nrhs + nb0 + lane;
+  const int rw = R >> 2, r0 = wave * rw;                      // this wave's rows (even count)
+  const float2* src = mu + (p0 * K + r0) * nrhs + nb0 + lane;
+  // the wave's mu rows, RB at a time, the first batch issued before the
+  // barrier that publishes Ubar
   float2 xa[RB], xb[RB];
-  auto load_rows = [&](int r0, float2 (&X)[RB]) {
+  auto load_rows = [&](int i0, float2 (&X)[RB]) {
 #pragma unroll
     for (int i = 0; i < RB; ++i)
-      X[i] = col ? src[(int64_t)(r0 + i) * nrhs] : make_float2(0.f, 0.f);
+      X[i] = (col && i0 + i < rw) ? src[(int64_t)(i0 + i) * nrhs] : make_float2(0.f, 0.f);
   };
-  auto mfma_rows = [&](int r0, const float2 (&X)[RB]) {
+  load_rows(0, xa);
+  __syncthreads();
+  v4f P[8], Q[8];
 #pragma unroll
-    for (int i = 0; i < RB; ++i) {
-      const float* fr = f + 2 * UP * (r0 + i);
-      const float a0 = fr[0], a1 = fr[16];
-      P[0] = __builtin_amdgcn_mfma_f32_4x4x1f32(a0, X[i].x, P[0], 0, 0, 0);
-      Q[0] = __builtin_amdgcn_mfma_f32_4x4x1f32(a0, X[i].y, Q[0], 0, 0, 0);
-      P[1] = __builtin_amdgcn_mfma_f32_4x4x1f32(a1, X[i].x, P[1], 0, 0, 0);
-      Q[1] = __builtin_amdgcn_mfma_f32_4x4x1f32(a1, X[i].y, Q[1], 0, 0, 0);
+  for (int q = 0; q < 8; ++q) {
+    P[q] = v4f{0.f, 0.f, 0.f, 0.f};
+    Q[q] = v4f{0.f, 0.f, 0.f, 0.f};
+  }
+  // A registers: float (lane & 31) of rows r0 + i + half, i even
+  const float* f = reinterpret_cast<const float*>(ul) + (size_t)(r0 + half) * 2 * UP + (lane & 31);
+  auto mfma_rows = [&](int i0, const float2 (&X)[RB]) {
+#pragma unroll
+    for (int i = 0; i < RB; i += 2) {
+      if (i0 + i < rw) {
+        const float av = f[(size_t)(i0 + i) * 2 * UP];
+        u_row<0>(av, X[i], P, Q);
+        u_row<1>(av, X[i + 1], P, Q);
+      }
     }
   };
-  // rows in batches of RB, the next batch's loads in flight during the MFMAs
-  load_rows(0, xa);
 #pragma unroll 1
-  for (int r0 = 0; r0 < R; r0 += 2 * RB) {
-    load_rows(r0 + RB, xb);
-    mfma_rows(r0, xa);
-    if (r0 + 2 * RB < R) load_rows(r0 + 2 * RB, xa);
-    mfma_rows(r0 + RB, xb);
+  for (int i0 = 0; i0 < rw; i0 += 2 * RB) {
+    load_rows(i0 + RB, xb);
+    mfma_rows(i0, xa);
+    if (i0 + 2 * RB < rw) load_rows(i0 + 2 * RB, xa);
+    mfma_rows(i0 + RB, xb);
   }
-  // points 2 q + h of pair q (q = wave, wave + 4) to the [16][64] tile
+  // partial tile of this wave: point 2 q + h, column lane
+  float2* pt = ot + (size_t)wave * SM * NB + lane;
 #pragma unroll
-  for (int m = 0; m < 2; ++m) {
-    const int q = wave + 4 * m;
-    const v4f pp = P[m], qq = Q[m];
-    ot[(2 * q) * NB + lane] = make_float2(pp[0] - qq[1], pp[1] + qq[0]);
-    ot[(2 * q + 1) * NB + lane] = make_float2(pp[2] - qq[3], pp[3] + qq[2]);
+  for (int q = 0; q < 8; ++q) {
+    const v4f pp = P[q], qq = Q[q];
+    pt[(2 * q) * NB] = make_float2(pp[0] - qq[1], pp[1] + qq[0]);
+    pt[(2 * q + 1) * NB] = make_float2(pp[2] - qq[3], pp[3] + qq[2]);
   }
   __syncthreads();
-  // point-contiguous stores: item = n * 16 + x
+  // sum of the four partials, point-contiguous stores: item = n * 16 + x
   for (int item = threadIdx.x; item < SM * NB; item += kBlock) {
     const int x = item & 15, n = item >> 4;
-    if (x < cnt && n < nbw) u[(int64_t)(nb0 + n) * ldu + d.perm_x[x0 + x]] = ot[x * NB + n];
+    if (x < cnt && n < nbw) {
+      float2 v = ot[x * NB + n];
+#pragma unroll
+      for (int w = 1; w < 4; ++w) {
+        const float2 t = ot[(size_t)w * SM * NB + x * NB + n];
+        v.x += t.x;
+        v.y += t.y;
+      }
+      u[(int64_t)(nb0 + n) * ldu + d.perm_x[x0 + x]] = v;
+    }
   }
 }
 
@@ -1901,7 +1922,7 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
       const int R = K << l0;
       const int nchu = (nrhs + 63) / 64;
       x.mfma = true;
-      x.lds = ((size_t)R * (kLeafMfma + 1) + (size_t)kLeafMfma * 64) * sizeof(VT);
+      x.lds = ((size_t)R * (kLeafMfma + 1) + (size_t)4 * kLeafMfma * 64) * sizeof(VT);
       x.nblocks = p->nleaf * nchu;
       x.u = UDesc{w[cur], u, ldu, p->d_perm_x, p->d_xoff, p->d_ubar, l0, K, nrhs, 64, nchu,
                   p->smax_x, 1};

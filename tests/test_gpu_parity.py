@@ -330,29 +330,41 @@ def test_determinism(torch_dev):
 
 def test_full_size_fio64k_fp32(torch_dev):
     """N = 65536, r = 12, 64 RHS, FP32 apply (the benchmark workload, in the
-    launch configuration the benchmark times): every column against the
-    oracle's full IBF (Frobenius and per-column maximum), ranks per level, and
-    the dense product on 256 rows."""
+    launch configuration the benchmark times) and the same with BF16X2
+    factors (its default schedule: per-pair-rank stages with BF16 split
+    products): every column against the oracle's full IBF (Frobenius and
+    per-column maximum; FP32 1e-5, BF16X2 1e-4), ranks per level, and the
+    dense product on 256 rows."""
+    import dataclasses
     torch = torch_dev
     from paper_1605_03616_amd import ibf
-    _say("full size fio1d n=65536 r=12 fp32 nrhs=64")
     P = I.workload_fio1d_64k(nrhs=64)
-    pl = ibf.Plan.from_problem(P)
-    pl.build()
     g = torch.from_numpy(np.ascontiguousarray(P.g.T)).to(torch.complex64).cuda()
-    u = pl.apply(g).cpu().numpy().T.astype(np.complex128)
-    q = pl.query()
-    pl.destroy()
+    res = {}
+    for prec in (I.PREC_FP32, I.PREC_BF16X2):
+        _say(f"full size fio1d n=65536 r=12 nrhs=64 precision={prec}")
+        pl = ibf.Plan.from_problem(dataclasses.replace(P, precision=prec))
+        pl.build()
+        u = pl.apply(g).cpu().numpy().T.astype(np.complex128)
+        prof_u = torch.empty_like(g)
+        names = {x[0] for x in pl.apply_profile(g, prof_u)}
+        res[prec] = (u, pl.query(), names)
+        pl.destroy()
+    assert "apply_stage_tight" in res[I.PREC_FP32][2]
+    assert "apply_stage_tight_split" in res[I.PREC_BF16X2][2]
     rows = I.error_rows(P.n)
     ud = O.dense_apply(P.phase, P.params, P.x, P.xi, P.g[:, :8], rows=rows)
-    assert O.rel_error(u[rows, :8], ud) < 3e-6
+    assert O.rel_error(res[I.PREC_FP32][0][rows, :8], ud) < 3e-6
+    assert O.rel_error(res[I.PREC_BF16X2][0][rows, :8], ud) < 1e-4
     _say("full size fio1d: oracle IBF on all 64 columns")
     prob, F, Op = O.build_optimal(P.phase, P.params, P.x, P.xi, P.r, P.tol, P.leaf)
     uo = O.apply_optimal(Op, P.g)
-    assert O.rel_error(u, uo) < 1e-5
-    assert O.rel_error_cols(u, uo) < 1e-5
-    assert q["rank"] == [v for _, v in sorted(O.level_ranks(Op).items())]
-    assert q["nnz_opt"] == O.nnz_optimal(Op)
+    for prec, tol in ((I.PREC_FP32, 1e-5), (I.PREC_BF16X2, 1e-4)):
+        u, q, _ = res[prec]
+        assert O.rel_error(u, uo) < tol
+        assert O.rel_error_cols(u, uo) < tol
+        assert q["rank"] == [v for _, v in sorted(O.level_ranks(Op).items())]
+        assert q["nnz_opt"] == O.nnz_optimal(Op)
 
 
 def test_nudft_64k_sweep_in_against_oracle(torch_dev):
