@@ -42,11 +42,14 @@ MEASURED_TRAFFIC = {
     # (workload, schedule path/chunk/max_fused) -> (sha1 of the apply source,
     #   kernel class, [(launches per step, FETCH_SIZE KiB, WRITE_SIZE KiB), ...])
     ("fio1d_n65536_r12_fp32", "default/0/0"): (
-        "5efd6b5c8edb6ef729c21598e35e266e4d220e14", "apply_stage_tight",
-        [(2, 323579, 295936)]),
+        "50ec3be4c77aea9df60a7d156f1c892b45d7986f", "apply_stage_tight",
+        [(2, 323159, 295936)]),
+    ("fio1d_n65536_r12_bf16x2", "default/0/0"): (
+        "50ec3be4c77aea9df60a7d156f1c892b45d7986f", "apply_stage_tight_split",
+        [(2, 311360, 294912)]),
     ("nudft_n1048576_r10", "default/0/0"): (
-        "5efd6b5c8edb6ef729c21598e35e266e4d220e14", "apply_fused_mfma",
-        [(2, 2424927, 983040), (1, 1769571, 917504), (1, 1822842, 1048576)]),
+        "50ec3be4c77aea9df60a7d156f1c892b45d7986f", "apply_fused_mfma",
+        [(2, 2424927, 983040), (1, 1769576, 917504), (1, 1822849, 1048576)]),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 

@@ -906,15 +906,19 @@ __device__ __forceinline__ void tight_body(const TightDesc& D, int64_t lb, int64
       // v = c WQ + i; register m holds quads 2 m (lanes 0-31) and 2 m + 1
       // (lanes 32-63).  Lane 32 h + 4 g + i takes the record of float
       // f = 4 g + i of quad 2 m + h: bf16 hi and lo of rows 4 q .. 4 q + 3,
-      // already in operand order.  f is clamped into the row and q into the
-      // child's quads, so every load stays inside the pair's records (the
-      // clamped ones feed only unused blocks or rows that meet zero state).
+      // already in operand order.  f is clamped to the output pair's rank and
+      // q to the quads of the child's rank (both inside the pair's records),
+      // so the padding of the stored blocks is not read: the clamped loads
+      // repeat a record already loaded and feed only unused blocks or rows
+      // that meet zero state.
       const int nq = (Kin + 3) >> 2, nf = 2 * kld;
       const uint4* qb = reinterpret_cast<const uint4*>(A.qblk[j]) + s.pout * (int64_t)(2 * nq * nf);
-      const int f = min(e, nf - 1);
+      const int f = min(e, max(2 * s.kout - 1, 0));
 #pragma unroll
       for (int m = 0; m < WR; ++m) {
-        const int v = 2 * m + half, c = v >= WQ ? 1 : 0, q = min(v - c * WQ, nq - 1);
+        const int v = 2 * m + half, c = v >= WQ ? 1 : 0;
+        const int qmax = max((((c ? s.kin1 : s.kin0) + 3) >> 2) - 1, 0);
+        const int q = min(v - c * WQ, qmax);
         const uint4 d = qb[(c * nq + q) * nf + f];
         W.h[m] = make_uint2(d.x, d.y);
         W.l[m] = make_uint2(d.z, d.w);
