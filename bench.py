@@ -153,7 +153,6 @@ def _cpu_baseline(P, nrhs_sample=20):
 def _bench_batched(args):
     """Uneven batch of 256 1-D FIO problems, one graph-replayed batched apply per step."""
     import torch
-    from oracle import ibf_oracle as O
     from paper_1605_03616_amd import ibf
     from paper_1605_03616_amd import inputs as I
 
@@ -249,14 +248,19 @@ def _bench_batched(args):
     if tune_info:
         out["tuning"] = tune_info
     if not args.no_accuracy:
+        # the library's device FP64 direct product on 64 sampled rows a problem
         worst = 0.0
         for P, u in zip(probs, us):
             rows = I.error_rows(P.n, count=64)
-            ud = O.dense_apply(P.phase, P.params, P.x, P.xi, P.g, rows=rows)
-            un = u.cpu().numpy().T[rows].astype(np.complex128)
-            worst = max(worst, O.rel_error(un, ud))
+            ud = ibf.dense_apply(P.phase, P.params,
+                                 torch.from_numpy(np.ascontiguousarray(P.x[rows])).cuda(),
+                                 torch.from_numpy(np.ascontiguousarray(P.xi)).cuda(),
+                                 torch.from_numpy(np.ascontiguousarray(P.g.T)).cuda())
+            un = u[:, torch.from_numpy(rows).cuda()].to(torch.complex128).contiguous()
+            worst = max(worst, ibf.rel_error(un, ud)[0])
         out["max_rel_err_vs_dense_sampled"] = worst
     if not args.no_cpu_baseline:
+        from oracle import ibf_oracle as O
         small = [P for P in probs if P.n <= 2048][:8]
         t_app = 0.0
         for P in small:
@@ -280,7 +284,6 @@ def _bench_batched(args):
 def _bench_2d(args):
     """2-D FIO on the 256 x 256 grid (multiscale IBF, r = 5 x 5, tol 1e-4, 8 RHS, FP32)."""
     import torch
-    from oracle import ibf2d_oracle as D
     from paper_1605_03616_amd import ibf
     from paper_1605_03616_amd import inputs as I
 
@@ -332,12 +335,17 @@ def _bench_2d(args):
         out["rel_err_vs_fp64"] = ibf.rel_error(u.to(torch.complex128), u64)[0]
         out["fp64_build_ms"] = round(pl64.query()["build_ms"], 3)
         pl64.destroy()
+        # the library's device FP64 direct 2-D product on 256 sampled rows
         rows = np.random.default_rng(1234).choice(P.n, 256, replace=False)
-        ud = D.dense_apply_2d(P.phase, P.params, P.x, P.xi, P.g[:, :2], rows=rows)
-        un = u[:2].cpu().numpy().T[rows].astype(np.complex128)
-        out["rel_err_vs_dense_sampled"] = float(np.linalg.norm(un - ud) / np.linalg.norm(ud))
+        ud = ibf.dense_apply_2d(P.phase, P.params,
+                                torch.from_numpy(np.ascontiguousarray(P.x[rows])).cuda(),
+                                torch.from_numpy(np.ascontiguousarray(P.xi)).cuda(),
+                                torch.from_numpy(np.ascontiguousarray(P.g[:, :2].T)).cuda())
+        un = u[:2][:, torch.from_numpy(rows).cuda()].to(torch.complex128).contiguous()
+        out["rel_err_vs_dense_sampled"] = ibf.rel_error(un, ud)[0]
     if not args.no_cpu_baseline:
         # the oracle MIBF apply on the 64 x 64 grid of the same workload (build not timed)
+        from oracle import ibf2d_oracle as D
         Ps = I.fio2d_grid(64, 5, P.nrhs, 3, tol=1e-4)
         part, built, cidx = D.mibf_build(Ps.phase, Ps.params, Ps.x, Ps.xi, 64, 5, 1e-4)
         t0 = time.perf_counter()
@@ -469,7 +477,6 @@ def main():
 
     import torch
 
-    from oracle import ibf_oracle as O
     from paper_1605_03616_amd import ibf
     from paper_1605_03616_amd import inputs as I
 
@@ -612,12 +619,41 @@ def main():
         ms1 = e0.elapsed_time(e1) / args.steps
         out["fp64_single_rhs"] = {"ms": round(ms1, 5), "value": round(P.n / (ms1 * 1e-3) / 1e9, 5),
                                   "build_ms": round(pl64.query()["build_ms"], 3)}
+        if P.precision == I.PREC_FP32:
+            # the same workload with BF16X2 factors, beside the FP32 line: its
+            # default schedule, error against the same FP64 IBF
+            import dataclasses
+            Pb = dataclasses.replace(P, precision=I.PREC_BF16X2)
+            plb = ibf.Plan.from_problem(Pb)
+            plb.build()
+            ub = torch.empty_like(u)
+            for _ in range(args.warmup):
+                plb.apply(g, ub)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(args.steps):
+                plb.apply(g, ub)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            msb = e0.elapsed_time(e1) / args.steps
+            lb = plb.apply_profile(g, ub)
+            out["bf16x2"] = {
+                "value": round(P.n * P.nrhs / (msb * 1e-3) / 1e9, 4), "ms_per_step": round(msb, 5),
+                "rel_err_vs_fp64": ibf.rel_error(ub.to(torch.complex128), u64)[0],
+                "stage_kernel": max({x[0] for x in lb},
+                                    key=lambda k: sum(x[1] for x in lb if x[0] == k)),
+                "build_ms": round(plb.query()["build_ms"], 3)}
+            plb.destroy()
         pl64.destroy()
+        # the library's device FP64 direct product on sampled rows
         rows = I.error_rows(P.n)
         nchk = min(P.nrhs, 4)
-        ud = O.dense_apply(P.phase, P.params, P.x, P.xi, P.g[:, :nchk], rows=rows)
-        un = u[:nchk].cpu().numpy().T[rows]
-        out["rel_err_vs_dense_sampled"] = O.rel_error(un, ud)
+        ud = ibf.dense_apply(P.phase, P.params,
+                             torch.from_numpy(np.ascontiguousarray(P.x[rows])).cuda(),
+                             torch.from_numpy(np.ascontiguousarray(P.xi)).cuda(),
+                             g64[:nchk].contiguous())
+        un = u[:nchk][:, torch.from_numpy(rows).cuda()].to(torch.complex128).contiguous()
+        out["rel_err_vs_dense_sampled"] = ibf.rel_error(un, ud)[0]
 
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)

@@ -406,6 +406,20 @@ int ibf_dense_apply(int phase_id, const double* phase_params, int n_params,
                     void* hip_stream);
 
 /*
+ * The same direct FP64 product for two dimensions (Sec. 5; the phases of
+ * Sec. 6.3): x is [n_x][2] and xi [n_xi][2] (device, coordinates of a point
+ * adjacent), g (ldg x nrhs) and u (ldu x nrhs) complex double2; phase_id
+ * IBF_PHASE_DFT, IBF_PHASE_FIO2D or IBF_PHASE_SEPARABLE with the parameters
+ * and defaults of ibf_plan with dim = 2.  O(n_x n_xi nrhs) work, meant for
+ * sampled rows of a product.  Errors: INVALID_ARG, UNSUPPORTED (phase),
+ * DEVICE.
+ */
+int ibf_dense_apply_2d(int phase_id, const double* phase_params, int n_params,
+                       const double* x, int64_t n_x, const double* xi, int64_t n_xi,
+                       const void* g, int64_t ldg, void* u, int64_t ldu, int64_t nrhs,
+                       void* hip_stream);
+
+/*
  * Relative error of eq:relativeerr on the device: out[0] =
  * ||u - ref||_F / ||ref||_F over all nrhs columns, out[1] = the largest
  * per-column ratio ||u_c - ref_c|| / ||ref_c||.  u and ref are device

@@ -2650,4 +2650,36 @@ void query2d(ibf_plan_t p, ibf_info* info) {
   }
 }
 
+// Direct 2-D product u(x_i) = sum_j exp(2 pi i Phi(x_i, xi_j)) g_j (the dense
+// definition of Sec. 5 with the phases of Sec. 6.3) in FP64: one thread per
+// (row, right-hand side); x and xi are [n][2].
+__global__ __launch_bounds__(256) void k2_dense(PhaseDesc ph, const double* __restrict__ x,
+                                                int64_t nx, const double* __restrict__ xi,
+                                                int64_t nxi, const double2* __restrict__ g,
+                                                int64_t ldg, double2* __restrict__ u,
+                                                int64_t ldu) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (i >= nx) return;
+  const double x1 = x[2 * i], x2 = x[2 * i + 1];
+  const double2* gc = g + c * ldg;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int64_t j = 0; j < nxi; ++j) {
+    const double2 k = kval2(ph, x1, x2, xi[2 * j], xi[2 * j + 1]);
+    const double2 gv = gc[j];
+    acc.x = fma(k.x, gv.x, fma(-k.y, gv.y, acc.x));
+    acc.y = fma(k.x, gv.y, fma(k.y, gv.x, acc.y));
+  }
+  u[c * ldu + i] = acc;
+}
+
+int dense_apply_2d(const PhaseDesc& ph, const double* x, int64_t nx, const double* xi,
+                   int64_t nxi, const void* g, int64_t ldg, void* u, int64_t ldu, int64_t nrhs,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k2_dense, dim3((unsigned)((nx + 255) / 256), (unsigned)nrhs), dim3(256), 0,
+                     s, ph, x, nx, xi, nxi, (const double2*)g, ldg, (double2*)u, ldu);
+  IBF_HIP_CHECK(hipGetLastError());
+  return IBF_OK;
+}
+
 }  // namespace ibf

@@ -146,6 +146,9 @@ int apply_plan(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu,
                int64_t nrhs, hipStream_t s, ibf_profile* prof = nullptr);
 int dense_apply(const PhaseDesc& ph, const double* x, int64_t nx, const double* xi, int64_t nxi,
                 const void* g, int64_t ldg, void* u, int64_t ldu, int64_t nrhs, hipStream_t s);
+int dense_apply_2d(const PhaseDesc& ph, const double* x, int64_t nx, const double* xi,
+                   int64_t nxi, const void* g, int64_t ldg, void* u, int64_t ldu, int64_t nrhs,
+                   hipStream_t s);
 int eval_kernel(const PhaseDesc& ph, const double* x, const double* xi,
                 int64_t n, void* out, hipStream_t s);
 int rel_error(const void* u, int64_t ldu, const void* ref, int64_t ldr, int64_t n, int64_t nrhs,

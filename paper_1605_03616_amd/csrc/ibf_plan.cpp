@@ -517,4 +517,25 @@ int ibf_dense_apply(int phase_id, const double* params, int n_params, const doub
   return ibf::dense_apply(ph, x, n_x, xi, n_xi, g, ldg, u, ldu, nrhs, (hipStream_t)stream);
 }
 
+int ibf_dense_apply_2d(int phase_id, const double* params, int n_params, const double* x,
+                       int64_t n_x, const double* xi, int64_t n_xi, const void* g, int64_t ldg,
+                       void* u, int64_t ldu, int64_t nrhs, void* stream) {
+  if (!x || !xi || !g || !u || n_x < 0 || n_xi < 0 || nrhs < 1 || nrhs > 65535 || ldg < n_xi ||
+      ldu < n_x)
+    return fail(IBF_ERR_INVALID_ARG, "ibf_dense_apply_2d: bad argument");
+  if (n_params < 0 || n_params > ibf::kMaxParams || (n_params > 0 && !params))
+    return fail(IBF_ERR_INVALID_ARG, "ibf_dense_apply_2d: bad phase parameters");
+  // the 2-D phases and defaults of ibf_plan with dim = 2
+  const double defaults[4][3] = {{1, 0, 0}, {0, 0, 0}, {2, 1, 16}, {3, 0.3125, 0}};
+  if (phase_id < 0 || phase_id > 3 || phase_id == IBF_PHASE_FIO1D)
+    return fail(IBF_ERR_UNSUPPORTED, "ibf_dense_apply_2d: unsupported phase");
+  ibf::PhaseDesc ph{};
+  ph.kind = phase_id;
+  for (int i = 0; i < 3; ++i) ph.p[i] = i < n_params ? params[i] : defaults[phase_id][i];
+  if (phase_id == IBF_PHASE_FIO2D && ph.p[2] == 0.0)
+    return fail(IBF_ERR_INVALID_ARG, "ibf_dense_apply_2d: p2 == 0");
+  if (n_x == 0) return IBF_OK;
+  return ibf::dense_apply_2d(ph, x, n_x, xi, n_xi, g, ldg, u, ldu, nrhs, (hipStream_t)stream);
+}
+
 }  // extern "C"

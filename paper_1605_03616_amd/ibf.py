@@ -26,7 +26,7 @@ EXPORTED = ["ibf_plan", "ibf_build", "ibf_apply", "ibf_apply_profile", "ibf_quer
             "ibf_mlp_features", "ibf_mlp_forward", "ibf_mlp_grad_work", "ibf_mlp_loss_grad",
             "ibf_mlp_adam", "ibf_mlp_select", "ibf_tune", "ibf_set_tuning", "ibf_set_allocator",
             "ibf_measure_peak", "ibf_apply_adjoint", "ibf_rel_error", "ibf_apply_noalloc",
-            "ibf_build_batch"]
+            "ibf_build_batch", "ibf_dense_apply_2d"]
 MLP_FEATURES = 5
 PATHS = ["default", "vector", "mfma", "tight", "tight_split"]      # ibf_tuning.path
 BATCH_GRAPH = 1
@@ -136,6 +136,7 @@ def load(path: str = LIB_PATH):
     vp, i64, f32 = C.c_void_p, C.c_int64, C.c_float
     lib.ibf_dense_apply.argtypes = [C.c_int, C.POINTER(C.c_double), C.c_int, vp, i64, vp, i64,
                                     vp, i64, vp, i64, i64, vp]
+    lib.ibf_dense_apply_2d.argtypes = lib.ibf_dense_apply.argtypes
     lib.ibf_mlp_n_params.argtypes = [C.c_int]
     lib.ibf_mlp_features.argtypes = [i64, C.c_int, C.c_int, C.c_double, C.POINTER(C.c_float)]
     lib.ibf_mlp_forward.argtypes = [vp, C.c_int, vp, i64, vp, vp]
@@ -159,7 +160,8 @@ def load(path: str = LIB_PATH):
                  "ibf_batch_destroy", "ibf_dense_apply", "ibf_mlp_n_params",
                  "ibf_mlp_features", "ibf_mlp_forward", "ibf_mlp_loss_grad", "ibf_mlp_adam",
                  "ibf_mlp_select", "ibf_tune", "ibf_set_tuning", "ibf_set_allocator", "ibf_measure_peak",
-                 "ibf_apply_adjoint", "ibf_rel_error", "ibf_apply_noalloc"):
+                 "ibf_apply_adjoint", "ibf_rel_error", "ibf_apply_noalloc",
+                 "ibf_dense_apply_2d"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -513,6 +515,23 @@ def dense_apply(phase, params, x_dev, xi_dev, g, stream=None):
                                C.c_void_p(xi_dev.data_ptr()), xi_dev.shape[0],
                                C.c_void_p(g.data_ptr()), g.shape[1], C.c_void_p(u.data_ptr()),
                                u.shape[1], nrhs, _stream_handle(stream)))
+    return u
+
+
+def dense_apply_2d(phase, params, x_dev, xi_dev, g, stream=None):
+    """Device FP64 direct 2-D product: x (n_x, 2), xi (n_xi, 2) float64 device
+    tensors, g (nrhs, n_xi) complex128 -> u (nrhs, n_x)."""
+    import torch
+    lib = load()
+    prm = np.ascontiguousarray(params if params is not None else [], dtype=np.float64)
+    nrhs = g.shape[0]
+    u = torch.empty((nrhs, x_dev.shape[0]), dtype=torch.complex128, device=g.device)
+    _check(lib.ibf_dense_apply_2d(int(phase),
+                                  prm.ctypes.data_as(C.POINTER(C.c_double)) if prm.size else None,
+                                  int(prm.size), C.c_void_p(x_dev.data_ptr()), x_dev.shape[0],
+                                  C.c_void_p(xi_dev.data_ptr()), xi_dev.shape[0],
+                                  C.c_void_p(g.data_ptr()), g.shape[1], C.c_void_p(u.data_ptr()),
+                                  u.shape[1], nrhs, _stream_handle(stream)))
     return u
 
 

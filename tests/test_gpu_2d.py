@@ -45,6 +45,28 @@ def fp64_bar(n):
     return max(1e-12, 8 * n * n * 2.0 ** -53)
 
 
+@pytest.mark.parametrize("phase", [I.PHASE_FIO2D, I.PHASE_DFT, I.PHASE_SEPARABLE])
+def test_dense_apply_2d_vs_oracle(torch_dev, phase):
+    """The device FP64 direct 2-D product (the dense check bench.py uses)
+    against the oracle's, on random x in [0,1)^2 and the integer xi of the
+    64 x 64 square: the FP64 phase floor of the grid's size."""
+    from paper_1605_03616_amd import ibf
+    torch = torch_dev
+    _say(f"device dense 2-D product phase={phase}")
+    rng = np.random.default_rng(57 + phase)
+    n = 64
+    x = rng.random((700, 2))
+    k = np.arange(n, dtype=np.float64) - n / 2
+    xi = np.stack(np.meshgrid(k, k, indexing="ij"), axis=-1).reshape(-1, 2)
+    g = I.complex_normal(len(xi), 2, rng)
+    params = I.DEFAULT_PARAMS[phase]
+    u = ibf.dense_apply_2d(phase, params, torch.from_numpy(x).cuda(),
+                           torch.from_numpy(np.ascontiguousarray(xi)).cuda(),
+                           torch.from_numpy(np.ascontiguousarray(g.T)).cuda())
+    ud = D.dense_apply_2d(phase, params, x, xi, g)
+    assert _rel(u.cpu().numpy().T, ud) <= fp64_bar(n)
+
+
 @functools.lru_cache(maxsize=None)
 def _case(n, r, phase=I.PHASE_FIO2D, nrhs=2, seed=41, tol=1e-4):
     P = I.fio2d_grid(n, r, nrhs, seed, tol=tol, precision=I.PREC_FP64)
