@@ -324,7 +324,9 @@ int pack_all(ibf_plan_t p, const std::vector<DevBuf<double2>>& stages, const dou
       Stage& sq = p->stages.back();
       const int64_t nrec = p->npairs * 2 * ((sq.k_in + 3) / 4) * 2 * sq.k_ld;
       sq.qbytes = (size_t)nrec * sizeof(uint4);
-      IBF_HIP_CHECK(ibf::dev_malloc(&sq.qblk, std::max<size_t>(sq.qbytes, 16)));
+      // + slack: with a stored input rank of 0 the clamped record loads of the
+      // stage kernel read the first 32 records of the buffer
+      IBF_HIP_CHECK(ibf::dev_malloc(&sq.qblk, sq.qbytes + kStageSlack));
       const unsigned qb = (unsigned)std::min<int64_t>((nrec + kBlock - 1) / kBlock, 1 << 20);
       hipLaunchKernelGGL(k_quad_split, dim3(std::max(qb, 1u)), dim3(kBlock), 0, s,
                          (const bf16x2c*)sq.blk, (uint4*)sq.qblk, p->npairs, sq.k_in, sq.k_ld);

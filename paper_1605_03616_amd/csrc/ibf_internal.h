@@ -22,9 +22,10 @@ struct Tuning {
   int path = 0, chunk = 0, max_fused = 0, split = 0;
 };
 constexpr int kMaxParams = 6;
-// Bytes allocated past a stage's stored blocks: the per-pair-rank stage
-// kernel reads whole two-row windows (and rows past a pair's rank) without
-// clamping; what it reads there is never used.
+// Bytes allocated past a stage's stored blocks and past its quad records:
+// the per-pair-rank stage kernels read whole two-row windows (and rows past
+// a pair's rank) without clamping, and clamped record loads of a stage with
+// input rank 0 start at the buffer; what they read there is never used.
 constexpr size_t kStageSlack = 8192;
 
 struct PhaseDesc {
