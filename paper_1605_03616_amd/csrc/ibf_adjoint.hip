@@ -7,12 +7,14 @@
 // transposed slices of the two forward blocks (2B + d, A >> 1), d = 0, 1, of
 // the forward stage with output level L - l' + 1, and its middle block (at
 // level L - h) is the conjugate transpose of Mdot at the transposed pair.  The
-// transposed copies are made on the first adjoint apply and run on the
-// forward apply kernels.
+// transposed copies (with the per-pair ranks at the transposed labels, and
+// the quad records of BF16X2 stages) are made on the first adjoint apply and
+// run on the forward apply kernels.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <string>
+#include <type_traits>
 
 #include "ibf_device.h"
 
@@ -73,6 +75,21 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint_mid(const FT* __restrict_
   const int64_t pf = (B << (L - h)) | A;
   const auto f = load_factor(src, (pf * kg + j) * kh + i);
   store_factor(dst, e, make_double2((double)f.x, -(double)f.y));
+}
+
+// Per-pair ranks of the adjoint plan: its pair p' = A 2^l + B at level
+// L - l (A: L - l bits, B: l bits) is the forward pair B 2^(L-l) + A at
+// level l, whose coefficients have the same rank.
+__global__ __launch_bounds__(kAdjBlock) void k_adjoint_prank(const uint8_t* __restrict__ src,
+                                                          uint8_t* __restrict__ dst, int L,
+                                                          int l0, int nlev, int64_t npairs) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)nlev * npairs) return;
+  const int li = (int)(e / npairs);
+  const int64_t pa = e - (int64_t)li * npairs;
+  const int l = L - (l0 + li);                                // forward level
+  const int64_t A = pa >> l, B = pa & (((int64_t)1 << l) - 1);
+  dst[e] = src[(int64_t)(l - l0) * npairs + ((B << (L - l)) | A)];
 }
 
 }  // namespace
@@ -141,11 +158,28 @@ int make_adjoint_t(ibf_plan_t p, hipStream_t s) {
     st.bytes = (size_t)p->npairs * 2 * st.k_in * st.k_ld * sizeof(FT);
     a->stages.push_back(st);
     Stage& sa = a->stages.back();
-    IBF_HIP_CHECK(ibf::dev_malloc(&sa.blk, std::max<size_t>(sa.bytes, 1)));
+    // + the stage slack: the per-pair-rank stage kernel reads whole rows past
+    // a block's last row (as for the forward plan's blocks)
+    IBF_HIP_CHECK(ibf::dev_malloc(&sa.blk, sa.bytes + kStageSlack));
     const int64_t n = (int64_t)p->npairs * 2 * st.k_in * st.k_ld;
     hipLaunchKernelGGL((k_adjoint_stage<FT>), dim3((unsigned)((n + kAdjBlock - 1) / kAdjBlock)),
                        dim3(kAdjBlock), 0, s, (const FT*)f.blk, (FT*)sa.blk, L, lp, f.k_in, f.k_out,
                        f.k_ld, st.k_ld, p->npairs);
+    IBF_HIP_CHECK(hipGetLastError());
+    // BF16X2 without the sweep-in: quad records for the BF16 split products
+    if (std::is_same<FT, bf16x2c>::value && p->d_prank) {
+      const int rc2 = make_quad_records(sa, p->npairs, s);
+      if (rc2) return rc2;
+    }
+  }
+  if (p->d_prank) {
+    // the forward per-pair ranks at the transposed labels: the adjoint runs on
+    // the per-pair-rank stage kernels as the forward apply does
+    const int nlev = L - 2 * l0 + 1;
+    const int64_t n = (int64_t)nlev * p->npairs;
+    IBF_HIP_CHECK(ibf::dev_malloc(reinterpret_cast<void**>(&a->d_prank), (size_t)n));
+    hipLaunchKernelGGL(k_adjoint_prank, dim3((unsigned)((n + kAdjBlock - 1) / kAdjBlock)),
+                       dim3(kAdjBlock), 0, s, p->d_prank, a->d_prank, L, l0, nlev, p->npairs);
     IBF_HIP_CHECK(hipGetLastError());
   }
   if (p->d_mdot) {
@@ -165,9 +199,11 @@ int make_adjoint_t(ibf_plan_t p, hipStream_t s) {
 void free_adjoint(ibf_plan_t p) {
   ibf_plan_s* a = p->adj;
   if (!a) return;
-  for (auto& st : a->stages)
+  for (auto& st : a->stages) {
     if (st.blk) (void)ibf::dev_free(st.blk);
-  void* own[] = {a->d_vbar, a->d_ubar, a->d_mdot, a->d_work[0], a->d_work[1]};
+    if (st.qblk) (void)ibf::dev_free(st.qblk);
+  }
+  void* own[] = {a->d_vbar, a->d_ubar, a->d_mdot, a->d_work[0], a->d_work[1], a->d_prank};
   for (void* b : own)
     if (b) (void)ibf::dev_free(b);
   delete a;                                                   // the point maps are p's

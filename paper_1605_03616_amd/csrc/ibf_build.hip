@@ -319,17 +319,10 @@ int pack_all(ibf_plan_t p, const std::vector<DevBuf<double2>>& stages, const dou
                        stages[l - l0 - 1].ptr, (FT*)st.blk, p->npairs, R, st.k_out, st.k_in,
                        st.k_ld);
     p->nnz_stored += count;
+    // quad records for the per-pair-rank stages with BF16 split products
     if (std::is_same<FT, bf16x2c>::value && p->d_prank) {
-      // quad records for the per-pair-rank stages with BF16 split products
-      Stage& sq = p->stages.back();
-      const int64_t nrec = p->npairs * 2 * ((sq.k_in + 3) / 4) * 2 * sq.k_ld;
-      sq.qbytes = (size_t)nrec * sizeof(uint4);
-      // + slack: with a stored input rank of 0 the clamped record loads of the
-      // stage kernel read the first 32 records of the buffer
-      IBF_HIP_CHECK(ibf::dev_malloc(&sq.qblk, sq.qbytes + kStageSlack));
-      const unsigned qb = (unsigned)std::min<int64_t>((nrec + kBlock - 1) / kBlock, 1 << 20);
-      hipLaunchKernelGGL(k_quad_split, dim3(std::max(qb, 1u)), dim3(kBlock), 0, s,
-                         (const bf16x2c*)sq.blk, (uint4*)sq.qblk, p->npairs, sq.k_in, sq.k_ld);
+      const int rc = make_quad_records(p->stages.back(), p->npairs, s);
+      if (rc) return rc;
     }
   }
   // Ubar at level L-l0, Vbar at level l0
@@ -522,6 +515,19 @@ int upload(T** dst, const std::vector<T>& src) {
 }
 
 }  // namespace
+
+int make_quad_records(Stage& st, int64_t npairs, hipStream_t s) {
+  const int64_t nrec = npairs * 2 * ((st.k_in + 3) / 4) * 2 * st.k_ld;
+  st.qbytes = (size_t)nrec * sizeof(uint4);
+  // + slack: with a stored input rank of 0 the clamped record loads of the
+  // stage kernel read the first 32 records of the buffer
+  IBF_HIP_CHECK(ibf::dev_malloc(&st.qblk, st.qbytes + kStageSlack));
+  const unsigned qb = (unsigned)std::min<int64_t>((nrec + kBlock - 1) / kBlock, 1 << 20);
+  hipLaunchKernelGGL(k_quad_split, dim3(std::max(qb, 1u)), dim3(kBlock), 0, s,
+                     (const bf16x2c*)st.blk, (uint4*)st.qblk, npairs, st.k_in, st.k_ld);
+  IBF_HIP_CHECK(hipGetLastError());
+  return IBF_OK;
+}
 
 int build_plan(ibf_plan_t p, hipStream_t s) {
   IBF_HIP_CHECK(hipSetDevice(p->device));

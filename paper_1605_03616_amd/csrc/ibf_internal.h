@@ -147,6 +147,9 @@ int apply_plan(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu,
                int64_t nrhs, hipStream_t s, ibf_profile* prof = nullptr);
 int dense_apply(const PhaseDesc& ph, const double* x, int64_t nx, const double* xi, int64_t nxi,
                 const void* g, int64_t ldg, void* u, int64_t ldu, int64_t nrhs, hipStream_t s);
+// Quad records of a BF16X2 stage (Stage::qblk, allocated with the stage
+// slack) from its stored blocks, on stream s.
+int make_quad_records(Stage& st, int64_t npairs, hipStream_t s);
 int dense_apply_2d(const PhaseDesc& ph, const double* x, int64_t nx, const double* xi,
                    int64_t nxi, const void* g, int64_t ldg, void* u, int64_t ldu, int64_t nrhs,
                    hipStream_t s);

@@ -71,10 +71,17 @@ def _adjoint(torch, P, precision, h, sweep_in=0):
     ("fio4k_r12", I.PREC_FP32, 8),
     ("fio4k_r12", I.PREC_FP32, 37),
     ("fio4k_r12", I.PREC_FP32, 64),
+    ("fio4k_r12", I.PREC_FP32, 130),
+    ("fio4k_r12", I.PREC_BF16X2, 64),
     ("nudft4k_r10", I.PREC_FP32, 16),
+    ("nudft4k_r10", I.PREC_FP32, 64),
     ("nudft4k_r10", I.PREC_BF16X2, 16),
+    ("nudft4k_r10", I.PREC_BF16X2, 70),
 ])
 def test_adjoint_parity(torch_dev, key, precision, nrhs):
+    """From 64 RHS the adjoint plan runs the per-pair-rank stage kernels (the
+    forward per-pair ranks at the transposed labels; BF16 split products for
+    BF16X2), below on the 16/32-column and vector kernels."""
     _say(f"adjoint parity {key} precision={precision} nrhs={nrhs}")
     P, Op = _case(key)
     h = I.complex_normal(len(P.x), nrhs, np.random.default_rng(50 + nrhs))
@@ -124,6 +131,37 @@ def test_adjoint_identity_and_rebuild(torch_dev):
     v2 = pl.apply_adjoint(ht).cpu().numpy().T
     pl.destroy()
     assert np.array_equal(v, v2)
+
+
+@pytest.mark.parametrize("precision,tol", [(I.PREC_FP32, 1e-5), (I.PREC_BF16X2, 1e-4)])
+def test_adjoint_full_size(torch_dev, precision, tol):
+    """The benchmark's plan (1-D FIO N = 65536, r = 12) with 64 RHS, whose
+    adjoint runs the per-pair-rank stage kernels at the transposed labels:
+    <K g, h> = <g, K^* h> per column with the GPU's forward and adjoint
+    applies (relative to ||K g|| ||h||), and the adjoint against the FP64
+    plan's adjoint, Frobenius and per column."""
+    import dataclasses
+    torch = torch_dev
+    from paper_1605_03616_amd import ibf
+    _say(f"adjoint full size fio1d n=65536 r=12 nrhs=64 precision={precision}")
+    P = I.workload_fio1d_64k(nrhs=64)
+    h = I.complex_normal(P.n, 64, np.random.default_rng(71))
+    g = torch.from_numpy(np.ascontiguousarray(P.g.T)).to(torch.complex64).cuda()
+    ht = torch.from_numpy(np.ascontiguousarray(h.T)).to(torch.complex64).cuda()
+    pl = ibf.Plan.from_problem(dataclasses.replace(P, precision=precision)).build()
+    u = pl.apply(g).cpu().numpy().T.astype(np.complex128)
+    v = pl.apply_adjoint(ht).cpu().numpy().T.astype(np.complex128)
+    pl.destroy()
+    lhs = np.einsum("ij,ij->j", h.conj(), u)
+    rhs = np.einsum("ij,ij->j", v.conj(), P.g)
+    scale = np.linalg.norm(u, axis=0) * np.linalg.norm(h, axis=0)
+    assert np.max(np.abs(lhs - rhs) / scale) <= tol
+    p64 = ibf.Plan.from_problem(dataclasses.replace(P, precision=I.PREC_FP64)).build()
+    v64 = p64.apply_adjoint(torch.from_numpy(np.ascontiguousarray(h.T)).cuda())
+    p64.destroy()
+    v64 = v64.cpu().numpy().T
+    assert O.rel_error(v, v64) < tol
+    assert O.rel_error_cols(v, v64) < tol
 
 
 def test_adjoint_unsupported(torch_dev):
