@@ -160,8 +160,12 @@ __global__ __launch_bounds__(kBlock) void k_sweep_g(PhaseDesc ph, Geo geo, const
 //   H_alpha[t][s] = exp(-2 pi i Phi(c_A, g^B_t)) M^B_t(g^C_s) exp(2 pi i Phi(c_A, g^C_s))
 //   Z = [H_0^* R_{A0 B}, H_1^* R_{A1 B}],  A = Z^*,  A[i][s] with i = alpha r + j.
 // ---------------------------------------------------------------------------
+// Up to r = 13 the register budget is that of 3 waves a SIMD, which the
+// other sweep kernels reach by themselves (at r = 12: 178 -> 168 VGPRs with
+// a few spills, measured 4 % off the build); larger r would spill more.
 template <int R, int G>
-__global__ __launch_bounds__(kBlock) void k_sweep_h(PhaseDesc ph, Geo geo, const double* cheb,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(R <= 13 ? 3 : 1)))
+void k_sweep_h(PhaseDesc ph, Geo geo, const double* cheb,
                                                     double tol, int cap, int l, int64_t npairs,
                                                     const double2* Rin, double2* Rout,
                                                     double2* stage, const int* rk_in, int* rk_out,
