@@ -42,14 +42,14 @@ MEASURED_TRAFFIC = {
     # (workload, schedule path/chunk/max_fused) -> (sha1 of the apply source,
     #   kernel class, [(launches per step, FETCH_SIZE KiB, WRITE_SIZE KiB), ...])
     ("fio1d_n65536_r12_fp32", "default/0/0"): (
-        "50ec3be4c77aea9df60a7d156f1c892b45d7986f", "apply_stage_tight",
-        [(2, 323159, 295936)]),
+        "dd691557a76f9a3356f790409089cd4c61c16094", "apply_stage_tight",
+        [(2, 323079, 238008)]),
     ("fio1d_n65536_r12_bf16x2", "default/0/0"): (
-        "50ec3be4c77aea9df60a7d156f1c892b45d7986f", "apply_stage_tight_split",
-        [(2, 311360, 294912)]),
+        "dd691557a76f9a3356f790409089cd4c61c16094", "apply_stage_tight_split",
+        [(2, 311345, 236984)]),
     ("nudft_n1048576_r10", "default/0/0"): (
-        "50ec3be4c77aea9df60a7d156f1c892b45d7986f", "apply_fused_mfma",
-        [(2, 2424927, 983040), (1, 1769576, 917504), (1, 1822849, 1048576)]),
+        "dd691557a76f9a3356f790409089cd4c61c16094", "apply_fused_mfma",
+        [(2, 2424919, 983040), (1, 1769577, 917504), (1, 1822846, 1048576)]),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 

@@ -118,6 +118,8 @@ struct VDesc {
   const void* vbar;
   void* mu;
   int L, l0, K, nrhs, NB, nchunk, smax, stage_f;
+  const uint8_t* prk;   // MFMA V: per-pair ranks at level l0; rows past a pair's
+                        // rank are not written (null: every row is written)
 };
 
 template <typename VT, typename FT, int KT>
@@ -726,6 +728,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_fused_mfma(const FusedDesc* __
 struct TightArgs {
   int L, l_start, nst, nrhs, nchunk;
   int KS;                            // rows per LDS slot: largest stored rank of the levels
+  int rank_out;                      // 1: the output rows past a pair's rank are not written
+                                     // (every reader of them skips them)
   int kst[kMaxR + 1];                // stored rank at level l_start - 1 + j (HBM row stride)
   int kld[kMaxR];                    // stored row length of stage j's blocks
   const void* blk[kMaxR];
@@ -1117,17 +1121,19 @@ __device__ __forceinline__ void tight_body(const TightDesc& D, int64_t lb, int64
           }
         }
       } else if (lane < cur.nbw) {
-        // last stage: all stored rows of the output pair to HBM (zero past its rank)
+        // last stage: the output pair's rows to HBM at the stored row stride:
+        // the rows of its rank, or all stored rows (zero past its rank)
         const int Kout = A.kst[K4];
+        const int Kw = A.rank_out ? sw.kout : Kout;
         float2* dst = out + sw.pout * Kout * (int64_t)nrhs + cur.nb0 + lane;
 #pragma unroll
         for (int g = 0; g < KG; ++g) {
-          if (2 * g < Kout) {
+          if (2 * g < Kw) {
             const v4f pp = P[g], qq = Q[g];
             const bool live = g < ng;
             dst[(int64_t)(2 * g) * nrhs] = live ? make_float2(pp[0] - qq[1], pp[1] + qq[0])
                                                 : make_float2(0.f, 0.f);
-            if (2 * g + 1 < Kout)
+            if (2 * g + 1 < Kw)
               dst[(int64_t)(2 * g + 1) * nrhs] = live ? make_float2(pp[2] - qq[3], pp[3] + qq[2])
                                                       : make_float2(0.f, 0.f);
           }
@@ -1202,6 +1208,8 @@ struct UDesc {
   const int32_t* xoff;
   const void* ubar;
   int l0, K, nrhs, NB, nchunk, smax, stage_f;
+  const uint8_t* prk;   // MFMA U: per-pair ranks at level L - l0; rows past a
+                        // pair's rank are not read (null: every row is read)
 };
 
 template <typename VT, typename FT>
@@ -1338,6 +1346,17 @@ __device__ __forceinline__ void apply_v_mfma_body(const VDesc& d, int64_t lb) {
                                 : make_float2(0.f, 0.f);
   });
   const FT* vsrc = vbar + (int64_t)j0 * R;
+  const int sh = L - l0;
+  const FastDiv divK(K);
+  // output row t = a K + k is written iff k is within the rank of pair
+  // (a, b) (a byte a row after Vbar in LDS, computed while the copies load)
+  unsigned char* rl = reinterpret_cast<unsigned char*>(vl + (size_t)SM * R + 2 * kVChunk);
+  if (d.prk)
+    for (int t = threadIdx.x; t < R; t += kBlock) {
+      int a, k;
+      divK.divmod(t, a, k);
+      rl[t] = k < (int)d.prk[((int64_t)a << sh) | b] ? 1 : 0;
+    }
   staged_copy_to<8>(cnt * R, vl, [&](int e, int& off) {
     off = e;
     return load_factor(vsrc, e);
@@ -1350,8 +1369,6 @@ __device__ __forceinline__ void apply_v_mfma_body(const VDesc& d, int64_t lb) {
 #pragma unroll
   for (int j = 0; j < SM; ++j) xr[j] = gl[j * GP + lane];
   const int npair = R >> 1, nchk = (npair + CH - 1) / CH;
-  const int sh = L - l0;
-  const FastDiv divK(K);
   for (int c = wave; c < nchk; c += 4) {
     v4f P[CH], Q[CH];
 #pragma unroll
@@ -1384,9 +1401,10 @@ __device__ __forceinline__ void apply_v_mfma_body(const VDesc& d, int64_t lb) {
             int a, k;
             divK.divmod(2 * rp + h, a, k);
             const int64_t pr = ((int64_t)a << sh) | b;
-            mu[(pr * K + k) * nrhs + nb0 + lane] =
-                h == 0 ? make_float2(pp[0] - qq[1], pp[1] + qq[0])
-                       : make_float2(pp[2] - qq[3], pp[3] + qq[2]);
+            if (!d.prk || rl[2 * rp + h])
+              mu[(pr * K + k) * nrhs + nb0 + lane] =
+                  h == 0 ? make_float2(pp[0] - qq[1], pp[1] + qq[0])
+                         : make_float2(pp[2] - qq[3], pp[3] + qq[2]);
           }
         }
       }
@@ -1448,11 +1466,23 @@ __device__ __forceinline__ void apply_u_mfma_body(const UDesc& d, int64_t lb) {
   const float2* src = mu + (p0 * K + r0) * nrhs + nb0 + lane;
   // the wave's mu rows, RB at a time, the first batch issued before the
   // barrier that publishes Ubar
+  // rows past their pair's rank hold no data (their Ubar entries are zero)
+  // and are not read: bit i of `live` is row r0 + i of this wave (rw <= 64
+  // when ranks are given)
+  uint64_t live = ~0ull;
+  if (d.prk) {
+    const FastDiv divK(K);
+    int q = 0, k = 0;
+    if (lane < rw) divK.divmod(r0 + lane, q, k);
+    live = __ballot(lane >= rw || k < (int)d.prk[p0 + q]);
+  }
   float2 xa[RB], xb[RB];
   auto load_rows = [&](int i0, float2 (&X)[RB]) {
 #pragma unroll
     for (int i = 0; i < RB; ++i)
-      X[i] = (col && i0 + i < rw) ? src[(int64_t)(i0 + i) * nrhs] : make_float2(0.f, 0.f);
+      X[i] = (col && i0 + i < rw && ((live >> ((i0 + i) & 63)) & 1ull))
+                 ? src[(int64_t)(i0 + i) * nrhs]
+                 : make_float2(0.f, 0.f);
   };
   load_rows(0, xa);
   __syncthreads();
@@ -1714,10 +1744,13 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
       const int R = K << l0;
       const int nchv = (nrhs + 63) / 64;
       x.mfma = true;
-      x.lds = ((size_t)kLeafMfma * 65 + (size_t)p->smax_xi * R + 2 * kVChunk) * sizeof(VT);
+      // + a byte a row (the rows written before per-pair-rank stages)
+      x.lds = ((size_t)kLeafMfma * 65 + (size_t)kLeafMfma * R + 2 * kVChunk) * sizeof(VT) + R;
       x.nblocks = p->nleaf * nchv;
+      // before per-pair-rank stages, which read only the rows of each
+      // pair's rank, the rows past it are not written
       x.v = VDesc{g, ldg, p->d_perm_xi, p->d_xioff, p->d_vbar, w[0], L, l0, K, nrhs, 64, nchv,
-                  p->smax_xi, 1};
+                  p->smax_xi, 1, tight ? p->d_prank : nullptr};
     } else {
       int NBv = NBo;
       while (NBv > 1 && (size_t)p->smax_xi * NBv * sizeof(VT) > kLdsBudget / 2) NBv /= 2;
@@ -1732,7 +1765,7 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
       x.lds = base + (stage_f ? fac : 0);
       x.nblocks = p->nleaf * nchv;
       x.v = VDesc{g, ldg, p->d_perm_xi, p->d_xioff, p->d_vbar, w[0], L, l0, K, nrhs, NBv, nchv,
-                  p->smax_xi, stage_f};
+                  p->smax_xi, stage_f, nullptr};
     }
     seq.push_back(x);
   }
@@ -1789,6 +1822,7 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
         x.kind = kLaunchTight;
         x.mfma = true;
         x.split = split;
+        x.t.A.rank_out = 1;                                   // the next reader skips them
         TightArgs& T = x.t.A;
         T.L = L;
         T.l_start = l;
@@ -1928,8 +1962,11 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
       x.mfma = true;
       x.lds = ((size_t)R * (kLeafMfma + 1) + (size_t)4 * kLeafMfma * 64) * sizeof(VT);
       x.nblocks = p->nleaf * nchu;
+      // after per-pair-rank stages the rows past each pair's rank are not
+      // written, and not read here
       x.u = UDesc{w[cur], u, ldu, p->d_perm_x, p->d_xoff, p->d_ubar, l0, K, nrhs, 64, nchu,
-                  p->smax_x, 1};
+                  p->smax_x, 1,
+                  tight && R <= 256 ? p->d_prank + (size_t)(L - 2 * l0) * p->npairs : nullptr};
     } else {
       int NBu = NBo;
       while (NBu > 1 && (size_t)(1 << l0) * K * NBu * sizeof(VT) > kLdsBudget / 2) NBu /= 2;
@@ -1946,8 +1983,12 @@ int make_schedule(ibf_plan_t p, const void* g, int64_t ldg, void* u, int64_t ldu
       x.lds = base;
       x.nblocks = p->nleaf * nchu;
       x.u = UDesc{w[cur], u, ldu, p->d_perm_x, p->d_xoff, p->d_ubar, l0, K, nrhs, NBu, nchu,
-                  p->smax_x, stage_f};
+                  p->smax_x, stage_f, nullptr};
     }
+    // the last stage launch writes all stored rows unless this U skips the
+    // rows past each pair's rank
+    if (!seq.empty() && seq.back().kind == kLaunchTight && !(x.mfma && x.u.prk))
+      seq.back().t.A.rank_out = 0;
     seq.push_back(x);
   }
   return IBF_OK;
