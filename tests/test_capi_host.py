@@ -268,3 +268,25 @@ def test_sampled_svd_descriptor_validation():
     with pytest.raises(ibf.IBFError) as e:
         ibf.Plan(x, xi, 2, (2.0, 1.0, 16.0), 6, 1e-3, 16, I.PREC_FP32, svd_sample=(7, -1))
     assert e.value.code == -1
+
+
+def test_dense_apply_arguments_host_only():
+    # argument and phase checks happen before any device call
+    lib = ibf.load()
+    vp = C.c_void_p(16)                                      # never dereferenced
+    for fn in (lib.ibf_dense_apply, lib.ibf_dense_apply_2d):
+        assert fn(I.PHASE_DFT, None, 0, None, 4, vp, 4, vp, 4, vp, 4, 1, None) == -1
+        assert fn(I.PHASE_DFT, None, 0, vp, 4, vp, 4, vp, 3, vp, 4, 1, None) == -1   # ldg < n_xi
+        assert fn(I.PHASE_DFT, None, 0, vp, 4, vp, 4, vp, 4, vp, 4, 0, None) == -1   # nrhs < 1
+        assert fn(I.PHASE_DFT, None, -1, vp, 4, vp, 4, vp, 4, vp, 4, 1, None) == -1
+        assert fn(7, None, 0, vp, 4, vp, 4, vp, 4, vp, 4, 1, None) == -2
+    # each dimension refuses the other's phase
+    assert lib.ibf_dense_apply(I.PHASE_FIO2D, None, 0, vp, 4, vp, 4, vp, 4, vp, 4, 1, None) == -2
+    assert lib.ibf_dense_apply_2d(I.PHASE_FIO1D, None, 0, vp, 4, vp, 4, vp, 4, vp, 4, 1,
+                                  None) == -2
+    bad = (C.c_double * 3)(2.0, 1.0, 0.0)                    # FIO2D with p2 == 0
+    assert lib.ibf_dense_apply_2d(I.PHASE_FIO2D, bad, 3, vp, 4, vp, 4, vp, 4, vp, 4, 1,
+                                  None) == -1
+    # nothing to do: no device call
+    assert lib.ibf_dense_apply_2d(I.PHASE_FIO2D, None, 0, vp, 0, vp, 4, vp, 4, vp, 4, 1,
+                                  None) == 0
