@@ -75,7 +75,10 @@ extern "C" {
 /* ---- factor storage / apply precision ---- */
 #define IBF_FP64    0   /* complex double factors and vectors */
 #define IBF_FP32    1   /* complex float factors and vectors, FP32 accumulation */
-#define IBF_BF16X2  2   /* factors as bf16 hi + lo pairs, float vectors, FP32 accumulation */
+#define IBF_BF16X2  2   /* factors as bf16 hi + lo pairs, float vectors, FP32 accumulation;
+                           the per-pair-rank stages (plans without the sweep-in, from 64
+                           RHS) multiply BF16 split products (hi.hi + hi.lo + lo.hi) on
+                           the bf16 MFMA, the other kernels widen the factors to FP32 */
 
 typedef struct ibf_plan_s* ibf_plan_t;
 
